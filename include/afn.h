@@ -1,0 +1,165 @@
+/*
+ * afn.h -- C-ABI of libafn: AFN-preconditioned conjugate gradients for
+ * regularized Gaussian kernel systems on AMD Instinct MI355X (gfx950).
+ *
+ * Method: "An Adaptive Factorized Nystrom Preconditioner for Regularized
+ * Kernel Matrices" (Zhao, Xu, Huang, Chow, Xi; arXiv 2304.05460).
+ * Problem (Eq. (1.1)): solve (K + mu I) a = b with
+ *   K_ij = exp(-||x_i - x_j||^2 / l^2)                      (Eq. (1.2)).
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers named *_dev are DEVICE pointers (e.g. from contiguous torch
+ *    tensors on the current HIP device); pointers named *_host are host
+ *    pointers.  The caller owns every buffer it passes; the library never
+ *    frees or retains caller buffers beyond the call.
+ *  - Points X are FP64, row-major n x d (point i at X[i*d .. i*d+d-1]).
+ *    Vectors are FP64 column-major n x nrhs with leading dimension ld >= n.
+ *    Every vector crosses the boundary in the ORIGINAL point order; the
+ *    landmark-first ordering is internal.
+ *  - 'stream' is a hipStream_t (NULL = the default stream).  Work is
+ *    stream-ordered.  kernel_matvec and afn_apply return without waiting;
+ *    afn_setup and afn_pcg_solve synchronize the stream before returning,
+ *    because they take host decisions (landmark count, convergence).
+ *  - Every function returns an afn_status; failures never throw across the
+ *    boundary.  afn_last_error() returns a thread-local message describing
+ *    the last failure on the calling thread.  On failure, outputs other than
+ *    those documented are unspecified.
+ *  - A handle may be used by one host thread at a time.
+ */
+#ifndef AFN_H
+#define AFN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum afn_status {
+    AFN_OK = 0,
+    AFN_EINVAL = 1,        /* invalid argument (sizes, l <= 0, mu < 0, ...)            */
+    AFN_ENOMEM = 2,        /* device allocation failed                                 */
+    AFN_ENOTSPD = 3,       /* a Cholesky pivot of K11 + mu I or of an FSAI block <= 0  */
+    AFN_ENOCONV = 4,       /* PCG reached maxit; x holds the last iterate, info valid  */
+    AFN_EBREAKDOWN = 5,    /* PCG breakdown: p'Ap <= 0 or a NaN appeared               */
+    AFN_ESTAGNATION = 6,   /* iterative refinement stopped reducing the residual       */
+    AFN_EDEVICE = 7        /* a HIP runtime call failed                                */
+} afn_status;
+
+/* Arithmetic of the kernel tiles.  AFN_FP64: FP64 throughout.  AFN_FP32:
+ * distances and kernel values in FP32 with FP32 accumulation (vectors stay
+ * FP64 at the boundary). */
+typedef enum afn_precision {
+    AFN_FP64 = 0,
+    AFN_FP32 = 1
+} afn_precision;
+
+/* Construction parameters (Algorithm 2, Algorithm 4). */
+typedef struct afn_params {
+    int32_t k;          /* landmark count; -1 = estimate it (Algorithm 4)         */
+    int32_t k_max;      /* cap on the estimated count (Section 3.2: e.g. 2000)     */
+    int32_t w;          /* FSAI nonzeros per row incl. the diagonal, 1 <= w <= 64  */
+    int32_t m;          /* rank-estimation subsample size; 0 = min(n, 2000)        */
+    int32_t precision;  /* afn_precision of the PCG operator (reserved: AFN_FP64)  */
+    int32_t reserved;   /* must be 0                                               */
+    uint64_t seed;      /* seed of the rank-estimation subsample (splitmix64)      */
+} afn_params;
+
+/* Facts about a constructed preconditioner. */
+typedef struct afn_setup_info {
+    int64_t n;
+    int32_t d;
+    int32_t k;               /* landmarks used                                     */
+    int32_t w;
+    int32_t rank_r;          /* Algorithm 4: Nystrom rank on the subsample, -1 if k given */
+    int64_t rank_k_est;      /* Algorithm 4: floor(r n / m), -1 if k given         */
+    int32_t rank_eig_branch; /* 1 if the eigenvalue count replaced k_est           */
+    int32_t rank_eig_count;  /* that count, -1 if not computed                     */
+    int64_t nnz_g;           /* nonzeros of the FSAI factor G                      */
+    double ms_rank, ms_fps, ms_chol, ms_knn, ms_v, ms_fsai, ms_total;  /* phase times */
+} afn_setup_info;
+
+/* Result of a PCG solve. */
+typedef struct afn_solve_info {
+    int32_t iterations;        /* products with K + mu I (per right-hand side: max) */
+    int32_t converged;         /* 1 if every right-hand side met tol                */
+    double relres;             /* recurrence residual ||r|| / ||b|| (max over rhs)   */
+    double relres_true;        /* ||b - (K + mu I) x|| / ||b|| recomputed in FP64    */
+    double ms_solve;
+} afn_solve_info;
+
+typedef struct afn_handle afn_handle;
+
+/* y = (K + mu I) v  (Eq. (1.1)), K evaluated on the fly from X (Eq. (1.2)).
+ * X_dev: n x d FP64 row-major.  v_dev, y_dev: n x nrhs FP64 column-major,
+ * leading dimension ld >= n; y must not alias v.  precision: afn_precision.
+ * Asynchronous on 'stream'.  Errors: EINVAL (n < 1, d < 1 or d > 64, l <= 0,
+ * mu < 0, nrhs < 1, ld < n), EDEVICE. */
+afn_status kernel_matvec(const double *X_dev, int64_t n, int32_t d, double l, double mu,
+                         const double *v_dev, double *y_dev, int32_t nrhs, int64_t ld,
+                         int32_t precision, void *stream);
+
+/* Construct the AFN preconditioner (Algorithm 2): landmarks by farthest point
+ * sampling (Algorithm 6) -- k from params or estimated (Algorithm 4) --,
+ * L = chol(K11 + mu I), and the FSAI factor G of the Schur complement
+ * K22 + mu I - K12^T (K11 + mu I)^{-1} K12 (Algorithm 1) on the pattern of
+ * the w-1 nearest earlier-numbered points (Section 3.1).
+ * The library copies what it needs from X_dev and owns the device memory of
+ * the handle (released by afn_destroy).  Synchronizes 'stream'.
+ * Errors: EINVAL (n < 1, d < 1 or d > 64, l <= 0, mu < 0, k < -1 or k > n,
+ * w < 1 or w > 64), ENOMEM, ENOTSPD, EDEVICE.  *out is NULL on failure. */
+afn_status afn_setup(const double *X_dev, int64_t n, int32_t d, double l, double mu,
+                     const afn_params *params, void *stream, afn_handle **out);
+
+/* z = M^{-1} r (Algorithm 3) for nrhs columns:
+ *   s2 = G^T G (r2 - K12^T (K11 + mu I)^{-1} r1),
+ *   s1 = (K11 + mu I)^{-1} (r1 - K12 s2).
+ * r_dev, z_dev: n x nrhs FP64 column-major, leading dimension ld >= n, no
+ * aliasing.  Asynchronous.  Errors: EINVAL, EDEVICE. */
+afn_status afn_apply(afn_handle *h, const double *r_dev, double *z_dev, int32_t nrhs,
+                     int64_t ld, void *stream);
+
+/* Preconditioned CG from x0 = 0 (Algorithm 5, AFN branch) for each of nrhs
+ * right-hand sides, stopping when ||r|| / ||b|| <= tol (Section 5 stopping
+ * rule) or after maxit products with K + mu I.  b_dev, x_dev: n x nrhs FP64
+ * column-major, leading dimension ld.  info_host may be NULL.  Synchronizes.
+ * Errors: EINVAL (tol <= 0, maxit < 1, nrhs < 1, ld < n), ENOCONV (x holds
+ * the last iterate, info valid), EBREAKDOWN, EDEVICE. */
+afn_status afn_pcg_solve(afn_handle *h, const double *b_dev, double *x_dev, int32_t nrhs,
+                         int64_t ld, double tol, int32_t maxit, afn_solve_info *info_host,
+                         void *stream);
+
+/* Setup facts (landmark count, rank-estimation outcome, phase timings). */
+afn_status afn_get_info(const afn_handle *h, afn_setup_info *info_host);
+
+/* Landmark indices (original numbering, FPS selection order) into idx_host
+ * (capacity cap >= k).  *k_out = k.  Synchronous. */
+afn_status afn_get_landmarks(const afn_handle *h, int32_t *idx_host, int64_t cap, int64_t *k_out);
+
+/* FSAI sparsity pattern in CSR over the non-landmark points, numbered
+ * 0..n-k-1 in ascending original index: rowptr_host (n-k+1 entries),
+ * cols_host (capacity cap >= nnz; columns ascending, the diagonal last) and,
+ * if vals_host is not NULL, the values of G (capacity cap).  *nnz_out = nnz. */
+afn_status afn_get_fsai(const afn_handle *h, int64_t *rowptr_host, int32_t *cols_host,
+                        double *vals_host, int64_t cap, int64_t *nnz_out);
+
+/* The Cholesky factor L of K11 + mu I, k x k column-major (lower triangle;
+ * the strict upper triangle is written as zero) into L_host with leading
+ * dimension ld >= k.  Synchronous. */
+afn_status afn_get_cholesky(const afn_handle *h, double *L_host, int64_t ld);
+
+/* Release the handle and its device memory.  NULL is allowed. */
+void afn_destroy(afn_handle *h);
+
+/* Static description of a status code. */
+const char *afn_status_string(afn_status s);
+
+/* Thread-local message of the last failure on this thread ("" if none). */
+const char *afn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AFN_H */

@@ -1,0 +1,268 @@
+"""Python binding of libafn (include/afn.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts torch device
+tensors to raw pointers and the current torch stream to a hipStream_t, checks
+shapes, and turns non-zero status codes into exceptions.  There is no CPU
+fallback: without the built library or a GPU every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import pathlib
+
+import torch
+
+_PKG = pathlib.Path(__file__).resolve().parent
+LIB_PATH = _PKG / "libafn.so"
+_lib = None
+
+AFN_OK, AFN_EINVAL, AFN_ENOMEM, AFN_ENOTSPD, AFN_ENOCONV, AFN_EBREAKDOWN, AFN_ESTAGNATION, \
+    AFN_EDEVICE = range(8)
+AFN_FP64, AFN_FP32 = 0, 1
+
+EXPORTED = ["kernel_matvec", "afn_setup", "afn_apply", "afn_pcg_solve", "afn_get_info",
+            "afn_get_landmarks", "afn_get_fsai", "afn_get_cholesky", "afn_destroy",
+            "afn_status_string", "afn_last_error"]
+
+
+class AFNError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = lib().afn_last_error().decode(errors="replace")
+        name = lib().afn_status_string(status).decode(errors="replace")
+        super().__init__(f"{where}: {name}: {msg}")
+        self.status = status
+
+
+class afn_params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("k_max", ctypes.c_int32), ("w", ctypes.c_int32),
+                ("m", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class afn_setup_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("w", ctypes.c_int32), ("rank_r", ctypes.c_int32),
+                ("rank_k_est", ctypes.c_int64), ("rank_eig_branch", ctypes.c_int32),
+                ("rank_eig_count", ctypes.c_int32), ("nnz_g", ctypes.c_int64),
+                ("ms_rank", ctypes.c_double), ("ms_fps", ctypes.c_double),
+                ("ms_chol", ctypes.c_double), ("ms_knn", ctypes.c_double),
+                ("ms_v", ctypes.c_double), ("ms_fsai", ctypes.c_double),
+                ("ms_total", ctypes.c_double)]
+
+
+class afn_solve_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("relres", ctypes.c_double), ("relres_true", ctypes.c_double),
+                ("ms_solve", ctypes.c_double)]
+
+
+def lib():
+    """Load libafn.so (building it if it was never built); raises if impossible."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            from . import build as _build
+            _build.build()
+        L = ctypes.CDLL(str(LIB_PATH))
+        _declare(L)
+        _lib = L
+    return _lib
+
+
+_P, _I32, _I64, _D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+
+
+def _declare(L):
+    L.kernel_matvec.argtypes = [_P, _I64, _I32, _D, _D, _P, _P, _I32, _I64, _I32, _P]
+    L.afn_setup.argtypes = [_P, _I64, _I32, _D, _D, ctypes.POINTER(afn_params), _P,
+                            ctypes.POINTER(_P)]
+    L.afn_apply.argtypes = [_P, _P, _P, _I32, _I64, _P]
+    L.afn_pcg_solve.argtypes = [_P, _P, _P, _I32, _I64, _D, _I32,
+                                ctypes.POINTER(afn_solve_info), _P]
+    L.afn_get_info.argtypes = [_P, ctypes.POINTER(afn_setup_info)]
+    L.afn_get_landmarks.argtypes = [_P, _P, _I64, ctypes.POINTER(_I64)]
+    L.afn_get_fsai.argtypes = [_P, _P, _P, _P, _I64, ctypes.POINTER(_I64)]
+    L.afn_get_cholesky.argtypes = [_P, _P, _I64]
+    L.afn_destroy.argtypes = [_P]
+    L.afn_destroy.restype = None
+    L.afn_status_string.argtypes = [ctypes.c_int]
+    L.afn_status_string.restype = ctypes.c_char_p
+    L.afn_last_error.argtypes = []
+    L.afn_last_error.restype = ctypes.c_char_p
+    for name in ("kernel_matvec", "afn_setup", "afn_apply", "afn_pcg_solve", "afn_get_info",
+                 "afn_get_landmarks", "afn_get_fsai", "afn_get_cholesky"):
+        getattr(L, name).restype = ctypes.c_int
+
+
+def _check(st: int, where: str, ok=(AFN_OK,)):
+    if st not in ok:
+        raise AFNError(st, where)
+    return st
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_f64(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64):
+        raise TypeError(f"{name} must be a float64 CUDA (HIP) tensor")
+    return t
+
+
+def _colmajor(t: torch.Tensor, name: str):
+    """(n,) or (n, nrhs) column-major FP64 device tensor -> (ptr, nrhs, ld)."""
+    _dev_f64(t, name)
+    if t.dim() == 1:
+        if t.stride(0) != 1:
+            raise ValueError(f"{name} must be contiguous")
+        return t.data_ptr(), 1, t.shape[0]
+    if t.dim() != 2 or t.stride(0) != 1:
+        raise ValueError(f"{name} must be (n,) or column-major (n, nrhs) (stride(0) == 1)")
+    return t.data_ptr(), t.shape[1], max(t.stride(1), t.shape[0])
+
+
+def empty_colmajor(n: int, nrhs: int, device=None) -> torch.Tensor:
+    """A column-major (n, nrhs) float64 device tensor."""
+    return torch.empty((nrhs, n), dtype=torch.float64, device=device or "cuda").t()
+
+
+def kernel_matvec(X: torch.Tensor, l: float, mu: float, v: torch.Tensor,
+                  precision: int = AFN_FP64, out: torch.Tensor | None = None,
+                  stream=None) -> torch.Tensor:
+    """y = (K + mu I) v (Eq. (1.1)) on the GPU; X (n, d) float64 row-major."""
+    X = _dev_f64(X, "X").contiguous()
+    n, d = X.shape
+    vp, nrhs, ldv = _colmajor(v, "v")
+    if v.shape[0] != n:
+        raise ValueError("v rows != n")
+    if out is None:
+        out = torch.empty_like(v) if v.dim() == 1 else empty_colmajor(n, nrhs, v.device)
+    yp, _, ldy = _colmajor(out, "out")
+    if ldv != ldy:
+        raise ValueError("v and out must share a leading dimension")
+    _check(lib().kernel_matvec(X.data_ptr(), n, d, l, mu, vp, yp, nrhs, ldv, precision,
+                               _stream(stream)), "kernel_matvec")
+    return out
+
+
+@dataclasses.dataclass
+class SetupInfo:
+    n: int
+    d: int
+    k: int
+    w: int
+    rank_r: int
+    rank_k_est: int
+    rank_eig_branch: int
+    rank_eig_count: int
+    nnz_g: int
+    ms: dict
+
+
+class Handle:
+    """Owns an afn_handle*; afn_destroy runs on close() or garbage collection."""
+
+    def __init__(self, ptr: ctypes.c_void_p, n: int, d: int):
+        self._ptr = ptr
+        self.n, self.d = n, d
+
+    @property
+    def ptr(self):
+        if not self._ptr:
+            raise RuntimeError("handle is closed")
+        return self._ptr
+
+    def close(self):
+        if self._ptr:
+            lib().afn_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> SetupInfo:
+        inf = afn_setup_info()
+        _check(lib().afn_get_info(self.ptr, ctypes.byref(inf)), "afn_get_info")
+        ms = {k: getattr(inf, "ms_" + k) for k in ("rank", "fps", "chol", "knn", "v", "fsai",
+                                                   "total")}
+        return SetupInfo(inf.n, inf.d, inf.k, inf.w, inf.rank_r, inf.rank_k_est,
+                         inf.rank_eig_branch, inf.rank_eig_count, inf.nnz_g, ms)
+
+    def landmarks(self):
+        import numpy as np
+        k = self.info().k
+        idx = np.zeros(max(k, 1), dtype=np.int32)
+        kk = _I64(0)
+        _check(lib().afn_get_landmarks(self.ptr, idx.ctypes.data, idx.shape[0], ctypes.byref(kk)),
+               "afn_get_landmarks")
+        return idx[: kk.value].copy()
+
+    def fsai(self):
+        """(rowptr, cols, vals) of G in CSR over the non-landmark points."""
+        import numpy as np
+        inf = self.info()
+        nr = inf.n - inf.k
+        rowptr = np.zeros(nr + 1, dtype=np.int64)
+        cap = max(int(inf.nnz_g), 1)
+        cols = np.zeros(cap, dtype=np.int32)
+        vals = np.zeros(cap)
+        nnz = _I64(0)
+        _check(lib().afn_get_fsai(self.ptr, rowptr.ctypes.data, cols.ctypes.data,
+                                  vals.ctypes.data, cap, ctypes.byref(nnz)), "afn_get_fsai")
+        return rowptr, cols[: nnz.value].copy(), vals[: nnz.value].copy()
+
+    def cholesky(self):
+        import numpy as np
+        k = self.info().k
+        L = np.zeros((max(k, 1), max(k, 1)), order="F")
+        _check(lib().afn_get_cholesky(self.ptr, L.ctypes.data, max(k, 1)), "afn_get_cholesky")
+        return L[:k, :k].copy(order="F")
+
+
+def afn_setup(X: torch.Tensor, l: float, mu: float, k: int = -1, w: int = 64, k_max: int = 2000,
+              m: int = 0, seed: int = 0, precision: int = AFN_FP64, stream=None) -> Handle:
+    """Algorithm 2 (landmarks by FPS, chol(K11 + mu I), FSAI of the Schur complement)."""
+    X = _dev_f64(X, "X").contiguous()
+    n, d = X.shape
+    prm = afn_params(k=k, k_max=k_max, w=w, m=m, precision=precision, reserved=0, seed=seed)
+    h = ctypes.c_void_p()
+    _check(lib().afn_setup(X.data_ptr(), n, d, l, mu, ctypes.byref(prm), _stream(stream),
+                           ctypes.byref(h)), "afn_setup")
+    return Handle(h, n, d)
+
+
+def afn_apply(h: Handle, r: torch.Tensor, out: torch.Tensor | None = None,
+              stream=None) -> torch.Tensor:
+    """z = M^{-1} r (Algorithm 3)."""
+    rp, nrhs, ld = _colmajor(r, "r")
+    if out is None:
+        out = torch.empty_like(r) if r.dim() == 1 else empty_colmajor(r.shape[0], nrhs, r.device)
+    zp, _, ldz = _colmajor(out, "out")
+    if ldz != ld:
+        raise ValueError("r and out must share a leading dimension")
+    _check(lib().afn_apply(h.ptr, rp, zp, nrhs, ld, _stream(stream)), "afn_apply")
+    return out
+
+
+def afn_pcg_solve(h: Handle, b: torch.Tensor, tol: float = 1e-6, maxit: int = 500,
+                  out: torch.Tensor | None = None, stream=None, allow_noconv: bool = True):
+    """PCG from x0 = 0; returns (x, info dict).  ENOCONV is returned in info, not raised,
+    when allow_noconv is set."""
+    bp, nrhs, ld = _colmajor(b, "b")
+    if out is None:
+        out = torch.empty_like(b) if b.dim() == 1 else empty_colmajor(b.shape[0], nrhs, b.device)
+    xp, _, ldx = _colmajor(out, "out")
+    if ldx != ld:
+        raise ValueError("b and out must share a leading dimension")
+    inf = afn_solve_info()
+    ok = (AFN_OK, AFN_ENOCONV) if allow_noconv else (AFN_OK,)
+    st = _check(lib().afn_pcg_solve(h.ptr, bp, xp, nrhs, ld, tol, maxit, ctypes.byref(inf),
+                                    _stream(stream)), "afn_pcg_solve", ok)
+    return out, dict(status=st, iterations=inf.iterations, converged=bool(inf.converged),
+                     relres=inf.relres, relres_true=inf.relres_true, ms_solve=inf.ms_solve)

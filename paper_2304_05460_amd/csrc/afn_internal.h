@@ -1,0 +1,176 @@
+// Internal declarations of libafn (gfx950).  Not part of the public C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <vector>
+
+#include "afn.h"
+
+namespace afn {
+
+// Thread-local error message (afn_last_error()).
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define AFN_HIP(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            ::afn::set_error("%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                             __LINE__);                                                \
+            return AFN_EDEVICE;                                                        \
+        }                                                                              \
+    } while (0)
+
+#define AFN_TRY(expr)                      \
+    do {                                   \
+        afn_status s_ = (expr);            \
+        if (s_ != AFN_OK) return s_;       \
+    } while (0)
+
+constexpr int kMaxD = 64;
+constexpr int kMaxW = 64;
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+// Device buffer list owned by a handle.
+struct DevArena {
+    std::vector<void *> ptrs;
+    afn_status alloc(void **p, size_t bytes);
+    template <class T>
+    afn_status alloc_n(T **p, int64_t count) {
+        return alloc(reinterpret_cast<void **>(p), sizeof(T) * (size_t)(count > 0 ? count : 1));
+    }
+    void release();
+};
+
+// Per-device scratch for entry points that do not own a handle.  Grows on
+// demand; calls that share it must be stream-ordered by the caller.
+afn_status library_scratch(size_t bytes, void **ptr);
+
+// ---------------------------------------------------------------- kernel matvec
+// Partial-sum workspace for kmv_f64 (doubles).
+int64_t kmv_splits(int64_t n);
+int64_t kmv_workspace_doubles(int64_t n);
+// y[:, c] = (K + mu I) v[:, c] for c < nrhs; X row-major n x d FP64.
+afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, const double *v,
+                   int64_t ldv, double *y, int64_t ldy, int nrhs, double *work,
+                   hipStream_t s);
+// FP32 tiles and accumulation; FP64 vectors at the interface.
+afn_status kmv_f32(const double *X, int64_t n, int d, double l, double mu, const double *v,
+                   int64_t ldv, double *y, int64_t ldy, int nrhs, void *work, hipStream_t s);
+
+// ---------------------------------------------------------------- FPS
+// Landmarks in selection order (Algorithm 6); idx_dev gets k entries, seld_dev
+// (optional) the squared selection distances.  work: fps_workspace_bytes(n).
+// err_dev is set to 1 if an invalid winner index ever appears.
+size_t fps_workspace_bytes(int64_t n);
+afn_status fps(const double *X, int64_t n, int d, int k, int32_t *idx_dev, double *seld_dev,
+               void *work, hipStream_t s, int *err_dev);
+// perm = [idx (k entries) ; the other indices ascending]; sel: n ints scratch.
+afn_status landmark_permutation(const int32_t *idx, int k, int64_t n, int32_t *perm, int *sel,
+                                hipStream_t s);
+
+// ---------------------------------------------------------------- kNN pattern
+// Row p (0 <= p < nr) of the predecessor pattern over Xr (row-major nr x d):
+// cols[p*w .. p*w+len) (ascending, p last), len = min(p+1, w), the rest -1.
+afn_status knn_pattern(const double *Xr, int64_t nr, int d, int w, int32_t *cols,
+                       hipStream_t s);
+
+// ---------------------------------------------------------------- dense factors
+// A = K11 + mu I for the first k points of Xp, column-major lda.
+afn_status fill_k11(const double *Xp, int k, int d, double l, double mu, double *A, int64_t lda,
+                    hipStream_t s);
+// K12[t + p*k] = K(x_t, x_{k+p}) for t < k, p < n - k.
+afn_status fill_k12(const double *Xp, int64_t n, int k, int d, double l, double *K12,
+                    hipStream_t s);
+// In-place lower Cholesky; *info_dev = 1 + index of the first non-positive pivot.
+afn_status cholesky(double *A, int k, int64_t lda, int *info_dev, hipStream_t s);
+// Inverses of the 64 x 64 diagonal blocks of L (dinv_doubles(k) doubles).
+int64_t dinv_doubles(int k);
+afn_status diag_inverses(const double *L, int k, double *Dinv, hipStream_t s);
+// B (k x ncols, ld k) := L^{-1} B.
+afn_status trsm_lower(const double *L, const double *Dinv, int k, double *B, int64_t ncols,
+                      hipStream_t s);
+afn_status identity(double *A, int k, hipStream_t s);
+
+// ---------------------------------------------------------------- FSAI
+// Padded rows of G (nr x w; row p has min(p+1, w) entries) for the Schur
+// complement, from V = L^{-1} K12 (k x nr) and the points.  *info_dev = 1 on
+// a non-positive pivot of a Schur block.
+afn_status fsai_rows(const double *Xp, int64_t n, int k, int d, double l, double mu,
+                     const double *V, const int32_t *cols, int w, double *gval, int *info_dev,
+                     hipStream_t s);
+// CSR of G^T: tptr (nr+1), trow/tval (nnz), rows of each column ascending.
+// work: nr 64-bit counters.
+afn_status fsai_transpose(const int32_t *cols, const double *gval, int64_t nr, int w,
+                          int64_t *tptr, int32_t *trow, double *tval, int64_t *work,
+                          hipStream_t s);
+
+// ---------------------------------------------------------------- vectors
+int64_t dot_partials(int64_t n);
+// out[c] = sum_i a[i + c*lda] b[i + c*ldb] (fixed reduction order).
+afn_status dot(const double *a, int64_t lda, const double *b, int64_t ldb, int64_t n, int nrhs,
+               double *out_dev, double *partials, hipStream_t s);
+int64_t gemv_partials(int64_t m, int64_t ncols);
+// y = base + sign * A x  (A m x ncols, column-major lda; base may be null)
+afn_status gemv_n(const double *A, int64_t lda, int64_t m, int64_t ncols, const double *x,
+                  const double *base, double sign, double *y, double *part, hipStream_t s);
+// y = base + sign * A^T x
+afn_status gemv_t(const double *A, int64_t lda, int64_t m, int64_t ncols, const double *x,
+                  const double *base, double sign, double *y, hipStream_t s);
+// u = G t (padded rows) ;  out = G^T u (CSR of G^T)
+afn_status spmv_g(const int32_t *cols, const double *gval, int64_t nr, int w, const double *t,
+                  double *u, hipStream_t s);
+afn_status spmv_gt(const int64_t *ptr, const int32_t *idx, const double *val, int64_t nr,
+                   const double *u, double *out, hipStream_t s);
+afn_status permute_gather(const double *src, int64_t lds, double *dst, int64_t ldd,
+                          const int32_t *perm, int64_t n, int nrhs, hipStream_t s);
+afn_status permute_scatter(const double *src, int64_t lds, double *dst, int64_t ldd,
+                           const int32_t *perm, int64_t n, int nrhs, hipStream_t s);
+afn_status gather_points(const double *X, const int32_t *perm, int64_t n, int d, double *Xp,
+                         hipStream_t s);
+// PCG scalar slots: sc[0] rho, sc[1] p'q, sc[2] r'r, sc[3] rho_new, sc[4] alpha,
+// sc[5] beta, sc[6] b'b, sc[7] true residual squared.
+afn_status pcg_alpha_launch(double *sc, hipStream_t s);
+afn_status pcg_beta_launch(double *sc, hipStream_t s);
+afn_status pcg_xr_launch(double *x, double *r, const double *p, const double *q, const double *sc,
+                         int64_t n, double *part, double *rr_out, hipStream_t s);
+afn_status pcg_p_launch(double *p, const double *z, const double *sc, int64_t n, hipStream_t s);
+afn_status sub_launch(const double *b, const double *y, double *r, int64_t n, hipStream_t s);
+// *flag |= 1 if a value is not finite
+afn_status finite_launch(const double *a, int64_t n, int *flag, hipStream_t s);
+
+}  // namespace afn
+
+// ------------------------------------------------------------------ handle
+struct afn_handle {
+    int device = 0;
+    int64_t n = 0, nr = 0;
+    int d = 0, k = 0, w = 0;
+    double l = 1.0, mu = 0.0;
+    afn::DevArena arena;
+    double *Xp = nullptr;       // n x d, block order (landmarks first)
+    int32_t *perm = nullptr;    // n: block position -> original index
+    double *L = nullptr;        // k x k column-major lower
+    double *Linv = nullptr;     // k x k column-major lower
+    double *Dinv = nullptr;     // inverses of the 64 x 64 diagonal blocks of L
+    double *V = nullptr;        // k x nr column-major: V = L^{-1} K12
+    int32_t *cols = nullptr;    // nr x w padded pattern rows (ascending, diagonal last)
+    double *gval = nullptr;     // nr x w padded values of G
+    int64_t *tptr = nullptr;    // CSR of G^T: nr + 1
+    int32_t *trow = nullptr;    // nnz
+    double *tval = nullptr;     // nnz
+    int64_t nnz = 0;
+    int *flags = nullptr;       // device status flags
+    double *work = nullptr;     // PCG / apply workspace
+    int64_t work_doubles = 0;
+    int64_t work_rhs = 0;       // right-hand sides the workspace is sized for
+    double *host_sc = nullptr;  // pinned host copy of PCG scalars
+    afn_setup_info info{};
+};

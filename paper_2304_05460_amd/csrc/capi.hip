@@ -1,0 +1,487 @@
+// C-ABI of libafn: preconditioner construction (Algorithm 2), application
+// (Algorithm 3) and preconditioned CG (Algorithm 5, AFN branch).
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "afn_internal.h"
+
+namespace afn {
+
+// Rank estimation (Algorithm 4); defined in rank.hip.
+afn_status rank_estimate(const double *X, int64_t n, int d, double l, double mu, int m,
+                         int kmax, uint64_t seed, hipStream_t s, afn_setup_info *info, int *k_out);
+
+namespace {
+
+struct Timer {
+    hipEvent_t ev[8] = {};
+    int used = 0;
+    bool ok = true;
+    Timer()
+    {
+        for (auto &e : ev)
+            if (hipEventCreate(&e) != hipSuccess) ok = false;
+    }
+    ~Timer()
+    {
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    void mark(int i, hipStream_t s)
+    {
+        if (ok) (void)hipEventRecord(ev[i], s);
+    }
+    double ms(int a, int b)
+    {
+        float t = 0.f;
+        if (!ok || hipEventElapsedTime(&t, ev[a], ev[b]) != hipSuccess) return -1.0;
+        return t;
+    }
+};
+
+// Workspace layout inside afn_handle::work (doubles).
+struct WorkLayout {
+    double *kmv, *dotp, *gemvp, *y1, *t, *u, *y1b, *x, *r, *z, *p, *q, *bp, *tmp, *rp, *sp, *sc;
+};
+
+int64_t work_doubles(int64_t n, int k, int64_t nr, WorkLayout *L, double *base)
+{
+    int64_t off = 0;
+    auto take = [&](int64_t cnt) {
+        double *ptr = base ? base + off : nullptr;
+        off += round_up(cnt > 0 ? cnt : 1, 32);
+        return ptr;
+    };
+    WorkLayout w;
+    int64_t gp = gemv_partials(k, nr > k ? nr : k);
+    int64_t gp2 = gemv_partials(k, k);
+    w.kmv = take(kmv_workspace_doubles(n));
+    w.dotp = take(dot_partials(n));
+    w.gemvp = take(gp > gp2 ? gp : gp2);
+    w.y1 = take(k);
+    w.t = take(nr);
+    w.u = take(nr);
+    w.y1b = take(k);
+    w.x = take(n);
+    w.r = take(n);
+    w.z = take(n);
+    w.p = take(n);
+    w.q = take(n);
+    w.bp = take(n);
+    w.tmp = take(n);
+    w.rp = take(n);
+    w.sp = take(n);
+    w.sc = take(16);
+    if (L) *L = w;
+    return off;
+}
+
+// s = M^{-1} r in block order (landmarks first): Algorithm 3 with
+// V = L^{-1} K12 and Linv = L^{-1}:
+//   y1 = Linv r1 ; t = r2 - V^T y1 ; s2 = G^T (G t) ; s1 = Linv^T (y1 - V s2)
+afn_status apply_block(afn_handle *h, const double *rp, double *sp, const WorkLayout &w,
+                       hipStream_t s)
+{
+    const int k = h->k;
+    const int64_t nr = h->nr;
+    if (k > 0) AFN_TRY(gemv_n(h->Linv, k, k, k, rp, nullptr, 1.0, w.y1, w.gemvp, s));
+    if (nr > 0) {
+        const double *t = rp + k;
+        if (k > 0) {
+            AFN_TRY(gemv_t(h->V, k, k, nr, w.y1, rp + k, -1.0, w.t, s));
+            t = w.t;
+        }
+        AFN_TRY(spmv_g(h->cols, h->gval, nr, h->w, t, w.u, s));
+        AFN_TRY(spmv_gt(h->tptr, h->trow, h->tval, nr, w.u, sp + k, s));
+    }
+    if (k > 0) {
+        const double *y = w.y1;
+        if (nr > 0) {
+            AFN_TRY(gemv_n(h->V, k, k, nr, sp + k, w.y1, -1.0, w.y1b, w.gemvp, s));
+            y = w.y1b;
+        }
+        AFN_TRY(gemv_t(h->Linv, k, k, k, y, nullptr, 1.0, sp, s));
+    }
+    return AFN_OK;
+}
+
+afn_status check_flags(afn_handle *h, hipStream_t s)
+{
+    int f[4] = {0, 0, 0, 0};
+    AFN_HIP(hipMemcpyAsync(f, h->flags, sizeof f, hipMemcpyDeviceToHost, s));
+    AFN_HIP(hipStreamSynchronize(s));
+    if (f[0]) {
+        set_error("afn_setup: X holds a non-finite coordinate");
+        return AFN_EINVAL;
+    }
+    if (f[1]) {
+        set_error("afn_setup: K11 + mu I is not positive definite (pivot %d)", f[1] - 1);
+        return AFN_ENOTSPD;
+    }
+    if (f[2]) {
+        set_error("afn_setup: an FSAI block of the Schur complement is not positive definite");
+        return AFN_ENOTSPD;
+    }
+    if (f[3]) {
+        set_error("afn_setup: landmark selection produced an invalid index");
+        return AFN_EDEVICE;
+    }
+    return AFN_OK;
+}
+
+afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, const afn_params *prm,
+                      hipStream_t s, afn_handle *h)
+{
+    Timer tm;
+    tm.mark(0, s);
+    AFN_HIP(hipGetDevice(&h->device));
+    h->n = n;
+    h->d = d;
+    h->l = l;
+    h->mu = mu;
+    h->w = prm->w;
+    AFN_TRY(h->arena.alloc_n(&h->flags, 16));
+    AFN_HIP(hipMemsetAsync(h->flags, 0, sizeof(int) * 16, s));
+    AFN_TRY(finite_launch(X, n * d, h->flags + 0, s));
+    // landmark count
+    h->info.rank_r = -1;
+    h->info.rank_k_est = -1;
+    h->info.rank_eig_branch = 0;
+    h->info.rank_eig_count = -1;
+    int k = prm->k;
+    if (k < 0) {
+        const int m = prm->m > 0 ? (int)(prm->m < n ? prm->m : n) : (int)(n < 2000 ? n : 2000);
+        const int kmax = prm->k_max > 0 ? prm->k_max : 2000;
+        AFN_TRY(rank_estimate(X, n, d, l, mu, m, kmax, prm->seed, s, &h->info, &k));
+    }
+    tm.mark(1, s);
+    h->k = k;
+    h->nr = n - k;
+    const int64_t nr = h->nr;
+    // FPS and the block order
+    DevArena tmp;
+    struct TmpGuard {
+        DevArena &a;
+        ~TmpGuard() { a.release(); }
+    } guard{tmp};
+    AFN_TRY(h->arena.alloc_n(&h->perm, n));
+    int32_t *idx = nullptr;
+    void *fws = nullptr;
+    int *sel = nullptr;
+    AFN_TRY(tmp.alloc_n(&idx, k));
+    AFN_TRY(tmp.alloc(&fws, fps_workspace_bytes(n)));
+    AFN_TRY(tmp.alloc_n(&sel, n));
+    AFN_TRY(fps(X, n, d, k, idx, nullptr, fws, s, h->flags + 3));
+    AFN_TRY(landmark_permutation(idx, k, n, h->perm, sel, s));
+    AFN_TRY(h->arena.alloc_n(&h->Xp, n * d));
+    AFN_TRY(gather_points(X, h->perm, n, d, h->Xp, s));
+    tm.mark(2, s);
+    // L = chol(K11 + mu I), Linv, V = L^{-1} K12
+    if (k > 0) {
+        AFN_TRY(h->arena.alloc_n(&h->L, (int64_t)k * k));
+        AFN_TRY(h->arena.alloc_n(&h->Linv, (int64_t)k * k));
+        AFN_TRY(h->arena.alloc_n(&h->Dinv, dinv_doubles(k)));
+        AFN_TRY(fill_k11(h->Xp, k, d, l, mu, h->L, k, s));
+        AFN_TRY(cholesky(h->L, k, k, h->flags + 1, s));
+        AFN_TRY(diag_inverses(h->L, k, h->Dinv, s));
+        AFN_TRY(identity(h->Linv, k, s));
+        AFN_TRY(trsm_lower(h->L, h->Dinv, k, h->Linv, k, s));
+    }
+    tm.mark(3, s);
+    if (nr > 0) {
+        AFN_TRY(h->arena.alloc_n(&h->cols, nr * h->w));
+        AFN_TRY(knn_pattern(h->Xp + (int64_t)k * d, nr, d, h->w, h->cols, s));
+    }
+    tm.mark(4, s);
+    if (k > 0 && nr > 0) {
+        AFN_TRY(h->arena.alloc_n(&h->V, (int64_t)k * nr));
+        AFN_TRY(fill_k12(h->Xp, n, k, d, l, h->V, s));
+        AFN_TRY(trsm_lower(h->L, h->Dinv, k, h->V, nr, s));
+    }
+    tm.mark(5, s);
+    if (nr > 0) {
+        AFN_TRY(h->arena.alloc_n(&h->gval, nr * h->w));
+        AFN_TRY(fsai_rows(h->Xp, n, k, d, l, mu, h->V, h->cols, h->w, h->gval, h->flags + 2, s));
+        AFN_TRY(h->arena.alloc_n(&h->tptr, nr + 1));
+        AFN_TRY(h->arena.alloc_n(&h->trow, nr * h->w));
+        AFN_TRY(h->arena.alloc_n(&h->tval, nr * h->w));
+        int64_t *cnt = nullptr;
+        AFN_TRY(tmp.alloc_n(&cnt, nr));
+        AFN_TRY(fsai_transpose(h->cols, h->gval, nr, h->w, h->tptr, h->trow, h->tval, cnt, s));
+    }
+    tm.mark(6, s);
+    // workspace for apply / PCG
+    h->work_doubles = work_doubles(n, k, nr, nullptr, nullptr);
+    AFN_TRY(h->arena.alloc_n(&h->work, h->work_doubles));
+    AFN_HIP(hipHostMalloc((void **)&h->host_sc, 16 * sizeof(double), hipHostMallocDefault));
+    AFN_TRY(check_flags(h, s));
+    h->nnz = 0;
+    if (nr > 0) AFN_HIP(hipMemcpy(&h->nnz, h->tptr + nr, sizeof(int64_t), hipMemcpyDeviceToHost));
+    tm.mark(7, s);
+    AFN_HIP(hipStreamSynchronize(s));
+    afn_setup_info &inf = h->info;
+    inf.n = n;
+    inf.d = d;
+    inf.k = k;
+    inf.w = h->w;
+    inf.nnz_g = h->nnz;
+    inf.ms_rank = tm.ms(0, 1);
+    inf.ms_fps = tm.ms(1, 2);
+    inf.ms_chol = tm.ms(2, 3);
+    inf.ms_knn = tm.ms(3, 4);
+    inf.ms_v = tm.ms(4, 5);
+    inf.ms_fsai = tm.ms(5, 6);
+    inf.ms_total = tm.ms(0, 7);
+    return AFN_OK;
+}
+
+afn_status pcg_one(afn_handle *h, const double *b, double *xout, double tol, int maxit,
+                   const WorkLayout &w, hipStream_t s, int *iters, double *relres,
+                   double *relres_true, int *converged)
+{
+    const int64_t n = h->n;
+    double *sc = w.sc;
+    double *hs = h->host_sc;
+    AFN_TRY(permute_gather(b, n, w.bp, n, h->perm, n, 1, s));
+    AFN_TRY(dot(w.bp, n, w.bp, n, n, 1, sc + 6, w.dotp, s));
+    AFN_HIP(hipMemsetAsync(w.x, 0, sizeof(double) * n, s));
+    AFN_HIP(hipMemcpyAsync(w.r, w.bp, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    AFN_HIP(hipMemcpyAsync(hs + 6, sc + 6, sizeof(double), hipMemcpyDeviceToHost, s));
+    AFN_HIP(hipStreamSynchronize(s));
+    const double bnorm = std::sqrt(hs[6]);
+    *iters = 0;
+    *relres = 0.0;
+    *relres_true = 0.0;
+    *converged = 1;
+    if (!(bnorm > 0.0)) {
+        if (!(bnorm == 0.0)) {
+            set_error("afn_pcg_solve: right-hand side holds a non-finite value");
+            *converged = 0;
+            *relres = NAN;
+            AFN_TRY(permute_scatter(w.x, n, xout, n, h->perm, n, 1, s));
+            return AFN_EBREAKDOWN;
+        }
+        AFN_TRY(permute_scatter(w.x, n, xout, n, h->perm, n, 1, s));
+        return AFN_OK;
+    }
+    AFN_TRY(apply_block(h, w.r, w.z, w, s));
+    AFN_HIP(hipMemcpyAsync(w.p, w.z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    AFN_TRY(dot(w.r, n, w.z, n, n, 1, sc + 0, w.dotp, s));
+    afn_status status = AFN_ENOCONV;
+    *converged = 0;
+    *relres = 1.0;
+    for (int it = 0; it < maxit; ++it) {
+        AFN_TRY(kmv_f64(h->Xp, n, h->d, h->l, h->mu, w.p, n, w.q, n, 1, w.kmv, s));
+        AFN_TRY(dot(w.p, n, w.q, n, n, 1, sc + 1, w.dotp, s));
+        AFN_TRY(pcg_alpha_launch(sc, s));
+        AFN_TRY(pcg_xr_launch(w.x, w.r, w.p, w.q, sc, n, w.dotp, sc + 2, s));
+        AFN_HIP(hipMemcpyAsync(hs + 1, sc + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        AFN_HIP(hipStreamSynchronize(s));
+        *iters = it + 1;
+        const double pq = hs[1];
+        const double rel = std::sqrt(hs[2]) / bnorm;
+        *relres = rel;
+        if (!(pq > 0.0) || !(rel == rel)) {
+            set_error("afn_pcg_solve: breakdown at iteration %d (p'Ap = %g)", it + 1, pq);
+            status = AFN_EBREAKDOWN;
+            break;
+        }
+        if (rel <= tol) {
+            status = AFN_OK;
+            *converged = 1;
+            break;
+        }
+        AFN_TRY(apply_block(h, w.r, w.z, w, s));
+        AFN_TRY(dot(w.r, n, w.z, n, n, 1, sc + 3, w.dotp, s));
+        AFN_TRY(pcg_beta_launch(sc, s));
+        AFN_TRY(pcg_p_launch(w.p, w.z, sc, n, s));
+    }
+    // true residual in FP64
+    AFN_TRY(kmv_f64(h->Xp, n, h->d, h->l, h->mu, w.x, n, w.q, n, 1, w.kmv, s));
+    AFN_TRY(sub_launch(w.bp, w.q, w.tmp, n, s));
+    AFN_TRY(dot(w.tmp, n, w.tmp, n, n, 1, sc + 7, w.dotp, s));
+    AFN_HIP(hipMemcpyAsync(hs + 7, sc + 7, sizeof(double), hipMemcpyDeviceToHost, s));
+    AFN_TRY(permute_scatter(w.x, n, xout, n, h->perm, n, 1, s));
+    AFN_HIP(hipStreamSynchronize(s));
+    *relres_true = std::sqrt(hs[7]) / bnorm;
+    if (status == AFN_ENOCONV)
+        set_error("afn_pcg_solve: no convergence in %d iterations (relres %g)", maxit, *relres);
+    return status;
+}
+
+}  // namespace
+}  // namespace afn
+
+using namespace afn;
+
+extern "C" {
+
+afn_status afn_setup(const double *X_dev, int64_t n, int32_t d, double l, double mu,
+                     const afn_params *prm, void *stream, afn_handle **out)
+{
+    clear_error();
+    if (!out) {
+        set_error("afn_setup: out is NULL");
+        return AFN_EINVAL;
+    }
+    *out = nullptr;
+    if (!X_dev || !prm || n < 1 || n > INT32_MAX - 1 || d < 1 || d > kMaxD || !(l > 0) ||
+        !std::isfinite(l) || !(mu >= 0) || !std::isfinite(mu) || prm->k < -1 || prm->k > n ||
+        prm->w < 1 || prm->w > kMaxW || prm->reserved != 0 ||
+        (prm->precision != AFN_FP64 && prm->precision != AFN_FP32)) {
+        set_error("afn_setup: invalid argument (n=%lld d=%d l=%g mu=%g k=%d w=%d)", (long long)n, d,
+                  l, mu, prm ? prm->k : 0, prm ? prm->w : 0);
+        return AFN_EINVAL;
+    }
+    std::unique_ptr<afn_handle> h(new afn_handle());
+    afn_status st = setup_impl(X_dev, n, d, l, mu, prm, (hipStream_t)stream, h.get());
+    if (st != AFN_OK) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        if (h->host_sc) (void)hipHostFree(h->host_sc);
+        h->arena.release();
+        return st;
+    }
+    *out = h.release();
+    return AFN_OK;
+}
+
+afn_status afn_apply(afn_handle *h, const double *r_dev, double *z_dev, int32_t nrhs, int64_t ld,
+                     void *stream)
+{
+    clear_error();
+    if (!h || !r_dev || !z_dev || nrhs < 1 || ld < h->n) {
+        set_error("afn_apply: invalid argument");
+        return AFN_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    WorkLayout w;
+    work_doubles(h->n, h->k, h->nr, &w, h->work);
+    for (int c = 0; c < nrhs; ++c) {
+        AFN_TRY(permute_gather(r_dev + c * ld, h->n, w.rp, h->n, h->perm, h->n, 1, s));
+        AFN_TRY(apply_block(h, w.rp, w.sp, w, s));
+        AFN_TRY(permute_scatter(w.sp, h->n, z_dev + c * ld, h->n, h->perm, h->n, 1, s));
+    }
+    return AFN_OK;
+}
+
+afn_status afn_pcg_solve(afn_handle *h, const double *b_dev, double *x_dev, int32_t nrhs,
+                         int64_t ld, double tol, int32_t maxit, afn_solve_info *info,
+                         void *stream)
+{
+    clear_error();
+    if (!h || !b_dev || !x_dev || nrhs < 1 || ld < h->n || !(tol > 0) || maxit < 1) {
+        set_error("afn_pcg_solve: invalid argument");
+        return AFN_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    WorkLayout w;
+    work_doubles(h->n, h->k, h->nr, &w, h->work);
+    Timer tm;
+    tm.mark(0, s);
+    afn_status worst = AFN_OK;
+    int it_max = 0, conv_all = 1;
+    double rel_max = 0.0, true_max = 0.0;
+    for (int c = 0; c < nrhs; ++c) {
+        int it = 0, conv = 0;
+        double rel = 0, rt = 0;
+        afn_status st = pcg_one(h, b_dev + c * ld, x_dev + c * ld, tol, maxit, w, s, &it, &rel,
+                                &rt, &conv);
+        if (st != AFN_OK && st != AFN_ENOCONV && st != AFN_EBREAKDOWN) return st;
+        if (st != AFN_OK && worst == AFN_OK) worst = st;
+        if (st == AFN_EBREAKDOWN) worst = st;
+        it_max = it > it_max ? it : it_max;
+        conv_all &= conv;
+        rel_max = rel > rel_max || rel != rel ? rel : rel_max;
+        true_max = rt > true_max || rt != rt ? rt : true_max;
+    }
+    tm.mark(1, s);
+    AFN_HIP(hipStreamSynchronize(s));
+    if (info) {
+        info->iterations = it_max;
+        info->converged = conv_all;
+        info->relres = rel_max;
+        info->relres_true = true_max;
+        info->ms_solve = tm.ms(0, 1);
+    }
+    return worst;
+}
+
+afn_status afn_get_info(const afn_handle *h, afn_setup_info *info)
+{
+    clear_error();
+    if (!h || !info) {
+        set_error("afn_get_info: invalid argument");
+        return AFN_EINVAL;
+    }
+    *info = h->info;
+    return AFN_OK;
+}
+
+afn_status afn_get_landmarks(const afn_handle *h, int32_t *idx_host, int64_t cap, int64_t *k_out)
+{
+    clear_error();
+    if (!h || !k_out || (h->k > 0 && (!idx_host || cap < h->k))) {
+        set_error("afn_get_landmarks: invalid argument");
+        return AFN_EINVAL;
+    }
+    *k_out = h->k;
+    if (h->k > 0)
+        AFN_HIP(hipMemcpy(idx_host, h->perm, sizeof(int32_t) * h->k, hipMemcpyDeviceToHost));
+    return AFN_OK;
+}
+
+afn_status afn_get_fsai(const afn_handle *h, int64_t *rowptr, int32_t *cols_host, double *vals_host,
+                        int64_t cap, int64_t *nnz_out)
+{
+    clear_error();
+    if (!h || !rowptr || !nnz_out || (h->nnz > 0 && (!cols_host || cap < h->nnz))) {
+        set_error("afn_get_fsai: invalid argument");
+        return AFN_EINVAL;
+    }
+    const int64_t nr = h->nr, w = h->w;
+    *nnz_out = h->nnz;
+    rowptr[0] = 0;
+    if (nr <= 0) return AFN_OK;
+    std::vector<int32_t> c((size_t)(nr * w));
+    std::vector<double> g(vals_host ? (size_t)(nr * w) : 0);
+    AFN_HIP(hipMemcpy(c.data(), h->cols, sizeof(int32_t) * nr * w, hipMemcpyDeviceToHost));
+    if (vals_host)
+        AFN_HIP(hipMemcpy(g.data(), h->gval, sizeof(double) * nr * w, hipMemcpyDeviceToHost));
+    int64_t e = 0;
+    for (int64_t p = 0; p < nr; ++p) {
+        const int64_t m = p + 1 < w ? p + 1 : w;
+        for (int64_t a = 0; a < m; ++a, ++e) {
+            cols_host[e] = c[(size_t)(p * w + a)];
+            if (vals_host) vals_host[e] = g[(size_t)(p * w + a)];
+        }
+        rowptr[p + 1] = e;
+    }
+    return AFN_OK;
+}
+
+afn_status afn_get_cholesky(const afn_handle *h, double *L_host, int64_t ld)
+{
+    clear_error();
+    if (!h || (h->k > 0 && (!L_host || ld < h->k))) {
+        set_error("afn_get_cholesky: invalid argument");
+        return AFN_EINVAL;
+    }
+    const int k = h->k;
+    if (k == 0) return AFN_OK;
+    AFN_HIP(hipMemcpy2D(L_host, sizeof(double) * ld, h->L, sizeof(double) * k, sizeof(double) * k, k,
+                        hipMemcpyDeviceToHost));
+    return AFN_OK;
+}
+
+void afn_destroy(afn_handle *h)
+{
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    if (h->host_sc) (void)hipHostFree(h->host_sc);
+    h->arena.release();
+    delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,320 @@
+// Dense factors of the landmark block (Algorithm 2):
+//   L = chol(K11 + mu I)           blocked right-looking Cholesky, 64-wide panels
+//   Linv = L^{-1}, V = L^{-1} K12   left-looking blocked triangular solve
+// All matrices column-major FP64.  Kernel values exp(-(d2 / l^2)) with the
+// squared distance by the fixed fma chain.
+#include "afn_internal.h"
+
+namespace afn {
+namespace {
+
+constexpr int NB = 64;
+
+__device__ __forceinline__ double kval(const double *a, const double *b, int d, double l2)
+{
+    double acc = 0.0;
+    for (int t = 0; t < d; ++t) {
+        double del = a[t] - b[t];
+        acc = __builtin_fma(del, del, acc);
+    }
+    return exp(-(acc / l2));
+}
+
+__global__ __launch_bounds__(256) void k11_fill(const double *__restrict__ Xp, int k, int d,
+                                                double l2, double mu, double *__restrict__ A,
+                                                int64_t lda)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)k * k) return;
+    int j = (int)(e / k), i = (int)(e - (int64_t)j * k);
+    if (i < j) {     // only the lower triangle is factored; keep the upper zero
+        A[i + (int64_t)j * lda] = 0.0;
+        return;
+    }
+    double v = kval(Xp + (int64_t)i * d, Xp + (int64_t)j * d, d, l2);
+    A[i + (int64_t)j * lda] = v + (i == j ? mu : 0.0);
+}
+
+__global__ __launch_bounds__(256) void k12_fill(const double *__restrict__ Xp, int64_t n, int k,
+                                                int d, double l2, double *__restrict__ K12)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t nr = n - k;
+    if (e >= (int64_t)k * nr) return;
+    int64_t p = e / k;
+    int t = (int)(e - p * k);
+    K12[e] = kval(Xp + (int64_t)t * d, Xp + (k + p) * d, d, l2);
+}
+
+// Unblocked Cholesky of the jb x jb diagonal block at (j0, j0), in LDS.
+__global__ __launch_bounds__(256) void potrf_diag(double *A, int64_t lda, int j0, int jb, int *info)
+{
+    __shared__ double S[NB][NB + 1];   // S[col][row]
+    const int tid = threadIdx.x;
+    for (int e = tid; e < jb * jb; e += 256) {
+        int c = e / jb, r = e - c * jb;
+        S[c][r] = A[(j0 + r) + (int64_t)(j0 + c) * lda];
+    }
+    __syncthreads();
+    for (int j = 0; j < jb; ++j) {
+        if (tid == 0) {
+            double p = S[j][j];
+            if (!(p > 0.0)) {
+                atomicCAS(info, 0, j0 + j + 1);
+                p = 1.0;
+            }
+            S[j][j] = sqrt(p);
+        }
+        __syncthreads();
+        const double piv = S[j][j];
+        for (int r = j + 1 + tid; r < jb; r += 256) S[j][r] /= piv;
+        __syncthreads();
+        const int m = jb - j - 1;
+        for (int e = tid; e < m * m; e += 256) {
+            int c = j + 1 + e / m, r = j + 1 + e % m;
+            if (r >= c) S[c][r] -= S[j][r] * S[j][c];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < jb * jb; e += 256) {
+        int c = e / jb, r = e - c * jb;
+        A[(j0 + r) + (int64_t)(j0 + c) * lda] = r >= c ? S[c][r] : 0.0;
+    }
+}
+
+// Rows below the diagonal block: L21 = A21 L11^{-T}, 64 rows per workgroup.
+__global__ __launch_bounds__(64) void trsm_panel(double *A, int64_t lda, int j0, int jb, int k)
+{
+    __shared__ double Ls[NB][NB + 1];  // Ls[col][row] of L11
+    __shared__ double Xs[NB][NB + 1];  // Xs[col][local row]
+    const int tid = threadIdx.x;
+    for (int e = tid; e < jb * jb; e += 64) {
+        int c = e / jb, r = e - c * jb;
+        Ls[c][r] = A[(j0 + r) + (int64_t)(j0 + c) * lda];
+    }
+    const int64_t row = (int64_t)j0 + jb + (int64_t)blockIdx.x * 64 + tid;
+    const bool ok = row < k;
+    for (int c = 0; c < jb; ++c) Xs[c][tid] = ok ? A[row + (int64_t)(j0 + c) * lda] : 0.0;
+    __syncthreads();
+    for (int c = 0; c < jb; ++c) {
+        double s = Xs[c][tid];
+        for (int t = 0; t < c; ++t) s -= Ls[t][c] * Xs[t][tid];
+        Xs[c][tid] = s / Ls[c][c];
+    }
+    if (ok)
+        for (int c = 0; c < jb; ++c) A[row + (int64_t)(j0 + c) * lda] = Xs[c][tid];
+}
+
+// Trailing update A22 -= L21 L21^T on lower 64 x 64 tiles.
+__global__ __launch_bounds__(256) void syrk_update(double *A, int64_t lda, int j0, int jb, int k)
+{
+    const int I = blockIdx.y, C = blockIdx.x;
+    if (C > I) return;
+    __shared__ double Ri[NB][NB + 2];  // Ri[t][row]
+    __shared__ double Rc[NB][NB + 2];  // Rc[t][col]
+    const int base = j0 + jb;
+    const int r0 = base + I * NB, c0 = base + C * NB;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < NB * jb; e += 256) {
+        int t = e / NB, r = e - t * NB;
+        Ri[t][r] = r0 + r < k ? A[(r0 + r) + (int64_t)(j0 + t) * lda] : 0.0;
+        Rc[t][r] = c0 + r < k ? A[(c0 + r) + (int64_t)(j0 + t) * lda] : 0.0;
+    }
+    __syncthreads();
+    const int ty = tid / 16, tx = tid % 16;
+    double acc[4][4] = {};
+    for (int t = 0; t < jb; ++t) {
+        double a[4], b[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) { a[q] = Ri[t][ty * 4 + q]; b[q] = Rc[t][tx * 4 + q]; }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[q][u] = __builtin_fma(a[q], b[u], acc[q][u]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int r = r0 + ty * 4 + q, c = c0 + tx * 4 + u;
+            if (r < k && c < k && r >= c) A[r + (int64_t)c * lda] -= acc[q][u];
+        }
+}
+
+// Inverse of each 64 x 64 lower diagonal block of L; identity-padded past k.
+// Dinv[b] column-major 64 x 64.  Thread c forms column c by forward
+// substitution on e_c.
+__global__ __launch_bounds__(64) void diag_inverse(const double *L, int k, double *Dinv)
+{
+    __shared__ double Ls[NB][NB + 1];  // Ls[col][row]
+    __shared__ double Ys[NB][NB + 1];  // Ys[c][row]: column c of the inverse
+    const int b = blockIdx.x, c = threadIdx.x;
+    const int j0 = b * NB;
+    const int jb = k - j0 < NB ? k - j0 : NB;
+    for (int col = 0; col < NB; ++col)
+        Ls[col][c] = (c < jb && col < jb) ? L[(j0 + c) + (int64_t)(j0 + col) * k]
+                                          : (c == col ? 1.0 : 0.0);
+    __syncthreads();
+    for (int i = 0; i < NB; ++i) {
+        double s = (i == c) ? 1.0 : 0.0;
+        if (i > c)
+            for (int t = c; t < i; ++t) s -= Ls[t][i] * Ys[c][t];
+        Ys[c][i] = i < c ? 0.0 : s / Ls[i][i];
+    }
+    double *out = Dinv + (int64_t)b * NB * NB + (int64_t)c * NB;
+    for (int i = 0; i < NB; ++i) out[i] = Ys[c][i];
+}
+
+// B (k x ncols, ld k) := L^{-1} B, left-looking by 64-row blocks; one
+// workgroup per 64-column tile (so every column tile is solved by the same
+// workgroup in order and no cross-workgroup synchronization is needed).
+__global__ __launch_bounds__(256) void trsm_left_lower(const double *__restrict__ L,
+                                                       const double *__restrict__ Dinv, int k,
+                                                       double *B, int64_t ncols)
+{
+    __shared__ double Ls[NB][NB + 2];  // Ls[t][row]
+    __shared__ double Xs[NB][NB + 2];  // Xs[t][col]
+    const int tid = threadIdx.x;
+    const int ty = tid / 16, tx = tid % 16;
+    const int64_t c0 = (int64_t)blockIdx.x * NB;
+    const int nblk = (int)ceil_div(k, NB);
+    for (int I = 0; I < nblk; ++I) {
+        const int r0 = I * NB;
+        double acc[4][4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                int r = r0 + ty * 4 + q;
+                int64_t c = c0 + tx * 4 + u;
+                acc[q][u] = (r < k && c < ncols) ? B[r + c * k] : 0.0;
+            }
+        for (int T = 0; T < I; ++T) {
+            __syncthreads();
+            for (int e = tid; e < NB * NB; e += 256) {
+                int t = e / NB, r = e - t * NB;   // Ls[t][r] = L[r0 + r, T*NB + t]
+                Ls[t][r] = r0 + r < k ? L[(r0 + r) + (int64_t)(T * NB + t) * k] : 0.0;
+                int cc = e / NB, tt = e - cc * NB;  // Xs[tt][cc] = B[T*NB + tt, c0 + cc]
+                Xs[tt][cc] = c0 + cc < ncols ? B[(T * NB + tt) + (c0 + cc) * k] : 0.0;
+            }
+            __syncthreads();
+            for (int t = 0; t < NB; ++t) {
+                double a[4], b[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) { a[q] = Ls[t][ty * 4 + q]; b[q] = Xs[t][tx * 4 + q]; }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc[q][u] = __builtin_fma(-a[q], b[u], acc[q][u]);
+            }
+        }
+        __syncthreads();
+        // X_I = Dinv_I * acc
+        for (int e = tid; e < NB * NB; e += 256) {
+            int t = e / NB, r = e - t * NB;     // Ls[t][r] = Dinv_I[r, t]
+            Ls[t][r] = Dinv[(int64_t)I * NB * NB + r + (int64_t)t * NB];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) Xs[ty * 4 + q][tx * 4 + u] = acc[q][u];
+        __syncthreads();
+        double out[4][4] = {};
+        for (int t = 0; t < NB; ++t) {
+            double a[4], b[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) { a[q] = Ls[t][ty * 4 + q]; b[q] = Xs[t][tx * 4 + q]; }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) out[q][u] = __builtin_fma(a[q], b[u], out[q][u]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                int r = r0 + ty * 4 + q;
+                int64_t c = c0 + tx * 4 + u;
+                if (r < k && c < ncols) B[r + c * k] = out[q][u];
+            }
+    }
+}
+
+__global__ __launch_bounds__(256) void set_identity(double *A, int k)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)k * k) return;
+    int j = (int)(e / k), i = (int)(e - (int64_t)j * k);
+    A[e] = i == j ? 1.0 : 0.0;
+}
+
+}  // namespace
+
+afn_status fill_k11(const double *Xp, int k, int d, double l, double mu, double *A, int64_t lda,
+                    hipStream_t s)
+{
+    if (k <= 0) return AFN_OK;
+    hipLaunchKernelGGL(k11_fill, dim3((unsigned)ceil_div((int64_t)k * k, 256)), dim3(256), 0, s, Xp,
+                       k, d, l * l, mu, A, lda);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status fill_k12(const double *Xp, int64_t n, int k, int d, double l, double *K12,
+                    hipStream_t s)
+{
+    int64_t total = (int64_t)k * (n - k);
+    if (total <= 0) return AFN_OK;
+    hipLaunchKernelGGL(k12_fill, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, Xp, n, k, d,
+                       l * l, K12);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status cholesky(double *A, int k, int64_t lda, int *info, hipStream_t s)
+{
+    for (int j0 = 0; j0 < k; j0 += NB) {
+        const int jb = k - j0 < NB ? k - j0 : NB;
+        hipLaunchKernelGGL(potrf_diag, dim3(1), dim3(256), 0, s, A, lda, j0, jb, info);
+        const int rest = k - j0 - jb;
+        if (rest > 0) {
+            hipLaunchKernelGGL(trsm_panel, dim3((unsigned)ceil_div(rest, 64)), dim3(64), 0, s, A, lda,
+                               j0, jb, k);
+            const unsigned T = (unsigned)ceil_div(rest, NB);
+            hipLaunchKernelGGL(syrk_update, dim3(T, T), dim3(256), 0, s, A, lda, j0, jb, k);
+        }
+        AFN_HIP(hipGetLastError());
+    }
+    return AFN_OK;
+}
+
+int64_t dinv_doubles(int k) { return ceil_div(k, NB) * NB * NB; }
+
+afn_status diag_inverses(const double *L, int k, double *Dinv, hipStream_t s)
+{
+    if (k <= 0) return AFN_OK;
+    hipLaunchKernelGGL(diag_inverse, dim3((unsigned)ceil_div(k, NB)), dim3(64), 0, s, L, k, Dinv);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status trsm_lower(const double *L, const double *Dinv, int k, double *B, int64_t ncols,
+                      hipStream_t s)
+{
+    if (k <= 0 || ncols <= 0) return AFN_OK;
+    hipLaunchKernelGGL(trsm_left_lower, dim3((unsigned)ceil_div(ncols, NB)), dim3(256), 0, s, L,
+                       Dinv, k, B, ncols);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status identity(double *A, int k, hipStream_t s)
+{
+    if (k <= 0) return AFN_OK;
+    hipLaunchKernelGGL(set_identity, dim3((unsigned)ceil_div((int64_t)k * k, 256)), dim3(256), 0, s,
+                       A, k);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+}  // namespace afn

@@ -1,0 +1,128 @@
+// Library runtime: error reporting, device memory bookkeeping, the per-device
+// scratch area and the kernel_matvec entry point of the C-ABI.
+#include <mutex>
+#include <string>
+
+#include "afn_internal.h"
+
+namespace afn {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char *fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+afn_status DevArena::alloc(void **p, size_t bytes)
+{
+    *p = nullptr;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+        *p = nullptr;
+        return AFN_ENOMEM;
+    }
+    ptrs.push_back(*p);
+    return AFN_OK;
+}
+
+void DevArena::release()
+{
+    for (void *p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+}
+
+namespace {
+struct Scratch {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_scratch_mu;
+Scratch g_scratch[64];
+}  // namespace
+
+afn_status library_scratch(size_t bytes, void **ptr)
+{
+    int dev = 0;
+    AFN_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) {
+        set_error("device ordinal %d out of range", dev);
+        return AFN_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    Scratch &sc = g_scratch[dev];
+    if (sc.bytes < bytes) {
+        if (sc.ptr) {
+            AFN_HIP(hipDeviceSynchronize());
+            AFN_HIP(hipFree(sc.ptr));
+            sc.ptr = nullptr;
+            sc.bytes = 0;
+        }
+        size_t want = bytes + bytes / 4;
+        hipError_t e = hipMalloc(&sc.ptr, want);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            sc.ptr = nullptr;
+            set_error("scratch hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
+            return AFN_ENOMEM;
+        }
+        sc.bytes = want;
+    }
+    *ptr = sc.ptr;
+    return AFN_OK;
+}
+
+}  // namespace afn
+
+extern "C" {
+
+const char *afn_status_string(afn_status s)
+{
+    switch (s) {
+        case AFN_OK: return "AFN_OK";
+        case AFN_EINVAL: return "AFN_EINVAL: invalid argument";
+        case AFN_ENOMEM: return "AFN_ENOMEM: device allocation failed";
+        case AFN_ENOTSPD: return "AFN_ENOTSPD: matrix not positive definite";
+        case AFN_ENOCONV: return "AFN_ENOCONV: no convergence within maxit";
+        case AFN_EBREAKDOWN: return "AFN_EBREAKDOWN: CG breakdown";
+        case AFN_ESTAGNATION: return "AFN_ESTAGNATION: refinement stagnated";
+        case AFN_EDEVICE: return "AFN_EDEVICE: HIP runtime error";
+    }
+    return "unknown afn_status";
+}
+
+const char *afn_last_error(void) { return afn::g_last_error.c_str(); }
+
+afn_status kernel_matvec(const double *X_dev, int64_t n, int32_t d, double l, double mu,
+                         const double *v_dev, double *y_dev, int32_t nrhs, int64_t ld,
+                         int32_t precision, void *stream)
+{
+    afn::clear_error();
+    if (n < 1 || d < 1 || d > afn::kMaxD || !(l > 0) || !(mu >= 0) || nrhs < 1 || ld < n ||
+        !X_dev || !v_dev || !y_dev) {
+        afn::set_error("kernel_matvec: invalid argument (n=%lld d=%d l=%g mu=%g nrhs=%d ld=%lld)",
+                       (long long)n, d, l, mu, nrhs, (long long)ld);
+        return AFN_EINVAL;
+    }
+    if (precision != AFN_FP64 && precision != AFN_FP32) {
+        afn::set_error("kernel_matvec: unknown precision %d", precision);
+        return AFN_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    void *work = nullptr;
+    AFN_TRY(afn::library_scratch(sizeof(double) * (size_t)afn::kmv_workspace_doubles(n), &work));
+    if (precision == AFN_FP32)
+        return afn::kmv_f32(X_dev, n, d, l, mu, v_dev, ld, y_dev, ld, nrhs, work, s);
+    return afn::kmv_f64(X_dev, n, d, l, mu, v_dev, ld, y_dev, ld, nrhs, (double *)work, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,377 @@
+// Vector kernels of the AFN apply (Algorithm 3) and of PCG.  Every reduction
+// has a fixed order (per-workgroup partials, then one ordered pass), so results
+// are bitwise reproducible run to run.
+#include "afn_internal.h"
+
+namespace afn {
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ double block_sum(double v)
+{
+    __shared__ double ws[16];
+    v = wave_sum(v);
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) ws[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    const int nw = (int)(blockDim.x >> 6);
+    for (int i = 0; i < nw; ++i) s += ws[i];
+    __syncthreads();
+    return s;
+}
+
+constexpr int kDotBlocks = 512;
+
+__global__ __launch_bounds__(256) void dot_stage1(const double *__restrict__ a,
+                                                  const double *__restrict__ b, int64_t n,
+                                                  int64_t chunk, double *__restrict__ part)
+{
+    const int64_t i0 = (int64_t)blockIdx.x * chunk;
+    const int64_t i1 = i0 + chunk < n ? i0 + chunk : n;
+    double s = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) s = __builtin_fma(a[i], b[i], s);
+    s = block_sum(s);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void sum_stage2(const double *__restrict__ part, int np,
+                                                  double *__restrict__ out)
+{
+    double s = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
+    s = block_sum(s);
+    if (threadIdx.x == 0) *out = s;
+}
+
+// y[i] (+)= sum over column chunk of A[i + j*lda] x[j]; partial per split.
+__global__ __launch_bounds__(256) void gemv_n_partial(const double *__restrict__ A, int64_t lda,
+                                                      int64_t m, int64_t ncols,
+                                                      const double *__restrict__ x,
+                                                      int64_t chunk, double *__restrict__ part)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.y * chunk;
+    const int64_t j1 = j0 + chunk < ncols ? j0 + chunk : ncols;
+    if (i >= m) return;
+    double s = 0.0;
+    for (int64_t j = j0; j < j1; ++j) s = __builtin_fma(A[i + j * lda], x[j], s);
+    part[(int64_t)blockIdx.y * m + i] = s;
+}
+
+// y[i] = base[i] + sign * sum_s part[s][i]   (base may be null -> 0)
+__global__ __launch_bounds__(256) void gemv_n_reduce(const double *__restrict__ part, int64_t m,
+                                                     int splits, const double *__restrict__ base,
+                                                     double sign, double *__restrict__ y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    double s = 0.0;
+    for (int k = 0; k < splits; ++k) s += part[(int64_t)k * m + i];
+    y[i] = (base ? base[i] : 0.0) + sign * s;
+}
+
+// y[j] = base[j] + sign * sum_i A[i + j*lda] x[i], one wavefront per column.
+__global__ __launch_bounds__(256) void gemv_t_kernel(const double *__restrict__ A, int64_t lda,
+                                                     int64_t m, int64_t ncols,
+                                                     const double *__restrict__ x,
+                                                     const double *__restrict__ base, double sign,
+                                                     double *__restrict__ y)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (j >= ncols) return;
+    const double *col = A + j * lda;
+    double s = 0.0;
+    for (int64_t i = lane; i < m; i += 64) s = __builtin_fma(col[i], x[i], s);
+    s = wave_sum(s);
+    if (lane == 0) y[j] = (base ? base[j] : 0.0) + sign * s;
+}
+
+// u[p] = sum_a gval[p*w + a] t[cols[p*w + a]], a < min(p+1, w); wave per row.
+__global__ __launch_bounds__(256) void spmv_padded(const int32_t *__restrict__ cols,
+                                                   const double *__restrict__ gval, int64_t nr,
+                                                   int w, const double *__restrict__ t,
+                                                   double *__restrict__ u)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (p >= nr) return;
+    const int m = (int)(p + 1 < w ? p + 1 : w);
+    double s = 0.0;
+    if (lane < m) s = gval[p * w + lane] * t[cols[p * w + lane]];
+    s = wave_sum(s);
+    if (lane == 0) u[p] = s;
+}
+
+// s[c] = sum_e tval[e] u[trow[e]] over e in [ptr[c], ptr[c+1]); wave per row.
+__global__ __launch_bounds__(256) void spmv_csr(const int64_t *__restrict__ ptr,
+                                                const int32_t *__restrict__ idx,
+                                                const double *__restrict__ val, int64_t nrows,
+                                                const double *__restrict__ u,
+                                                double *__restrict__ out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (c >= nrows) return;
+    double s = 0.0;
+    for (int64_t e = ptr[c] + lane; e < ptr[c + 1]; e += 64) s = __builtin_fma(val[e], u[idx[e]], s);
+    s = wave_sum(s);
+    if (lane == 0) out[c] = s;
+}
+
+__global__ __launch_bounds__(256) void gather_kernel(const double *__restrict__ src, int64_t lds,
+                                                     double *__restrict__ dst, int64_t ldd,
+                                                     const int32_t *__restrict__ perm, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = blockIdx.y;
+    dst[i + c * ldd] = src[perm[i] + c * lds];
+}
+
+__global__ __launch_bounds__(256) void scatter_kernel(const double *__restrict__ src, int64_t lds,
+                                                      double *__restrict__ dst, int64_t ldd,
+                                                      const int32_t *__restrict__ perm, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = blockIdx.y;
+    dst[perm[i] + c * ldd] = src[i + c * lds];
+}
+
+__global__ __launch_bounds__(256) void gather_points_kernel(const double *__restrict__ X,
+                                                            const int32_t *__restrict__ perm,
+                                                            int64_t n, int d,
+                                                            double *__restrict__ Xp)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * d) return;
+    const int64_t i = e / d;
+    const int t = (int)(e - i * d);
+    Xp[e] = X[(int64_t)perm[i] * d + t];
+}
+
+// PCG scalar slots (device): see PcgScalars.
+__global__ void pcg_alpha(double *sc)
+{
+    // sc[0] rho, sc[1] pq -> sc[4] alpha
+    sc[4] = sc[0] / sc[1];
+}
+
+__global__ void pcg_beta(double *sc)
+{
+    // sc[3] rho_new, sc[0] rho -> sc[5] beta; rho = rho_new
+    sc[5] = sc[3] / sc[0];
+    sc[0] = sc[3];
+}
+
+// x += alpha p; r -= alpha q; partial sums of r.r
+__global__ __launch_bounds__(256) void pcg_xr(double *__restrict__ x, double *__restrict__ r,
+                                              const double *__restrict__ p,
+                                              const double *__restrict__ q,
+                                              const double *__restrict__ sc, int64_t n,
+                                              int64_t chunk, double *__restrict__ part)
+{
+    const double alpha = sc[4];
+    const int64_t i0 = (int64_t)blockIdx.x * chunk;
+    const int64_t i1 = i0 + chunk < n ? i0 + chunk : n;
+    double s = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        x[i] = __builtin_fma(alpha, p[i], x[i]);
+        double ri = __builtin_fma(-alpha, q[i], r[i]);
+        r[i] = ri;
+        s = __builtin_fma(ri, ri, s);
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// p = z + beta p
+__global__ __launch_bounds__(256) void pcg_p(double *__restrict__ p, const double *__restrict__ z,
+                                             const double *__restrict__ sc, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    p[i] = __builtin_fma(sc[5], p[i], z[i]);
+}
+
+// r = b - y (true residual)
+__global__ __launch_bounds__(256) void sub_kernel(const double *__restrict__ b,
+                                                  const double *__restrict__ y,
+                                                  double *__restrict__ r, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    r[i] = b[i] - y[i];
+}
+
+__global__ __launch_bounds__(256) void finite_check(const double *__restrict__ a, int64_t n,
+                                                    int *flag)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v = a[i];
+    if (!(v - v == 0.0)) atomicOr(flag, 1);
+}
+
+}  // namespace
+
+int64_t dot_partials(int64_t n)
+{
+    int64_t b = ceil_div(n, 2048);
+    return b < 1 ? 1 : (b > kDotBlocks ? kDotBlocks : b);
+}
+
+afn_status dot(const double *a, int64_t lda, const double *b, int64_t ldb, int64_t n, int nrhs,
+               double *out, double *part, hipStream_t s)
+{
+    const int64_t nb = dot_partials(n);
+    const int64_t chunk = ceil_div(n, nb);
+    for (int c = 0; c < nrhs; ++c) {
+        hipLaunchKernelGGL(dot_stage1, dim3((unsigned)nb), dim3(256), 0, s, a + c * lda, b + c * ldb, n,
+                           chunk, part);
+        hipLaunchKernelGGL(sum_stage2, dim3(1), dim3(256), 0, s, part, (int)nb, out + c);
+    }
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+int64_t gemv_splits(int64_t m, int64_t ncols)
+{
+    if (m <= 0 || ncols <= 0) return 1;
+    int64_t rb = ceil_div(m, 256);
+    int64_t s = ceil_div(1024, rb);
+    int64_t smax = ceil_div(ncols, 32);
+    if (s > smax) s = smax;
+    if (s > 512) s = 512;
+    return s < 1 ? 1 : s;
+}
+
+int64_t gemv_partials(int64_t m, int64_t ncols) { return gemv_splits(m, ncols) * m; }
+
+afn_status gemv_n(const double *A, int64_t lda, int64_t m, int64_t ncols, const double *x,
+                  const double *base, double sign, double *y, double *part, hipStream_t s)
+{
+    if (m <= 0) return AFN_OK;
+    const int64_t S = gemv_splits(m, ncols);
+    const int64_t chunk = ceil_div(ncols, S);
+    hipLaunchKernelGGL(gemv_n_partial, dim3((unsigned)ceil_div(m, 256), (unsigned)S), dim3(256), 0, s,
+                       A, lda, m, ncols, x, chunk, part);
+    hipLaunchKernelGGL(gemv_n_reduce, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, part, m,
+                       (int)S, base, sign, y);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status gemv_t(const double *A, int64_t lda, int64_t m, int64_t ncols, const double *x,
+                  const double *base, double sign, double *y, hipStream_t s)
+{
+    if (ncols <= 0) return AFN_OK;
+    hipLaunchKernelGGL(gemv_t_kernel, dim3((unsigned)ceil_div(ncols, 4)), dim3(256), 0, s, A, lda, m,
+                       ncols, x, base, sign, y);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status spmv_g(const int32_t *cols, const double *gval, int64_t nr, int w, const double *t,
+                  double *u, hipStream_t s)
+{
+    if (nr <= 0) return AFN_OK;
+    hipLaunchKernelGGL(spmv_padded, dim3((unsigned)ceil_div(nr, 4)), dim3(256), 0, s, cols, gval, nr,
+                       w, t, u);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status spmv_gt(const int64_t *ptr, const int32_t *idx, const double *val, int64_t nr,
+                   const double *u, double *out, hipStream_t s)
+{
+    if (nr <= 0) return AFN_OK;
+    hipLaunchKernelGGL(spmv_csr, dim3((unsigned)ceil_div(nr, 4)), dim3(256), 0, s, ptr, idx, val, nr,
+                       u, out);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status permute_gather(const double *src, int64_t lds, double *dst, int64_t ldd,
+                          const int32_t *perm, int64_t n, int nrhs, hipStream_t s)
+{
+    hipLaunchKernelGGL(gather_kernel, dim3((unsigned)ceil_div(n, 256), (unsigned)nrhs), dim3(256), 0, s,
+                       src, lds, dst, ldd, perm, n);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status permute_scatter(const double *src, int64_t lds, double *dst, int64_t ldd,
+                           const int32_t *perm, int64_t n, int nrhs, hipStream_t s)
+{
+    hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)ceil_div(n, 256), (unsigned)nrhs), dim3(256), 0, s,
+                       src, lds, dst, ldd, perm, n);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status gather_points(const double *X, const int32_t *perm, int64_t n, int d, double *Xp,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(gather_points_kernel, dim3((unsigned)ceil_div(n * d, 256)), dim3(256), 0, s, X,
+                       perm, n, d, Xp);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status pcg_alpha_launch(double *sc, hipStream_t s)
+{
+    hipLaunchKernelGGL(pcg_alpha, dim3(1), dim3(1), 0, s, sc);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status pcg_beta_launch(double *sc, hipStream_t s)
+{
+    hipLaunchKernelGGL(pcg_beta, dim3(1), dim3(1), 0, s, sc);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status pcg_xr_launch(double *x, double *r, const double *p, const double *q, const double *sc,
+                         int64_t n, double *part, double *rr_out, hipStream_t s)
+{
+    const int64_t nb = dot_partials(n);
+    const int64_t chunk = ceil_div(n, nb);
+    hipLaunchKernelGGL(pcg_xr, dim3((unsigned)nb), dim3(256), 0, s, x, r, p, q, sc, n, chunk, part);
+    hipLaunchKernelGGL(sum_stage2, dim3(1), dim3(256), 0, s, part, (int)nb, rr_out);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status pcg_p_launch(double *p, const double *z, const double *sc, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(pcg_p, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, p, z, sc, n);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status sub_launch(const double *b, const double *y, double *r, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(sub_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, b, y, r, n);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status finite_launch(const double *a, int64_t n, int *flag, hipStream_t s)
+{
+    if (n <= 0) return AFN_OK;
+    hipLaunchKernelGGL(finite_check, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, a, n, flag);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+}  // namespace afn

@@ -1,0 +1,380 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle.
+
+Tolerances (u = 2^-53 for FP64, u32 = 2^-24):
+- kernel matvec FP64: any summation order of n terms, each with a faithfully
+  rounded exp, is within (n + 4) u sum_j |K_ij v_j| of the exact sum; the
+  same bound holds for the oracle, so |y_gpu - y_ora| <= 2 (n + 4) u abs_i.
+- FP32 tiles: the exponent argument a = d^2 / l^2 carries a relative error of
+  about (d + 4) u32 (coordinate rounding, d fma steps, scaling), so a term
+  with a <= 30 has relative error <= 30 (d + 4) u32 ln 2; terms with a > 30
+  are below 1e-13.  Accumulation adds L u32 (L = terms per partial sum).
+- landmark indices, kNN patterns: bit-exact.
+- L: backward error of a Cholesky factorization, ||L L^T - A|| <= 8 k u ||A||.
+- G, apply, solutions: compared through invariants of the definitions and by
+  relative differences bounded by the condition numbers stated in each test.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2304_05460_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def afn():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2304_05460_amd import afn as mod
+    mod.lib()
+    return mod
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def dense_K(X, l):
+    D = ((X[:, None, :] - X[None, :, :]) ** 2).sum(-1)
+    return np.exp(-D / l**2)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+# ------------------------------------------------------------------ kernel matvec
+
+@pytest.mark.parametrize("n,d,l,pts", [(2000, 3, 0.1, "uniform"), (2000, 3, 1.0, "uniform"),
+                                       (1037, 8, 2.0, "normal"), (1, 3, 0.5, "uniform"),
+                                       (300, 1, 0.05, "uniform"), (517, 12, 3.0, "normal"),
+                                       (777, 3, 1e-3, "uniform")])
+def test_kernel_matvec_fp64_all_rows(afn, n, d, l, pts):
+    say(f"kmv fp64 n={n} d={d} l={l}")
+    X = W.points(pts, n, d, 11)
+    v = np.random.default_rng(12).standard_normal(n)
+    y = afn.kernel_matvec(dev(X), l, 1e-4, dev(v)).cpu().numpy()
+    yo, ab = oracle.kernel_matvec_rows(X, l, 1e-4, v, np.arange(n))
+    bound = 2 * (n + 4) * U * ab
+    assert np.all(np.abs(y - yo) <= bound), np.max(np.abs(y - yo) / ab)
+
+
+def test_kernel_matvec_multi_rhs_strided(afn):
+    n, nrhs, ld = 901, 3, 1000
+    X = W.points("uniform", n, 3, 13)
+    V = np.random.default_rng(14).standard_normal((n, nrhs))
+    Vt = torch.zeros((nrhs, ld), dtype=torch.float64, device="cuda")
+    Vt[:, :n] = dev(V.T)
+    Yt = torch.zeros((nrhs, ld), dtype=torch.float64, device="cuda")
+    vin, yout = Vt.t()[:n], Yt.t()[:n]          # column-major views with ld = 1000
+    afn.kernel_matvec(dev(X), 0.2, 1e-3, vin, out=yout)
+    Y = Yt[:, :n].t().cpu().numpy()
+    for c in range(nrhs):
+        yo, ab = oracle.kernel_matvec_rows(X, 0.2, 1e-3, V[:, c], np.arange(n))
+        assert np.all(np.abs(Y[:, c] - yo) <= 2 * (n + 4) * U * ab)
+    assert not Yt[:, n:].any()                  # padding untouched
+
+
+@pytest.mark.parametrize("n,d,l,pts", [(2000, 3, 0.1, "uniform"), (1037, 8, 2.0, "normal")])
+def test_kernel_matvec_fp32_tiles(afn, n, d, l, pts):
+    X = W.points(pts, n, d, 15)
+    v = np.random.default_rng(16).standard_normal(n)
+    y = afn.kernel_matvec(dev(X), l, 1e-4, dev(v), precision=afn.AFN_FP32).cpu().numpy()
+    yo, ab = oracle.kernel_matvec_rows(X, l, 1e-4, v, np.arange(n))
+    bound = (30 * (d + 4) * math.log(2) + n + 8) * U32 * ab + 1e-13 * np.abs(v).sum()
+    assert np.all(np.abs(y - yo) <= bound), np.max(np.abs(y - yo) / ab)
+
+
+def test_kernel_matvec_large_sampled_rows(afn):
+    p = W.c2(0.1)
+    X = W.points(p.points, p.n, p.d, p.seed)
+    v = np.random.default_rng(17).standard_normal(p.n)
+    y = afn.kernel_matvec(dev(X), p.l, p.mu, dev(v)).cpu().numpy()
+    rows = np.concatenate([np.arange(5), np.random.default_rng(18).integers(0, p.n, 40),
+                           np.arange(p.n - 5, p.n)])
+    yo, ab = oracle.kernel_matvec_rows(X, p.l, p.mu, v, rows)
+    assert np.all(np.abs(y[rows] - yo) <= 2 * (p.n + 4) * U * ab)
+
+
+def test_kernel_matvec_invalid_arguments(afn):
+    X = dev(np.zeros((10, 3)))
+    v = dev(np.ones(10))
+    for l, mu in [(0.0, 1e-3), (-1.0, 1e-3), (1.0, -1.0), (float("nan"), 0.0)]:
+        with pytest.raises(afn.AFNError) as e:
+            afn.kernel_matvec(X, l, mu, v)
+        assert e.value.status == afn.AFN_EINVAL
+
+
+# ------------------------------------------------------------------ setup pieces
+
+def oracle_setup(X, l, mu, k, w):
+    idx, _ = oracle.fps(X, k)
+    return oracle.afn_build(X, l, mu, idx, w)
+
+
+def gpu_csr(h):
+    return h.fsai()
+
+
+@pytest.fixture(scope="module")
+def c1(afn):
+    p = W.C1
+    X, b = W.make(p)
+    say("C1 setup")
+    h = afn.afn_setup(dev(X), p.l, p.mu, k=p.k, w=p.w)
+    A = oracle_setup(X, p.l, p.mu, p.k, p.w)
+    return p, X, b, h, A
+
+
+def test_c1_landmarks_bit_exact(c1):
+    p, X, b, h, A = c1
+    np.testing.assert_array_equal(h.landmarks(), A.perm[: p.k])
+
+
+def test_c1_pattern_bit_exact(c1):
+    p, X, b, h, A = c1
+    rowptr, cols, _ = h.fsai()
+    np.testing.assert_array_equal(rowptr, A.rowptr)
+    np.testing.assert_array_equal(cols, A.cols)
+
+
+def test_c1_cholesky_backward_error_and_oracle(c1):
+    p, X, b, h, A = c1
+    L = h.cholesky()
+    Xp = X[A.perm]
+    A11 = dense_K(Xp[: p.k], p.l) + p.mu * np.eye(p.k)
+    assert np.all(np.triu(L, 1) == 0)
+    assert np.linalg.norm(L @ L.T - A11) <= 8 * p.k * U * np.linalg.norm(A11)
+    kappa = np.linalg.cond(A11)
+    assert np.linalg.norm(L - A.L) <= 8 * p.k * U * kappa * np.linalg.norm(A.L)
+
+
+def test_c1_fsai_invariants_and_oracle(c1):
+    # Kolotilina-Yeremin conditions against the dense Schur complement, and
+    # agreement with the oracle's G within the conditioning of the blocks.
+    p, X, b, h, A = c1
+    rowptr, cols, vals = h.fsai()
+    Xp = X[A.perm]
+    K = dense_K(Xp, p.l) + p.mu * np.eye(p.n)
+    k = p.k
+    S = K[k:, k:] - K[:k, k:].T @ np.linalg.solve(K[:k, :k], K[:k, k:])
+    rng = np.random.default_rng(19)
+    worst = dict(ky_diag=0.0, ky_off=0.0, rel_vs_oracle=0.0, bound=0.0)
+    for q in np.concatenate([np.arange(3), rng.integers(0, p.n - k, 30)]):
+        s = cols[rowptr[q]:rowptr[q + 1]]
+        g = vals[rowptr[q]:rowptr[q + 1]]
+        Sss = S[np.ix_(s, s)]
+        r = g @ Sss
+        kap = np.linalg.cond(Sss)
+        assert g[-1] > 0
+        ky_diag = abs(r[-1] * g[-1] - 1.0)
+        ky_off = np.max(np.abs(r[:-1]), initial=0.0) / abs(r[-1])
+        rel = np.linalg.norm(g - A.gval[rowptr[q]:rowptr[q + 1]]) / np.linalg.norm(g)
+        bound = kap * k * 1e3 * U
+        worst = {key: max(worst[key], val) for key, val in
+                 dict(ky_diag=ky_diag, ky_off=ky_off, rel_vs_oracle=rel, bound=bound).items()}
+        # the dense Schur complement carries cancellation error of order
+        # k u kappa(K11 + mu I) relative to its entries, which enters the
+        # invariants through kappa(S_ss)
+        assert ky_diag <= 1e-5 and ky_off <= 1e-5
+        assert rel <= max(1e-9, bound)
+    say("C1 FSAI worst", worst)
+
+
+def test_c1_apply_matches_oracle_and_is_symmetric(afn, c1):
+    p, X, b, h, A = c1
+    rng = np.random.default_rng(20)
+    R = rng.standard_normal((p.n, 2))
+    S = np.stack([oracle.afn_apply(A, R[:, c]) for c in range(2)], axis=1)
+    Sg = np.stack([afn.afn_apply(h, dev(R[:, c])).cpu().numpy() for c in range(2)], axis=1)
+    rel = np.linalg.norm(Sg - S) / np.linalg.norm(S)
+    say("apply rel diff", rel)
+    assert rel <= 1e-7
+    assert R[:, 0] @ Sg[:, 1] == pytest.approx(R[:, 1] @ Sg[:, 0], rel=1e-9)
+
+
+def test_c1_pcg_matching_residual(afn, c1):
+    p, X, b, h, A = c1
+    x, info = afn.afn_pcg_solve(h, dev(b), tol=p.tol, maxit=p.maxit)
+    x = x.cpu().numpy()
+    say("C1 gpu", info)
+    assert info["converged"] and info["relres"] <= p.tol
+    # true residual recomputed by the oracle's FP64 matvec
+    r = b - oracle.kernel_matvec(X, p.l, p.mu, x)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 2 * p.tol
+    xo, ito, rel_o, trel_o, st = oracle.pcg(A, b, p.tol, p.maxit)
+    say("C1 oracle iterations", ito, "gpu", info["iterations"])
+    assert abs(info["iterations"] - ito) <= 2
+    # at a tightened tolerance both solutions sit within kappa * tol of the
+    # exact one, so they agree to well below 1e-6
+    x2, info2 = afn.afn_pcg_solve(h, dev(b), tol=1e-12, maxit=p.maxit)
+    xo2, *_ = oracle.pcg(A, b, 1e-12, p.maxit)
+    rel = np.linalg.norm(x2.cpu().numpy() - xo2) / np.linalg.norm(xo2)
+    say("C1 solution agreement at tol 1e-12:", rel)
+    assert rel <= 1e-6
+
+
+def test_c1_deterministic(afn, c1):
+    p, X, b, h, A = c1
+    h2 = afn.afn_setup(dev(X), p.l, p.mu, k=p.k, w=p.w)
+    r1, c1_, v1 = h.fsai()
+    r2, c2_, v2 = h2.fsai()
+    np.testing.assert_array_equal(v1, v2)
+    x1, _ = afn.afn_pcg_solve(h, dev(b), tol=1e-6)
+    x2, _ = afn.afn_pcg_solve(h2, dev(b), tol=1e-6)
+    assert torch.equal(x1, x2)
+
+
+# ------------------------------------------------------------------ exact / degenerate cases
+
+def test_k_equals_n_is_exact(afn):
+    n = 300
+    X = W.points("uniform", n, 3, 21)
+    b = np.random.default_rng(22).standard_normal(n)
+    h = afn.afn_setup(dev(X), 0.3, 1e-2, k=n, w=8)
+    x, info = afn.afn_pcg_solve(h, dev(b), tol=1e-10)
+    assert info["iterations"] == 1
+    xs = np.linalg.solve(dense_K(X, 0.3) + 1e-2 * np.eye(n), b)
+    np.testing.assert_allclose(x.cpu().numpy(), xs, rtol=1e-6, atol=1e-8)
+
+
+def test_full_pattern_is_exact(afn):
+    n, k = 100, 40                       # n - k = 60 <= w = 64: every row is complete
+    X = W.points("uniform", n, 3, 23)
+    b = np.random.default_rng(24).standard_normal(n)
+    h = afn.afn_setup(dev(X), 0.3, 1e-2, k=k, w=64)
+    x, info = afn.afn_pcg_solve(h, dev(b), tol=1e-10)
+    assert info["iterations"] == 1
+    xs = np.linalg.solve(dense_K(X, 0.3) + 1e-2 * np.eye(n), b)
+    np.testing.assert_allclose(x.cpu().numpy(), xs, rtol=1e-6, atol=1e-8)
+
+
+def test_k0_w1_is_plain_cg(afn):
+    n = 400
+    X = W.points("uniform", n, 3, 25)
+    b = np.random.default_rng(26).standard_normal(n)
+    l, mu = 0.1, 1e-2
+    h = afn.afn_setup(dev(X), l, mu, k=0, w=1)
+    x, info = afn.afn_pcg_solve(h, dev(b), tol=1e-10)
+    A = dense_K(X, l) + mu * np.eye(n)
+    xk = np.zeros(n); r = b.copy(); pp = r.copy(); rr = r @ r; its = 0
+    while True:
+        q = A @ pp; a = rr / (pp @ q); xk += a * pp; r -= a * q; its += 1
+        if np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10 or its >= 500:
+            break
+        rn = r @ r; pp = r + rn / rr * pp; rr = rn
+    assert abs(info["iterations"] - its) <= 1
+    np.testing.assert_allclose(x.cpu().numpy(), xk, rtol=1e-7, atol=1e-9)
+
+
+@pytest.mark.parametrize("n,k,w,d", [(1, 1, 1, 3), (5, 0, 3, 2), (70, 3, 64, 3), (333, 17, 5, 8),
+                                     (129, 64, 64, 3), (200, 65, 7, 12)])
+def test_small_and_ragged_shapes_match_oracle(afn, n, k, w, d):
+    say(f"ragged n={n} k={k} w={w} d={d}")
+    X = W.points("normal" if d == 8 else "uniform", n, d, 27 + n)
+    l, mu = 0.7, 1e-2
+    h = afn.afn_setup(dev(X), l, mu, k=k, w=w)
+    A = oracle_setup(X, l, mu, k, w)
+    np.testing.assert_array_equal(h.landmarks(), A.perm[:k])
+    rowptr, cols, vals = h.fsai()
+    np.testing.assert_array_equal(rowptr, A.rowptr)
+    np.testing.assert_array_equal(cols, A.cols)
+    if vals.size:
+        assert np.linalg.norm(vals - A.gval) <= 1e-8 * np.linalg.norm(A.gval)
+    r = np.random.default_rng(n).standard_normal(n)
+    s = afn.afn_apply(h, dev(r)).cpu().numpy()
+    so = oracle.afn_apply(A, r)
+    assert np.linalg.norm(s - so) <= 1e-8 * np.linalg.norm(so)
+
+
+def test_fps_with_ties_and_duplicates(afn):
+    rng = np.random.default_rng(31)
+    X = rng.integers(0, 5, size=(3000, 3)).astype(float)
+    h = afn.afn_setup(dev(X), 0.5, 1e-2, k=100, w=16)
+    idx, _ = oracle.fps(X, 100)
+    np.testing.assert_array_equal(h.landmarks(), idx)
+
+
+# ------------------------------------------------------------------ full-size setup (C2 shape)
+
+def test_c2_fps_pattern_and_fsai_sampled(afn):
+    p = W.c2(0.1)
+    X = W.points(p.points, p.n, p.d, p.seed)
+    k = 2000
+    say("C2 setup k=2000")
+    h = afn.afn_setup(dev(X), p.l, p.mu, k=k, w=p.w)
+    idx, _ = oracle.fps(X, k)
+    np.testing.assert_array_equal(h.landmarks(), idx)
+    perm = oracle.permutation(p.n, idx)
+    Xr = X[perm[k:]]
+    rowptr, cols, vals = h.fsai()
+    rows = np.concatenate([np.arange(3), [62, 63, 64],
+                           np.random.default_rng(32).integers(0, p.n - k, 20)])
+    oc, ol = oracle.knn_rows(Xr, p.w, rows)
+    for s_, q in enumerate(rows):
+        np.testing.assert_array_equal(cols[rowptr[q]:rowptr[q + 1]], oc[s_, :ol[s_]])
+    L = oracle.landmark_cholesky(X[perm], k, p.l, p.mu)
+    fc, fl, fg = oracle.fsai_rows(X, p.l, p.mu, perm, L, p.w, rows[:8])
+    for s_, q in enumerate(rows[:8]):
+        g = vals[rowptr[q]:rowptr[q + 1]]
+        assert np.linalg.norm(g - fg[s_, :fl[s_]]) <= 1e-6 * np.linalg.norm(g)
+
+
+# ------------------------------------------------------------------ rank estimation
+
+@pytest.mark.parametrize("l", [0.02, 0.1, 1.0])
+def test_rank_estimate_matches_oracle(afn, l):
+    n, m = 20000, 400
+    X = W.points("mixture5", n, 3, 33)
+    say(f"rank l={l}")
+    h = afn.afn_setup(dev(X), l, 1e-3, k=-1, w=16, k_max=2000, m=m, seed=99)
+    inf = h.info()
+    ko, info = oracle.rank_estimate(X, l, 1e-3, m, kmax=2000, kswitch=2000, seed=99)
+    say("gpu", inf.k, inf.rank_r, inf.rank_k_est, inf.rank_eig_count, "oracle", ko, info)
+    assert inf.rank_r == info[0]
+    assert inf.rank_eig_branch == info[2]
+    assert inf.k == ko
+    idx, _ = oracle.fps(X, ko)
+    np.testing.assert_array_equal(h.landmarks(), idx)
+
+
+# ------------------------------------------------------------------ failures
+
+def test_setup_errors(afn):
+    X = np.zeros((20, 3))
+    X[10:] = 1.0
+    with pytest.raises(afn.AFNError) as e:
+        afn.afn_setup(dev(X), 0.5, 0.0, k=4, w=4)          # duplicate landmarks, mu = 0
+    assert e.value.status == afn.AFN_ENOTSPD
+    for kw in [dict(k=21, w=4), dict(k=2, w=0), dict(k=2, w=65), dict(k=-2, w=4)]:
+        with pytest.raises(afn.AFNError) as e:
+            afn.afn_setup(dev(W.points("uniform", 20, 3, 1)), 0.5, 1e-2, **kw)
+        assert e.value.status == afn.AFN_EINVAL
+    Xn = W.points("uniform", 20, 3, 1)
+    Xn[3, 1] = np.nan
+    with pytest.raises(afn.AFNError) as e:
+        afn.afn_setup(dev(Xn), 0.5, 1e-2, k=2, w=4)
+    assert e.value.status == afn.AFN_EINVAL
+
+
+def test_solve_status_codes(afn):
+    n = 500
+    X = W.points("uniform", n, 3, 41)
+    h = afn.afn_setup(dev(X), 0.1, 1e-4, k=20, w=8)
+    b = np.random.default_rng(42).standard_normal(n)
+    x, info = afn.afn_pcg_solve(h, dev(b), tol=1e-14, maxit=1)
+    assert info["status"] == afn.AFN_ENOCONV and info["iterations"] == 1
+    bn = b.copy()
+    bn[7] = np.nan
+    with pytest.raises(afn.AFNError) as e:
+        afn.afn_pcg_solve(h, dev(bn), tol=1e-8)
+    assert e.value.status == afn.AFN_EBREAKDOWN
+    x, info = afn.afn_pcg_solve(h, dev(np.zeros(n)), tol=1e-8)
+    assert info["iterations"] == 0 and not x.any()
