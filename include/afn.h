@@ -87,6 +87,10 @@ typedef struct afn_solve_info {
     double relres;             /* recurrence residual ||r|| / ||b|| (max over rhs)   */
     double relres_true;        /* ||b - (K + mu I) x|| / ||b|| recomputed in FP64    */
     double ms_solve;
+    double ms_matvec;          /* summed device time of the kernel-matvec tile kernel,
+                                  from HIP events recorded around each of its launches */
+    int32_t matvec_launches;   /* launches timed in ms_matvec                        */
+    int32_t reserved;
 } afn_solve_info;
 
 typedef struct afn_handle afn_handle;

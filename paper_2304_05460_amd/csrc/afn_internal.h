@@ -58,9 +58,10 @@ afn_status library_scratch(size_t bytes, void **ptr);
 int64_t kmv_splits(int64_t n);
 int64_t kmv_workspace_doubles(int64_t n);
 // y[:, c] = (K + mu I) v[:, c] for c < nrhs; X row-major n x d FP64.
+// ev0/ev1 (optional, single right-hand side): recorded around the tile kernel.
 afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, const double *v,
                    int64_t ldv, double *y, int64_t ldy, int nrhs, double *work,
-                   hipStream_t s);
+                   hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // FP32 tiles and accumulation; FP64 vectors at the interface.
 afn_status kmv_f32(const double *X, int64_t n, int d, double l, double mu, const double *v,
                    int64_t ldv, double *y, int64_t ldy, int nrhs, void *work, hipStream_t s);
@@ -172,5 +173,6 @@ struct afn_handle {
     int64_t work_doubles = 0;
     int64_t work_rhs = 0;       // right-hand sides the workspace is sized for
     double *host_sc = nullptr;  // pinned host copy of PCG scalars
+    hipEvent_t kmv_ev[2] = {nullptr, nullptr};  // timing of the matvec tile kernel
     afn_setup_info info{};
 };

@@ -216,6 +216,8 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     h->work_doubles = work_doubles(n, k, nr, nullptr, nullptr);
     AFN_TRY(h->arena.alloc_n(&h->work, h->work_doubles));
     AFN_HIP(hipHostMalloc((void **)&h->host_sc, 16 * sizeof(double), hipHostMallocDefault));
+    AFN_HIP(hipEventCreate(&h->kmv_ev[0]));
+    AFN_HIP(hipEventCreate(&h->kmv_ev[1]));
     AFN_TRY(check_flags(h, s));
     h->nnz = 0;
     if (nr > 0) AFN_HIP(hipMemcpy(&h->nnz, h->tptr + nr, sizeof(int64_t), hipMemcpyDeviceToHost));
@@ -239,7 +241,7 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
 
 afn_status pcg_one(afn_handle *h, const double *b, double *xout, double tol, int maxit,
                    const WorkLayout &w, hipStream_t s, int *iters, double *relres,
-                   double *relres_true, int *converged)
+                   double *relres_true, int *converged, double *ms_kmv, int *n_kmv)
 {
     const int64_t n = h->n;
     double *sc = w.sc;
@@ -273,12 +275,20 @@ afn_status pcg_one(afn_handle *h, const double *b, double *xout, double tol, int
     *converged = 0;
     *relres = 1.0;
     for (int it = 0; it < maxit; ++it) {
-        AFN_TRY(kmv_f64(h->Xp, n, h->d, h->l, h->mu, w.p, n, w.q, n, 1, w.kmv, s));
+        AFN_TRY(kmv_f64(h->Xp, n, h->d, h->l, h->mu, w.p, n, w.q, n, 1, w.kmv, s, h->kmv_ev[0],
+                        h->kmv_ev[1]));
         AFN_TRY(dot(w.p, n, w.q, n, n, 1, sc + 1, w.dotp, s));
         AFN_TRY(pcg_alpha_launch(sc, s));
         AFN_TRY(pcg_xr_launch(w.x, w.r, w.p, w.q, sc, n, w.dotp, sc + 2, s));
         AFN_HIP(hipMemcpyAsync(hs + 1, sc + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
         AFN_HIP(hipStreamSynchronize(s));
+        {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, h->kmv_ev[0], h->kmv_ev[1]) == hipSuccess) {
+                *ms_kmv += t;
+                *n_kmv += 1;
+            }
+        }
         *iters = it + 1;
         const double pq = hs[1];
         const double rel = std::sqrt(hs[2]) / bnorm;
@@ -340,6 +350,8 @@ afn_status afn_setup(const double *X_dev, int64_t n, int32_t d, double l, double
     if (st != AFN_OK) {
         (void)hipStreamSynchronize((hipStream_t)stream);
         if (h->host_sc) (void)hipHostFree(h->host_sc);
+        for (auto &e : h->kmv_ev)
+            if (e) (void)hipEventDestroy(e);
         h->arena.release();
         return st;
     }
@@ -381,13 +393,14 @@ afn_status afn_pcg_solve(afn_handle *h, const double *b_dev, double *x_dev, int3
     Timer tm;
     tm.mark(0, s);
     afn_status worst = AFN_OK;
-    int it_max = 0, conv_all = 1;
+    int it_max = 0, conv_all = 1, n_kmv = 0;
+    double ms_kmv = 0.0;
     double rel_max = 0.0, true_max = 0.0;
     for (int c = 0; c < nrhs; ++c) {
         int it = 0, conv = 0;
         double rel = 0, rt = 0;
         afn_status st = pcg_one(h, b_dev + c * ld, x_dev + c * ld, tol, maxit, w, s, &it, &rel,
-                                &rt, &conv);
+                                &rt, &conv, &ms_kmv, &n_kmv);
         if (st != AFN_OK && st != AFN_ENOCONV && st != AFN_EBREAKDOWN) return st;
         if (st != AFN_OK && worst == AFN_OK) worst = st;
         if (st == AFN_EBREAKDOWN) worst = st;
@@ -404,6 +417,9 @@ afn_status afn_pcg_solve(afn_handle *h, const double *b_dev, double *x_dev, int3
         info->relres = rel_max;
         info->relres_true = true_max;
         info->ms_solve = tm.ms(0, 1);
+        info->ms_matvec = ms_kmv;
+        info->matvec_launches = n_kmv;
+        info->reserved = 0;
     }
     return worst;
 }
@@ -480,6 +496,8 @@ void afn_destroy(afn_handle *h)
     if (!h) return;
     (void)hipDeviceSynchronize();
     if (h->host_sc) (void)hipHostFree(h->host_sc);
+    for (auto &e : h->kmv_ev)
+        if (e) (void)hipEventDestroy(e);
     h->arena.release();
     delete h;
 }

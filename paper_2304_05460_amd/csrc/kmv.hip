@@ -177,7 +177,8 @@ int64_t kmv_splits(int64_t n)
 int64_t kmv_workspace_doubles(int64_t n) { return kmv_splits(n) * n; }
 
 afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, const double *v,
-                   int64_t ldv, double *y, int64_t ldy, int nrhs, double *work, hipStream_t s)
+                   int64_t ldv, double *y, int64_t ldy, int nrhs, double *work, hipStream_t s,
+                   hipEvent_t ev0, hipEvent_t ev1)
 {
     const int64_t S = kmv_splits(n);
     const int64_t split_len = ceil_div(n, S);
@@ -185,6 +186,7 @@ afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, const
     dim3 grid((unsigned)ceil_div(n, kRows), (unsigned)S);
     for (int c = 0; c < nrhs; ++c) {
         const double *vc = v + c * ldv;
+        if (ev0) AFN_HIP(hipEventRecord(ev0, s));
         switch (d) {
             case 1: launch_partial<1, 512>(grid, X, n, d, nil2, vc, work, split_len, s); break;
             case 2: launch_partial<2, 512>(grid, X, n, d, nil2, vc, work, split_len, s); break;
@@ -197,6 +199,7 @@ afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, const
             default: launch_partial<0, 32>(grid, X, n, d, nil2, vc, work, split_len, s); break;
         }
         AFN_HIP(hipGetLastError());
+        if (ev1) AFN_HIP(hipEventRecord(ev1, s));
         hipLaunchKernelGGL(kmv_reduce, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, work, n,
                            (int)S, mu, vc, y + c * ldy);
         AFN_HIP(hipGetLastError());
