@@ -56,7 +56,7 @@ afn_status library_scratch(size_t bytes, void **ptr);
 // ---------------------------------------------------------------- kernel matvec
 // Partial-sum workspace for kmv_f64 (doubles).
 int64_t kmv_splits(int64_t n);
-int64_t kmv_workspace_doubles(int64_t n);
+int64_t kmv_workspace_doubles(int64_t n, int d);
 // y[:, c] = (K + mu I) v[:, c] for c < nrhs; X row-major n x d FP64.
 // ev0/ev1 (optional, single right-hand side): recorded around the tile kernel.
 afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, const double *v,

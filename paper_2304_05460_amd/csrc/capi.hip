@@ -46,7 +46,7 @@ struct WorkLayout {
     double *kmv, *dotp, *gemvp, *y1, *t, *u, *y1b, *x, *r, *z, *p, *q, *bp, *tmp, *rp, *sp, *sc;
 };
 
-int64_t work_doubles(int64_t n, int k, int64_t nr, WorkLayout *L, double *base)
+int64_t work_doubles(int64_t n, int d, int k, int64_t nr, WorkLayout *L, double *base)
 {
     int64_t off = 0;
     auto take = [&](int64_t cnt) {
@@ -57,7 +57,7 @@ int64_t work_doubles(int64_t n, int k, int64_t nr, WorkLayout *L, double *base)
     WorkLayout w;
     int64_t gp = gemv_partials(k, nr > k ? nr : k);
     int64_t gp2 = gemv_partials(k, k);
-    w.kmv = take(kmv_workspace_doubles(n));
+    w.kmv = take(kmv_workspace_doubles(n, d));
     w.dotp = take(dot_partials(n));
     w.gemvp = take(gp > gp2 ? gp : gp2);
     w.y1 = take(k);
@@ -213,7 +213,7 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     }
     tm.mark(6, s);
     // workspace for apply / PCG
-    h->work_doubles = work_doubles(n, k, nr, nullptr, nullptr);
+    h->work_doubles = work_doubles(n, d, k, nr, nullptr, nullptr);
     AFN_TRY(h->arena.alloc_n(&h->work, h->work_doubles));
     AFN_HIP(hipHostMalloc((void **)&h->host_sc, 16 * sizeof(double), hipHostMallocDefault));
     AFN_HIP(hipEventCreate(&h->kmv_ev[0]));
@@ -369,7 +369,7 @@ afn_status afn_apply(afn_handle *h, const double *r_dev, double *z_dev, int32_t 
     }
     hipStream_t s = (hipStream_t)stream;
     WorkLayout w;
-    work_doubles(h->n, h->k, h->nr, &w, h->work);
+    work_doubles(h->n, h->d, h->k, h->nr, &w, h->work);
     for (int c = 0; c < nrhs; ++c) {
         AFN_TRY(permute_gather(r_dev + c * ld, h->n, w.rp, h->n, h->perm, h->n, 1, s));
         AFN_TRY(apply_block(h, w.rp, w.sp, w, s));
@@ -389,7 +389,7 @@ afn_status afn_pcg_solve(afn_handle *h, const double *b_dev, double *x_dev, int3
     }
     hipStream_t s = (hipStream_t)stream;
     WorkLayout w;
-    work_doubles(h->n, h->k, h->nr, &w, h->work);
+    work_doubles(h->n, h->d, h->k, h->nr, &w, h->work);
     Timer tm;
     tm.mark(0, s);
     afn_status worst = AFN_OK;

@@ -1,19 +1,192 @@
 // Kernel matvec y = (K + mu I) v with the Gaussian kernel evaluated on the fly
-// (Eq. (1.1), Eq. (1.2)).  FP64 path.
+// (Eq. (1.1), Eq. (1.2)).
 //
-// Layout: X row-major n x d FP64.  A workgroup owns 256 consecutive rows (one
-// per thread, point coordinates in registers) and one of S contiguous column
-// ranges; the column range is streamed through LDS in tiles of BN points
-// (coordinates stored coordinate-major so that every lane reads the same
-// address: LDS broadcast).  Each (row, split) partial sum goes to a workspace;
-// a second pass adds the S partials in ascending split order, so the result
-// is deterministic and independent of scheduling.
+// FP64 path (d <= 8): symmetric tiles.  Coordinates are pre-scaled by
+// sqrt(log2 e) / l (SoA, zero-padded), so K_ij = 2^(-t) with t the squared
+// distance of the scaled points.  The 64-point tile partition is grouped into
+// super-blocks of ST tiles; one workgroup owns a super-block pair (BI <= BJ)
+// and evaluates every unique pair once, adding K_ij v_j to row i and K_ij v_i
+// to row j.  Row partials stay in registers across the column tiles; column
+// partials are reduced over the 16 thread-rows through LDS in a fixed order.
+// Each workgroup writes one row-partial and one column-partial vector; a final
+// pass adds them in ascending super-block order (deterministic result).
+// Diagonal 64 x 64 tiles are evaluated in full and feed rows only.
+//
+// 2^(-t): t clamped to 2000 (the result underflows long before), k = rint(t),
+// f = k - t in [-1/2, 1/2] exactly, 2^(-t) = p(f) 2^(-k) with p the degree-11
+// polynomial interpolating 2^f at the Chebyshev nodes of [-1/2, 1/2]
+// (interpolation error 4.4e-18 relative; Horner in FP64 <= 1.7 ulp).
+//
+// Generic d (> 8) and the FP32 variant use row-block x column-split tiles:
+// 256 rows per workgroup, columns streamed through LDS, S split partials
+// added in order by kmv_reduce.
+#include <cmath>
+
 #include "afn_internal.h"
 
 namespace afn {
 namespace {
 
 constexpr int kRows = 256;
+
+constexpr int kTile = 64;
+constexpr int kMaxST = 16;
+
+__device__ __forceinline__ double exp2_neg(double t)
+{
+    t = t < 2000.0 ? t : 2000.0;
+    const double kd = __builtin_rint(t);
+    const double f = kd - t;
+    double p = 4.45594401136235e-10;
+    p = __builtin_fma(p, f, 7.074200215313511e-09);
+    p = __builtin_fma(p, f, 1.0178056459844976e-07);
+    p = __builtin_fma(p, f, 1.3215432494521488e-06);
+    p = __builtin_fma(p, f, 1.5252733842373628e-05);
+    p = __builtin_fma(p, f, 0.00015403530463828206);
+    p = __builtin_fma(p, f, 0.0013333558146406623);
+    p = __builtin_fma(p, f, 0.009618129107587145);
+    p = __builtin_fma(p, f, 0.05550410866482162);
+    p = __builtin_fma(p, f, 0.2402265069591016);
+    p = __builtin_fma(p, f, 0.6931471805599453);
+    p = __builtin_fma(p, f, 1.0);
+    return __builtin_ldexp(p, (int)(-kd));
+}
+
+// Xs[t * npad + i] = X[i*d + t] * scale for i < n, 0 beyond.
+__global__ __launch_bounds__(256) void pack_scaled(const double *__restrict__ X, int64_t n, int d,
+                                                   int64_t npad, double scale,
+                                                   double *__restrict__ Xs)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= npad * d) return;
+    const int t = (int)(e / npad);
+    const int64_t i = e - (int64_t)t * npad;
+    Xs[e] = i < n ? X[i * d + t] * scale : 0.0;
+}
+
+__device__ __forceinline__ void decode_pair(int q, int S, int &BI, int &BJ)
+{
+    int bi = 0, rem = q;
+    while (rem >= S - bi) {
+        rem -= S - bi;
+        ++bi;
+    }
+    BI = bi;
+    BJ = bi + rem;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void kmv_sym_f64(const double *__restrict__ Xs, int64_t npad,
+                                                   int64_t n, const double *__restrict__ v, int S,
+                                                   int ST, double *__restrict__ part)
+{
+    __shared__ double cx[D][kTile];
+    __shared__ double cv[kTile];
+    __shared__ double red[16][kTile + 1];
+    __shared__ double colacc[kMaxST][kTile];
+    const int tid = threadIdx.x;
+    const int ty = tid >> 4, tx = tid & 15;
+    int BI, BJ;
+    decode_pair(blockIdx.x, S, BI, BJ);
+    const int64_t SB = (int64_t)ST * kTile;
+    const bool diag_super = BI == BJ;
+    for (int e = tid; e < kMaxST * kTile; e += 256) (&colacc[0][0])[e] = 0.0;
+    double *rowout = part + (int64_t)blockIdx.x * 2 * SB;
+    double *colout = rowout + SB;
+    for (int ti = 0; ti < ST; ++ti) {
+        const int64_t i0 = BI * SB + (int64_t)ti * kTile + ty * 4;
+        double xi[4][D], vi[4], racc[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+            for (int t = 0; t < D; ++t) xi[r][t] = Xs[(int64_t)t * npad + i0 + r];
+            vi[r] = i0 + r < n ? v[i0 + r] : 0.0;
+            racc[r] = 0.0;
+        }
+        for (int tj = diag_super ? ti : 0; tj < ST; ++tj) {
+            const int64_t j0 = BJ * SB + (int64_t)tj * kTile;
+            __syncthreads();
+            if (tid < kTile * (D + 1)) {
+                const int t = tid / kTile, j = tid % kTile;
+                if (t < D) cx[t][j] = Xs[(int64_t)t * npad + j0 + j];
+                else cv[j] = j0 + j < n ? v[j0 + j] : 0.0;
+            }
+            for (int e = tid + 256; e < kTile * (D + 1); e += 256) {
+                const int t = e / kTile, j = e % kTile;
+                if (t < D) cx[t][j] = Xs[(int64_t)t * npad + j0 + j];
+                else cv[j] = j0 + j < n ? v[j0 + j] : 0.0;
+            }
+            __syncthreads();
+            const bool diag_tile = diag_super && tj == ti;
+            double cacc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                double xj[D];
+#pragma unroll
+                for (int t = 0; t < D; ++t) xj[t] = cx[t][tx * 4 + c];
+                const double vj = cv[tx * 4 + c];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double d2 = 0.0;
+#pragma unroll
+                    for (int t = 0; t < D; ++t) {
+                        const double del = xi[r][t] - xj[t];
+                        d2 = __builtin_fma(del, del, d2);
+                    }
+                    const double kij = exp2_neg(d2);
+                    racc[r] = __builtin_fma(kij, vj, racc[r]);
+                    cacc[c] = __builtin_fma(kij, vi[r], cacc[c]);
+                }
+            }
+            if (!diag_tile) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) red[ty][tx * 4 + c] = cacc[c];
+                __syncthreads();
+                if (tid < kTile) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int y = 0; y < 16; ++y) s += red[y][tid];
+                    colacc[tj][tid] += s;
+                }
+            }
+        }
+        // rows of tile ti: add the 16 thread-columns in order
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[tx][ty * 4 + r] = racc[r];
+        __syncthreads();
+        if (tid < kTile) {
+            double s = 0.0;
+#pragma unroll
+            for (int x = 0; x < 16; ++x) s += red[x][tid];
+            rowout[(int64_t)ti * kTile + tid] = s;
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < ST * kTile; e += 256) colout[e] = (&colacc[0][0])[e];
+}
+
+// y_i = sum over BJ >= s of row partials + sum over BI <= s of column
+// partials (ascending) + mu v_i, s = super-block of i.
+__global__ __launch_bounds__(256) void kmv_sym_reduce(const double *__restrict__ part, int64_t n,
+                                                      int S, int ST, double mu,
+                                                      const double *__restrict__ v,
+                                                      double *__restrict__ y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t SB = (int64_t)ST * kTile;
+    const int s = (int)(i / SB);
+    const int64_t ii = i - (int64_t)s * SB;
+    double acc = 0.0;
+    const int64_t qs = (int64_t)s * S - (int64_t)s * (s - 1) / 2;   // q(s, s)
+    for (int bj = s; bj < S; ++bj) acc += part[(qs + bj - s) * 2 * SB + ii];
+    for (int bi = 0; bi <= s; ++bi) {
+        const int64_t q = (int64_t)bi * S - (int64_t)bi * (bi - 1) / 2 + (s - bi);
+        acc += part[q * 2 * SB + SB + ii];
+    }
+    y[i] = acc + mu * v[i];
+}
 
 template <int D, int BN>
 __global__ __launch_bounds__(256) void kmv_f64_partial(const double *__restrict__ X, int64_t n,
@@ -174,12 +347,72 @@ int64_t kmv_splits(int64_t n)
     return s < 1 ? 1 : s;
 }
 
-int64_t kmv_workspace_doubles(int64_t n) { return kmv_splits(n) * n; }
+namespace {
+
+// Super-block size: enough workgroups to fill the chip, at most 16 tiles.
+struct SymShape {
+    int ST, S;
+    int64_t npad, nwg;
+};
+
+SymShape sym_shape(int64_t n)
+{
+    SymShape sh;
+    int64_t tiles = ceil_div(n, kTile);
+    int64_t st = tiles / 45;
+    sh.ST = (int)(st < 1 ? 1 : (st > kMaxST ? kMaxST : st));
+    sh.S = (int)ceil_div(tiles, sh.ST);
+    sh.npad = (int64_t)sh.S * sh.ST * kTile;
+    sh.nwg = (int64_t)sh.S * (sh.S + 1) / 2;
+    return sh;
+}
+
+}  // namespace
+
+int64_t kmv_workspace_doubles(int64_t n, int d)
+{
+    const int64_t split = kmv_splits(n) * n;     // generic-d and FP32 paths
+    if (d >= 1 && d <= 8) {
+        SymShape sh = sym_shape(n);
+        const int64_t sym = sh.npad * d + sh.nwg * 2 * sh.npad / sh.S;
+        return sym > split ? sym : split;
+    }
+    return split;
+}
 
 afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, const double *v,
                    int64_t ldv, double *y, int64_t ldy, int nrhs, double *work, hipStream_t s,
                    hipEvent_t ev0, hipEvent_t ev1)
 {
+    if (d >= 1 && d <= 8) {
+        const SymShape sh = sym_shape(n);
+        double *Xs = work;
+        double *part = work + sh.npad * d;
+        const double scale = std::sqrt(1.4426950408889634) / l;
+        hipLaunchKernelGGL(pack_scaled, dim3((unsigned)ceil_div(sh.npad * d, 256)), dim3(256), 0, s, X,
+                           n, d, sh.npad, scale, Xs);
+        for (int c = 0; c < nrhs; ++c) {
+            const double *vc = v + c * ldv;
+            if (ev0) AFN_HIP(hipEventRecord(ev0, s));
+            dim3 grid((unsigned)sh.nwg), block(256);
+            switch (d) {
+                case 1: hipLaunchKernelGGL(kmv_sym_f64<1>, grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
+                case 2: hipLaunchKernelGGL(kmv_sym_f64<2>, grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
+                case 3: hipLaunchKernelGGL(kmv_sym_f64<3>, grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
+                case 4: hipLaunchKernelGGL(kmv_sym_f64<4>, grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
+                case 5: hipLaunchKernelGGL(kmv_sym_f64<5>, grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
+                case 6: hipLaunchKernelGGL(kmv_sym_f64<6>, grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
+                case 7: hipLaunchKernelGGL(kmv_sym_f64<7>, grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
+                default: hipLaunchKernelGGL(kmv_sym_f64<8>, grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
+            }
+            AFN_HIP(hipGetLastError());
+            if (ev1) AFN_HIP(hipEventRecord(ev1, s));
+            hipLaunchKernelGGL(kmv_sym_reduce, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, part, n,
+                               sh.S, sh.ST, mu, vc, y + c * ldy);
+            AFN_HIP(hipGetLastError());
+        }
+        return AFN_OK;
+    }
     const int64_t S = kmv_splits(n);
     const int64_t split_len = ceil_div(n, S);
     const double nil2 = -1.0 / (l * l);
@@ -187,17 +420,7 @@ afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, const
     for (int c = 0; c < nrhs; ++c) {
         const double *vc = v + c * ldv;
         if (ev0) AFN_HIP(hipEventRecord(ev0, s));
-        switch (d) {
-            case 1: launch_partial<1, 512>(grid, X, n, d, nil2, vc, work, split_len, s); break;
-            case 2: launch_partial<2, 512>(grid, X, n, d, nil2, vc, work, split_len, s); break;
-            case 3: launch_partial<3, 512>(grid, X, n, d, nil2, vc, work, split_len, s); break;
-            case 4: launch_partial<4, 512>(grid, X, n, d, nil2, vc, work, split_len, s); break;
-            case 5: launch_partial<5, 256>(grid, X, n, d, nil2, vc, work, split_len, s); break;
-            case 6: launch_partial<6, 256>(grid, X, n, d, nil2, vc, work, split_len, s); break;
-            case 7: launch_partial<7, 256>(grid, X, n, d, nil2, vc, work, split_len, s); break;
-            case 8: launch_partial<8, 256>(grid, X, n, d, nil2, vc, work, split_len, s); break;
-            default: launch_partial<0, 32>(grid, X, n, d, nil2, vc, work, split_len, s); break;
-        }
+        launch_partial<0, 32>(grid, X, n, d, nil2, vc, work, split_len, s);
         AFN_HIP(hipGetLastError());
         if (ev1) AFN_HIP(hipEventRecord(ev1, s));
         hipLaunchKernelGGL(kmv_reduce, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, work, n,

@@ -119,7 +119,7 @@ afn_status kernel_matvec(const double *X_dev, int64_t n, int32_t d, double l, do
     }
     hipStream_t s = (hipStream_t)stream;
     void *work = nullptr;
-    AFN_TRY(afn::library_scratch(sizeof(double) * (size_t)afn::kmv_workspace_doubles(n), &work));
+    AFN_TRY(afn::library_scratch(sizeof(double) * (size_t)afn::kmv_workspace_doubles(n, d), &work));
     if (precision == AFN_FP32)
         return afn::kmv_f32(X_dev, n, d, l, mu, v_dev, ld, y_dev, ld, nrhs, work, s);
     return afn::kmv_f64(X_dev, n, d, l, mu, v_dev, ld, y_dev, ld, nrhs, (double *)work, s);
