@@ -47,9 +47,13 @@ typedef enum afn_status {
     AFN_EDEVICE = 7        /* a HIP runtime call failed                                */
 } afn_status;
 
-/* Arithmetic of the kernel tiles.  AFN_FP64: FP64 throughout.  AFN_FP32:
- * distances and kernel values in FP32 with FP32 accumulation (vectors stay
- * FP64 at the boundary). */
+/* Arithmetic.  kernel_matvec: AFN_FP64 = FP64 tiles; AFN_FP32 = distances,
+ * kernel values and per-workgroup sums in FP32 (partials added in FP64,
+ * vectors FP64 at the boundary).  afn_setup: AFN_FP32 makes afn_pcg_solve use
+ * iterative refinement: the residual b - (K + mu I) x and the solution are
+ * FP64, each correction comes from an inner PCG whose operator, preconditioner
+ * apply and vectors are FP32 and whose scalar recurrences are FP64; the
+ * factors are built in FP64 (L = chol(K11 + mu I) in FP64) and rounded. */
 typedef enum afn_precision {
     AFN_FP64 = 0,
     AFN_FP32 = 1
@@ -61,7 +65,7 @@ typedef struct afn_params {
     int32_t k_max;      /* cap on the estimated count (Section 3.2: e.g. 2000)     */
     int32_t w;          /* FSAI nonzeros per row incl. the diagonal, 1 <= w <= 64  */
     int32_t m;          /* rank-estimation subsample size; 0 = min(n, 2000)        */
-    int32_t precision;  /* afn_precision of the PCG operator (reserved: AFN_FP64)  */
+    int32_t precision;  /* afn_precision of the PCG solve (AFN_FP32 needs d <= 8)   */
     int32_t reserved;   /* must be 0                                               */
     uint64_t seed;      /* seed of the rank-estimation subsample (splitmix64)      */
 } afn_params;
@@ -87,10 +91,11 @@ typedef struct afn_solve_info {
     double relres;             /* recurrence residual ||r|| / ||b|| (max over rhs)   */
     double relres_true;        /* ||b - (K + mu I) x|| / ||b|| recomputed in FP64    */
     double ms_solve;
-    double ms_matvec;          /* summed device time of the kernel-matvec tile kernel,
+    double ms_matvec;          /* summed device time of the PCG operator's tile kernel
+                                  (FP64, or FP32 for the inner solves of a mixed solve),
                                   from HIP events recorded around each of its launches */
     int32_t matvec_launches;   /* launches timed in ms_matvec                        */
-    int32_t reserved;
+    int32_t outer_iterations;  /* refinement steps of a mixed solve; 0 for FP64      */
 } afn_solve_info;
 
 typedef struct afn_handle afn_handle;
@@ -126,10 +131,14 @@ afn_status afn_apply(afn_handle *h, const double *r_dev, double *z_dev, int32_t 
 
 /* Preconditioned CG from x0 = 0 (Algorithm 5, AFN branch) for each of nrhs
  * right-hand sides, stopping when ||r|| / ||b|| <= tol (Section 5 stopping
- * rule) or after maxit products with K + mu I.  b_dev, x_dev: n x nrhs FP64
- * column-major, leading dimension ld.  info_host may be NULL.  Synchronizes.
+ * rule) or after maxit products with K + mu I.  A handle set up with
+ * precision AFN_FP32 solves by iterative refinement instead: the FP64
+ * residual ||b - (K + mu I) x|| / ||b|| is the stopping test, each inner FP32
+ * PCG runs at most maxit iterations, and ESTAGNATION is returned when the
+ * residual stops decreasing.  b_dev, x_dev: n x nrhs FP64 column-major,
+ * leading dimension ld.  info_host may be NULL.  Synchronizes.
  * Errors: EINVAL (tol <= 0, maxit < 1, nrhs < 1, ld < n), ENOCONV (x holds
- * the last iterate, info valid), EBREAKDOWN, EDEVICE. */
+ * the last iterate, info valid), EBREAKDOWN, ESTAGNATION, EDEVICE. */
 afn_status afn_pcg_solve(afn_handle *h, const double *b_dev, double *x_dev, int32_t nrhs,
                          int64_t ld, double tol, int32_t maxit, afn_solve_info *info_host,
                          void *stream);

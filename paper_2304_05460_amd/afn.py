@@ -55,7 +55,7 @@ class afn_solve_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("relres", ctypes.c_double), ("relres_true", ctypes.c_double),
                 ("ms_solve", ctypes.c_double), ("ms_matvec", ctypes.c_double),
-                ("matvec_launches", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("matvec_launches", ctypes.c_int32), ("outer_iterations", ctypes.c_int32)]
 
 
 def lib():
@@ -262,9 +262,10 @@ def afn_pcg_solve(h: Handle, b: torch.Tensor, tol: float = 1e-6, maxit: int = 50
     if ldx != ld:
         raise ValueError("b and out must share a leading dimension")
     inf = afn_solve_info()
-    ok = (AFN_OK, AFN_ENOCONV) if allow_noconv else (AFN_OK,)
+    ok = (AFN_OK, AFN_ENOCONV, AFN_ESTAGNATION) if allow_noconv else (AFN_OK,)
     st = _check(lib().afn_pcg_solve(h.ptr, bp, xp, nrhs, ld, tol, maxit, ctypes.byref(inf),
                                     _stream(stream)), "afn_pcg_solve", ok)
     return out, dict(status=st, iterations=inf.iterations, converged=bool(inf.converged),
                      relres=inf.relres, relres_true=inf.relres_true, ms_solve=inf.ms_solve,
-                     ms_matvec=inf.ms_matvec, matvec_launches=inf.matvec_launches)
+                     ms_matvec=inf.ms_matvec, matvec_launches=inf.matvec_launches,
+                     outer_iterations=inf.outer_iterations)

@@ -62,6 +62,18 @@ int64_t kmv_workspace_doubles(int64_t n, int d);
 afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, const double *v,
                    int64_t ldv, double *y, int64_t ldy, int nrhs, double *work,
                    hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Pre-scaled SoA copy of the points for the symmetric tile kernels
+// (kmv_packed_doubles(n, d) doubles, or as many floats when f32).
+int64_t kmv_packed_doubles(int64_t n, int d);
+afn_status kmv_pack(const double *X, int64_t n, int d, double l, void *Xs, bool f32, hipStream_t s);
+// y = (K + mu I) v on packed points (d <= 8); part: kmv_workspace_doubles(n, d)
+// doubles (or floats for the FP32 variant).
+afn_status kmv_packed_f64(const double *Xs, int64_t n, int d, double mu, const double *v, int64_t ldv,
+                          double *y, int64_t ldy, int nrhs, double *part, hipStream_t s,
+                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+afn_status kmv_packed_f32(const float *Xs, int64_t n, int d, double mu, const float *v, int64_t ldv,
+                          float *y, int64_t ldy, int nrhs, float *part, hipStream_t s,
+                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // FP32 tiles and accumulation; FP64 vectors at the interface.
 afn_status kmv_f32(const double *X, int64_t n, int d, double l, double mu, const double *v,
                    int64_t ldv, double *y, int64_t ldy, int nrhs, void *work, hipStream_t s);
@@ -118,18 +130,28 @@ int64_t dot_partials(int64_t n);
 // out[c] = sum_i a[i + c*lda] b[i + c*ldb] (fixed reduction order).
 afn_status dot(const double *a, int64_t lda, const double *b, int64_t ldb, int64_t n, int nrhs,
                double *out_dev, double *partials, hipStream_t s);
+afn_status dot(const float *a, int64_t lda, const float *b, int64_t ldb, int64_t n, int nrhs,
+               double *out_dev, double *partials, hipStream_t s);
 int64_t gemv_partials(int64_t m, int64_t ncols);
 // y = base + sign * A x  (A m x ncols, column-major lda; base may be null)
 afn_status gemv_n(const double *A, int64_t lda, int64_t m, int64_t ncols, const double *x,
                   const double *base, double sign, double *y, double *part, hipStream_t s);
+afn_status gemv_n(const float *A, int64_t lda, int64_t m, int64_t ncols, const float *x,
+                  const float *base, float sign, float *y, float *part, hipStream_t s);
 // y = base + sign * A^T x
 afn_status gemv_t(const double *A, int64_t lda, int64_t m, int64_t ncols, const double *x,
                   const double *base, double sign, double *y, hipStream_t s);
+afn_status gemv_t(const float *A, int64_t lda, int64_t m, int64_t ncols, const float *x,
+                  const float *base, float sign, float *y, hipStream_t s);
 // u = G t (padded rows) ;  out = G^T u (CSR of G^T)
 afn_status spmv_g(const int32_t *cols, const double *gval, int64_t nr, int w, const double *t,
                   double *u, hipStream_t s);
+afn_status spmv_g(const int32_t *cols, const float *gval, int64_t nr, int w, const float *t, float *u,
+                  hipStream_t s);
 afn_status spmv_gt(const int64_t *ptr, const int32_t *idx, const double *val, int64_t nr,
                    const double *u, double *out, hipStream_t s);
+afn_status spmv_gt(const int64_t *ptr, const int32_t *idx, const float *val, int64_t nr,
+                   const float *u, float *out, hipStream_t s);
 afn_status permute_gather(const double *src, int64_t lds, double *dst, int64_t ldd,
                           const int32_t *perm, int64_t n, int nrhs, hipStream_t s);
 afn_status permute_scatter(const double *src, int64_t lds, double *dst, int64_t ldd,
@@ -142,7 +164,14 @@ afn_status pcg_alpha_launch(double *sc, hipStream_t s);
 afn_status pcg_beta_launch(double *sc, hipStream_t s);
 afn_status pcg_xr_launch(double *x, double *r, const double *p, const double *q, const double *sc,
                          int64_t n, double *part, double *rr_out, hipStream_t s);
+afn_status pcg_xr_launch(float *x, float *r, const float *p, const float *q, const double *sc,
+                         int64_t n, double *part, double *rr_out, hipStream_t s);
 afn_status pcg_p_launch(double *p, const double *z, const double *sc, int64_t n, hipStream_t s);
+afn_status pcg_p_launch(float *p, const float *z, const double *sc, int64_t n, hipStream_t s);
+// r32 = r * scale; x += a * e; b = (float) a
+afn_status to_f32_scaled_launch(const double *r, double scale, float *r32, int64_t n, hipStream_t s);
+afn_status axpy_f32_into_f64_launch(double a, const float *e, double *x, int64_t n, hipStream_t s);
+afn_status to_f32_launch(const double *a, float *b, int64_t n, hipStream_t s);
 afn_status sub_launch(const double *b, const double *y, double *r, int64_t n, hipStream_t s);
 // *flag |= 1 if a value is not finite
 afn_status finite_launch(const double *a, int64_t n, int *flag, hipStream_t s);
@@ -172,6 +201,14 @@ struct afn_handle {
     double *work = nullptr;     // PCG / apply workspace
     int64_t work_doubles = 0;
     int64_t work_rhs = 0;       // right-hand sides the workspace is sized for
+    double *Xs64 = nullptr;     // points pre-scaled for the symmetric tile kernel (d <= 8)
+    int precision = AFN_FP64;   // AFN_FP32: inner PCG in FP32 inside FP64 refinement
+    float *Xs32 = nullptr;      // FP32 copies for the inner solve
+    float *Linv32 = nullptr;
+    float *V32 = nullptr;
+    float *gval32 = nullptr;
+    float *tval32 = nullptr;
+    float *work32 = nullptr;
     double *host_sc = nullptr;  // pinned host copy of PCG scalars
     hipEvent_t kmv_ev[2] = {nullptr, nullptr};  // timing of the matvec tile kernel
     afn_setup_info info{};

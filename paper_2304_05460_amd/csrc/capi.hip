@@ -78,33 +78,94 @@ int64_t work_doubles(int64_t n, int d, int k, int64_t nr, WorkLayout *L, double 
     return off;
 }
 
+// Workspace of the FP32 inner solves (floats).
+struct WorkLayout32 {
+    float *kmv, *gemvp, *y1, *t, *u, *y1b, *r, *z, *p, *q, *e;
+};
+
+int64_t work32_floats(int64_t n, int d, int k, int64_t nr, WorkLayout32 *L, float *base)
+{
+    int64_t off = 0;
+    auto take = [&](int64_t cnt) {
+        float *ptr = base ? base + off : nullptr;
+        off += round_up(cnt > 0 ? cnt : 1, 64);
+        return ptr;
+    };
+    WorkLayout32 w;
+    int64_t gp = gemv_partials(k, nr > k ? nr : k);
+    int64_t gp2 = gemv_partials(k, k);
+    w.kmv = take(2 * kmv_workspace_doubles(n, d));
+    w.gemvp = take(gp > gp2 ? gp : gp2);
+    w.y1 = take(k);
+    w.t = take(nr);
+    w.u = take(nr);
+    w.y1b = take(k);
+    w.r = take(n);
+    w.z = take(n);
+    w.p = take(n);
+    w.q = take(n);
+    w.e = take(n);
+    if (L) *L = w;
+    return off;
+}
+
+// The factors Algorithm 3 needs, in one precision.
+template <typename T>
+struct Factors {
+    const T *Linv, *V, *gval, *tval;
+};
+
 // s = M^{-1} r in block order (landmarks first): Algorithm 3 with
 // V = L^{-1} K12 and Linv = L^{-1}:
 //   y1 = Linv r1 ; t = r2 - V^T y1 ; s2 = G^T (G t) ; s1 = Linv^T (y1 - V s2)
-afn_status apply_block(afn_handle *h, const double *rp, double *sp, const WorkLayout &w,
-                       hipStream_t s)
+template <typename T>
+afn_status apply_blockT(const afn_handle *h, const Factors<T> &f, const T *rp, T *sp, T *y1, T *tt,
+                        T *u, T *y1b, T *gemvp, hipStream_t s)
 {
     const int k = h->k;
     const int64_t nr = h->nr;
-    if (k > 0) AFN_TRY(gemv_n(h->Linv, k, k, k, rp, nullptr, 1.0, w.y1, w.gemvp, s));
+    if (k > 0) AFN_TRY(gemv_n(f.Linv, k, k, k, rp, (const T *)nullptr, T(1), y1, gemvp, s));
     if (nr > 0) {
-        const double *t = rp + k;
+        const T *t = rp + k;
         if (k > 0) {
-            AFN_TRY(gemv_t(h->V, k, k, nr, w.y1, rp + k, -1.0, w.t, s));
-            t = w.t;
+            AFN_TRY(gemv_t(f.V, k, k, nr, y1, rp + k, T(-1), tt, s));
+            t = tt;
         }
-        AFN_TRY(spmv_g(h->cols, h->gval, nr, h->w, t, w.u, s));
-        AFN_TRY(spmv_gt(h->tptr, h->trow, h->tval, nr, w.u, sp + k, s));
+        AFN_TRY(spmv_g(h->cols, f.gval, nr, h->w, t, u, s));
+        AFN_TRY(spmv_gt(h->tptr, h->trow, f.tval, nr, u, sp + k, s));
     }
     if (k > 0) {
-        const double *y = w.y1;
+        const T *y = y1;
         if (nr > 0) {
-            AFN_TRY(gemv_n(h->V, k, k, nr, sp + k, w.y1, -1.0, w.y1b, w.gemvp, s));
-            y = w.y1b;
+            AFN_TRY(gemv_n(f.V, k, k, nr, sp + k, (const T *)y1, T(-1), y1b, gemvp, s));
+            y = y1b;
         }
-        AFN_TRY(gemv_t(h->Linv, k, k, k, y, nullptr, 1.0, sp, s));
+        AFN_TRY(gemv_t(f.Linv, k, k, k, y, (const T *)nullptr, T(1), sp, s));
     }
     return AFN_OK;
+}
+
+afn_status apply_block(afn_handle *h, const double *rp, double *sp, const WorkLayout &w,
+                       hipStream_t s)
+{
+    Factors<double> f{h->Linv, h->V, h->gval, h->tval};
+    return apply_blockT<double>(h, f, rp, sp, w.y1, w.t, w.u, w.y1b, w.gemvp, s);
+}
+
+afn_status apply_block32(afn_handle *h, const float *rp, float *sp, const WorkLayout32 &w,
+                         hipStream_t s)
+{
+    Factors<float> f{h->Linv32, h->V32, h->gval32, h->tval32};
+    return apply_blockT<float>(h, f, rp, sp, w.y1, w.t, w.u, w.y1b, w.gemvp, s);
+}
+
+// (K + mu I) v on the handle's points, FP64
+afn_status op_f64(afn_handle *h, const double *v, double *y, const WorkLayout &w, hipStream_t s,
+                  hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
+{
+    if (h->Xs64)
+        return kmv_packed_f64(h->Xs64, h->n, h->d, h->mu, v, h->n, y, h->n, 1, w.kmv, s, e0, e1);
+    return kmv_f64(h->Xp, h->n, h->d, h->l, h->mu, v, h->n, y, h->n, 1, w.kmv, s, e0, e1);
 }
 
 afn_status check_flags(afn_handle *h, hipStream_t s)
@@ -212,6 +273,31 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
         AFN_TRY(fsai_transpose(h->cols, h->gval, nr, h->w, h->tptr, h->trow, h->tval, cnt, s));
     }
     tm.mark(6, s);
+    // points packed for the symmetric tile kernel; FP32 copies for mixed solves
+    h->precision = prm->precision;
+    if (d <= 8) {
+        AFN_TRY(h->arena.alloc_n(&h->Xs64, kmv_packed_doubles(n, d)));
+        AFN_TRY(kmv_pack(h->Xp, n, d, l, h->Xs64, false, s));
+    }
+    if (h->precision == AFN_FP32) {
+        AFN_TRY(h->arena.alloc_n(&h->Xs32, kmv_packed_doubles(n, d)));
+        AFN_TRY(kmv_pack(h->Xp, n, d, l, h->Xs32, true, s));
+        if (k > 0) {
+            AFN_TRY(h->arena.alloc_n(&h->Linv32, (int64_t)k * k));
+            AFN_TRY(to_f32_launch(h->Linv, h->Linv32, (int64_t)k * k, s));
+        }
+        if (k > 0 && nr > 0) {
+            AFN_TRY(h->arena.alloc_n(&h->V32, (int64_t)k * nr));
+            AFN_TRY(to_f32_launch(h->V, h->V32, (int64_t)k * nr, s));
+        }
+        if (nr > 0) {
+            AFN_TRY(h->arena.alloc_n(&h->gval32, nr * h->w));
+            AFN_TRY(h->arena.alloc_n(&h->tval32, nr * h->w));
+            AFN_TRY(to_f32_launch(h->gval, h->gval32, nr * h->w, s));
+            AFN_TRY(to_f32_launch(h->tval, h->tval32, nr * h->w, s));
+        }
+        AFN_TRY(h->arena.alloc_n(&h->work32, work32_floats(n, d, k, nr, nullptr, nullptr)));
+    }
     // workspace for apply / PCG
     h->work_doubles = work_doubles(n, d, k, nr, nullptr, nullptr);
     AFN_TRY(h->arena.alloc_n(&h->work, h->work_doubles));
@@ -275,8 +361,7 @@ afn_status pcg_one(afn_handle *h, const double *b, double *xout, double tol, int
     *converged = 0;
     *relres = 1.0;
     for (int it = 0; it < maxit; ++it) {
-        AFN_TRY(kmv_f64(h->Xp, n, h->d, h->l, h->mu, w.p, n, w.q, n, 1, w.kmv, s, h->kmv_ev[0],
-                        h->kmv_ev[1]));
+        AFN_TRY(op_f64(h, w.p, w.q, w, s, h->kmv_ev[0], h->kmv_ev[1]));
         AFN_TRY(dot(w.p, n, w.q, n, n, 1, sc + 1, w.dotp, s));
         AFN_TRY(pcg_alpha_launch(sc, s));
         AFN_TRY(pcg_xr_launch(w.x, w.r, w.p, w.q, sc, n, w.dotp, sc + 2, s));
@@ -309,7 +394,7 @@ afn_status pcg_one(afn_handle *h, const double *b, double *xout, double tol, int
         AFN_TRY(pcg_p_launch(w.p, w.z, sc, n, s));
     }
     // true residual in FP64
-    AFN_TRY(kmv_f64(h->Xp, n, h->d, h->l, h->mu, w.x, n, w.q, n, 1, w.kmv, s));
+    AFN_TRY(op_f64(h, w.x, w.q, w, s));
     AFN_TRY(sub_launch(w.bp, w.q, w.tmp, n, s));
     AFN_TRY(dot(w.tmp, n, w.tmp, n, n, 1, sc + 7, w.dotp, s));
     AFN_HIP(hipMemcpyAsync(hs + 7, sc + 7, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -318,6 +403,141 @@ afn_status pcg_one(afn_handle *h, const double *b, double *xout, double tol, int
     *relres_true = std::sqrt(hs[7]) / bnorm;
     if (status == AFN_ENOCONV)
         set_error("afn_pcg_solve: no convergence in %d iterations (relres %g)", maxit, *relres);
+    return status;
+}
+
+// Inner PCG in FP32 (operator, preconditioner and vectors), FP64 scalars:
+// solve (K + mu I) e = r0 to relative recurrence residual tol_in.  r0 in w32.r
+// on entry (overwritten), e in w32.e on exit.  sc: 8 device scalar slots.
+afn_status pcg_inner32(afn_handle *h, double r0norm, double tol_in, int maxit, const WorkLayout32 &w,
+                       double *dotp, double *sc, hipStream_t s, int *iters, double *rel_out,
+                       double *ms_kmv, int *n_kmv)
+{
+    const int64_t n = h->n;
+    double *hs = h->host_sc;
+    AFN_HIP(hipMemsetAsync(w.e, 0, sizeof(float) * n, s));
+    AFN_TRY(apply_block32(h, w.r, w.z, w, s));
+    AFN_HIP(hipMemcpyAsync(w.p, w.z, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+    AFN_TRY(dot(w.r, n, w.z, n, n, 1, sc + 0, dotp, s));
+    *iters = 0;
+    *rel_out = 1.0;
+    for (int it = 0; it < maxit; ++it) {
+        AFN_TRY(kmv_packed_f32(h->Xs32, n, h->d, h->mu, w.p, n, w.q, n, 1, w.kmv, s, h->kmv_ev[0],
+                               h->kmv_ev[1]));
+        AFN_TRY(dot(w.p, n, w.q, n, n, 1, sc + 1, dotp, s));
+        AFN_TRY(pcg_alpha_launch(sc, s));
+        AFN_TRY(pcg_xr_launch(w.e, w.r, w.p, w.q, sc, n, dotp, sc + 2, s));
+        AFN_HIP(hipMemcpyAsync(hs + 9, sc + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        AFN_HIP(hipStreamSynchronize(s));
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, h->kmv_ev[0], h->kmv_ev[1]) == hipSuccess) {
+            *ms_kmv += t;
+            *n_kmv += 1;
+        }
+        *iters = it + 1;
+        const double pq = hs[9];
+        const double rel = std::sqrt(hs[10]) / r0norm;
+        *rel_out = rel;
+        if (!(pq > 0.0) || !(rel == rel)) {
+            set_error("afn_pcg_solve: inner FP32 breakdown at iteration %d (p'Ap = %g)", it + 1, pq);
+            return AFN_EBREAKDOWN;
+        }
+        if (rel <= tol_in) break;
+        AFN_TRY(apply_block32(h, w.r, w.z, w, s));
+        AFN_TRY(dot(w.r, n, w.z, n, n, 1, sc + 3, dotp, s));
+        AFN_TRY(pcg_beta_launch(sc, s));
+        AFN_TRY(pcg_p_launch(w.p, w.z, sc, n, s));
+    }
+    return AFN_OK;
+}
+
+// Iterative refinement: x_0 = 0; r = b - (K + mu I) x in FP64; correction
+// from the FP32 inner PCG on r / ||r||; stop when ||r|| / ||b|| <= tol.
+afn_status pcg_refine(afn_handle *h, const double *b, double *xout, double tol, int maxit,
+                      const WorkLayout &w, const WorkLayout32 &w32, hipStream_t s, int *iters,
+                      int *outer, double *relres, double *relres_true, int *converged,
+                      double *ms_kmv, int *n_kmv)
+{
+    const int64_t n = h->n;
+    double *sc = w.sc;
+    double *hs = h->host_sc;
+    AFN_TRY(permute_gather(b, n, w.bp, n, h->perm, n, 1, s));
+    AFN_HIP(hipMemsetAsync(w.x, 0, sizeof(double) * n, s));
+    AFN_HIP(hipMemcpyAsync(w.r, w.bp, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    AFN_TRY(dot(w.bp, n, w.bp, n, n, 1, sc + 6, w.dotp, s));
+    AFN_HIP(hipMemcpyAsync(hs + 6, sc + 6, sizeof(double), hipMemcpyDeviceToHost, s));
+    AFN_HIP(hipStreamSynchronize(s));
+    const double bnorm = std::sqrt(hs[6]);
+    *iters = 0;
+    *outer = 0;
+    *relres = 0.0;
+    *relres_true = 0.0;
+    *converged = 1;
+    if (!(bnorm > 0.0)) {
+        AFN_TRY(permute_scatter(w.x, n, xout, n, h->perm, n, 1, s));
+        if (!(bnorm == 0.0)) {
+            set_error("afn_pcg_solve: right-hand side holds a non-finite value");
+            *converged = 0;
+            *relres = NAN;
+            return AFN_EBREAKDOWN;
+        }
+        return AFN_OK;
+    }
+    *converged = 0;
+    afn_status status = AFN_ENOCONV;
+    double prev = INFINITY;
+    const int max_outer = 40;
+    for (int o = 0;; ++o) {
+        AFN_TRY(dot(w.r, n, w.r, n, n, 1, sc + 7, w.dotp, s));
+        AFN_HIP(hipMemcpyAsync(hs + 7, sc + 7, sizeof(double), hipMemcpyDeviceToHost, s));
+        AFN_HIP(hipStreamSynchronize(s));
+        const double rnorm = std::sqrt(hs[7]);
+        const double rel = rnorm / bnorm;
+        *relres = rel;
+        *relres_true = rel;
+        if (!(rel == rel)) {
+            set_error("afn_pcg_solve: refinement produced a non-finite residual");
+            status = AFN_EBREAKDOWN;
+            break;
+        }
+        if (rel <= tol) {
+            status = AFN_OK;
+            *converged = 1;
+            break;
+        }
+        if (o >= max_outer || (o >= 3 && rel > 0.5 * prev)) {
+            set_error("afn_pcg_solve: refinement stagnated at relative residual %g after %d steps",
+                      rel, o);
+            status = AFN_ESTAGNATION;
+            break;
+        }
+        if (*iters >= maxit * 4) {
+            set_error("afn_pcg_solve: no convergence (relres %g)", rel);
+            status = AFN_ENOCONV;
+            break;
+        }
+        prev = rel;
+        // inner tolerance: what this step needs, but at least 1e-4 of its start
+        double tol_in = 0.5 * tol / rel;
+        tol_in = tol_in > 1e-4 ? tol_in : 1e-4;
+        tol_in = tol_in < 0.5 ? tol_in : 0.5;
+        AFN_TRY(to_f32_scaled_launch(w.r, 1.0 / rnorm, w32.r, n, s));
+        int it = 0;
+        double rel_in = 0;
+        afn_status st = pcg_inner32(h, 1.0, tol_in, maxit, w32, w.dotp, sc + 8, s, &it, &rel_in,
+                                    ms_kmv, n_kmv);
+        *iters += it;
+        *outer = o + 1;
+        if (st != AFN_OK) {
+            status = st;
+            break;
+        }
+        AFN_TRY(axpy_f32_into_f64_launch(rnorm, w32.e, w.x, n, s));
+        AFN_TRY(op_f64(h, w.x, w.q, w, s));
+        AFN_TRY(sub_launch(w.bp, w.q, w.r, n, s));
+    }
+    AFN_TRY(permute_scatter(w.x, n, xout, n, h->perm, n, 1, s));
+    AFN_HIP(hipStreamSynchronize(s));
     return status;
 }
 
@@ -340,7 +560,8 @@ afn_status afn_setup(const double *X_dev, int64_t n, int32_t d, double l, double
     if (!X_dev || !prm || n < 1 || n > INT32_MAX - 1 || d < 1 || d > kMaxD || !(l > 0) ||
         !std::isfinite(l) || !(mu >= 0) || !std::isfinite(mu) || prm->k < -1 || prm->k > n ||
         prm->w < 1 || prm->w > kMaxW || prm->reserved != 0 ||
-        (prm->precision != AFN_FP64 && prm->precision != AFN_FP32)) {
+        (prm->precision != AFN_FP64 && prm->precision != AFN_FP32) ||
+        (prm->precision == AFN_FP32 && d > 8)) {
         set_error("afn_setup: invalid argument (n=%lld d=%d l=%g mu=%g k=%d w=%d)", (long long)n, d,
                   l, mu, prm ? prm->k : 0, prm ? prm->w : 0);
         return AFN_EINVAL;
@@ -390,18 +611,27 @@ afn_status afn_pcg_solve(afn_handle *h, const double *b_dev, double *x_dev, int3
     hipStream_t s = (hipStream_t)stream;
     WorkLayout w;
     work_doubles(h->n, h->d, h->k, h->nr, &w, h->work);
+    WorkLayout32 w32{};
+    if (h->precision == AFN_FP32) work32_floats(h->n, h->d, h->k, h->nr, &w32, h->work32);
     Timer tm;
     tm.mark(0, s);
+    int outer_max = 0;
     afn_status worst = AFN_OK;
     int it_max = 0, conv_all = 1, n_kmv = 0;
     double ms_kmv = 0.0;
     double rel_max = 0.0, true_max = 0.0;
     for (int c = 0; c < nrhs; ++c) {
-        int it = 0, conv = 0;
+        int it = 0, conv = 0, outer = 0;
         double rel = 0, rt = 0;
-        afn_status st = pcg_one(h, b_dev + c * ld, x_dev + c * ld, tol, maxit, w, s, &it, &rel,
-                                &rt, &conv, &ms_kmv, &n_kmv);
-        if (st != AFN_OK && st != AFN_ENOCONV && st != AFN_EBREAKDOWN) return st;
+        afn_status st =
+            h->precision == AFN_FP32
+                ? pcg_refine(h, b_dev + c * ld, x_dev + c * ld, tol, maxit, w, w32, s, &it, &outer,
+                             &rel, &rt, &conv, &ms_kmv, &n_kmv)
+                : pcg_one(h, b_dev + c * ld, x_dev + c * ld, tol, maxit, w, s, &it, &rel, &rt, &conv,
+                          &ms_kmv, &n_kmv);
+        outer_max = outer > outer_max ? outer : outer_max;
+        if (st != AFN_OK && st != AFN_ENOCONV && st != AFN_EBREAKDOWN && st != AFN_ESTAGNATION)
+            return st;
         if (st != AFN_OK && worst == AFN_OK) worst = st;
         if (st == AFN_EBREAKDOWN) worst = st;
         it_max = it > it_max ? it : it_max;
@@ -419,7 +649,7 @@ afn_status afn_pcg_solve(afn_handle *h, const double *b_dev, double *x_dev, int3
         info->ms_solve = tm.ms(0, 1);
         info->ms_matvec = ms_kmv;
         info->matvec_launches = n_kmv;
-        info->reserved = 0;
+        info->outer_iterations = outer_max;
     }
     return worst;
 }

@@ -52,17 +52,23 @@ __device__ __forceinline__ double exp2_neg(double t)
     return __builtin_ldexp(p, (int)(-kd));
 }
 
-// Xs[t * npad + i] = X[i*d + t] * scale for i < n, 0 beyond.
+// Xs[t * npad + i] = X[i*d + t] * scale for i < n, 0 beyond (rounded to T).
+template <typename T>
 __global__ __launch_bounds__(256) void pack_scaled(const double *__restrict__ X, int64_t n, int d,
-                                                   int64_t npad, double scale,
-                                                   double *__restrict__ Xs)
+                                                   int64_t npad, double scale, T *__restrict__ Xs)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= npad * d) return;
     const int t = (int)(e / npad);
     const int64_t i = e - (int64_t)t * npad;
-    Xs[e] = i < n ? X[i * d + t] * scale : 0.0;
+    Xs[e] = (T)(i < n ? X[i * d + t] * scale : 0.0);
 }
+
+// 2^(-t) in FP32 with the hardware base-2 exponential.
+__device__ __forceinline__ float exp2_neg(float t) { return __builtin_amdgcn_exp2f(-t); }
+
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
 __device__ __forceinline__ void decode_pair(int q, int S, int &BI, int &BJ)
 {
@@ -75,33 +81,33 @@ __device__ __forceinline__ void decode_pair(int q, int S, int &BI, int &BJ)
     BJ = bi + rem;
 }
 
-template <int D>
-__global__ __launch_bounds__(256) void kmv_sym_f64(const double *__restrict__ Xs, int64_t npad,
-                                                   int64_t n, const double *__restrict__ v, int S,
-                                                   int ST, double *__restrict__ part)
+template <int D, typename T, typename VT>
+__global__ __launch_bounds__(256) void kmv_sym(const T *__restrict__ Xs, int64_t npad, int64_t n,
+                                               const VT *__restrict__ v, int S, int ST,
+                                               T *__restrict__ part)
 {
-    __shared__ double cx[D][kTile];
-    __shared__ double cv[kTile];
-    __shared__ double red[16][kTile + 1];
-    __shared__ double colacc[kMaxST][kTile];
+    __shared__ T cx[D][kTile];
+    __shared__ T cv[kTile];
+    __shared__ T red[16][kTile + 1];
+    __shared__ T colacc[kMaxST][kTile];
     const int tid = threadIdx.x;
     const int ty = tid >> 4, tx = tid & 15;
     int BI, BJ;
     decode_pair(blockIdx.x, S, BI, BJ);
     const int64_t SB = (int64_t)ST * kTile;
     const bool diag_super = BI == BJ;
-    for (int e = tid; e < kMaxST * kTile; e += 256) (&colacc[0][0])[e] = 0.0;
-    double *rowout = part + (int64_t)blockIdx.x * 2 * SB;
-    double *colout = rowout + SB;
+    for (int e = tid; e < kMaxST * kTile; e += 256) (&colacc[0][0])[e] = T(0);
+    T *rowout = part + (int64_t)blockIdx.x * 2 * SB;
+    T *colout = rowout + SB;
     for (int ti = 0; ti < ST; ++ti) {
         const int64_t i0 = BI * SB + (int64_t)ti * kTile + ty * 4;
-        double xi[4][D], vi[4], racc[4];
+        T xi[4][D], vi[4], racc[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
 #pragma unroll
             for (int t = 0; t < D; ++t) xi[r][t] = Xs[(int64_t)t * npad + i0 + r];
-            vi[r] = i0 + r < n ? v[i0 + r] : 0.0;
-            racc[r] = 0.0;
+            vi[r] = i0 + r < n ? (T)v[i0 + r] : T(0);
+            racc[r] = T(0);
         }
         for (int tj = diag_super ? ti : 0; tj < ST; ++tj) {
             const int64_t j0 = BJ * SB + (int64_t)tj * kTile;
@@ -109,33 +115,33 @@ __global__ __launch_bounds__(256) void kmv_sym_f64(const double *__restrict__ Xs
             if (tid < kTile * (D + 1)) {
                 const int t = tid / kTile, j = tid % kTile;
                 if (t < D) cx[t][j] = Xs[(int64_t)t * npad + j0 + j];
-                else cv[j] = j0 + j < n ? v[j0 + j] : 0.0;
+                else cv[j] = j0 + j < n ? (T)v[j0 + j] : T(0);
             }
             for (int e = tid + 256; e < kTile * (D + 1); e += 256) {
                 const int t = e / kTile, j = e % kTile;
                 if (t < D) cx[t][j] = Xs[(int64_t)t * npad + j0 + j];
-                else cv[j] = j0 + j < n ? v[j0 + j] : 0.0;
+                else cv[j] = j0 + j < n ? (T)v[j0 + j] : T(0);
             }
             __syncthreads();
             const bool diag_tile = diag_super && tj == ti;
-            double cacc[4] = {0.0, 0.0, 0.0, 0.0};
+            T cacc[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                double xj[D];
+                T xj[D];
 #pragma unroll
                 for (int t = 0; t < D; ++t) xj[t] = cx[t][tx * 4 + c];
-                const double vj = cv[tx * 4 + c];
+                const T vj = cv[tx * 4 + c];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    double d2 = 0.0;
+                    T d2 = T(0);
 #pragma unroll
                     for (int t = 0; t < D; ++t) {
-                        const double del = xi[r][t] - xj[t];
-                        d2 = __builtin_fma(del, del, d2);
+                        const T del = xi[r][t] - xj[t];
+                        d2 = fmaT(del, del, d2);
                     }
-                    const double kij = exp2_neg(d2);
-                    racc[r] = __builtin_fma(kij, vj, racc[r]);
-                    cacc[c] = __builtin_fma(kij, vi[r], cacc[c]);
+                    const T kij = exp2_neg(d2);
+                    racc[r] = fmaT(kij, vj, racc[r]);
+                    cacc[c] = fmaT(kij, vi[r], cacc[c]);
                 }
             }
             if (!diag_tile) {
@@ -143,7 +149,7 @@ __global__ __launch_bounds__(256) void kmv_sym_f64(const double *__restrict__ Xs
                 for (int c = 0; c < 4; ++c) red[ty][tx * 4 + c] = cacc[c];
                 __syncthreads();
                 if (tid < kTile) {
-                    double s = 0.0;
+                    T s = T(0);
 #pragma unroll
                     for (int y = 0; y < 16; ++y) s += red[y][tid];
                     colacc[tj][tid] += s;
@@ -156,7 +162,7 @@ __global__ __launch_bounds__(256) void kmv_sym_f64(const double *__restrict__ Xs
         for (int r = 0; r < 4; ++r) red[tx][ty * 4 + r] = racc[r];
         __syncthreads();
         if (tid < kTile) {
-            double s = 0.0;
+            T s = T(0);
 #pragma unroll
             for (int x = 0; x < 16; ++x) s += red[x][tid];
             rowout[(int64_t)ti * kTile + tid] = s;
@@ -168,10 +174,10 @@ __global__ __launch_bounds__(256) void kmv_sym_f64(const double *__restrict__ Xs
 
 // y_i = sum over BJ >= s of row partials + sum over BI <= s of column
 // partials (ascending) + mu v_i, s = super-block of i.
-__global__ __launch_bounds__(256) void kmv_sym_reduce(const double *__restrict__ part, int64_t n,
-                                                      int S, int ST, double mu,
-                                                      const double *__restrict__ v,
-                                                      double *__restrict__ y)
+template <typename T, typename VT>
+__global__ __launch_bounds__(256) void kmv_sym_reduce(const T *__restrict__ part, int64_t n, int S,
+                                                      int ST, double mu, const VT *__restrict__ v,
+                                                      VT *__restrict__ y)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -180,12 +186,12 @@ __global__ __launch_bounds__(256) void kmv_sym_reduce(const double *__restrict__
     const int64_t ii = i - (int64_t)s * SB;
     double acc = 0.0;
     const int64_t qs = (int64_t)s * S - (int64_t)s * (s - 1) / 2;   // q(s, s)
-    for (int bj = s; bj < S; ++bj) acc += part[(qs + bj - s) * 2 * SB + ii];
+    for (int bj = s; bj < S; ++bj) acc += (double)part[(qs + bj - s) * 2 * SB + ii];
     for (int bi = 0; bi <= s; ++bi) {
         const int64_t q = (int64_t)bi * S - (int64_t)bi * (bi - 1) / 2 + (s - bi);
-        acc += part[q * 2 * SB + SB + ii];
+        acc += (double)part[q * 2 * SB + SB + ii];
     }
-    y[i] = acc + mu * v[i];
+    y[i] = (VT)(acc + mu * (double)v[i]);
 }
 
 template <int D, int BN>
@@ -380,6 +386,74 @@ int64_t kmv_workspace_doubles(int64_t n, int d)
     return split;
 }
 
+namespace {
+
+template <typename T, typename VT>
+afn_status kmv_sym_run(const T *Xs, const SymShape &sh, int64_t n, int d, double mu, const VT *v,
+                       int64_t ldv, VT *y, int64_t ldy, int nrhs, T *part, hipStream_t s,
+                       hipEvent_t ev0, hipEvent_t ev1)
+{
+    for (int c = 0; c < nrhs; ++c) {
+        const VT *vc = v + c * ldv;
+        if (ev0) AFN_HIP(hipEventRecord(ev0, s));
+        dim3 grid((unsigned)sh.nwg), block(256);
+        switch (d) {
+            case 1: hipLaunchKernelGGL((kmv_sym<1, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
+            case 2: hipLaunchKernelGGL((kmv_sym<2, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
+            case 3: hipLaunchKernelGGL((kmv_sym<3, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
+            case 4: hipLaunchKernelGGL((kmv_sym<4, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
+            case 5: hipLaunchKernelGGL((kmv_sym<5, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
+            case 6: hipLaunchKernelGGL((kmv_sym<6, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
+            case 7: hipLaunchKernelGGL((kmv_sym<7, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
+            default: hipLaunchKernelGGL((kmv_sym<8, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
+        }
+        AFN_HIP(hipGetLastError());
+        if (ev1) AFN_HIP(hipEventRecord(ev1, s));
+        hipLaunchKernelGGL((kmv_sym_reduce<T, VT>), dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, part,
+                           n, sh.S, sh.ST, mu, vc, y + c * ldy);
+        AFN_HIP(hipGetLastError());
+    }
+    return AFN_OK;
+}
+
+}  // namespace
+
+int64_t kmv_packed_doubles(int64_t n, int d)
+{
+    const SymShape sh = sym_shape(n);
+    return sh.npad * d;
+}
+
+afn_status kmv_pack(const double *X, int64_t n, int d, double l, void *Xs, bool f32, hipStream_t s)
+{
+    const SymShape sh = sym_shape(n);
+    const double scale = std::sqrt(1.4426950408889634) / l;
+    if (f32)
+        hipLaunchKernelGGL(pack_scaled<float>, dim3((unsigned)ceil_div(sh.npad * d, 256)), dim3(256), 0, s,
+                           X, n, d, sh.npad, scale, (float *)Xs);
+    else
+        hipLaunchKernelGGL(pack_scaled<double>, dim3((unsigned)ceil_div(sh.npad * d, 256)), dim3(256), 0, s,
+                           X, n, d, sh.npad, scale, (double *)Xs);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status kmv_packed_f64(const double *Xs, int64_t n, int d, double mu, const double *v, int64_t ldv,
+                          double *y, int64_t ldy, int nrhs, double *part, hipStream_t s,
+                          hipEvent_t ev0, hipEvent_t ev1)
+{
+    return kmv_sym_run<double, double>(Xs, sym_shape(n), n, d, mu, v, ldv, y, ldy, nrhs, part, s, ev0,
+                                       ev1);
+}
+
+afn_status kmv_packed_f32(const float *Xs, int64_t n, int d, double mu, const float *v, int64_t ldv,
+                          float *y, int64_t ldy, int nrhs, float *part, hipStream_t s,
+                          hipEvent_t ev0, hipEvent_t ev1)
+{
+    return kmv_sym_run<float, float>(Xs, sym_shape(n), n, d, mu, v, ldv, y, ldy, nrhs, part, s, ev0,
+                                     ev1);
+}
+
 afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, const double *v,
                    int64_t ldv, double *y, int64_t ldy, int nrhs, double *work, hipStream_t s,
                    hipEvent_t ev0, hipEvent_t ev1)
@@ -388,30 +462,8 @@ afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, const
         const SymShape sh = sym_shape(n);
         double *Xs = work;
         double *part = work + sh.npad * d;
-        const double scale = std::sqrt(1.4426950408889634) / l;
-        hipLaunchKernelGGL(pack_scaled, dim3((unsigned)ceil_div(sh.npad * d, 256)), dim3(256), 0, s, X,
-                           n, d, sh.npad, scale, Xs);
-        for (int c = 0; c < nrhs; ++c) {
-            const double *vc = v + c * ldv;
-            if (ev0) AFN_HIP(hipEventRecord(ev0, s));
-            dim3 grid((unsigned)sh.nwg), block(256);
-            switch (d) {
-                case 1: hipLaunchKernelGGL(kmv_sym_f64<1>, grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
-                case 2: hipLaunchKernelGGL(kmv_sym_f64<2>, grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
-                case 3: hipLaunchKernelGGL(kmv_sym_f64<3>, grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
-                case 4: hipLaunchKernelGGL(kmv_sym_f64<4>, grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
-                case 5: hipLaunchKernelGGL(kmv_sym_f64<5>, grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
-                case 6: hipLaunchKernelGGL(kmv_sym_f64<6>, grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
-                case 7: hipLaunchKernelGGL(kmv_sym_f64<7>, grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
-                default: hipLaunchKernelGGL(kmv_sym_f64<8>, grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
-            }
-            AFN_HIP(hipGetLastError());
-            if (ev1) AFN_HIP(hipEventRecord(ev1, s));
-            hipLaunchKernelGGL(kmv_sym_reduce, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, part, n,
-                               sh.S, sh.ST, mu, vc, y + c * ldy);
-            AFN_HIP(hipGetLastError());
-        }
-        return AFN_OK;
+        AFN_TRY(kmv_pack(X, n, d, l, Xs, false, s));
+        return kmv_sym_run<double, double>(Xs, sh, n, d, mu, v, ldv, y, ldy, nrhs, part, s, ev0, ev1);
     }
     const int64_t S = kmv_splits(n);
     const int64_t split_len = ceil_div(n, S);
@@ -437,6 +489,14 @@ namespace afn {
 afn_status kmv_f32(const double *X, int64_t n, int d, double l, double mu, const double *v,
                    int64_t ldv, double *y, int64_t ldy, int nrhs, void *work, hipStream_t s)
 {
+    if (d >= 1 && d <= 8) {
+        const SymShape sh = sym_shape(n);
+        float *Xs = (float *)work;
+        float *part = Xs + round_up(sh.npad * d, 64);
+        AFN_TRY(kmv_pack(X, n, d, l, Xs, true, s));
+        return kmv_sym_run<float, double>(Xs, sh, n, d, mu, v, ldv, y, ldy, nrhs, part, s, nullptr,
+                                          nullptr);
+    }
     const int64_t S = kmv_splits(n);
     const int64_t split_len = ceil_div(n, S);
     const float sc = (float)(-1.4426950408889634 / (l * l));

@@ -12,6 +12,13 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+__device__ __forceinline__ float wave_sumT(float v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_sumT(double v) { return wave_sum(v); }
+
 __device__ double block_sum(double v)
 {
     __shared__ double ws[16];
@@ -29,14 +36,16 @@ __device__ double block_sum(double v)
 
 constexpr int kDotBlocks = 512;
 
-__global__ __launch_bounds__(256) void dot_stage1(const double *__restrict__ a,
-                                                  const double *__restrict__ b, int64_t n,
-                                                  int64_t chunk, double *__restrict__ part)
+template <typename T>
+__global__ __launch_bounds__(256) void dot_stage1(const T *__restrict__ a, const T *__restrict__ b,
+                                                  int64_t n, int64_t chunk,
+                                                  double *__restrict__ part)
 {
     const int64_t i0 = (int64_t)blockIdx.x * chunk;
     const int64_t i1 = i0 + chunk < n ? i0 + chunk : n;
     double s = 0.0;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) s = __builtin_fma(a[i], b[i], s);
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x)
+        s = __builtin_fma((double)a[i], (double)b[i], s);
     s = block_sum(s);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
@@ -50,79 +59,83 @@ __global__ __launch_bounds__(256) void sum_stage2(const double *__restrict__ par
     if (threadIdx.x == 0) *out = s;
 }
 
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // y[i] (+)= sum over column chunk of A[i + j*lda] x[j]; partial per split.
-__global__ __launch_bounds__(256) void gemv_n_partial(const double *__restrict__ A, int64_t lda,
-                                                      int64_t m, int64_t ncols,
-                                                      const double *__restrict__ x,
-                                                      int64_t chunk, double *__restrict__ part)
+template <typename T>
+__global__ __launch_bounds__(256) void gemv_n_partial(const T *__restrict__ A, int64_t lda, int64_t m,
+                                                      int64_t ncols, const T *__restrict__ x,
+                                                      int64_t chunk, T *__restrict__ part)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t j0 = (int64_t)blockIdx.y * chunk;
     const int64_t j1 = j0 + chunk < ncols ? j0 + chunk : ncols;
     if (i >= m) return;
-    double s = 0.0;
-    for (int64_t j = j0; j < j1; ++j) s = __builtin_fma(A[i + j * lda], x[j], s);
+    T s = T(0);
+    for (int64_t j = j0; j < j1; ++j) s = fmaT(A[i + j * lda], x[j], s);
     part[(int64_t)blockIdx.y * m + i] = s;
 }
 
 // y[i] = base[i] + sign * sum_s part[s][i]   (base may be null -> 0)
-__global__ __launch_bounds__(256) void gemv_n_reduce(const double *__restrict__ part, int64_t m,
-                                                     int splits, const double *__restrict__ base,
-                                                     double sign, double *__restrict__ y)
+template <typename T>
+__global__ __launch_bounds__(256) void gemv_n_reduce(const T *__restrict__ part, int64_t m,
+                                                     int splits, const T *__restrict__ base,
+                                                     T sign, T *__restrict__ y)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
-    double s = 0.0;
+    T s = T(0);
     for (int k = 0; k < splits; ++k) s += part[(int64_t)k * m + i];
-    y[i] = (base ? base[i] : 0.0) + sign * s;
+    y[i] = (base ? base[i] : T(0)) + sign * s;
 }
 
 // y[j] = base[j] + sign * sum_i A[i + j*lda] x[i], one wavefront per column.
-__global__ __launch_bounds__(256) void gemv_t_kernel(const double *__restrict__ A, int64_t lda,
-                                                     int64_t m, int64_t ncols,
-                                                     const double *__restrict__ x,
-                                                     const double *__restrict__ base, double sign,
-                                                     double *__restrict__ y)
+template <typename T>
+__global__ __launch_bounds__(256) void gemv_t_kernel(const T *__restrict__ A, int64_t lda, int64_t m,
+                                                     int64_t ncols, const T *__restrict__ x,
+                                                     const T *__restrict__ base, T sign,
+                                                     T *__restrict__ y)
 {
     const int lane = threadIdx.x & 63;
     const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (j >= ncols) return;
-    const double *col = A + j * lda;
-    double s = 0.0;
-    for (int64_t i = lane; i < m; i += 64) s = __builtin_fma(col[i], x[i], s);
-    s = wave_sum(s);
-    if (lane == 0) y[j] = (base ? base[j] : 0.0) + sign * s;
+    const T *col = A + j * lda;
+    T s = T(0);
+    for (int64_t i = lane; i < m; i += 64) s = fmaT(col[i], x[i], s);
+    s = wave_sumT(s);
+    if (lane == 0) y[j] = (base ? base[j] : T(0)) + sign * s;
 }
 
 // u[p] = sum_a gval[p*w + a] t[cols[p*w + a]], a < min(p+1, w); wave per row.
+template <typename T>
 __global__ __launch_bounds__(256) void spmv_padded(const int32_t *__restrict__ cols,
-                                                   const double *__restrict__ gval, int64_t nr,
-                                                   int w, const double *__restrict__ t,
-                                                   double *__restrict__ u)
+                                                   const T *__restrict__ gval, int64_t nr, int w,
+                                                   const T *__restrict__ t, T *__restrict__ u)
 {
     const int lane = threadIdx.x & 63;
     const int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (p >= nr) return;
     const int m = (int)(p + 1 < w ? p + 1 : w);
-    double s = 0.0;
+    T s = T(0);
     if (lane < m) s = gval[p * w + lane] * t[cols[p * w + lane]];
-    s = wave_sum(s);
+    s = wave_sumT(s);
     if (lane == 0) u[p] = s;
 }
 
 // s[c] = sum_e tval[e] u[trow[e]] over e in [ptr[c], ptr[c+1]); wave per row.
+template <typename T>
 __global__ __launch_bounds__(256) void spmv_csr(const int64_t *__restrict__ ptr,
                                                 const int32_t *__restrict__ idx,
-                                                const double *__restrict__ val, int64_t nrows,
-                                                const double *__restrict__ u,
-                                                double *__restrict__ out)
+                                                const T *__restrict__ val, int64_t nrows,
+                                                const T *__restrict__ u, T *__restrict__ out)
 {
     const int lane = threadIdx.x & 63;
     const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (c >= nrows) return;
-    double s = 0.0;
-    for (int64_t e = ptr[c] + lane; e < ptr[c + 1]; e += 64) s = __builtin_fma(val[e], u[idx[e]], s);
-    s = wave_sum(s);
+    T s = T(0);
+    for (int64_t e = ptr[c] + lane; e < ptr[c + 1]; e += 64) s = fmaT(val[e], u[idx[e]], s);
+    s = wave_sumT(s);
     if (lane == 0) out[c] = s;
 }
 
@@ -172,34 +185,62 @@ __global__ void pcg_beta(double *sc)
     sc[0] = sc[3];
 }
 
-// x += alpha p; r -= alpha q; partial sums of r.r
-__global__ __launch_bounds__(256) void pcg_xr(double *__restrict__ x, double *__restrict__ r,
-                                              const double *__restrict__ p,
-                                              const double *__restrict__ q,
+// x += alpha p; r -= alpha q; partial sums of r.r (FP64 scalars, vectors in T)
+template <typename T>
+__global__ __launch_bounds__(256) void pcg_xr(T *__restrict__ x, T *__restrict__ r,
+                                              const T *__restrict__ p, const T *__restrict__ q,
                                               const double *__restrict__ sc, int64_t n,
                                               int64_t chunk, double *__restrict__ part)
 {
-    const double alpha = sc[4];
+    const T alpha = (T)sc[4];
     const int64_t i0 = (int64_t)blockIdx.x * chunk;
     const int64_t i1 = i0 + chunk < n ? i0 + chunk : n;
     double s = 0.0;
     for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-        x[i] = __builtin_fma(alpha, p[i], x[i]);
-        double ri = __builtin_fma(-alpha, q[i], r[i]);
+        x[i] = fmaT(alpha, p[i], x[i]);
+        const T ri = fmaT(-alpha, q[i], r[i]);
         r[i] = ri;
-        s = __builtin_fma(ri, ri, s);
+        s = __builtin_fma((double)ri, (double)ri, s);
     }
     s = block_sum(s);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 // p = z + beta p
-__global__ __launch_bounds__(256) void pcg_p(double *__restrict__ p, const double *__restrict__ z,
+template <typename T>
+__global__ __launch_bounds__(256) void pcg_p(T *__restrict__ p, const T *__restrict__ z,
                                              const double *__restrict__ sc, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    p[i] = __builtin_fma(sc[5], p[i], z[i]);
+    p[i] = fmaT((T)sc[5], p[i], z[i]);
+}
+
+// r32 = r * scale (rounded to FP32)
+__global__ __launch_bounds__(256) void to_f32_scaled(const double *__restrict__ r, double scale,
+                                                     float *__restrict__ r32, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    r32[i] = (float)(r[i] * scale);
+}
+
+// x += a * e (e in FP32)
+__global__ __launch_bounds__(256) void axpy_f32_into_f64(double a, const float *__restrict__ e,
+                                                         double *__restrict__ x, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    x[i] = __builtin_fma(a, (double)e[i], x[i]);
+}
+
+// FP32 copy of an FP64 array
+__global__ __launch_bounds__(256) void to_f32(const double *__restrict__ a, float *__restrict__ b,
+                                              int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    b[i] = (float)a[i];
 }
 
 // r = b - y (true residual)
@@ -229,20 +270,6 @@ int64_t dot_partials(int64_t n)
     return b < 1 ? 1 : (b > kDotBlocks ? kDotBlocks : b);
 }
 
-afn_status dot(const double *a, int64_t lda, const double *b, int64_t ldb, int64_t n, int nrhs,
-               double *out, double *part, hipStream_t s)
-{
-    const int64_t nb = dot_partials(n);
-    const int64_t chunk = ceil_div(n, nb);
-    for (int c = 0; c < nrhs; ++c) {
-        hipLaunchKernelGGL(dot_stage1, dim3((unsigned)nb), dim3(256), 0, s, a + c * lda, b + c * ldb, n,
-                           chunk, part);
-        hipLaunchKernelGGL(sum_stage2, dim3(1), dim3(256), 0, s, part, (int)nb, out + c);
-    }
-    AFN_HIP(hipGetLastError());
-    return AFN_OK;
-}
-
 int64_t gemv_splits(int64_t m, int64_t ncols)
 {
     if (m <= 0 || ncols <= 0) return 1;
@@ -256,46 +283,180 @@ int64_t gemv_splits(int64_t m, int64_t ncols)
 
 int64_t gemv_partials(int64_t m, int64_t ncols) { return gemv_splits(m, ncols) * m; }
 
-afn_status gemv_n(const double *A, int64_t lda, int64_t m, int64_t ncols, const double *x,
-                  const double *base, double sign, double *y, double *part, hipStream_t s)
+namespace {
+
+template <typename T>
+afn_status dotT(const T *a, int64_t lda, const T *b, int64_t ldb, int64_t n, int nrhs, double *out,
+                double *part, hipStream_t s)
+{
+    const int64_t nb = dot_partials(n);
+    const int64_t chunk = ceil_div(n, nb);
+    for (int c = 0; c < nrhs; ++c) {
+        hipLaunchKernelGGL((dot_stage1<T>), dim3((unsigned)nb), dim3(256), 0, s, a + c * lda, b + c * ldb, n,
+                           chunk, part);
+        hipLaunchKernelGGL(sum_stage2, dim3(1), dim3(256), 0, s, part, (int)nb, out + c);
+    }
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+template <typename T>
+afn_status gemv_nT(const T *A, int64_t lda, int64_t m, int64_t ncols, const T *x, const T *base,
+                   T sign, T *y, T *part, hipStream_t s)
 {
     if (m <= 0) return AFN_OK;
     const int64_t S = gemv_splits(m, ncols);
     const int64_t chunk = ceil_div(ncols, S);
-    hipLaunchKernelGGL(gemv_n_partial, dim3((unsigned)ceil_div(m, 256), (unsigned)S), dim3(256), 0, s,
+    hipLaunchKernelGGL((gemv_n_partial<T>), dim3((unsigned)ceil_div(m, 256), (unsigned)S), dim3(256), 0, s,
                        A, lda, m, ncols, x, chunk, part);
-    hipLaunchKernelGGL(gemv_n_reduce, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, part, m,
+    hipLaunchKernelGGL((gemv_n_reduce<T>), dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, part, m,
                        (int)S, base, sign, y);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }
 
-afn_status gemv_t(const double *A, int64_t lda, int64_t m, int64_t ncols, const double *x,
-                  const double *base, double sign, double *y, hipStream_t s)
+template <typename T>
+afn_status gemv_tT(const T *A, int64_t lda, int64_t m, int64_t ncols, const T *x, const T *base,
+                   T sign, T *y, hipStream_t s)
 {
     if (ncols <= 0) return AFN_OK;
-    hipLaunchKernelGGL(gemv_t_kernel, dim3((unsigned)ceil_div(ncols, 4)), dim3(256), 0, s, A, lda, m,
+    hipLaunchKernelGGL((gemv_t_kernel<T>), dim3((unsigned)ceil_div(ncols, 4)), dim3(256), 0, s, A, lda, m,
                        ncols, x, base, sign, y);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }
 
-afn_status spmv_g(const int32_t *cols, const double *gval, int64_t nr, int w, const double *t,
-                  double *u, hipStream_t s)
+template <typename T>
+afn_status spmv_gT(const int32_t *cols, const T *gval, int64_t nr, int w, const T *t, T *u,
+                   hipStream_t s)
 {
     if (nr <= 0) return AFN_OK;
-    hipLaunchKernelGGL(spmv_padded, dim3((unsigned)ceil_div(nr, 4)), dim3(256), 0, s, cols, gval, nr,
+    hipLaunchKernelGGL((spmv_padded<T>), dim3((unsigned)ceil_div(nr, 4)), dim3(256), 0, s, cols, gval, nr,
                        w, t, u);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }
 
+template <typename T>
+afn_status spmv_gtT(const int64_t *ptr, const int32_t *idx, const T *val, int64_t nr, const T *u,
+                    T *out, hipStream_t s)
+{
+    if (nr <= 0) return AFN_OK;
+    hipLaunchKernelGGL((spmv_csr<T>), dim3((unsigned)ceil_div(nr, 4)), dim3(256), 0, s, ptr, idx, val, nr,
+                       u, out);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+template <typename T>
+afn_status pcg_xrT(T *x, T *r, const T *p, const T *q, const double *sc, int64_t n, double *part,
+                   double *rr_out, hipStream_t s)
+{
+    const int64_t nb = dot_partials(n);
+    const int64_t chunk = ceil_div(n, nb);
+    hipLaunchKernelGGL((pcg_xr<T>), dim3((unsigned)nb), dim3(256), 0, s, x, r, p, q, sc, n, chunk, part);
+    hipLaunchKernelGGL(sum_stage2, dim3(1), dim3(256), 0, s, part, (int)nb, rr_out);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+template <typename T>
+afn_status pcg_pT(T *p, const T *z, const double *sc, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL((pcg_p<T>), dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, p, z, sc, n);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+}  // namespace
+
+afn_status dot(const double *a, int64_t lda, const double *b, int64_t ldb, int64_t n, int nrhs,
+               double *out, double *part, hipStream_t s)
+{
+    return dotT(a, lda, b, ldb, n, nrhs, out, part, s);
+}
+afn_status dot(const float *a, int64_t lda, const float *b, int64_t ldb, int64_t n, int nrhs,
+               double *out, double *part, hipStream_t s)
+{
+    return dotT(a, lda, b, ldb, n, nrhs, out, part, s);
+}
+afn_status gemv_n(const double *A, int64_t lda, int64_t m, int64_t ncols, const double *x,
+                  const double *base, double sign, double *y, double *part, hipStream_t s)
+{
+    return gemv_nT(A, lda, m, ncols, x, base, sign, y, part, s);
+}
+afn_status gemv_n(const float *A, int64_t lda, int64_t m, int64_t ncols, const float *x,
+                  const float *base, float sign, float *y, float *part, hipStream_t s)
+{
+    return gemv_nT(A, lda, m, ncols, x, base, sign, y, part, s);
+}
+afn_status gemv_t(const double *A, int64_t lda, int64_t m, int64_t ncols, const double *x,
+                  const double *base, double sign, double *y, hipStream_t s)
+{
+    return gemv_tT(A, lda, m, ncols, x, base, sign, y, s);
+}
+afn_status gemv_t(const float *A, int64_t lda, int64_t m, int64_t ncols, const float *x,
+                  const float *base, float sign, float *y, hipStream_t s)
+{
+    return gemv_tT(A, lda, m, ncols, x, base, sign, y, s);
+}
+afn_status spmv_g(const int32_t *cols, const double *gval, int64_t nr, int w, const double *t,
+                  double *u, hipStream_t s)
+{
+    return spmv_gT(cols, gval, nr, w, t, u, s);
+}
+afn_status spmv_g(const int32_t *cols, const float *gval, int64_t nr, int w, const float *t, float *u,
+                  hipStream_t s)
+{
+    return spmv_gT(cols, gval, nr, w, t, u, s);
+}
 afn_status spmv_gt(const int64_t *ptr, const int32_t *idx, const double *val, int64_t nr,
                    const double *u, double *out, hipStream_t s)
 {
-    if (nr <= 0) return AFN_OK;
-    hipLaunchKernelGGL(spmv_csr, dim3((unsigned)ceil_div(nr, 4)), dim3(256), 0, s, ptr, idx, val, nr,
-                       u, out);
+    return spmv_gtT(ptr, idx, val, nr, u, out, s);
+}
+afn_status spmv_gt(const int64_t *ptr, const int32_t *idx, const float *val, int64_t nr,
+                   const float *u, float *out, hipStream_t s)
+{
+    return spmv_gtT(ptr, idx, val, nr, u, out, s);
+}
+afn_status pcg_xr_launch(double *x, double *r, const double *p, const double *q, const double *sc,
+                         int64_t n, double *part, double *rr_out, hipStream_t s)
+{
+    return pcg_xrT(x, r, p, q, sc, n, part, rr_out, s);
+}
+afn_status pcg_xr_launch(float *x, float *r, const float *p, const float *q, const double *sc,
+                         int64_t n, double *part, double *rr_out, hipStream_t s)
+{
+    return pcg_xrT(x, r, p, q, sc, n, part, rr_out, s);
+}
+afn_status pcg_p_launch(double *p, const double *z, const double *sc, int64_t n, hipStream_t s)
+{
+    return pcg_pT(p, z, sc, n, s);
+}
+afn_status pcg_p_launch(float *p, const float *z, const double *sc, int64_t n, hipStream_t s)
+{
+    return pcg_pT(p, z, sc, n, s);
+}
+
+afn_status to_f32_scaled_launch(const double *r, double scale, float *r32, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(to_f32_scaled, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, r, scale, r32, n);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status axpy_f32_into_f64_launch(double a, const float *e, double *x, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(axpy_f32_into_f64, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, a, e, x, n);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status to_f32_launch(const double *a, float *b, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return AFN_OK;
+    hipLaunchKernelGGL(to_f32, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, a, b, n);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }
@@ -337,24 +498,6 @@ afn_status pcg_alpha_launch(double *sc, hipStream_t s)
 afn_status pcg_beta_launch(double *sc, hipStream_t s)
 {
     hipLaunchKernelGGL(pcg_beta, dim3(1), dim3(1), 0, s, sc);
-    AFN_HIP(hipGetLastError());
-    return AFN_OK;
-}
-
-afn_status pcg_xr_launch(double *x, double *r, const double *p, const double *q, const double *sc,
-                         int64_t n, double *part, double *rr_out, hipStream_t s)
-{
-    const int64_t nb = dot_partials(n);
-    const int64_t chunk = ceil_div(n, nb);
-    hipLaunchKernelGGL(pcg_xr, dim3((unsigned)nb), dim3(256), 0, s, x, r, p, q, sc, n, chunk, part);
-    hipLaunchKernelGGL(sum_stage2, dim3(1), dim3(256), 0, s, part, (int)nb, rr_out);
-    AFN_HIP(hipGetLastError());
-    return AFN_OK;
-}
-
-afn_status pcg_p_launch(double *p, const double *z, const double *sc, int64_t n, hipStream_t s)
-{
-    hipLaunchKernelGGL(pcg_p, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, p, z, sc, n);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }

@@ -378,3 +378,57 @@ def test_solve_status_codes(afn):
     assert e.value.status == afn.AFN_EBREAKDOWN
     x, info = afn.afn_pcg_solve(h, dev(np.zeros(n)), tol=1e-8)
     assert info["iterations"] == 0 and not x.any()
+
+
+# ------------------------------------------------------------------ mixed precision (FP32 inner, FP64 refinement)
+
+def test_mixed_c1_matches_fp64_oracle(afn, c1):
+    p, X, b, h, A = c1
+    hm = afn.afn_setup(dev(X), p.l, p.mu, k=p.k, w=p.w, precision=afn.AFN_FP32)
+    x, info = afn.afn_pcg_solve(hm, dev(b), tol=1e-12, maxit=p.maxit)
+    say("C1 mixed", info)
+    assert info["converged"] and info["outer_iterations"] >= 2
+    xg = x.cpu().numpy()
+    r = b - oracle.kernel_matvec(X, p.l, p.mu, xg)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 2e-12
+    xo, *_ = oracle.pcg(A, b, 1e-12, p.maxit)
+    rel = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    say("C1 mixed vs FP64 oracle:", rel)
+    assert rel <= 1e-6
+    # the same factors drive the FP64 path
+    np.testing.assert_array_equal(hm.landmarks(), h.landmarks())
+
+
+def test_mixed_c2_shape_reaches_tolerance(afn):
+    p = W.c2(0.1)
+    X, b = W.make(p)
+    Xt, bt = dev(X), dev(b)
+    hm = afn.afn_setup(Xt, p.l, p.mu, k=p.k, w=p.w, precision=afn.AFN_FP32)
+    x, info = afn.afn_pcg_solve(hm, bt, tol=1e-6, maxit=500)
+    say("C2 mixed", info)
+    assert info["converged"] and info["relres_true"] <= 1e-6
+    r = bt - afn.kernel_matvec(Xt, p.l, p.mu, x)          # FP64 matvec (parity-tested above)
+    assert (torch.linalg.norm(r) / torch.linalg.norm(bt)).item() <= 1.01e-6
+
+
+def test_mixed_reports_failure_instead_of_wrong_answer(afn):
+    # mu far below the FP32 operator's rounding: the rounded operator is not
+    # positive definite and refinement cannot converge; the solve must end
+    # with a failure status (breakdown, stagnation or no convergence), never
+    # with a converged flag on a wrong answer
+    n = 2000
+    X = W.points("uniform", n, 3, 51)
+    b = np.random.default_rng(52).standard_normal(n)
+    h = afn.afn_setup(dev(X), 0.5, 1e-12, k=50, w=16, precision=afn.AFN_FP32)
+    try:
+        x, info = afn.afn_pcg_solve(h, dev(b), tol=1e-10, maxit=100)
+    except afn.AFNError as e:
+        say("mixed ill-conditioned:", e)
+        assert e.status in (afn.AFN_EBREAKDOWN, afn.AFN_ESTAGNATION, afn.AFN_ENOCONV)
+        return
+    say("mixed ill-conditioned", info)
+    if info["converged"]:
+        r = b - oracle.kernel_matvec(X, 0.5, 1e-12, x.cpu().numpy())
+        assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(b)
+    else:
+        assert info["status"] in (afn.AFN_ESTAGNATION, afn.AFN_ENOCONV)
