@@ -176,6 +176,59 @@ afn_status sub_launch(const double *b, const double *y, double *r, int64_t n, hi
 // *flag |= 1 if a value is not finite
 afn_status finite_launch(const double *a, int64_t n, int *flag, hipStream_t s);
 
+// ---------------------------------------------------------------- many right-hand sides
+// Row-major (point-major) n x R blocks, R <= 64.
+int mrhs_splits(int64_t npad);
+int64_t mrhs_part_elems(int64_t npad);
+template <typename T>
+afn_status kmv_mrhs_run(const T *Xs, int64_t npad, int64_t n, int d, double mu, const T *P,
+                        int64_t ldp, T *Y, int64_t ldy, int R, T *part, hipStream_t s,
+                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+int gemm_splits(int64_t m, int64_t K);
+int64_t gemm_part_elems(int64_t m, int64_t K);
+template <typename T>
+afn_status gemm_rows(const T *A, int64_t ars, int64_t acs, int64_t m, int64_t K, const T *B,
+                     int64_t ldb, int R, const T *base, T sign, T *C, int64_t ldc, T *part,
+                     hipStream_t s);
+template <typename T>
+afn_status spmm_g(const int32_t *cols, const T *g, int64_t nr, int w, const T *X, int R, T *U,
+                  hipStream_t s);
+template <typename T>
+afn_status spmm_gt(const int64_t *ptr, const int32_t *idx, const T *val, int64_t nr, const T *X,
+                   int R, T *U, hipStream_t s);
+int64_t coldot_blocks(int64_t n);
+template <typename T>
+afn_status coldot(const T *A, const T *B, int64_t n, int R, double *out, double *part,
+                  hipStream_t s);
+template <typename T>
+afn_status col_xr_launch(T *X, T *Rv, const T *Pv, const T *Q, const double *alpha, int64_t n,
+                         int R, double *rr, double *part, hipStream_t s);
+template <typename T>
+afn_status col_p_launch(T *Pv, const T *Z, const double *beta, int64_t n, int R, hipStream_t s);
+afn_status col_alpha_launch(const double *rho, const double *pq, const int *active, double *alpha,
+                            int R, int *bad, hipStream_t s);
+afn_status col_beta_launch(double *rho, const double *rho_new, const int *active, double *beta,
+                           int R, hipStream_t s);
+afn_status col_converged_launch(const double *rr, const double *bnorm2, const double *tol,
+                                int *active, int *count, int R, int *bad, hipStream_t s);
+template <typename T>
+afn_status gather_rows(const double *X, int64_t ld, const int32_t *perm, int64_t n, int R,
+                       const double *scale, T *Y, hipStream_t s);
+afn_status scatter_rows(const double *Y, const int32_t *perm, int64_t n, int R, double *X,
+                        int64_t ld, hipStream_t s);
+afn_status scatter_rows_f32(const float *Y, int64_t n, int R, double *X, int64_t ld,
+                            hipStream_t s);
+afn_status sub_rows_launch(const double *B, const double *Y, double *Rr, int64_t total,
+                           hipStream_t s);
+// Block solve (R <= 64, d <= 8, FP32 copies present); see block.hip.
+afn_status block_refine_solve(afn_handle *h, const double *B, int64_t ld, double *Xout, int R,
+                              double tol, int maxit, hipStream_t s, int *iters, int *outer,
+                              double *relres_max, int *conv_all);
+afn_status scale_to_f32_launch(const double *r, const double *inv, float *r32, int64_t n, int R,
+                               hipStream_t s);
+afn_status axpy_cols_f32_launch(const double *a, const float *e32, double *x, int64_t n, int R,
+                                hipStream_t s);
+
 }  // namespace afn
 
 // ------------------------------------------------------------------ handle
@@ -209,6 +262,8 @@ struct afn_handle {
     float *gval32 = nullptr;
     float *tval32 = nullptr;
     float *work32 = nullptr;
+    void *mrhs_ws = nullptr;    // workspace of block solves (allocated on first use)
+    size_t mrhs_bytes = 0;
     double *host_sc = nullptr;  // pinned host copy of PCG scalars
     hipEvent_t kmv_ev[2] = {nullptr, nullptr};  // timing of the matvec tile kernel
     afn_setup_info info{};

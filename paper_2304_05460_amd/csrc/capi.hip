@@ -620,6 +620,24 @@ afn_status afn_pcg_solve(afn_handle *h, const double *b_dev, double *x_dev, int3
     int it_max = 0, conv_all = 1, n_kmv = 0;
     double ms_kmv = 0.0;
     double rel_max = 0.0, true_max = 0.0;
+    if (nrhs >= 2 && h->precision == AFN_FP32 && h->d <= 8) {
+        for (int c0 = 0; c0 < nrhs; c0 += 64) {
+            const int Rc = nrhs - c0 < 64 ? nrhs - c0 : 64;
+            int it = 0, outer = 0, conv = 0;
+            double rel = 0.0;
+            afn_status st = block_refine_solve(h, b_dev + c0 * ld, ld, x_dev + c0 * ld, Rc, tol, maxit,
+                                               s, &it, &outer, &rel, &conv);
+            if (st != AFN_OK && st != AFN_ENOCONV && st != AFN_EBREAKDOWN && st != AFN_ESTAGNATION)
+                return st;
+            if (st != AFN_OK && (worst == AFN_OK || st == AFN_EBREAKDOWN)) worst = st;
+            it_max = it > it_max ? it : it_max;
+            outer_max = outer > outer_max ? outer : outer_max;
+            conv_all &= conv;
+            rel_max = rel > rel_max || rel != rel ? rel : rel_max;
+        }
+        true_max = rel_max;
+        nrhs = 0;   // done
+    }
     for (int c = 0; c < nrhs; ++c) {
         int it = 0, conv = 0, outer = 0;
         double rel = 0, rt = 0;
@@ -728,6 +746,7 @@ void afn_destroy(afn_handle *h)
     if (h->host_sc) (void)hipHostFree(h->host_sc);
     for (auto &e : h->kmv_ev)
         if (e) (void)hipEventDestroy(e);
+    if (h->mrhs_ws) (void)hipFree(h->mrhs_ws);
     h->arena.release();
     delete h;
 }

@@ -367,7 +367,9 @@ SymShape sym_shape(int64_t n)
     int64_t tiles = ceil_div(n, kTile);
     int64_t st = tiles / 45;
     sh.ST = (int)(st < 1 ? 1 : (st > kMaxST ? kMaxST : st));
+    sh.ST = sh.ST > 1 ? sh.ST & ~1 : 1;       // even: packed length a multiple of 128
     sh.S = (int)ceil_div(tiles, sh.ST);
+    if (sh.ST == 1 && (sh.S & 1)) ++sh.S;
     sh.npad = (int64_t)sh.S * sh.ST * kTile;
     sh.nwg = (int64_t)sh.S * (sh.S + 1) / 2;
     return sh;

@@ -1,0 +1,722 @@
+// Many right-hand sides at once.
+//
+// Kernel matvec Y = (K + mu I) P for R <= 64 columns: per 64 x 64 tile the
+// kernel values E are formed on the VALU (same scaled-coordinate exp2 as the
+// single-vector kernels) and stored transposed in LDS; the product E P_J is
+// a GEMM with K = 64 and runs on the matrix cores (MFMA 16x16x4, FP32 or
+// FP64).  A workgroup owns 64 rows and a range of column tiles; split
+// partials are added in order by a second pass (deterministic).
+//
+// The batched apply (Algorithm 3 for R columns) uses an MFMA GEMM with split
+// K for the L^{-1} and V products and SpMMs for G and G^T.  Vectors of R
+// columns are point-major (row-major n x R, columns contiguous) inside the
+// solver so that the SpMM gathers and the kernel tile loads are coalesced.
+//
+// MFMA 16x16x4 operand layout on gfx950 (wave64, checked on the device): lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator element i of
+// lane l is C[4 (l / 16) + i][l % 16] for FP32 and C[l / 16 + 4 i][l % 16]
+// for FP64.
+#include <cmath>
+
+#include "afn_internal.h"
+
+namespace afn {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+    using acc_t = floatx4;
+    static __device__ __forceinline__ acc_t op(float a, float b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+template <>
+struct Mfma<double> {
+    using acc_t = doublex4;
+    static __device__ __forceinline__ acc_t op(double a, double b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int i) { return (lane >> 4) + 4 * i; }
+};
+
+constexpr int TL = 64;      // tile edge (points / rows / k-chunk)
+constexpr int LS = 80;      // LDS row stride: (lane/16) * LS = 16 (mod 64) -> conflict-free MFMA reads
+
+__device__ __forceinline__ double kexp2(double t)
+{
+    t = t < 2000.0 ? t : 2000.0;
+    const double kd = __builtin_rint(t);
+    const double f = kd - t;
+    double p = 4.45594401136235e-10;
+    p = __builtin_fma(p, f, 7.074200215313511e-09);
+    p = __builtin_fma(p, f, 1.0178056459844976e-07);
+    p = __builtin_fma(p, f, 1.3215432494521488e-06);
+    p = __builtin_fma(p, f, 1.5252733842373628e-05);
+    p = __builtin_fma(p, f, 0.00015403530463828206);
+    p = __builtin_fma(p, f, 0.0013333558146406623);
+    p = __builtin_fma(p, f, 0.009618129107587145);
+    p = __builtin_fma(p, f, 0.05550410866482162);
+    p = __builtin_fma(p, f, 0.2402265069591016);
+    p = __builtin_fma(p, f, 0.6931471805599453);
+    p = __builtin_fma(p, f, 1.0);
+    return __builtin_ldexp(p, (int)(-kd));
+}
+__device__ __forceinline__ float kexp2(float t) { return __builtin_amdgcn_exp2f(-t); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// part[s][i * RP + c] = sum over the column tiles of split s of K_ij P_jc.
+// Xs: packed scaled coordinates (npad a multiple of 128, zero padded).
+// P: row-major n x R (leading dimension ldp).  RP = 16 * NB >= R.
+// 128 rows per workgroup (8 waves).  Kernel values: lane = row within a
+// 64-row half, wave pair = 16-column group, so the transposed stores into
+// LDS are consecutive and the column coordinates are broadcast reads.
+constexpr int BM = 128;
+constexpr int LSE = 144;    // (lane/16) * 144 = 16 (mod 64): conflict-free MFMA A reads
+
+template <int D, typename T, int NB>
+__global__ __launch_bounds__(512) void kmv_mrhs(const T *__restrict__ Xs, int64_t npad, int64_t n,
+                                                const T *__restrict__ P, int64_t ldp, int R,
+                                                int tiles_per_split, T *__restrict__ part)
+{
+    using M = Mfma<T>;
+    constexpr int RP = 16 * NB;
+    __shared__ T cx[D][TL];
+    __shared__ T EsT[TL][LSE];      // EsT[j][i] = K(row i, column j)
+    __shared__ T PJ[TL][LS];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int half = wave & 1, cgrp = wave >> 1;     // rows half*64 + lane, columns cgrp*16 ..
+    const int64_t i0 = (int64_t)blockIdx.x * BM;
+    const int64_t ntiles = npad / TL;
+    const int64_t J0 = (int64_t)blockIdx.y * tiles_per_split;
+    const int64_t J1 = J0 + tiles_per_split < ntiles ? J0 + tiles_per_split : ntiles;
+    T xi[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t) xi[t] = Xs[(int64_t)t * npad + i0 + half * 64 + lane];
+    typename M::acc_t acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = typename M::acc_t{};
+    for (int64_t J = J0; J < J1; ++J) {
+        const int64_t j0 = J * TL;
+        __syncthreads();
+        for (int e = tid; e < D * TL; e += 512) {
+            const int t = e / TL, j = e % TL;
+            cx[t][j] = Xs[(int64_t)t * npad + j0 + j];
+        }
+        for (int e = tid; e < TL * RP; e += 512) {
+            const int k = e / RP, c = e % RP;
+            PJ[k][c] = (j0 + k < n && c < R) ? P[(j0 + k) * ldp + c] : T(0);
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int c = 0; c < 16; ++c) {
+            const int j = cgrp * 16 + c;
+            T d2 = T(0);
+#pragma unroll
+            for (int t = 0; t < D; ++t) {
+                const T del = xi[t] - cx[t][j];
+                d2 = fmaT(del, del, d2);
+            }
+            EsT[j][half * 64 + lane] = kexp2(d2);
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < TL / 4; ++kk) {
+            const int k = 4 * kk + (lane >> 4);
+            const T a = EsT[k][16 * wave + (lane & 15)];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) acc[b] = M::op(a, PJ[k][16 * b + (lane & 15)], acc[b]);
+        }
+    }
+    T *out = part + (int64_t)blockIdx.y * npad * RP;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t row = i0 + 16 * wave + M::row(lane, q);
+            out[row * RP + 16 * b + (lane & 15)] = acc[b][q];
+        }
+}
+
+// Y[i * ldy + c] = sum_s part[s][i * RP + c] + mu P[i * ldp + c]
+template <typename T>
+__global__ __launch_bounds__(256) void mrhs_reduce(const T *__restrict__ part, int64_t npad, int RP,
+                                                   int splits, int64_t n, int R, double mu,
+                                                   const T *__restrict__ P, int64_t ldp,
+                                                   T *__restrict__ Y, int64_t ldy)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * R) return;
+    const int64_t i = e / R;
+    const int c = (int)(e - i * R);
+    double s = 0.0;
+    for (int q = 0; q < splits; ++q) s += (double)part[(int64_t)q * npad * RP + i * RP + c];
+    Y[i * ldy + c] = (T)(s + mu * (double)P[i * ldp + c]);
+}
+
+// part[s][i * RP + c] = sum_{t in split s} A(i, t) B(t, c), A(i,t) = A[i*ars + t*acs],
+// B row-major (ldb).  64 rows per workgroup, K in chunks of 64.
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void gemm_splitk(const T *__restrict__ A, int64_t ars, int64_t acs,
+                                                   int64_t m, int64_t K, const T *__restrict__ B,
+                                                   int64_t ldb, int R, int64_t k_per_split,
+                                                   T *__restrict__ part, int64_t mpad)
+{
+    using M = Mfma<T>;
+    constexpr int RP = 16 * NB;
+    __shared__ T AsT[TL][LS];   // AsT[k][i]
+    __shared__ T Bs[TL][LS];    // Bs[k][c]
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int64_t i0 = (int64_t)blockIdx.x * TL;
+    const int64_t t0 = (int64_t)blockIdx.y * k_per_split;
+    const int64_t t1 = t0 + k_per_split < K ? t0 + k_per_split : K;
+    typename M::acc_t acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = typename M::acc_t{};
+    const bool k_fast = acs == 1;
+    for (int64_t tc = t0; tc < t1; tc += TL) {
+        __syncthreads();
+        for (int e = tid; e < TL * TL; e += 256) {
+            int i, k;
+            if (k_fast) { i = e / TL; k = e % TL; } else { k = e / TL; i = e % TL; }
+            const int64_t gi = i0 + i, gt = tc + k;
+            AsT[k][i] = (gi < m && gt < t1) ? A[gi * ars + gt * acs] : T(0);
+        }
+        for (int e = tid; e < TL * RP; e += 256) {
+            const int k = e / RP, c = e % RP;
+            const int64_t gt = tc + k;
+            Bs[k][c] = (gt < t1 && c < R) ? B[gt * ldb + c] : T(0);
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < TL / 4; ++kk) {
+            const int k = 4 * kk + (lane >> 4);
+            const T a = AsT[k][16 * wave + (lane & 15)];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) acc[b] = M::op(a, Bs[k][16 * b + (lane & 15)], acc[b]);
+        }
+    }
+    T *out = part + (int64_t)blockIdx.y * mpad * RP;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t row = i0 + 16 * wave + M::row(lane, q);
+            out[row * RP + 16 * b + (lane & 15)] = acc[b][q];
+        }
+}
+
+// C[i * ldc + c] = base[i * ldc + c] + sign * sum_s part[s][i * RP + c]
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_reduce(const T *__restrict__ part, int64_t mpad, int RP,
+                                                   int splits, int64_t m, int R,
+                                                   const T *__restrict__ base, T sign,
+                                                   T *__restrict__ C, int64_t ldc)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m * R) return;
+    const int64_t i = e / R;
+    const int c = (int)(e - i * R);
+    T s = T(0);
+    for (int q = 0; q < splits; ++q) s += part[(int64_t)q * mpad * RP + i * RP + c];
+    C[i * ldc + c] = (base ? base[i * ldc + c] : T(0)) + sign * s;
+}
+
+// U[p*ld + c] = sum_a g[p*w + a] T[cols[p*w + a]*ld + c]  (wave per row, lane = column)
+template <typename T>
+__global__ __launch_bounds__(256) void spmm_padded(const int32_t *__restrict__ cols,
+                                                   const T *__restrict__ g, int64_t nr, int w,
+                                                   const T *__restrict__ X, int64_t ld, int R,
+                                                   T *__restrict__ U)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (p >= nr || lane >= R) return;
+    const int m = (int)(p + 1 < w ? p + 1 : w);
+    T s = T(0);
+    for (int a = 0; a < m; ++a) s = fmaT(g[p * w + a], X[(int64_t)cols[p * w + a] * ld + lane], s);
+    U[p * ld + lane] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void spmm_csr(const int64_t *__restrict__ ptr,
+                                                const int32_t *__restrict__ idx,
+                                                const T *__restrict__ val, int64_t nrows,
+                                                const T *__restrict__ X, int64_t ld, int R,
+                                                T *__restrict__ U)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (q >= nrows || lane >= R) return;
+    T s = T(0);
+    for (int64_t e = ptr[q]; e < ptr[q + 1]; ++e) s = fmaT(val[e], X[(int64_t)idx[e] * ld + lane], s);
+    U[q * ld + lane] = s;
+}
+
+// Per-column dot products of row-major n x R blocks: stage 1 (4 row groups x
+// 64 columns per workgroup), stage 2 sums the block partials in order.
+template <typename T>
+__global__ __launch_bounds__(256) void coldot_stage1(const T *__restrict__ A, const T *__restrict__ B,
+                                                     int64_t n, int R, int64_t chunk,
+                                                     double *__restrict__ part)
+{
+    __shared__ double red[4][64];
+    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int64_t i0 = (int64_t)blockIdx.x * chunk;
+    const int64_t i1 = i0 + chunk < n ? i0 + chunk : n;
+    double s = 0.0;
+    if (c < R)
+        for (int64_t i = i0 + g; i < i1; i += 4) s = __builtin_fma((double)A[i * R + c], (double)B[i * R + c], s);
+    red[g][c] = s;
+    __syncthreads();
+    if (g == 0 && c < R) part[(int64_t)blockIdx.x * R + c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
+}
+
+__global__ __launch_bounds__(64) void coldot_stage2(const double *__restrict__ part, int nb, int R,
+                                                    double *__restrict__ out)
+{
+    const int c = threadIdx.x;
+    if (c >= R) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * R + c];
+    out[c] = s;
+}
+
+// Per-column scalars (arrays of R): alpha = rho / pq for active columns.
+__global__ __launch_bounds__(64) void col_alpha(const double *rho, const double *pq, int *active,
+                                                double *alpha, int R, int *bad)
+{
+    const int c = threadIdx.x;
+    if (c >= R) return;
+    double a = 0.0;
+    if (active[c]) {
+        if (pq[c] > 0.0) {
+            a = rho[c] / pq[c];
+        } else {
+            atomicOr(bad, 2);     // p'Ap <= 0 or NaN: breakdown of this column
+            active[c] = 0;
+        }
+    }
+    alpha[c] = a;
+}
+
+__global__ __launch_bounds__(64) void col_beta(double *rho, const double *rho_new, const int *active,
+                                               double *beta, int R)
+{
+    const int c = threadIdx.x;
+    if (c >= R) return;
+    beta[c] = active[c] ? rho_new[c] / rho[c] : 0.0;
+    rho[c] = rho_new[c];
+}
+
+// x += alpha_c p; r -= alpha_c q; partial r.r per column
+template <typename T>
+__global__ __launch_bounds__(256) void col_xr(T *__restrict__ X, T *__restrict__ Rv,
+                                              const T *__restrict__ Pv, const T *__restrict__ Q,
+                                              const double *__restrict__ alpha, int64_t n, int R,
+                                              int64_t chunk, double *__restrict__ part)
+{
+    __shared__ double red[4][64];
+    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int64_t i0 = (int64_t)blockIdx.x * chunk;
+    const int64_t i1 = i0 + chunk < n ? i0 + chunk : n;
+    double s = 0.0;
+    if (c < R) {
+        const T a = (T)alpha[c];
+        for (int64_t i = i0 + g; i < i1; i += 4) {
+            const int64_t e = i * R + c;
+            X[e] = fmaT(a, Pv[e], X[e]);
+            const T r = fmaT(-a, Q[e], Rv[e]);
+            Rv[e] = r;
+            s = __builtin_fma((double)r, (double)r, s);
+        }
+    }
+    red[g][c] = s;
+    __syncthreads();
+    if (g == 0 && c < R) part[(int64_t)blockIdx.x * R + c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void col_p(T *__restrict__ Pv, const T *__restrict__ Z,
+                                             const double *__restrict__ beta, int64_t n, int R)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * R) return;
+    const int c = (int)(e % R);
+    Pv[e] = fmaT((T)beta[c], Pv[e], Z[e]);
+}
+
+// active_c &= (sqrt(rr_c / bnorm2_c) > tol_c); count of active columns.
+__global__ __launch_bounds__(64) void col_converged(const double *rr, const double *bnorm2,
+                                                    const double *tol, int *active, int *count, int R,
+                                                    int *bad)
+{
+    const int c = threadIdx.x;
+    int a = 0;
+    if (c < R && active[c]) {
+        const double rel = sqrt(rr[c] / bnorm2[c]);
+        if (!(rel == rel)) atomicOr(bad, 1);
+        a = rel > tol[c] && rel == rel;
+        active[c] = a;
+    }
+    const uint64_t m = __ballot(a);
+    if (c == 0) *count = __popcll(m);
+}
+
+// Gather columns from a column-major block into a row-major one, with the
+// point permutation: Y[i * R + c] = (T) (X[perm[i] + c * ld] * scale_c).
+template <typename T>
+__global__ __launch_bounds__(256) void gather_rowmajor(const double *__restrict__ X, int64_t ld,
+                                                       const int32_t *__restrict__ perm, int64_t n,
+                                                       int R, const double *__restrict__ scale,
+                                                       T *__restrict__ Y)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * R) return;
+    const int64_t i = e / R;
+    const int c = (int)(e - i * R);
+    const double v = X[(perm ? perm[i] : i) + c * ld];
+    Y[e] = (T)(scale ? v * scale[c] : v);
+}
+
+__global__ __launch_bounds__(256) void scatter_rowmajor(const double *__restrict__ Y,
+                                                        const int32_t *__restrict__ perm, int64_t n,
+                                                        int R, double *__restrict__ X, int64_t ld)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * R) return;
+    const int64_t i = e / R;
+    const int c = (int)(e - i * R);
+    X[(perm ? perm[i] : i) + c * ld] = Y[e];
+}
+
+// X[i + c * ld] = Y[i * R + c] for FP32 Y (identity order)
+__global__ __launch_bounds__(256) void scatter_rowmajor_f32(const float *__restrict__ Y, int64_t n, int R,
+                                                            double *__restrict__ X, int64_t ld)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * R) return;
+    const int64_t i = e / R;
+    const int c = (int)(e - i * R);
+    X[i + c * ld] = (double)Y[e];
+}
+
+// R64 = B64 - A64 (row-major n x R)
+__global__ __launch_bounds__(256) void sub_rows(const double *__restrict__ B, const double *__restrict__ Y,
+                                                double *__restrict__ Rr, int64_t total)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    Rr[e] = B[e] - Y[e];
+}
+
+// r32[i*R + c] = r64[i*R + c] * inv_c ; x64 += norm_c * e32
+__global__ __launch_bounds__(256) void scale_to_f32(const double *__restrict__ r, const double *__restrict__ inv,
+                                                    float *__restrict__ r32, int64_t n, int R)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * R) return;
+    r32[e] = (float)(r[e] * inv[e % R]);
+}
+
+__global__ __launch_bounds__(256) void axpy_cols_f32(const double *__restrict__ a, const float *__restrict__ e32,
+                                                     double *__restrict__ x, int64_t n, int R)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * R) return;
+    x[e] = __builtin_fma(a[e % R], (double)e32[e], x[e]);
+}
+
+template <int D, typename T, int NB>
+void launch_mrhs(dim3 g, const T *Xs, int64_t npad, int64_t n, const T *P, int64_t ldp, int R, int tps,
+                 T *part, hipStream_t s)
+{
+    hipLaunchKernelGGL((kmv_mrhs<D, T, NB>), g, dim3(512), 0, s, Xs, npad, n, P, ldp, R, tps, part);
+}
+
+template <typename T, int NB>
+void launch_mrhs_d(int d, dim3 g, const T *Xs, int64_t npad, int64_t n, const T *P, int64_t ldp, int R,
+                   int tps, T *part, hipStream_t s)
+{
+    switch (d) {
+        case 1: launch_mrhs<1, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, s); break;
+        case 2: launch_mrhs<2, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, s); break;
+        case 3: launch_mrhs<3, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, s); break;
+        case 4: launch_mrhs<4, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, s); break;
+        case 5: launch_mrhs<5, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, s); break;
+        case 6: launch_mrhs<6, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, s); break;
+        case 7: launch_mrhs<7, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, s); break;
+        default: launch_mrhs<8, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, s); break;
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host side
+
+int mrhs_splits(int64_t npad)
+{
+    const int64_t rt = npad / BM;
+    int64_t s = ceil_div(1024, rt);
+    if (s > rt) s = rt;
+    if (s > 64) s = 64;
+    return (int)(s < 1 ? 1 : s);
+}
+
+int64_t mrhs_part_elems(int64_t npad) { return (int64_t)mrhs_splits(npad) * npad * 64; }
+
+template <typename T>
+afn_status kmv_mrhs_run(const T *Xs, int64_t npad, int64_t n, int d, double mu, const T *P,
+                        int64_t ldp, T *Y, int64_t ldy, int R, T *part, hipStream_t s,
+                        hipEvent_t e0, hipEvent_t e1)
+{
+    if (R < 1 || R > 64 || d < 1 || d > 8) {
+        set_error("kmv_mrhs: R=%d d=%d outside [1, 64] x [1, 8]", R, d);
+        return AFN_EINVAL;
+    }
+    if (npad % BM != 0) {
+        set_error("kmv_mrhs: padded size %lld is not a multiple of %d", (long long)npad, BM);
+        return AFN_EINVAL;
+    }
+    const int NBk = (R + 15) / 16;
+    const int S = mrhs_splits(npad);
+    const int64_t ntiles = npad / TL;
+    const int tps = (int)ceil_div(ntiles, S);
+    dim3 g((unsigned)(npad / BM), (unsigned)S);
+    if (e0) AFN_HIP(hipEventRecord(e0, s));
+    switch (NBk) {
+        case 1: launch_mrhs_d<T, 1>(d, g, Xs, npad, n, P, ldp, R, tps, part, s); break;
+        case 2: launch_mrhs_d<T, 2>(d, g, Xs, npad, n, P, ldp, R, tps, part, s); break;
+        case 3: launch_mrhs_d<T, 3>(d, g, Xs, npad, n, P, ldp, R, tps, part, s); break;
+        default: launch_mrhs_d<T, 4>(d, g, Xs, npad, n, P, ldp, R, tps, part, s); break;
+    }
+    AFN_HIP(hipGetLastError());
+    if (e1) AFN_HIP(hipEventRecord(e1, s));
+    hipLaunchKernelGGL((mrhs_reduce<T>), dim3((unsigned)ceil_div(n * R, 256)), dim3(256), 0, s, part, npad,
+                       16 * NBk, S, n, R, mu, P, ldp, Y, ldy);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+template afn_status kmv_mrhs_run<float>(const float *, int64_t, int64_t, int, double, const float *,
+                                        int64_t, float *, int64_t, int, float *, hipStream_t,
+                                        hipEvent_t, hipEvent_t);
+template afn_status kmv_mrhs_run<double>(const double *, int64_t, int64_t, int, double, const double *,
+                                         int64_t, double *, int64_t, int, double *, hipStream_t,
+                                         hipEvent_t, hipEvent_t);
+
+int gemm_splits(int64_t m, int64_t K)
+{
+    const int64_t rt = ceil_div(m, TL);
+    int64_t s = ceil_div(1024, rt);
+    const int64_t smax = ceil_div(K, TL);
+    if (s > smax) s = smax;
+    if (s > 256) s = 256;
+    return (int)(s < 1 ? 1 : s);
+}
+
+int64_t gemm_part_elems(int64_t m, int64_t K)
+{
+    return (int64_t)gemm_splits(m, K) * round_up(m, TL) * 64;
+}
+
+// C = base + sign * A B  (A(i,t) = A[i*ars + t*acs], m x K; B row-major K x R)
+template <typename T>
+afn_status gemm_rows(const T *A, int64_t ars, int64_t acs, int64_t m, int64_t K, const T *B,
+                     int64_t ldb, int R, const T *base, T sign, T *C, int64_t ldc, T *part,
+                     hipStream_t s)
+{
+    if (m <= 0 || R <= 0) return AFN_OK;
+    const int NBk = (R + 15) / 16;
+    const int S = gemm_splits(m, K);
+    const int64_t kps = round_up(ceil_div(K, S), TL);
+    const int64_t mpad = round_up(m, TL);
+    dim3 g((unsigned)ceil_div(m, TL), (unsigned)S);
+    switch (NBk) {
+        case 1: hipLaunchKernelGGL((gemm_splitk<T, 1>), g, dim3(256), 0, s, A, ars, acs, m, K, B, ldb, R, kps, part, mpad); break;
+        case 2: hipLaunchKernelGGL((gemm_splitk<T, 2>), g, dim3(256), 0, s, A, ars, acs, m, K, B, ldb, R, kps, part, mpad); break;
+        case 3: hipLaunchKernelGGL((gemm_splitk<T, 3>), g, dim3(256), 0, s, A, ars, acs, m, K, B, ldb, R, kps, part, mpad); break;
+        default: hipLaunchKernelGGL((gemm_splitk<T, 4>), g, dim3(256), 0, s, A, ars, acs, m, K, B, ldb, R, kps, part, mpad); break;
+    }
+    AFN_HIP(hipGetLastError());
+    hipLaunchKernelGGL((gemm_reduce<T>), dim3((unsigned)ceil_div(m * R, 256)), dim3(256), 0, s, part, mpad,
+                       16 * NBk, S, m, R, base, sign, C, ldc);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+template afn_status gemm_rows<float>(const float *, int64_t, int64_t, int64_t, int64_t, const float *,
+                                     int64_t, int, const float *, float, float *, int64_t, float *,
+                                     hipStream_t);
+template afn_status gemm_rows<double>(const double *, int64_t, int64_t, int64_t, int64_t,
+                                      const double *, int64_t, int, const double *, double, double *,
+                                      int64_t, double *, hipStream_t);
+
+template <typename T>
+afn_status spmm_g(const int32_t *cols, const T *g, int64_t nr, int w, const T *X, int R, T *U,
+                  hipStream_t s)
+{
+    if (nr <= 0) return AFN_OK;
+    hipLaunchKernelGGL((spmm_padded<T>), dim3((unsigned)ceil_div(nr, 4)), dim3(256), 0, s, cols, g, nr, w, X,
+                       (int64_t)R, R, U);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+template <typename T>
+afn_status spmm_gt(const int64_t *ptr, const int32_t *idx, const T *val, int64_t nr, const T *X, int R,
+                   T *U, hipStream_t s)
+{
+    if (nr <= 0) return AFN_OK;
+    hipLaunchKernelGGL((spmm_csr<T>), dim3((unsigned)ceil_div(nr, 4)), dim3(256), 0, s, ptr, idx, val, nr, X,
+                       (int64_t)R, R, U);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+template afn_status spmm_g<float>(const int32_t *, const float *, int64_t, int, const float *, int,
+                                  float *, hipStream_t);
+template afn_status spmm_g<double>(const int32_t *, const double *, int64_t, int, const double *, int,
+                                   double *, hipStream_t);
+template afn_status spmm_gt<float>(const int64_t *, const int32_t *, const float *, int64_t,
+                                   const float *, int, float *, hipStream_t);
+template afn_status spmm_gt<double>(const int64_t *, const int32_t *, const double *, int64_t,
+                                    const double *, int, double *, hipStream_t);
+
+int64_t coldot_blocks(int64_t n)
+{
+    int64_t b = ceil_div(n, 1024);
+    return b < 1 ? 1 : (b > 512 ? 512 : b);
+}
+
+template <typename T>
+afn_status coldot(const T *A, const T *B, int64_t n, int R, double *out, double *part, hipStream_t s)
+{
+    const int64_t nb = coldot_blocks(n);
+    hipLaunchKernelGGL((coldot_stage1<T>), dim3((unsigned)nb), dim3(256), 0, s, A, B, n, R, ceil_div(n, nb),
+                       part);
+    hipLaunchKernelGGL(coldot_stage2, dim3(1), dim3(64), 0, s, part, (int)nb, R, out);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+template afn_status coldot<float>(const float *, const float *, int64_t, int, double *, double *,
+                                  hipStream_t);
+template afn_status coldot<double>(const double *, const double *, int64_t, int, double *, double *,
+                                   hipStream_t);
+
+template <typename T>
+afn_status col_xr_launch(T *X, T *Rv, const T *Pv, const T *Q, const double *alpha, int64_t n, int R,
+                         double *rr, double *part, hipStream_t s)
+{
+    const int64_t nb = coldot_blocks(n);
+    hipLaunchKernelGGL((col_xr<T>), dim3((unsigned)nb), dim3(256), 0, s, X, Rv, Pv, Q, alpha, n, R,
+                       ceil_div(n, nb), part);
+    hipLaunchKernelGGL(coldot_stage2, dim3(1), dim3(64), 0, s, part, (int)nb, R, rr);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+template afn_status col_xr_launch<float>(float *, float *, const float *, const float *, const double *,
+                                         int64_t, int, double *, double *, hipStream_t);
+template afn_status col_xr_launch<double>(double *, double *, const double *, const double *,
+                                          const double *, int64_t, int, double *, double *, hipStream_t);
+
+template <typename T>
+afn_status col_p_launch(T *Pv, const T *Z, const double *beta, int64_t n, int R, hipStream_t s)
+{
+    hipLaunchKernelGGL((col_p<T>), dim3((unsigned)ceil_div(n * R, 256)), dim3(256), 0, s, Pv, Z, beta, n, R);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+template afn_status col_p_launch<float>(float *, const float *, const double *, int64_t, int, hipStream_t);
+template afn_status col_p_launch<double>(double *, const double *, const double *, int64_t, int,
+                                         hipStream_t);
+
+afn_status col_alpha_launch(const double *rho, const double *pq, const int *active, double *alpha, int R,
+                            int *bad, hipStream_t s)
+{
+    hipLaunchKernelGGL(col_alpha, dim3(1), dim3(64), 0, s, rho, pq, (int *)active, alpha, R, bad);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status col_beta_launch(double *rho, const double *rho_new, const int *active, double *beta, int R,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(col_beta, dim3(1), dim3(64), 0, s, rho, rho_new, active, beta, R);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status col_converged_launch(const double *rr, const double *bnorm2, const double *tol, int *active,
+                                int *count, int R, int *bad, hipStream_t s)
+{
+    hipLaunchKernelGGL(col_converged, dim3(1), dim3(64), 0, s, rr, bnorm2, tol, active, count, R, bad);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+template <typename T>
+afn_status gather_rows(const double *X, int64_t ld, const int32_t *perm, int64_t n, int R,
+                       const double *scale, T *Y, hipStream_t s)
+{
+    hipLaunchKernelGGL((gather_rowmajor<T>), dim3((unsigned)ceil_div(n * R, 256)), dim3(256), 0, s, X, ld,
+                       perm, n, R, scale, Y);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+template afn_status gather_rows<float>(const double *, int64_t, const int32_t *, int64_t, int,
+                                       const double *, float *, hipStream_t);
+template afn_status gather_rows<double>(const double *, int64_t, const int32_t *, int64_t, int,
+                                        const double *, double *, hipStream_t);
+
+afn_status scatter_rows(const double *Y, const int32_t *perm, int64_t n, int R, double *X, int64_t ld,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(scatter_rowmajor, dim3((unsigned)ceil_div(n * R, 256)), dim3(256), 0, s, Y, perm, n,
+                       R, X, ld);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status scatter_rows_f32(const float *Y, int64_t n, int R, double *X, int64_t ld, hipStream_t s)
+{
+    hipLaunchKernelGGL(scatter_rowmajor_f32, dim3((unsigned)ceil_div(n * R, 256)), dim3(256), 0, s, Y, n, R,
+                       X, ld);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status sub_rows_launch(const double *B, const double *Y, double *Rr, int64_t total, hipStream_t s)
+{
+    hipLaunchKernelGGL(sub_rows, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, B, Y, Rr, total);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status scale_to_f32_launch(const double *r, const double *inv, float *r32, int64_t n, int R,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(scale_to_f32, dim3((unsigned)ceil_div(n * R, 256)), dim3(256), 0, s, r, inv, r32, n, R);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status axpy_cols_f32_launch(const double *a, const float *e32, double *x, int64_t n, int R,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(axpy_cols_f32, dim3((unsigned)ceil_div(n * R, 256)), dim3(256), 0, s, a, e32, x, n, R);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+}  // namespace afn

@@ -119,6 +119,32 @@ afn_status kernel_matvec(const double *X_dev, int64_t n, int32_t d, double l, do
     }
     hipStream_t s = (hipStream_t)stream;
     void *work = nullptr;
+    if (nrhs >= 2 && d <= 8) {
+        // many columns: MFMA tile kernel on point-major blocks of <= 64 columns
+        const int64_t npad = afn::kmv_packed_doubles(n, d) / d;
+        const int64_t R = nrhs < 64 ? nrhs : 64;
+        const size_t bytes = sizeof(double) * (size_t)(npad * d + 2 * n * R + afn::mrhs_part_elems(npad)) + 1024;
+        AFN_TRY(afn::library_scratch(bytes, &work));
+        double *Xs = (double *)work;
+        double *Pr = Xs + npad * d;
+        double *Yr = Pr + n * R;
+        double *part = Yr + n * R;
+        AFN_TRY(afn::kmv_pack(X_dev, n, d, l, Xs, precision == AFN_FP32, s));
+        for (int64_t c0 = 0; c0 < nrhs; c0 += 64) {
+            const int Rc = (int)(nrhs - c0 < 64 ? nrhs - c0 : 64);
+            if (precision == AFN_FP32) {
+                AFN_TRY(afn::gather_rows<float>(v_dev + c0 * ld, ld, nullptr, n, Rc, nullptr, (float *)Pr, s));
+                AFN_TRY(afn::kmv_mrhs_run<float>((const float *)Xs, npad, n, d, mu, (const float *)Pr, Rc,
+                                                 (float *)Yr, Rc, Rc, (float *)part, s));
+                AFN_TRY(afn::scatter_rows_f32((const float *)Yr, n, Rc, y_dev + c0 * ld, ld, s));
+            } else {
+                AFN_TRY(afn::gather_rows<double>(v_dev + c0 * ld, ld, nullptr, n, Rc, nullptr, Pr, s));
+                AFN_TRY(afn::kmv_mrhs_run<double>(Xs, npad, n, d, mu, Pr, Rc, Yr, Rc, Rc, part, s));
+                AFN_TRY(afn::scatter_rows(Yr, nullptr, n, Rc, y_dev + c0 * ld, ld, s));
+            }
+        }
+        return AFN_OK;
+    }
     AFN_TRY(afn::library_scratch(sizeof(double) * (size_t)afn::kmv_workspace_doubles(n, d), &work));
     if (precision == AFN_FP32)
         return afn::kmv_f32(X_dev, n, d, l, mu, v_dev, ld, y_dev, ld, nrhs, work, s);

@@ -432,3 +432,76 @@ def test_mixed_reports_failure_instead_of_wrong_answer(afn):
         assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(b)
     else:
         assert info["status"] in (afn.AFN_ESTAGNATION, afn.AFN_ENOCONV)
+
+
+# ------------------------------------------------------------------ many right-hand sides (MFMA tiles, block PCG)
+
+@pytest.mark.parametrize("n,d,nrhs,prec", [(1037, 3, 16, 0), (900, 8, 64, 0), (1111, 3, 70, 0),
+                                           (1037, 3, 64, 1), (700, 8, 5, 1)])
+def test_kernel_matvec_many_rhs_mfma(afn, n, d, nrhs, prec):
+    say(f"kmv mrhs n={n} d={d} nrhs={nrhs} prec={prec}")
+    X = W.points("uniform" if d == 3 else "normal", n, d, 61)
+    l = 0.15 if d == 3 else 2.0
+    V = np.random.default_rng(62).standard_normal((n, nrhs))
+    Vt = torch.tensor(V.T.copy(), device="cuda").t()            # column-major (n, nrhs)
+    Y = afn.kernel_matvec(dev(X), l, 1e-3, Vt, precision=prec).cpu().numpy()
+    for c in sorted({0, 1, nrhs // 2, nrhs - 1}):
+        yo, ab = oracle.kernel_matvec_rows(X, l, 1e-3, V[:, c], np.arange(n))
+        if prec == 0:
+            bound = 2 * (n + 4) * U * ab
+        else:
+            bound = (30 * (d + 4) * math.log(2) + n + 8) * U32 * ab + 1e-13 * np.abs(V[:, c]).sum()
+        assert np.all(np.abs(Y[:, c] - yo) <= bound), (c, np.max(np.abs(Y[:, c] - yo) / ab))
+
+
+@pytest.fixture(scope="module")
+def block_case(afn):
+    n, R = 2000, 8
+    X = W.points("uniform", n, 3, 71)
+    B = np.random.default_rng(72).standard_normal((n, R))
+    l, mu, k, w = 0.1, 1e-4, 200, 32
+    h = afn.afn_setup(dev(X), l, mu, k=k, w=w, precision=afn.AFN_FP32)
+    return X, B, l, mu, k, w, h
+
+
+def _block_solve(afn, h, B, tol):
+    Bt = torch.tensor(B.T.copy(), device="cuda").t()
+    return afn.afn_pcg_solve(h, Bt, tol=tol, maxit=500)
+
+
+def test_block_solve_matches_oracle_per_column(afn, block_case):
+    X, B, l, mu, k, w, h = block_case
+    x, info = _block_solve(afn, h, B, 1e-10)
+    say("block", info)
+    assert info["converged"] and info["outer_iterations"] >= 2
+    x = x.cpu().numpy()
+    idx, _ = oracle.fps(X, k)
+    A = oracle.afn_build(X, l, mu, idx, w)
+    for c in (0, 3, 7):
+        r = B[:, c] - oracle.kernel_matvec(X, l, mu, x[:, c])
+        assert np.linalg.norm(r) / np.linalg.norm(B[:, c]) <= 2e-10
+        xo, *_ = oracle.pcg(A, B[:, c], 1e-10, 500)
+        rel = np.linalg.norm(x[:, c] - xo) / np.linalg.norm(xo)
+        say(f"column {c}: vs FP64 oracle {rel:.2e}")
+        assert rel <= 1e-6
+
+
+def test_block_solve_graph_replays_equal_eager(afn, block_case, monkeypatch):
+    X, B, l, mu, k, w, h = block_case
+    xg, ig = _block_solve(afn, h, B, 1e-8)
+    monkeypatch.setenv("AFN_NO_GRAPH", "1")
+    xe, ie = _block_solve(afn, h, B, 1e-8)
+    monkeypatch.delenv("AFN_NO_GRAPH")
+    xg2, ig2 = _block_solve(afn, h, B, 1e-8)
+    say("graph", ig, "eager", ie)
+    assert ig["iterations"] == ie["iterations"] and ig["outer_iterations"] == ie["outer_iterations"]
+    assert torch.equal(xg, xe) and torch.equal(xg, xg2)
+
+
+def test_block_solve_column_equals_single_solve(afn, block_case):
+    X, B, l, mu, k, w, h = block_case
+    xb, _ = _block_solve(afn, h, B, 1e-10)
+    xs, _ = afn.afn_pcg_solve(h, dev(B[:, 5]), tol=1e-10, maxit=500)
+    rel = (torch.linalg.norm(xb[:, 5] - xs) / torch.linalg.norm(xs)).item()
+    say("block column vs single solve", rel)
+    assert rel <= 1e-6
