@@ -103,8 +103,12 @@ typedef struct afn_handle afn_handle;
 /* y = (K + mu I) v  (Eq. (1.1)), K evaluated on the fly from X (Eq. (1.2)).
  * X_dev: n x d FP64 row-major.  v_dev, y_dev: n x nrhs FP64 column-major,
  * leading dimension ld >= n; y must not alias v.  precision: afn_precision.
- * Asynchronous on 'stream'.  Errors: EINVAL (n < 1, d < 1 or d > 64, l <= 0,
- * mu < 0, nrhs < 1, ld < n), EDEVICE. */
+ * Asynchronous on 'stream'.  Uses a library-owned per-device workspace
+ * (grown on demand, kept until the process ends): calls on one device that
+ * overlap in time, from several threads or streams, race on it.  The handle
+ * functions below use only per-handle memory and may run concurrently on
+ * different handles and streams.  Errors: EINVAL (n < 1, d < 1 or d > 64,
+ * l <= 0, mu < 0, nrhs < 1, ld < n), ENOMEM, EDEVICE. */
 afn_status kernel_matvec(const double *X_dev, int64_t n, int32_t d, double l, double mu,
                          const double *v_dev, double *y_dev, int32_t nrhs, int64_t ld,
                          int32_t precision, void *stream);
@@ -162,7 +166,14 @@ afn_status afn_get_fsai(const afn_handle *h, int64_t *rowptr_host, int32_t *cols
  * dimension ld >= k.  Synchronous. */
 afn_status afn_get_cholesky(const afn_handle *h, double *L_host, int64_t ld);
 
-/* Release the handle and its device memory.  NULL is allowed. */
+/* Upper bound of the device memory afn_setup allocates (persistent plus its
+ * temporaries) for n points in d dimensions with these parameters; an
+ * adaptive landmark count is priced at min(k_max, n).  Host-only (no device
+ * call); used to admit requests by HBM footprint.  Errors: EINVAL. */
+afn_status afn_footprint_bytes(int64_t n, int32_t d, const afn_params *params, size_t *bytes);
+
+/* Release the handle and its device memory.  NULL is allowed.  Work the
+ * caller queued with afn_apply on the handle must be complete. */
 void afn_destroy(afn_handle *h);
 
 /* Static description of a status code. */

@@ -22,8 +22,8 @@ AFN_OK, AFN_EINVAL, AFN_ENOMEM, AFN_ENOTSPD, AFN_ENOCONV, AFN_EBREAKDOWN, AFN_ES
 AFN_FP64, AFN_FP32 = 0, 1
 
 EXPORTED = ["kernel_matvec", "afn_setup", "afn_apply", "afn_pcg_solve", "afn_get_info",
-            "afn_get_landmarks", "afn_get_fsai", "afn_get_cholesky", "afn_destroy",
-            "afn_status_string", "afn_last_error"]
+            "afn_get_landmarks", "afn_get_fsai", "afn_get_cholesky", "afn_footprint_bytes",
+            "afn_destroy", "afn_status_string", "afn_last_error"]
 
 
 class AFNError(RuntimeError):
@@ -85,6 +85,8 @@ def _declare(L):
     L.afn_get_landmarks.argtypes = [_P, _P, _I64, ctypes.POINTER(_I64)]
     L.afn_get_fsai.argtypes = [_P, _P, _P, _P, _I64, ctypes.POINTER(_I64)]
     L.afn_get_cholesky.argtypes = [_P, _P, _I64]
+    L.afn_footprint_bytes.argtypes = [_I64, _I32, ctypes.POINTER(afn_params),
+                                      ctypes.POINTER(ctypes.c_size_t)]
     L.afn_destroy.argtypes = [_P]
     L.afn_destroy.restype = None
     L.afn_status_string.argtypes = [ctypes.c_int]
@@ -92,7 +94,7 @@ def _declare(L):
     L.afn_last_error.argtypes = []
     L.afn_last_error.restype = ctypes.c_char_p
     for name in ("kernel_matvec", "afn_setup", "afn_apply", "afn_pcg_solve", "afn_get_info",
-                 "afn_get_landmarks", "afn_get_fsai", "afn_get_cholesky"):
+                 "afn_get_landmarks", "afn_get_fsai", "afn_get_cholesky", "afn_footprint_bytes"):
         getattr(L, name).restype = ctypes.c_int
 
 
@@ -236,6 +238,16 @@ def afn_setup(X: torch.Tensor, l: float, mu: float, k: int = -1, w: int = 64, k_
     _check(lib().afn_setup(X.data_ptr(), n, d, l, mu, ctypes.byref(prm), _stream(stream),
                            ctypes.byref(h)), "afn_setup")
     return Handle(h, n, d)
+
+
+def afn_footprint_bytes(n: int, d: int, k: int = -1, w: int = 64, k_max: int = 2000, m: int = 0,
+                        precision: int = AFN_FP64) -> int:
+    """Upper bound of afn_setup's device memory for these sizes (host-only)."""
+    prm = afn_params(k=k, k_max=k_max, w=w, m=m, precision=precision, reserved=0, seed=0)
+    out = ctypes.c_size_t(0)
+    _check(lib().afn_footprint_bytes(n, d, ctypes.byref(prm), ctypes.byref(out)),
+           "afn_footprint_bytes")
+    return out.value
 
 
 def afn_apply(h: Handle, r: torch.Tensor, out: torch.Tensor | None = None,

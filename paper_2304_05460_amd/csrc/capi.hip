@@ -739,10 +739,44 @@ afn_status afn_get_cholesky(const afn_handle *h, double *L_host, int64_t ld)
     return AFN_OK;
 }
 
+afn_status afn_footprint_bytes(int64_t n, int32_t d, const afn_params *prm, size_t *bytes)
+{
+    clear_error();
+    if (!prm || !bytes || n < 1 || d < 1 || d > kMaxD || prm->w < 1 || prm->w > kMaxW ||
+        prm->k < -1 || prm->k > n) {
+        set_error("afn_footprint_bytes: invalid argument");
+        return AFN_EINVAL;
+    }
+    const int64_t kmax = prm->k_max > 0 ? prm->k_max : 2000;
+    const int64_t k = prm->k >= 0 ? prm->k : (kmax < n ? kmax : n);
+    const int64_t nr = n - k, w = prm->w;
+    const bool f32 = prm->precision == AFN_FP32;
+    auto r = [](int64_t b) { return (size_t)round_up(b > 0 ? b : 1, 256); };
+    size_t t = 0;
+    t += r(64) + r(4 * n) + r(8 * n * d);                                   // flags, perm, Xp
+    if (k > 0) t += 2 * r(8 * k * k) + r(8 * dinv_doubles((int)k));       // L, Linv, Dinv
+    if (nr > 0) t += r(4 * nr * w) + r(8 * nr * w) + r(8 * (nr + 1)) + r(4 * nr * w) + r(8 * nr * w);
+    if (k > 0 && nr > 0) t += r(8 * k * nr);                               // V
+    if (d <= 8) t += r(8 * kmv_packed_doubles(n, d));                     // Xs64
+    if (f32) {
+        t += r(4 * kmv_packed_doubles(n, d)) + r(4 * k * k) + r(4 * k * nr) + 2 * r(4 * nr * w);
+        t += r(4 * work32_floats(n, d, (int)k, nr, nullptr, nullptr));
+    }
+    t += r(8 * work_doubles(n, d, (int)k, nr, nullptr, nullptr));
+    // setup temporaries: landmark indices, FPS workspace, marks, transpose
+    // counters, and the rank-estimation buffers (K_m and its companions)
+    size_t tmp = r(4 * k) + (size_t)fps_workspace_bytes(n) + r(4 * n) + r(8 * nr);
+    if (prm->k < 0) {
+        const int64_t m = prm->m > 0 ? (prm->m < n ? prm->m : n) : (n < 2000 ? n : 2000);
+        tmp += r(8 * m * m) + r(8 * m * (d + 16)) + (size_t)fps_workspace_bytes(m) + r(8 * 8 * m);
+    }
+    *bytes = t + tmp;
+    return AFN_OK;
+}
+
 void afn_destroy(afn_handle *h)
 {
     if (!h) return;
-    (void)hipDeviceSynchronize();
     if (h->host_sc) (void)hipHostFree(h->host_sc);
     for (auto &e : h->kmv_ev)
         if (e) (void)hipEventDestroy(e);

@@ -119,3 +119,9 @@ def serving_requests(count: int = 256, seed: int = 5):
                            maxit=500, seed=10_000 + i,
                            points="uniform" if d == 3 else "normal"))
     return out
+
+
+def poisson_arrivals(count: int, rate_hz: float, seed: int = 7) -> np.ndarray:
+    """Arrival times (seconds) of a Poisson stream: exponential gaps of mean 1/rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate_hz, size=count))
