@@ -28,18 +28,23 @@ ROOT = pathlib.Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
 PEAK_FP64_TFLOPS = 78.6          # MI355X FP64 vector (FMA = 2 flops)
-# FP64 exp charged at 13 FMA-class operations (26 flops): Cody-Waite range
-# reduction (2 FMA), a degree-10 Horner polynomial on |r| <= ln2/2 (10 FMA)
-# and the exponent scaling (1).
-FLOPS_PER_EXP_F64 = 26
+PEAK_FP32_TFLOPS = 157.3         # MI355X FP32 vector
+# FP64 VALU lane-operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+VALU_F64_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# FP64 VALU instructions per unique kernel evaluation in the inner loop of
+# kmv_sym<3, double, double> (AMD assembly of this build: 385 FP64 VALU
+# instructions per 4 x 4 block of pairs -- 6 for the distance, 16 for the
+# software 2^-t, 2 FMAs for the row and column products).
+VALU_F64_OPS_PER_PAIR_D3 = 385 / 16
 
 
-def kmv_flops(n: int, d: int, nrhs: int = 1, flops_exp: int = FLOPS_PER_EXP_F64) -> float:
+def kmv_flops(n: int, d: int, nrhs: int = 1) -> float:
     """Algorithmic flops of one (K + mu I) v: E = n(n-1)/2 unique kernel
-    evaluations at (3d + 1) flops for the scaled squared distance plus the
-    exponential, 2 n^2 R flops for the products with v and 2 n R for mu v."""
+    evaluations at (3d + 1) flops each (difference, square and sum per
+    coordinate, the exponential counted as one flop), 2 n^2 R flops for the
+    products with v and 2 n R for mu v."""
     E = n * (n - 1) / 2
-    return E * (3 * d + 1 + flops_exp) + 2.0 * n * n * nrhs + 2.0 * n * nrhs
+    return E * (3 * d + 1) + 2.0 * n * n * nrhs + 2.0 * n * nrhs
 
 
 def source_hash(path: pathlib.Path) -> str:
@@ -123,6 +128,80 @@ def cpu_baseline(X, b, l, mu, k, w, iters, n_rows=2000, n_knn=500, n_fsai=6):
     }
 
 
+def serving_bench(args):
+    """Mixed-size request stream: a burst run (every request at t = 0) gives
+    the saturated throughput; a Poisson stream at 0.7 x that rate gives the
+    latency percentiles.  Mixed precision (FP32 inner PCG, FP64 refinement
+    to rel-res 1e-6), one right-hand side per request."""
+    import numpy as np
+    import torch
+    from paper_2304_05460_amd import afn, serving, workloads as W
+
+    afn.lib()
+    probs = W.serving_requests(args.serving_count)
+    data = [W.make(q) for q in probs]
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    def reqs(arrivals):
+        return [serving.Request(i, X, b, q.l, q.mu, arrival=float(arrivals[i]), k=q.k, w=q.w,
+                                k_max=q.k_max, tol=q.tol, maxit=q.maxit)
+                for i, (q, (X, b)) in enumerate(zip(probs, data))]
+
+    def progress(label):
+        count = [0]
+        lock = __import__("threading").Lock()
+
+        def cb(res):
+            with lock:
+                count[0] += 1
+                if count[0] % 16 == 0 or count[0] == len(probs):
+                    log(f"{label}: {count[0]}/{len(probs)} done")
+        return cb
+
+    # warm-up: one small request (library load, first allocations)
+    srv = serving.Server(slots=args.slots, precision=afn.AFN_FP32)
+    small = int(np.argmin([q.n for q in probs]))
+    srv.run([reqs(np.zeros(len(probs)))[small]])
+    log(f"{len(probs)} requests; burst run")
+    srv = serving.Server(slots=args.slots, precision=afn.AFN_FP32)
+    t0 = time.perf_counter()
+    burst = srv.run(reqs(np.zeros(len(probs))), on_done=progress("burst"))
+    t_burst = time.perf_counter() - t0
+    sb = serving.summarize(burst)
+    rate = 0.7 * sb["completed"] / t_burst
+    log(f"burst: {sb}; Poisson run at {rate:.3f} requests/s")
+    srv = serving.Server(slots=args.slots, precision=afn.AFN_FP32)
+    t0 = time.perf_counter()
+    pois = srv.run(reqs(W.poisson_arrivals(len(probs), rate, seed=5)), on_done=progress("poisson"))
+    t_pois = time.perf_counter() - t0
+    sp = serving.summarize(pois)
+    ns = np.array([q.n for q in probs])
+    out = {
+        "metric": "serving solves/s under a Poisson stream (p50/p99 latency beside it)",
+        "value": round(sp["completed"] / t_pois, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": len(probs),
+        "warmup": 1,
+        "ms_per_step": round(t_pois / len(probs) * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"serving_{len(probs)}_requests_n5e3_2e5_d3_8",
+                   "slots": args.slots, "poisson_rate_per_s": round(rate, 4),
+                   "n_median": int(np.median(ns)), "n_max": int(ns.max())},
+        "poisson": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in sp.items()},
+        "burst": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in sb.items()},
+        "statuses": {str(s): int(c) for s, c in
+                     zip(*np.unique([r.status for r in pois], return_counts=True))},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +210,12 @@ def main():
     ap.add_argument("--l", type=float, default=0.1)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision run on the same input")
+    ap.add_argument("--serving", action="store_true",
+                    help="run the mixed-size request stream instead (p50/p99 latency, solves/s)")
+    ap.add_argument("--serving-count", type=int, default=256)
+    ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -153,14 +238,18 @@ def main():
         print(json.dumps({"copy_bytes": nbytes}))
         return
 
+    if args.serving:
+        serving_bench(args)
+        return
+
     p = W.c2(args.l, tol=args.tol)
     X_np, b_np = W.make(p)
     X = torch.tensor(X_np, device="cuda")
     b = torch.tensor(b_np, device="cuda")
     afn.lib()
 
-    def step():
-        h = afn.afn_setup(X, p.l, p.mu, k=p.k, w=p.w, k_max=p.k_max)
+    def step(precision=afn.AFN_FP64):
+        h = afn.afn_setup(X, p.l, p.mu, k=p.k, w=p.w, k_max=p.k_max, precision=precision)
         x, info = afn.afn_pcg_solve(h, b, tol=p.tol, maxit=p.maxit)
         sinfo = h.info()
         h.close()
@@ -169,19 +258,34 @@ def main():
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
-    log(f"workload {p.name}; warmup {args.warmup} step(s)")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log("warmup done; timing")
-    t0 = time.perf_counter()
-    infos = []
-    for _ in range(args.steps):
-        x, info, sinfo = step()
-        infos.append((info, sinfo))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    log(f"timed {args.steps} step(s) in {elapsed:.3f} s")
+    def timed(precision, label):
+        log(f"{label}: workload {p.name}; warmup {args.warmup} step(s)")
+        for _ in range(args.warmup):
+            step(precision)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = []
+        for _ in range(args.steps):
+            x, info, sinfo = step(precision)
+            infos.append((info, sinfo))
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        log(f"{label}: timed {args.steps} step(s) in {elapsed:.3f} s")
+        return x, infos, elapsed
+
+    def mixed_block(x64, value):
+        x32, infos32, elapsed32 = timed(afn.AFN_FP32, "mixed")
+        i32, s32 = infos32[-1]
+        rel = float(torch.linalg.vector_norm(x32 - x64) / torch.linalg.vector_norm(x64))
+        return {"value": round(args.steps / elapsed32, 4), "unit": "solves/s",
+                "ms_per_step": round(elapsed32 / args.steps * 1e3, 2),
+                "speedup_vs_fp64": round((args.steps / elapsed32) / value, 3),
+                "inner_iterations": i32["iterations"], "outer_iterations": i32["outer_iterations"],
+                "relres_true_fp64": i32["relres_true"], "rel_diff_vs_fp64_solution": rel,
+                "setup_ms": round(s32.ms["total"], 2), "solve_ms": round(i32["ms_solve"], 2),
+                "kmv_f32_avg_launch_ms": round(i32["ms_matvec"] / max(i32["matvec_launches"], 1), 4)}
+
+    x64, infos, elapsed = timed(afn.AFN_FP64, "fp64")
     ms_per_step = elapsed / args.steps * 1e3
     value = args.steps / elapsed
 
@@ -192,14 +296,25 @@ def main():
     achieved = F / (kmv_ms * 1e-3) / 1e12
     kern_src = ROOT / "paper_2304_05460_amd" / "csrc" / "kmv.hip"
     traffic = traffic_from_profile(kern_src)
+    E = p.n * (p.n - 1) / 2
+    valu_floor_ms = E * VALU_F64_OPS_PER_PAIR_D3 / VALU_F64_LANE_OPS * 1e3
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                "traffic": traffic, "kernel": "kmv_f64_partial",
+                "traffic": traffic, "kernel": "kmv_sym<3, double, double>",
                 "avg_launch_ms": round(kmv_ms, 4), "launches": launches,
-                "flops_per_launch": F}
+                "flops_per_launch": F,
+                "kernel_evals_per_s": round(E / (kmv_ms * 1e-3), 1),
+                "valu_instr_floor_ms": round(valu_floor_ms, 4),
+                "valu_instr_frac": round(valu_floor_ms / kmv_ms, 4)}
+
+    # the same input through the mixed-precision path (FP32 inner PCG inside
+    # FP64 iterative refinement)
+    mixed = None
+    if not args.no_mixed:
+        mixed = mixed_block(x64, value)
 
     out = {
-        "metric": "AFN-PCG solves/s at rel-res 1e-6 (FP64)",
+        "metric": "AFN-PCG solves/s at rel-res 1e-6 (FP64; mixed precision on the same input beside it)",
         "value": round(value, 4),
         "unit": "solves/s",
         "n_gpus": 1,
@@ -218,6 +333,7 @@ def main():
                   "setup_phases_ms": {k: round(v, 2) for k, v in sinfo.ms.items()},
                   "rank": {"r": sinfo.rank_r, "k_est": sinfo.rank_k_est,
                            "eig_branch": sinfo.rank_eig_branch}},
+        "mixed": mixed,
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

@@ -85,6 +85,11 @@ afn_status kmv_f32(const double *X, int64_t n, int d, double l, double mu, const
 size_t fps_workspace_bytes(int64_t n);
 afn_status fps(const double *X, int64_t n, int d, int k, int32_t *idx_dev, double *seld_dev,
                void *work, hipStream_t s, int *err_dev);
+// The same selection in pieces: fps_start picks the first point, fps_advance
+// runs steps st0+1 .. st1 of a k_total-step selection and can be resumed.
+afn_status fps_start(const double *X, int64_t n, int d, void *work, hipStream_t s, int *err);
+afn_status fps_advance(const double *X, int64_t n, int d, int st0, int st1, int k_total, int32_t *idx,
+                       double *seld, void *work, hipStream_t s, int *err);
 // perm = [idx (k entries) ; the other indices ascending]; sel: n ints scratch.
 afn_status landmark_permutation(const int32_t *idx, int k, int64_t n, int32_t *perm, int *sel,
                                 hipStream_t s);
@@ -116,14 +121,19 @@ afn_status identity(double *A, int k, hipStream_t s);
 // Padded rows of G (nr x w; row p has min(p+1, w) entries) for the Schur
 // complement, from V = L^{-1} K12 (k x nr) and the points.  *info_dev = 1 on
 // a non-positive pivot of a Schur block.
+// order (optional, nr entries): the sequence in which rows are processed.
 afn_status fsai_rows(const double *Xp, int64_t n, int k, int d, double l, double mu,
                      const double *V, const int32_t *cols, int w, double *gval, int *info_dev,
-                     hipStream_t s);
+                     const int32_t *order, hipStream_t s);
+// A spatially coherent processing order of the rows (Morton order of grid
+// cells over the points Xr, nr x d); work: fsai_order_work_bytes(nr, d).
+size_t fsai_order_work_bytes(int64_t nr, int d);
+afn_status fsai_row_order(const double *Xr, int64_t nr, int d, int32_t *order, void *work, hipStream_t s);
 // CSR of G^T: tptr (nr+1), trow/tval (nnz), rows of each column ascending.
-// work: nr 64-bit counters.
+// work: fsai_transpose_work_bytes(nr, w) bytes.
+size_t fsai_transpose_work_bytes(int64_t nr, int w);
 afn_status fsai_transpose(const int32_t *cols, const double *gval, int64_t nr, int w,
-                          int64_t *tptr, int32_t *trow, double *tval, int64_t *work,
-                          hipStream_t s);
+                          int64_t *tptr, int32_t *trow, double *tval, void *work, hipStream_t s);
 
 // ---------------------------------------------------------------- vectors
 int64_t dot_partials(int64_t n);

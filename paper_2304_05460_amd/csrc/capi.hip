@@ -264,13 +264,18 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     tm.mark(5, s);
     if (nr > 0) {
         AFN_TRY(h->arena.alloc_n(&h->gval, nr * h->w));
-        AFN_TRY(fsai_rows(h->Xp, n, k, d, l, mu, h->V, h->cols, h->w, h->gval, h->flags + 2, s));
+        int32_t *rorder = nullptr;
+        void *ows = nullptr;
+        AFN_TRY(tmp.alloc_n(&rorder, nr));
+        AFN_TRY(tmp.alloc(&ows, fsai_order_work_bytes(nr, d)));
+        AFN_TRY(fsai_row_order(h->Xp + (int64_t)k * d, nr, d, rorder, ows, s));
+        AFN_TRY(fsai_rows(h->Xp, n, k, d, l, mu, h->V, h->cols, h->w, h->gval, h->flags + 2, rorder, s));
         AFN_TRY(h->arena.alloc_n(&h->tptr, nr + 1));
         AFN_TRY(h->arena.alloc_n(&h->trow, nr * h->w));
         AFN_TRY(h->arena.alloc_n(&h->tval, nr * h->w));
-        int64_t *cnt = nullptr;
-        AFN_TRY(tmp.alloc_n(&cnt, nr));
-        AFN_TRY(fsai_transpose(h->cols, h->gval, nr, h->w, h->tptr, h->trow, h->tval, cnt, s));
+        void *tws = nullptr;
+        AFN_TRY(tmp.alloc(&tws, fsai_transpose_work_bytes(nr, h->w)));
+        AFN_TRY(fsai_transpose(h->cols, h->gval, nr, h->w, h->tptr, h->trow, h->tval, tws, s));
     }
     tm.mark(6, s);
     // points packed for the symmetric tile kernel; FP32 copies for mixed solves
@@ -765,7 +770,9 @@ afn_status afn_footprint_bytes(int64_t n, int32_t d, const afn_params *prm, size
     t += r(8 * work_doubles(n, d, (int)k, nr, nullptr, nullptr));
     // setup temporaries: landmark indices, FPS workspace, marks, transpose
     // counters, and the rank-estimation buffers (K_m and its companions)
-    size_t tmp = r(4 * k) + (size_t)fps_workspace_bytes(n) + r(4 * n) + r(8 * nr);
+    size_t tmp = r(4 * k) + (size_t)fps_workspace_bytes(n) + r(4 * n) +
+                 r((int64_t)fsai_transpose_work_bytes(nr, prm->w)) + r(4 * nr) +
+                 r((int64_t)fsai_order_work_bytes(nr, d));
     if (prm->k < 0) {
         const int64_t m = prm->m > 0 ? (prm->m < n ? prm->m : n) : (n < 2000 ? n : 2000);
         tmp += r(8 * m * m) + r(8 * m * (d + 16)) + (size_t)fps_workspace_bytes(m) + r(8 * 8 * m);

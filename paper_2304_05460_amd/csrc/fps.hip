@@ -222,10 +222,9 @@ size_t fps_workspace_bytes(int64_t n)
                     round_up(8 * kMaxWG, 256) + round_up(4 * kMaxWG, 256) + 256);
 }
 
-afn_status fps(const double *X, int64_t n, int d, int k, int32_t *idx, double *seld, void *work,
-               hipStream_t s, int *err)
+// First landmark (nearest to the centroid) into the step-0 slots.
+afn_status fps_start(const double *X, int64_t n, int d, void *work, hipStream_t s, int *err)
 {
-    if (k <= 0) return AFN_OK;
     Ws w = carve(work, n, d);
     const int64_t nb = ceil_div(n, 256);
     const int nwg = (int)(ceil_div(n, kThreads) < kMaxWG ? ceil_div(n, kThreads) : kMaxWG);
@@ -238,15 +237,34 @@ afn_status fps(const double *X, int64_t n, int d, int k, int32_t *idx, double *s
     hipLaunchKernelGGL(fps_first, dim3(1), dim3(kThreads), 0, s, w.min_d, w.min_i, nwg, n, w.slot_d,
                        w.slot_i, err);
     AFN_HIP(hipGetLastError());
-    for (int st = 1; st <= k; ++st) {
+    return AFN_OK;
+}
+
+// Selection steps st0+1 .. st1 (step st writes idx[st-1]); the step k_total
+// only reports its winner.  A later call resumes from st1.
+afn_status fps_advance(const double *X, int64_t n, int d, int st0, int st1, int k_total, int32_t *idx,
+                       double *seld, void *work, hipStream_t s, int *err)
+{
+    Ws w = carve(work, n, d);
+    const int nwg = (int)(ceil_div(n, kThreads) < kMaxWG ? ceil_div(n, kThreads) : kMaxWG);
+    const int64_t chunk = ceil_div(n, nwg);
+    for (int st = st0 + 1; st <= st1; ++st) {
         const int pb = (st - 1) & 1, nbuf = st & 1;
-        hipLaunchKernelGGL(fps_step, dim3(st == k ? 1 : nwg), dim3(kThreads), 0, s, X, n, d, w.dist,
-                           chunk, nwg, w.slot_d + pb * kMaxWG, w.slot_i + pb * kMaxWG,
-                           w.slot_d + nbuf * kMaxWG, w.slot_i + nbuf * kMaxWG, idx, seld, st,
-                           st == k ? 1 : 0, err);
+        const int fin = st == k_total ? 1 : 0;
+        hipLaunchKernelGGL(fps_step, dim3(fin ? 1 : nwg), dim3(kThreads), 0, s, X, n, d, w.dist, chunk,
+                           nwg, w.slot_d + pb * kMaxWG, w.slot_i + pb * kMaxWG,
+                           w.slot_d + nbuf * kMaxWG, w.slot_i + nbuf * kMaxWG, idx, seld, st, fin, err);
     }
     AFN_HIP(hipGetLastError());
     return AFN_OK;
+}
+
+afn_status fps(const double *X, int64_t n, int d, int k, int32_t *idx, double *seld, void *work,
+               hipStream_t s, int *err)
+{
+    if (k <= 0) return AFN_OK;
+    AFN_TRY(fps_start(X, n, d, work, s, err));
+    return fps_advance(X, n, d, 0, k, k, idx, seld, work, s, err);
 }
 
 namespace {

@@ -7,106 +7,270 @@
 // with y = S_ss^{-1} e_m = R^{-T} R^{-1} e_m and R^{-1} e_m = e_m / R_mm,
 // y_m = 1 / R_mm^2, so y / sqrt(y_m) = R^{-T} e_m.
 //
-// One workgroup per row: the k x m gathered columns of V stream through LDS
-// in chunks of 32 rows; each thread accumulates a 4 x 4 block of the Gram
-// matrix; the m x m Schur block is factored in LDS.
+// One wavefront (workgroup of 64) per row, pattern padded to N = 16 NT:
+//  1. Gram V_s^T V_s on MFMA (v_mfma_f64_16x16x4f64): the k x N gathered
+//     columns of V stream through LDS in chunks of 16 (coalesced along k);
+//     the same 16 x 4 fragment of a tile row serves as A and B operand, and
+//     only the NT (NT + 1) / 2 tiles on and below the diagonal are formed.
+//  2. S_ss = K22[s,s] + mu I - Gram in the accumulator layout; padding
+//     rows/columns (a >= m) become the identity.  The lower triangle goes to
+//     LDS (packed) and comes back one row per lane.
+//  3. Cholesky S_ss = R R^T in registers: lane r holds row r; the column of
+//     step j is broadcast lane by lane (v_readlane).
+//  4. g = R^{-T} e_m by back substitution (a wavefront sum per entry).
+//
+// The transpose G^T (CSR over columns) is filled with atomic cursors and
+// then put in ascending row order per column: one wavefront per column ranks
+// each entry among its column's entries (rows in a column are distinct), so
+// the layout, and every sum over it, does not depend on scheduling.
 #include "afn_internal.h"
 
 namespace afn {
 namespace {
 
-constexpr int W = 64;
-constexpr int TK = 32;
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void fsai_row_kernel(const double *__restrict__ Xp, int k, int d,
-                                                       double l2, double mu,
-                                                       const double *__restrict__ V,
-                                                       const int32_t *__restrict__ cols, int w,
-                                                       double *__restrict__ gval, int *info,
-                                                       int64_t row0)
+__device__ __forceinline__ double readlane_f64(double x, int l)
 {
-    __shared__ int s[W];
-    __shared__ double Vt[TK][W + 1];
-    __shared__ double S[W][W + 1];    // S[col][row]
-    __shared__ double g[W];
-    const int tid = threadIdx.x;
-    const int64_t p = row0 + blockIdx.x;
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum(double x)
+{
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+constexpr int tile_index(int I, int J) { return I * (I + 1) / 2 + J; }
+
+// Block b of a launch of G blocks, in XCD-aware order: blocks are dealt to
+// the 8 XCDs round-robin, so XCD x gets b = x, x+8, ...; giving it a
+// contiguous range of the (spatially ordered) rows keeps each XCD's gathers of
+// V columns within its own L2.
+__device__ __forceinline__ int64_t xcd_contiguous(int64_t b, int64_t G)
+{
+    const int64_t x = b & 7, j = b >> 3;
+    int64_t start = 0;
+    for (int64_t y = 0; y < x; ++y) start += (G - y + 7) >> 3;
+    return start + j;
+}
+
+template <int NT>
+__global__ __launch_bounds__(64) void fsai_row_mfma(const double *__restrict__ Xp, int k, int d, double l2,
+                                                    double mu, const double *__restrict__ V,
+                                                    const int32_t *__restrict__ cols, int w,
+                                                    double *__restrict__ gval, int *info,
+                                                    const int32_t *__restrict__ order, int64_t row0,
+                                                    int64_t G)
+{
+    constexpr int N = 16 * NT;
+    constexpr int TK = 16;
+    constexpr int QN = N * TK / 64;          // staged values per lane and chunk
+    constexpr int NTILE = NT * (NT + 1) / 2;
+    constexpr int PACK = N * (N + 1) / 2;
+    constexpr int STAGE = TK * (N + 1);
+    __shared__ double lds[PACK > STAGE ? PACK : STAGE];
+    __shared__ int sidx[N];
+    const int lane = threadIdx.x;
+    const int64_t slot = row0 + xcd_contiguous(blockIdx.x, G);
+    const int64_t p = order ? (int64_t)order[slot] : slot;
     const int m = (int)(p + 1 < w ? p + 1 : w);
-    if (tid < W) s[tid] = tid < m ? cols[p * w + tid] : 0;
+    if (lane < N) sidx[lane] = lane < m ? cols[p * w + lane] : -1;
     __syncthreads();
-    const int ty = tid / 16, tx = tid % 16;
-    double acc[4][4] = {};
+
+    // chunk t0 of the gathered columns: lane takes entries e = lane + 64 q,
+    // column a = e / TK, row t0 + e % TK (16 consecutive lanes read 128
+    // contiguous bytes of one column); out-of-range entries load a valid
+    // address and are zeroed, so all loads issue back to back
+    auto load_chunk = [&](int t0, double (&dst)[QN]) {
+#pragma unroll
+        for (int q = 0; q < QN; ++q) {
+            const int e = lane + 64 * q;
+            const int a = e / TK, tt = e - a * TK;
+            const int c = sidx[a];
+            const bool ok = c >= 0 && t0 + tt < k;
+            dst[q] = V[ok ? (int64_t)(t0 + tt) + (int64_t)c * k : 0];
+            if (!ok) dst[q] = 0.0;
+        }
+    };
+    doublex4 acc[NTILE];
+#pragma unroll
+    for (int t = 0; t < NTILE; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+    double nxt[QN];
+    if (k > 0) load_chunk(0, nxt);
     for (int t0 = 0; t0 < k; t0 += TK) {
-        for (int e = tid; e < TK * W; e += 256) {
-            int a = e / TK, tt = e - a * TK;
-            Vt[tt][a] = (a < m && t0 + tt < k) ? V[(int64_t)(t0 + tt) + (int64_t)s[a] * k] : 0.0;
+        double cur[QN];
+#pragma unroll
+        for (int q = 0; q < QN; ++q) cur[q] = nxt[q];
+        if (t0 + TK < k) load_chunk(t0 + TK, nxt);
+#pragma unroll
+        for (int q = 0; q < QN; ++q) {
+            const int e = lane + 64 * q;
+            const int a = e / TK, tt = e - a * TK;
+            lds[tt * (N + 1) + a] = cur[q];
         }
         __syncthreads();
-        for (int tt = 0; tt < TK; ++tt) {
-            double x[4], y[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) { x[q] = Vt[tt][ty * 4 + q]; y[q] = Vt[tt][tx * 4 + q]; }
+        for (int q = 0; q < TK / 4; ++q) {
+            double f[NT];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int I = 0; I < NT; ++I) f[I] = lds[(4 * q + (lane >> 4)) * (N + 1) + 16 * I + (lane & 15)];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) acc[q][u] = __builtin_fma(x[q], y[u], acc[q][u]);
+            for (int I = 0; I < NT; ++I)
+#pragma unroll
+                for (int J = 0; J <= I; ++J)
+                    acc[tile_index(I, J)] =
+                        __builtin_amdgcn_mfma_f64_16x16x4f64(f[I], f[J], acc[tile_index(I, J)], 0, 0, 0);
         }
         __syncthreads();
     }
+
+    // S_ss entries of the lower tiles: lane l, element i -> (16I + l/16 + 4i, 16J + l%16)
     const double *Xr = Xp + (int64_t)k * d;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int I = 0; I < NT; ++I)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int a = ty * 4 + q, b = tx * 4 + u;
-            double v = 0.0;
-            if (a < m && b < m) {
-                const double *xa = Xr + (int64_t)s[a] * d, *xb = Xr + (int64_t)s[b] * d;
-                double dd = 0.0;
-                for (int t = 0; t < d; ++t) {
-                    double del = xa[t] - xb[t];
-                    dd = __builtin_fma(del, del, dd);
+        for (int J = 0; J <= I; ++J)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * I + (lane >> 4) + 4 * i, c = 16 * J + (lane & 15);
+                if (r < c) continue;
+                double v;
+                if (r < m && c < m) {
+                    const double *xa = Xr + (int64_t)sidx[r] * d, *xb = Xr + (int64_t)sidx[c] * d;
+                    double dd = 0.0;
+                    for (int t = 0; t < d; ++t) {
+                        const double del = xa[t] - xb[t];
+                        dd = __builtin_fma(del, del, dd);
+                    }
+                    v = exp(-(dd / l2)) + (r == c ? mu : 0.0) - acc[tile_index(I, J)][i];
+                } else {
+                    v = r == c ? 1.0 : 0.0;
                 }
-                v = exp(-(dd / l2)) + (a == b ? mu : 0.0) - acc[q][u];
+                lds[r * (r + 1) / 2 + c] = v;
             }
-            S[b][a] = v;
-        }
     __syncthreads();
-    // Cholesky S = R R^T (lower R stored in S[col][row], row >= col)
-    for (int j = 0; j < m; ++j) {
-        if (tid == 0) {
-            double pv = S[j][j];
-            if (!(pv > 0.0)) {
-                atomicCAS(info, 0, 1);
-                pv = 1.0;
+    double a[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) a[c] = (lane < N && c <= lane) ? lds[lane * (lane + 1) / 2 + c] : 0.0;
+
+    // Cholesky: after step j, lane r holds R[r][j] in a[j] (r >= j)
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const double djj = readlane_f64(a[j], j);
+        bad = bad || !(djj > 0.0);
+        const double rjj = sqrt(djj > 0.0 ? djj : 1.0);
+        const double lr = lane == j ? rjj : a[j] / rjj;
+        a[j] = lr;
+#pragma unroll
+        for (int c = j + 1; c < N; ++c) a[c] = __builtin_fma(-lr, readlane_f64(lr, c), a[c]);
+    }
+    if (bad && lane == 0) atomicCAS(info, 0, 1);
+
+    // R^T g = e_{m-1} column by column: R goes back through LDS so that lane t
+    // holds column t (a[i] = R[i][t], i >= t); b is the running right-hand side.
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < N; ++c)
+        if (lane < N && c <= lane) lds[lane * (lane + 1) / 2 + c] = a[c];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) a[i] = (lane < N && i >= lane) ? lds[i * (i + 1) / 2 + lane] : 0.0;
+    double b = lane == m - 1 ? 1.0 : 0.0, g = 0.0;
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+        const double gi = readlane_f64(b, i) / readlane_f64(a[i], i);
+        if (lane == i) g = gi;
+        b = __builtin_fma(-a[i], gi, b);
+    }
+    if (lane < w) gval[p * w + lane] = lane < m ? g : 0.0;
+}
+
+// ---------------------------------------------------------------- row order
+// Rows of G are independent; processing them in Morton order of a coarse grid
+// of cells (at most 2^18) makes concurrently running rows share pattern
+// columns.  Bounding box by two-stage min/max, cell keys, counting sort (the
+// order inside a cell is arbitrary: it changes no result).
+constexpr int kCellBits = 18;
+
+__host__ __device__ inline void cell_shape(int d, int &bits, int &dims)
+{
+    bits = kCellBits / d > 0 ? kCellBits / d : 1;
+    if (bits > 16) bits = 16;
+    dims = kCellBits / bits < d ? kCellBits / bits : d;
+}
+
+__global__ __launch_bounds__(256) void bbox_partial(const double *Xr, int64_t nr, int d, int dims,
+                                                    double *part)
+{
+    __shared__ double lo[256], hi[256];
+    for (int t = 0; t < dims; ++t) {
+        double a = __builtin_inf(), b = -__builtin_inf();
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nr; i += (int64_t)gridDim.x * 256) {
+            const double x = Xr[i * d + t];
+            a = x < a ? x : a;
+            b = x > b ? x : b;
+        }
+        lo[threadIdx.x] = a;
+        hi[threadIdx.x] = b;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (threadIdx.x < h) {
+                lo[threadIdx.x] = lo[threadIdx.x + h] < lo[threadIdx.x] ? lo[threadIdx.x + h] : lo[threadIdx.x];
+                hi[threadIdx.x] = hi[threadIdx.x + h] > hi[threadIdx.x] ? hi[threadIdx.x + h] : hi[threadIdx.x];
             }
-            S[j][j] = sqrt(pv);
+            __syncthreads();
         }
-        __syncthreads();
-        const double piv = S[j][j];
-        for (int r = j + 1 + tid; r < m; r += 256) S[j][r] /= piv;
-        __syncthreads();
-        const int mm = m - j - 1;
-        for (int e = tid; e < mm * mm; e += 256) {
-            int c = j + 1 + e / mm, r = j + 1 + e % mm;
-            if (r >= c) S[c][r] -= S[j][r] * S[j][c];
+        if (threadIdx.x == 0) {
+            part[(blockIdx.x * dims + t) * 2] = lo[0];
+            part[(blockIdx.x * dims + t) * 2 + 1] = hi[0];
         }
         __syncthreads();
     }
-    // g = R^{-T} e_m by back substitution, one wavefront
-    if (tid < 64) {
-        const int lane = tid;
-        double gl = 0.0;   // g[lane] once known
-        if (lane == m - 1) gl = 1.0 / S[m - 1][m - 1];
-        for (int i = m - 2; i >= 0; --i) {
-            // sum_{t > i} R[t][i] g[t],  R[t][i] = S[i][t]
-            double term = (lane > i && lane < m) ? S[i][lane] * gl : 0.0;
-            for (int off = 32; off > 0; off >>= 1) term += __shfl_xor(term, off, 64);
-            if (lane == i) gl = -term / S[i][i];
-        }
-        if (lane < w) gval[p * w + lane] = lane < m ? gl : 0.0;
-        (void)g;
+}
+
+__global__ __launch_bounds__(64) void bbox_final(const double *part, int nb, int dims, double *box)
+{
+    const int t = threadIdx.x;
+    if (t >= dims) return;
+    double a = __builtin_inf(), b = -__builtin_inf();
+    for (int g = 0; g < nb; ++g) {
+        const double x = part[(g * dims + t) * 2], y = part[(g * dims + t) * 2 + 1];
+        a = x < a ? x : a;
+        b = y > b ? y : b;
     }
+    box[2 * t] = a;
+    box[2 * t + 1] = b;
+}
+
+__global__ __launch_bounds__(256) void cell_keys(const double *Xr, int64_t nr, int d, int bits, int dims,
+                                                 const double *box, int32_t *key, unsigned long long *cnt)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nr) return;
+    const int cells1 = 1 << bits;
+    uint32_t kk = 0;
+    for (int t = 0; t < dims; ++t) {
+        const double lo = box[2 * t], span = box[2 * t + 1] - lo;
+        int q = span > 0.0 ? (int)((Xr[i * d + t] - lo) / span * cells1) : 0;
+        q = q < 0 ? 0 : (q >= cells1 ? cells1 - 1 : q);
+        for (int bb = 0; bb < bits; ++bb) kk |= (uint32_t)((q >> bb) & 1) << (bb * dims + t);
+    }
+    key[i] = (int32_t)kk;
+    atomicAdd(&cnt[kk], 1ULL);
+}
+
+__global__ __launch_bounds__(256) void cell_scatter(const int32_t *key, int64_t nr, const int64_t *start,
+                                                    unsigned long long *cursor, int32_t *order)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nr) return;
+    const int32_t kk = key[i];
+    const unsigned long long pos = atomicAdd(&cursor[kk], 1ULL);
+    order[start[kk] + (int64_t)pos] = (int32_t)i;
 }
 
 __global__ __launch_bounds__(256) void count_cols(const int32_t *cols, int64_t nr, int w,
@@ -165,63 +329,120 @@ __global__ __launch_bounds__(256) void fill_transpose(const int32_t *cols, const
     tval[at] = gval[e];
 }
 
-// Order every column of G^T's CSR by row index (deterministic layout).
-__global__ __launch_bounds__(256) void sort_segments(const int64_t *ptr, int64_t nr, int32_t *trow,
-                                                     double *tval)
+// Entry i of column c goes to position ptr[c] + #{entries of c with a smaller
+// row} (ties by fill position, so the placement is a permutation even for
+// malformed input); one wavefront per column.
+__global__ __launch_bounds__(256) void place_sorted(const int64_t *__restrict__ ptr, int64_t nr,
+                                                    const int32_t *__restrict__ urow,
+                                                    const double *__restrict__ uval,
+                                                    int32_t *__restrict__ trow, double *__restrict__ tval)
 {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (c >= nr) return;
-    int64_t b = ptr[c], e = ptr[c + 1];
-    for (int64_t i = b + 1; i < e; ++i) {
-        int32_t r = trow[i];
-        double v = tval[i];
-        int64_t j = i;
-        while (j > b && trow[j - 1] > r) {
-            trow[j] = trow[j - 1];
-            tval[j] = tval[j - 1];
-            --j;
+    const int64_t b = ptr[c], len = ptr[c + 1] - b;
+    for (int64_t i = lane; i < len; i += 64) {
+        const int32_t r = urow[b + i];
+        int64_t rank = 0;
+        for (int64_t j = 0; j < len; ++j) {
+            const int32_t q = urow[b + j];
+            rank += (q < r || (q == r && j < i)) ? 1 : 0;
         }
-        trow[j] = r;
-        tval[j] = v;
+        trow[b + rank] = r;
+        tval[b + rank] = uval[b + i];
     }
 }
 
 }  // namespace
 
+size_t fsai_order_work_bytes(int64_t nr, int d)
+{
+    int bits, dims;
+    cell_shape(d, bits, dims);
+    const int64_t cells = (int64_t)1 << (bits * dims);
+    return (size_t)(round_up(8 * 256 * 2 * dims, 256) + round_up(8 * 2 * dims, 256) +
+                    round_up(4 * (nr > 0 ? nr : 1), 256) + round_up(8 * cells, 256) +
+                    round_up(8 * (cells + 1), 256));
+}
+
+afn_status fsai_row_order(const double *Xr, int64_t nr, int d, int32_t *order, void *work, hipStream_t s)
+{
+    if (nr <= 0) return AFN_OK;
+    int bits, dims;
+    cell_shape(d, bits, dims);
+    const int64_t cells = (int64_t)1 << (bits * dims);
+    char *q = (char *)work;
+    auto take = [&](int64_t bytes) {
+        char *r = q;
+        q += round_up(bytes, 256);
+        return r;
+    };
+    double *part = (double *)take(8 * 256 * 2 * dims);
+    double *box = (double *)take(8 * 2 * dims);
+    int32_t *key = (int32_t *)take(4 * nr);
+    unsigned long long *cnt = (unsigned long long *)take(8 * cells);
+    int64_t *start = (int64_t *)take(8 * (cells + 1));
+    const int nb = (int)(ceil_div(nr, 256) < 256 ? ceil_div(nr, 256) : 256);
+    const unsigned g = (unsigned)ceil_div(nr, 256);
+    hipLaunchKernelGGL(bbox_partial, dim3(nb), dim3(256), 0, s, Xr, nr, d, dims, part);
+    hipLaunchKernelGGL(bbox_final, dim3(1), dim3(64), 0, s, part, nb, dims, box);
+    AFN_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * (size_t)cells, s));
+    hipLaunchKernelGGL(cell_keys, dim3(g), dim3(256), 0, s, Xr, nr, d, bits, dims, box, key, cnt);
+    hipLaunchKernelGGL(scan_counts, dim3(1), dim3(1024), 0, s, cnt, cells, start);
+    AFN_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * (size_t)cells, s));
+    hipLaunchKernelGGL(cell_scatter, dim3(g), dim3(256), 0, s, key, nr, start, cnt, order);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
 afn_status fsai_rows(const double *Xp, int64_t n, int k, int d, double l, double mu,
                      const double *V, const int32_t *cols, int w, double *gval, int *info,
-                     hipStream_t s)
+                     const int32_t *order, hipStream_t s)
 {
     const int64_t nr = n - k;
     if (nr <= 0) return AFN_OK;
     const int64_t chunk = 1 << 20;
     for (int64_t r0 = 0; r0 < nr; r0 += chunk) {
-        int64_t cnt = nr - r0 < chunk ? nr - r0 : chunk;
-        hipLaunchKernelGGL(fsai_row_kernel, dim3((unsigned)cnt), dim3(256), 0, s, Xp, k, d, l * l, mu,
-                           V, cols, w, gval, info, r0);
+        const int64_t cnt = nr - r0 < chunk ? nr - r0 : chunk;
+        const dim3 grid((unsigned)cnt), block(64);
+        switch ((w + 15) / 16) {
+            case 1: hipLaunchKernelGGL(fsai_row_mfma<1>, grid, block, 0, s, Xp, k, d, l * l, mu, V, cols, w, gval, info, order, r0, cnt); break;
+            case 2: hipLaunchKernelGGL(fsai_row_mfma<2>, grid, block, 0, s, Xp, k, d, l * l, mu, V, cols, w, gval, info, order, r0, cnt); break;
+            case 3: hipLaunchKernelGGL(fsai_row_mfma<3>, grid, block, 0, s, Xp, k, d, l * l, mu, V, cols, w, gval, info, order, r0, cnt); break;
+            default: hipLaunchKernelGGL(fsai_row_mfma<4>, grid, block, 0, s, Xp, k, d, l * l, mu, V, cols, w, gval, info, order, r0, cnt); break;
+        }
         AFN_HIP(hipGetLastError());
     }
     return AFN_OK;
 }
 
+size_t fsai_transpose_work_bytes(int64_t nr, int w)
+{
+    const int64_t nnz = nr * w;
+    return (size_t)(round_up(8 * (nr > 0 ? nr : 1), 256) + round_up(4 * (nnz > 0 ? nnz : 1), 256) +
+                    round_up(8 * (nnz > 0 ? nnz : 1), 256));
+}
+
 afn_status fsai_transpose(const int32_t *cols, const double *gval, int64_t nr, int w,
-                          int64_t *tptr, int32_t *trow, double *tval, int64_t *work,
-                          hipStream_t s)
+                          int64_t *tptr, int32_t *trow, double *tval, void *work, hipStream_t s)
 {
     if (nr <= 0) {
         AFN_HIP(hipMemsetAsync(tptr, 0, sizeof(int64_t), s));
         return AFN_OK;
     }
-    unsigned long long *cnt = (unsigned long long *)work;
+    char *base = (char *)work;
+    unsigned long long *cnt = (unsigned long long *)base;
+    int32_t *urow = (int32_t *)(base + round_up(8 * nr, 256));
+    double *uval = (double *)(base + round_up(8 * nr, 256) + round_up(4 * nr * w, 256));
     AFN_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * (size_t)nr, s));
     const unsigned blocks = (unsigned)ceil_div(nr * w, 256);
     hipLaunchKernelGGL(count_cols, dim3(blocks), dim3(256), 0, s, cols, nr, w, cnt);
     hipLaunchKernelGGL(scan_counts, dim3(1), dim3(1024), 0, s, cnt, nr, tptr);
     AFN_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * (size_t)nr, s));
     hipLaunchKernelGGL(fill_transpose, dim3(blocks), dim3(256), 0, s, cols, gval, nr, w, tptr, cnt,
-                       trow, tval);
-    hipLaunchKernelGGL(sort_segments, dim3((unsigned)ceil_div(nr, 256)), dim3(256), 0, s, tptr, nr,
-                       trow, tval);
+                       urow, uval);
+    hipLaunchKernelGGL(place_sorted, dim3((unsigned)ceil_div(nr, 4)), dim3(256), 0, s, tptr, nr, urow,
+                       uval, trow, tval);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }

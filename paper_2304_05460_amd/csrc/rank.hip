@@ -20,8 +20,6 @@
 
 namespace afn {
 
-afn_status fps(const double *X, int64_t n, int d, int k, int32_t *idx, double *seld, void *work,
-               hipStream_t s, int *err);
 namespace {
 
 constexpr int kMaxM = 4096;
@@ -151,112 +149,166 @@ __global__ __launch_bounds__(256) void scan_update(double *K, int m, const int32
 }
 
 // ---------------------------------------------------------------- eigen count
-// Householder step j on A (m x m, column-major): scalars sc[0] = beta,
-// sc[1] = s (new sub-diagonal), sc[2] = skip flag; v (m, zero outside j+1..).
-__global__ __launch_bounds__(256) void hh_vector(double *A, int m, int j, double *v, double *sc)
+// Householder tridiagonalization of the symmetric A (m x m, column-major),
+// two launches per step j = 0 .. m-3.  The reflector of step j is
+// H = I - beta v v^T with v supported on rows j+1 .. m-1, kept in one of two
+// buffers (step parity) with beta in sc[0]; the step replaces the trailing
+// block B = A[j+1:, j+1:] by H B H = B - v w^T - w v^T with p = beta B v,
+// K = beta/2 v^T p and w = p - K v.  Each column of B is handled by one
+// wavefront: reads along the column are coalesced, and every sum runs in a
+// fixed order (lane partials in row order, then a butterfly), so the result
+// does not depend on scheduling.  Rows and columns <= j+1 are never read
+// after step j, so the update writes only A[j+2:, j+2:] and the column j+1
+// is consumed on the fly: its wavefront forms the reflector of step j+1.
+// diag[c] / off[c] collect the tridiagonal T (the sub-diagonal up to sign).
+
+__device__ __forceinline__ double wave_sum(double x)
 {
-    __shared__ double ws[4];
-    const int tid = threadIdx.x;
-    double a2 = 0.0;
-    for (int i = j + 1 + tid; i < m; i += 256) a2 += A[i + (int64_t)j * m] * A[i + (int64_t)j * m];
-    for (int off = 32; off > 0; off >>= 1) a2 += __shfl_xor(a2, off, 64);
-    if ((tid & 63) == 0) ws[tid >> 6] = a2;
-    __syncthreads();
-    const double alpha2 = ws[0] + ws[1] + ws[2] + ws[3];
-    __syncthreads();
-    const double alpha = sqrt(alpha2);
-    const double x0 = A[j + 1 + (int64_t)j * m];
-    const double snew = x0 >= 0.0 ? -alpha : alpha;
-    for (int i = tid; i < m; i += 256) {
-        double vi = 0.0;
-        if (i == j + 1) vi = x0 - snew;
-        else if (i > j + 1) vi = A[i + (int64_t)j * m];
-        v[i] = vi;
-    }
-    double vn = 0.0;
-    for (int i = j + 1 + tid; i < m; i += 256) {
-        double vi = (i == j + 1) ? x0 - snew : A[i + (int64_t)j * m];
-        vn += vi * vi;
-    }
-    for (int off = 32; off > 0; off >>= 1) vn += __shfl_xor(vn, off, 64);
-    if ((tid & 63) == 0) ws[tid >> 6] = vn;
-    __syncthreads();
-    if (tid == 0) {
-        const double vnorm2 = ws[0] + ws[1] + ws[2] + ws[3];
-        const bool skip = alpha == 0.0 || vnorm2 == 0.0;
-        sc[0] = skip ? 0.0 : 2.0 / vnorm2;
-        sc[1] = snew;
-        sc[2] = skip ? 1.0 : 0.0;
-    }
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
 }
 
-// pw[i] = beta * sum_t A[i,t] v[t] for i > j, partial over column chunks
-__global__ __launch_bounds__(256) void hh_matvec(const double *A, int m, int j, const double *v,
-                                                 int chunk, double *part)
-{
-    const int i = j + 1 + blockIdx.x * blockDim.x + threadIdx.x;
-    const int t0 = j + 1 + blockIdx.y * chunk;
-    const int t1 = t0 + chunk < m ? t0 + chunk : m;
-    if (i >= m) return;
-    double s = 0.0;
-    for (int t = t0; t < t1; ++t) s = __builtin_fma(A[i + (int64_t)t * m], v[t], s);
-    part[(int64_t)blockIdx.y * m + i] = s;
-}
+constexpr int kUnroll = 8;     // rows per lane with loads in flight together
 
-__global__ __launch_bounds__(256) void hh_pw(const double *part, int splits, int m, int j,
-                                             const double *v, const double *sc, double *pw)
+// Reflector of the column whose entries at rows r0 .. m-1 are colval(i):
+// v[r0] = x0 - snew, v[i] = colval(i) beyond, snew = -sign(x0) alpha with
+// alpha = ||col||, and v^T v = 2 alpha (alpha + |x0|) (both terms >= 0).
+template <class F>
+__device__ void house_wave(F colval, int r0, int m, double *v, double *sc, double *offp)
 {
-    __shared__ double ws[4];
-    const int tid = threadIdx.x;
-    const double beta = sc[0];
-    double vtp = 0.0;
-    for (int i = j + 1 + tid; i < m; i += 256) {
-        double s = 0.0;
-        for (int q = 0; q < splits; ++q) s += part[(int64_t)q * m + i];
-        double p = beta * s;
-        pw[i] = p;
-        vtp += v[i] * p;
-    }
-    for (int off = 32; off > 0; off >>= 1) vtp += __shfl_xor(vtp, off, 64);
-    if ((tid & 63) == 0) ws[tid >> 6] = vtp;
-    __syncthreads();
-    const double kk = 0.5 * beta * (ws[0] + ws[1] + ws[2] + ws[3]);
-    for (int i = j + 1 + tid; i < m; i += 256) pw[i] -= kk * v[i];
-}
-
-__global__ __launch_bounds__(256) void hh_update(double *A, int m, int j, const double *v,
-                                                 const double *pw, const double *sc)
-{
-    const int64_t mm = m - j - 1;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool skip = sc[2] != 0.0;
-    if (e < mm * mm && !skip) {
-        const int c = j + 1 + (int)(e / mm), i = j + 1 + (int)(e % mm);
-        A[i + (int64_t)c * m] -= v[i] * pw[c] + pw[i] * v[c];
-    }
-    // column / row j: new sub-diagonal, zeros below
-    if (!skip && e < m) {
-        const int i = (int)e;
-        if (i == j + 1) {
-            A[i + (int64_t)j * m] = sc[1];
-            A[j + (int64_t)i * m] = sc[1];
-        } else if (i > j + 1) {
-            A[i + (int64_t)j * m] = 0.0;
-            A[j + (int64_t)i * m] = 0.0;
+    const int lane = threadIdx.x & 63;
+    double a2 = 0.0, x0 = 0.0;
+    for (int base = r0 + lane; base < m; base += 64 * kUnroll) {
+        double a[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int i = base + 64 * u;
+            a[u] = i < m ? colval(i) : 0.0;
         }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int i = base + 64 * u;
+            if (i < m) v[i] = a[u];
+            a2 = __builtin_fma(a[u], a[u], a2);
+        }
+        if (base == r0) x0 = a[0];
+    }
+    a2 = wave_sum(a2);
+    x0 = __shfl(x0, 0, 64);
+    const double alpha = sqrt(a2);
+    const double snew = x0 >= 0.0 ? -alpha : alpha;
+    if (lane == 0) {
+        const double vn2 = 2.0 * alpha * (alpha + fabs(x0));
+        v[r0] = x0 - snew;
+        sc[0] = alpha == 0.0 || !(vn2 > 0.0) ? 0.0 : 2.0 / vn2;
+        *offp = snew;
     }
 }
 
-__global__ void sturm_count(const double *A, int m, double tau, int *count)
+// One wavefront: diag[0], and the reflector of step 0 (m >= 3) or T (m <= 2).
+__global__ __launch_bounds__(64) void hh_init(const double *A, int m, double *v, double *sc, double *diag,
+                                              double *off)
+{
+    const int lane = threadIdx.x;
+    if (lane == 0) diag[0] = A[0];
+    if (m == 2 && lane == 0) {
+        diag[1] = A[1 + m];
+        off[0] = A[1];
+    }
+    if (m < 3) return;
+    house_wave([&](int i) { return A[i]; }, 1, m, v, sc, off);
+}
+
+// p[c] = beta * sum_{i > j} A[i,c] v[i] for c > j; part[b] = sum over the
+// block's (<= 4) columns of v[c] p[c].
+__global__ __launch_bounds__(256) void hh_mv(const double *__restrict__ A, int m, int j,
+                                             const double *__restrict__ v, const double *__restrict__ sc,
+                                             double *__restrict__ p, double *__restrict__ part)
+{
+    __shared__ double ws[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int c = j + 1 + (int)blockIdx.x * 4 + wv;
+    double dotc = 0.0;
+    if (c < m) {
+        const double *col = A + (int64_t)c * m;
+        double s = 0.0;
+        for (int base = j + 1 + lane; base < m; base += 64 * kUnroll) {
+            double a[kUnroll], b[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int i = base + 64 * u;
+                a[u] = i < m ? col[i] : 0.0;
+                b[u] = i < m ? v[i] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) s = __builtin_fma(a[u], b[u], s);
+        }
+        s = wave_sum(s);
+        const double pc = sc[0] * s;
+        if (lane == 0) p[c] = pc;
+        dotc = v[c] * pc;
+    }
+    if (lane == 0) ws[wv] = dotc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+}
+
+// Rank-two update of step j on the columns c > j, and the reflector of step
+// j+1 (into vn / scn / off[j+1]) from the updated column j+1.  Every
+// wavefront forms K = beta/2 v^T p from the per-block partials itself (same
+// order everywhere).
+__global__ __launch_bounds__(256) void hh_up(double *__restrict__ A, int m, int j, const double *__restrict__ v,
+                                             const double *__restrict__ sc, const double *__restrict__ p,
+                                             const double *__restrict__ part, int nb, double *__restrict__ vn,
+                                             double *__restrict__ scn, double *__restrict__ diag,
+                                             double *__restrict__ off)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int c = j + 1 + (int)blockIdx.x * 4 + wv;
+    if (c >= m) return;
+    double s = 0.0;
+    for (int b = lane; b < nb; b += 64) s += part[b];
+    const double K = 0.5 * sc[0] * wave_sum(s);
+    const double vc = v[c], wc = p[c] - K * vc;
+    double *col = A + (int64_t)c * m;
+    if (c > j + 1) {
+        for (int base = j + 2 + lane; base < m; base += 64 * kUnroll) {
+            double a[kUnroll], vv[kUnroll], pp[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int i = base + 64 * u;
+                a[u] = i < m ? col[i] : 0.0;
+                vv[u] = i < m ? v[i] : 0.0;
+                pp[u] = i < m ? p[i] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int i = base + 64 * u;
+                const double wi = pp[u] - K * vv[u];
+                const double x = a[u] - (vv[u] * wc + wi * vc);
+                if (i < m) col[i] = x;
+                if (i == c) diag[c] = x;
+            }
+        }
+        return;
+    }
+    if (lane == 0) diag[c] = col[c] - (vc * wc + wc * vc);
+    auto updated = [&](int i) {
+        const double vi = v[i], wi = p[i] - K * vi;
+        return col[i] - (vi * wc + wi * vc);
+    };
+    house_wave(updated, j + 2, m, vn, scn, off + c);
+}
+
+// Number of eigenvalues of T above tau: positive pivots of the LDL^T of
+// T - tau I (Sylvester's law of inertia / Sturm sequence).
+__global__ void sturm_count(const double *diag, const double *off, int m, double tau, int *count)
 {
     int cnt = 0;
     double q = 0.0;
     for (int i = 0; i < m; ++i) {
-        double qi = A[i + (int64_t)i * m] - tau;
-        if (i > 0) {
-            double b = A[i + (int64_t)(i - 1) * m];
-            qi -= b * b / q;
-        }
+        double qi = diag[i] - tau;
+        if (i > 0) qi -= off[i - 1] * off[i - 1] / q;
         if (qi == 0.0) qi = -1e-300;
         if (qi > 0.0) ++cnt;
         q = qi;
@@ -280,7 +332,7 @@ afn_status rank_estimate(const double *X, int64_t n, int d, double l, double mu,
     } guard{tmp};
     int32_t *sub = nullptr, *ord = nullptr;
     double *Xm = nullptr, *K = nullptr, *c = nullptr, *pv = nullptr, *part = nullptr, *errs = nullptr;
-    double *v = nullptr, *pw = nullptr, *gp = nullptr, *sc = nullptr;
+    double *v = nullptr, *pw = nullptr, *gp = nullptr, *sc = nullptr, *tdiag = nullptr, *toff = nullptr;
     int *cnt = nullptr, *err = nullptr;
     void *fws = nullptr;
     const int nparts = 256;
@@ -303,7 +355,8 @@ afn_status rank_estimate(const double *X, int64_t n, int d, double l, double mu,
     hipLaunchKernelGGL(gather_scaled, dim3((unsigned)ceil_div((int64_t)m * d, 256)), dim3(256), 0, s, X,
                        sub, m, d, scale, Xm);
     hipLaunchKernelGGL(kmat_fill, dim3(gmm), dim3(256), 0, s, Xm, m, d, l2, K);
-    AFN_TRY(fps(Xm, m, d, m, ord, nullptr, fws, s, err));
+    // FPS order of the subsample, produced 64 positions at a time as the scan needs them
+    AFN_TRY(fps_start(Xm, m, d, fws, s, err));
     hipLaunchKernelGGL(sumsq_partial, dim3(nparts), dim3(256), 0, s, K, mm, part);
     hipLaunchKernelGGL(sum_parts, dim3(1), dim3(256), 0, s, part, nparts, errs + m);
     AFN_HIP(hipGetLastError());
@@ -316,6 +369,7 @@ afn_status rank_estimate(const double *X, int64_t n, int d, double l, double mu,
     int r_found = m;
     for (int r0 = 0; r0 < m && r_found == m; r0 += 64) {
         const int r1 = r0 + 64 < m ? r0 + 64 : m;
+        AFN_TRY(fps_advance(Xm, m, d, r0, r1, m, ord, nullptr, fws, s, err));
         for (int r = r0; r < r1; ++r) {
             hipLaunchKernelGGL(scan_column, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, K, m, ord,
                                r, pivtol, c, pv);
@@ -349,27 +403,26 @@ afn_status rank_estimate(const double *X, int64_t n, int d, double l, double mu,
     info->rank_eig_count = -1;
     if (kest < 2000) {
         // eigenvalues of K(X_m, X_m) on the unscaled subsample above 0.1 mu
-        AFN_TRY(tmp.alloc_n(&v, m));
+        AFN_TRY(tmp.alloc_n(&v, 2 * (int64_t)m));
         AFN_TRY(tmp.alloc_n(&pw, m));
-        AFN_TRY(tmp.alloc_n(&sc, 4));
+        AFN_TRY(tmp.alloc_n(&sc, 8));
         AFN_TRY(tmp.alloc_n(&cnt, 1));
+        AFN_TRY(tmp.alloc_n(&gp, ceil_div(m, 4) + 1));
+        AFN_TRY(tmp.alloc_n(&tdiag, m));
+        AFN_TRY(tmp.alloc_n(&toff, m));
         hipLaunchKernelGGL(gather_scaled, dim3((unsigned)ceil_div((int64_t)m * d, 256)), dim3(256), 0, s,
                            X, sub, m, d, 1.0, Xm);
         hipLaunchKernelGGL(kmat_fill, dim3(gmm), dim3(256), 0, s, Xm, m, d, l2, K);
-        const int splits = 8;
-        AFN_TRY(tmp.alloc_n(&gp, (int64_t)splits * m));
+        hipLaunchKernelGGL(hh_init, dim3(1), dim3(64), 0, s, K, m, v, sc, tdiag, toff);
         for (int j = 0; j + 2 < m; ++j) {
-            const int rows = m - j - 1;
-            const int chunk = (int)ceil_div(rows, splits);
-            hipLaunchKernelGGL(hh_vector, dim3(1), dim3(256), 0, s, K, m, j, v, sc);
-            hipLaunchKernelGGL(hh_matvec, dim3((unsigned)ceil_div(rows, 256), (unsigned)splits),
-                               dim3(256), 0, s, K, m, j, v, chunk, gp);
-            hipLaunchKernelGGL(hh_pw, dim3(1), dim3(256), 0, s, gp, splits, m, j, v, sc, pw);
-            const int64_t upd = (int64_t)rows * rows > m ? (int64_t)rows * rows : m;
-            hipLaunchKernelGGL(hh_update, dim3((unsigned)ceil_div(upd, 256)), dim3(256), 0, s, K, m, j, v,
-                               pw, sc);
+            const int nb = (int)ceil_div(m - j - 1, 4);
+            const int cur = j & 1, nxt = cur ^ 1;
+            hipLaunchKernelGGL(hh_mv, dim3((unsigned)nb), dim3(256), 0, s, K, m, j, v + (int64_t)cur * m,
+                               sc + 4 * cur, pw, gp);
+            hipLaunchKernelGGL(hh_up, dim3((unsigned)nb), dim3(256), 0, s, K, m, j, v + (int64_t)cur * m,
+                               sc + 4 * cur, pw, gp, nb, v + (int64_t)nxt * m, sc + 4 * nxt, tdiag, toff);
         }
-        hipLaunchKernelGGL(sturm_count, dim3(1), dim3(1), 0, s, K, m, 0.1 * mu, cnt);
+        hipLaunchKernelGGL(sturm_count, dim3(1), dim3(1), 0, s, tdiag, toff, m, 0.1 * mu, cnt);
         AFN_HIP(hipGetLastError());
         int hc = 0;
         AFN_HIP(hipMemcpyAsync(&hc, cnt, sizeof(int), hipMemcpyDeviceToHost, s));

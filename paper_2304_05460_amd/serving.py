@@ -118,7 +118,9 @@ class Server:
             res.status = afn.AFN_EDEVICE
             res.error = repr(e)
 
-    def run(self, requests: list[Request]) -> list[Result]:
+    def run(self, requests: list[Request], on_done=None) -> list[Result]:
+        """Serve the requests (arrival times relative to the call); on_done(result)
+        runs on the worker thread after each request finishes."""
         order = sorted(requests, key=lambda q: (q.arrival, q.rid))
         results = {q.rid: Result(q.rid, 0, q.X.shape[0], q.X.shape[1], self.footprint(q),
                                  q.arrival) for q in order}
@@ -143,6 +145,8 @@ class Server:
                 self._work(q, res, streams[sidx])
             finally:
                 finish(q, res, sidx)
+                if on_done is not None:
+                    on_done(res)
 
         threads = []
         with cv:
@@ -182,9 +186,10 @@ class Server:
 
 
 def summarize(results: list[Result]) -> dict:
-    """Throughput and latency percentiles (nearest rank) of completed requests."""
+    """Throughput of converged requests; latency percentiles (nearest rank)
+    over every request that ran, converged or not."""
     ok = [r for r in results if r.status in (afn.AFN_OK,)]
-    lat = sorted(r.latency for r in ok)
+    lat = sorted(r.latency for r in results if r.status != REJECTED)
 
     def pct(p):
         if not lat:
