@@ -54,7 +54,7 @@ def source_hash(path: pathlib.Path) -> str:
 def traffic_from_profile(kernel_src: pathlib.Path):
     """HBM bytes per launch of the tile kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
-    f = ROOT / "profiles" / "kmv_f64_tile_c2_counters.txt"
+    f = ROOT / "profiles" / "kmv_f64_sym_c2_counters.txt"
     if not f.exists():
         return None
     vals = {}
@@ -128,6 +128,99 @@ def cpu_baseline(X, b, l, mu, k, w, iters, n_rows=2000, n_knn=500, n_fsai=6):
     }
 
 
+def _line(metric, value, unit, steps, warmup, ms, dtype, config, **extra):
+    out = {"metric": metric, "value": round(value, 4), "unit": unit, "n_gpus": 1, "steps": steps,
+           "warmup": warmup, "ms_per_step": round(ms, 2), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+    out.update(extra)
+    print(json.dumps(out))
+
+
+def c3_bench(args):
+    """n = 2e5 standard normal points in R^8, l = 2, mu = 1e-2, k = 4000, w = 64:
+    one solve (setup + PCG, maxit 500) in mixed precision and one in FP64 on the
+    same input; reports each path's status, iterations, residual and time."""
+    import torch
+    from paper_2304_05460_amd import afn, workloads as W
+
+    p = W.C3
+    X_np, b_np = W.make(p)
+    X = torch.tensor(X_np, device="cuda")
+    b = torch.tensor(b_np, device="cuda")
+    afn.lib()
+    res = {}
+    for name, prec in (("mixed", afn.AFN_FP32), ("fp64", afn.AFN_FP64)):
+        print(f"[bench] c3 {name}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = afn.afn_setup(X, p.l, p.mu, k=p.k, w=p.w, precision=prec)
+        x, info = afn.afn_pcg_solve(h, b, tol=p.tol, maxit=p.maxit)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        si = h.info()
+        h.close()
+        res[name] = {"seconds": round(t, 3), "status": afn.status_name(info["status"]),
+                     "iterations": info["iterations"], "outer_iterations": info["outer_iterations"],
+                     "relres_true": info["relres_true"], "setup_ms": round(si.ms["total"], 1),
+                     "solve_ms": round(info["ms_solve"], 1),
+                     "kmv_avg_launch_ms": round(info["ms_matvec"] / max(info["matvec_launches"], 1), 3)}
+        print(f"[bench] c3 {name}: {res[name]}", file=sys.stderr, flush=True)
+    _line("AFN-PCG solves/s, mixed precision (FP64 path on the same input beside it)",
+          1.0 / res["mixed"]["seconds"], "solves/s", 1, 0, res["mixed"]["seconds"] * 1e3, "f32+f64",
+          {"workload": p.name, "n": p.n, "d": p.d, "l": p.l, "mu": p.mu, "k": p.k, "w": p.w,
+           "tol": p.tol, "maxit": p.maxit}, c3=res)
+
+
+def c4_bench(args):
+    """n = 1.5e5 uniform in [0,1]^3, l = 0.05, mu = 1e-4, k = 3000, w = 64, 64
+    right-hand sides: FP32 setup + graph-captured block PCG with per-column FP64
+    refinement to rel-res 1e-6.  value = right-hand sides solved per second."""
+    import numpy as np
+    import torch
+    from paper_2304_05460_amd import afn, workloads as W
+
+    p = W.C4
+    X_np, B_np = W.make(p)
+    X = torch.tensor(X_np, device="cuda")
+    B = torch.tensor(np.ascontiguousarray(B_np.T), device="cuda").t()
+    afn.lib()
+    print("[bench] c4 kernel matvec, 64 columns", file=sys.stderr, flush=True)
+    mv = {}
+    for name, prec in (("f32", afn.AFN_FP32), ("f64", afn.AFN_FP64)):
+        afn.kernel_matvec(X, p.l, p.mu, B, precision=prec)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        afn.kernel_matvec(X, p.l, p.mu, B, precision=prec)
+        e1.record()
+        torch.cuda.synchronize()
+        mv[name + "_ms"] = round(e0.elapsed_time(e1), 3)
+    print(f"[bench] c4 setup + block solve", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = afn.afn_setup(X, p.l, p.mu, k=p.k, w=p.w, precision=afn.AFN_FP32)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    x, info = afn.afn_pcg_solve(h, B, tol=p.tol, maxit=p.maxit)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    si = h.info()
+    h.close()
+    R = B.shape[1]
+    n = p.n
+    F = (n * (n - 1) / 2) * (3 * p.d + 1) + 2.0 * n * n * R + 2.0 * n * R
+    _line("right-hand sides solved per second (64 per block, setup included)", R / (t2 - t0),
+          "rhs-solves/s", 1, 0, (t2 - t0) * 1e3, "f32+f64",
+          {"workload": p.name, "n": n, "d": p.d, "l": p.l, "mu": p.mu, "k": p.k, "w": p.w,
+           "tol": p.tol, "nrhs": R},
+          c4={"setup_ms": round((t1 - t0) * 1e3, 1), "solve_ms": round((t2 - t1) * 1e3, 1),
+              "status": afn.status_name(info["status"]), "inner_iterations": info["iterations"],
+              "outer_iterations": info["outer_iterations"], "relres_true_max": info["relres_true"],
+              "setup_phases_ms": {k: round(v, 1) for k, v in si.ms.items()},
+              "kmv_64rhs": dict(mv, tflops_f32=round(F / (mv["f32_ms"] * 1e-3) / 1e12, 2),
+                                 tflops_f64=round(F / (mv["f64_ms"] * 1e-3) / 1e12, 2))})
+
+
 def serving_bench(args):
     """Mixed-size request stream: a burst run (every request at t = 0) gives
     the saturated throughput; a Poisson stream at 0.7 x that rate gives the
@@ -194,8 +287,8 @@ def serving_bench(args):
         "config": {"workload": f"serving_{len(probs)}_requests_n5e3_2e5_d3_8",
                    "slots": args.slots, "poisson_rate_per_s": round(rate, 4),
                    "n_median": int(np.median(ns)), "n_max": int(ns.max())},
-        "poisson": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in sp.items()},
-        "burst": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in sb.items()},
+        "poisson": {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in sp.items()},
+        "burst": {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in sb.items()},
         "statuses": {str(s): int(c) for s, c in
                      zip(*np.unique([r.status for r in pois], return_counts=True))},
     }
@@ -212,6 +305,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision run on the same input")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4"],
+                    help="c2 (default): the solves/s line; c3: mixed vs FP64 at n=2e5, d=8; "
+                         "c4: 64 right-hand sides at n=1.5e5")
     ap.add_argument("--serving", action="store_true",
                     help="run the mixed-size request stream instead (p50/p99 latency, solves/s)")
     ap.add_argument("--serving-count", type=int, default=256)
@@ -240,6 +336,12 @@ def main():
 
     if args.serving:
         serving_bench(args)
+        return
+    if args.workload == "c3":
+        c3_bench(args)
+        return
+    if args.workload == "c4":
+        c4_bench(args)
         return
 
     p = W.c2(args.l, tol=args.tol)

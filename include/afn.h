@@ -24,7 +24,10 @@
  *    boundary.  afn_last_error() returns a thread-local message describing
  *    the last failure on the calling thread.  On failure, outputs other than
  *    those documented are unspecified.
- *  - A handle may be used by one host thread at a time.
+ *  - A handle may be used by one host thread at a time, and its calls must
+ *    not overlap on the device: they share the handle's workspace (use one
+ *    stream per handle, or synchronize between calls on different streams).
+ *    Different handles are independent.
  */
 #ifndef AFN_H
 #define AFN_H
@@ -53,7 +56,11 @@ typedef enum afn_status {
  * iterative refinement: the residual b - (K + mu I) x and the solution are
  * FP64, each correction comes from an inner PCG whose operator, preconditioner
  * apply and vectors are FP32 and whose scalar recurrences are FP64; the
- * factors are built in FP64 (L = chol(K11 + mu I) in FP64) and rounded. */
+ * factors are built in FP64 (L = chol(K11 + mu I) in FP64) and rounded.  If
+ * an inner PCG breaks down (p'Ap <= 0 in FP32), or the refinement stops
+ * halving the residual, or the inner products exceed 4 maxit, the solve
+ * continues with textbook FP64 PCG from the current x (at most maxit more
+ * products), so a mixed solve fails only where the FP64 solve would. */
 typedef enum afn_precision {
     AFN_FP64 = 0,
     AFN_FP32 = 1
@@ -96,6 +103,9 @@ typedef struct afn_solve_info {
                                   from HIP events recorded around each of its launches */
     int32_t matvec_launches;   /* launches timed in ms_matvec                        */
     int32_t outer_iterations;  /* refinement steps of a mixed solve; 0 for FP64      */
+    int32_t fp64_iterations;   /* mixed solve: FP64 PCG products after the FP32
+                                  corrections broke down or stalled (max over rhs)  */
+    int32_t reserved;
 } afn_solve_info;
 
 typedef struct afn_handle afn_handle;
@@ -138,9 +148,12 @@ afn_status afn_apply(afn_handle *h, const double *r_dev, double *z_dev, int32_t 
  * rule) or after maxit products with K + mu I.  A handle set up with
  * precision AFN_FP32 solves by iterative refinement instead: the FP64
  * residual ||b - (K + mu I) x|| / ||b|| is the stopping test, each inner FP32
- * PCG runs at most maxit iterations, and ESTAGNATION is returned when the
- * residual stops decreasing.  b_dev, x_dev: n x nrhs FP64 column-major,
- * leading dimension ld.  info_host may be NULL.  Synchronizes.
+ * PCG runs at most maxit iterations, and the FP64 PCG described under
+ * afn_precision takes over when the FP32 corrections stop working (the
+ * status is then that of the FP64 PCG).  With nrhs >= 2 and d <= 8 the
+ * right-hand sides go through the block solver 64 at a time; a column it
+ * leaves above tol is solved again on its own.  b_dev, x_dev: n x nrhs FP64
+ * column-major, leading dimension ld.  info_host may be NULL.  Synchronizes.
  * Errors: EINVAL (tol <= 0, maxit < 1, nrhs < 1, ld < n), ENOCONV (x holds
  * the last iterate, info valid), EBREAKDOWN, ESTAGNATION, EDEVICE. */
 afn_status afn_pcg_solve(afn_handle *h, const double *b_dev, double *x_dev, int32_t nrhs,

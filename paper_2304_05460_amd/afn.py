@@ -20,6 +20,12 @@ _lib = None
 AFN_OK, AFN_EINVAL, AFN_ENOMEM, AFN_ENOTSPD, AFN_ENOCONV, AFN_EBREAKDOWN, AFN_ESTAGNATION, \
     AFN_EDEVICE = range(8)
 AFN_FP64, AFN_FP32 = 0, 1
+_STATUS_NAMES = ["AFN_OK", "AFN_EINVAL", "AFN_ENOMEM", "AFN_ENOTSPD", "AFN_ENOCONV",
+                 "AFN_EBREAKDOWN", "AFN_ESTAGNATION", "AFN_EDEVICE"]
+
+
+def status_name(status: int) -> str:
+    return _STATUS_NAMES[status] if 0 <= status < len(_STATUS_NAMES) else f"status {status}"
 
 EXPORTED = ["kernel_matvec", "afn_setup", "afn_apply", "afn_pcg_solve", "afn_get_info",
             "afn_get_landmarks", "afn_get_fsai", "afn_get_cholesky", "afn_footprint_bytes",
@@ -55,7 +61,8 @@ class afn_solve_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("relres", ctypes.c_double), ("relres_true", ctypes.c_double),
                 ("ms_solve", ctypes.c_double), ("ms_matvec", ctypes.c_double),
-                ("matvec_launches", ctypes.c_int32), ("outer_iterations", ctypes.c_int32)]
+                ("matvec_launches", ctypes.c_int32), ("outer_iterations", ctypes.c_int32),
+                ("fp64_iterations", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 def lib():
@@ -280,4 +287,4 @@ def afn_pcg_solve(h: Handle, b: torch.Tensor, tol: float = 1e-6, maxit: int = 50
     return out, dict(status=st, iterations=inf.iterations, converged=bool(inf.converged),
                      relres=inf.relres, relres_true=inf.relres_true, ms_solve=inf.ms_solve,
                      ms_matvec=inf.ms_matvec, matvec_launches=inf.matvec_launches,
-                     outer_iterations=inf.outer_iterations)
+                     outer_iterations=inf.outer_iterations, fp64_iterations=inf.fp64_iterations)

@@ -233,7 +233,7 @@ afn_status sub_rows_launch(const double *B, const double *Y, double *Rr, int64_t
 // Block solve (R <= 64, d <= 8, FP32 copies present); see block.hip.
 afn_status block_refine_solve(afn_handle *h, const double *B, int64_t ld, double *Xout, int R,
                               double tol, int maxit, hipStream_t s, int *iters, int *outer,
-                              double *relres_max, int *conv_all);
+                              double *relres_max, int *conv_all, int *col_ok);
 afn_status scale_to_f32_launch(const double *r, const double *inv, float *r32, int64_t n, int R,
                                hipStream_t s);
 afn_status axpy_cols_f32_launch(const double *a, const float *e32, double *x, int64_t n, int R,

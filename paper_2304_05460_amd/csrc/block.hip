@@ -196,7 +196,7 @@ afn_status inner_block(afn_handle *h, int R, int maxit, const BlockWs &w, hipStr
 
 afn_status block_refine_solve(afn_handle *h, const double *B, int64_t ld, double *Xout, int R,
                               double tol, int maxit, hipStream_t user_s, int *iters, int *outer,
-                              double *relres_max, int *conv_all)
+                              double *relres_max, int *conv_all, int *col_ok)
 {
     const int64_t n = h->n;
     const int64_t npad = kmv_packed_doubles(n, h->d) / h->d;
@@ -258,6 +258,7 @@ afn_status block_refine_solve(afn_handle *h, const double *B, int64_t ld, double
     *iters = 0;
     *outer = 0;
     *conv_all = 0;
+    for (int c = 0; c < R; ++c) col_ok[c] = 0;
     afn_status status = AFN_ENOCONV;
     double prev = INFINITY;
     for (int o = 0;; ++o) {
@@ -271,6 +272,7 @@ afn_status block_refine_solve(afn_handle *h, const double *B, int64_t ld, double
             if (!(rel == rel)) worst = NAN;
             else if (rel > worst) worst = rel;
             const bool act = rel > tol;
+            col_ok[c] = act ? 0 : 1;
             nactive += act;
             inv[c] = act ? 1.0 / std::sqrt(rr[c]) : 0.0;
             amul[c] = act ? std::sqrt(rr[c]) : 0.0;

@@ -330,6 +330,63 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     return AFN_OK;
 }
 
+// FP64 PCG iterations from the state x = w.x, r = w.r = b - (K + mu I) x (block
+// order): stops when ||r|| <= tol * bnorm (recurrence residual), on a
+// breakdown, or after maxit products.
+afn_status pcg64_iterate(afn_handle *h, double bnorm, double tol, int maxit, const WorkLayout &w,
+                         hipStream_t s, int *iters, double *relres, double *ms_kmv, int *n_kmv)
+{
+    const int64_t n = h->n;
+    double *sc = w.sc;
+    double *hs = h->host_sc;
+    AFN_TRY(apply_block(h, w.r, w.z, w, s));
+    AFN_HIP(hipMemcpyAsync(w.p, w.z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    AFN_TRY(dot(w.r, n, w.z, n, n, 1, sc + 0, w.dotp, s));
+    *iters = 0;
+    for (int it = 0; it < maxit; ++it) {
+        AFN_TRY(op_f64(h, w.p, w.q, w, s, h->kmv_ev[0], h->kmv_ev[1]));
+        AFN_TRY(dot(w.p, n, w.q, n, n, 1, sc + 1, w.dotp, s));
+        AFN_TRY(pcg_alpha_launch(sc, s));
+        AFN_TRY(pcg_xr_launch(w.x, w.r, w.p, w.q, sc, n, w.dotp, sc + 2, s));
+        AFN_HIP(hipMemcpyAsync(hs + 1, sc + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        AFN_HIP(hipStreamSynchronize(s));
+        {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, h->kmv_ev[0], h->kmv_ev[1]) == hipSuccess) {
+                *ms_kmv += t;
+                *n_kmv += 1;
+            }
+        }
+        *iters = it + 1;
+        const double pq = hs[1];
+        const double rel = std::sqrt(hs[2]) / bnorm;
+        *relres = rel;
+        if (!(pq > 0.0) || !(rel == rel)) {
+            set_error("afn_pcg_solve: breakdown at iteration %d (p'Ap = %g)", it + 1, pq);
+            return AFN_EBREAKDOWN;
+        }
+        if (rel <= tol) return AFN_OK;
+        AFN_TRY(apply_block(h, w.r, w.z, w, s));
+        AFN_TRY(dot(w.r, n, w.z, n, n, 1, sc + 3, w.dotp, s));
+        AFN_TRY(pcg_beta_launch(sc, s));
+        AFN_TRY(pcg_p_launch(w.p, w.z, sc, n, s));
+    }
+    return AFN_ENOCONV;
+}
+
+// ||b - (K + mu I) x|| / bnorm in FP64 (block order; w.tmp clobbered).
+afn_status true_relres(afn_handle *h, double bnorm, const WorkLayout &w, hipStream_t s, double *out)
+{
+    const int64_t n = h->n;
+    AFN_TRY(op_f64(h, w.x, w.q, w, s));
+    AFN_TRY(sub_launch(w.bp, w.q, w.tmp, n, s));
+    AFN_TRY(dot(w.tmp, n, w.tmp, n, n, 1, w.sc + 7, w.dotp, s));
+    AFN_HIP(hipMemcpyAsync(h->host_sc + 7, w.sc + 7, sizeof(double), hipMemcpyDeviceToHost, s));
+    AFN_HIP(hipStreamSynchronize(s));
+    *out = std::sqrt(h->host_sc[7]) / bnorm;
+    return AFN_OK;
+}
+
 afn_status pcg_one(afn_handle *h, const double *b, double *xout, double tol, int maxit,
                    const WorkLayout &w, hipStream_t s, int *iters, double *relres,
                    double *relres_true, int *converged, double *ms_kmv, int *n_kmv)
@@ -359,53 +416,13 @@ afn_status pcg_one(afn_handle *h, const double *b, double *xout, double tol, int
         AFN_TRY(permute_scatter(w.x, n, xout, n, h->perm, n, 1, s));
         return AFN_OK;
     }
-    AFN_TRY(apply_block(h, w.r, w.z, w, s));
-    AFN_HIP(hipMemcpyAsync(w.p, w.z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    AFN_TRY(dot(w.r, n, w.z, n, n, 1, sc + 0, w.dotp, s));
-    afn_status status = AFN_ENOCONV;
     *converged = 0;
     *relres = 1.0;
-    for (int it = 0; it < maxit; ++it) {
-        AFN_TRY(op_f64(h, w.p, w.q, w, s, h->kmv_ev[0], h->kmv_ev[1]));
-        AFN_TRY(dot(w.p, n, w.q, n, n, 1, sc + 1, w.dotp, s));
-        AFN_TRY(pcg_alpha_launch(sc, s));
-        AFN_TRY(pcg_xr_launch(w.x, w.r, w.p, w.q, sc, n, w.dotp, sc + 2, s));
-        AFN_HIP(hipMemcpyAsync(hs + 1, sc + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-        AFN_HIP(hipStreamSynchronize(s));
-        {
-            float t = 0.f;
-            if (hipEventElapsedTime(&t, h->kmv_ev[0], h->kmv_ev[1]) == hipSuccess) {
-                *ms_kmv += t;
-                *n_kmv += 1;
-            }
-        }
-        *iters = it + 1;
-        const double pq = hs[1];
-        const double rel = std::sqrt(hs[2]) / bnorm;
-        *relres = rel;
-        if (!(pq > 0.0) || !(rel == rel)) {
-            set_error("afn_pcg_solve: breakdown at iteration %d (p'Ap = %g)", it + 1, pq);
-            status = AFN_EBREAKDOWN;
-            break;
-        }
-        if (rel <= tol) {
-            status = AFN_OK;
-            *converged = 1;
-            break;
-        }
-        AFN_TRY(apply_block(h, w.r, w.z, w, s));
-        AFN_TRY(dot(w.r, n, w.z, n, n, 1, sc + 3, w.dotp, s));
-        AFN_TRY(pcg_beta_launch(sc, s));
-        AFN_TRY(pcg_p_launch(w.p, w.z, sc, n, s));
-    }
-    // true residual in FP64
-    AFN_TRY(op_f64(h, w.x, w.q, w, s));
-    AFN_TRY(sub_launch(w.bp, w.q, w.tmp, n, s));
-    AFN_TRY(dot(w.tmp, n, w.tmp, n, n, 1, sc + 7, w.dotp, s));
-    AFN_HIP(hipMemcpyAsync(hs + 7, sc + 7, sizeof(double), hipMemcpyDeviceToHost, s));
+    const afn_status status = pcg64_iterate(h, bnorm, tol, maxit, w, s, iters, relres, ms_kmv, n_kmv);
+    *converged = status == AFN_OK ? 1 : 0;
+    AFN_TRY(true_relres(h, bnorm, w, s, relres_true));
     AFN_TRY(permute_scatter(w.x, n, xout, n, h->perm, n, 1, s));
     AFN_HIP(hipStreamSynchronize(s));
-    *relres_true = std::sqrt(hs[7]) / bnorm;
     if (status == AFN_ENOCONV)
         set_error("afn_pcg_solve: no convergence in %d iterations (relres %g)", maxit, *relres);
     return status;
@@ -460,9 +477,10 @@ afn_status pcg_inner32(afn_handle *h, double r0norm, double tol_in, int maxit, c
 // from the FP32 inner PCG on r / ||r||; stop when ||r|| / ||b|| <= tol.
 afn_status pcg_refine(afn_handle *h, const double *b, double *xout, double tol, int maxit,
                       const WorkLayout &w, const WorkLayout32 &w32, hipStream_t s, int *iters,
-                      int *outer, double *relres, double *relres_true, int *converged,
+                      int *outer, int *iters64, double *relres, double *relres_true, int *converged,
                       double *ms_kmv, int *n_kmv)
 {
+    *iters64 = 0;
     const int64_t n = h->n;
     double *sc = w.sc;
     double *hs = h->host_sc;
@@ -492,12 +510,22 @@ afn_status pcg_refine(afn_handle *h, const double *b, double *xout, double tol, 
     afn_status status = AFN_ENOCONV;
     double prev = INFINITY;
     const int max_outer = 40;
+    bool fallback = false;     // the FP32 corrections stopped helping: finish in FP64
     for (int o = 0;; ++o) {
         AFN_TRY(dot(w.r, n, w.r, n, n, 1, sc + 7, w.dotp, s));
         AFN_HIP(hipMemcpyAsync(hs + 7, sc + 7, sizeof(double), hipMemcpyDeviceToHost, s));
         AFN_HIP(hipStreamSynchronize(s));
-        const double rnorm = std::sqrt(hs[7]);
-        const double rel = rnorm / bnorm;
+        double rnorm = std::sqrt(hs[7]);
+        double rel = rnorm / bnorm;
+        if (o > 0 && !(rel <= prev)) {
+            // the last FP32 correction made things worse: take it back (x and
+            // its residual were kept in rp / sp) and finish in FP64
+            AFN_HIP(hipMemcpyAsync(w.x, w.rp, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+            AFN_HIP(hipMemcpyAsync(w.r, w.sp, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+            rel = prev;
+            rnorm = prev * bnorm;
+            fallback = true;
+        }
         *relres = rel;
         *relres_true = rel;
         if (!(rel == rel)) {
@@ -510,18 +538,32 @@ afn_status pcg_refine(afn_handle *h, const double *b, double *xout, double tol, 
             *converged = 1;
             break;
         }
-        if (o >= max_outer || (o >= 3 && rel > 0.5 * prev)) {
-            set_error("afn_pcg_solve: refinement stagnated at relative residual %g after %d steps",
-                      rel, o);
-            status = AFN_ESTAGNATION;
-            break;
-        }
-        if (*iters >= maxit * 4) {
-            set_error("afn_pcg_solve: no convergence (relres %g)", rel);
-            status = AFN_ENOCONV;
+        if (o >= max_outer || (o >= 3 && rel > 0.5 * prev) || *iters >= maxit * 4) fallback = true;
+        if (fallback) {
+            // textbook FP64 PCG from the current x and its FP64 residual
+            int it64 = 0;
+            double rel64 = rel;
+            const afn_status st64 =
+                pcg64_iterate(h, bnorm, tol, maxit, w, s, &it64, &rel64, ms_kmv, n_kmv);
+            *iters64 = it64;
+            *outer = o + 1;
+            double rt = 0.0;
+            AFN_TRY(true_relres(h, bnorm, w, s, &rt));
+            *relres = rel64;
+            *relres_true = rt;
+            if (st64 == AFN_OK) {
+                status = AFN_OK;
+                *converged = 1;
+            } else {
+                status = st64;
+                if (st64 == AFN_ENOCONV)
+                    set_error("afn_pcg_solve: no convergence (FP64 after refinement, relres %g)", rel64);
+            }
             break;
         }
         prev = rel;
+        AFN_HIP(hipMemcpyAsync(w.rp, w.x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        AFN_HIP(hipMemcpyAsync(w.sp, w.r, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
         // inner tolerance: what this step needs, but at least 1e-4 of its start
         double tol_in = 0.5 * tol / rel;
         tol_in = tol_in > 1e-4 ? tol_in : 1e-4;
@@ -533,6 +575,12 @@ afn_status pcg_refine(afn_handle *h, const double *b, double *xout, double tol, 
                                     ms_kmv, n_kmv);
         *iters += it;
         *outer = o + 1;
+        if (st == AFN_EBREAKDOWN) {
+            // the FP32 operator or apply lost definiteness: redo this step in FP64
+            fallback = true;
+            --o;
+            continue;
+        }
         if (st != AFN_OK) {
             status = st;
             break;
@@ -620,39 +668,50 @@ afn_status afn_pcg_solve(afn_handle *h, const double *b_dev, double *x_dev, int3
     if (h->precision == AFN_FP32) work32_floats(h->n, h->d, h->k, h->nr, &w32, h->work32);
     Timer tm;
     tm.mark(0, s);
-    int outer_max = 0;
+    int outer_max = 0, it64_max = 0;
     afn_status worst = AFN_OK;
     int it_max = 0, conv_all = 1, n_kmv = 0;
     double ms_kmv = 0.0;
     double rel_max = 0.0, true_max = 0.0;
+    // columns still to solve one at a time (all of them outside the block path)
+    std::vector<int> single;
     if (nrhs >= 2 && h->precision == AFN_FP32 && h->d <= 8) {
+        std::vector<int> col_ok(64);
         for (int c0 = 0; c0 < nrhs; c0 += 64) {
             const int Rc = nrhs - c0 < 64 ? nrhs - c0 : 64;
             int it = 0, outer = 0, conv = 0;
             double rel = 0.0;
             afn_status st = block_refine_solve(h, b_dev + c0 * ld, ld, x_dev + c0 * ld, Rc, tol, maxit,
-                                               s, &it, &outer, &rel, &conv);
+                                               s, &it, &outer, &rel, &conv, col_ok.data());
             if (st != AFN_OK && st != AFN_ENOCONV && st != AFN_EBREAKDOWN && st != AFN_ESTAGNATION)
                 return st;
-            if (st != AFN_OK && (worst == AFN_OK || st == AFN_EBREAKDOWN)) worst = st;
             it_max = it > it_max ? it : it_max;
             outer_max = outer > outer_max ? outer : outer_max;
-            conv_all &= conv;
-            rel_max = rel > rel_max || rel != rel ? rel : rel_max;
+            for (int c = 0; c < Rc; ++c) {
+                if (col_ok[c]) continue;
+                if (st == AFN_OK) continue;
+                single.push_back(c0 + c);   // re-solved below (refinement with FP64 fallback)
+            }
+            if (st == AFN_OK) rel_max = rel > rel_max || rel != rel ? rel : rel_max;
+            else
+                for (int c = 0; c < Rc; ++c)
+                    if (col_ok[c]) rel_max = rel_max > tol ? rel_max : tol;
         }
         true_max = rel_max;
-        nrhs = 0;   // done
+    } else {
+        for (int c = 0; c < nrhs; ++c) single.push_back(c);
     }
-    for (int c = 0; c < nrhs; ++c) {
-        int it = 0, conv = 0, outer = 0;
+    for (const int c : single) {
+        int it = 0, conv = 0, outer = 0, it64 = 0;
         double rel = 0, rt = 0;
         afn_status st =
             h->precision == AFN_FP32
                 ? pcg_refine(h, b_dev + c * ld, x_dev + c * ld, tol, maxit, w, w32, s, &it, &outer,
-                             &rel, &rt, &conv, &ms_kmv, &n_kmv)
+                             &it64, &rel, &rt, &conv, &ms_kmv, &n_kmv)
                 : pcg_one(h, b_dev + c * ld, x_dev + c * ld, tol, maxit, w, s, &it, &rel, &rt, &conv,
                           &ms_kmv, &n_kmv);
         outer_max = outer > outer_max ? outer : outer_max;
+        it64_max = it64 > it64_max ? it64 : it64_max;
         if (st != AFN_OK && st != AFN_ENOCONV && st != AFN_EBREAKDOWN && st != AFN_ESTAGNATION)
             return st;
         if (st != AFN_OK && worst == AFN_OK) worst = st;
@@ -673,6 +732,8 @@ afn_status afn_pcg_solve(afn_handle *h, const double *b_dev, double *x_dev, int3
         info->ms_matvec = ms_kmv;
         info->matvec_launches = n_kmv;
         info->outer_iterations = outer_max;
+        info->fp64_iterations = it64_max;
+        info->reserved = 0;
     }
     return worst;
 }

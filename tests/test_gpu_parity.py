@@ -505,3 +505,32 @@ def test_block_solve_column_equals_single_solve(afn, block_case):
     rel = (torch.linalg.norm(xb[:, 5] - xs) / torch.linalg.norm(xs)).item()
     say("block column vs single solve", rel)
     assert rel <= 1e-6
+
+
+# ------------------------------------------------------------------ mixed precision: FP64 fallback
+
+@pytest.mark.parametrize("n,l,mu,k,tol", [(4000, 0.5, 1e-8, 200, 1e-6), (2000, 0.3, 1e-6, 100, 1e-10),
+                                          (3000, 1.0, 1e-6, 150, 1e-8)])
+def test_mixed_falls_back_to_fp64(afn, n, l, mu, k, tol):
+    """Where the FP32 corrections break down or stop reducing the residual,
+    the mixed solve finishes with FP64 PCG and ends no worse than the FP64
+    solve of the same system (same status; true residual within 10x)."""
+    X = W.points("uniform", n, 3, 61)
+    b = np.random.default_rng(62).standard_normal(n)
+    res = {}
+    for prec in (afn.AFN_FP32, afn.AFN_FP64):
+        h = afn.afn_setup(dev(X), l, mu, k=k, w=32, precision=prec)
+        x, info = afn.afn_pcg_solve(h, dev(b), tol=tol, maxit=400)
+        h.close()
+        xh = x.cpu().numpy()
+        y, ab = oracle.kernel_matvec_rows(X, l, mu, xh, np.arange(n))
+        r = b - y
+        # rounding floor of any FP64 evaluation of ||b - A x|| / ||b||
+        floor = 2 * (n + 4) * U * np.linalg.norm(ab) / np.linalg.norm(b)
+        res[prec] = (info, np.linalg.norm(r) / np.linalg.norm(b), floor)
+        say(f"fallback n={n} l={l} mu={mu} prec={prec}", info, res[prec][1:])
+    (i32, t32, f32), (i64, t64, f64) = res[afn.AFN_FP32], res[afn.AFN_FP64]
+    assert i32["fp64_iterations"] > 0
+    assert i32["status"] == i64["status"]
+    assert t32 <= max(10.0 * t64, tol)
+    assert abs(i32["relres_true"] - t32) <= 1e-3 * t32 + f32
