@@ -64,16 +64,31 @@ afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, const
                    hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // Pre-scaled SoA copy of the points for the symmetric tile kernels
 // (kmv_packed_doubles(n, d) doubles, or as many floats when f32).
+// perm (optional): packed position q holds point perm[q] (vectors stay in
+// the caller's order and are indexed through perm).
 int64_t kmv_packed_doubles(int64_t n, int d);
-afn_status kmv_pack(const double *X, int64_t n, int d, double l, void *Xs, bool f32, hipStream_t s);
+afn_status kmv_pack(const double *X, int64_t n, int d, double l, void *Xs, bool f32, hipStream_t s,
+                    const int32_t *perm = nullptr);
+// Tile pruning.  Per 64-point tile of the packed layout, the box of its
+// scaled coordinates (kmv_box_count(n, d) values of the packed type).  A pair
+// of tiles whose boxes are at least sqrt(cut) apart in scaled units holds only
+// kernel values below 2^-cut and is skipped: cut = kCullF64 for FP64 tiles,
+// kCullF32 for FP32 tiles.  The dropped part of row i is below
+// 2^-cut sum_j |v_j|.
+constexpr double kCullF64 = 64.0;
+constexpr double kCullF32 = 44.0;
+int64_t kmv_box_count(int64_t n, int d);
+afn_status kmv_boxes(const void *Xs, int64_t n, int d, bool f32, void *box, hipStream_t s);
 // y = (K + mu I) v on packed points (d <= 8); part: kmv_workspace_doubles(n, d)
-// doubles (or floats for the FP32 variant).
+// doubles (or floats for the FP32 variant).  box (optional) enables pruning.
 afn_status kmv_packed_f64(const double *Xs, int64_t n, int d, double mu, const double *v, int64_t ldv,
                           double *y, int64_t ldy, int nrhs, double *part, hipStream_t s,
-                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                          const int32_t *perm = nullptr, const double *box = nullptr);
 afn_status kmv_packed_f32(const float *Xs, int64_t n, int d, double mu, const float *v, int64_t ldv,
                           float *y, int64_t ldy, int nrhs, float *part, hipStream_t s,
-                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                          const int32_t *perm = nullptr, const float *box = nullptr);
 // FP32 tiles and accumulation; FP64 vectors at the interface.
 afn_status kmv_f32(const double *X, int64_t n, int d, double l, double mu, const double *v,
                    int64_t ldv, double *y, int64_t ldy, int nrhs, void *work, hipStream_t s);
@@ -125,10 +140,13 @@ afn_status identity(double *A, int k, hipStream_t s);
 afn_status fsai_rows(const double *Xp, int64_t n, int k, int d, double l, double mu,
                      const double *V, const int32_t *cols, int w, double *gval, int *info_dev,
                      const int32_t *order, hipStream_t s);
-// A spatially coherent processing order of the rows (Morton order of grid
-// cells over the points Xr, nr x d); work: fsai_order_work_bytes(nr, d).
-size_t fsai_order_work_bytes(int64_t nr, int d);
-afn_status fsai_row_order(const double *Xr, int64_t nr, int d, int32_t *order, void *work, hipStream_t s);
+
+// ---------------------------------------------------------------- spatial order
+// order[q] = index of the point at position q: Morton order of grid cells over
+// the points X (n x d row-major), ascending index inside a cell.
+// Deterministic.  work: spatial_order_work_bytes(n, d).
+size_t spatial_order_work_bytes(int64_t n, int d);
+afn_status spatial_order(const double *X, int64_t n, int d, int32_t *order, void *work, hipStream_t s);
 // CSR of G^T: tptr (nr+1), trow/tval (nnz), rows of each column ascending.
 // work: fsai_transpose_work_bytes(nr, w) bytes.
 size_t fsai_transpose_work_bytes(int64_t nr, int w);
@@ -193,7 +211,8 @@ int64_t mrhs_part_elems(int64_t npad);
 template <typename T>
 afn_status kmv_mrhs_run(const T *Xs, int64_t npad, int64_t n, int d, double mu, const T *P,
                         int64_t ldp, T *Y, int64_t ldy, int R, T *part, hipStream_t s,
-                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
+                        const int32_t *perm = nullptr, const T *box = nullptr);
 int gemm_splits(int64_t m, int64_t K);
 int64_t gemm_part_elems(int64_t m, int64_t K);
 template <typename T>
@@ -264,7 +283,11 @@ struct afn_handle {
     double *work = nullptr;     // PCG / apply workspace
     int64_t work_doubles = 0;
     int64_t work_rhs = 0;       // right-hand sides the workspace is sized for
-    double *Xs64 = nullptr;     // points pre-scaled for the symmetric tile kernel (d <= 8)
+    double *Xs64 = nullptr;     // points pre-scaled for the symmetric tile kernel (d <= 8),
+                                // in the spatial order kperm, with per-tile boxes box64
+    int32_t *kperm = nullptr;   // packed position -> block index
+    double *box64 = nullptr;
+    float *box32 = nullptr;
     int precision = AFN_FP64;   // AFN_FP32: inner PCG in FP32 inside FP64 refinement
     float *Xs32 = nullptr;      // FP32 copies for the inner solve
     float *Linv32 = nullptr;

@@ -164,7 +164,8 @@ afn_status op_f64(afn_handle *h, const double *v, double *y, const WorkLayout &w
                   hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
     if (h->Xs64)
-        return kmv_packed_f64(h->Xs64, h->n, h->d, h->mu, v, h->n, y, h->n, 1, w.kmv, s, e0, e1);
+        return kmv_packed_f64(h->Xs64, h->n, h->d, h->mu, v, h->n, y, h->n, 1, w.kmv, s, e0, e1, h->kperm,
+                              h->box64);
     return kmv_f64(h->Xp, h->n, h->d, h->l, h->mu, v, h->n, y, h->n, 1, w.kmv, s, e0, e1);
 }
 
@@ -267,8 +268,8 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
         int32_t *rorder = nullptr;
         void *ows = nullptr;
         AFN_TRY(tmp.alloc_n(&rorder, nr));
-        AFN_TRY(tmp.alloc(&ows, fsai_order_work_bytes(nr, d)));
-        AFN_TRY(fsai_row_order(h->Xp + (int64_t)k * d, nr, d, rorder, ows, s));
+        AFN_TRY(tmp.alloc(&ows, spatial_order_work_bytes(nr, d)));
+        AFN_TRY(spatial_order(h->Xp + (int64_t)k * d, nr, d, rorder, ows, s));
         AFN_TRY(fsai_rows(h->Xp, n, k, d, l, mu, h->V, h->cols, h->w, h->gval, h->flags + 2, rorder, s));
         AFN_TRY(h->arena.alloc_n(&h->tptr, nr + 1));
         AFN_TRY(h->arena.alloc_n(&h->trow, nr * h->w));
@@ -281,12 +282,22 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     // points packed for the symmetric tile kernel; FP32 copies for mixed solves
     h->precision = prm->precision;
     if (d <= 8) {
+        // spatial order of all points for the tile kernels: far-apart tile
+        // pairs (kernel values below 2^-cut) are skipped
+        void *kws = nullptr;
+        AFN_TRY(h->arena.alloc_n(&h->kperm, n));
+        AFN_TRY(tmp.alloc(&kws, spatial_order_work_bytes(n, d)));
+        AFN_TRY(spatial_order(h->Xp, n, d, h->kperm, kws, s));
         AFN_TRY(h->arena.alloc_n(&h->Xs64, kmv_packed_doubles(n, d)));
-        AFN_TRY(kmv_pack(h->Xp, n, d, l, h->Xs64, false, s));
+        AFN_TRY(kmv_pack(h->Xp, n, d, l, h->Xs64, false, s, h->kperm));
+        AFN_TRY(h->arena.alloc_n(&h->box64, kmv_box_count(n, d)));
+        AFN_TRY(kmv_boxes(h->Xs64, n, d, false, h->box64, s));
     }
     if (h->precision == AFN_FP32) {
         AFN_TRY(h->arena.alloc_n(&h->Xs32, kmv_packed_doubles(n, d)));
-        AFN_TRY(kmv_pack(h->Xp, n, d, l, h->Xs32, true, s));
+        AFN_TRY(kmv_pack(h->Xp, n, d, l, h->Xs32, true, s, h->kperm));
+        AFN_TRY(h->arena.alloc_n(&h->box32, kmv_box_count(n, d)));
+        AFN_TRY(kmv_boxes(h->Xs32, n, d, true, h->box32, s));
         if (k > 0) {
             AFN_TRY(h->arena.alloc_n(&h->Linv32, (int64_t)k * k));
             AFN_TRY(to_f32_launch(h->Linv, h->Linv32, (int64_t)k * k, s));
@@ -445,7 +456,7 @@ afn_status pcg_inner32(afn_handle *h, double r0norm, double tol_in, int maxit, c
     *rel_out = 1.0;
     for (int it = 0; it < maxit; ++it) {
         AFN_TRY(kmv_packed_f32(h->Xs32, n, h->d, h->mu, w.p, n, w.q, n, 1, w.kmv, s, h->kmv_ev[0],
-                               h->kmv_ev[1]));
+                               h->kmv_ev[1], h->kperm, h->box32));
         AFN_TRY(dot(w.p, n, w.q, n, n, 1, sc + 1, dotp, s));
         AFN_TRY(pcg_alpha_launch(sc, s));
         AFN_TRY(pcg_xr_launch(w.e, w.r, w.p, w.q, sc, n, dotp, sc + 2, s));
@@ -823,9 +834,10 @@ afn_status afn_footprint_bytes(int64_t n, int32_t d, const afn_params *prm, size
     if (k > 0) t += 2 * r(8 * k * k) + r(8 * dinv_doubles((int)k));       // L, Linv, Dinv
     if (nr > 0) t += r(4 * nr * w) + r(8 * nr * w) + r(8 * (nr + 1)) + r(4 * nr * w) + r(8 * nr * w);
     if (k > 0 && nr > 0) t += r(8 * k * nr);                               // V
-    if (d <= 8) t += r(8 * kmv_packed_doubles(n, d));                     // Xs64
+    if (d <= 8) t += r(8 * kmv_packed_doubles(n, d)) + r(4 * n) + r(8 * kmv_box_count(n, d));  // Xs64, kperm, box64
     if (f32) {
-        t += r(4 * kmv_packed_doubles(n, d)) + r(4 * k * k) + r(4 * k * nr) + 2 * r(4 * nr * w);
+        t += r(4 * kmv_packed_doubles(n, d)) + r(4 * kmv_box_count(n, d)) + r(4 * k * k) + r(4 * k * nr) +
+             2 * r(4 * nr * w);
         t += r(4 * work32_floats(n, d, (int)k, nr, nullptr, nullptr));
     }
     t += r(8 * work_doubles(n, d, (int)k, nr, nullptr, nullptr));
@@ -833,7 +845,7 @@ afn_status afn_footprint_bytes(int64_t n, int32_t d, const afn_params *prm, size
     // counters, and the rank-estimation buffers (K_m and its companions)
     size_t tmp = r(4 * k) + (size_t)fps_workspace_bytes(n) + r(4 * n) +
                  r((int64_t)fsai_transpose_work_bytes(nr, prm->w)) + r(4 * nr) +
-                 r((int64_t)fsai_order_work_bytes(nr, d));
+                 r((int64_t)spatial_order_work_bytes(n, d));
     if (prm->k < 0) {
         const int64_t m = prm->m > 0 ? (prm->m < n ? prm->m : n) : (n < 2000 ? n : 2000);
         tmp += r(8 * m * m) + r(8 * m * (d + 16)) + (size_t)fps_workspace_bytes(m) + r(8 * 8 * m);

@@ -189,90 +189,6 @@ __global__ __launch_bounds__(64) void fsai_row_mfma(const double *__restrict__ X
     if (lane < w) gval[p * w + lane] = lane < m ? g : 0.0;
 }
 
-// ---------------------------------------------------------------- row order
-// Rows of G are independent; processing them in Morton order of a coarse grid
-// of cells (at most 2^18) makes concurrently running rows share pattern
-// columns.  Bounding box by two-stage min/max, cell keys, counting sort (the
-// order inside a cell is arbitrary: it changes no result).
-constexpr int kCellBits = 18;
-
-__host__ __device__ inline void cell_shape(int d, int &bits, int &dims)
-{
-    bits = kCellBits / d > 0 ? kCellBits / d : 1;
-    if (bits > 16) bits = 16;
-    dims = kCellBits / bits < d ? kCellBits / bits : d;
-}
-
-__global__ __launch_bounds__(256) void bbox_partial(const double *Xr, int64_t nr, int d, int dims,
-                                                    double *part)
-{
-    __shared__ double lo[256], hi[256];
-    for (int t = 0; t < dims; ++t) {
-        double a = __builtin_inf(), b = -__builtin_inf();
-        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nr; i += (int64_t)gridDim.x * 256) {
-            const double x = Xr[i * d + t];
-            a = x < a ? x : a;
-            b = x > b ? x : b;
-        }
-        lo[threadIdx.x] = a;
-        hi[threadIdx.x] = b;
-        __syncthreads();
-        for (int h = 128; h > 0; h >>= 1) {
-            if (threadIdx.x < h) {
-                lo[threadIdx.x] = lo[threadIdx.x + h] < lo[threadIdx.x] ? lo[threadIdx.x + h] : lo[threadIdx.x];
-                hi[threadIdx.x] = hi[threadIdx.x + h] > hi[threadIdx.x] ? hi[threadIdx.x + h] : hi[threadIdx.x];
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            part[(blockIdx.x * dims + t) * 2] = lo[0];
-            part[(blockIdx.x * dims + t) * 2 + 1] = hi[0];
-        }
-        __syncthreads();
-    }
-}
-
-__global__ __launch_bounds__(64) void bbox_final(const double *part, int nb, int dims, double *box)
-{
-    const int t = threadIdx.x;
-    if (t >= dims) return;
-    double a = __builtin_inf(), b = -__builtin_inf();
-    for (int g = 0; g < nb; ++g) {
-        const double x = part[(g * dims + t) * 2], y = part[(g * dims + t) * 2 + 1];
-        a = x < a ? x : a;
-        b = y > b ? y : b;
-    }
-    box[2 * t] = a;
-    box[2 * t + 1] = b;
-}
-
-__global__ __launch_bounds__(256) void cell_keys(const double *Xr, int64_t nr, int d, int bits, int dims,
-                                                 const double *box, int32_t *key, unsigned long long *cnt)
-{
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= nr) return;
-    const int cells1 = 1 << bits;
-    uint32_t kk = 0;
-    for (int t = 0; t < dims; ++t) {
-        const double lo = box[2 * t], span = box[2 * t + 1] - lo;
-        int q = span > 0.0 ? (int)((Xr[i * d + t] - lo) / span * cells1) : 0;
-        q = q < 0 ? 0 : (q >= cells1 ? cells1 - 1 : q);
-        for (int bb = 0; bb < bits; ++bb) kk |= (uint32_t)((q >> bb) & 1) << (bb * dims + t);
-    }
-    key[i] = (int32_t)kk;
-    atomicAdd(&cnt[kk], 1ULL);
-}
-
-__global__ __launch_bounds__(256) void cell_scatter(const int32_t *key, int64_t nr, const int64_t *start,
-                                                    unsigned long long *cursor, int32_t *order)
-{
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= nr) return;
-    const int32_t kk = key[i];
-    const unsigned long long pos = atomicAdd(&cursor[kk], 1ULL);
-    order[start[kk] + (int64_t)pos] = (int32_t)i;
-}
-
 __global__ __launch_bounds__(256) void count_cols(const int32_t *cols, int64_t nr, int w,
                                                   unsigned long long *cnt)
 {
@@ -354,46 +270,6 @@ __global__ __launch_bounds__(256) void place_sorted(const int64_t *__restrict__ 
 }
 
 }  // namespace
-
-size_t fsai_order_work_bytes(int64_t nr, int d)
-{
-    int bits, dims;
-    cell_shape(d, bits, dims);
-    const int64_t cells = (int64_t)1 << (bits * dims);
-    return (size_t)(round_up(8 * 256 * 2 * dims, 256) + round_up(8 * 2 * dims, 256) +
-                    round_up(4 * (nr > 0 ? nr : 1), 256) + round_up(8 * cells, 256) +
-                    round_up(8 * (cells + 1), 256));
-}
-
-afn_status fsai_row_order(const double *Xr, int64_t nr, int d, int32_t *order, void *work, hipStream_t s)
-{
-    if (nr <= 0) return AFN_OK;
-    int bits, dims;
-    cell_shape(d, bits, dims);
-    const int64_t cells = (int64_t)1 << (bits * dims);
-    char *q = (char *)work;
-    auto take = [&](int64_t bytes) {
-        char *r = q;
-        q += round_up(bytes, 256);
-        return r;
-    };
-    double *part = (double *)take(8 * 256 * 2 * dims);
-    double *box = (double *)take(8 * 2 * dims);
-    int32_t *key = (int32_t *)take(4 * nr);
-    unsigned long long *cnt = (unsigned long long *)take(8 * cells);
-    int64_t *start = (int64_t *)take(8 * (cells + 1));
-    const int nb = (int)(ceil_div(nr, 256) < 256 ? ceil_div(nr, 256) : 256);
-    const unsigned g = (unsigned)ceil_div(nr, 256);
-    hipLaunchKernelGGL(bbox_partial, dim3(nb), dim3(256), 0, s, Xr, nr, d, dims, part);
-    hipLaunchKernelGGL(bbox_final, dim3(1), dim3(64), 0, s, part, nb, dims, box);
-    AFN_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * (size_t)cells, s));
-    hipLaunchKernelGGL(cell_keys, dim3(g), dim3(256), 0, s, Xr, nr, d, bits, dims, box, key, cnt);
-    hipLaunchKernelGGL(scan_counts, dim3(1), dim3(1024), 0, s, cnt, cells, start);
-    AFN_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * (size_t)cells, s));
-    hipLaunchKernelGGL(cell_scatter, dim3(g), dim3(256), 0, s, key, nr, start, cnt, order);
-    AFN_HIP(hipGetLastError());
-    return AFN_OK;
-}
 
 afn_status fsai_rows(const double *Xp, int64_t n, int k, int d, double l, double mu,
                      const double *V, const int32_t *cols, int w, double *gval, int *info,

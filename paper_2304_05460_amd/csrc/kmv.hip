@@ -52,16 +52,19 @@ __device__ __forceinline__ double exp2_neg(double t)
     return __builtin_ldexp(p, (int)(-kd));
 }
 
-// Xs[t * npad + i] = X[i*d + t] * scale for i < n, 0 beyond (rounded to T).
+// Xs[t * npad + q] = X[perm[q]*d + t] * scale for q < n (perm may be null:
+// identity), 0 beyond (rounded to T).
 template <typename T>
-__global__ __launch_bounds__(256) void pack_scaled(const double *__restrict__ X, int64_t n, int d,
+__global__ __launch_bounds__(256) void pack_scaled(const double *__restrict__ X,
+                                                   const int32_t *__restrict__ perm, int64_t n, int d,
                                                    int64_t npad, double scale, T *__restrict__ Xs)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= npad * d) return;
     const int t = (int)(e / npad);
-    const int64_t i = e - (int64_t)t * npad;
-    Xs[e] = (T)(i < n ? X[i * d + t] * scale : 0.0);
+    const int64_t q = e - (int64_t)t * npad;
+    const int64_t i = q < n ? (perm ? (int64_t)perm[q] : q) : 0;
+    Xs[e] = (T)(q < n ? X[i * d + t] * scale : 0.0);
 }
 
 // 2^(-t) in FP32 with the hardware base-2 exponential.
@@ -69,6 +72,45 @@ __device__ __forceinline__ float exp2_neg(float t) { return __builtin_amdgcn_exp
 
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// box[(tile * d + t) * 2 + {0, 1}] = min / max of the packed coordinate t over
+// the valid points of the 64-point tile; an empty tile gets [+inf, -inf].
+template <typename T>
+__global__ __launch_bounds__(256) void tile_boxes(const T *__restrict__ Xs, int64_t npad, int64_t n, int d,
+                                                  T *__restrict__ box)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ntiles = npad / kTile;
+    if (e >= ntiles * d) return;
+    const int64_t tile = e / d;
+    const int t = (int)(e - tile * d);
+    T lo = (T)__builtin_inf(), hi = -(T)__builtin_inf();
+    for (int j = 0; j < kTile; ++j) {
+        const int64_t q = tile * kTile + j;
+        if (q >= n) break;
+        const T x = Xs[(int64_t)t * npad + q];
+        lo = x < lo ? x : lo;
+        hi = x > hi ? x : hi;
+    }
+    box[e * 2] = lo;
+    box[e * 2 + 1] = hi;
+}
+
+// Squared gap between the boxes of tiles a and b (0 where they overlap).
+template <int D, typename T>
+__device__ __forceinline__ T box_gap2(const T *__restrict__ box, int64_t a, int64_t b)
+{
+    T g2 = T(0);
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        const T alo = box[(a * D + t) * 2], ahi = box[(a * D + t) * 2 + 1];
+        const T blo = box[(b * D + t) * 2], bhi = box[(b * D + t) * 2 + 1];
+        T gap = blo - ahi > alo - bhi ? blo - ahi : alo - bhi;
+        gap = gap > T(0) ? gap : T(0);
+        g2 = fmaT(gap, gap, g2);
+    }
+    return g2;
+}
 
 __device__ __forceinline__ void decode_pair(int q, int S, int &BI, int &BJ)
 {
@@ -81,9 +123,13 @@ __device__ __forceinline__ void decode_pair(int q, int S, int &BI, int &BJ)
     BJ = bi + rem;
 }
 
+// perm (may be null): v is indexed through it (v[perm[q]] for packed point
+// q).  box (may be null): a tile pair whose box gap^2 is >= tcut is skipped:
+// every kernel value in it is below 2^-tcut.
 template <int D, typename T, typename VT>
 __global__ __launch_bounds__(256) void kmv_sym(const T *__restrict__ Xs, int64_t npad, int64_t n,
-                                               const VT *__restrict__ v, int S, int ST,
+                                               const VT *__restrict__ v, const int32_t *__restrict__ perm,
+                                               const T *__restrict__ box, T tcut, int S, int ST,
                                                T *__restrict__ part)
 {
     __shared__ T cx[D][kTile];
@@ -106,21 +152,20 @@ __global__ __launch_bounds__(256) void kmv_sym(const T *__restrict__ Xs, int64_t
         for (int r = 0; r < 4; ++r) {
 #pragma unroll
             for (int t = 0; t < D; ++t) xi[r][t] = Xs[(int64_t)t * npad + i0 + r];
-            vi[r] = i0 + r < n ? (T)v[i0 + r] : T(0);
+            const int64_t q = i0 + r;
+            vi[r] = q < n ? (T)v[perm ? (int64_t)perm[q] : q] : T(0);
             racc[r] = T(0);
         }
         for (int tj = diag_super ? ti : 0; tj < ST; ++tj) {
             const int64_t j0 = BJ * SB + (int64_t)tj * kTile;
+            // uniform over the workgroup: every thread reads the same two boxes
+            if (box && box_gap2<D, T>(box, (int64_t)BI * ST + ti, (int64_t)BJ * ST + tj) >= tcut) continue;
             __syncthreads();
-            if (tid < kTile * (D + 1)) {
-                const int t = tid / kTile, j = tid % kTile;
-                if (t < D) cx[t][j] = Xs[(int64_t)t * npad + j0 + j];
-                else cv[j] = j0 + j < n ? (T)v[j0 + j] : T(0);
-            }
-            for (int e = tid + 256; e < kTile * (D + 1); e += 256) {
+            for (int e = tid; e < kTile * (D + 1); e += 256) {
                 const int t = e / kTile, j = e % kTile;
-                if (t < D) cx[t][j] = Xs[(int64_t)t * npad + j0 + j];
-                else cv[j] = j0 + j < n ? (T)v[j0 + j] : T(0);
+                const int64_t q = j0 + j;
+                if (t < D) cx[t][j] = Xs[(int64_t)t * npad + q];
+                else cv[j] = q < n ? (T)v[perm ? (int64_t)perm[q] : q] : T(0);
             }
             __syncthreads();
             const bool diag_tile = diag_super && tj == ti;
@@ -177,10 +222,12 @@ __global__ __launch_bounds__(256) void kmv_sym(const T *__restrict__ Xs, int64_t
 template <typename T, typename VT>
 __global__ __launch_bounds__(256) void kmv_sym_reduce(const T *__restrict__ part, int64_t n, int S,
                                                       int ST, double mu, const VT *__restrict__ v,
+                                                      const int32_t *__restrict__ perm,
                                                       VT *__restrict__ y)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int64_t o = perm ? (int64_t)perm[i] : i;
     const int64_t SB = (int64_t)ST * kTile;
     const int s = (int)(i / SB);
     const int64_t ii = i - (int64_t)s * SB;
@@ -191,7 +238,7 @@ __global__ __launch_bounds__(256) void kmv_sym_reduce(const T *__restrict__ part
         const int64_t q = (int64_t)bi * S - (int64_t)bi * (bi - 1) / 2 + (s - bi);
         acc += (double)part[q * 2 * SB + SB + ii];
     }
-    y[i] = (VT)(acc + mu * (double)v[i]);
+    y[o] = (VT)(acc + mu * (double)v[o]);
 }
 
 template <int D, int BN>
@@ -393,26 +440,27 @@ namespace {
 template <typename T, typename VT>
 afn_status kmv_sym_run(const T *Xs, const SymShape &sh, int64_t n, int d, double mu, const VT *v,
                        int64_t ldv, VT *y, int64_t ldy, int nrhs, T *part, hipStream_t s,
-                       hipEvent_t ev0, hipEvent_t ev1)
+                       hipEvent_t ev0, hipEvent_t ev1, const int32_t *perm, const T *box)
 {
+    const T tcut = (T)(sizeof(T) == 8 ? kCullF64 : kCullF32);
     for (int c = 0; c < nrhs; ++c) {
         const VT *vc = v + c * ldv;
         if (ev0) AFN_HIP(hipEventRecord(ev0, s));
         dim3 grid((unsigned)sh.nwg), block(256);
         switch (d) {
-            case 1: hipLaunchKernelGGL((kmv_sym<1, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
-            case 2: hipLaunchKernelGGL((kmv_sym<2, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
-            case 3: hipLaunchKernelGGL((kmv_sym<3, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
-            case 4: hipLaunchKernelGGL((kmv_sym<4, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
-            case 5: hipLaunchKernelGGL((kmv_sym<5, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
-            case 6: hipLaunchKernelGGL((kmv_sym<6, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
-            case 7: hipLaunchKernelGGL((kmv_sym<7, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
-            default: hipLaunchKernelGGL((kmv_sym<8, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, sh.S, sh.ST, part); break;
+            case 1: hipLaunchKernelGGL((kmv_sym<1, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, perm, box, tcut, sh.S, sh.ST, part); break;
+            case 2: hipLaunchKernelGGL((kmv_sym<2, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, perm, box, tcut, sh.S, sh.ST, part); break;
+            case 3: hipLaunchKernelGGL((kmv_sym<3, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, perm, box, tcut, sh.S, sh.ST, part); break;
+            case 4: hipLaunchKernelGGL((kmv_sym<4, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, perm, box, tcut, sh.S, sh.ST, part); break;
+            case 5: hipLaunchKernelGGL((kmv_sym<5, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, perm, box, tcut, sh.S, sh.ST, part); break;
+            case 6: hipLaunchKernelGGL((kmv_sym<6, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, perm, box, tcut, sh.S, sh.ST, part); break;
+            case 7: hipLaunchKernelGGL((kmv_sym<7, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, perm, box, tcut, sh.S, sh.ST, part); break;
+            default: hipLaunchKernelGGL((kmv_sym<8, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, perm, box, tcut, sh.S, sh.ST, part); break;
         }
         AFN_HIP(hipGetLastError());
         if (ev1) AFN_HIP(hipEventRecord(ev1, s));
         hipLaunchKernelGGL((kmv_sym_reduce<T, VT>), dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, part,
-                           n, sh.S, sh.ST, mu, vc, y + c * ldy);
+                           n, sh.S, sh.ST, mu, vc, perm, y + c * ldy);
         AFN_HIP(hipGetLastError());
     }
     return AFN_OK;
@@ -426,34 +474,51 @@ int64_t kmv_packed_doubles(int64_t n, int d)
     return sh.npad * d;
 }
 
-afn_status kmv_pack(const double *X, int64_t n, int d, double l, void *Xs, bool f32, hipStream_t s)
+afn_status kmv_pack(const double *X, int64_t n, int d, double l, void *Xs, bool f32, hipStream_t s,
+                    const int32_t *perm)
 {
     const SymShape sh = sym_shape(n);
     const double scale = std::sqrt(1.4426950408889634) / l;
     if (f32)
         hipLaunchKernelGGL(pack_scaled<float>, dim3((unsigned)ceil_div(sh.npad * d, 256)), dim3(256), 0, s,
-                           X, n, d, sh.npad, scale, (float *)Xs);
+                           X, perm, n, d, sh.npad, scale, (float *)Xs);
     else
         hipLaunchKernelGGL(pack_scaled<double>, dim3((unsigned)ceil_div(sh.npad * d, 256)), dim3(256), 0, s,
-                           X, n, d, sh.npad, scale, (double *)Xs);
+                           X, perm, n, d, sh.npad, scale, (double *)Xs);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+int64_t kmv_box_count(int64_t n, int d) { return sym_shape(n).npad / kTile * d * 2; }
+
+afn_status kmv_boxes(const void *Xs, int64_t n, int d, bool f32, void *box, hipStream_t s)
+{
+    const SymShape sh = sym_shape(n);
+    const unsigned g = (unsigned)ceil_div(sh.npad / kTile * d, 256);
+    if (f32)
+        hipLaunchKernelGGL(tile_boxes<float>, dim3(g), dim3(256), 0, s, (const float *)Xs, sh.npad, n, d,
+                           (float *)box);
+    else
+        hipLaunchKernelGGL(tile_boxes<double>, dim3(g), dim3(256), 0, s, (const double *)Xs, sh.npad, n, d,
+                           (double *)box);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }
 
 afn_status kmv_packed_f64(const double *Xs, int64_t n, int d, double mu, const double *v, int64_t ldv,
                           double *y, int64_t ldy, int nrhs, double *part, hipStream_t s,
-                          hipEvent_t ev0, hipEvent_t ev1)
+                          hipEvent_t ev0, hipEvent_t ev1, const int32_t *perm, const double *box)
 {
     return kmv_sym_run<double, double>(Xs, sym_shape(n), n, d, mu, v, ldv, y, ldy, nrhs, part, s, ev0,
-                                       ev1);
+                                       ev1, perm, box);
 }
 
 afn_status kmv_packed_f32(const float *Xs, int64_t n, int d, double mu, const float *v, int64_t ldv,
                           float *y, int64_t ldy, int nrhs, float *part, hipStream_t s,
-                          hipEvent_t ev0, hipEvent_t ev1)
+                          hipEvent_t ev0, hipEvent_t ev1, const int32_t *perm, const float *box)
 {
     return kmv_sym_run<float, float>(Xs, sym_shape(n), n, d, mu, v, ldv, y, ldy, nrhs, part, s, ev0,
-                                     ev1);
+                                     ev1, perm, box);
 }
 
 afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, const double *v,
@@ -465,7 +530,8 @@ afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, const
         double *Xs = work;
         double *part = work + sh.npad * d;
         AFN_TRY(kmv_pack(X, n, d, l, Xs, false, s));
-        return kmv_sym_run<double, double>(Xs, sh, n, d, mu, v, ldv, y, ldy, nrhs, part, s, ev0, ev1);
+        return kmv_sym_run<double, double>(Xs, sh, n, d, mu, v, ldv, y, ldy, nrhs, part, s, ev0, ev1,
+                                           nullptr, nullptr);
     }
     const int64_t S = kmv_splits(n);
     const int64_t split_len = ceil_div(n, S);
@@ -497,7 +563,7 @@ afn_status kmv_f32(const double *X, int64_t n, int d, double l, double mu, const
         float *part = Xs + round_up(sh.npad * d, 64);
         AFN_TRY(kmv_pack(X, n, d, l, Xs, true, s));
         return kmv_sym_run<float, double>(Xs, sh, n, d, mu, v, ldv, y, ldy, nrhs, part, s, nullptr,
-                                          nullptr);
+                                          nullptr, nullptr, nullptr);
     }
     const int64_t S = kmv_splits(n);
     const int64_t split_len = ceil_div(n, S);

@@ -82,10 +82,15 @@ __device__ __forceinline__ float fmaT(float a, float b, float c) { return __buil
 constexpr int BM = 128;
 constexpr int LSE = 144;    // (lane/16) * 144 = 16 (mod 64): conflict-free MFMA A reads
 
+// perm (may be null): row q of P is row perm[q] of the caller's array.  box
+// (may be null): per 64-point tile, [min, max] of each packed coordinate; a
+// column tile whose box gap^2 to this block's rows is >= tcut is skipped.
 template <int D, typename T, int NB>
 __global__ __launch_bounds__(512) void kmv_mrhs(const T *__restrict__ Xs, int64_t npad, int64_t n,
                                                 const T *__restrict__ P, int64_t ldp, int R,
-                                                int tiles_per_split, T *__restrict__ part)
+                                                int tiles_per_split, T *__restrict__ part,
+                                                const int32_t *__restrict__ perm, const T *__restrict__ box,
+                                                T tcut)
 {
     using M = Mfma<T>;
     constexpr int RP = 16 * NB;
@@ -105,8 +110,32 @@ __global__ __launch_bounds__(512) void kmv_mrhs(const T *__restrict__ Xs, int64_
     typename M::acc_t acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = typename M::acc_t{};
+    // box of this block's 128 rows (tiles 2 blockIdx.x and 2 blockIdx.x + 1)
+    T rlo[D], rhi[D];
+    if (box) {
+        const int64_t ta = 2 * (int64_t)blockIdx.x, tb = ta + 1;
+#pragma unroll
+        for (int t = 0; t < D; ++t) {
+            const T alo = box[(ta * D + t) * 2], ahi = box[(ta * D + t) * 2 + 1];
+            const T blo = box[(tb * D + t) * 2], bhi = box[(tb * D + t) * 2 + 1];
+            rlo[t] = alo < blo ? alo : blo;
+            rhi[t] = ahi > bhi ? ahi : bhi;
+        }
+    }
     for (int64_t J = J0; J < J1; ++J) {
         const int64_t j0 = J * TL;
+        if (box) {
+            // uniform over the workgroup: every thread reads the same boxes
+            T g2 = T(0);
+#pragma unroll
+            for (int t = 0; t < D; ++t) {
+                const T blo = box[(J * D + t) * 2], bhi = box[(J * D + t) * 2 + 1];
+                T gap = blo - rhi[t] > rlo[t] - bhi ? blo - rhi[t] : rlo[t] - bhi;
+                gap = gap > T(0) ? gap : T(0);
+                g2 = fmaT(gap, gap, g2);
+            }
+            if (g2 >= tcut) continue;
+        }
         __syncthreads();
         for (int e = tid; e < D * TL; e += 512) {
             const int t = e / TL, j = e % TL;
@@ -114,7 +143,8 @@ __global__ __launch_bounds__(512) void kmv_mrhs(const T *__restrict__ Xs, int64_
         }
         for (int e = tid; e < TL * RP; e += 512) {
             const int k = e / RP, c = e % RP;
-            PJ[k][c] = (j0 + k < n && c < R) ? P[(j0 + k) * ldp + c] : T(0);
+            const int64_t q = j0 + k;
+            PJ[k][c] = (q < n && c < R) ? P[(perm ? (int64_t)perm[q] : q) * ldp + c] : T(0);
         }
         __syncthreads();
 #pragma unroll 4
@@ -152,15 +182,17 @@ template <typename T>
 __global__ __launch_bounds__(256) void mrhs_reduce(const T *__restrict__ part, int64_t npad, int RP,
                                                    int splits, int64_t n, int R, double mu,
                                                    const T *__restrict__ P, int64_t ldp,
-                                                   T *__restrict__ Y, int64_t ldy)
+                                                   T *__restrict__ Y, int64_t ldy,
+                                                   const int32_t *__restrict__ perm)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n * R) return;
     const int64_t i = e / R;
     const int c = (int)(e - i * R);
+    const int64_t o = perm ? (int64_t)perm[i] : i;
     double s = 0.0;
     for (int q = 0; q < splits; ++q) s += (double)part[(int64_t)q * npad * RP + i * RP + c];
-    Y[i * ldy + c] = (T)(s + mu * (double)P[i * ldp + c]);
+    Y[o * ldy + c] = (T)(s + mu * (double)P[o * ldp + c]);
 }
 
 // part[s][i * RP + c] = sum_{t in split s} A(i, t) B(t, c), A(i,t) = A[i*ars + t*acs],
@@ -439,24 +471,26 @@ __global__ __launch_bounds__(256) void axpy_cols_f32(const double *__restrict__ 
 
 template <int D, typename T, int NB>
 void launch_mrhs(dim3 g, const T *Xs, int64_t npad, int64_t n, const T *P, int64_t ldp, int R, int tps,
-                 T *part, hipStream_t s)
+                 T *part, const int32_t *perm, const T *box, hipStream_t s)
 {
-    hipLaunchKernelGGL((kmv_mrhs<D, T, NB>), g, dim3(512), 0, s, Xs, npad, n, P, ldp, R, tps, part);
+    const T tcut = (T)(sizeof(T) == 8 ? kCullF64 : kCullF32);
+    hipLaunchKernelGGL((kmv_mrhs<D, T, NB>), g, dim3(512), 0, s, Xs, npad, n, P, ldp, R, tps, part, perm,
+                       box, tcut);
 }
 
 template <typename T, int NB>
 void launch_mrhs_d(int d, dim3 g, const T *Xs, int64_t npad, int64_t n, const T *P, int64_t ldp, int R,
-                   int tps, T *part, hipStream_t s)
+                   int tps, T *part, const int32_t *perm, const T *box, hipStream_t s)
 {
     switch (d) {
-        case 1: launch_mrhs<1, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, s); break;
-        case 2: launch_mrhs<2, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, s); break;
-        case 3: launch_mrhs<3, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, s); break;
-        case 4: launch_mrhs<4, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, s); break;
-        case 5: launch_mrhs<5, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, s); break;
-        case 6: launch_mrhs<6, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, s); break;
-        case 7: launch_mrhs<7, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, s); break;
-        default: launch_mrhs<8, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, s); break;
+        case 1: launch_mrhs<1, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
+        case 2: launch_mrhs<2, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
+        case 3: launch_mrhs<3, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
+        case 4: launch_mrhs<4, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
+        case 5: launch_mrhs<5, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
+        case 6: launch_mrhs<6, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
+        case 7: launch_mrhs<7, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
+        default: launch_mrhs<8, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
     }
 }
 
@@ -478,7 +512,7 @@ int64_t mrhs_part_elems(int64_t npad) { return (int64_t)mrhs_splits(npad) * npad
 template <typename T>
 afn_status kmv_mrhs_run(const T *Xs, int64_t npad, int64_t n, int d, double mu, const T *P,
                         int64_t ldp, T *Y, int64_t ldy, int R, T *part, hipStream_t s,
-                        hipEvent_t e0, hipEvent_t e1)
+                        hipEvent_t e0, hipEvent_t e1, const int32_t *perm, const T *box)
 {
     if (R < 1 || R > 64 || d < 1 || d > 8) {
         set_error("kmv_mrhs: R=%d d=%d outside [1, 64] x [1, 8]", R, d);
@@ -495,25 +529,25 @@ afn_status kmv_mrhs_run(const T *Xs, int64_t npad, int64_t n, int d, double mu, 
     dim3 g((unsigned)(npad / BM), (unsigned)S);
     if (e0) AFN_HIP(hipEventRecord(e0, s));
     switch (NBk) {
-        case 1: launch_mrhs_d<T, 1>(d, g, Xs, npad, n, P, ldp, R, tps, part, s); break;
-        case 2: launch_mrhs_d<T, 2>(d, g, Xs, npad, n, P, ldp, R, tps, part, s); break;
-        case 3: launch_mrhs_d<T, 3>(d, g, Xs, npad, n, P, ldp, R, tps, part, s); break;
-        default: launch_mrhs_d<T, 4>(d, g, Xs, npad, n, P, ldp, R, tps, part, s); break;
+        case 1: launch_mrhs_d<T, 1>(d, g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
+        case 2: launch_mrhs_d<T, 2>(d, g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
+        case 3: launch_mrhs_d<T, 3>(d, g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
+        default: launch_mrhs_d<T, 4>(d, g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
     }
     AFN_HIP(hipGetLastError());
     if (e1) AFN_HIP(hipEventRecord(e1, s));
     hipLaunchKernelGGL((mrhs_reduce<T>), dim3((unsigned)ceil_div(n * R, 256)), dim3(256), 0, s, part, npad,
-                       16 * NBk, S, n, R, mu, P, ldp, Y, ldy);
+                       16 * NBk, S, n, R, mu, P, ldp, Y, ldy, perm);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }
 
 template afn_status kmv_mrhs_run<float>(const float *, int64_t, int64_t, int, double, const float *,
                                         int64_t, float *, int64_t, int, float *, hipStream_t,
-                                        hipEvent_t, hipEvent_t);
+                                        hipEvent_t, hipEvent_t, const int32_t *, const float *);
 template afn_status kmv_mrhs_run<double>(const double *, int64_t, int64_t, int, double, const double *,
                                          int64_t, double *, int64_t, int, double *, hipStream_t,
-                                         hipEvent_t, hipEvent_t);
+                                         hipEvent_t, hipEvent_t, const int32_t *, const double *);
 
 int gemm_splits(int64_t m, int64_t K)
 {
