@@ -2,9 +2,10 @@
 
 TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no code
-with the GPU library: the arithmetic lives in ``afn_oracle.c`` (plain C, FP64,
-``-ffp-contract=off``, OpenMP ``parallel for`` over independent outputs only) and
-this module only marshals numpy arrays through ctypes.
+with the GPU library: the AFN arithmetic lives in ``afn_oracle.c`` (plain C,
+FP64, ``-ffp-contract=off``, OpenMP ``parallel for`` over independent outputs
+only) and this module only marshals numpy arrays through ctypes; the Nystrom
+branch of Algorithm 5 is plain numpy in ``nystrom.py``.
 
 Every wrapper names the passage of the paper its C function follows.
 """
@@ -340,3 +341,17 @@ def rank_estimate(X, l: float, mu: float, m: int, kmax: int = 2000, kswitch: int
                                    ctypes.c_uint64(seed), ctypes.byref(k), _p(info)),
            "rank_estimate")
     return int(k.value), tuple(int(v) for v in info)
+
+
+# --- Algorithm 5, Nystrom branch (nystrom.py) ------------------------------------
+
+from .nystrom import Nystrom, kernel_columns, nystrom_apply, nystrom_build, nystrom_pcg  # noqa: E402,F401
+
+
+def nystrom_solve(X, l: float, mu: float, k: int, b, tol: float, maxit: int = 500):
+    """FPS landmarks (Algorithm 6), the Nystrom preconditioner, textbook PCG."""
+    idx, _ = fps(X, k)
+    N = nystrom_build(X, l, mu, idx)
+    x, it, rel, conv = nystrom_pcg(N, b, tol, maxit, lambda v: kernel_matvec(X, l, mu, v))
+    return N, x, it, rel, conv
+
