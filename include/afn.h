@@ -66,14 +66,32 @@ typedef enum afn_precision {
     AFN_FP32 = 1
 } afn_precision;
 
-/* Construction parameters (Algorithm 2, Algorithm 4). */
+/* Preconditioner (Algorithm 5).  AFN_METHOD_AFN: the AFN factorization
+ * (Algorithm 2).  AFN_METHOD_NYSTROM: the column-sampling Nystrom
+ * preconditioner M = K_nys + mu I on the same FPS landmarks, applied by the
+ * Sherman-Morrison-Woodbury identity (Section 2) -- with
+ * B = K[:, S] chol(K_SS + nu I)^{-T} (nu = eps ||K[:, S]||_F, the stabilizing
+ * shift of the randomized Nystrom construction) it computes
+ * M^{-1} r = (r - B (B^T B + mu I)^{-1} B^T r) / mu, which equals
+ * U (Lambda + mu I)^{-1} U^T r + (r - U U^T r) / mu for the thin SVD
+ * B = U Sigma V^T up to the shift (Lambda = Sigma^2 - nu; relative
+ * difference <= nu / mu).  Needs mu > 0.  AFN_METHOD_AUTO: Algorithm 5's
+ * choice -- Nystrom when the rank (the estimate of Algorithm 4, or k when
+ * given) is below 2000, AFN otherwise. */
+typedef enum afn_method {
+    AFN_METHOD_AFN = 0,
+    AFN_METHOD_NYSTROM = 1,
+    AFN_METHOD_AUTO = 2
+} afn_method;
+
+/* Construction parameters (Algorithm 2, Algorithm 4, Algorithm 5). */
 typedef struct afn_params {
     int32_t k;          /* landmark count; -1 = estimate it (Algorithm 4)         */
     int32_t k_max;      /* cap on the estimated count (Section 3.2: e.g. 2000)     */
     int32_t w;          /* FSAI nonzeros per row incl. the diagonal, 1 <= w <= 64  */
     int32_t m;          /* rank-estimation subsample size; 0 = min(n, 2000)        */
     int32_t precision;  /* afn_precision of the PCG solve (AFN_FP32 needs d <= 8)   */
-    int32_t reserved;   /* must be 0                                               */
+    int32_t method;     /* afn_method                                              */
     uint64_t seed;      /* seed of the rank-estimation subsample (splitmix64)      */
 } afn_params;
 
@@ -87,8 +105,12 @@ typedef struct afn_setup_info {
     int64_t rank_k_est;      /* Algorithm 4: floor(r n / m), -1 if k given         */
     int32_t rank_eig_branch; /* 1 if the eigenvalue count replaced k_est           */
     int32_t rank_eig_count;  /* that count, -1 if not computed                     */
-    int64_t nnz_g;           /* nonzeros of the FSAI factor G                      */
-    double ms_rank, ms_fps, ms_chol, ms_knn, ms_v, ms_fsai, ms_total;  /* phase times */
+    int64_t nnz_g;           /* nonzeros of the FSAI factor G (0 for Nystrom)      */
+    double ms_rank, ms_fps, ms_chol, ms_knn, ms_v, ms_fsai, ms_total;  /* phase times;
+                                Nystrom: ms_fsai = forming and factoring B^T B + mu I */
+    int32_t method;          /* afn_method built: AFN_METHOD_AFN or _NYSTROM       */
+    int32_t reserved;
+    double nu;               /* Nystrom stabilizing shift (0 for AFN)              */
 } afn_setup_info;
 
 /* Result of a PCG solve. */
@@ -123,15 +145,17 @@ afn_status kernel_matvec(const double *X_dev, int64_t n, int32_t d, double l, do
                          const double *v_dev, double *y_dev, int32_t nrhs, int64_t ld,
                          int32_t precision, void *stream);
 
-/* Construct the AFN preconditioner (Algorithm 2): landmarks by farthest point
- * sampling (Algorithm 6) -- k from params or estimated (Algorithm 4) --,
+/* Construct the preconditioner.  AFN (Algorithm 2): landmarks by farthest
+ * point sampling (Algorithm 6) -- k from params or estimated (Algorithm 4) --,
  * L = chol(K11 + mu I), and the FSAI factor G of the Schur complement
  * K22 + mu I - K12^T (K11 + mu I)^{-1} K12 (Algorithm 1) on the pattern of
- * the w-1 nearest earlier-numbered points (Section 3.1).
+ * the w-1 nearest earlier-numbered points (Section 3.1).  Nystrom and the
+ * Algorithm 5 choice: see afn_method (w is then unused).
  * The library copies what it needs from X_dev and owns the device memory of
  * the handle (released by afn_destroy).  Synchronizes 'stream'.
  * Errors: EINVAL (n < 1, d < 1 or d > 64, l <= 0, mu < 0, k < -1 or k > n,
- * w < 1 or w > 64), ENOMEM, ENOTSPD, EDEVICE.  *out is NULL on failure. */
+ * w < 1 or w > 64, unknown method, Nystrom with mu = 0), ENOMEM, ENOTSPD,
+ * EDEVICE.  *out is NULL on failure. */
 afn_status afn_setup(const double *X_dev, int64_t n, int32_t d, double l, double mu,
                      const afn_params *params, void *stream, afn_handle **out);
 

@@ -20,6 +20,7 @@ _lib = None
 AFN_OK, AFN_EINVAL, AFN_ENOMEM, AFN_ENOTSPD, AFN_ENOCONV, AFN_EBREAKDOWN, AFN_ESTAGNATION, \
     AFN_EDEVICE = range(8)
 AFN_FP64, AFN_FP32 = 0, 1
+AFN_METHOD_AFN, AFN_METHOD_NYSTROM, AFN_METHOD_AUTO = 0, 1, 2
 _STATUS_NAMES = ["AFN_OK", "AFN_EINVAL", "AFN_ENOMEM", "AFN_ENOTSPD", "AFN_ENOCONV",
                  "AFN_EBREAKDOWN", "AFN_ESTAGNATION", "AFN_EDEVICE"]
 
@@ -43,7 +44,7 @@ class AFNError(RuntimeError):
 class afn_params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("k_max", ctypes.c_int32), ("w", ctypes.c_int32),
                 ("m", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("method", ctypes.c_int32), ("seed", ctypes.c_uint64)]
 
 
 class afn_setup_info(ctypes.Structure):
@@ -54,7 +55,8 @@ class afn_setup_info(ctypes.Structure):
                 ("ms_rank", ctypes.c_double), ("ms_fps", ctypes.c_double),
                 ("ms_chol", ctypes.c_double), ("ms_knn", ctypes.c_double),
                 ("ms_v", ctypes.c_double), ("ms_fsai", ctypes.c_double),
-                ("ms_total", ctypes.c_double)]
+                ("ms_total", ctypes.c_double), ("method", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("nu", ctypes.c_double)]
 
 
 class afn_solve_info(ctypes.Structure):
@@ -170,6 +172,8 @@ class SetupInfo:
     rank_eig_count: int
     nnz_g: int
     ms: dict
+    method: int = 0
+    nu: float = 0.0
 
 
 class Handle:
@@ -202,7 +206,7 @@ class Handle:
         ms = {k: getattr(inf, "ms_" + k) for k in ("rank", "fps", "chol", "knn", "v", "fsai",
                                                    "total")}
         return SetupInfo(inf.n, inf.d, inf.k, inf.w, inf.rank_r, inf.rank_k_est,
-                         inf.rank_eig_branch, inf.rank_eig_count, inf.nnz_g, ms)
+                         inf.rank_eig_branch, inf.rank_eig_count, inf.nnz_g, ms, inf.method, inf.nu)
 
     def landmarks(self):
         import numpy as np
@@ -236,11 +240,13 @@ class Handle:
 
 
 def afn_setup(X: torch.Tensor, l: float, mu: float, k: int = -1, w: int = 64, k_max: int = 2000,
-              m: int = 0, seed: int = 0, precision: int = AFN_FP64, stream=None) -> Handle:
-    """Algorithm 2 (landmarks by FPS, chol(K11 + mu I), FSAI of the Schur complement)."""
+              m: int = 0, seed: int = 0, precision: int = AFN_FP64, method: int = AFN_METHOD_AFN,
+              stream=None) -> Handle:
+    """Algorithm 2 (landmarks by FPS, chol(K11 + mu I), FSAI of the Schur complement),
+    or the Nystrom preconditioner, or Algorithm 5's choice between them (method)."""
     X = _dev_f64(X, "X").contiguous()
     n, d = X.shape
-    prm = afn_params(k=k, k_max=k_max, w=w, m=m, precision=precision, reserved=0, seed=seed)
+    prm = afn_params(k=k, k_max=k_max, w=w, m=m, precision=precision, method=method, seed=seed)
     h = ctypes.c_void_p()
     _check(lib().afn_setup(X.data_ptr(), n, d, l, mu, ctypes.byref(prm), _stream(stream),
                            ctypes.byref(h)), "afn_setup")
@@ -248,9 +254,9 @@ def afn_setup(X: torch.Tensor, l: float, mu: float, k: int = -1, w: int = 64, k_
 
 
 def afn_footprint_bytes(n: int, d: int, k: int = -1, w: int = 64, k_max: int = 2000, m: int = 0,
-                        precision: int = AFN_FP64) -> int:
+                        precision: int = AFN_FP64, method: int = AFN_METHOD_AFN) -> int:
     """Upper bound of afn_setup's device memory for these sizes (host-only)."""
-    prm = afn_params(k=k, k_max=k_max, w=w, m=m, precision=precision, reserved=0, seed=0)
+    prm = afn_params(k=k, k_max=k_max, w=w, m=m, precision=precision, method=method, seed=0)
     out = ctypes.c_size_t(0)
     _check(lib().afn_footprint_bytes(n, d, ctypes.byref(prm), ctypes.byref(out)),
            "afn_footprint_bytes")

@@ -131,6 +131,12 @@ afn_status diag_inverses(const double *L, int k, double *Dinv, hipStream_t s);
 afn_status trsm_lower(const double *L, const double *Dinv, int k, double *B, int64_t ncols,
                       hipStream_t s);
 afn_status identity(double *A, int k, hipStream_t s);
+// A[i + j lda] = 0 for i < j < k.
+afn_status zero_upper(double *A, int k, int64_t lda, hipStream_t s);
+// A[i + i lda] += shift for i < k.
+afn_status add_diagonal(double *A, int k, int64_t lda, double shift, hipStream_t s);
+// B[t + i ldb] = A[i + t lda] for i, t < k (B = A^T of a k x k block).
+afn_status transpose_square(const double *A, int k, int64_t lda, double *B, int64_t ldb, hipStream_t s);
 
 // ---------------------------------------------------------------- FSAI
 // Padded rows of G (nr x w; row p has min(p+1, w) entries) for the Schur
@@ -201,6 +207,8 @@ afn_status to_f32_scaled_launch(const double *r, double scale, float *r32, int64
 afn_status axpy_f32_into_f64_launch(double a, const float *e, double *x, int64_t n, hipStream_t s);
 afn_status to_f32_launch(const double *a, float *b, int64_t n, hipStream_t s);
 afn_status sub_launch(const double *b, const double *y, double *r, int64_t n, hipStream_t s);
+afn_status scale_launch(double *x, double a, int64_t n, hipStream_t s);
+afn_status scale_launch(float *x, float a, int64_t n, hipStream_t s);
 // *flag |= 1 if a value is not finite
 afn_status finite_launch(const double *a, int64_t n, int *flag, hipStream_t s);
 
@@ -295,6 +303,14 @@ struct afn_handle {
     float *gval32 = nullptr;
     float *tval32 = nullptr;
     float *work32 = nullptr;
+    // Nystrom preconditioner (method == AFN_METHOD_NYSTROM): W = [L^T | V]
+    // (k x n column-major, V = L^{-1} K12 with L = chol(K11 + nu I)) and the
+    // inverse Rginv of the lower Cholesky factor of W W^T + mu I
+    int method = AFN_METHOD_AFN;
+    double *W = nullptr;
+    double *Rginv = nullptr;
+    float *W32 = nullptr;
+    float *Rginv32 = nullptr;
     void *mrhs_ws = nullptr;    // workspace of block solves (allocated on first use)
     size_t mrhs_bytes = 0;
     double *host_sc = nullptr;  // pinned host copy of PCG scalars

@@ -23,7 +23,7 @@ struct BlockWs {
     double *Bp, *X64, *R64, *Y64, *part64;
     double *bn2, *rr64, *inv, *amul, *tolc;       // R each
     // FP32
-    float *Rr, *Rw, *Z, *P, *Q, *E, *Y1, *Y1b, *T, *U, *gpart, *kpart;
+    float *Rr, *Rw, *Z, *P, *Q, *E, *Y1, *Y1b, *Y2, *T, *U, *gpart, *kpart;
     // FP64 scalars of the inner solve (R each) and dot partials
     double *rho, *pq, *rr, *rho_new, *alpha, *beta, *bn2_in, *dotp;
     int *active, *count, *bad;
@@ -59,13 +59,16 @@ size_t block_ws(const afn_handle *h, int R, BlockWs *w, char *base)
     t.E = (float *)take(4 * nR);
     t.Y1 = (float *)take(4 * (size_t)(k * R + 1));
     t.Y1b = (float *)take(4 * (size_t)(k * R + 1));
+    t.Y2 = (float *)take(4 * (size_t)(k * R + 1));
     t.T = (float *)take(4 * (size_t)(nr * R + 1));
     t.U = (float *)take(4 * (size_t)(nr * R + 1));
     int64_t gp = gemm_part_elems(k, k);
-    int64_t g2 = gemm_part_elems(nr, k);
-    int64_t g3 = gemm_part_elems(k, nr);
+    const int64_t g2 = gemm_part_elems(nr, k), g3 = gemm_part_elems(k, nr);
+    const int64_t g4 = gemm_part_elems(n, k), g5 = gemm_part_elems(k, n);    // Nystrom
     gp = gp > g2 ? gp : g2;
     gp = gp > g3 ? gp : g3;
+    gp = gp > g4 ? gp : g4;
+    gp = gp > g5 ? gp : g5;
     t.gpart = (float *)take(4 * (size_t)(gp + 1));
     t.kpart = (float *)take(4 * (size_t)mrhs_part_elems(npad));
     t.rho = (double *)take(8 * 64);
@@ -89,10 +92,28 @@ __global__ void init_active(const double *bn2, int *active, int R)
     if (c < R) active[c] = bn2[c] > 0.0 ? 1 : 0;
 }
 
+// Z = M^{-1} Rin for the Nystrom preconditioner (see apply_nysT), R columns.
+afn_status apply32_block_nys(afn_handle *h, const float *Rin, float *Zout, int R, const BlockWs &w,
+                             hipStream_t s)
+{
+    const int k = h->k;
+    const int64_t n = h->n;
+    if (k > 0) {
+        AFN_TRY(gemm_rows<float>(h->W32, 1, k, k, n, Rin, R, R, nullptr, 1.0f, w.Y1, R, w.gpart, s));
+        AFN_TRY(gemm_rows<float>(h->Rginv32, 1, k, k, k, w.Y1, R, R, nullptr, 1.0f, w.Y1b, R, w.gpart, s));
+        AFN_TRY(gemm_rows<float>(h->Rginv32, k, 1, k, k, w.Y1b, R, R, nullptr, 1.0f, w.Y2, R, w.gpart, s));
+        AFN_TRY(gemm_rows<float>(h->W32, k, 1, n, k, w.Y2, R, R, Rin, -1.0f, Zout, R, w.gpart, s));
+    } else {
+        AFN_HIP(hipMemcpyAsync(Zout, Rin, sizeof(float) * n * R, hipMemcpyDeviceToDevice, s));
+    }
+    return scale_launch(Zout, (float)(1.0 / h->mu), n * R, s);
+}
+
 // Z = M^{-1} Rin for R columns (row-major blocks, block order).
 afn_status apply32_block(afn_handle *h, const float *Rin, float *Zout, int R, const BlockWs &w,
                          hipStream_t s)
 {
+    if (h->method == AFN_METHOD_NYSTROM) return apply32_block_nys(h, Rin, Zout, R, w, s);
     const int k = h->k;
     const int64_t nr = h->nr;
     if (k > 0)

@@ -1,5 +1,6 @@
 // C-ABI of libafn: preconditioner construction (Algorithm 2), application
 // (Algorithm 3) and preconditioned CG (Algorithm 5, AFN branch).
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -43,7 +44,7 @@ struct Timer {
 
 // Workspace layout inside afn_handle::work (doubles).
 struct WorkLayout {
-    double *kmv, *dotp, *gemvp, *y1, *t, *u, *y1b, *x, *r, *z, *p, *q, *bp, *tmp, *rp, *sp, *sc;
+    double *kmv, *dotp, *gemvp, *y1, *t, *u, *y1b, *y2, *x, *r, *z, *p, *q, *bp, *tmp, *rp, *sp, *sc;
 };
 
 int64_t work_doubles(int64_t n, int d, int k, int64_t nr, WorkLayout *L, double *base)
@@ -55,7 +56,7 @@ int64_t work_doubles(int64_t n, int d, int k, int64_t nr, WorkLayout *L, double 
         return ptr;
     };
     WorkLayout w;
-    int64_t gp = gemv_partials(k, nr > k ? nr : k);
+    int64_t gp = gemv_partials(k, n > k ? n : k);
     int64_t gp2 = gemv_partials(k, k);
     w.kmv = take(kmv_workspace_doubles(n, d));
     w.dotp = take(dot_partials(n));
@@ -64,6 +65,7 @@ int64_t work_doubles(int64_t n, int d, int k, int64_t nr, WorkLayout *L, double 
     w.t = take(nr);
     w.u = take(nr);
     w.y1b = take(k);
+    w.y2 = take(k);
     w.x = take(n);
     w.r = take(n);
     w.z = take(n);
@@ -80,7 +82,7 @@ int64_t work_doubles(int64_t n, int d, int k, int64_t nr, WorkLayout *L, double 
 
 // Workspace of the FP32 inner solves (floats).
 struct WorkLayout32 {
-    float *kmv, *gemvp, *y1, *t, *u, *y1b, *r, *z, *p, *q, *e;
+    float *kmv, *gemvp, *y1, *t, *u, *y1b, *y2, *r, *z, *p, *q, *e;
 };
 
 int64_t work32_floats(int64_t n, int d, int k, int64_t nr, WorkLayout32 *L, float *base)
@@ -92,7 +94,7 @@ int64_t work32_floats(int64_t n, int d, int k, int64_t nr, WorkLayout32 *L, floa
         return ptr;
     };
     WorkLayout32 w;
-    int64_t gp = gemv_partials(k, nr > k ? nr : k);
+    int64_t gp = gemv_partials(k, n > k ? n : k);
     int64_t gp2 = gemv_partials(k, k);
     w.kmv = take(2 * kmv_workspace_doubles(n, d));
     w.gemvp = take(gp > gp2 ? gp : gp2);
@@ -100,6 +102,7 @@ int64_t work32_floats(int64_t n, int d, int k, int64_t nr, WorkLayout32 *L, floa
     w.t = take(nr);
     w.u = take(nr);
     w.y1b = take(k);
+    w.y2 = take(k);
     w.r = take(n);
     w.z = take(n);
     w.p = take(n);
@@ -145,9 +148,31 @@ afn_status apply_blockT(const afn_handle *h, const Factors<T> &f, const T *rp, T
     return AFN_OK;
 }
 
+// s = M^{-1} r for the Nystrom preconditioner M = B B^T + mu I, B = W^T
+// (block order): Sherman-Morrison-Woodbury with B^T B + mu I = Rg Rg^T,
+//   y1 = W r ; y2 = Rg^{-T} Rg^{-1} y1 ; s = (r - W^T y2) / mu.
+template <typename T>
+afn_status apply_nysT(const afn_handle *h, const T *W, const T *Rginv, const T *rp, T *sp, T *y1, T *y1b,
+                      T *y2, T *gemvp, hipStream_t s)
+{
+    const int k = h->k;
+    const int64_t n = h->n;
+    if (k > 0) {
+        AFN_TRY(gemv_n(W, k, k, n, rp, (const T *)nullptr, T(1), y1, gemvp, s));
+        AFN_TRY(gemv_n(Rginv, k, k, k, y1, (const T *)nullptr, T(1), y1b, gemvp, s));
+        AFN_TRY(gemv_t(Rginv, k, k, k, y1b, (const T *)nullptr, T(1), y2, s));
+        AFN_TRY(gemv_t(W, k, k, n, y2, rp, T(-1), sp, s));
+    } else {
+        AFN_HIP(hipMemcpyAsync(sp, rp, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
+    }
+    return scale_launch(sp, T(1.0 / h->mu), n, s);
+}
+
 afn_status apply_block(afn_handle *h, const double *rp, double *sp, const WorkLayout &w,
                        hipStream_t s)
 {
+    if (h->method == AFN_METHOD_NYSTROM)
+        return apply_nysT<double>(h, h->W, h->Rginv, rp, sp, w.y1, w.y1b, w.y2, w.gemvp, s);
     Factors<double> f{h->Linv, h->V, h->gval, h->tval};
     return apply_blockT<double>(h, f, rp, sp, w.y1, w.t, w.u, w.y1b, w.gemvp, s);
 }
@@ -155,6 +180,8 @@ afn_status apply_block(afn_handle *h, const double *rp, double *sp, const WorkLa
 afn_status apply_block32(afn_handle *h, const float *rp, float *sp, const WorkLayout32 &w,
                          hipStream_t s)
 {
+    if (h->method == AFN_METHOD_NYSTROM)
+        return apply_nysT<float>(h, h->W32, h->Rginv32, rp, sp, w.y1, w.y1b, w.y2, w.gemvp, s);
     Factors<float> f{h->Linv32, h->V32, h->gval32, h->tval32};
     return apply_blockT<float>(h, f, rp, sp, w.y1, w.t, w.u, w.y1b, w.gemvp, s);
 }
@@ -171,7 +198,7 @@ afn_status op_f64(afn_handle *h, const double *v, double *y, const WorkLayout &w
 
 afn_status check_flags(afn_handle *h, hipStream_t s)
 {
-    int f[4] = {0, 0, 0, 0};
+    int f[6] = {0, 0, 0, 0, 0, 0};
     AFN_HIP(hipMemcpyAsync(f, h->flags, sizeof f, hipMemcpyDeviceToHost, s));
     AFN_HIP(hipStreamSynchronize(s));
     if (f[0]) {
@@ -179,7 +206,8 @@ afn_status check_flags(afn_handle *h, hipStream_t s)
         return AFN_EINVAL;
     }
     if (f[1]) {
-        set_error("afn_setup: K11 + mu I is not positive definite (pivot %d)", f[1] - 1);
+        set_error("afn_setup: the landmark block K11 + shift I is not positive definite (pivot %d)",
+                  f[1] - 1);
         return AFN_ENOTSPD;
     }
     if (f[2]) {
@@ -190,6 +218,70 @@ afn_status check_flags(afn_handle *h, hipStream_t s)
         set_error("afn_setup: landmark selection produced an invalid index");
         return AFN_EDEVICE;
     }
+    if (f[5]) {
+        set_error("afn_setup: B^T B + mu I of the Nystrom preconditioner is not positive definite");
+        return AFN_ENOTSPD;
+    }
+    return AFN_OK;
+}
+
+// Nystrom factors (see afn_method): L = chol(K11 + nu I) with
+// nu = eps ||K[:, S]||_F, W = [L^T | L^{-1} K12], Rginv = inverse of the lower
+// Cholesky factor of W W^T + mu I.  Marks timer slots 3 .. 6.
+afn_status nystrom_factors(afn_handle *h, DevArena &tmp, Timer &tm, hipStream_t s)
+{
+    const int64_t n = h->n, nr = h->nr;
+    const int k = h->k, d = h->d;
+    h->info.nu = 0.0;
+    if (k == 0) {
+        for (int m = 3; m <= 6; ++m) tm.mark(m, s);
+        return AFN_OK;
+    }
+    const int64_t kk = (int64_t)k * k, knr = (int64_t)k * nr;
+    AFN_TRY(h->arena.alloc_n(&h->L, kk));
+    AFN_TRY(h->arena.alloc_n(&h->Dinv, dinv_doubles(k)));
+    AFN_TRY(h->arena.alloc_n(&h->W, (int64_t)k * n));
+    h->V = h->W + kk;
+    AFN_TRY(fill_k11(h->Xp, k, d, h->l, 0.0, h->L, k, s));    // lower triangle, unit diagonal
+    if (nr > 0) AFN_TRY(fill_k12(h->Xp, n, k, d, h->l, h->V, s));
+    // ||K[:, S]||_F^2 = ||K12||_F^2 + 2 (lower triangle of K11)^2 - k
+    double *dp = nullptr, *sc = nullptr;
+    AFN_TRY(tmp.alloc_n(&dp, dot_partials(kk > knr ? kk : knr)));
+    AFN_TRY(tmp.alloc_n(&sc, 2));
+    AFN_HIP(hipMemsetAsync(sc, 0, 2 * sizeof(double), s));
+    AFN_TRY(dot(h->L, kk, h->L, kk, kk, 1, sc, dp, s));
+    if (nr > 0) AFN_TRY(dot(h->V, knr, h->V, knr, knr, 1, sc + 1, dp, s));
+    double hs[2] = {0.0, 0.0};
+    AFN_HIP(hipMemcpyAsync(hs, sc, sizeof hs, hipMemcpyDeviceToHost, s));
+    AFN_HIP(hipStreamSynchronize(s));
+    const double f2 = 2.0 * hs[0] - (double)k + hs[1];
+    const double nu = DBL_EPSILON * std::sqrt(f2 > 0.0 ? f2 : 0.0);
+    h->info.nu = nu;
+    AFN_TRY(add_diagonal(h->L, k, k, nu, s));
+    AFN_TRY(cholesky(h->L, k, k, h->flags + 1, s));
+    AFN_TRY(diag_inverses(h->L, k, h->Dinv, s));
+    tm.mark(3, s);
+    tm.mark(4, s);
+    if (nr > 0) AFN_TRY(trsm_lower(h->L, h->Dinv, k, h->V, nr, s));
+    AFN_TRY(transpose_square(h->L, k, k, h->W, k, s));
+    tm.mark(5, s);
+    // W W^T + mu I by 64-column blocks on FP64 MFMA, its factor and inverse
+    double *G = nullptr, *Dg = nullptr, *part = nullptr;
+    AFN_TRY(tmp.alloc_n(&G, kk));
+    AFN_TRY(tmp.alloc_n(&Dg, dinv_doubles(k)));
+    AFN_TRY(tmp.alloc_n(&part, gemm_part_elems(k, n)));
+    for (int c0 = 0; c0 < k; c0 += 64) {
+        const int R = k - c0 < 64 ? k - c0 : 64;
+        AFN_TRY(gemm_rows<double>(h->W, 1, k, k, n, h->W + c0, k, R, nullptr, 1.0, G + c0, k, part, s));
+    }
+    AFN_TRY(zero_upper(G, k, k, s));
+    AFN_TRY(add_diagonal(G, k, k, h->mu, s));
+    AFN_TRY(cholesky(G, k, k, h->flags + 5, s));
+    AFN_TRY(diag_inverses(G, k, Dg, s));
+    AFN_TRY(h->arena.alloc_n(&h->Rginv, kk));
+    AFN_TRY(identity(h->Rginv, k, s));
+    AFN_TRY(trsm_lower(G, Dg, k, h->Rginv, k, s));
+    tm.mark(6, s);
     return AFN_OK;
 }
 
@@ -219,6 +311,18 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
         AFN_TRY(rank_estimate(X, n, d, l, mu, m, kmax, prm->seed, s, &h->info, &k));
     }
     tm.mark(1, s);
+    // Algorithm 5: the rank decides between AFN and Nystrom
+    h->method = prm->method;
+    if (h->method == AFN_METHOD_AUTO) {
+        const int64_t rank = prm->k >= 0 ? (int64_t)prm->k
+                                         : (h->info.rank_eig_branch ? (int64_t)h->info.rank_eig_count
+                                                                    : h->info.rank_k_est);
+        h->method = rank < 2000 ? AFN_METHOD_NYSTROM : AFN_METHOD_AFN;
+    }
+    if (h->method == AFN_METHOD_NYSTROM && !(mu > 0.0)) {
+        set_error("afn_setup: the Nystrom preconditioner needs mu > 0");
+        return AFN_EINVAL;
+    }
     h->k = k;
     h->nr = n - k;
     const int64_t nr = h->nr;
@@ -240,6 +344,9 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     AFN_TRY(h->arena.alloc_n(&h->Xp, n * d));
     AFN_TRY(gather_points(X, h->perm, n, d, h->Xp, s));
     tm.mark(2, s);
+    if (h->method == AFN_METHOD_NYSTROM) {
+        AFN_TRY(nystrom_factors(h, tmp, tm, s));
+    } else {
     // L = chol(K11 + mu I), Linv, V = L^{-1} K12
     if (k > 0) {
         AFN_TRY(h->arena.alloc_n(&h->L, (int64_t)k * k));
@@ -279,6 +386,7 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
         AFN_TRY(fsai_transpose(h->cols, h->gval, nr, h->w, h->tptr, h->trow, h->tval, tws, s));
     }
     tm.mark(6, s);
+    }
     // points packed for the symmetric tile kernel; FP32 copies for mixed solves
     h->precision = prm->precision;
     if (d <= 8) {
@@ -298,15 +406,23 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
         AFN_TRY(kmv_pack(h->Xp, n, d, l, h->Xs32, true, s, h->kperm));
         AFN_TRY(h->arena.alloc_n(&h->box32, kmv_box_count(n, d)));
         AFN_TRY(kmv_boxes(h->Xs32, n, d, true, h->box32, s));
-        if (k > 0) {
+        if (h->method == AFN_METHOD_NYSTROM) {
+            if (k > 0) {
+                AFN_TRY(h->arena.alloc_n(&h->W32, (int64_t)k * n));
+                AFN_TRY(to_f32_launch(h->W, h->W32, (int64_t)k * n, s));
+                AFN_TRY(h->arena.alloc_n(&h->Rginv32, (int64_t)k * k));
+                AFN_TRY(to_f32_launch(h->Rginv, h->Rginv32, (int64_t)k * k, s));
+            }
+        }
+        if (h->method != AFN_METHOD_NYSTROM && k > 0) {
             AFN_TRY(h->arena.alloc_n(&h->Linv32, (int64_t)k * k));
             AFN_TRY(to_f32_launch(h->Linv, h->Linv32, (int64_t)k * k, s));
         }
-        if (k > 0 && nr > 0) {
+        if (h->method != AFN_METHOD_NYSTROM && k > 0 && nr > 0) {
             AFN_TRY(h->arena.alloc_n(&h->V32, (int64_t)k * nr));
             AFN_TRY(to_f32_launch(h->V, h->V32, (int64_t)k * nr, s));
         }
-        if (nr > 0) {
+        if (h->method != AFN_METHOD_NYSTROM && nr > 0) {
             AFN_TRY(h->arena.alloc_n(&h->gval32, nr * h->w));
             AFN_TRY(h->arena.alloc_n(&h->tval32, nr * h->w));
             AFN_TRY(to_f32_launch(h->gval, h->gval32, nr * h->w, s));
@@ -322,7 +438,7 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     AFN_HIP(hipEventCreate(&h->kmv_ev[1]));
     AFN_TRY(check_flags(h, s));
     h->nnz = 0;
-    if (nr > 0) AFN_HIP(hipMemcpy(&h->nnz, h->tptr + nr, sizeof(int64_t), hipMemcpyDeviceToHost));
+    if (nr > 0 && h->tptr) AFN_HIP(hipMemcpy(&h->nnz, h->tptr + nr, sizeof(int64_t), hipMemcpyDeviceToHost));
     tm.mark(7, s);
     AFN_HIP(hipStreamSynchronize(s));
     afn_setup_info &inf = h->info;
@@ -338,6 +454,8 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     inf.ms_v = tm.ms(4, 5);
     inf.ms_fsai = tm.ms(5, 6);
     inf.ms_total = tm.ms(0, 7);
+    inf.method = h->method;
+    inf.reserved = 0;
     return AFN_OK;
 }
 
@@ -623,7 +741,7 @@ afn_status afn_setup(const double *X_dev, int64_t n, int32_t d, double l, double
     *out = nullptr;
     if (!X_dev || !prm || n < 1 || n > INT32_MAX - 1 || d < 1 || d > kMaxD || !(l > 0) ||
         !std::isfinite(l) || !(mu >= 0) || !std::isfinite(mu) || prm->k < -1 || prm->k > n ||
-        prm->w < 1 || prm->w > kMaxW || prm->reserved != 0 ||
+        prm->w < 1 || prm->w > kMaxW || prm->method < AFN_METHOD_AFN || prm->method > AFN_METHOD_AUTO ||
         (prm->precision != AFN_FP64 && prm->precision != AFN_FP32) ||
         (prm->precision == AFN_FP32 && d > 8)) {
         set_error("afn_setup: invalid argument (n=%lld d=%d l=%g mu=%g k=%d w=%d)", (long long)n, d,
@@ -785,6 +903,10 @@ afn_status afn_get_fsai(const afn_handle *h, int64_t *rowptr, int32_t *cols_host
     *nnz_out = h->nnz;
     rowptr[0] = 0;
     if (nr <= 0) return AFN_OK;
+    if (!h->cols) {     // Nystrom preconditioner: no FSAI factor
+        for (int64_t p = 0; p < nr; ++p) rowptr[p + 1] = 0;
+        return AFN_OK;
+    }
     std::vector<int32_t> c((size_t)(nr * w));
     std::vector<double> g(vals_host ? (size_t)(nr * w) : 0);
     AFN_HIP(hipMemcpy(c.data(), h->cols, sizeof(int32_t) * nr * w, hipMemcpyDeviceToHost));
@@ -820,7 +942,7 @@ afn_status afn_footprint_bytes(int64_t n, int32_t d, const afn_params *prm, size
 {
     clear_error();
     if (!prm || !bytes || n < 1 || d < 1 || d > kMaxD || prm->w < 1 || prm->w > kMaxW ||
-        prm->k < -1 || prm->k > n) {
+        prm->k < -1 || prm->k > n || prm->method < AFN_METHOD_AFN || prm->method > AFN_METHOD_AUTO) {
         set_error("afn_footprint_bytes: invalid argument");
         return AFN_EINVAL;
     }
@@ -829,28 +951,37 @@ afn_status afn_footprint_bytes(int64_t n, int32_t d, const afn_params *prm, size
     const int64_t nr = n - k, w = prm->w;
     const bool f32 = prm->precision == AFN_FP32;
     auto r = [](int64_t b) { return (size_t)round_up(b > 0 ? b : 1, 256); };
-    size_t t = 0;
-    t += r(64) + r(4 * n) + r(8 * n * d);                                   // flags, perm, Xp
-    if (k > 0) t += 2 * r(8 * k * k) + r(8 * dinv_doubles((int)k));       // L, Linv, Dinv
-    if (nr > 0) t += r(4 * nr * w) + r(8 * nr * w) + r(8 * (nr + 1)) + r(4 * nr * w) + r(8 * nr * w);
-    if (k > 0 && nr > 0) t += r(8 * k * nr);                               // V
-    if (d <= 8) t += r(8 * kmv_packed_doubles(n, d)) + r(4 * n) + r(8 * kmv_box_count(n, d));  // Xs64, kperm, box64
-    if (f32) {
-        t += r(4 * kmv_packed_doubles(n, d)) + r(4 * kmv_box_count(n, d)) + r(4 * k * k) + r(4 * k * nr) +
-             2 * r(4 * nr * w);
-        t += r(4 * work32_floats(n, d, (int)k, nr, nullptr, nullptr));
-    }
-    t += r(8 * work_doubles(n, d, (int)k, nr, nullptr, nullptr));
-    // setup temporaries: landmark indices, FPS workspace, marks, transpose
-    // counters, and the rank-estimation buffers (K_m and its companions)
-    size_t tmp = r(4 * k) + (size_t)fps_workspace_bytes(n) + r(4 * n) +
-                 r((int64_t)fsai_transpose_work_bytes(nr, prm->w)) + r(4 * nr) +
-                 r((int64_t)spatial_order_work_bytes(n, d));
+    // shared by both preconditioners: flags, perm, Xp, packed points, workspaces
+    size_t base = r(64) + r(4 * n) + r(8 * n * d);
+    if (d <= 8) base += r(8 * kmv_packed_doubles(n, d)) + r(4 * n) + r(8 * kmv_box_count(n, d));
+    if (f32) base += r(4 * kmv_packed_doubles(n, d)) + r(4 * kmv_box_count(n, d)) +
+                     r(4 * work32_floats(n, d, (int)k, nr, nullptr, nullptr));
+    base += r(8 * work_doubles(n, d, (int)k, nr, nullptr, nullptr));
+    size_t tmp_base = r(4 * k) + (size_t)fps_workspace_bytes(n) + r(4 * n) +
+                      r((int64_t)spatial_order_work_bytes(n, d));
     if (prm->k < 0) {
         const int64_t m = prm->m > 0 ? (prm->m < n ? prm->m : n) : (n < 2000 ? n : 2000);
-        tmp += r(8 * m * m) + r(8 * m * (d + 16)) + (size_t)fps_workspace_bytes(m) + r(8 * 8 * m);
+        tmp_base += r(8 * m * m) + r(8 * m * (d + 16)) + (size_t)fps_workspace_bytes(m) + r(8 * 8 * m);
     }
-    *bytes = t + tmp;
+    // AFN: L, Linv, Dinv, pattern, G, G^T, V (+ FP32 copies); transpose and row-order temporaries
+    size_t afn = 0;
+    if (k > 0) afn += 2 * r(8 * k * k) + r(8 * dinv_doubles((int)k));
+    if (nr > 0) afn += r(4 * nr * w) + r(8 * nr * w) + r(8 * (nr + 1)) + r(4 * nr * w) + r(8 * nr * w);
+    if (k > 0 && nr > 0) afn += r(8 * k * nr);
+    if (f32) afn += r(4 * k * k) + r(4 * k * nr) + 2 * r(4 * nr * w);
+    afn += r((int64_t)fsai_transpose_work_bytes(nr, prm->w)) + r(4 * nr);
+    // Nystrom: L, Dinv, W, Rginv (+ FP32 W, Rginv); G, its block inverses and GEMM partials
+    size_t nys = 0;
+    if (k > 0) {
+        nys += 2 * r(8 * k * k) + r(8 * dinv_doubles((int)k)) + r(8 * k * n);
+        if (f32) nys += r(4 * k * n) + r(4 * k * k);
+        nys += r(8 * k * k) + r(8 * dinv_doubles((int)k)) + r(8 * gemm_part_elems(k, n)) +
+               r(8 * dot_partials(k * (nr > k ? nr : k))) + r(16);
+    }
+    size_t extra = prm->method == AFN_METHOD_AFN ? afn
+                   : prm->method == AFN_METHOD_NYSTROM ? nys
+                                                       : (afn > nys ? afn : nys);
+    *bytes = base + tmp_base + extra;
     return AFN_OK;
 }
 

@@ -248,7 +248,56 @@ __global__ __launch_bounds__(256) void set_identity(double *A, int k)
     A[e] = i == j ? 1.0 : 0.0;
 }
 
+__global__ __launch_bounds__(256) void add_diag_kernel(double *A, int k, int64_t lda, double shift)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < k) A[i + (int64_t)i * lda] += shift;
+}
+
+__global__ __launch_bounds__(256) void transpose_kernel(const double *A, int k, int64_t lda, double *B,
+                                                        int64_t ldb)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)k * k) return;
+    const int i = (int)(e / k), t = (int)(e - (int64_t)i * k);
+    B[t + (int64_t)i * ldb] = A[i + (int64_t)t * lda];
+}
+
+__global__ __launch_bounds__(256) void zero_upper_kernel(double *A, int k, int64_t lda)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)k * k) return;
+    const int j = (int)(e / k), i = (int)(e - (int64_t)j * k);
+    if (i < j) A[i + (int64_t)j * lda] = 0.0;
+}
+
 }  // namespace
+
+afn_status zero_upper(double *A, int k, int64_t lda, hipStream_t s)
+{
+    if (k <= 0) return AFN_OK;
+    hipLaunchKernelGGL(zero_upper_kernel, dim3((unsigned)ceil_div((int64_t)k * k, 256)), dim3(256), 0, s, A, k,
+                       lda);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status add_diagonal(double *A, int k, int64_t lda, double shift, hipStream_t s)
+{
+    if (k <= 0) return AFN_OK;
+    hipLaunchKernelGGL(add_diag_kernel, dim3((unsigned)ceil_div(k, 256)), dim3(256), 0, s, A, k, lda, shift);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status transpose_square(const double *A, int k, int64_t lda, double *B, int64_t ldb, hipStream_t s)
+{
+    if (k <= 0) return AFN_OK;
+    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)ceil_div((int64_t)k * k, 256)), dim3(256), 0, s, A, k,
+                       lda, B, ldb);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
 
 afn_status fill_k11(const double *Xp, int k, int d, double l, double mu, double *A, int64_t lda,
                     hipStream_t s)

@@ -244,6 +244,13 @@ __global__ __launch_bounds__(256) void to_f32(const double *__restrict__ a, floa
 }
 
 // r = b - y (true residual)
+template <typename T>
+__global__ __launch_bounds__(256) void scale_kernel(T *__restrict__ x, T a, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] *= a;
+}
+
 __global__ __launch_bounds__(256) void sub_kernel(const double *__restrict__ b,
                                                   const double *__restrict__ y,
                                                   double *__restrict__ r, int64_t n)
@@ -505,6 +512,22 @@ afn_status pcg_beta_launch(double *sc, hipStream_t s)
 afn_status sub_launch(const double *b, const double *y, double *r, int64_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(sub_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, b, y, r, n);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status scale_launch(double *x, double a, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return AFN_OK;
+    hipLaunchKernelGGL(scale_kernel<double>, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, x, a, n);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status scale_launch(float *x, float a, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return AFN_OK;
+    hipLaunchKernelGGL(scale_kernel<float>, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, x, a, n);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }
