@@ -239,7 +239,7 @@ def serving_bench(args):
 
     def reqs(arrivals):
         return [serving.Request(i, X, b, q.l, q.mu, arrival=float(arrivals[i]), k=q.k, w=q.w,
-                                k_max=q.k_max, tol=q.tol, maxit=q.maxit)
+                                k_max=q.k_max, tol=q.tol, maxit=q.maxit, method=afn.AFN_METHOD_AUTO)
                 for i, (q, (X, b)) in enumerate(zip(probs, data))]
 
     def progress(label):
@@ -291,6 +291,9 @@ def serving_bench(args):
         "burst": {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in sb.items()},
         "statuses": {str(s): int(c) for s, c in
                      zip(*np.unique([r.status for r in pois], return_counts=True))},
+        "methods": {["afn", "nystrom"][m]: int(c) for m, c in
+                    zip(*np.unique([r.method for r in pois if r.method >= 0], return_counts=True))},
+        "fp64_fallbacks": int(sum(1 for r in pois if r.fp64_iterations > 0)),
     }
     print(json.dumps(out))
 
@@ -304,7 +307,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
-                    help="skip the mixed-precision run on the same input")
+                    help="skip the mixed-precision and Algorithm 5 runs on the same input")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4"],
                     help="c2 (default): the solves/s line; c3: mixed vs FP64 at n=2e5, d=8; "
                          "c4: 64 right-hand sides at n=1.5e5")
@@ -350,8 +353,8 @@ def main():
     b = torch.tensor(b_np, device="cuda")
     afn.lib()
 
-    def step(precision=afn.AFN_FP64):
-        h = afn.afn_setup(X, p.l, p.mu, k=p.k, w=p.w, k_max=p.k_max, precision=precision)
+    def step(precision=afn.AFN_FP64, method=afn.AFN_METHOD_AFN):
+        h = afn.afn_setup(X, p.l, p.mu, k=p.k, w=p.w, k_max=p.k_max, precision=precision, method=method)
         x, info = afn.afn_pcg_solve(h, b, tol=p.tol, maxit=p.maxit)
         sinfo = h.info()
         h.close()
@@ -360,15 +363,15 @@ def main():
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
-    def timed(precision, label):
+    def timed(precision, label, method=afn.AFN_METHOD_AFN):
         log(f"{label}: workload {p.name}; warmup {args.warmup} step(s)")
         for _ in range(args.warmup):
-            step(precision)
+            step(precision, method)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         infos = []
         for _ in range(args.steps):
-            x, info, sinfo = step(precision)
+            x, info, sinfo = step(precision, method)
             infos.append((info, sinfo))
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
@@ -414,6 +417,15 @@ def main():
     mixed = None
     if not args.no_mixed:
         mixed = mixed_block(x64, value)
+    # Algorithm 5 on the same input: Nystrom below the rank switch, AFN above
+    alg5 = None
+    if not args.no_mixed:
+        x5, infos5, el5 = timed(afn.AFN_FP64, "alg5", afn.AFN_METHOD_AUTO)
+        i5, s5 = infos5[-1]
+        alg5 = {"value": round(args.steps / el5, 4), "unit": "solves/s",
+                "method": ["afn", "nystrom"][s5.method], "k": s5.k, "iterations": i5["iterations"],
+                "relres_true": i5["relres_true"], "setup_ms": round(s5.ms["total"], 2),
+                "solve_ms": round(i5["ms_solve"], 2)}
 
     out = {
         "metric": "AFN-PCG solves/s at rel-res 1e-6 (FP64; mixed precision on the same input beside it)",
@@ -436,6 +448,7 @@ def main():
                   "rank": {"r": sinfo.rank_r, "k_est": sinfo.rank_k_est,
                            "eig_branch": sinfo.rank_eig_branch}},
         "mixed": mixed,
+        "alg5": alg5,
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

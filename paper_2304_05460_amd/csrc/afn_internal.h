@@ -89,6 +89,10 @@ afn_status kmv_packed_f32(const float *Xs, int64_t n, int d, double mu, const fl
                           float *y, int64_t ldy, int nrhs, float *part, hipStream_t s,
                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
                           const int32_t *perm = nullptr, const float *box = nullptr);
+// FP32 tiles on packed points with FP64 vectors (part: floats).
+afn_status kmv_packed_f32_dvec(const float *Xs, int64_t n, int d, double mu, const double *v, int64_t ldv,
+                               double *y, int64_t ldy, int nrhs, float *part, hipStream_t s,
+                               const int32_t *perm, const float *box);
 // FP32 tiles and accumulation; FP64 vectors at the interface.
 afn_status kmv_f32(const double *X, int64_t n, int d, double l, double mu, const double *v,
                    int64_t ldv, double *y, int64_t ldy, int nrhs, void *work, hipStream_t s);

@@ -521,6 +521,14 @@ afn_status kmv_packed_f32(const float *Xs, int64_t n, int d, double mu, const fl
                                      ev1, perm, box);
 }
 
+afn_status kmv_packed_f32_dvec(const float *Xs, int64_t n, int d, double mu, const double *v, int64_t ldv,
+                               double *y, int64_t ldy, int nrhs, float *part, hipStream_t s,
+                               const int32_t *perm, const float *box)
+{
+    return kmv_sym_run<float, double>(Xs, sym_shape(n), n, d, mu, v, ldv, y, ldy, nrhs, part, s, nullptr,
+                                      nullptr, perm, box);
+}
+
 afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, const double *v,
                    int64_t ldv, double *y, int64_t ldy, int nrhs, double *work, hipStream_t s,
                    hipEvent_t ev0, hipEvent_t ev1)

@@ -102,6 +102,9 @@ const char *afn_status_string(afn_status s)
 
 const char *afn_last_error(void) { return afn::g_last_error.c_str(); }
 
+// Below this size the ordering costs more than the pruning saves.
+static constexpr int64_t kPruneMinN = 8192;
+
 afn_status kernel_matvec(const double *X_dev, int64_t n, int32_t d, double l, double mu,
                          const double *v_dev, double *y_dev, int32_t nrhs, int64_t ld,
                          int32_t precision, void *stream)
@@ -119,6 +122,55 @@ afn_status kernel_matvec(const double *X_dev, int64_t n, int32_t d, double l, do
     }
     hipStream_t s = (hipStream_t)stream;
     void *work = nullptr;
+    if (d <= 8 && n >= kPruneMinN) {
+        // spatial order, packed points and tile boxes: far-apart tile pairs are
+        // skipped (kernel values below 2^-64 in FP64 tiles, 2^-44 in FP32)
+        const bool f32 = precision == AFN_FP32;
+        const int64_t npad = afn::kmv_packed_doubles(n, d) / d;
+        const int64_t R = nrhs >= 2 ? (nrhs < 64 ? nrhs : 64) : 0;
+        const size_t ob = afn::round_up((int64_t)afn::spatial_order_work_bytes(n, d), 256);
+        const size_t pb = afn::round_up(4 * n, 256);
+        const size_t xb = afn::round_up(8 * npad * d, 256);
+        const size_t bb = afn::round_up(8 * afn::kmv_box_count(n, d), 256);
+        const size_t wb = nrhs >= 2 ? sizeof(double) * (size_t)(2 * n * R + afn::mrhs_part_elems(npad))
+                                    : sizeof(double) * (size_t)afn::kmv_workspace_doubles(n, d);
+        AFN_TRY(afn::library_scratch(ob + pb + xb + bb + wb + 1024, &work));
+        char *base = (char *)work;
+        void *ows = base;
+        int32_t *kperm = (int32_t *)(base + ob);
+        void *Xs = base + ob + pb;
+        void *box = base + ob + pb + xb;
+        double *rest = (double *)(base + ob + pb + xb + bb);
+        AFN_TRY(afn::spatial_order(X_dev, n, d, kperm, ows, s));
+        AFN_TRY(afn::kmv_pack(X_dev, n, d, l, Xs, f32, s, kperm));
+        AFN_TRY(afn::kmv_boxes(Xs, n, d, f32, box, s));
+        if (nrhs >= 2) {
+            double *Pr = rest;
+            double *Yr = Pr + n * R;
+            double *part = Yr + n * R;
+            for (int64_t c0 = 0; c0 < nrhs; c0 += 64) {
+                const int Rc = (int)(nrhs - c0 < 64 ? nrhs - c0 : 64);
+                if (f32) {
+                    AFN_TRY(afn::gather_rows<float>(v_dev + c0 * ld, ld, nullptr, n, Rc, nullptr, (float *)Pr, s));
+                    AFN_TRY(afn::kmv_mrhs_run<float>((const float *)Xs, npad, n, d, mu, (const float *)Pr, Rc,
+                                                     (float *)Yr, Rc, Rc, (float *)part, s, nullptr, nullptr,
+                                                     kperm, (const float *)box));
+                    AFN_TRY(afn::scatter_rows_f32((const float *)Yr, n, Rc, y_dev + c0 * ld, ld, s));
+                } else {
+                    AFN_TRY(afn::gather_rows<double>(v_dev + c0 * ld, ld, nullptr, n, Rc, nullptr, Pr, s));
+                    AFN_TRY(afn::kmv_mrhs_run<double>((const double *)Xs, npad, n, d, mu, Pr, Rc, Yr, Rc, Rc,
+                                                      part, s, nullptr, nullptr, kperm, (const double *)box));
+                    AFN_TRY(afn::scatter_rows(Yr, nullptr, n, Rc, y_dev + c0 * ld, ld, s));
+                }
+            }
+            return AFN_OK;
+        }
+        if (f32)
+            return afn::kmv_packed_f32_dvec((const float *)Xs, n, d, mu, v_dev, ld, y_dev, ld, nrhs,
+                                            (float *)rest, s, kperm, (const float *)box);
+        return afn::kmv_packed_f64((const double *)Xs, n, d, mu, v_dev, ld, y_dev, ld, nrhs, rest, s, nullptr,
+                                   nullptr, kperm, (const double *)box);
+    }
     if (nrhs >= 2 && d <= 8) {
         // many columns: MFMA tile kernel on point-major blocks of <= 64 columns
         const int64_t npad = afn::kmv_packed_doubles(n, d) / d;

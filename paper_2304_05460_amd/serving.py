@@ -41,6 +41,7 @@ class Request:
     w: int = 64
     k_max: int = 2000
     tol: float = 1e-6
+    method: int = afn.AFN_METHOD_AFN
     maxit: int = 500
 
 
@@ -58,6 +59,8 @@ class Result:
     outer_iterations: int = 0
     relres_true: float = float("nan")
     k: int = 0
+    method: int = -1
+    fp64_iterations: int = 0
     x: torch.Tensor | None = None
     error: str = ""
 
@@ -86,7 +89,7 @@ class Server:
     def footprint(self, r: Request) -> int:
         n, d = r.X.shape
         fp = afn.afn_footprint_bytes(n, d, k=r.k, w=r.w, k_max=r.k_max,
-                                     precision=self.precision)
+                                     precision=self.precision, method=r.method)
         return fp + 8 * n * (d + 2) + (1 << 20)     # inputs, solution, allocator slack
 
     def _make_stream(self):
@@ -98,15 +101,17 @@ class Server:
                 X = torch.from_numpy(np.ascontiguousarray(r.X)).to(self.device, non_blocking=False)
                 b = torch.from_numpy(np.ascontiguousarray(r.b)).to(self.device, non_blocking=False)
                 h = afn.afn_setup(X, r.l, r.mu, k=r.k, w=r.w, k_max=r.k_max,
-                                  precision=self.precision, stream=stream)
+                                  precision=self.precision, method=r.method, stream=stream)
                 try:
                     x, info = afn.afn_pcg_solve(h, b, tol=r.tol, maxit=r.maxit, stream=stream)
-                    res.k = h.info().k
+                    si = h.info()
+                    res.k, res.method = si.k, si.method
                 finally:
                     h.close()
                 res.status = info["status"]
                 res.iterations = info["iterations"]
                 res.outer_iterations = info["outer_iterations"]
+                res.fp64_iterations = info["fp64_iterations"]
                 res.relres_true = info["relres_true"]
                 if self.keep_x:
                     res.x = x.cpu() if self.keep_x == "host" else x

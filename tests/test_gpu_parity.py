@@ -92,15 +92,61 @@ def test_kernel_matvec_fp32_tiles(afn, n, d, l, pts):
     assert np.all(np.abs(y - yo) <= bound), np.max(np.abs(y - yo) / ab)
 
 
+# At n >= 8192 the kernels skip tile pairs whose kernel values are all below
+# 2^-64 (FP64 tiles) or 2^-44 (FP32 tiles): each row may drop up to that
+# bound times sum_j |v_j|, added to the rounding bounds below.
+PRUNE64, PRUNE32 = 2.0 ** -64, 2.0 ** -44
+
+
+def sample_rows(n, seed, count=40):
+    return np.concatenate([np.arange(5), np.random.default_rng(seed).integers(0, n, count),
+                           np.arange(n - 5, n)])
+
+
 def test_kernel_matvec_large_sampled_rows(afn):
     p = W.c2(0.1)
     X = W.points(p.points, p.n, p.d, p.seed)
     v = np.random.default_rng(17).standard_normal(p.n)
     y = afn.kernel_matvec(dev(X), p.l, p.mu, dev(v)).cpu().numpy()
-    rows = np.concatenate([np.arange(5), np.random.default_rng(18).integers(0, p.n, 40),
-                           np.arange(p.n - 5, p.n)])
+    rows = sample_rows(p.n, 18)
     yo, ab = oracle.kernel_matvec_rows(X, p.l, p.mu, v, rows)
-    assert np.all(np.abs(y[rows] - yo) <= 2 * (p.n + 4) * U * ab)
+    assert np.all(np.abs(y[rows] - yo) <= 2 * (p.n + 4) * U * ab + PRUNE64 * np.abs(v).sum())
+
+
+def test_kernel_matvec_full_size_fp32_and_d8(afn):
+    # the benchmark's mixture at n = 1e5 with FP32 tiles; 2e5 normal points in R^8 (FP64)
+    p = W.c2(0.1)
+    X = W.points(p.points, p.n, p.d, p.seed)
+    v = np.random.default_rng(21).standard_normal(p.n)
+    y = afn.kernel_matvec(dev(X), p.l, p.mu, dev(v), precision=afn.AFN_FP32).cpu().numpy()
+    rows = sample_rows(p.n, 22)
+    yo, ab = oracle.kernel_matvec_rows(X, p.l, p.mu, v, rows)
+    bound = (30 * (p.d + 4) * math.log(2) + p.n + 8) * U32 * ab + (1e-13 + PRUNE32) * np.abs(v).sum()
+    assert np.all(np.abs(y[rows] - yo) <= bound), np.max(np.abs(y[rows] - yo) / bound)
+    q = W.C3
+    X = W.points(q.points, q.n, q.d, q.seed)
+    v = np.random.default_rng(23).standard_normal(q.n)
+    y = afn.kernel_matvec(dev(X), q.l, q.mu, dev(v)).cpu().numpy()
+    rows = sample_rows(q.n, 24, count=20)
+    yo, ab = oracle.kernel_matvec_rows(X, q.l, q.mu, v, rows)
+    assert np.all(np.abs(y[rows] - yo) <= 2 * (q.n + 4) * U * ab + PRUNE64 * np.abs(v).sum())
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_kernel_matvec_full_size_64_columns(afn, prec):
+    # 1.5e5 uniform points, l = 0.05, 64 columns: the MFMA tile kernel with pruning
+    p = W.C4
+    X = W.points(p.points, p.n, p.d, p.seed)
+    V = np.random.default_rng(25).standard_normal((p.n, 64))
+    Y = afn.kernel_matvec(dev(X), p.l, p.mu, dev(V.T).t(), precision=prec).cpu().numpy()
+    rows = sample_rows(p.n, 26, count=15)
+    for c in (0, 31, 63):
+        yo, ab = oracle.kernel_matvec_rows(X, p.l, p.mu, V[:, c], rows)
+        if prec == 0:
+            bound = 2 * (p.n + 4) * U * ab + PRUNE64 * np.abs(V[:, c]).sum()
+        else:
+            bound = (30 * (p.d + 4) * math.log(2) + p.n + 8) * U32 * ab + (1e-13 + PRUNE32) * np.abs(V[:, c]).sum()
+        assert np.all(np.abs(Y[rows, c] - yo) <= bound), (c, np.max(np.abs(Y[rows, c] - yo) / bound))
 
 
 def test_kernel_matvec_invalid_arguments(afn):
