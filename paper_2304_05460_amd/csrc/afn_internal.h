@@ -152,7 +152,7 @@ afn_status fsai_rows(const double *Xp, int64_t n, int k, int d, double l, double
                      const int32_t *order, hipStream_t s);
 
 // ---------------------------------------------------------------- spatial order
-// order[q] = index of the point at position q: Morton order of grid cells over
+// order[q] = index of the point at position q: Hilbert order of grid cells over
 // the points X (n x d row-major), ascending index inside a cell.
 // Deterministic.  work: spatial_order_work_bytes(n, d).
 size_t spatial_order_work_bytes(int64_t n, int d);

@@ -143,6 +143,11 @@ __global__ __launch_bounds__(256) void kmv_sym(const T *__restrict__ Xs, int64_t
     const int64_t SB = (int64_t)ST * kTile;
     const bool diag_super = BI == BJ;
     for (int e = tid; e < kMaxST * kTile; e += 256) (&colacc[0][0])[e] = T(0);
+    // pruning decisions for all ST x ST tile pairs, one per thread
+    __shared__ unsigned char keep[kMaxST * kMaxST];
+    if (tid < ST * ST)
+        keep[tid] = !box || box_gap2<D, T>(box, (int64_t)BI * ST + tid / ST, (int64_t)BJ * ST + tid % ST) < tcut;
+    __syncthreads();
     T *rowout = part + (int64_t)blockIdx.x * 2 * SB;
     T *colout = rowout + SB;
     for (int ti = 0; ti < ST; ++ti) {
@@ -158,8 +163,7 @@ __global__ __launch_bounds__(256) void kmv_sym(const T *__restrict__ Xs, int64_t
         }
         for (int tj = diag_super ? ti : 0; tj < ST; ++tj) {
             const int64_t j0 = BJ * SB + (int64_t)tj * kTile;
-            // uniform over the workgroup: every thread reads the same two boxes
-            if (box && box_gap2<D, T>(box, (int64_t)BI * ST + ti, (int64_t)BJ * ST + tj) >= tcut) continue;
+            if (!keep[ti * ST + tj]) continue;
             __syncthreads();
             for (int e = tid; e < kTile * (D + 1); e += 256) {
                 const int t = e / kTile, j = e % kTile;

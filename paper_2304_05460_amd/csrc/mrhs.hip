@@ -122,49 +122,69 @@ __global__ __launch_bounds__(512) void kmv_mrhs(const T *__restrict__ Xs, int64_
             rhi[t] = ahi > bhi ? ahi : bhi;
         }
     }
-    for (int64_t J = J0; J < J1; ++J) {
-        const int64_t j0 = J * TL;
-        if (box) {
-            // uniform over the workgroup: every thread reads the same boxes
+    // candidate column tiles in chunks of 512: every thread tests one, the
+    // survivors are listed in ascending order (the summation order over tiles
+    // is the same as without pruning)
+    __shared__ int jlist[512];
+    __shared__ int wcnt[8];
+    for (int64_t Jc = J0; Jc < J1; Jc += 512) {
+        const int64_t Jt = Jc + tid;
+        bool keep = Jt < J1;
+        if (keep && box) {
             T g2 = T(0);
 #pragma unroll
             for (int t = 0; t < D; ++t) {
-                const T blo = box[(J * D + t) * 2], bhi = box[(J * D + t) * 2 + 1];
+                const T blo = box[(Jt * D + t) * 2], bhi = box[(Jt * D + t) * 2 + 1];
                 T gap = blo - rhi[t] > rlo[t] - bhi ? blo - rhi[t] : rlo[t] - bhi;
                 gap = gap > T(0) ? gap : T(0);
                 g2 = fmaT(gap, gap, g2);
             }
-            if (g2 >= tcut) continue;
+            keep = g2 < tcut;
         }
+        const unsigned long long mask = __ballot(keep);
         __syncthreads();
-        for (int e = tid; e < D * TL; e += 512) {
-            const int t = e / TL, j = e % TL;
-            cx[t][j] = Xs[(int64_t)t * npad + j0 + j];
-        }
-        for (int e = tid; e < TL * RP; e += 512) {
-            const int k = e / RP, c = e % RP;
-            const int64_t q = j0 + k;
-            PJ[k][c] = (q < n && c < R) ? P[(perm ? (int64_t)perm[q] : q) * ldp + c] : T(0);
-        }
+        if (lane == 0) wcnt[wave] = (int)__popcll(mask);
         __syncthreads();
-#pragma unroll 4
-        for (int c = 0; c < 16; ++c) {
-            const int j = cgrp * 16 + c;
-            T d2 = T(0);
+        int before = 0, total = 0;
 #pragma unroll
-            for (int t = 0; t < D; ++t) {
-                const T del = xi[t] - cx[t][j];
-                d2 = fmaT(del, del, d2);
+        for (int w2 = 0; w2 < 8; ++w2) {
+            before += w2 < wave ? wcnt[w2] : 0;
+            total += wcnt[w2];
+        }
+        if (keep) jlist[before + (int)__popcll(mask & ((1ull << lane) - 1ull))] = tid;
+        __syncthreads();
+        for (int qj = 0; qj < total; ++qj) {
+            const int64_t j0 = (Jc + jlist[qj]) * TL;
+            __syncthreads();
+            for (int e = tid; e < D * TL; e += 512) {
+                const int t = e / TL, j = e % TL;
+                cx[t][j] = Xs[(int64_t)t * npad + j0 + j];
             }
-            EsT[j][half * 64 + lane] = kexp2(d2);
-        }
-        __syncthreads();
+            for (int e = tid; e < TL * RP; e += 512) {
+                const int k = e / RP, c = e % RP;
+                const int64_t q = j0 + k;
+                PJ[k][c] = (q < n && c < R) ? P[(perm ? (int64_t)perm[q] : q) * ldp + c] : T(0);
+            }
+            __syncthreads();
 #pragma unroll 4
-        for (int kk = 0; kk < TL / 4; ++kk) {
-            const int k = 4 * kk + (lane >> 4);
-            const T a = EsT[k][16 * wave + (lane & 15)];
+            for (int c = 0; c < 16; ++c) {
+                const int j = cgrp * 16 + c;
+                T d2 = T(0);
 #pragma unroll
-            for (int b = 0; b < NB; ++b) acc[b] = M::op(a, PJ[k][16 * b + (lane & 15)], acc[b]);
+                for (int t = 0; t < D; ++t) {
+                    const T del = xi[t] - cx[t][j];
+                    d2 = fmaT(del, del, d2);
+                }
+                EsT[j][half * 64 + lane] = kexp2(d2);
+            }
+            __syncthreads();
+#pragma unroll 4
+            for (int kk = 0; kk < TL / 4; ++kk) {
+                const int k = 4 * kk + (lane >> 4);
+                const T a = EsT[k][16 * wave + (lane & 15)];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) acc[b] = M::op(a, PJ[k][16 * b + (lane & 15)], acc[b]);
+            }
         }
     }
     T *out = part + (int64_t)blockIdx.y * npad * RP;

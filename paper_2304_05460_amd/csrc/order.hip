@@ -2,10 +2,13 @@
 //
 // The points are binned into a grid of at most 2^18 cells over their bounding
 // box (B bits per coordinate on the first D' coordinates, B * D' <= 18), the
-// cells are visited in Morton (bit-interleaved) order, and the points of one
-// cell in ascending index.  Counting sort: cell counts, exclusive scan, an
-// atomic scatter into the cell segments, then one wavefront per cell ranks its
-// entries by index, so the result does not depend on scheduling.
+// cells are visited along a Hilbert curve (consecutive cells are neighbours,
+// so runs of consecutive points stay compact), and the points of one cell in
+// ascending index.  The Hilbert index comes from Skilling's transpose
+// algorithm ("Programming the Hilbert curve", AIP Conf. Proc. 707, 2004).
+// Counting sort: cell counts, exclusive scan, an atomic scatter into the cell
+// segments, then one wavefront per cell ranks its entries by index, so the
+// result does not depend on scheduling.
 //
 // Uses: the tile kernels of the kernel matvec read the points in this order
 // (nearby points share tiles, so tile pairs that are far apart can be
@@ -67,19 +70,48 @@ __global__ __launch_bounds__(64) void bbox_final(const double *part, int nb, int
     box[2 * t + 1] = b;
 }
 
+// Hilbert index of the cell with coordinates x[0..dims) (each < 2^bits):
+// undo the excess work of the curve's reflections and rotations, Gray-encode,
+// then interleave the transposed bits (most significant axis first).
+__device__ uint32_t hilbert_index(uint32_t *x, int bits, int dims)
+{
+    const uint32_t M = 1u << (bits - 1);
+    for (uint32_t Q = M; Q > 1; Q >>= 1) {
+        const uint32_t P = Q - 1;
+        for (int i = 0; i < dims; ++i) {
+            if (x[i] & Q) {
+                x[0] ^= P;
+            } else {
+                const uint32_t t = (x[0] ^ x[i]) & P;
+                x[0] ^= t;
+                x[i] ^= t;
+            }
+        }
+    }
+    for (int i = 1; i < dims; ++i) x[i] ^= x[i - 1];
+    uint32_t t = 0;
+    for (uint32_t Q = M; Q > 1; Q >>= 1)
+        if (x[dims - 1] & Q) t ^= Q - 1;
+    for (int i = 0; i < dims; ++i) x[i] ^= t;
+    uint32_t h = 0;
+    for (int b = 0; b < bits; ++b)
+        for (int i = 0; i < dims; ++i) h |= ((x[i] >> b) & 1u) << (b * dims + (dims - 1 - i));
+    return h;
+}
+
 __global__ __launch_bounds__(256) void cell_keys(const double *X, int64_t n, int d, int bits, int dims,
                                                  const double *box, int32_t *key, unsigned long long *cnt)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const int cells1 = 1 << bits;
-    uint32_t kk = 0;
+    uint32_t x[kCellBits];
     for (int t = 0; t < dims; ++t) {
         const double lo = box[2 * t], span = box[2 * t + 1] - lo;
         int q = span > 0.0 ? (int)((X[i * d + t] - lo) / span * cells1) : 0;
-        q = q < 0 ? 0 : (q >= cells1 ? cells1 - 1 : q);
-        for (int bb = 0; bb < bits; ++bb) kk |= (uint32_t)((q >> bb) & 1) << (bb * dims + t);
+        x[t] = (uint32_t)(q < 0 ? 0 : (q >= cells1 ? cells1 - 1 : q));
     }
+    const uint32_t kk = dims == 1 ? x[0] : hilbert_index(x, bits, dims);
     key[i] = (int32_t)kk;
     atomicAdd(&cnt[kk], 1ULL);
 }
