@@ -111,6 +111,8 @@ typedef struct afn_setup_info {
     int32_t method;          /* afn_method built: AFN_METHOD_AFN or _NYSTROM       */
     int32_t reserved;
     double nu;               /* Nystrom stabilizing shift (0 for AFN)              */
+    double kmv_kept_f64;     /* fraction of tile pairs the pruned kernel matvec   */
+    double kmv_kept_f32;     /* evaluates with FP64 / FP32 tiles (1 if not pruned) */
 } afn_setup_info;
 
 /* Result of a PCG solve. */

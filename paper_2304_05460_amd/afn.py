@@ -56,7 +56,8 @@ class afn_setup_info(ctypes.Structure):
                 ("ms_chol", ctypes.c_double), ("ms_knn", ctypes.c_double),
                 ("ms_v", ctypes.c_double), ("ms_fsai", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("method", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("nu", ctypes.c_double)]
+                ("reserved", ctypes.c_int32), ("nu", ctypes.c_double),
+                ("kmv_kept_f64", ctypes.c_double), ("kmv_kept_f32", ctypes.c_double)]
 
 
 class afn_solve_info(ctypes.Structure):
@@ -174,6 +175,8 @@ class SetupInfo:
     ms: dict
     method: int = 0
     nu: float = 0.0
+    kmv_kept_f64: float = 1.0
+    kmv_kept_f32: float = 1.0
 
 
 class Handle:
@@ -206,7 +209,8 @@ class Handle:
         ms = {k: getattr(inf, "ms_" + k) for k in ("rank", "fps", "chol", "knn", "v", "fsai",
                                                    "total")}
         return SetupInfo(inf.n, inf.d, inf.k, inf.w, inf.rank_r, inf.rank_k_est,
-                         inf.rank_eig_branch, inf.rank_eig_count, inf.nnz_g, ms, inf.method, inf.nu)
+                         inf.rank_eig_branch, inf.rank_eig_count, inf.nnz_g, ms, inf.method, inf.nu,
+                         inf.kmv_kept_f64, inf.kmv_kept_f32)
 
     def landmarks(self):
         import numpy as np

@@ -78,6 +78,10 @@ afn_status kmv_pack(const double *X, int64_t n, int d, double l, void *Xs, bool 
 constexpr double kCullF64 = 64.0;
 constexpr double kCullF32 = 44.0;
 int64_t kmv_box_count(int64_t n, int d);
+// counts[0] = unordered pairs of non-empty tiles kept at cut tcut, counts[1] =
+// all such pairs (FP64 boxes, d <= 8).
+afn_status kmv_kept_fraction(const double *box, int64_t n, int d, double tcut, unsigned long long *counts,
+                             hipStream_t s);
 afn_status kmv_boxes(const void *Xs, int64_t n, int d, bool f32, void *box, hipStream_t s);
 // y = (K + mu I) v on packed points (d <= 8); part: kmv_workspace_doubles(n, d)
 // doubles (or floats for the FP32 variant).  box (optional) enables pruning.

@@ -495,6 +495,47 @@ afn_status kmv_pack(const double *X, int64_t n, int d, double l, void *Xs, bool 
 
 int64_t kmv_box_count(int64_t n, int d) { return sym_shape(n).npad / kTile * d * 2; }
 
+namespace {
+
+// Unordered pairs (a <= b) of non-empty tiles that the pruned kernels evaluate
+// at cut^2 = tcut, and all such pairs (counts[0], counts[1]).
+template <int D>
+__global__ __launch_bounds__(256) void count_kept_pairs(const double *__restrict__ box, int64_t ntiles,
+                                                        int64_t a0, double tcut, unsigned long long *counts)
+{
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t a = a0 + blockIdx.y;
+    if (b >= ntiles || b < a) return;
+    if (!(box[a * D * 2] <= box[a * D * 2 + 1]) || !(box[b * D * 2] <= box[b * D * 2 + 1])) return;
+    atomicAdd(&counts[1], 1ULL);
+    if (box_gap2<D, double>(box, a, b) < tcut) atomicAdd(&counts[0], 1ULL);
+}
+
+}  // namespace
+
+afn_status kmv_kept_fraction(const double *box, int64_t n, int d, double tcut, unsigned long long *counts,
+                             hipStream_t s)
+{
+    const int64_t ntiles = sym_shape(n).npad / kTile;
+    AFN_HIP(hipMemsetAsync(counts, 0, 2 * sizeof(unsigned long long), s));
+    for (int64_t a0 = 0; a0 < ntiles; a0 += 32768) {
+        const int64_t rows = ntiles - a0 < 32768 ? ntiles - a0 : 32768;
+        const dim3 g((unsigned)ceil_div(ntiles, 256), (unsigned)rows);
+        switch (d) {
+            case 1: hipLaunchKernelGGL(count_kept_pairs<1>, g, dim3(256), 0, s, box, ntiles, a0, tcut, counts); break;
+            case 2: hipLaunchKernelGGL(count_kept_pairs<2>, g, dim3(256), 0, s, box, ntiles, a0, tcut, counts); break;
+            case 3: hipLaunchKernelGGL(count_kept_pairs<3>, g, dim3(256), 0, s, box, ntiles, a0, tcut, counts); break;
+            case 4: hipLaunchKernelGGL(count_kept_pairs<4>, g, dim3(256), 0, s, box, ntiles, a0, tcut, counts); break;
+            case 5: hipLaunchKernelGGL(count_kept_pairs<5>, g, dim3(256), 0, s, box, ntiles, a0, tcut, counts); break;
+            case 6: hipLaunchKernelGGL(count_kept_pairs<6>, g, dim3(256), 0, s, box, ntiles, a0, tcut, counts); break;
+            case 7: hipLaunchKernelGGL(count_kept_pairs<7>, g, dim3(256), 0, s, box, ntiles, a0, tcut, counts); break;
+            default: hipLaunchKernelGGL(count_kept_pairs<8>, g, dim3(256), 0, s, box, ntiles, a0, tcut, counts); break;
+        }
+        AFN_HIP(hipGetLastError());
+    }
+    return AFN_OK;
+}
+
 afn_status kmv_boxes(const void *Xs, int64_t n, int d, bool f32, void *box, hipStream_t s)
 {
     const SymShape sh = sym_shape(n);

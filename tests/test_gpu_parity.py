@@ -580,3 +580,18 @@ def test_mixed_falls_back_to_fp64(afn, n, l, mu, k, tol):
     assert i32["status"] == i64["status"]
     assert t32 <= max(10.0 * t64, tol)
     assert abs(i32["relres_true"] - t32) <= 1e-3 * t32 + f32
+
+
+def test_pruned_pair_fraction(afn):
+    # a short length-scale leaves few tile pairs above 2^-64; a long one keeps all
+    X = dev(W.points("uniform", 20000, 3, 91))
+    h = afn.afn_setup(X, 0.01, 1e-3, k=50, w=8)
+    inf = h.info()
+    h.close()
+    say("kept fractions l=0.01", inf.kmv_kept_f64, inf.kmv_kept_f32)
+    assert 0.0 < inf.kmv_kept_f32 <= inf.kmv_kept_f64 < 0.2
+    h = afn.afn_setup(X, 10.0, 1e-3, k=50, w=8)
+    inf = h.info()
+    h.close()
+    assert inf.kmv_kept_f64 == 1.0 and inf.kmv_kept_f32 == 1.0
+
