@@ -171,6 +171,51 @@ def c3_bench(args):
            "tol": p.tol, "maxit": p.maxit}, c3=res)
 
 
+def highd_bench(args):
+    """n = 49990 uniform points in [0,1]^22, l = 1, mu = n 1e-6, adaptive k <= 2000:
+    Algorithm 2 takes uniform landmarks above d = 10; FP64 (the packed tile
+    kernels cover d <= 8, so the generic FP64 tile kernel runs)."""
+    import torch
+    from paper_2304_05460_amd import afn, workloads as W
+
+    p = W.HIGHD
+    X_np, b_np = W.make(p)
+    X = torch.tensor(X_np, device="cuda")
+    b = torch.tensor(b_np, device="cuda")
+    afn.lib()
+
+    def step():
+        h = afn.afn_setup(X, p.l, p.mu, k=p.k, w=p.w, k_max=p.k_max)
+        x, info = afn.afn_pcg_solve(h, b, tol=p.tol, maxit=p.maxit)
+        si = h.info()
+        h.close()
+        return info, si
+
+    print(f"[bench] highd warmup", file=sys.stderr, flush=True)
+    info, si = step()
+    print(f"[bench] highd warmup done: {afn.status_name(info['status'])} {info['iterations']} its, "
+          f"setup {si.ms['total']:.0f} ms, solve {info['ms_solve']:.0f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for st in range(args.steps):
+        infos.append(step())
+        print(f"[bench] highd step {st + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    info, si = infos[-1]
+    _line("AFN-PCG solves/s at rel-res 1e-6 (FP64, d = 22, uniform landmarks)", args.steps / el,
+          "solves/s", args.steps, 1, el / args.steps * 1e3, "f64",
+          {"workload": p.name, "n": p.n, "d": p.d, "l": p.l, "mu": p.mu, "k": si.k, "w": p.w,
+           "tol": p.tol},
+          highd={"status": afn.status_name(info["status"]), "iterations": info["iterations"],
+                 "relres_true": info["relres_true"], "landmarks": ["auto", "fps", "uniform"][si.landmarks],
+                 "rank": {"r": si.rank_r, "k_est": si.rank_k_est}, "setup_ms": round(si.ms["total"], 1),
+                 "setup_phases_ms": {k: round(v, 1) for k, v in si.ms.items()},
+                 "solve_ms": round(info["ms_solve"], 1),
+                 "kmv_avg_launch_ms": round(info["ms_matvec"] / max(info["matvec_launches"], 1), 3)})
+
+
 def c4_bench(args):
     """n = 1.5e5 uniform in [0,1]^3, l = 0.05, mu = 1e-4, k = 3000, w = 64, 64
     right-hand sides: FP32 setup + graph-captured block PCG with per-column FP64
@@ -311,9 +356,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision and Algorithm 5 runs on the same input")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "highd"],
                     help="c2 (default): the solves/s line; c3: mixed vs FP64 at n=2e5, d=8; "
-                         "c4: 64 right-hand sides at n=1.5e5")
+                         "c4: 64 right-hand sides at n=1.5e5; highd: n=49990, d=22 (uniform landmarks)")
     ap.add_argument("--serving", action="store_true",
                     help="run the mixed-size request stream instead (p50/p99 latency, solves/s)")
     ap.add_argument("--serving-count", type=int, default=256)
@@ -348,6 +393,9 @@ def main():
         return
     if args.workload == "c4":
         c4_bench(args)
+        return
+    if args.workload == "highd":
+        highd_bench(args)
         return
 
     p = W.c2(args.l, tol=args.tol)

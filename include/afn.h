@@ -84,6 +84,17 @@ typedef enum afn_method {
     AFN_METHOD_AUTO = 2
 } afn_method;
 
+/* Landmark selection (Algorithm 2): AFN_LANDMARKS_AUTO = farthest point
+ * sampling (Algorithm 6) for d <= 10 and uniform sampling above;
+ * AFN_LANDMARKS_FPS / AFN_LANDMARKS_UNIFORM force one of them.  Uniform
+ * sampling takes the first k entries of the splitmix64 partial Fisher-Yates
+ * shuffle of 0..n-1 seeded with seed + 1 (k <= 4096), in that order. */
+typedef enum afn_landmarks {
+    AFN_LANDMARKS_AUTO = 0,
+    AFN_LANDMARKS_FPS = 1,
+    AFN_LANDMARKS_UNIFORM = 2
+} afn_landmarks;
+
 /* Construction parameters (Algorithm 2, Algorithm 4, Algorithm 5). */
 typedef struct afn_params {
     int32_t k;          /* landmark count; -1 = estimate it (Algorithm 4)         */
@@ -93,6 +104,8 @@ typedef struct afn_params {
     int32_t precision;  /* afn_precision of the PCG solve (AFN_FP32 needs d <= 8)   */
     int32_t method;     /* afn_method                                              */
     uint64_t seed;      /* seed of the rank-estimation subsample (splitmix64)      */
+    int32_t landmarks;  /* afn_landmarks                                           */
+    int32_t reserved;   /* must be 0                                               */
 } afn_params;
 
 /* Facts about a constructed preconditioner. */
@@ -109,7 +122,7 @@ typedef struct afn_setup_info {
     double ms_rank, ms_fps, ms_chol, ms_knn, ms_v, ms_fsai, ms_total;  /* phase times;
                                 Nystrom: ms_fsai = forming and factoring B^T B + mu I */
     int32_t method;          /* afn_method built: AFN_METHOD_AFN or _NYSTROM       */
-    int32_t reserved;
+    int32_t landmarks;       /* AFN_LANDMARKS_FPS or _UNIFORM, as used             */
     double nu;               /* Nystrom stabilizing shift (0 for AFN)              */
     double kmv_kept_f64;     /* fraction of tile pairs the pruned kernel matvec   */
     double kmv_kept_f32;     /* evaluates with FP64 / FP32 tiles (1 if not pruned) */

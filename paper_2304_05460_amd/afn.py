@@ -21,6 +21,7 @@ AFN_OK, AFN_EINVAL, AFN_ENOMEM, AFN_ENOTSPD, AFN_ENOCONV, AFN_EBREAKDOWN, AFN_ES
     AFN_EDEVICE = range(8)
 AFN_FP64, AFN_FP32 = 0, 1
 AFN_METHOD_AFN, AFN_METHOD_NYSTROM, AFN_METHOD_AUTO = 0, 1, 2
+AFN_LANDMARKS_AUTO, AFN_LANDMARKS_FPS, AFN_LANDMARKS_UNIFORM = 0, 1, 2
 _STATUS_NAMES = ["AFN_OK", "AFN_EINVAL", "AFN_ENOMEM", "AFN_ENOTSPD", "AFN_ENOCONV",
                  "AFN_EBREAKDOWN", "AFN_ESTAGNATION", "AFN_EDEVICE"]
 
@@ -44,7 +45,8 @@ class AFNError(RuntimeError):
 class afn_params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("k_max", ctypes.c_int32), ("w", ctypes.c_int32),
                 ("m", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("method", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("method", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("landmarks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class afn_setup_info(ctypes.Structure):
@@ -56,7 +58,7 @@ class afn_setup_info(ctypes.Structure):
                 ("ms_chol", ctypes.c_double), ("ms_knn", ctypes.c_double),
                 ("ms_v", ctypes.c_double), ("ms_fsai", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("method", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("nu", ctypes.c_double),
+                ("landmarks", ctypes.c_int32), ("nu", ctypes.c_double),
                 ("kmv_kept_f64", ctypes.c_double), ("kmv_kept_f32", ctypes.c_double)]
 
 
@@ -177,6 +179,7 @@ class SetupInfo:
     nu: float = 0.0
     kmv_kept_f64: float = 1.0
     kmv_kept_f32: float = 1.0
+    landmarks: int = 1
 
 
 class Handle:
@@ -210,7 +213,7 @@ class Handle:
                                                    "total")}
         return SetupInfo(inf.n, inf.d, inf.k, inf.w, inf.rank_r, inf.rank_k_est,
                          inf.rank_eig_branch, inf.rank_eig_count, inf.nnz_g, ms, inf.method, inf.nu,
-                         inf.kmv_kept_f64, inf.kmv_kept_f32)
+                         inf.kmv_kept_f64, inf.kmv_kept_f32, inf.landmarks)
 
     def landmarks(self):
         import numpy as np
@@ -245,12 +248,13 @@ class Handle:
 
 def afn_setup(X: torch.Tensor, l: float, mu: float, k: int = -1, w: int = 64, k_max: int = 2000,
               m: int = 0, seed: int = 0, precision: int = AFN_FP64, method: int = AFN_METHOD_AFN,
-              stream=None) -> Handle:
+              landmarks: int = AFN_LANDMARKS_AUTO, stream=None) -> Handle:
     """Algorithm 2 (landmarks by FPS, chol(K11 + mu I), FSAI of the Schur complement),
     or the Nystrom preconditioner, or Algorithm 5's choice between them (method)."""
     X = _dev_f64(X, "X").contiguous()
     n, d = X.shape
-    prm = afn_params(k=k, k_max=k_max, w=w, m=m, precision=precision, method=method, seed=seed)
+    prm = afn_params(k=k, k_max=k_max, w=w, m=m, precision=precision, method=method, seed=seed,
+                     landmarks=landmarks, reserved=0)
     h = ctypes.c_void_p()
     _check(lib().afn_setup(X.data_ptr(), n, d, l, mu, ctypes.byref(prm), _stream(stream),
                            ctypes.byref(h)), "afn_setup")

@@ -130,6 +130,10 @@ afn_status fill_k11(const double *Xp, int k, int d, double l, double mu, double 
 // K12[t + p*k] = K(x_t, x_{k+p}) for t < k, p < n - k.
 afn_status fill_k12(const double *Xp, int64_t n, int k, int d, double l, double *K12,
                     hipStream_t s);
+// K12 columns of the FSAI patterns of rows r0 .. r0+B-1 (k x B w, see
+// fsai_rows_batched).
+afn_status fill_k12_patterns(const double *Xp, int64_t n, int k, int d, double l, const int32_t *cols, int w,
+                             int64_t r0, int64_t B, double *Kb, hipStream_t s);
 // In-place lower Cholesky; *info_dev = 1 + index of the first non-positive pivot.
 afn_status cholesky(double *A, int k, int64_t lda, int *info_dev, hipStream_t s);
 // Inverses of the 64 x 64 diagonal blocks of L (dinv_doubles(k) doubles).
@@ -154,6 +158,16 @@ afn_status transpose_square(const double *A, int k, int64_t lda, double *B, int6
 afn_status fsai_rows(const double *Xp, int64_t n, int k, int d, double l, double mu,
                      const double *V, const int32_t *cols, int w, double *gval, int *info_dev,
                      const int32_t *order, hipStream_t s);
+// The same rows with the V columns of each row's pattern recomputed instead of
+// gathered from V: batches of rows whose pattern columns of K12 are filled
+// and solved with L (L^{-1} K12 column by column, identical to V's columns),
+// then read contiguously.  For point sets whose neighbourhoods share few
+// columns (high dimension), where gathers from V would come from HBM.
+// Dinv: diagonal-block inverses of L.  work: fsai_batch_doubles(k, w) doubles.
+int64_t fsai_batch_rows(int k, int w);
+afn_status fsai_rows_batched(const double *Xp, int64_t n, int k, int d, double l, double mu, const double *L,
+                             const double *Dinv, const int32_t *cols, int w, double *gval, int *info_dev,
+                             double *work, hipStream_t s);
 
 // ---------------------------------------------------------------- spatial order
 // order[q] = index of the point at position q: Hilbert order of grid cells over

@@ -2,6 +2,7 @@
 // (Algorithm 3) and preconditioned CG (Algorithm 5, AFN branch).
 #include <cfloat>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <vector>
@@ -11,6 +12,7 @@
 namespace afn {
 
 // Rank estimation (Algorithm 4); defined in rank.hip.
+afn_status uniform_landmarks(int64_t n, int k, uint64_t seed, int32_t *idx, hipStream_t s);
 afn_status rank_estimate(const double *X, int64_t n, int d, double l, double mu, int m,
                          int kmax, uint64_t seed, hipStream_t s, afn_setup_info *info, int *k_out);
 
@@ -339,7 +341,14 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     AFN_TRY(tmp.alloc_n(&idx, k));
     AFN_TRY(tmp.alloc(&fws, fps_workspace_bytes(n)));
     AFN_TRY(tmp.alloc_n(&sel, n));
-    AFN_TRY(fps(X, n, d, k, idx, nullptr, fws, s, h->flags + 3));
+    // landmarks (Algorithm 2): FPS in low dimension, uniform sampling above d = 10
+    const int lm = prm->landmarks == AFN_LANDMARKS_AUTO ? (d <= 10 ? AFN_LANDMARKS_FPS : AFN_LANDMARKS_UNIFORM)
+                                                        : prm->landmarks;
+    h->info.landmarks = lm;
+    if (lm == AFN_LANDMARKS_UNIFORM)
+        AFN_TRY(uniform_landmarks(n, k, prm->seed + 1, idx, s));
+    else
+        AFN_TRY(fps(X, n, d, k, idx, nullptr, fws, s, h->flags + 3));
     AFN_TRY(landmark_permutation(idx, k, n, h->perm, sel, s));
     AFN_TRY(h->arena.alloc_n(&h->Xp, n * d));
     AFN_TRY(gather_points(X, h->perm, n, d, h->Xp, s));
@@ -372,12 +381,24 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     tm.mark(5, s);
     if (nr > 0) {
         AFN_TRY(h->arena.alloc_n(&h->gval, nr * h->w));
-        int32_t *rorder = nullptr;
-        void *ows = nullptr;
-        AFN_TRY(tmp.alloc_n(&rorder, nr));
-        AFN_TRY(tmp.alloc(&ows, spatial_order_work_bytes(nr, d)));
-        AFN_TRY(spatial_order(h->Xp + (int64_t)k * d, nr, d, rorder, ows, s));
-        AFN_TRY(fsai_rows(h->Xp, n, k, d, l, mu, h->V, h->cols, h->w, h->gval, h->flags + 2, rorder, s));
+        // above d = 10 the pattern neighbourhoods share few columns, so each
+        // row's columns of V are recomputed in batches rather than gathered
+        // (AFN_FSAI_RECOMPUTE=0/1 overrides the choice)
+        const char *fr = std::getenv("AFN_FSAI_RECOMPUTE");
+        const bool recompute = fr && (fr[0] == '0' || fr[0] == '1') ? fr[0] == '1' : d > 10;
+        if (recompute) {
+            double *fb = nullptr;
+            AFN_TRY(tmp.alloc_n(&fb, (int64_t)(k > 0 ? k : 1) * fsai_batch_rows(k, h->w) * h->w));
+            AFN_TRY(fsai_rows_batched(h->Xp, n, k, d, l, mu, h->L, h->Dinv, h->cols, h->w, h->gval,
+                                      h->flags + 2, fb, s));
+        } else {
+            int32_t *rorder = nullptr;
+            void *ows = nullptr;
+            AFN_TRY(tmp.alloc_n(&rorder, nr));
+            AFN_TRY(tmp.alloc(&ows, spatial_order_work_bytes(nr, d)));
+            AFN_TRY(spatial_order(h->Xp + (int64_t)k * d, nr, d, rorder, ows, s));
+            AFN_TRY(fsai_rows(h->Xp, n, k, d, l, mu, h->V, h->cols, h->w, h->gval, h->flags + 2, rorder, s));
+        }
         AFN_TRY(h->arena.alloc_n(&h->tptr, nr + 1));
         AFN_TRY(h->arena.alloc_n(&h->trow, nr * h->w));
         AFN_TRY(h->arena.alloc_n(&h->tval, nr * h->w));
@@ -465,7 +486,6 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     inf.ms_fsai = tm.ms(5, 6);
     inf.ms_total = tm.ms(0, 7);
     inf.method = h->method;
-    inf.reserved = 0;
     return AFN_OK;
 }
 
@@ -752,6 +772,7 @@ afn_status afn_setup(const double *X_dev, int64_t n, int32_t d, double l, double
     if (!X_dev || !prm || n < 1 || n > INT32_MAX - 1 || d < 1 || d > kMaxD || !(l > 0) ||
         !std::isfinite(l) || !(mu >= 0) || !std::isfinite(mu) || prm->k < -1 || prm->k > n ||
         prm->w < 1 || prm->w > kMaxW || prm->method < AFN_METHOD_AFN || prm->method > AFN_METHOD_AUTO ||
+        prm->landmarks < AFN_LANDMARKS_AUTO || prm->landmarks > AFN_LANDMARKS_UNIFORM || prm->reserved != 0 ||
         (prm->precision != AFN_FP64 && prm->precision != AFN_FP32) ||
         (prm->precision == AFN_FP32 && d > 8)) {
         set_error("afn_setup: invalid argument (n=%lld d=%d l=%g mu=%g k=%d w=%d)", (long long)n, d,
@@ -980,6 +1001,7 @@ afn_status afn_footprint_bytes(int64_t n, int32_t d, const afn_params *prm, size
     if (k > 0 && nr > 0) afn += r(8 * k * nr);
     if (f32) afn += r(4 * k * k) + r(4 * k * nr) + 2 * r(4 * nr * w);
     afn += r((int64_t)fsai_transpose_work_bytes(nr, prm->w)) + r(4 * nr);
+    if (d > 10) afn += r(8 * (k > 0 ? k : 1) * fsai_batch_rows((int)k, (int)w) * w);
     // Nystrom: L, Dinv, W, Rginv (+ FP32 W, Rginv); G, its block inverses and GEMM partials
     size_t nys = 0;
     if (k > 0) {

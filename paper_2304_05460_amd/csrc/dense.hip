@@ -46,6 +46,29 @@ __global__ __launch_bounds__(256) void k12_fill(const double *__restrict__ Xp, i
     K12[e] = kval(Xp + (int64_t)t * d, Xp + (k + p) * d, d, l2);
 }
 
+// Columns of K12 for the FSAI patterns of rows r0 .. r0+B-1: column
+// c = (q - r0) w + a holds K(x_t, x_{k + cols[q w + a]}) for t < k (the same
+// values k12_fill computes), zero for padding entries (a >= min(q + 1, w)).
+__global__ __launch_bounds__(256) void k12_pattern_fill(const double *__restrict__ Xp, int64_t nr, int k,
+                                                        int d, double l2, const int32_t *__restrict__ cols,
+                                                        int w, int64_t r0, int64_t B,
+                                                        double *__restrict__ Kb)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)k * B * w) return;
+    const int64_t c = e / k;
+    const int t = (int)(e - c * k);
+    const int64_t q = r0 + c / w;
+    const int a = (int)(c - (c / w) * w);
+    const int64_t m = q + 1 < w ? q + 1 : w;
+    if (q >= nr || a >= m) {
+        Kb[e] = 0.0;
+        return;
+    }
+    const int64_t pt = cols[q * w + a];
+    Kb[e] = kval(Xp + (int64_t)t * d, Xp + (k + pt) * d, d, l2);
+}
+
 // Unblocked Cholesky of the jb x jb diagonal block at (j0, j0), in LDS.
 __global__ __launch_bounds__(256) void potrf_diag(double *A, int64_t lda, int j0, int jb, int *info)
 {
@@ -316,6 +339,17 @@ afn_status fill_k12(const double *Xp, int64_t n, int k, int d, double l, double 
     if (total <= 0) return AFN_OK;
     hipLaunchKernelGGL(k12_fill, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, Xp, n, k, d,
                        l * l, K12);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status fill_k12_patterns(const double *Xp, int64_t n, int k, int d, double l, const int32_t *cols, int w,
+                             int64_t r0, int64_t B, double *Kb, hipStream_t s)
+{
+    const int64_t total = (int64_t)k * B * w;
+    if (total <= 0) return AFN_OK;
+    hipLaunchKernelGGL(k12_pattern_fill, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, Xp, n - k, k,
+                       d, l * l, cols, w, r0, B, Kb);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }

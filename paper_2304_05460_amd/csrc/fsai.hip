@@ -63,7 +63,7 @@ __global__ __launch_bounds__(64) void fsai_row_mfma(const double *__restrict__ X
                                                     const int32_t *__restrict__ cols, int w,
                                                     double *__restrict__ gval, int *info,
                                                     const int32_t *__restrict__ order, int64_t row0,
-                                                    int64_t G)
+                                                    int64_t G, int64_t vbase)
 {
     constexpr int N = 16 * NT;
     constexpr int TK = 16;
@@ -83,7 +83,9 @@ __global__ __launch_bounds__(64) void fsai_row_mfma(const double *__restrict__ X
     // chunk t0 of the gathered columns: lane takes entries e = lane + 64 q,
     // column a = e / TK, row t0 + e % TK (16 consecutive lanes read 128
     // contiguous bytes of one column); out-of-range entries load a valid
-    // address and are zeroed, so all loads issue back to back
+    // address and are zeroed, so all loads issue back to back.  The column of
+    // pattern entry a is V[:, s_a], or column (p - vbase) w + a of a batch of
+    // recomputed pattern columns (vbase >= 0).
     auto load_chunk = [&](int t0, double (&dst)[QN]) {
 #pragma unroll
         for (int q = 0; q < QN; ++q) {
@@ -91,7 +93,8 @@ __global__ __launch_bounds__(64) void fsai_row_mfma(const double *__restrict__ X
             const int a = e / TK, tt = e - a * TK;
             const int c = sidx[a];
             const bool ok = c >= 0 && t0 + tt < k;
-            dst[q] = V[ok ? (int64_t)(t0 + tt) + (int64_t)c * k : 0];
+            const int64_t vc = vbase >= 0 ? (p - vbase) * w + a : (int64_t)c;
+            dst[q] = V[ok ? (int64_t)(t0 + tt) + vc * k : 0];
             if (!ok) dst[q] = 0.0;
         }
     };
@@ -282,10 +285,44 @@ afn_status fsai_rows(const double *Xp, int64_t n, int k, int d, double l, double
         const int64_t cnt = nr - r0 < chunk ? nr - r0 : chunk;
         const dim3 grid((unsigned)cnt), block(64);
         switch ((w + 15) / 16) {
-            case 1: hipLaunchKernelGGL(fsai_row_mfma<1>, grid, block, 0, s, Xp, k, d, l * l, mu, V, cols, w, gval, info, order, r0, cnt); break;
-            case 2: hipLaunchKernelGGL(fsai_row_mfma<2>, grid, block, 0, s, Xp, k, d, l * l, mu, V, cols, w, gval, info, order, r0, cnt); break;
-            case 3: hipLaunchKernelGGL(fsai_row_mfma<3>, grid, block, 0, s, Xp, k, d, l * l, mu, V, cols, w, gval, info, order, r0, cnt); break;
-            default: hipLaunchKernelGGL(fsai_row_mfma<4>, grid, block, 0, s, Xp, k, d, l * l, mu, V, cols, w, gval, info, order, r0, cnt); break;
+            case 1: hipLaunchKernelGGL(fsai_row_mfma<1>, grid, block, 0, s, Xp, k, d, l * l, mu, V, cols, w, gval, info, order, r0, cnt, (int64_t)-1); break;
+            case 2: hipLaunchKernelGGL(fsai_row_mfma<2>, grid, block, 0, s, Xp, k, d, l * l, mu, V, cols, w, gval, info, order, r0, cnt, (int64_t)-1); break;
+            case 3: hipLaunchKernelGGL(fsai_row_mfma<3>, grid, block, 0, s, Xp, k, d, l * l, mu, V, cols, w, gval, info, order, r0, cnt, (int64_t)-1); break;
+            default: hipLaunchKernelGGL(fsai_row_mfma<4>, grid, block, 0, s, Xp, k, d, l * l, mu, V, cols, w, gval, info, order, r0, cnt, (int64_t)-1); break;
+        }
+        AFN_HIP(hipGetLastError());
+    }
+    return AFN_OK;
+}
+
+int64_t fsai_batch_rows(int k, int w)
+{
+    // about 256 MB of recomputed columns per batch, between 16 and 4096 rows
+    const int64_t per_row = (int64_t)(k > 0 ? k : 1) * w * 8;
+    int64_t b = ((int64_t)256 << 20) / per_row;
+    b = b < 16 ? 16 : (b > 4096 ? 4096 : b);
+    return b;
+}
+
+afn_status fsai_rows_batched(const double *Xp, int64_t n, int k, int d, double l, double mu, const double *L,
+                             const double *Dinv, const int32_t *cols, int w, double *gval, int *info,
+                             double *work, hipStream_t s)
+{
+    const int64_t nr = n - k;
+    if (nr <= 0) return AFN_OK;
+    const int64_t B = fsai_batch_rows(k, w);
+    for (int64_t r0 = 0; r0 < nr; r0 += B) {
+        const int64_t cnt = nr - r0 < B ? nr - r0 : B;
+        if (k > 0) {
+            AFN_TRY(fill_k12_patterns(Xp, n, k, d, l, cols, w, r0, cnt, work, s));
+            AFN_TRY(trsm_lower(L, Dinv, k, work, cnt * w, s));
+        }
+        const dim3 grid((unsigned)cnt), block(64);
+        switch ((w + 15) / 16) {
+            case 1: hipLaunchKernelGGL(fsai_row_mfma<1>, grid, block, 0, s, Xp, k, d, l * l, mu, work, cols, w, gval, info, nullptr, r0, cnt, r0); break;
+            case 2: hipLaunchKernelGGL(fsai_row_mfma<2>, grid, block, 0, s, Xp, k, d, l * l, mu, work, cols, w, gval, info, nullptr, r0, cnt, r0); break;
+            case 3: hipLaunchKernelGGL(fsai_row_mfma<3>, grid, block, 0, s, Xp, k, d, l * l, mu, work, cols, w, gval, info, nullptr, r0, cnt, r0); break;
+            default: hipLaunchKernelGGL(fsai_row_mfma<4>, grid, block, 0, s, Xp, k, d, l * l, mu, work, cols, w, gval, info, nullptr, r0, cnt, r0); break;
         }
         AFN_HIP(hipGetLastError());
     }

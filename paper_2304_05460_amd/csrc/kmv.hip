@@ -245,58 +245,44 @@ __global__ __launch_bounds__(256) void kmv_sym_reduce(const T *__restrict__ part
     y[o] = (VT)(acc + mu * (double)v[o]);
 }
 
+// Generic tiles (any d <= D): one thread per row, the row's coordinates in
+// registers zero-padded to D, column coordinates staged through LDS (also
+// zero-padded, so the padding adds nothing to the distance).
 template <int D, int BN>
 __global__ __launch_bounds__(256) void kmv_f64_partial(const double *__restrict__ X, int64_t n,
-                                                       int d_rt, double neg_inv_l2,
+                                                       int d, double neg_inv_l2,
                                                        const double *__restrict__ v,
                                                        double *__restrict__ part,
                                                        int64_t split_len)
 {
-    constexpr int DC = D > 0 ? D : 1;
-    __shared__ double sx[(D > 0 ? D : kMaxD) * BN];
+    __shared__ double sx[D * BN];
     __shared__ double sv[BN];
-    const int d = D > 0 ? D : d_rt;
     const int tid = threadIdx.x;
     const int64_t i = (int64_t)blockIdx.x * kRows + tid;
     const int64_t c0 = (int64_t)blockIdx.y * split_len;
     const int64_t c1 = c0 + split_len < n ? c0 + split_len : n;
     const bool row_ok = i < n;
-
-    double xi[DC];
-    if (D > 0) {
+    double xi[D];
 #pragma unroll
-        for (int t = 0; t < DC; ++t) xi[t] = row_ok ? X[i * D + t] : 0.0;
-    }
+    for (int t = 0; t < D; ++t) xi[t] = (row_ok && t < d) ? X[i * d + t] : 0.0;
     double acc = 0.0;
     for (int64_t j0 = c0; j0 < c1; j0 += BN) {
         const int jn = (int)(c1 - j0 < BN ? c1 - j0 : BN);
-        for (int e = tid; e < BN * d; e += blockDim.x) {
-            int j = e / d, t = e - j * d;
-            sx[t * BN + j] = j < jn ? X[(j0 + j) * d + t] : 0.0;
+        for (int e = tid; e < BN * D; e += blockDim.x) {
+            const int j = e / D, t = e - j * D;
+            sx[t * BN + j] = (j < jn && t < d) ? X[(j0 + j) * d + t] : 0.0;
         }
         for (int j = tid; j < BN; j += blockDim.x) sv[j] = j < jn ? v[j0 + j] : 0.0;
         __syncthreads();
-        if (D > 0) {
 #pragma unroll 4
-            for (int j = 0; j < jn; ++j) {
-                double d2 = 0.0;
+        for (int j = 0; j < jn; ++j) {
+            double d2 = 0.0;
 #pragma unroll
-                for (int t = 0; t < DC; ++t) {
-                    double del = xi[t] - sx[t * BN + j];
-                    d2 = __builtin_fma(del, del, d2);
-                }
-                acc = __builtin_fma(exp(d2 * neg_inv_l2), sv[j], acc);
+            for (int t = 0; t < D; ++t) {
+                const double del = xi[t] - sx[t * BN + j];
+                d2 = __builtin_fma(del, del, d2);
             }
-        } else {
-            for (int j = 0; j < jn; ++j) {
-                double d2 = 0.0;
-                for (int t = 0; t < d; ++t) {
-                    double xit = row_ok ? X[i * d + t] : 0.0;
-                    double del = xit - sx[t * BN + j];
-                    d2 = __builtin_fma(del, del, d2);
-                }
-                acc = __builtin_fma(exp(d2 * neg_inv_l2), sv[j], acc);
-            }
+            acc = __builtin_fma(exp(d2 * neg_inv_l2), sv[j], acc);
         }
         __syncthreads();
     }
@@ -306,58 +292,42 @@ __global__ __launch_bounds__(256) void kmv_f64_partial(const double *__restrict_
 // FP32 tiles: coordinates rounded to FP32 on load, squared distance and the
 // kernel value in FP32 (exp via the hardware base-2 exponential with log2(e)
 // folded into the scale), FP32 accumulation within a split; the S split
-// partials are added in FP64 by kmv_reduce.
+// partials are added in FP64 by kmv_reduce.  Same layout as above.
 template <int D, int BN>
 __global__ __launch_bounds__(256) void kmv_f32_partial(const double *__restrict__ X, int64_t n,
-                                                       int d_rt, float neg_log2e_inv_l2,
+                                                       int d, float neg_log2e_inv_l2,
                                                        const double *__restrict__ v,
                                                        double *__restrict__ part,
                                                        int64_t split_len)
 {
-    constexpr int DC = D > 0 ? D : 1;
-    __shared__ float sx[(D > 0 ? D : kMaxD) * BN];
+    __shared__ float sx[D * BN];
     __shared__ float sv[BN];
-    const int d = D > 0 ? D : d_rt;
     const int tid = threadIdx.x;
     const int64_t i = (int64_t)blockIdx.x * kRows + tid;
     const int64_t c0 = (int64_t)blockIdx.y * split_len;
     const int64_t c1 = c0 + split_len < n ? c0 + split_len : n;
     const bool row_ok = i < n;
-    float xi[DC];
-    if (D > 0) {
+    float xi[D];
 #pragma unroll
-        for (int t = 0; t < DC; ++t) xi[t] = row_ok ? (float)X[i * D + t] : 0.0f;
-    }
+    for (int t = 0; t < D; ++t) xi[t] = (row_ok && t < d) ? (float)X[i * d + t] : 0.0f;
     float acc = 0.0f;
     for (int64_t j0 = c0; j0 < c1; j0 += BN) {
         const int jn = (int)(c1 - j0 < BN ? c1 - j0 : BN);
-        for (int e = tid; e < BN * d; e += blockDim.x) {
-            int j = e / d, t = e - j * d;
-            sx[t * BN + j] = j < jn ? (float)X[(j0 + j) * d + t] : 0.0f;
+        for (int e = tid; e < BN * D; e += blockDim.x) {
+            const int j = e / D, t = e - j * D;
+            sx[t * BN + j] = (j < jn && t < d) ? (float)X[(j0 + j) * d + t] : 0.0f;
         }
         for (int j = tid; j < BN; j += blockDim.x) sv[j] = j < jn ? (float)v[j0 + j] : 0.0f;
         __syncthreads();
-        if (D > 0) {
 #pragma unroll 8
-            for (int j = 0; j < jn; ++j) {
-                float d2 = 0.0f;
+        for (int j = 0; j < jn; ++j) {
+            float d2 = 0.0f;
 #pragma unroll
-                for (int t = 0; t < DC; ++t) {
-                    float del = xi[t] - sx[t * BN + j];
-                    d2 = __builtin_fmaf(del, del, d2);
-                }
-                acc = __builtin_fmaf(__builtin_amdgcn_exp2f(d2 * neg_log2e_inv_l2), sv[j], acc);
+            for (int t = 0; t < D; ++t) {
+                const float del = xi[t] - sx[t * BN + j];
+                d2 = __builtin_fmaf(del, del, d2);
             }
-        } else {
-            for (int j = 0; j < jn; ++j) {
-                float d2 = 0.0f;
-                for (int t = 0; t < d; ++t) {
-                    float xit = row_ok ? (float)X[i * d + t] : 0.0f;
-                    float del = xit - sx[t * BN + j];
-                    d2 = __builtin_fmaf(del, del, d2);
-                }
-                acc = __builtin_fmaf(__builtin_amdgcn_exp2f(d2 * neg_log2e_inv_l2), sv[j], acc);
-            }
+            acc = __builtin_fmaf(__builtin_amdgcn_exp2f(d2 * neg_log2e_inv_l2), sv[j], acc);
         }
         __syncthreads();
     }
@@ -593,7 +563,13 @@ afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, const
     for (int c = 0; c < nrhs; ++c) {
         const double *vc = v + c * ldv;
         if (ev0) AFN_HIP(hipEventRecord(ev0, s));
-        launch_partial<0, 32>(grid, X, n, d, nil2, vc, work, split_len, s);
+        if (d <= 12) launch_partial<12, 32>(grid, X, n, d, nil2, vc, work, split_len, s);
+        else if (d <= 16) launch_partial<16, 32>(grid, X, n, d, nil2, vc, work, split_len, s);
+        else if (d <= 20) launch_partial<20, 32>(grid, X, n, d, nil2, vc, work, split_len, s);
+        else if (d <= 24) launch_partial<24, 32>(grid, X, n, d, nil2, vc, work, split_len, s);
+        else if (d <= 32) launch_partial<32, 32>(grid, X, n, d, nil2, vc, work, split_len, s);
+        else if (d <= 48) launch_partial<48, 32>(grid, X, n, d, nil2, vc, work, split_len, s);
+        else launch_partial<64, 32>(grid, X, n, d, nil2, vc, work, split_len, s);
         AFN_HIP(hipGetLastError());
         if (ev1) AFN_HIP(hipEventRecord(ev1, s));
         hipLaunchKernelGGL(kmv_reduce, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, work, n,
@@ -634,7 +610,15 @@ afn_status kmv_f32(const double *X, int64_t n, int d, double l, double mu, const
             case 6: launch_partial32<6, 512>(grid, X, n, d, sc, vc, part, split_len, s); break;
             case 7: launch_partial32<7, 512>(grid, X, n, d, sc, vc, part, split_len, s); break;
             case 8: launch_partial32<8, 512>(grid, X, n, d, sc, vc, part, split_len, s); break;
-            default: launch_partial32<0, 32>(grid, X, n, d, sc, vc, part, split_len, s); break;
+            default:
+                if (d <= 12) launch_partial32<12, 32>(grid, X, n, d, sc, vc, part, split_len, s);
+                else if (d <= 16) launch_partial32<16, 32>(grid, X, n, d, sc, vc, part, split_len, s);
+                else if (d <= 20) launch_partial32<20, 32>(grid, X, n, d, sc, vc, part, split_len, s);
+                else if (d <= 24) launch_partial32<24, 32>(grid, X, n, d, sc, vc, part, split_len, s);
+                else if (d <= 32) launch_partial32<32, 32>(grid, X, n, d, sc, vc, part, split_len, s);
+                else if (d <= 48) launch_partial32<48, 32>(grid, X, n, d, sc, vc, part, split_len, s);
+                else launch_partial32<64, 32>(grid, X, n, d, sc, vc, part, split_len, s);
+                break;
         }
         AFN_HIP(hipGetLastError());
         hipLaunchKernelGGL(kmv_reduce, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, part, n,

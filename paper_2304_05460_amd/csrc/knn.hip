@@ -22,22 +22,21 @@ __device__ __forceinline__ bool key_less(double d1, int q1, double d2, int q2)
     return d1 < d2 || (d1 == d2 && q1 < q2);
 }
 
+// D >= d: the query's coordinates sit in registers, zero-padded to D; the
+// candidate's coordinates beyond d are taken as zero too, so the squared
+// distance is the fma chain over t = 0..d-1 followed by additions of +0.
 template <int D>
-__global__ __launch_bounds__(256) void knn_pred(const double *__restrict__ Xr, int64_t nr, int d_rt,
+__global__ __launch_bounds__(256) void knn_pred(const double *__restrict__ Xr, int64_t nr, int d,
                                                 int w, int32_t *__restrict__ cols)
 {
-    const int d = D > 0 ? D : d_rt;
-    constexpr int DC = D > 0 ? D : 1;
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int want = w - 1;
     for (int64_t p = wave; p < nr; p += nwaves) {
-        double xp[DC];
-        if (D > 0) {
+        double xp[D];
 #pragma unroll
-            for (int t = 0; t < DC; ++t) xp[t] = Xr[p * D + t];
-        }
+        for (int t = 0; t < D; ++t) xp[t] = t < d ? Xr[p * d + t] : 0.0;
         double ld = __builtin_inf();   // this lane's list entry
         int lq = INT_MAX;
         int cnt = 0;
@@ -50,15 +49,10 @@ __global__ __launch_bounds__(256) void knn_pred(const double *__restrict__ Xr, i
                 double dq = __builtin_inf();
                 if (valid) {
                     double acc = 0.0;
-                    if (D > 0) {
 #pragma unroll
-                        for (int t = 0; t < DC; ++t) {
-                            double del = xp[t] - Xr[q * D + t];
-                            acc = __builtin_fma(del, del, acc);
-                        }
-                    } else {
-                        for (int t = 0; t < d; ++t) {
-                            double del = Xr[p * d + t] - Xr[q * d + t];
+                    for (int t = 0; t < D; ++t) {
+                        if (t < d) {
+                            const double del = xp[t] - Xr[q * d + t];
                             acc = __builtin_fma(del, del, acc);
                         }
                     }
@@ -117,8 +111,18 @@ afn_status knn_pattern(const double *Xr, int64_t nr, int d, int w, int32_t *cols
         case 2: hipLaunchKernelGGL(knn_pred<2>, grid, block, 0, s, Xr, nr, d, w, cols); break;
         case 3: hipLaunchKernelGGL(knn_pred<3>, grid, block, 0, s, Xr, nr, d, w, cols); break;
         case 4: hipLaunchKernelGGL(knn_pred<4>, grid, block, 0, s, Xr, nr, d, w, cols); break;
+        case 5: hipLaunchKernelGGL(knn_pred<5>, grid, block, 0, s, Xr, nr, d, w, cols); break;
+        case 6: hipLaunchKernelGGL(knn_pred<6>, grid, block, 0, s, Xr, nr, d, w, cols); break;
+        case 7: hipLaunchKernelGGL(knn_pred<7>, grid, block, 0, s, Xr, nr, d, w, cols); break;
         case 8: hipLaunchKernelGGL(knn_pred<8>, grid, block, 0, s, Xr, nr, d, w, cols); break;
-        default: hipLaunchKernelGGL(knn_pred<0>, grid, block, 0, s, Xr, nr, d, w, cols); break;
+        default:
+            if (d <= 12) hipLaunchKernelGGL(knn_pred<12>, grid, block, 0, s, Xr, nr, d, w, cols);
+            else if (d <= 16) hipLaunchKernelGGL(knn_pred<16>, grid, block, 0, s, Xr, nr, d, w, cols);
+            else if (d <= 24) hipLaunchKernelGGL(knn_pred<24>, grid, block, 0, s, Xr, nr, d, w, cols);
+            else if (d <= 32) hipLaunchKernelGGL(knn_pred<32>, grid, block, 0, s, Xr, nr, d, w, cols);
+            else if (d <= 48) hipLaunchKernelGGL(knn_pred<48>, grid, block, 0, s, Xr, nr, d, w, cols);
+            else hipLaunchKernelGGL(knn_pred<64>, grid, block, 0, s, Xr, nr, d, w, cols);
+            break;
     }
     AFN_HIP(hipGetLastError());
     return AFN_OK;

@@ -318,6 +318,18 @@ __global__ void sturm_count(const double *diag, const double *off, int m, double
 
 }  // namespace
 
+afn_status uniform_landmarks(int64_t n, int k, uint64_t seed, int32_t *idx, hipStream_t s)
+{
+    if (k < 0 || k > n || k > kMaxM) {
+        set_error("uniform landmarks: k=%d outside [0, min(n, %d)]", k, kMaxM);
+        return AFN_EINVAL;
+    }
+    if (k == 0) return AFN_OK;
+    hipLaunchKernelGGL(subsample_kernel, dim3(1), dim3(64), 0, s, n, k, seed, idx);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
 afn_status rank_estimate(const double *X, int64_t n, int d, double l, double mu, int m, int kmax,
                          uint64_t seed, hipStream_t s, afn_setup_info *info, int *k_out)
 {

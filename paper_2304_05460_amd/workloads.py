@@ -98,6 +98,12 @@ C4 = Problem("c4_uniform3d_n150000_r64", n=150_000, d=3, l=0.05, mu=1e-4, k=3000
              tol=1e-6, maxit=500, seed=4, points="uniform", nrhs=64)
 
 
+# High-dimensional case shaped like the paper's 22-feature dataset (n = 49990,
+# mu = n 1e-6, l = 1); synthetic points uniform in [0,1]^22 stand in for it.
+HIGHD = Problem("highd_uniform22d_n49990", n=49_990, d=22, l=1.0, mu=49_990e-6, k=-1, w=64,
+                tol=1e-6, maxit=500, seed=9, points="uniform")
+
+
 def paper_table1a(l2_paper: float, n: int = 160_000) -> Problem:
     """Table 1a workload mapped to the unit cube: l = sqrt(l2)/n^{1/3}."""
     l = math.sqrt(l2_paper) / n ** (1.0 / 3.0)

@@ -39,7 +39,7 @@ def test_status_strings_without_gpu():
 
 def test_param_struct_layout_matches_header():
     from paper_2304_05460_amd import afn
-    assert ctypes.sizeof(afn.afn_params) == 32
+    assert ctypes.sizeof(afn.afn_params) == 40
     assert afn.afn_params.seed.offset == 24
 
 

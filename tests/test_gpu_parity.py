@@ -326,7 +326,7 @@ def test_small_and_ragged_shapes_match_oracle(afn, n, k, w, d):
     say(f"ragged n={n} k={k} w={w} d={d}")
     X = W.points("normal" if d == 8 else "uniform", n, d, 27 + n)
     l, mu = 0.7, 1e-2
-    h = afn.afn_setup(dev(X), l, mu, k=k, w=w)
+    h = afn.afn_setup(dev(X), l, mu, k=k, w=w, landmarks=afn.AFN_LANDMARKS_FPS)
     A = oracle_setup(X, l, mu, k, w)
     np.testing.assert_array_equal(h.landmarks(), A.perm[:k])
     rowptr, cols, vals = h.fsai()
@@ -595,3 +595,51 @@ def test_pruned_pair_fraction(afn):
     h.close()
     assert inf.kmv_kept_f64 == 1.0 and inf.kmv_kept_f32 == 1.0
 
+
+@pytest.mark.parametrize("n,d,k,lm", [(3000, 22, 300, 0), (1500, 18, 150, 0), (800, 3, 64, 2)])
+def test_uniform_landmarks_match_oracle(afn, n, d, k, lm):
+    # Algorithm 2: above d = 10 the landmarks are a uniform sample (the first k
+    # entries of the splitmix64 Fisher-Yates shuffle, seed + 1); the rest of
+    # the construction is the same as with FPS landmarks
+    X = W.points("normal", n, d, 92)
+    l, mu, w, seed = 3.0, 1e-2, 16, 5
+    h = afn.afn_setup(dev(X), l, mu, k=k, w=w, seed=seed, landmarks=lm)
+    inf = h.info()
+    idx = oracle.subsample(n, k, seed + 1)
+    assert inf.landmarks == afn.AFN_LANDMARKS_UNIFORM
+    np.testing.assert_array_equal(h.landmarks(), idx)
+    A = oracle.afn_build(X, l, mu, idx, w)
+    rowptr, cols, vals = h.fsai()
+    np.testing.assert_array_equal(rowptr, A.rowptr)
+    np.testing.assert_array_equal(cols, A.cols)
+    r = np.random.default_rng(93).standard_normal(n)
+    s_ = afn.afn_apply(h, dev(r)).cpu().numpy()
+    so = oracle.afn_apply(A, r)
+    assert np.linalg.norm(s_ - so) <= 1e-8 * np.linalg.norm(so)
+    x, info = afn.afn_pcg_solve(h, dev(r), tol=1e-8, maxit=500)
+    h.close()
+    res = r - oracle.kernel_matvec(X, l, mu, x.cpu().numpy())
+    assert info["status"] == afn.AFN_OK and np.linalg.norm(res) <= 2e-8 * np.linalg.norm(r)
+
+
+def test_uniform_landmarks_limit(afn):
+    X = dev(W.points("normal", 5000, 12, 94))
+    with pytest.raises(afn.AFNError) as e:
+        afn.afn_setup(X, 3.0, 1e-2, k=4097, w=8)
+    assert e.value.status == afn.AFN_EINVAL
+
+
+
+@pytest.mark.parametrize("n,d,k,w", [(3000, 3, 200, 32), (2500, 12, 150, 64)])
+def test_fsai_recompute_equals_gather(afn, monkeypatch, n, d, k, w):
+    # the batched mode recomputes each pattern's columns of L^{-1} K12 with the
+    # same arithmetic as V, so G is bitwise the same as with gathers from V
+    X = dev(W.points("uniform", n, d, 95))
+    out = []
+    for mode in ("0", "1"):
+        monkeypatch.setenv("AFN_FSAI_RECOMPUTE", mode)
+        h = afn.afn_setup(X, 0.4, 1e-3, k=k, w=w, landmarks=afn.AFN_LANDMARKS_FPS)
+        out.append(h.fsai())
+        h.close()
+    for a, b in zip(out[0], out[1]):
+        np.testing.assert_array_equal(a, b)
