@@ -87,6 +87,7 @@ def _declare(L):
     L.ora_count_eigs_above.restype = _I64
     L.ora_rank_estimate.argtypes = [_P, _I64, _I, _D, _D, _I64, _I64, _I64, ctypes.c_uint64,
                                     _P, _P]
+    L.ora_set_kernel.argtypes = [_I]
 
 
 def _p(a: np.ndarray):
@@ -103,6 +104,32 @@ def _check(st: int, where: str):
 
 
 # --- kernel function and matvec (Eq. (1.1), Eq. (1.2)) -------------------------
+
+KERNELS = {"gaussian": 0, "matern32": 1}
+
+
+def set_kernel(kind: str) -> None:
+    """Kernel of every later oracle call (Section 5): "gaussian" (Eq. (1.2)) or
+    "matern32" ((1 + sqrt(3) r / l) exp(-sqrt(3) r / l))."""
+    from . import nystrom as _nys
+    _check(lib().ora_set_kernel(KERNELS[kind]), "set_kernel")
+    _nys.KIND[0] = KERNELS[kind]
+
+
+class use_kernel:
+    """Context manager: set_kernel(kind) inside, Gaussian again on exit."""
+
+    def __init__(self, kind: str):
+        self.kind = kind
+
+    def __enter__(self):
+        set_kernel(self.kind)
+        return self
+
+    def __exit__(self, *exc):
+        set_kernel("gaussian")
+        return False
+
 
 def sqdist(a, b) -> float:
     a, b = _f64(a), _f64(b)

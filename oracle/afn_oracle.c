@@ -48,9 +48,26 @@ double ora_sqdist(const double *a, const double *b, int d)
     return acc;
 }
 
-/* K(x,y) = exp(-||x-y||^2 / l^2)  (Eq. (1.2)). */
+/* The kernel function (Section 5): kind 0 = Gaussian
+ *   K(x,y) = exp(-||x-y||^2 / l^2)                     (Eq. (1.2)),
+ * kind 1 = Matern-3/2
+ *   K(x,y) = (1 + sqrt(3) ||x-y|| / l) exp(-sqrt(3) ||x-y|| / l).
+ * The kind is process-wide state of this test library (ora_set_kernel). */
+static int g_kernel_kind = 0;
+
+int ora_set_kernel(int kind)
+{
+    if (kind != 0 && kind != 1) return ORA_EINVAL;
+    g_kernel_kind = kind;
+    return ORA_OK;
+}
+
 double ora_kernel(const double *a, const double *b, int d, double l)
 {
+    if (g_kernel_kind == 1) {
+        const double s = sqrt(3.0) * sqrt(ora_sqdist(a, b, d)) / l;
+        return (1.0 + s) * exp(-s);
+    }
     return exp(-(ora_sqdist(a, b, d) / (l * l)));
 }
 

@@ -31,12 +31,16 @@ import numpy as np
 import scipy.linalg
 
 EPS = np.finfo(np.float64).eps
+KIND = [0]      # 0 = Gaussian (Eq. (1.2)), 1 = Matern-3/2; set through oracle.set_kernel
 
 
 def kernel_columns(X, l: float, cols) -> np.ndarray:
-    """K[:, cols] with K_ij = exp(-||x_i - x_j||^2 / l^2) (Eq. (1.2))."""
+    """K[:, cols]: Gaussian exp(-r^2 / l^2) or Matern-3/2 (1 + sqrt(3) r / l) exp(-sqrt(3) r / l)."""
     X = np.asarray(X, dtype=np.float64)
     D = ((X[:, None, :] - X[None, np.asarray(cols), :]) ** 2).sum(-1)
+    if KIND[0] == 1:
+        s = np.sqrt(3.0) * np.sqrt(D) / l
+        return (1.0 + s) * np.exp(-s)
     return np.exp(-D / (l * l))
 
 
