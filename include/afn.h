@@ -1,11 +1,12 @@
 /*
  * afn.h -- C-ABI of libafn: AFN-preconditioned conjugate gradients for
- * regularized Gaussian kernel systems on AMD Instinct MI355X (gfx950).
+ * regularized kernel systems on AMD Instinct MI355X (gfx950).
  *
  * Method: "An Adaptive Factorized Nystrom Preconditioner for Regularized
  * Kernel Matrices" (Zhao, Xu, Huang, Chow, Xi; arXiv 2304.05460).
- * Problem (Eq. (1.1)): solve (K + mu I) a = b with
- *   K_ij = exp(-||x_i - x_j||^2 / l^2)                      (Eq. (1.2)).
+ * Problem (Eq. (1.1)): solve (K + mu I) a = b with the Gaussian kernel
+ *   K_ij = exp(-||x_i - x_j||^2 / l^2)                      (Eq. (1.2)),
+ * or the Matern-3/2 kernel of Section 5 (afn_kernel).
  *
  * Conventions shared by every entry point:
  *  - Pointers named *_dev are DEVICE pointers (e.g. from contiguous torch
@@ -84,6 +85,14 @@ typedef enum afn_method {
     AFN_METHOD_AUTO = 2
 } afn_method;
 
+/* Kernel function (Section 5), r = ||x - y||:
+ *   AFN_KERNEL_GAUSSIAN   exp(-r^2 / l^2)                       (Eq. (1.2))
+ *   AFN_KERNEL_MATERN32   (1 + sqrt(3) r / l) exp(-sqrt(3) r / l). */
+typedef enum afn_kernel {
+    AFN_KERNEL_GAUSSIAN = 0,
+    AFN_KERNEL_MATERN32 = 1
+} afn_kernel;
+
 /* Landmark selection (Algorithm 2): AFN_LANDMARKS_AUTO = farthest point
  * sampling (Algorithm 6) for d <= 10 and uniform sampling above;
  * AFN_LANDMARKS_FPS / AFN_LANDMARKS_UNIFORM force one of them.  Uniform
@@ -105,7 +114,7 @@ typedef struct afn_params {
     int32_t method;     /* afn_method                                              */
     uint64_t seed;      /* seed of the rank-estimation subsample (splitmix64)      */
     int32_t landmarks;  /* afn_landmarks                                           */
-    int32_t reserved;   /* must be 0                                               */
+    int32_t kernel;     /* afn_kernel                                              */
 } afn_params;
 
 /* Facts about a constructed preconditioner. */
@@ -159,6 +168,13 @@ typedef struct afn_handle afn_handle;
 afn_status kernel_matvec(const double *X_dev, int64_t n, int32_t d, double l, double mu,
                          const double *v_dev, double *y_dev, int32_t nrhs, int64_t ld,
                          int32_t precision, void *stream);
+
+/* kernel_matvec with the kernel function chosen (afn_kernel); kernel_matvec
+ * is kernel_matvec_ex with AFN_KERNEL_GAUSSIAN.  Errors as kernel_matvec,
+ * and EINVAL for an unknown kernel. */
+afn_status kernel_matvec_ex(const double *X_dev, int64_t n, int32_t d, double l, double mu,
+                            const double *v_dev, double *y_dev, int32_t nrhs, int64_t ld,
+                            int32_t precision, int32_t kernel, void *stream);
 
 /* Construct the preconditioner.  AFN (Algorithm 2): landmarks by farthest
  * point sampling (Algorithm 6) -- k from params or estimated (Algorithm 4) --,

@@ -22,6 +22,7 @@ AFN_OK, AFN_EINVAL, AFN_ENOMEM, AFN_ENOTSPD, AFN_ENOCONV, AFN_EBREAKDOWN, AFN_ES
 AFN_FP64, AFN_FP32 = 0, 1
 AFN_METHOD_AFN, AFN_METHOD_NYSTROM, AFN_METHOD_AUTO = 0, 1, 2
 AFN_LANDMARKS_AUTO, AFN_LANDMARKS_FPS, AFN_LANDMARKS_UNIFORM = 0, 1, 2
+AFN_KERNEL_GAUSSIAN, AFN_KERNEL_MATERN32 = 0, 1
 _STATUS_NAMES = ["AFN_OK", "AFN_EINVAL", "AFN_ENOMEM", "AFN_ENOTSPD", "AFN_ENOCONV",
                  "AFN_EBREAKDOWN", "AFN_ESTAGNATION", "AFN_EDEVICE"]
 
@@ -29,7 +30,7 @@ _STATUS_NAMES = ["AFN_OK", "AFN_EINVAL", "AFN_ENOMEM", "AFN_ENOTSPD", "AFN_ENOCO
 def status_name(status: int) -> str:
     return _STATUS_NAMES[status] if 0 <= status < len(_STATUS_NAMES) else f"status {status}"
 
-EXPORTED = ["kernel_matvec", "afn_setup", "afn_apply", "afn_pcg_solve", "afn_get_info",
+EXPORTED = ["kernel_matvec", "kernel_matvec_ex", "afn_setup", "afn_apply", "afn_pcg_solve", "afn_get_info",
             "afn_get_landmarks", "afn_get_fsai", "afn_get_cholesky", "afn_footprint_bytes",
             "afn_destroy", "afn_status_string", "afn_last_error"]
 
@@ -46,7 +47,7 @@ class afn_params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("k_max", ctypes.c_int32), ("w", ctypes.c_int32),
                 ("m", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("method", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("landmarks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("landmarks", ctypes.c_int32), ("kernel", ctypes.c_int32)]
 
 
 class afn_setup_info(ctypes.Structure):
@@ -88,6 +89,7 @@ _P, _I32, _I64, _D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_d
 
 def _declare(L):
     L.kernel_matvec.argtypes = [_P, _I64, _I32, _D, _D, _P, _P, _I32, _I64, _I32, _P]
+    L.kernel_matvec_ex.argtypes = [_P, _I64, _I32, _D, _D, _P, _P, _I32, _I64, _I32, _I32, _P]
     L.afn_setup.argtypes = [_P, _I64, _I32, _D, _D, ctypes.POINTER(afn_params), _P,
                             ctypes.POINTER(_P)]
     L.afn_apply.argtypes = [_P, _P, _P, _I32, _I64, _P]
@@ -105,7 +107,7 @@ def _declare(L):
     L.afn_status_string.restype = ctypes.c_char_p
     L.afn_last_error.argtypes = []
     L.afn_last_error.restype = ctypes.c_char_p
-    for name in ("kernel_matvec", "afn_setup", "afn_apply", "afn_pcg_solve", "afn_get_info",
+    for name in ("kernel_matvec", "kernel_matvec_ex", "afn_setup", "afn_apply", "afn_pcg_solve", "afn_get_info",
                  "afn_get_landmarks", "afn_get_fsai", "afn_get_cholesky", "afn_footprint_bytes"):
         getattr(L, name).restype = ctypes.c_int
 
@@ -146,8 +148,9 @@ def empty_colmajor(n: int, nrhs: int, device=None) -> torch.Tensor:
 
 def kernel_matvec(X: torch.Tensor, l: float, mu: float, v: torch.Tensor,
                   precision: int = AFN_FP64, out: torch.Tensor | None = None,
-                  stream=None) -> torch.Tensor:
-    """y = (K + mu I) v (Eq. (1.1)) on the GPU; X (n, d) float64 row-major."""
+                  stream=None, kernel: int = 0) -> torch.Tensor:
+    """y = (K + mu I) v (Eq. (1.1)) on the GPU; X (n, d) float64 row-major;
+    kernel: AFN_KERNEL_GAUSSIAN or AFN_KERNEL_MATERN32."""
     X = _dev_f64(X, "X").contiguous()
     n, d = X.shape
     vp, nrhs, ldv = _colmajor(v, "v")
@@ -158,8 +161,12 @@ def kernel_matvec(X: torch.Tensor, l: float, mu: float, v: torch.Tensor,
     yp, _, ldy = _colmajor(out, "out")
     if ldv != ldy:
         raise ValueError("v and out must share a leading dimension")
-    _check(lib().kernel_matvec(X.data_ptr(), n, d, l, mu, vp, yp, nrhs, ldv, precision,
-                               _stream(stream)), "kernel_matvec")
+    if kernel == AFN_KERNEL_GAUSSIAN:
+        st = lib().kernel_matvec(X.data_ptr(), n, d, l, mu, vp, yp, nrhs, ldv, precision, _stream(stream))
+    else:
+        st = lib().kernel_matvec_ex(X.data_ptr(), n, d, l, mu, vp, yp, nrhs, ldv, precision, kernel,
+                                    _stream(stream))
+    _check(st, "kernel_matvec")
     return out
 
 
@@ -248,13 +255,13 @@ class Handle:
 
 def afn_setup(X: torch.Tensor, l: float, mu: float, k: int = -1, w: int = 64, k_max: int = 2000,
               m: int = 0, seed: int = 0, precision: int = AFN_FP64, method: int = AFN_METHOD_AFN,
-              landmarks: int = AFN_LANDMARKS_AUTO, stream=None) -> Handle:
+              landmarks: int = AFN_LANDMARKS_AUTO, kernel: int = 0, stream=None) -> Handle:
     """Algorithm 2 (landmarks by FPS, chol(K11 + mu I), FSAI of the Schur complement),
     or the Nystrom preconditioner, or Algorithm 5's choice between them (method)."""
     X = _dev_f64(X, "X").contiguous()
     n, d = X.shape
     prm = afn_params(k=k, k_max=k_max, w=w, m=m, precision=precision, method=method, seed=seed,
-                     landmarks=landmarks, reserved=0)
+                     landmarks=landmarks, kernel=kernel)
     h = ctypes.c_void_p()
     _check(lib().afn_setup(X.data_ptr(), n, d, l, mu, ctypes.byref(prm), _stream(stream),
                            ctypes.byref(h)), "afn_setup")

@@ -54,12 +54,14 @@ struct DevArena {
 afn_status library_scratch(size_t bytes, void **ptr);
 
 // ---------------------------------------------------------------- kernel matvec
+// kind: afn_kernel (kfun.h defines the kernel functions and the coordinate
+// scaling of the packed layout).
 // Partial-sum workspace for kmv_f64 (doubles).
 int64_t kmv_splits(int64_t n);
 int64_t kmv_workspace_doubles(int64_t n, int d);
 // y[:, c] = (K + mu I) v[:, c] for c < nrhs; X row-major n x d FP64.
 // ev0/ev1 (optional, single right-hand side): recorded around the tile kernel.
-afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, const double *v,
+afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, int kind, const double *v,
                    int64_t ldv, double *y, int64_t ldy, int nrhs, double *work,
                    hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // Pre-scaled SoA copy of the points for the symmetric tile kernels
@@ -67,14 +69,14 @@ afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, const
 // perm (optional): packed position q holds point perm[q] (vectors stay in
 // the caller's order and are indexed through perm).
 int64_t kmv_packed_doubles(int64_t n, int d);
-afn_status kmv_pack(const double *X, int64_t n, int d, double l, void *Xs, bool f32, hipStream_t s,
+afn_status kmv_pack(const double *X, int64_t n, int d, double l, int kind, void *Xs, bool f32, hipStream_t s,
                     const int32_t *perm = nullptr);
 // Tile pruning.  Per 64-point tile of the packed layout, the box of its
 // scaled coordinates (kmv_box_count(n, d) values of the packed type).  A pair
-// of tiles whose boxes are at least sqrt(cut) apart in scaled units holds only
-// kernel values below 2^-cut and is skipped: cut = kCullF64 for FP64 tiles,
-// kCullF32 for FP32 tiles.  The dropped part of row i is below
-// 2^-cut sum_j |v_j|.
+// of tiles whose boxes are at least sqrt(kernel_cut_t(kind, cut)) apart in
+// scaled units holds only kernel values below 2^-cut and is skipped: cut =
+// kCullF64 for FP64 tiles, kCullF32 for FP32 tiles.  The dropped part of row
+// i is below 2^-cut sum_j |v_j|.
 constexpr double kCullF64 = 64.0;
 constexpr double kCullF32 = 44.0;
 int64_t kmv_box_count(int64_t n, int d);
@@ -85,20 +87,20 @@ afn_status kmv_kept_fraction(const double *box, int64_t n, int d, double tcut, u
 afn_status kmv_boxes(const void *Xs, int64_t n, int d, bool f32, void *box, hipStream_t s);
 // y = (K + mu I) v on packed points (d <= 8); part: kmv_workspace_doubles(n, d)
 // doubles (or floats for the FP32 variant).  box (optional) enables pruning.
-afn_status kmv_packed_f64(const double *Xs, int64_t n, int d, double mu, const double *v, int64_t ldv,
+afn_status kmv_packed_f64(const double *Xs, int64_t n, int d, double mu, int kind, const double *v, int64_t ldv,
                           double *y, int64_t ldy, int nrhs, double *part, hipStream_t s,
                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
                           const int32_t *perm = nullptr, const double *box = nullptr);
-afn_status kmv_packed_f32(const float *Xs, int64_t n, int d, double mu, const float *v, int64_t ldv,
+afn_status kmv_packed_f32(const float *Xs, int64_t n, int d, double mu, int kind, const float *v, int64_t ldv,
                           float *y, int64_t ldy, int nrhs, float *part, hipStream_t s,
                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
                           const int32_t *perm = nullptr, const float *box = nullptr);
 // FP32 tiles on packed points with FP64 vectors (part: floats).
-afn_status kmv_packed_f32_dvec(const float *Xs, int64_t n, int d, double mu, const double *v, int64_t ldv,
-                               double *y, int64_t ldy, int nrhs, float *part, hipStream_t s,
+afn_status kmv_packed_f32_dvec(const float *Xs, int64_t n, int d, double mu, int kind, const double *v,
+                               int64_t ldv, double *y, int64_t ldy, int nrhs, float *part, hipStream_t s,
                                const int32_t *perm, const float *box);
 // FP32 tiles and accumulation; FP64 vectors at the interface.
-afn_status kmv_f32(const double *X, int64_t n, int d, double l, double mu, const double *v,
+afn_status kmv_f32(const double *X, int64_t n, int d, double l, double mu, int kind, const double *v,
                    int64_t ldv, double *y, int64_t ldy, int nrhs, void *work, hipStream_t s);
 
 // ---------------------------------------------------------------- FPS
@@ -125,15 +127,15 @@ afn_status knn_pattern(const double *Xr, int64_t nr, int d, int w, int32_t *cols
 
 // ---------------------------------------------------------------- dense factors
 // A = K11 + mu I for the first k points of Xp, column-major lda.
-afn_status fill_k11(const double *Xp, int k, int d, double l, double mu, double *A, int64_t lda,
+afn_status fill_k11(const double *Xp, int k, int d, double l, int kind, double mu, double *A, int64_t lda,
                     hipStream_t s);
 // K12[t + p*k] = K(x_t, x_{k+p}) for t < k, p < n - k.
-afn_status fill_k12(const double *Xp, int64_t n, int k, int d, double l, double *K12,
+afn_status fill_k12(const double *Xp, int64_t n, int k, int d, double l, int kind, double *K12,
                     hipStream_t s);
 // K12 columns of the FSAI patterns of rows r0 .. r0+B-1 (k x B w, see
 // fsai_rows_batched).
-afn_status fill_k12_patterns(const double *Xp, int64_t n, int k, int d, double l, const int32_t *cols, int w,
-                             int64_t r0, int64_t B, double *Kb, hipStream_t s);
+afn_status fill_k12_patterns(const double *Xp, int64_t n, int k, int d, double l, int kind, const int32_t *cols,
+                             int w, int64_t r0, int64_t B, double *Kb, hipStream_t s);
 // In-place lower Cholesky; *info_dev = 1 + index of the first non-positive pivot.
 afn_status cholesky(double *A, int k, int64_t lda, int *info_dev, hipStream_t s);
 // Inverses of the 64 x 64 diagonal blocks of L (dinv_doubles(k) doubles).
@@ -155,7 +157,7 @@ afn_status transpose_square(const double *A, int k, int64_t lda, double *B, int6
 // complement, from V = L^{-1} K12 (k x nr) and the points.  *info_dev = 1 on
 // a non-positive pivot of a Schur block.
 // order (optional, nr entries): the sequence in which rows are processed.
-afn_status fsai_rows(const double *Xp, int64_t n, int k, int d, double l, double mu,
+afn_status fsai_rows(const double *Xp, int64_t n, int k, int d, double l, int kind, double mu,
                      const double *V, const int32_t *cols, int w, double *gval, int *info_dev,
                      const int32_t *order, hipStream_t s);
 // The same rows with the V columns of each row's pattern recomputed instead of
@@ -165,7 +167,8 @@ afn_status fsai_rows(const double *Xp, int64_t n, int k, int d, double l, double
 // columns (high dimension), where gathers from V would come from HBM.
 // Dinv: diagonal-block inverses of L.  work: fsai_batch_doubles(k, w) doubles.
 int64_t fsai_batch_rows(int k, int w);
-afn_status fsai_rows_batched(const double *Xp, int64_t n, int k, int d, double l, double mu, const double *L,
+afn_status fsai_rows_batched(const double *Xp, int64_t n, int k, int d, double l, int kind, double mu,
+                             const double *L,
                              const double *Dinv, const int32_t *cols, int w, double *gval, int *info_dev,
                              double *work, hipStream_t s);
 
@@ -239,7 +242,7 @@ afn_status finite_launch(const double *a, int64_t n, int *flag, hipStream_t s);
 int mrhs_splits(int64_t npad);
 int64_t mrhs_part_elems(int64_t npad);
 template <typename T>
-afn_status kmv_mrhs_run(const T *Xs, int64_t npad, int64_t n, int d, double mu, const T *P,
+afn_status kmv_mrhs_run(const T *Xs, int64_t npad, int64_t n, int d, double mu, int kind, const T *P,
                         int64_t ldp, T *Y, int64_t ldy, int R, T *part, hipStream_t s,
                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
                         const int32_t *perm = nullptr, const T *box = nullptr);
@@ -296,6 +299,7 @@ struct afn_handle {
     int64_t n = 0, nr = 0;
     int d = 0, k = 0, w = 0;
     double l = 1.0, mu = 0.0;
+    int kind = AFN_KERNEL_GAUSSIAN;   // afn_kernel
     afn::DevArena arena;
     double *Xp = nullptr;       // n x d, block order (landmarks first)
     int32_t *perm = nullptr;    // n: block position -> original index

@@ -144,7 +144,7 @@ afn_status inner_body(afn_handle *h, int R, const BlockWs &w, hipStream_t s)
 {
     const int64_t n = h->n;
     const int64_t npad = kmv_packed_doubles(n, h->d) / h->d;
-    AFN_TRY(kmv_mrhs_run<float>(h->Xs32, npad, n, h->d, h->mu, w.P, R, w.Q, R, R, w.kpart, s, nullptr, nullptr,
+    AFN_TRY(kmv_mrhs_run<float>(h->Xs32, npad, n, h->d, h->mu, h->kind, w.P, R, w.Q, R, R, w.kpart, s, nullptr, nullptr,
                                 h->kperm, h->box32));
     AFN_TRY(coldot<float>(w.P, w.Q, n, R, w.pq, w.dotp, s));
     AFN_TRY(col_alpha_launch(w.rho, w.pq, w.active, w.alpha, R, w.bad, s));
@@ -338,7 +338,7 @@ afn_status block_refine_solve(afn_handle *h, const double *B, int64_t ld, double
             break;
         }
         AFN_TRY(axpy_cols_f32_launch(w.amul, w.E, w.X64, n, R, s));
-        AFN_TRY(kmv_mrhs_run<double>(h->Xs64, npad, n, h->d, h->mu, w.X64, R, w.Y64, R, R, w.part64, s,
+        AFN_TRY(kmv_mrhs_run<double>(h->Xs64, npad, n, h->d, h->mu, h->kind, w.X64, R, w.Y64, R, R, w.part64, s,
                                      nullptr, nullptr, h->kperm, h->box64));
         AFN_TRY(sub_rows_launch(w.Bp, w.Y64, w.R64, n * R, s));
     }

@@ -8,12 +8,13 @@
 #include <vector>
 
 #include "afn_internal.h"
+#include "kfun.h"
 
 namespace afn {
 
 // Rank estimation (Algorithm 4); defined in rank.hip.
 afn_status uniform_landmarks(int64_t n, int k, uint64_t seed, int32_t *idx, hipStream_t s);
-afn_status rank_estimate(const double *X, int64_t n, int d, double l, double mu, int m,
+afn_status rank_estimate(const double *X, int64_t n, int d, double l, int kind, double mu, int m,
                          int kmax, uint64_t seed, hipStream_t s, afn_setup_info *info, int *k_out);
 
 namespace {
@@ -193,9 +194,9 @@ afn_status op_f64(afn_handle *h, const double *v, double *y, const WorkLayout &w
                   hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
     if (h->Xs64)
-        return kmv_packed_f64(h->Xs64, h->n, h->d, h->mu, v, h->n, y, h->n, 1, w.kmv, s, e0, e1, h->kperm,
+        return kmv_packed_f64(h->Xs64, h->n, h->d, h->mu, h->kind, v, h->n, y, h->n, 1, w.kmv, s, e0, e1, h->kperm,
                               h->box64);
-    return kmv_f64(h->Xp, h->n, h->d, h->l, h->mu, v, h->n, y, h->n, 1, w.kmv, s, e0, e1);
+    return kmv_f64(h->Xp, h->n, h->d, h->l, h->mu, h->kind, v, h->n, y, h->n, 1, w.kmv, s, e0, e1);
 }
 
 afn_status check_flags(afn_handle *h, hipStream_t s)
@@ -244,8 +245,8 @@ afn_status nystrom_factors(afn_handle *h, DevArena &tmp, Timer &tm, hipStream_t 
     AFN_TRY(h->arena.alloc_n(&h->Dinv, dinv_doubles(k)));
     AFN_TRY(h->arena.alloc_n(&h->W, (int64_t)k * n));
     h->V = h->W + kk;
-    AFN_TRY(fill_k11(h->Xp, k, d, h->l, 0.0, h->L, k, s));    // lower triangle, unit diagonal
-    if (nr > 0) AFN_TRY(fill_k12(h->Xp, n, k, d, h->l, h->V, s));
+    AFN_TRY(fill_k11(h->Xp, k, d, h->l, h->kind, 0.0, h->L, k, s));    // lower triangle, unit diagonal
+    if (nr > 0) AFN_TRY(fill_k12(h->Xp, n, k, d, h->l, h->kind, h->V, s));
     // ||K[:, S]||_F^2 = ||K12||_F^2 + 2 (lower triangle of K11)^2 - k
     double *dp = nullptr, *sc = nullptr;
     AFN_TRY(tmp.alloc_n(&dp, dot_partials(kk > knr ? kk : knr)));
@@ -297,6 +298,7 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     h->d = d;
     h->l = l;
     h->mu = mu;
+    h->kind = prm->kernel;
     h->w = prm->w;
     AFN_TRY(h->arena.alloc_n(&h->flags, 16));
     AFN_HIP(hipMemsetAsync(h->flags, 0, sizeof(int) * 16, s));
@@ -310,7 +312,7 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     if (k < 0) {
         const int m = prm->m > 0 ? (int)(prm->m < n ? prm->m : n) : (int)(n < 2000 ? n : 2000);
         const int kmax = prm->k_max > 0 ? prm->k_max : 2000;
-        AFN_TRY(rank_estimate(X, n, d, l, mu, m, kmax, prm->seed, s, &h->info, &k));
+        AFN_TRY(rank_estimate(X, n, d, l, h->kind, mu, m, kmax, prm->seed, s, &h->info, &k));
     }
     tm.mark(1, s);
     // Algorithm 5: the rank decides between AFN and Nystrom
@@ -361,7 +363,7 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
         AFN_TRY(h->arena.alloc_n(&h->L, (int64_t)k * k));
         AFN_TRY(h->arena.alloc_n(&h->Linv, (int64_t)k * k));
         AFN_TRY(h->arena.alloc_n(&h->Dinv, dinv_doubles(k)));
-        AFN_TRY(fill_k11(h->Xp, k, d, l, mu, h->L, k, s));
+        AFN_TRY(fill_k11(h->Xp, k, d, l, h->kind, mu, h->L, k, s));
         AFN_TRY(cholesky(h->L, k, k, h->flags + 1, s));
         AFN_TRY(diag_inverses(h->L, k, h->Dinv, s));
         AFN_TRY(identity(h->Linv, k, s));
@@ -375,7 +377,7 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     tm.mark(4, s);
     if (k > 0 && nr > 0) {
         AFN_TRY(h->arena.alloc_n(&h->V, (int64_t)k * nr));
-        AFN_TRY(fill_k12(h->Xp, n, k, d, l, h->V, s));
+        AFN_TRY(fill_k12(h->Xp, n, k, d, l, h->kind, h->V, s));
         AFN_TRY(trsm_lower(h->L, h->Dinv, k, h->V, nr, s));
     }
     tm.mark(5, s);
@@ -389,7 +391,7 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
         if (recompute) {
             double *fb = nullptr;
             AFN_TRY(tmp.alloc_n(&fb, (int64_t)(k > 0 ? k : 1) * fsai_batch_rows(k, h->w) * h->w));
-            AFN_TRY(fsai_rows_batched(h->Xp, n, k, d, l, mu, h->L, h->Dinv, h->cols, h->w, h->gval,
+            AFN_TRY(fsai_rows_batched(h->Xp, n, k, d, l, h->kind, mu, h->L, h->Dinv, h->cols, h->w, h->gval,
                                       h->flags + 2, fb, s));
         } else {
             int32_t *rorder = nullptr;
@@ -397,7 +399,7 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
             AFN_TRY(tmp.alloc_n(&rorder, nr));
             AFN_TRY(tmp.alloc(&ows, spatial_order_work_bytes(nr, d)));
             AFN_TRY(spatial_order(h->Xp + (int64_t)k * d, nr, d, rorder, ows, s));
-            AFN_TRY(fsai_rows(h->Xp, n, k, d, l, mu, h->V, h->cols, h->w, h->gval, h->flags + 2, rorder, s));
+            AFN_TRY(fsai_rows(h->Xp, n, k, d, l, h->kind, mu, h->V, h->cols, h->w, h->gval, h->flags + 2, rorder, s));
         }
         AFN_TRY(h->arena.alloc_n(&h->tptr, nr + 1));
         AFN_TRY(h->arena.alloc_n(&h->trow, nr * h->w));
@@ -418,13 +420,13 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
         AFN_TRY(tmp.alloc(&kws, spatial_order_work_bytes(n, d)));
         AFN_TRY(spatial_order(h->Xp, n, d, h->kperm, kws, s));
         AFN_TRY(h->arena.alloc_n(&h->Xs64, kmv_packed_doubles(n, d)));
-        AFN_TRY(kmv_pack(h->Xp, n, d, l, h->Xs64, false, s, h->kperm));
+        AFN_TRY(kmv_pack(h->Xp, n, d, l, h->kind, h->Xs64, false, s, h->kperm));
         AFN_TRY(h->arena.alloc_n(&h->box64, kmv_box_count(n, d)));
         AFN_TRY(kmv_boxes(h->Xs64, n, d, false, h->box64, s));
         unsigned long long *cnt = nullptr, hc[4] = {0, 0, 0, 0};
         AFN_TRY(tmp.alloc_n(&cnt, 4));
-        AFN_TRY(kmv_kept_fraction(h->box64, n, d, kCullF64, cnt, s));
-        AFN_TRY(kmv_kept_fraction(h->box64, n, d, kCullF32, cnt + 2, s));
+        AFN_TRY(kmv_kept_fraction(h->box64, n, d, kernel_cut_t(h->kind, kCullF64), cnt, s));
+        AFN_TRY(kmv_kept_fraction(h->box64, n, d, kernel_cut_t(h->kind, kCullF32), cnt + 2, s));
         AFN_HIP(hipMemcpyAsync(hc, cnt, sizeof hc, hipMemcpyDeviceToHost, s));
         AFN_HIP(hipStreamSynchronize(s));
         h->info.kmv_kept_f64 = hc[1] ? (double)hc[0] / (double)hc[1] : 1.0;
@@ -434,7 +436,7 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     }
     if (h->precision == AFN_FP32) {
         AFN_TRY(h->arena.alloc_n(&h->Xs32, kmv_packed_doubles(n, d)));
-        AFN_TRY(kmv_pack(h->Xp, n, d, l, h->Xs32, true, s, h->kperm));
+        AFN_TRY(kmv_pack(h->Xp, n, d, l, h->kind, h->Xs32, true, s, h->kperm));
         AFN_TRY(h->arena.alloc_n(&h->box32, kmv_box_count(n, d)));
         AFN_TRY(kmv_boxes(h->Xs32, n, d, true, h->box32, s));
         if (h->method == AFN_METHOD_NYSTROM) {
@@ -603,7 +605,7 @@ afn_status pcg_inner32(afn_handle *h, double r0norm, double tol_in, int maxit, c
     *iters = 0;
     *rel_out = 1.0;
     for (int it = 0; it < maxit; ++it) {
-        AFN_TRY(kmv_packed_f32(h->Xs32, n, h->d, h->mu, w.p, n, w.q, n, 1, w.kmv, s, h->kmv_ev[0],
+        AFN_TRY(kmv_packed_f32(h->Xs32, n, h->d, h->mu, h->kind, w.p, n, w.q, n, 1, w.kmv, s, h->kmv_ev[0],
                                h->kmv_ev[1], h->kperm, h->box32));
         AFN_TRY(dot(w.p, n, w.q, n, n, 1, sc + 1, dotp, s));
         AFN_TRY(pcg_alpha_launch(sc, s));
@@ -772,7 +774,8 @@ afn_status afn_setup(const double *X_dev, int64_t n, int32_t d, double l, double
     if (!X_dev || !prm || n < 1 || n > INT32_MAX - 1 || d < 1 || d > kMaxD || !(l > 0) ||
         !std::isfinite(l) || !(mu >= 0) || !std::isfinite(mu) || prm->k < -1 || prm->k > n ||
         prm->w < 1 || prm->w > kMaxW || prm->method < AFN_METHOD_AFN || prm->method > AFN_METHOD_AUTO ||
-        prm->landmarks < AFN_LANDMARKS_AUTO || prm->landmarks > AFN_LANDMARKS_UNIFORM || prm->reserved != 0 ||
+        prm->landmarks < AFN_LANDMARKS_AUTO || prm->landmarks > AFN_LANDMARKS_UNIFORM ||
+        (prm->kernel != AFN_KERNEL_GAUSSIAN && prm->kernel != AFN_KERNEL_MATERN32) ||
         (prm->precision != AFN_FP64 && prm->precision != AFN_FP32) ||
         (prm->precision == AFN_FP32 && d > 8)) {
         set_error("afn_setup: invalid argument (n=%lld d=%d l=%g mu=%g k=%d w=%d)", (long long)n, d,

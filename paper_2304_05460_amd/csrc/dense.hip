@@ -1,27 +1,28 @@
 // Dense factors of the landmark block (Algorithm 2):
 //   L = chol(K11 + mu I)           blocked right-looking Cholesky, 64-wide panels
 //   Linv = L^{-1}, V = L^{-1} K12   left-looking blocked triangular solve
-// All matrices column-major FP64.  Kernel values exp(-(d2 / l^2)) with the
+// All matrices column-major FP64.  Kernel values kernel_d2 (kfun.h) of the
 // squared distance by the fixed fma chain.
 #include "afn_internal.h"
+#include "kfun.h"
 
 namespace afn {
 namespace {
 
 constexpr int NB = 64;
 
-__device__ __forceinline__ double kval(const double *a, const double *b, int d, double l2)
+__device__ __forceinline__ double kval(const double *a, const double *b, int d, double l2, int kind)
 {
     double acc = 0.0;
     for (int t = 0; t < d; ++t) {
         double del = a[t] - b[t];
         acc = __builtin_fma(del, del, acc);
     }
-    return exp(-(acc / l2));
+    return kernel_d2(acc, l2, kind);
 }
 
 __global__ __launch_bounds__(256) void k11_fill(const double *__restrict__ Xp, int k, int d,
-                                                double l2, double mu, double *__restrict__ A,
+                                                double l2, int kind, double mu, double *__restrict__ A,
                                                 int64_t lda)
 {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -31,26 +32,27 @@ __global__ __launch_bounds__(256) void k11_fill(const double *__restrict__ Xp, i
         A[i + (int64_t)j * lda] = 0.0;
         return;
     }
-    double v = kval(Xp + (int64_t)i * d, Xp + (int64_t)j * d, d, l2);
+    double v = kval(Xp + (int64_t)i * d, Xp + (int64_t)j * d, d, l2, kind);
     A[i + (int64_t)j * lda] = v + (i == j ? mu : 0.0);
 }
 
 __global__ __launch_bounds__(256) void k12_fill(const double *__restrict__ Xp, int64_t n, int k,
-                                                int d, double l2, double *__restrict__ K12)
+                                                int d, double l2, int kind, double *__restrict__ K12)
 {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t nr = n - k;
     if (e >= (int64_t)k * nr) return;
     int64_t p = e / k;
     int t = (int)(e - p * k);
-    K12[e] = kval(Xp + (int64_t)t * d, Xp + (k + p) * d, d, l2);
+    K12[e] = kval(Xp + (int64_t)t * d, Xp + (k + p) * d, d, l2, kind);
 }
 
 // Columns of K12 for the FSAI patterns of rows r0 .. r0+B-1: column
 // c = (q - r0) w + a holds K(x_t, x_{k + cols[q w + a]}) for t < k (the same
 // values k12_fill computes), zero for padding entries (a >= min(q + 1, w)).
 __global__ __launch_bounds__(256) void k12_pattern_fill(const double *__restrict__ Xp, int64_t nr, int k,
-                                                        int d, double l2, const int32_t *__restrict__ cols,
+                                                        int d, double l2, int kind,
+                                                        const int32_t *__restrict__ cols,
                                                         int w, int64_t r0, int64_t B,
                                                         double *__restrict__ Kb)
 {
@@ -66,7 +68,7 @@ __global__ __launch_bounds__(256) void k12_pattern_fill(const double *__restrict
         return;
     }
     const int64_t pt = cols[q * w + a];
-    Kb[e] = kval(Xp + (int64_t)t * d, Xp + (k + pt) * d, d, l2);
+    Kb[e] = kval(Xp + (int64_t)t * d, Xp + (k + pt) * d, d, l2, kind);
 }
 
 // Unblocked Cholesky of the jb x jb diagonal block at (j0, j0), in LDS.
@@ -322,34 +324,34 @@ afn_status transpose_square(const double *A, int k, int64_t lda, double *B, int6
     return AFN_OK;
 }
 
-afn_status fill_k11(const double *Xp, int k, int d, double l, double mu, double *A, int64_t lda,
+afn_status fill_k11(const double *Xp, int k, int d, double l, int kind, double mu, double *A, int64_t lda,
                     hipStream_t s)
 {
     if (k <= 0) return AFN_OK;
     hipLaunchKernelGGL(k11_fill, dim3((unsigned)ceil_div((int64_t)k * k, 256)), dim3(256), 0, s, Xp,
-                       k, d, l * l, mu, A, lda);
+                       k, d, l * l, kind, mu, A, lda);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }
 
-afn_status fill_k12(const double *Xp, int64_t n, int k, int d, double l, double *K12,
+afn_status fill_k12(const double *Xp, int64_t n, int k, int d, double l, int kind, double *K12,
                     hipStream_t s)
 {
     int64_t total = (int64_t)k * (n - k);
     if (total <= 0) return AFN_OK;
     hipLaunchKernelGGL(k12_fill, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, Xp, n, k, d,
-                       l * l, K12);
+                       l * l, kind, K12);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }
 
-afn_status fill_k12_patterns(const double *Xp, int64_t n, int k, int d, double l, const int32_t *cols, int w,
-                             int64_t r0, int64_t B, double *Kb, hipStream_t s)
+afn_status fill_k12_patterns(const double *Xp, int64_t n, int k, int d, double l, int kind, const int32_t *cols,
+                             int w, int64_t r0, int64_t B, double *Kb, hipStream_t s)
 {
     const int64_t total = (int64_t)k * B * w;
     if (total <= 0) return AFN_OK;
     hipLaunchKernelGGL(k12_pattern_fill, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, Xp, n - k, k,
-                       d, l * l, cols, w, r0, B, Kb);
+                       d, l * l, kind, cols, w, r0, B, Kb);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }

@@ -24,6 +24,7 @@
 // each entry among its column's entries (rows in a column are distinct), so
 // the layout, and every sum over it, does not depend on scheduling.
 #include "afn_internal.h"
+#include "kfun.h"
 
 namespace afn {
 namespace {
@@ -59,7 +60,7 @@ __device__ __forceinline__ int64_t xcd_contiguous(int64_t b, int64_t G)
 
 template <int NT>
 __global__ __launch_bounds__(64) void fsai_row_mfma(const double *__restrict__ Xp, int k, int d, double l2,
-                                                    double mu, const double *__restrict__ V,
+                                                    int kind, double mu, const double *__restrict__ V,
                                                     const int32_t *__restrict__ cols, int w,
                                                     double *__restrict__ gval, int *info,
                                                     const int32_t *__restrict__ order, int64_t row0,
@@ -148,7 +149,7 @@ __global__ __launch_bounds__(64) void fsai_row_mfma(const double *__restrict__ X
                         const double del = xa[t] - xb[t];
                         dd = __builtin_fma(del, del, dd);
                     }
-                    v = exp(-(dd / l2)) + (r == c ? mu : 0.0) - acc[tile_index(I, J)][i];
+                    v = kernel_d2(dd, l2, kind) + (r == c ? mu : 0.0) - acc[tile_index(I, J)][i];
                 } else {
                     v = r == c ? 1.0 : 0.0;
                 }
@@ -274,7 +275,7 @@ __global__ __launch_bounds__(256) void place_sorted(const int64_t *__restrict__ 
 
 }  // namespace
 
-afn_status fsai_rows(const double *Xp, int64_t n, int k, int d, double l, double mu,
+afn_status fsai_rows(const double *Xp, int64_t n, int k, int d, double l, int kind, double mu,
                      const double *V, const int32_t *cols, int w, double *gval, int *info,
                      const int32_t *order, hipStream_t s)
 {
@@ -285,10 +286,10 @@ afn_status fsai_rows(const double *Xp, int64_t n, int k, int d, double l, double
         const int64_t cnt = nr - r0 < chunk ? nr - r0 : chunk;
         const dim3 grid((unsigned)cnt), block(64);
         switch ((w + 15) / 16) {
-            case 1: hipLaunchKernelGGL(fsai_row_mfma<1>, grid, block, 0, s, Xp, k, d, l * l, mu, V, cols, w, gval, info, order, r0, cnt, (int64_t)-1); break;
-            case 2: hipLaunchKernelGGL(fsai_row_mfma<2>, grid, block, 0, s, Xp, k, d, l * l, mu, V, cols, w, gval, info, order, r0, cnt, (int64_t)-1); break;
-            case 3: hipLaunchKernelGGL(fsai_row_mfma<3>, grid, block, 0, s, Xp, k, d, l * l, mu, V, cols, w, gval, info, order, r0, cnt, (int64_t)-1); break;
-            default: hipLaunchKernelGGL(fsai_row_mfma<4>, grid, block, 0, s, Xp, k, d, l * l, mu, V, cols, w, gval, info, order, r0, cnt, (int64_t)-1); break;
+            case 1: hipLaunchKernelGGL(fsai_row_mfma<1>, grid, block, 0, s, Xp, k, d, l * l, kind, mu, V, cols, w, gval, info, order, r0, cnt, (int64_t)-1); break;
+            case 2: hipLaunchKernelGGL(fsai_row_mfma<2>, grid, block, 0, s, Xp, k, d, l * l, kind, mu, V, cols, w, gval, info, order, r0, cnt, (int64_t)-1); break;
+            case 3: hipLaunchKernelGGL(fsai_row_mfma<3>, grid, block, 0, s, Xp, k, d, l * l, kind, mu, V, cols, w, gval, info, order, r0, cnt, (int64_t)-1); break;
+            default: hipLaunchKernelGGL(fsai_row_mfma<4>, grid, block, 0, s, Xp, k, d, l * l, kind, mu, V, cols, w, gval, info, order, r0, cnt, (int64_t)-1); break;
         }
         AFN_HIP(hipGetLastError());
     }
@@ -304,7 +305,8 @@ int64_t fsai_batch_rows(int k, int w)
     return b;
 }
 
-afn_status fsai_rows_batched(const double *Xp, int64_t n, int k, int d, double l, double mu, const double *L,
+afn_status fsai_rows_batched(const double *Xp, int64_t n, int k, int d, double l, int kind, double mu,
+                             const double *L,
                              const double *Dinv, const int32_t *cols, int w, double *gval, int *info,
                              double *work, hipStream_t s)
 {
@@ -314,15 +316,15 @@ afn_status fsai_rows_batched(const double *Xp, int64_t n, int k, int d, double l
     for (int64_t r0 = 0; r0 < nr; r0 += B) {
         const int64_t cnt = nr - r0 < B ? nr - r0 : B;
         if (k > 0) {
-            AFN_TRY(fill_k12_patterns(Xp, n, k, d, l, cols, w, r0, cnt, work, s));
+            AFN_TRY(fill_k12_patterns(Xp, n, k, d, l, kind, cols, w, r0, cnt, work, s));
             AFN_TRY(trsm_lower(L, Dinv, k, work, cnt * w, s));
         }
         const dim3 grid((unsigned)cnt), block(64);
         switch ((w + 15) / 16) {
-            case 1: hipLaunchKernelGGL(fsai_row_mfma<1>, grid, block, 0, s, Xp, k, d, l * l, mu, work, cols, w, gval, info, nullptr, r0, cnt, r0); break;
-            case 2: hipLaunchKernelGGL(fsai_row_mfma<2>, grid, block, 0, s, Xp, k, d, l * l, mu, work, cols, w, gval, info, nullptr, r0, cnt, r0); break;
-            case 3: hipLaunchKernelGGL(fsai_row_mfma<3>, grid, block, 0, s, Xp, k, d, l * l, mu, work, cols, w, gval, info, nullptr, r0, cnt, r0); break;
-            default: hipLaunchKernelGGL(fsai_row_mfma<4>, grid, block, 0, s, Xp, k, d, l * l, mu, work, cols, w, gval, info, nullptr, r0, cnt, r0); break;
+            case 1: hipLaunchKernelGGL(fsai_row_mfma<1>, grid, block, 0, s, Xp, k, d, l * l, kind, mu, work, cols, w, gval, info, nullptr, r0, cnt, r0); break;
+            case 2: hipLaunchKernelGGL(fsai_row_mfma<2>, grid, block, 0, s, Xp, k, d, l * l, kind, mu, work, cols, w, gval, info, nullptr, r0, cnt, r0); break;
+            case 3: hipLaunchKernelGGL(fsai_row_mfma<3>, grid, block, 0, s, Xp, k, d, l * l, kind, mu, work, cols, w, gval, info, nullptr, r0, cnt, r0); break;
+            default: hipLaunchKernelGGL(fsai_row_mfma<4>, grid, block, 0, s, Xp, k, d, l * l, kind, mu, work, cols, w, gval, info, nullptr, r0, cnt, r0); break;
         }
         AFN_HIP(hipGetLastError());
     }

@@ -1,9 +1,9 @@
-// Kernel matvec y = (K + mu I) v with the Gaussian kernel evaluated on the fly
-// (Eq. (1.1), Eq. (1.2)).
+// Kernel matvec y = (K + mu I) v with the kernel evaluated on the fly
+// (Eq. (1.1); Gaussian Eq. (1.2) or Matern-3/2, Section 5).
 //
 // FP64 path (d <= 8): symmetric tiles.  Coordinates are pre-scaled by
-// sqrt(log2 e) / l (SoA, zero-padded), so K_ij = 2^(-t) with t the squared
-// distance of the scaled points.  The 64-point tile partition is grouped into
+// kernel_scale(kind, l) (SoA, zero-padded), so K_ij is a function of the
+// squared distance t of the scaled points alone (kfun.h).  The 64-point tile partition is grouped into
 // super-blocks of ST tiles; one workgroup owns a super-block pair (BI <= BJ)
 // and evaluates every unique pair once, adding K_ij v_j to row i and K_ij v_i
 // to row j.  Row partials stay in registers across the column tiles; column
@@ -12,17 +12,13 @@
 // pass adds them in ascending super-block order (deterministic result).
 // Diagonal 64 x 64 tiles are evaluated in full and feed rows only.
 //
-// 2^(-t): t clamped to 2000 (the result underflows long before), k = rint(t),
-// f = k - t in [-1/2, 1/2] exactly, 2^(-t) = p(f) 2^(-k) with p the degree-11
-// polynomial interpolating 2^f at the Chebyshev nodes of [-1/2, 1/2]
-// (interpolation error 4.4e-18 relative; Horner in FP64 <= 1.7 ulp).
-//
 // Generic d (> 8) and the FP32 variant use row-block x column-split tiles:
 // 256 rows per workgroup, columns streamed through LDS, S split partials
 // added in order by kmv_reduce.
 #include <cmath>
 
 #include "afn_internal.h"
+#include "kfun.h"
 
 namespace afn {
 namespace {
@@ -31,26 +27,6 @@ constexpr int kRows = 256;
 
 constexpr int kTile = 64;
 constexpr int kMaxST = 16;
-
-__device__ __forceinline__ double exp2_neg(double t)
-{
-    t = t < 2000.0 ? t : 2000.0;
-    const double kd = __builtin_rint(t);
-    const double f = kd - t;
-    double p = 4.45594401136235e-10;
-    p = __builtin_fma(p, f, 7.074200215313511e-09);
-    p = __builtin_fma(p, f, 1.0178056459844976e-07);
-    p = __builtin_fma(p, f, 1.3215432494521488e-06);
-    p = __builtin_fma(p, f, 1.5252733842373628e-05);
-    p = __builtin_fma(p, f, 0.00015403530463828206);
-    p = __builtin_fma(p, f, 0.0013333558146406623);
-    p = __builtin_fma(p, f, 0.009618129107587145);
-    p = __builtin_fma(p, f, 0.05550410866482162);
-    p = __builtin_fma(p, f, 0.2402265069591016);
-    p = __builtin_fma(p, f, 0.6931471805599453);
-    p = __builtin_fma(p, f, 1.0);
-    return __builtin_ldexp(p, (int)(-kd));
-}
 
 // Xs[t * npad + q] = X[perm[q]*d + t] * scale for q < n (perm may be null:
 // identity), 0 beyond (rounded to T).
@@ -66,9 +42,6 @@ __global__ __launch_bounds__(256) void pack_scaled(const double *__restrict__ X,
     const int64_t i = q < n ? (perm ? (int64_t)perm[q] : q) : 0;
     Xs[e] = (T)(q < n ? X[i * d + t] * scale : 0.0);
 }
-
-// 2^(-t) in FP32 with the hardware base-2 exponential.
-__device__ __forceinline__ float exp2_neg(float t) { return __builtin_amdgcn_exp2f(-t); }
 
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -125,8 +98,8 @@ __device__ __forceinline__ void decode_pair(int q, int S, int &BI, int &BJ)
 
 // perm (may be null): v is indexed through it (v[perm[q]] for packed point
 // q).  box (may be null): a tile pair whose box gap^2 is >= tcut is skipped:
-// every kernel value in it is below 2^-tcut.
-template <int D, typename T, typename VT>
+// every kernel value in it is below the cut tcut was derived from.
+template <int KIND, int D, typename T, typename VT>
 __global__ __launch_bounds__(256) void kmv_sym(const T *__restrict__ Xs, int64_t npad, int64_t n,
                                                const VT *__restrict__ v, const int32_t *__restrict__ perm,
                                                const T *__restrict__ box, T tcut, int S, int ST,
@@ -188,7 +161,7 @@ __global__ __launch_bounds__(256) void kmv_sym(const T *__restrict__ Xs, int64_t
                         const T del = xi[r][t] - xj[t];
                         d2 = fmaT(del, del, d2);
                     }
-                    const T kij = exp2_neg(d2);
+                    const T kij = kernel_scaled<KIND, T>(d2);
                     racc[r] = fmaT(kij, vj, racc[r]);
                     cacc[c] = fmaT(kij, vi[r], cacc[c]);
                 }
@@ -247,10 +220,12 @@ __global__ __launch_bounds__(256) void kmv_sym_reduce(const T *__restrict__ part
 
 // Generic tiles (any d <= D): one thread per row, the row's coordinates in
 // registers zero-padded to D, column coordinates staged through LDS (also
-// zero-padded, so the padding adds nothing to the distance).
-template <int D, int BN>
+// zero-padded, so the padding adds nothing to the distance).  Unscaled
+// coordinates; c2 = kernel_scale(kind, l)^2 turns the squared distance into
+// the scaled one.
+template <int KIND, int D, int BN>
 __global__ __launch_bounds__(256) void kmv_f64_partial(const double *__restrict__ X, int64_t n,
-                                                       int d, double neg_inv_l2,
+                                                       int d, double c2,
                                                        const double *__restrict__ v,
                                                        double *__restrict__ part,
                                                        int64_t split_len)
@@ -282,7 +257,7 @@ __global__ __launch_bounds__(256) void kmv_f64_partial(const double *__restrict_
                 const double del = xi[t] - sx[t * BN + j];
                 d2 = __builtin_fma(del, del, d2);
             }
-            acc = __builtin_fma(exp(d2 * neg_inv_l2), sv[j], acc);
+            acc = __builtin_fma(kernel_scaled<KIND, double>(d2 * c2), sv[j], acc);
         }
         __syncthreads();
     }
@@ -290,12 +265,12 @@ __global__ __launch_bounds__(256) void kmv_f64_partial(const double *__restrict_
 }
 
 // FP32 tiles: coordinates rounded to FP32 on load, squared distance and the
-// kernel value in FP32 (exp via the hardware base-2 exponential with log2(e)
-// folded into the scale), FP32 accumulation within a split; the S split
-// partials are added in FP64 by kmv_reduce.  Same layout as above.
-template <int D, int BN>
+// kernel value in FP32 (the hardware base-2 exponential), FP32 accumulation
+// within a split; the S split partials are added in FP64 by kmv_reduce.  Same
+// layout as above.
+template <int KIND, int D, int BN>
 __global__ __launch_bounds__(256) void kmv_f32_partial(const double *__restrict__ X, int64_t n,
-                                                       int d, float neg_log2e_inv_l2,
+                                                       int d, float c2,
                                                        const double *__restrict__ v,
                                                        double *__restrict__ part,
                                                        int64_t split_len)
@@ -327,7 +302,7 @@ __global__ __launch_bounds__(256) void kmv_f32_partial(const double *__restrict_
                 const float del = xi[t] - sx[t * BN + j];
                 d2 = __builtin_fmaf(del, del, d2);
             }
-            acc = __builtin_fmaf(__builtin_amdgcn_exp2f(d2 * neg_log2e_inv_l2), sv[j], acc);
+            acc = __builtin_fmaf(kernel_scaled<KIND, float>(d2 * c2), sv[j], acc);
         }
         __syncthreads();
     }
@@ -347,19 +322,27 @@ __global__ __launch_bounds__(256) void kmv_reduce(const double *__restrict__ par
 }
 
 template <int D, int BN>
-void launch_partial(dim3 grid, const double *X, int64_t n, int d, double nil2, const double *v,
+void launch_partial(int kind, dim3 grid, const double *X, int64_t n, int d, double c2, const double *v,
                     double *part, int64_t split_len, hipStream_t s)
 {
-    hipLaunchKernelGGL((kmv_f64_partial<D, BN>), grid, dim3(256), 0, s, X, n, d, nil2, v, part,
-                       split_len);
+    if (kind == AFN_KERNEL_MATERN32)
+        hipLaunchKernelGGL((kmv_f64_partial<AFN_KERNEL_MATERN32, D, BN>), grid, dim3(256), 0, s, X, n, d, c2,
+                           v, part, split_len);
+    else
+        hipLaunchKernelGGL((kmv_f64_partial<AFN_KERNEL_GAUSSIAN, D, BN>), grid, dim3(256), 0, s, X, n, d, c2,
+                           v, part, split_len);
 }
 
 template <int D, int BN>
-void launch_partial32(dim3 grid, const double *X, int64_t n, int d, float sc, const double *v,
+void launch_partial32(int kind, dim3 grid, const double *X, int64_t n, int d, float c2, const double *v,
                       double *part, int64_t split_len, hipStream_t s)
 {
-    hipLaunchKernelGGL((kmv_f32_partial<D, BN>), grid, dim3(256), 0, s, X, n, d, sc, v, part,
-                       split_len);
+    if (kind == AFN_KERNEL_MATERN32)
+        hipLaunchKernelGGL((kmv_f32_partial<AFN_KERNEL_MATERN32, D, BN>), grid, dim3(256), 0, s, X, n, d, c2,
+                           v, part, split_len);
+    else
+        hipLaunchKernelGGL((kmv_f32_partial<AFN_KERNEL_GAUSSIAN, D, BN>), grid, dim3(256), 0, s, X, n, d, c2,
+                           v, part, split_len);
 }
 
 }  // namespace
@@ -411,26 +394,39 @@ int64_t kmv_workspace_doubles(int64_t n, int d)
 
 namespace {
 
+template <int KIND, typename T, typename VT>
+void launch_sym(int d, dim3 grid, const T *Xs, int64_t npad, int64_t n, const VT *v, const int32_t *perm,
+                const T *box, T tcut, int S, int ST, T *part, hipStream_t s)
+{
+    const dim3 block(256);
+    switch (d) {
+        case 1: hipLaunchKernelGGL((kmv_sym<KIND, 1, T, VT>), grid, block, 0, s, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
+        case 2: hipLaunchKernelGGL((kmv_sym<KIND, 2, T, VT>), grid, block, 0, s, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
+        case 3: hipLaunchKernelGGL((kmv_sym<KIND, 3, T, VT>), grid, block, 0, s, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
+        case 4: hipLaunchKernelGGL((kmv_sym<KIND, 4, T, VT>), grid, block, 0, s, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
+        case 5: hipLaunchKernelGGL((kmv_sym<KIND, 5, T, VT>), grid, block, 0, s, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
+        case 6: hipLaunchKernelGGL((kmv_sym<KIND, 6, T, VT>), grid, block, 0, s, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
+        case 7: hipLaunchKernelGGL((kmv_sym<KIND, 7, T, VT>), grid, block, 0, s, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
+        default: hipLaunchKernelGGL((kmv_sym<KIND, 8, T, VT>), grid, block, 0, s, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
+    }
+}
+
 template <typename T, typename VT>
-afn_status kmv_sym_run(const T *Xs, const SymShape &sh, int64_t n, int d, double mu, const VT *v,
+afn_status kmv_sym_run(const T *Xs, const SymShape &sh, int64_t n, int d, double mu, int kind, const VT *v,
                        int64_t ldv, VT *y, int64_t ldy, int nrhs, T *part, hipStream_t s,
                        hipEvent_t ev0, hipEvent_t ev1, const int32_t *perm, const T *box)
 {
-    const T tcut = (T)(sizeof(T) == 8 ? kCullF64 : kCullF32);
+    const T tcut = (T)kernel_cut_t(kind, sizeof(T) == 8 ? kCullF64 : kCullF32);
     for (int c = 0; c < nrhs; ++c) {
         const VT *vc = v + c * ldv;
         if (ev0) AFN_HIP(hipEventRecord(ev0, s));
-        dim3 grid((unsigned)sh.nwg), block(256);
-        switch (d) {
-            case 1: hipLaunchKernelGGL((kmv_sym<1, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, perm, box, tcut, sh.S, sh.ST, part); break;
-            case 2: hipLaunchKernelGGL((kmv_sym<2, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, perm, box, tcut, sh.S, sh.ST, part); break;
-            case 3: hipLaunchKernelGGL((kmv_sym<3, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, perm, box, tcut, sh.S, sh.ST, part); break;
-            case 4: hipLaunchKernelGGL((kmv_sym<4, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, perm, box, tcut, sh.S, sh.ST, part); break;
-            case 5: hipLaunchKernelGGL((kmv_sym<5, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, perm, box, tcut, sh.S, sh.ST, part); break;
-            case 6: hipLaunchKernelGGL((kmv_sym<6, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, perm, box, tcut, sh.S, sh.ST, part); break;
-            case 7: hipLaunchKernelGGL((kmv_sym<7, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, perm, box, tcut, sh.S, sh.ST, part); break;
-            default: hipLaunchKernelGGL((kmv_sym<8, T, VT>), grid, block, 0, s, Xs, sh.npad, n, vc, perm, box, tcut, sh.S, sh.ST, part); break;
-        }
+        const dim3 grid((unsigned)sh.nwg);
+        if (kind == AFN_KERNEL_MATERN32)
+            launch_sym<AFN_KERNEL_MATERN32, T, VT>(d, grid, Xs, sh.npad, n, vc, perm, box, tcut, sh.S, sh.ST,
+                                                   part, s);
+        else
+            launch_sym<AFN_KERNEL_GAUSSIAN, T, VT>(d, grid, Xs, sh.npad, n, vc, perm, box, tcut, sh.S, sh.ST,
+                                                   part, s);
         AFN_HIP(hipGetLastError());
         if (ev1) AFN_HIP(hipEventRecord(ev1, s));
         hipLaunchKernelGGL((kmv_sym_reduce<T, VT>), dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, part,
@@ -442,17 +438,42 @@ afn_status kmv_sym_run(const T *Xs, const SymShape &sh, int64_t n, int d, double
 
 }  // namespace
 
+double kernel_scale(int kind, double l)
+{
+    if (kind == AFN_KERNEL_MATERN32) return std::sqrt(3.0) * 1.4426950408889634 / l;
+    return std::sqrt(1.4426950408889634) / l;
+}
+
+// Gaussian: 2^-t = 2^-cut at t = cut.  Matern: (1 + s ln 2) 2^-s = 2^-cut at
+// the root of g(s) = s - log2(1 + s ln 2) - cut, convex and increasing for
+// s > 0, so Newton's method from a point right of the root decreases
+// monotonically onto it; t = s^2.
+double kernel_cut_t(int kind, double cut)
+{
+    if (kind != AFN_KERNEL_MATERN32) return cut;
+    const double ln2 = 0.6931471805599453;
+    double s = 2.0 * cut + 16.0;
+    for (int it = 0; it < 60; ++it) {
+        const double g = s - std::log2(1.0 + s * ln2) - cut;
+        const double dg = s * ln2 / (1.0 + s * ln2);
+        const double step = g / dg;
+        s -= step;
+        if (step < 1e-13 * s) break;
+    }
+    return s * s;
+}
+
 int64_t kmv_packed_doubles(int64_t n, int d)
 {
     const SymShape sh = sym_shape(n);
     return sh.npad * d;
 }
 
-afn_status kmv_pack(const double *X, int64_t n, int d, double l, void *Xs, bool f32, hipStream_t s,
+afn_status kmv_pack(const double *X, int64_t n, int d, double l, int kind, void *Xs, bool f32, hipStream_t s,
                     const int32_t *perm)
 {
     const SymShape sh = sym_shape(n);
-    const double scale = std::sqrt(1.4426950408889634) / l;
+    const double scale = kernel_scale(kind, l);
     if (f32)
         hipLaunchKernelGGL(pack_scaled<float>, dim3((unsigned)ceil_div(sh.npad * d, 256)), dim3(256), 0, s,
                            X, perm, n, d, sh.npad, scale, (float *)Xs);
@@ -520,31 +541,31 @@ afn_status kmv_boxes(const void *Xs, int64_t n, int d, bool f32, void *box, hipS
     return AFN_OK;
 }
 
-afn_status kmv_packed_f64(const double *Xs, int64_t n, int d, double mu, const double *v, int64_t ldv,
+afn_status kmv_packed_f64(const double *Xs, int64_t n, int d, double mu, int kind, const double *v, int64_t ldv,
                           double *y, int64_t ldy, int nrhs, double *part, hipStream_t s,
                           hipEvent_t ev0, hipEvent_t ev1, const int32_t *perm, const double *box)
 {
-    return kmv_sym_run<double, double>(Xs, sym_shape(n), n, d, mu, v, ldv, y, ldy, nrhs, part, s, ev0,
+    return kmv_sym_run<double, double>(Xs, sym_shape(n), n, d, mu, kind, v, ldv, y, ldy, nrhs, part, s, ev0,
                                        ev1, perm, box);
 }
 
-afn_status kmv_packed_f32(const float *Xs, int64_t n, int d, double mu, const float *v, int64_t ldv,
+afn_status kmv_packed_f32(const float *Xs, int64_t n, int d, double mu, int kind, const float *v, int64_t ldv,
                           float *y, int64_t ldy, int nrhs, float *part, hipStream_t s,
                           hipEvent_t ev0, hipEvent_t ev1, const int32_t *perm, const float *box)
 {
-    return kmv_sym_run<float, float>(Xs, sym_shape(n), n, d, mu, v, ldv, y, ldy, nrhs, part, s, ev0,
+    return kmv_sym_run<float, float>(Xs, sym_shape(n), n, d, mu, kind, v, ldv, y, ldy, nrhs, part, s, ev0,
                                      ev1, perm, box);
 }
 
-afn_status kmv_packed_f32_dvec(const float *Xs, int64_t n, int d, double mu, const double *v, int64_t ldv,
-                               double *y, int64_t ldy, int nrhs, float *part, hipStream_t s,
+afn_status kmv_packed_f32_dvec(const float *Xs, int64_t n, int d, double mu, int kind, const double *v,
+                               int64_t ldv, double *y, int64_t ldy, int nrhs, float *part, hipStream_t s,
                                const int32_t *perm, const float *box)
 {
-    return kmv_sym_run<float, double>(Xs, sym_shape(n), n, d, mu, v, ldv, y, ldy, nrhs, part, s, nullptr,
+    return kmv_sym_run<float, double>(Xs, sym_shape(n), n, d, mu, kind, v, ldv, y, ldy, nrhs, part, s, nullptr,
                                       nullptr, perm, box);
 }
 
-afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, const double *v,
+afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, int kind, const double *v,
                    int64_t ldv, double *y, int64_t ldy, int nrhs, double *work, hipStream_t s,
                    hipEvent_t ev0, hipEvent_t ev1)
 {
@@ -552,24 +573,24 @@ afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, const
         const SymShape sh = sym_shape(n);
         double *Xs = work;
         double *part = work + sh.npad * d;
-        AFN_TRY(kmv_pack(X, n, d, l, Xs, false, s));
-        return kmv_sym_run<double, double>(Xs, sh, n, d, mu, v, ldv, y, ldy, nrhs, part, s, ev0, ev1,
+        AFN_TRY(kmv_pack(X, n, d, l, kind, Xs, false, s));
+        return kmv_sym_run<double, double>(Xs, sh, n, d, mu, kind, v, ldv, y, ldy, nrhs, part, s, ev0, ev1,
                                            nullptr, nullptr);
     }
     const int64_t S = kmv_splits(n);
     const int64_t split_len = ceil_div(n, S);
-    const double nil2 = -1.0 / (l * l);
+    const double c2 = kernel_scale(kind, l) * kernel_scale(kind, l);
     dim3 grid((unsigned)ceil_div(n, kRows), (unsigned)S);
     for (int c = 0; c < nrhs; ++c) {
         const double *vc = v + c * ldv;
         if (ev0) AFN_HIP(hipEventRecord(ev0, s));
-        if (d <= 12) launch_partial<12, 32>(grid, X, n, d, nil2, vc, work, split_len, s);
-        else if (d <= 16) launch_partial<16, 32>(grid, X, n, d, nil2, vc, work, split_len, s);
-        else if (d <= 20) launch_partial<20, 32>(grid, X, n, d, nil2, vc, work, split_len, s);
-        else if (d <= 24) launch_partial<24, 32>(grid, X, n, d, nil2, vc, work, split_len, s);
-        else if (d <= 32) launch_partial<32, 32>(grid, X, n, d, nil2, vc, work, split_len, s);
-        else if (d <= 48) launch_partial<48, 32>(grid, X, n, d, nil2, vc, work, split_len, s);
-        else launch_partial<64, 32>(grid, X, n, d, nil2, vc, work, split_len, s);
+        if (d <= 12) launch_partial<12, 32>(kind, grid, X, n, d, c2, vc, work, split_len, s);
+        else if (d <= 16) launch_partial<16, 32>(kind, grid, X, n, d, c2, vc, work, split_len, s);
+        else if (d <= 20) launch_partial<20, 32>(kind, grid, X, n, d, c2, vc, work, split_len, s);
+        else if (d <= 24) launch_partial<24, 32>(kind, grid, X, n, d, c2, vc, work, split_len, s);
+        else if (d <= 32) launch_partial<32, 32>(kind, grid, X, n, d, c2, vc, work, split_len, s);
+        else if (d <= 48) launch_partial<48, 32>(kind, grid, X, n, d, c2, vc, work, split_len, s);
+        else launch_partial<64, 32>(kind, grid, X, n, d, c2, vc, work, split_len, s);
         AFN_HIP(hipGetLastError());
         if (ev1) AFN_HIP(hipEventRecord(ev1, s));
         hipLaunchKernelGGL(kmv_reduce, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, work, n,
@@ -583,43 +604,31 @@ afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, const
 
 namespace afn {
 
-afn_status kmv_f32(const double *X, int64_t n, int d, double l, double mu, const double *v,
+afn_status kmv_f32(const double *X, int64_t n, int d, double l, double mu, int kind, const double *v,
                    int64_t ldv, double *y, int64_t ldy, int nrhs, void *work, hipStream_t s)
 {
     if (d >= 1 && d <= 8) {
         const SymShape sh = sym_shape(n);
         float *Xs = (float *)work;
         float *part = Xs + round_up(sh.npad * d, 64);
-        AFN_TRY(kmv_pack(X, n, d, l, Xs, true, s));
-        return kmv_sym_run<float, double>(Xs, sh, n, d, mu, v, ldv, y, ldy, nrhs, part, s, nullptr,
+        AFN_TRY(kmv_pack(X, n, d, l, kind, Xs, true, s));
+        return kmv_sym_run<float, double>(Xs, sh, n, d, mu, kind, v, ldv, y, ldy, nrhs, part, s, nullptr,
                                           nullptr, nullptr, nullptr);
     }
     const int64_t S = kmv_splits(n);
     const int64_t split_len = ceil_div(n, S);
-    const float sc = (float)(-1.4426950408889634 / (l * l));
+    const float c2 = (float)(kernel_scale(kind, l) * kernel_scale(kind, l));
     double *part = (double *)work;
     dim3 grid((unsigned)ceil_div(n, kRows), (unsigned)S);
     for (int c = 0; c < nrhs; ++c) {
         const double *vc = v + c * ldv;
-        switch (d) {
-            case 1: launch_partial32<1, 512>(grid, X, n, d, sc, vc, part, split_len, s); break;
-            case 2: launch_partial32<2, 512>(grid, X, n, d, sc, vc, part, split_len, s); break;
-            case 3: launch_partial32<3, 512>(grid, X, n, d, sc, vc, part, split_len, s); break;
-            case 4: launch_partial32<4, 512>(grid, X, n, d, sc, vc, part, split_len, s); break;
-            case 5: launch_partial32<5, 512>(grid, X, n, d, sc, vc, part, split_len, s); break;
-            case 6: launch_partial32<6, 512>(grid, X, n, d, sc, vc, part, split_len, s); break;
-            case 7: launch_partial32<7, 512>(grid, X, n, d, sc, vc, part, split_len, s); break;
-            case 8: launch_partial32<8, 512>(grid, X, n, d, sc, vc, part, split_len, s); break;
-            default:
-                if (d <= 12) launch_partial32<12, 32>(grid, X, n, d, sc, vc, part, split_len, s);
-                else if (d <= 16) launch_partial32<16, 32>(grid, X, n, d, sc, vc, part, split_len, s);
-                else if (d <= 20) launch_partial32<20, 32>(grid, X, n, d, sc, vc, part, split_len, s);
-                else if (d <= 24) launch_partial32<24, 32>(grid, X, n, d, sc, vc, part, split_len, s);
-                else if (d <= 32) launch_partial32<32, 32>(grid, X, n, d, sc, vc, part, split_len, s);
-                else if (d <= 48) launch_partial32<48, 32>(grid, X, n, d, sc, vc, part, split_len, s);
-                else launch_partial32<64, 32>(grid, X, n, d, sc, vc, part, split_len, s);
-                break;
-        }
+        if (d <= 12) launch_partial32<12, 32>(kind, grid, X, n, d, c2, vc, part, split_len, s);
+        else if (d <= 16) launch_partial32<16, 32>(kind, grid, X, n, d, c2, vc, part, split_len, s);
+        else if (d <= 20) launch_partial32<20, 32>(kind, grid, X, n, d, c2, vc, part, split_len, s);
+        else if (d <= 24) launch_partial32<24, 32>(kind, grid, X, n, d, c2, vc, part, split_len, s);
+        else if (d <= 32) launch_partial32<32, 32>(kind, grid, X, n, d, c2, vc, part, split_len, s);
+        else if (d <= 48) launch_partial32<48, 32>(kind, grid, X, n, d, c2, vc, part, split_len, s);
+        else launch_partial32<64, 32>(kind, grid, X, n, d, c2, vc, part, split_len, s);
         AFN_HIP(hipGetLastError());
         hipLaunchKernelGGL(kmv_reduce, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, part, n,
                            (int)S, mu, vc, y + c * ldy);

@@ -1,8 +1,8 @@
 // Many right-hand sides at once.
 //
 // Kernel matvec Y = (K + mu I) P for R <= 64 columns: per 64 x 64 tile the
-// kernel values E are formed on the VALU (same scaled-coordinate exp2 as the
-// single-vector kernels) and stored transposed in LDS; the product E P_J is
+// kernel values E are formed on the VALU (from the same pre-scaled
+// coordinates as the single-vector kernels, kfun.h) and stored transposed in LDS; the product E P_J is
 // a GEMM with K = 64 and runs on the matrix cores (MFMA 16x16x4, FP32 or
 // FP64).  A workgroup owns 64 rows and a range of column tiles; split
 // partials are added in order by a second pass (deterministic).
@@ -19,6 +19,7 @@
 #include <cmath>
 
 #include "afn_internal.h"
+#include "kfun.h"
 
 namespace afn {
 namespace {
@@ -50,26 +51,6 @@ struct Mfma<double> {
 constexpr int TL = 64;      // tile edge (points / rows / k-chunk)
 constexpr int LS = 80;      // LDS row stride: (lane/16) * LS = 16 (mod 64) -> conflict-free MFMA reads
 
-__device__ __forceinline__ double kexp2(double t)
-{
-    t = t < 2000.0 ? t : 2000.0;
-    const double kd = __builtin_rint(t);
-    const double f = kd - t;
-    double p = 4.45594401136235e-10;
-    p = __builtin_fma(p, f, 7.074200215313511e-09);
-    p = __builtin_fma(p, f, 1.0178056459844976e-07);
-    p = __builtin_fma(p, f, 1.3215432494521488e-06);
-    p = __builtin_fma(p, f, 1.5252733842373628e-05);
-    p = __builtin_fma(p, f, 0.00015403530463828206);
-    p = __builtin_fma(p, f, 0.0013333558146406623);
-    p = __builtin_fma(p, f, 0.009618129107587145);
-    p = __builtin_fma(p, f, 0.05550410866482162);
-    p = __builtin_fma(p, f, 0.2402265069591016);
-    p = __builtin_fma(p, f, 0.6931471805599453);
-    p = __builtin_fma(p, f, 1.0);
-    return __builtin_ldexp(p, (int)(-kd));
-}
-__device__ __forceinline__ float kexp2(float t) { return __builtin_amdgcn_exp2f(-t); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
@@ -85,7 +66,7 @@ constexpr int LSE = 144;    // (lane/16) * 144 = 16 (mod 64): conflict-free MFMA
 // perm (may be null): row q of P is row perm[q] of the caller's array.  box
 // (may be null): per 64-point tile, [min, max] of each packed coordinate; a
 // column tile whose box gap^2 to this block's rows is >= tcut is skipped.
-template <int D, typename T, int NB>
+template <int KIND, int D, typename T, int NB>
 __global__ __launch_bounds__(512) void kmv_mrhs(const T *__restrict__ Xs, int64_t npad, int64_t n,
                                                 const T *__restrict__ P, int64_t ldp, int R,
                                                 int tiles_per_split, T *__restrict__ part,
@@ -175,7 +156,7 @@ __global__ __launch_bounds__(512) void kmv_mrhs(const T *__restrict__ Xs, int64_
                     const T del = xi[t] - cx[t][j];
                     d2 = fmaT(del, del, d2);
                 }
-                EsT[j][half * 64 + lane] = kexp2(d2);
+                EsT[j][half * 64 + lane] = kernel_scaled<KIND, T>(d2);
             }
             __syncthreads();
 #pragma unroll 4
@@ -489,28 +470,39 @@ __global__ __launch_bounds__(256) void axpy_cols_f32(const double *__restrict__ 
     x[e] = __builtin_fma(a[e % R], (double)e32[e], x[e]);
 }
 
-template <int D, typename T, int NB>
+template <int KIND, int D, typename T, int NB>
 void launch_mrhs(dim3 g, const T *Xs, int64_t npad, int64_t n, const T *P, int64_t ldp, int R, int tps,
-                 T *part, const int32_t *perm, const T *box, hipStream_t s)
+                 T *part, const int32_t *perm, const T *box, T tcut, hipStream_t s)
 {
-    const T tcut = (T)(sizeof(T) == 8 ? kCullF64 : kCullF32);
-    hipLaunchKernelGGL((kmv_mrhs<D, T, NB>), g, dim3(512), 0, s, Xs, npad, n, P, ldp, R, tps, part, perm,
+    hipLaunchKernelGGL((kmv_mrhs<KIND, D, T, NB>), g, dim3(512), 0, s, Xs, npad, n, P, ldp, R, tps, part, perm,
                        box, tcut);
 }
 
-template <typename T, int NB>
+template <int KIND, typename T, int NB>
 void launch_mrhs_d(int d, dim3 g, const T *Xs, int64_t npad, int64_t n, const T *P, int64_t ldp, int R,
-                   int tps, T *part, const int32_t *perm, const T *box, hipStream_t s)
+                   int tps, T *part, const int32_t *perm, const T *box, T tcut, hipStream_t s)
 {
     switch (d) {
-        case 1: launch_mrhs<1, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
-        case 2: launch_mrhs<2, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
-        case 3: launch_mrhs<3, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
-        case 4: launch_mrhs<4, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
-        case 5: launch_mrhs<5, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
-        case 6: launch_mrhs<6, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
-        case 7: launch_mrhs<7, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
-        default: launch_mrhs<8, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
+        case 1: launch_mrhs<KIND, 1, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, tcut, s); break;
+        case 2: launch_mrhs<KIND, 2, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, tcut, s); break;
+        case 3: launch_mrhs<KIND, 3, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, tcut, s); break;
+        case 4: launch_mrhs<KIND, 4, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, tcut, s); break;
+        case 5: launch_mrhs<KIND, 5, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, tcut, s); break;
+        case 6: launch_mrhs<KIND, 6, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, tcut, s); break;
+        case 7: launch_mrhs<KIND, 7, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, tcut, s); break;
+        default: launch_mrhs<KIND, 8, T, NB>(g, Xs, npad, n, P, ldp, R, tps, part, perm, box, tcut, s); break;
+    }
+}
+
+template <int KIND, typename T>
+void launch_mrhs_nb(int NBk, int d, dim3 g, const T *Xs, int64_t npad, int64_t n, const T *P, int64_t ldp,
+                    int R, int tps, T *part, const int32_t *perm, const T *box, T tcut, hipStream_t s)
+{
+    switch (NBk) {
+        case 1: launch_mrhs_d<KIND, T, 1>(d, g, Xs, npad, n, P, ldp, R, tps, part, perm, box, tcut, s); break;
+        case 2: launch_mrhs_d<KIND, T, 2>(d, g, Xs, npad, n, P, ldp, R, tps, part, perm, box, tcut, s); break;
+        case 3: launch_mrhs_d<KIND, T, 3>(d, g, Xs, npad, n, P, ldp, R, tps, part, perm, box, tcut, s); break;
+        default: launch_mrhs_d<KIND, T, 4>(d, g, Xs, npad, n, P, ldp, R, tps, part, perm, box, tcut, s); break;
     }
 }
 
@@ -530,7 +522,7 @@ int mrhs_splits(int64_t npad)
 int64_t mrhs_part_elems(int64_t npad) { return (int64_t)mrhs_splits(npad) * npad * 64; }
 
 template <typename T>
-afn_status kmv_mrhs_run(const T *Xs, int64_t npad, int64_t n, int d, double mu, const T *P,
+afn_status kmv_mrhs_run(const T *Xs, int64_t npad, int64_t n, int d, double mu, int kind, const T *P,
                         int64_t ldp, T *Y, int64_t ldy, int R, T *part, hipStream_t s,
                         hipEvent_t e0, hipEvent_t e1, const int32_t *perm, const T *box)
 {
@@ -547,13 +539,12 @@ afn_status kmv_mrhs_run(const T *Xs, int64_t npad, int64_t n, int d, double mu, 
     const int64_t ntiles = npad / TL;
     const int tps = (int)ceil_div(ntiles, S);
     dim3 g((unsigned)(npad / BM), (unsigned)S);
+    const T tcut = (T)kernel_cut_t(kind, sizeof(T) == 8 ? kCullF64 : kCullF32);
     if (e0) AFN_HIP(hipEventRecord(e0, s));
-    switch (NBk) {
-        case 1: launch_mrhs_d<T, 1>(d, g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
-        case 2: launch_mrhs_d<T, 2>(d, g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
-        case 3: launch_mrhs_d<T, 3>(d, g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
-        default: launch_mrhs_d<T, 4>(d, g, Xs, npad, n, P, ldp, R, tps, part, perm, box, s); break;
-    }
+    if (kind == AFN_KERNEL_MATERN32)
+        launch_mrhs_nb<AFN_KERNEL_MATERN32, T>(NBk, d, g, Xs, npad, n, P, ldp, R, tps, part, perm, box, tcut, s);
+    else
+        launch_mrhs_nb<AFN_KERNEL_GAUSSIAN, T>(NBk, d, g, Xs, npad, n, P, ldp, R, tps, part, perm, box, tcut, s);
     AFN_HIP(hipGetLastError());
     if (e1) AFN_HIP(hipEventRecord(e1, s));
     hipLaunchKernelGGL((mrhs_reduce<T>), dim3((unsigned)ceil_div(n * R, 256)), dim3(256), 0, s, part, npad,
@@ -562,10 +553,10 @@ afn_status kmv_mrhs_run(const T *Xs, int64_t npad, int64_t n, int d, double mu, 
     return AFN_OK;
 }
 
-template afn_status kmv_mrhs_run<float>(const float *, int64_t, int64_t, int, double, const float *,
+template afn_status kmv_mrhs_run<float>(const float *, int64_t, int64_t, int, double, int, const float *,
                                         int64_t, float *, int64_t, int, float *, hipStream_t,
                                         hipEvent_t, hipEvent_t, const int32_t *, const float *);
-template afn_status kmv_mrhs_run<double>(const double *, int64_t, int64_t, int, double, const double *,
+template afn_status kmv_mrhs_run<double>(const double *, int64_t, int64_t, int, double, int, const double *,
                                          int64_t, double *, int64_t, int, double *, hipStream_t,
                                          hipEvent_t, hipEvent_t, const int32_t *, const double *);
 

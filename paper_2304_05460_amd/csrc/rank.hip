@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "afn_internal.h"
+#include "kfun.h"
 
 namespace afn {
 
@@ -76,7 +77,7 @@ __global__ __launch_bounds__(256) void gather_scaled(const double *X, const int3
     Xm[e] = X[(int64_t)sub[i] * d + t] * scale;
 }
 
-__global__ __launch_bounds__(256) void kmat_fill(const double *Xm, int m, int d, double l2, double *K)
+__global__ __launch_bounds__(256) void kmat_fill(const double *Xm, int m, int d, double l2, int kind, double *K)
 {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)m * m) return;
@@ -86,7 +87,7 @@ __global__ __launch_bounds__(256) void kmat_fill(const double *Xm, int m, int d,
         double del = Xm[i * d + t] - Xm[j * d + t];
         acc = __builtin_fma(del, del, acc);
     }
-    K[e] = exp(-(acc / l2));
+    K[e] = kernel_d2(acc, l2, kind);
 }
 
 // Block partial of sum of squares of K (m x m).
@@ -330,7 +331,7 @@ afn_status uniform_landmarks(int64_t n, int k, uint64_t seed, int32_t *idx, hipS
     return AFN_OK;
 }
 
-afn_status rank_estimate(const double *X, int64_t n, int d, double l, double mu, int m, int kmax,
+afn_status rank_estimate(const double *X, int64_t n, int d, double l, int kind, double mu, int m, int kmax,
                          uint64_t seed, hipStream_t s, afn_setup_info *info, int *k_out)
 {
     if (m < 1 || m > n || m > kMaxM) {
@@ -366,7 +367,7 @@ afn_status rank_estimate(const double *X, int64_t n, int d, double l, double mu,
     const double scale = std::pow((double)m / (double)n, 1.0 / (double)d);
     hipLaunchKernelGGL(gather_scaled, dim3((unsigned)ceil_div((int64_t)m * d, 256)), dim3(256), 0, s, X,
                        sub, m, d, scale, Xm);
-    hipLaunchKernelGGL(kmat_fill, dim3(gmm), dim3(256), 0, s, Xm, m, d, l2, K);
+    hipLaunchKernelGGL(kmat_fill, dim3(gmm), dim3(256), 0, s, Xm, m, d, l2, kind, K);
     // FPS order of the subsample, produced 64 positions at a time as the scan needs them
     AFN_TRY(fps_start(Xm, m, d, fws, s, err));
     hipLaunchKernelGGL(sumsq_partial, dim3(nparts), dim3(256), 0, s, K, mm, part);
@@ -424,7 +425,7 @@ afn_status rank_estimate(const double *X, int64_t n, int d, double l, double mu,
         AFN_TRY(tmp.alloc_n(&toff, m));
         hipLaunchKernelGGL(gather_scaled, dim3((unsigned)ceil_div((int64_t)m * d, 256)), dim3(256), 0, s,
                            X, sub, m, d, 1.0, Xm);
-        hipLaunchKernelGGL(kmat_fill, dim3(gmm), dim3(256), 0, s, Xm, m, d, l2, K);
+        hipLaunchKernelGGL(kmat_fill, dim3(gmm), dim3(256), 0, s, Xm, m, d, l2, kind, K);
         hipLaunchKernelGGL(hh_init, dim3(1), dim3(64), 0, s, K, m, v, sc, tdiag, toff);
         for (int j = 0; j + 2 < m; ++j) {
             const int nb = (int)ceil_div(m - j - 1, 4);

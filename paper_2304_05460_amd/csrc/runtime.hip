@@ -109,6 +109,13 @@ afn_status kernel_matvec(const double *X_dev, int64_t n, int32_t d, double l, do
                          const double *v_dev, double *y_dev, int32_t nrhs, int64_t ld,
                          int32_t precision, void *stream)
 {
+    return kernel_matvec_ex(X_dev, n, d, l, mu, v_dev, y_dev, nrhs, ld, precision, AFN_KERNEL_GAUSSIAN, stream);
+}
+
+afn_status kernel_matvec_ex(const double *X_dev, int64_t n, int32_t d, double l, double mu,
+                            const double *v_dev, double *y_dev, int32_t nrhs, int64_t ld,
+                            int32_t precision, int32_t kind, void *stream)
+{
     afn::clear_error();
     if (n < 1 || d < 1 || d > afn::kMaxD || !(l > 0) || !(mu >= 0) || nrhs < 1 || ld < n ||
         !X_dev || !v_dev || !y_dev) {
@@ -118,6 +125,10 @@ afn_status kernel_matvec(const double *X_dev, int64_t n, int32_t d, double l, do
     }
     if (precision != AFN_FP64 && precision != AFN_FP32) {
         afn::set_error("kernel_matvec: unknown precision %d", precision);
+        return AFN_EINVAL;
+    }
+    if (kind != AFN_KERNEL_GAUSSIAN && kind != AFN_KERNEL_MATERN32) {
+        afn::set_error("kernel_matvec: unknown kernel %d", kind);
         return AFN_EINVAL;
     }
     hipStream_t s = (hipStream_t)stream;
@@ -142,7 +153,7 @@ afn_status kernel_matvec(const double *X_dev, int64_t n, int32_t d, double l, do
         void *box = base + ob + pb + xb;
         double *rest = (double *)(base + ob + pb + xb + bb);
         AFN_TRY(afn::spatial_order(X_dev, n, d, kperm, ows, s));
-        AFN_TRY(afn::kmv_pack(X_dev, n, d, l, Xs, f32, s, kperm));
+        AFN_TRY(afn::kmv_pack(X_dev, n, d, l, kind, Xs, f32, s, kperm));
         AFN_TRY(afn::kmv_boxes(Xs, n, d, f32, box, s));
         if (nrhs >= 2) {
             double *Pr = rest;
@@ -152,13 +163,13 @@ afn_status kernel_matvec(const double *X_dev, int64_t n, int32_t d, double l, do
                 const int Rc = (int)(nrhs - c0 < 64 ? nrhs - c0 : 64);
                 if (f32) {
                     AFN_TRY(afn::gather_rows<float>(v_dev + c0 * ld, ld, nullptr, n, Rc, nullptr, (float *)Pr, s));
-                    AFN_TRY(afn::kmv_mrhs_run<float>((const float *)Xs, npad, n, d, mu, (const float *)Pr, Rc,
+                    AFN_TRY(afn::kmv_mrhs_run<float>((const float *)Xs, npad, n, d, mu, kind, (const float *)Pr, Rc,
                                                      (float *)Yr, Rc, Rc, (float *)part, s, nullptr, nullptr,
                                                      kperm, (const float *)box));
                     AFN_TRY(afn::scatter_rows_f32((const float *)Yr, n, Rc, y_dev + c0 * ld, ld, s));
                 } else {
                     AFN_TRY(afn::gather_rows<double>(v_dev + c0 * ld, ld, nullptr, n, Rc, nullptr, Pr, s));
-                    AFN_TRY(afn::kmv_mrhs_run<double>((const double *)Xs, npad, n, d, mu, Pr, Rc, Yr, Rc, Rc,
+                    AFN_TRY(afn::kmv_mrhs_run<double>((const double *)Xs, npad, n, d, mu, kind, Pr, Rc, Yr, Rc, Rc,
                                                       part, s, nullptr, nullptr, kperm, (const double *)box));
                     AFN_TRY(afn::scatter_rows(Yr, nullptr, n, Rc, y_dev + c0 * ld, ld, s));
                 }
@@ -166,9 +177,9 @@ afn_status kernel_matvec(const double *X_dev, int64_t n, int32_t d, double l, do
             return AFN_OK;
         }
         if (f32)
-            return afn::kmv_packed_f32_dvec((const float *)Xs, n, d, mu, v_dev, ld, y_dev, ld, nrhs,
+            return afn::kmv_packed_f32_dvec((const float *)Xs, n, d, mu, kind, v_dev, ld, y_dev, ld, nrhs,
                                             (float *)rest, s, kperm, (const float *)box);
-        return afn::kmv_packed_f64((const double *)Xs, n, d, mu, v_dev, ld, y_dev, ld, nrhs, rest, s, nullptr,
+        return afn::kmv_packed_f64((const double *)Xs, n, d, mu, kind, v_dev, ld, y_dev, ld, nrhs, rest, s, nullptr,
                                    nullptr, kperm, (const double *)box);
     }
     if (nrhs >= 2 && d <= 8) {
@@ -181,17 +192,17 @@ afn_status kernel_matvec(const double *X_dev, int64_t n, int32_t d, double l, do
         double *Pr = Xs + npad * d;
         double *Yr = Pr + n * R;
         double *part = Yr + n * R;
-        AFN_TRY(afn::kmv_pack(X_dev, n, d, l, Xs, precision == AFN_FP32, s));
+        AFN_TRY(afn::kmv_pack(X_dev, n, d, l, kind, Xs, precision == AFN_FP32, s));
         for (int64_t c0 = 0; c0 < nrhs; c0 += 64) {
             const int Rc = (int)(nrhs - c0 < 64 ? nrhs - c0 : 64);
             if (precision == AFN_FP32) {
                 AFN_TRY(afn::gather_rows<float>(v_dev + c0 * ld, ld, nullptr, n, Rc, nullptr, (float *)Pr, s));
-                AFN_TRY(afn::kmv_mrhs_run<float>((const float *)Xs, npad, n, d, mu, (const float *)Pr, Rc,
+                AFN_TRY(afn::kmv_mrhs_run<float>((const float *)Xs, npad, n, d, mu, kind, (const float *)Pr, Rc,
                                                  (float *)Yr, Rc, Rc, (float *)part, s));
                 AFN_TRY(afn::scatter_rows_f32((const float *)Yr, n, Rc, y_dev + c0 * ld, ld, s));
             } else {
                 AFN_TRY(afn::gather_rows<double>(v_dev + c0 * ld, ld, nullptr, n, Rc, nullptr, Pr, s));
-                AFN_TRY(afn::kmv_mrhs_run<double>(Xs, npad, n, d, mu, Pr, Rc, Yr, Rc, Rc, part, s));
+                AFN_TRY(afn::kmv_mrhs_run<double>(Xs, npad, n, d, mu, kind, Pr, Rc, Yr, Rc, Rc, part, s));
                 AFN_TRY(afn::scatter_rows(Yr, nullptr, n, Rc, y_dev + c0 * ld, ld, s));
             }
         }
@@ -199,8 +210,8 @@ afn_status kernel_matvec(const double *X_dev, int64_t n, int32_t d, double l, do
     }
     AFN_TRY(afn::library_scratch(sizeof(double) * (size_t)afn::kmv_workspace_doubles(n, d), &work));
     if (precision == AFN_FP32)
-        return afn::kmv_f32(X_dev, n, d, l, mu, v_dev, ld, y_dev, ld, nrhs, work, s);
-    return afn::kmv_f64(X_dev, n, d, l, mu, v_dev, ld, y_dev, ld, nrhs, (double *)work, s);
+        return afn::kmv_f32(X_dev, n, d, l, mu, kind, v_dev, ld, y_dev, ld, nrhs, work, s);
+    return afn::kmv_f64(X_dev, n, d, l, mu, kind, v_dev, ld, y_dev, ld, nrhs, (double *)work, s);
 }
 
 }  // extern "C"

@@ -43,6 +43,7 @@ class Request:
     tol: float = 1e-6
     method: int = afn.AFN_METHOD_AFN
     maxit: int = 500
+    kernel: int = afn.AFN_KERNEL_GAUSSIAN
 
 
 @dataclasses.dataclass
@@ -101,7 +102,8 @@ class Server:
                 X = torch.from_numpy(np.ascontiguousarray(r.X)).to(self.device, non_blocking=False)
                 b = torch.from_numpy(np.ascontiguousarray(r.b)).to(self.device, non_blocking=False)
                 h = afn.afn_setup(X, r.l, r.mu, k=r.k, w=r.w, k_max=r.k_max,
-                                  precision=self.precision, method=r.method, stream=stream)
+                                  precision=self.precision, method=r.method, kernel=r.kernel,
+                                  stream=stream)
                 try:
                     x, info = afn.afn_pcg_solve(h, b, tol=r.tol, maxit=r.maxit, stream=stream)
                     si = h.info()
