@@ -48,7 +48,11 @@ def kmv_flops(n: int, d: int, nrhs: int = 1) -> float:
 
 
 def source_hash(path: pathlib.Path) -> str:
-    return hashlib.sha256(path.read_bytes()).hexdigest()[:16]
+    """sha256[:16] of a tile-kernel source together with the kernel-function
+    header it includes."""
+    h = hashlib.sha256(path.read_bytes())
+    h.update((path.parent / "kfun.h").read_bytes())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_profile(kernel_src: pathlib.Path):

@@ -12,11 +12,15 @@
 // every kernel value in it; kernel_cut_t(kind, cut) is the t at which the
 // kernel value is 2^-cut.
 //
-// 2^(-t) in FP64: t clamped to 2000 (the result underflows long before),
-// k = rint(t), f = k - t in [-1/2, 1/2] exactly, 2^(-t) = p(f) 2^(-k) with p
-// the degree-11 polynomial interpolating 2^f at the Chebyshev nodes of
-// [-1/2, 1/2] (interpolation error 4.4e-18 relative; Horner in FP64 <= 1.7
-// ulp).  FP32: the hardware base-2 exponential.
+// 2^(-t) in FP64 (t >= 0): t clamped to 2000 (the result underflows long
+// before), k = rint(t) from c - t with c = 1.5 * 2^52 (ulp 1 there, so the
+// subtraction rounds t to the nearest integer, ties to even, and the low word
+// of c - t is -k as a 32-bit integer), f = k - t in [-1/2, 1/2] exactly, and
+// 2^(-t) = p(f) 2^(-k) with p the degree-11 polynomial interpolating 2^f at
+// the Chebyshev nodes of [-1/2, 1/2] (interpolation error 4.4e-18 relative;
+// Horner in FP64 <= 1.7 ulp).  No FP64 round or convert instruction (both
+// slower than an FMA on this hardware).  FP32: the hardware base-2
+// exponential.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -30,7 +34,8 @@ constexpr double kLn2 = 0.6931471805599453;
 __device__ __forceinline__ double exp2_neg(double t)
 {
     t = t < 2000.0 ? t : 2000.0;
-    const double kd = __builtin_rint(t);
+    const double kb = 6755399441055744.0 - t;
+    const double kd = 6755399441055744.0 - kb;
     const double f = kd - t;
     double p = 4.45594401136235e-10;
     p = __builtin_fma(p, f, 7.074200215313511e-09);
@@ -44,7 +49,7 @@ __device__ __forceinline__ double exp2_neg(double t)
     p = __builtin_fma(p, f, 0.2402265069591016);
     p = __builtin_fma(p, f, 0.6931471805599453);
     p = __builtin_fma(p, f, 1.0);
-    return __builtin_ldexp(p, (int)(-kd));
+    return __builtin_ldexp(p, __double2loint(kb));
 }
 
 __device__ __forceinline__ float exp2_neg(float t) { return __builtin_amdgcn_exp2f(-t); }
