@@ -32,10 +32,10 @@ PEAK_FP32_TFLOPS = 157.3         # MI355X FP32 vector
 # FP64 VALU lane-operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 VALU_F64_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # FP64 VALU instructions per unique kernel evaluation in the inner loop of
-# kmv_sym<3, double, double> (AMD assembly of this build: 385 FP64 VALU
-# instructions per 4 x 4 block of pairs -- 6 for the distance, 16 for the
+# kmv_sym<0, 3, double, double> (AMD assembly of this build: 401 VALU
+# instructions per 4 x 4 block of pairs -- 6 for the distance, 17 for the
 # software 2^-t, 2 FMAs for the row and column products).
-VALU_F64_OPS_PER_PAIR_D3 = 385 / 16
+VALU_F64_OPS_PER_PAIR_D3 = 401 / 16
 
 
 def kmv_flops(n: int, d: int, nrhs: int = 1) -> float:
@@ -55,23 +55,27 @@ def source_hash(path: pathlib.Path) -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel_src: pathlib.Path):
-    """HBM bytes per launch of the tile kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
+def counters_from_profile(kernel_src: pathlib.Path) -> dict:
+    """HBM bytes per launch, clock and VALU issue fraction of the tile kernel
+    from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel source (else an empty dict)."""
     f = ROOT / "profiles" / "kmv_f64_sym_c2_counters.txt"
     if not f.exists():
-        return None
+        return {}
     vals = {}
     for line in f.read_text().splitlines():
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != source_hash(kernel_src):
-        return None
-    try:
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+        return {}
+    out = {}
+    for key in ("hbm_bytes_per_launch", "clock_ghz", "valu_issue_frac"):
+        try:
+            out[key] = float(vals[key])
+        except (KeyError, ValueError):
+            pass
+    return out
 
 
 def cpu_baseline(X, b, l, mu, k, w, iters, n_rows=2000, n_knn=500, n_fsai=6):
@@ -455,7 +459,8 @@ def main():
     F = kmv_flops(p.n, p.d)
     achieved = F / (kmv_ms * 1e-3) / 1e12
     kern_src = ROOT / "paper_2304_05460_amd" / "csrc" / "kmv.hip"
-    traffic = traffic_from_profile(kern_src)
+    ctrs = counters_from_profile(kern_src)
+    traffic = ctrs.get("hbm_bytes_per_launch")
     E = p.n * (p.n - 1) / 2
     # the pruned kernel evaluates only the tile pairs whose kernel values can
     # exceed 2^-64; the instruction floor is for the pairs it evaluates
@@ -470,6 +475,11 @@ def main():
                 "tile_pairs_evaluated": round(kept, 4),
                 "valu_instr_floor_ms": round(valu_floor_ms, 4),
                 "valu_instr_frac": round(valu_floor_ms / kmv_ms, 4)}
+    if "valu_issue_frac" in ctrs:
+        # measured by counters on this kernel source: VALU instructions issued
+        # per SIMD-cycle against one every 4 cycles, at the measured clock
+        roofline["valu_issue_frac_counters"] = ctrs["valu_issue_frac"]
+        roofline["clock_ghz_counters"] = ctrs.get("clock_ghz")
 
     # the same input through the mixed-precision path (FP32 inner PCG inside
     # FP64 iterative refinement)

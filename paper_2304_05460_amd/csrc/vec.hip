@@ -90,6 +90,24 @@ __global__ __launch_bounds__(256) void gemv_n_reduce(const T *__restrict__ part,
     y[i] = (base ? base[i] : T(0)) + sign * s;
 }
 
+// The same with one wavefront per row, for many splits: lane q adds splits
+// q, q + 64, ... in order, then the 64 lane sums are added by a fixed
+// butterfly (deterministic).
+template <typename T>
+__global__ __launch_bounds__(256) void gemv_n_reduce_wave(const T *__restrict__ part, int64_t m,
+                                                          int splits, const T *__restrict__ base,
+                                                          T sign, T *__restrict__ y)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= m) return;
+    T s = T(0);
+    for (int k = lane; k < splits; k += 64) s += part[(int64_t)k * m + i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) y[i] = (base ? base[i] : T(0)) + sign * s;
+}
+
 // y[j] = base[j] + sign * sum_i A[i + j*lda] x[i], one wavefront per column.
 template <typename T>
 __global__ __launch_bounds__(256) void gemv_t_kernel(const T *__restrict__ A, int64_t lda, int64_t m,
@@ -316,8 +334,12 @@ afn_status gemv_nT(const T *A, int64_t lda, int64_t m, int64_t ncols, const T *x
     const int64_t chunk = ceil_div(ncols, S);
     hipLaunchKernelGGL((gemv_n_partial<T>), dim3((unsigned)ceil_div(m, 256), (unsigned)S), dim3(256), 0, s,
                        A, lda, m, ncols, x, chunk, part);
-    hipLaunchKernelGGL((gemv_n_reduce<T>), dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, part, m,
-                       (int)S, base, sign, y);
+    if (S > 32)
+        hipLaunchKernelGGL((gemv_n_reduce_wave<T>), dim3((unsigned)ceil_div(m, 4)), dim3(256), 0, s, part, m,
+                           (int)S, base, sign, y);
+    else
+        hipLaunchKernelGGL((gemv_n_reduce<T>), dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, part, m,
+                           (int)S, base, sign, y);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }
