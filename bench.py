@@ -31,11 +31,12 @@ PEAK_FP64_TFLOPS = 78.6          # MI355X FP64 vector (FMA = 2 flops)
 PEAK_FP32_TFLOPS = 157.3         # MI355X FP32 vector
 # FP64 VALU lane-operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 VALU_F64_LANE_OPS = 256 * 4 * 16 * 2.4e9
-# FP64 VALU instructions per unique kernel evaluation in the inner loop of
-# kmv_sym<0, 3, double, double> (AMD assembly of this build: 401 VALU
-# instructions per 4 x 4 block of pairs -- 6 for the distance, 17 for the
-# software 2^-t, 2 FMAs for the row and column products).
-VALU_F64_OPS_PER_PAIR_D3 = 401 / 16
+# VALU instructions per unique kernel evaluation in the inner loop of
+# kmv_sym_mf<0, 3, double, double> (AMD assembly of this build: 335 VALU
+# instructions besides 4 MFMAs per tile pair and lane, i.e. per 16 pairs --
+# the squared norms into the accumulator, 17 for the software 2^-t, 2 FMAs
+# for the row and column products, the column-sum exchanges).
+VALU_F64_OPS_PER_PAIR_D3 = 335 / 16
 
 
 def kmv_flops(n: int, d: int, nrhs: int = 1) -> float:
@@ -468,7 +469,7 @@ def main():
     valu_floor_ms = kept * E * VALU_F64_OPS_PER_PAIR_D3 / VALU_F64_LANE_OPS * 1e3
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                "traffic": traffic, "kernel": "kmv_sym<3, double, double>",
+                "traffic": traffic, "kernel": "kmv_sym_mf<0, 3, double, double>",
                 "avg_launch_ms": round(kmv_ms, 4), "launches": launches,
                 "flops_per_launch": F,
                 "kernel_evals_per_s": round(E / (kmv_ms * 1e-3), 1),

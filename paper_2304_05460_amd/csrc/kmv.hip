@@ -16,9 +16,11 @@
 // 256 rows per workgroup, columns streamed through LDS, S split partials
 // added in order by kmv_reduce.
 #include <cmath>
+#include <type_traits>
 
 #include "afn_internal.h"
 #include "kfun.h"
+#include "mfma.h"
 
 namespace afn {
 namespace {
@@ -26,7 +28,10 @@ namespace {
 constexpr int kRows = 256;
 
 constexpr int kTile = 64;
-constexpr int kMaxST = 16;
+constexpr int kMaxST = 8;
+// Largest squared half-diagonal (scaled units) of a row tile whose distances
+// the MFMA variant forms from norms and dot products.
+constexpr double kCentredR2Max = 16.0;
 
 // Xs[t * npad + q] = X[perm[q]*d + t] * scale for q < n (perm may be null:
 // identity), 0 beyond (rounded to T).
@@ -194,6 +199,260 @@ __global__ __launch_bounds__(256) void kmv_sym(const T *__restrict__ Xs, int64_t
     for (int e = tid; e < ST * kTile; e += 256) colout[e] = (&colacc[0][0])[e];
 }
 
+// Cross-lane sums in a fixed order.  Each step keeps half of a lane's values
+// and trades the other half with its partner (the empty asm keeps the
+// selects on values; otherwise they are folded into a runtime index into the
+// array, which becomes a compare-and-select chain).
+template <typename T>
+__device__ __forceinline__ void keep_or_send(bool hi, T &a, T &b, T &keep, T &send)
+{
+    asm volatile("" : "+v"(a), "+v"(b));
+    keep = hi ? b : a;
+    send = hi ? a : b;
+}
+
+// Four values over the four lane groups (lanes l, l + 16, l + 32, l + 48):
+// on return lane l holds the total of value l >> 4.
+template <typename T>
+__device__ __forceinline__ T groups4_sum(T (&v)[4], int lane)
+{
+    T h[2], keep, send;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        keep_or_send((lane & 32) != 0, v[j], v[2 + j], keep, send);
+        h[j] = keep + __shfl_xor(send, 32);
+    }
+    keep_or_send((lane & 16) != 0, h[0], h[1], keep, send);
+    return keep + __shfl_xor(send, 16);
+}
+
+// Four values over the 16 lanes of a lane group: on return lane l holds the
+// total of value (l & 15) >> 2.
+template <typename T>
+__device__ __forceinline__ T lanes16_sum4(T (&v)[4], int lane)
+{
+    T h[2], keep, send;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        keep_or_send((lane & 8) != 0, v[j], v[2 + j], keep, send);
+        h[j] = keep + __shfl_xor(send, 8);
+    }
+    keep_or_send((lane & 4) != 0, h[0], h[1], keep, send);
+    T q = keep + __shfl_xor(send, 4);
+    q += __shfl_xor(q, 2);
+    q += __shfl_xor(q, 1);
+    return q;
+}
+
+// The symmetric tile kernel with the distance contraction on the matrix
+// cores (Hilbert-ordered points with tile boxes).
+//
+// In a 64 x 64 tile pair, wave w owns rows 16 w .. 16 w + 15 and all 64
+// columns.  Coordinates are centred on the middle of the row tile's box; for
+// each 16-column block one MFMA 16x16x4 per 4 coordinates forms
+// |x_i|^2 + |x_j|^2 - 2 x_i . x_j (the accumulator starts at the two squared
+// norms).  Centring bounds the cancellation: with h2 the squared
+// half-diagonal of the row tile's box, the distance carries an absolute
+// error of about 2 (h2 + (sqrt(t) + sqrt(h2))^2) (d + 2) u, and a row tile
+// with h2 > r2max uses the plain differences instead.
+//
+// A lane holds 4 rows x 4 columns of each tile pair.  Its column sums are
+// transposed over the four lane groups so that lane l ends with column l,
+// which it adds to its wave's own LDS accumulator (no barrier); the four
+// waves' accumulators are added in order at the end.  Row sums are added
+// over the lane group once per row tile.  Column tiles are centred and
+// staged in LDS.  FP32: all kept column tiles of a row tile at once (loads
+// from every thread in flight together), so the tile loop has no barrier.
+// FP64 (whose registers allow 4 waves per SIMD only with a small LDS
+// footprint): two buffers, the next kept tile read into registers while the
+// current one is evaluated, one barrier per tile pair.
+template <int KIND, int D, typename T, typename VT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void kmv_sym_mf(
+    const T *__restrict__ Xs, int64_t npad, int64_t n, const VT *__restrict__ v, const int32_t *__restrict__ perm,
+    const T *__restrict__ box, T tcut, T r2max, int S, int ST, T *__restrict__ part)
+{
+    using M = Mfma<T>;
+    constexpr int KC = D <= 4 ? 1 : 2;
+    __shared__ T rx[4 * KC][kTile];         // centred row coordinates, zero beyond D
+    __shared__ T rn[kTile], rv[kTile];      // row squared norms and vector values
+    constexpr bool STAGE_ALL = sizeof(T) == 4;
+    constexpr int NBUF = STAGE_ALL ? kMaxST : 2;
+    __shared__ T cb[NBUF][4 * KC][kTile];   // -2 x centred column coordinates
+    __shared__ T cn[NBUF][kTile], cv[NBUF][kTile];
+    __shared__ T colacc[4][kMaxST][kTile];  // per-wave column partial sums
+    __shared__ unsigned char keep[kMaxST * kMaxST];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int lc = lane & 15, lg = lane >> 4;
+    int BI, BJ;
+    decode_pair(blockIdx.x, S, BI, BJ);
+    const int64_t SB = (int64_t)ST * kTile;
+    const bool diag_super = BI == BJ;
+    for (int e = tid; e < 4 * kMaxST * kTile; e += 256) (&colacc[0][0][0])[e] = T(0);
+    if (tid < ST * ST)
+        keep[tid] = box_gap2<D, T>(box, (int64_t)BI * ST + tid / ST, (int64_t)BJ * ST + tid % ST) < tcut;
+    T *rowout = part + (int64_t)blockIdx.x * 2 * SB;
+    T *colout = rowout + SB;
+    auto next_kept = [&](int ti, int tj) {
+        while (tj < ST && !keep[ti * ST + tj]) ++tj;
+        return tj;
+    };
+    T cen[D];
+    // one column per thread 0..63 (two-buffer mode)
+    T xn[D], vn = T(0);
+    auto load_col = [&](int tt) {
+        const int64_t q = BJ * SB + (int64_t)tt * kTile + tid;
+#pragma unroll
+        for (int t = 0; t < D; ++t) xn[t] = Xs[(int64_t)t * npad + q];
+        vn = q < n ? (T)v[perm ? (int64_t)perm[q] : q] : T(0);
+    };
+    auto store_col = [&](int buf) {
+        T nrm = T(0);
+#pragma unroll
+        for (int t = 0; t < 4 * KC; ++t) {
+            const T xc = t < D ? xn[t] - cen[t] : T(0);
+            cb[buf][t][tid] = T(-2) * xc;
+            nrm = fmaT(xc, xc, nrm);
+        }
+        cn[buf][tid] = nrm;
+        cv[buf][tid] = vn;
+    };
+    for (int ti = 0; ti < ST; ++ti) {
+        const int64_t rt = (int64_t)BI * ST + ti;
+        T h2 = T(0);
+        bool empty = false;
+#pragma unroll
+        for (int t = 0; t < D; ++t) {
+            const T lo = box[(rt * D + t) * 2], hi = box[(rt * D + t) * 2 + 1];
+            empty = empty || !(lo <= hi);
+            cen[t] = (lo + hi) * T(0.5);
+            const T half = (hi - lo) * T(0.5);
+            h2 = fmaT(half, half, h2);
+        }
+        if (empty) {          // padding tile: no point, nothing to add
+            if (tid < kTile) rowout[(int64_t)ti * kTile + tid] = T(0);
+            continue;
+        }
+        const bool use_mf = h2 <= r2max;
+        __syncthreads();      // the previous row tile's readers are done
+        const int tfirst = diag_super ? ti : 0;
+        int tj = next_kept(ti, tfirst);
+        if (tid < kTile) {
+            const int64_t q = rt * kTile + tid;
+            T nrm = T(0);
+#pragma unroll
+            for (int t = 0; t < 4 * KC; ++t) {
+                const T xr = t < D ? Xs[(int64_t)t * npad + q] - cen[t] : T(0);
+                rx[t][tid] = xr;
+                nrm = fmaT(xr, xr, nrm);
+            }
+            rn[tid] = nrm;
+            rv[tid] = q < n ? (T)v[perm ? (int64_t)perm[q] : q] : T(0);
+        }
+        if constexpr (STAGE_ALL) {
+            for (int e = tid; e < ST * kTile; e += 256) {
+                const int tt = e / kTile, j = e % kTile;
+                if (tt < tfirst || !keep[ti * ST + tt]) continue;
+                const int64_t q = BJ * SB + (int64_t)tt * kTile + j;
+                T nrm = T(0);
+#pragma unroll
+                for (int t = 0; t < 4 * KC; ++t) {
+                    const T xc = t < D ? Xs[(int64_t)t * npad + q] - cen[t] : T(0);
+                    cb[tt][t][j] = T(-2) * xc;
+                    nrm = fmaT(xc, xc, nrm);
+                }
+                cn[tt][j] = nrm;
+                cv[tt][j] = q < n ? (T)v[perm ? (int64_t)perm[q] : q] : T(0);
+            }
+        } else {
+            if (tid < kTile && tj < ST) {
+                load_col(tj);
+                store_col(0);
+            }
+        }
+        __syncthreads();
+        T a[KC], nr[4], vr[4], racc[4];
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) a[kc] = rx[4 * kc + lg][16 * wave + lc];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * wave + M::row(lane, i);
+            nr[i] = rn[r];
+            vr[i] = rv[r];
+            racc[i] = T(0);
+        }
+        // the tile loop, instantiated once per way of forming the distances
+        auto tile_loop = [&](auto mf_tag) {
+            constexpr bool MF = decltype(mf_tag)::value;
+            int nb = 0;
+            while (tj < ST) {
+                const int tn = next_kept(ti, tj + 1);
+                if constexpr (!STAGE_ALL) {
+                    if (tn < ST && tid < kTile) load_col(tn);
+                }
+                const int b = STAGE_ALL ? tj : nb;
+                T cacc[4];
+                typename M::acc_t c[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int col = 16 * m + lc;
+                    if constexpr (MF) {
+                        const T ncol = cn[b][col];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) c[m][i] = nr[i] + ncol;
+#pragma unroll
+                        for (int kc = 0; kc < KC; ++kc) c[m] = M::op(a[kc], cb[b][4 * kc + lg][col], c[m]);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int r = 16 * wave + M::row(lane, i);
+                            T d2 = T(0);
+#pragma unroll
+                            for (int t = 0; t < D; ++t) {
+                                const T del = fmaT(T(0.5), cb[b][t][col], rx[t][r]);
+                                d2 = fmaT(del, del, d2);
+                            }
+                            c[m][i] = d2;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const T vcol = cv[b][16 * m + lc];
+                    cacc[m] = T(0);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        // a slightly negative distance (rounding) is harmless in
+                        // 2^-t, but not under the square root of the Matern kernel
+                        T t2 = c[m][i];
+                        if constexpr (KIND == AFN_KERNEL_MATERN32) t2 = t2 > T(0) ? t2 : T(0);
+                        const T kij = kernel_scaled<KIND, T>(t2);
+                        racc[i] = fmaT(kij, vcol, racc[i]);
+                        cacc[m] = fmaT(kij, vr[i], cacc[m]);
+                    }
+                }
+                if (!(diag_super && tj == ti)) colacc[wave][tj][lane] += groups4_sum(cacc, lane);
+                if constexpr (!STAGE_ALL) {
+                    if (tn < ST && tid < kTile) store_col(nb ^ 1);
+                    __syncthreads();
+                    nb ^= 1;
+                }
+                tj = tn;
+            }
+        };
+        if (use_mf) tile_loop(std::true_type{});
+        else tile_loop(std::false_type{});
+        // rows of this wave's stripe: lane l ends with row value i = (l & 15) >> 2
+        const T tot = lanes16_sum4(racc, lane);
+        if ((lc & 3) == 0) rowout[(int64_t)ti * kTile + 16 * wave + M::row(lane, lc >> 2)] = tot;
+    }
+    __syncthreads();
+    for (int e = tid; e < ST * kTile; e += 256) {
+        const int tt = e / kTile, j = e % kTile;
+        colout[e] = ((colacc[0][tt][j] + colacc[1][tt][j]) + colacc[2][tt][j]) + colacc[3][tt][j];
+    }
+}
+
 // y_i = sum over BJ >= s of row partials + sum over BI <= s of column
 // partials (ascending) + mu v_i, s = super-block of i.
 template <typename T, typename VT>
@@ -359,7 +618,7 @@ int64_t kmv_splits(int64_t n)
 
 namespace {
 
-// Super-block size: enough workgroups to fill the chip, at most 16 tiles.
+// Super-block size: enough workgroups to fill the chip, at most kMaxST tiles.
 struct SymShape {
     int ST, S;
     int64_t npad, nwg;
@@ -394,11 +653,36 @@ int64_t kmv_workspace_doubles(int64_t n, int d)
 
 namespace {
 
+template <int KIND, int D, typename T, typename VT>
+void launch_mf(dim3 grid, const T *Xs, int64_t npad, int64_t n, const VT *v, const int32_t *perm, const T *box,
+               T tcut, T r2, int S, int ST, T *part, hipStream_t s)
+{
+    if constexpr (sizeof(T) == 4 || D <= 4)
+        hipLaunchKernelGGL((kmv_sym_mf<KIND, D, T, VT>), grid, dim3(256), 0, s, Xs, npad, n, v, perm, box, tcut, r2,
+                           S, ST, part);
+}
+
 template <int KIND, typename T, typename VT>
 void launch_sym(int d, dim3 grid, const T *Xs, int64_t npad, int64_t n, const VT *v, const int32_t *perm,
                 const T *box, T tcut, int S, int ST, T *part, hipStream_t s)
 {
     const dim3 block(256);
+    // the MFMA variant needs tile boxes; FP64 above d = 4 (two coordinate
+    // chunks) does not fit its register budget and keeps the plain kernel
+    if (box && (sizeof(T) == 4 || d <= 4)) {
+        const T r2 = T(kCentredR2Max);
+        switch (d) {
+            case 1: launch_mf<KIND, 1, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, r2, S, ST, part, s); break;
+            case 2: launch_mf<KIND, 2, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, r2, S, ST, part, s); break;
+            case 3: launch_mf<KIND, 3, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, r2, S, ST, part, s); break;
+            case 4: launch_mf<KIND, 4, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, r2, S, ST, part, s); break;
+            case 5: launch_mf<KIND, 5, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, r2, S, ST, part, s); break;
+            case 6: launch_mf<KIND, 6, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, r2, S, ST, part, s); break;
+            case 7: launch_mf<KIND, 7, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, r2, S, ST, part, s); break;
+            default: launch_mf<KIND, 8, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, r2, S, ST, part, s); break;
+        }
+        return;
+    }
     switch (d) {
         case 1: hipLaunchKernelGGL((kmv_sym<KIND, 1, T, VT>), grid, block, 0, s, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
         case 2: hipLaunchKernelGGL((kmv_sym<KIND, 2, T, VT>), grid, block, 0, s, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;

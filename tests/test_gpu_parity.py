@@ -132,6 +132,31 @@ def test_kernel_matvec_full_size_fp32_and_d8(afn):
     assert np.all(np.abs(y[rows] - yo) <= 2 * (q.n + 4) * U * ab + PRUNE64 * np.abs(v).sum())
 
 
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_kernel_matvec_compact_and_wide_tiles(afn, kernel):
+    # a tight cluster (compact tiles: distances from norms and MFMA dot
+    # products) and a sparse uniform background (tiles wider than the
+    # centring limit: plain differences) in one pruned call
+    rng = np.random.default_rng(25)
+    n, l = 20000, 0.01
+    X = np.concatenate([0.5 + 0.002 * rng.standard_normal((19000, 3)), rng.random((1000, 3))])
+    v = rng.standard_normal(n)
+    rows = np.concatenate([np.arange(8), 19000 + np.arange(8), rng.integers(0, n, 30)])
+    with oracle.use_kernel("matern32" if kernel else "gaussian"):
+        yo, ab = oracle.kernel_matvec_rows(X, l, 1e-3, v, rows)
+    # Matern: the pruned pairs are below 2^-64 (2^-44) as well; its values
+    # carry the extra sqrt rounding, covered by the factor 4
+    for prec in (afn.AFN_FP64, afn.AFN_FP32):
+        y = afn.kernel_matvec(dev(X), l, 1e-3, dev(v), precision=prec, kernel=kernel).cpu().numpy()
+        if prec == afn.AFN_FP64:
+            bound = 4 * 2 * (n + 4) * U * ab + PRUNE64 * np.abs(v).sum()
+        else:
+            bound = 4 * (30 * 7 * math.log(2) + n + 8) * U32 * ab + (1e-13 + PRUNE32) * np.abs(v).sum()
+        err = np.abs(y[rows] - yo)
+        say(f"compact+wide kernel={kernel} prec={prec}: worst err/bound {np.max(err / bound):.3f}")
+        assert np.all(err <= bound)
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_kernel_matvec_full_size_64_columns(afn, prec):
     # 1.5e5 uniform points, l = 0.05, 64 columns: the MFMA tile kernel with pruning
