@@ -152,6 +152,167 @@ __global__ __launch_bounds__(512) void kmv_mrhs(const T *__restrict__ Xs, int64_
         }
 }
 
+// FP32 variant, software-pipelined.  64 rows per workgroup (4 waves); for
+// each kept column tile the MFMAs consume the kernel-value tile E and the
+// vector block P_J staged in LDS by the previous step, while the same waves
+// compute E and load P_J for the next kept tile into the other buffer (the
+// two parts sit in one basic block, so the scheduler can interleave the
+// VALU work with the matrix-core work).  One barrier per tile.  LDS tiles
+// are XOR-swizzled instead of padded (two workgroups fit per CU):
+//   E:   element (k, r) at k * 64 + (r ^ 16 (k & 3))
+//   P_J: element (k, c) at k * LD + (c ^ 16 (k & 3)) for R = 64; rows of
+//        16 or 48 values (LD = 16, 48) need no swizzle
+// so the MFMA operand reads of the four lane groups (rows 4 kk + g) fall in
+// four different 16-bank groups.
+template <int NB>
+struct PjLayout {
+    static constexpr int RP = 16 * NB;
+    static constexpr int LD = NB == 2 ? 48 : RP;
+    static __device__ __forceinline__ int at(int k, int c)
+    {
+        return k * LD + (NB == 4 ? (c ^ (16 * (k & 3))) : c);
+    }
+};
+
+template <int KIND, int D, int NB>
+__global__ __launch_bounds__(256) void kmv_mrhs_pipe(const float *__restrict__ Xs, int64_t npad, int64_t n,
+                                                     const float *__restrict__ P, int64_t ldp, int R,
+                                                     int tiles_per_split, float *__restrict__ part,
+                                                     const int32_t *__restrict__ perm, const float *__restrict__ box,
+                                                     float tcut)
+{
+    using M = Mfma<float>;
+    using L = PjLayout<NB>;
+    constexpr int RP = L::RP;
+    constexpr int PV4 = NB;             // groups of 4 P values per thread and tile (64 RP / 1024)
+    constexpr int CHUNK = 2048;         // column tiles listed at a time
+    __shared__ float Es[2][TL * TL];
+    __shared__ float Pj[2][TL * L::LD];
+    __shared__ int jlist[CHUNK];
+    __shared__ int wcnt[4];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63, lc = lane & 15, g = lane >> 4;
+    const int64_t r0 = (int64_t)blockIdx.x * TL;
+    const int64_t ntiles = npad / TL;
+    const int64_t J0 = (int64_t)blockIdx.y * tiles_per_split;
+    const int64_t J1 = J0 + tiles_per_split < ntiles ? J0 + tiles_per_split : ntiles;
+    float xi[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t) xi[t] = Xs[(int64_t)t * npad + r0 + lane];
+    float rlo[D], rhi[D];
+    if (box) {
+#pragma unroll
+        for (int t = 0; t < D; ++t) {
+            rlo[t] = box[((int64_t)blockIdx.x * D + t) * 2];
+            rhi[t] = box[((int64_t)blockIdx.x * D + t) * 2 + 1];
+        }
+    }
+    typename M::acc_t acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = typename M::acc_t{};
+    // staging of the next tile: values 4 e .. 4 e + 3 of P_J for
+    // e = tid + 256 i (row 4 e / RP), so that 16 / NB consecutive lanes read
+    // a row and write it to LDS as whole 16-byte words; coordinates of this
+    // wave's 16 columns
+    float pv[PV4][4], xc[16][D];
+    auto load_next = [&](int64_t j0) {
+#pragma unroll
+        for (int i = 0; i < PV4; ++i) {
+            const int e = 4 * (tid + 256 * i), k = e / RP, c = e % RP;
+            const int64_t q = j0 + k;
+            const float *src = P + (q < n ? (perm ? (int64_t)perm[q] : q) * ldp : 0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pv[i][u] = (q < n && c + u < R) ? src[c + u] : 0.0f;
+        }
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+#pragma unroll
+            for (int t = 0; t < D; ++t) xc[c][t] = Xs[(int64_t)t * npad + j0 + 16 * wave + c];
+    };
+    auto stage_next = [&](int b) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const int col = 16 * wave + c;
+            float d2 = 0.0f;
+#pragma unroll
+            for (int t = 0; t < D; ++t) {
+                const float del = xi[t] - xc[c][t];
+                d2 = __builtin_fmaf(del, del, d2);
+            }
+            Es[b][col * TL + (lane ^ (16 * (col & 3)))] = kernel_scaled<KIND, float>(d2);
+        }
+#pragma unroll
+        for (int i = 0; i < PV4; ++i) {
+            const int e = 4 * (tid + 256 * i);
+            float *dst = &Pj[b][L::at(e / RP, e % RP)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) dst[u] = pv[i][u];
+        }
+    };
+    for (int64_t Jc = J0; Jc < J1; Jc += CHUNK) {
+        const int64_t Je = Jc + CHUNK < J1 ? Jc + CHUNK : J1;
+        // kept column tiles of this chunk in ascending order (the summation
+        // order over tiles is the same as without pruning)
+        int total = 0;
+        for (int64_t Jr = Jc; Jr < Je; Jr += 256) {
+            const int64_t Jt = Jr + tid;
+            bool keep = Jt < Je;
+            if (keep && box) {
+                float g2 = 0.0f;
+#pragma unroll
+                for (int t = 0; t < D; ++t) {
+                    const float blo = box[(Jt * D + t) * 2], bhi = box[(Jt * D + t) * 2 + 1];
+                    float gap = blo - rhi[t] > rlo[t] - bhi ? blo - rhi[t] : rlo[t] - bhi;
+                    gap = gap > 0.0f ? gap : 0.0f;
+                    g2 = __builtin_fmaf(gap, gap, g2);
+                }
+                keep = g2 < tcut;
+            }
+            const unsigned long long mask = __ballot(keep);
+            __syncthreads();
+            if (lane == 0) wcnt[wave] = (int)__popcll(mask);
+            __syncthreads();
+            int before = 0, cnt = 0;
+#pragma unroll
+            for (int w2 = 0; w2 < 4; ++w2) {
+                before += w2 < wave ? wcnt[w2] : 0;
+                cnt += wcnt[w2];
+            }
+            if (keep) jlist[total + before + (int)__popcll(mask & ((1ull << lane) - 1ull))] = (int)(Jt - Jc);
+            total += cnt;
+        }
+        __syncthreads();
+        if (total == 0) continue;
+        load_next((Jc + jlist[0]) * TL);
+        stage_next(0);
+        __syncthreads();
+        for (int qj = 0; qj < total; ++qj) {
+            const int b = qj & 1;
+            // the next kept tile (past the end: the first one again; staged
+            // into the unused buffer and never read)
+            const int64_t jn = (Jc + jlist[qj + 1 < total ? qj + 1 : 0]) * TL;
+            load_next(jn);
+#pragma unroll
+            for (int kk = 0; kk < TL / 4; ++kk) {
+                const int k = 4 * kk + g;
+                const float a = Es[b][k * TL + ((16 * wave + lc) ^ (16 * (k & 3)))];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) acc[nb] = M::op(a, Pj[b][L::at(k, 16 * nb + lc)], acc[nb]);
+            }
+            stage_next(b ^ 1);
+            __syncthreads();
+        }
+    }
+    float *out = part + (int64_t)blockIdx.y * npad * RP;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t row = r0 + 16 * wave + M::row(lane, q);
+            out[row * RP + 16 * nb + lc] = acc[nb][q];
+        }
+}
+
 // Y[i * ldy + c] = sum_s part[s][i * RP + c] + mu P[i * ldp + c]
 template <typename T>
 __global__ __launch_bounds__(256) void mrhs_reduce(const T *__restrict__ part, int64_t npad, int RP,
@@ -448,8 +609,14 @@ template <int KIND, int D, typename T, int NB>
 void launch_mrhs(dim3 g, const T *Xs, int64_t npad, int64_t n, const T *P, int64_t ldp, int R, int tps,
                  T *part, const int32_t *perm, const T *box, T tcut, hipStream_t s)
 {
-    hipLaunchKernelGGL((kmv_mrhs<KIND, D, T, NB>), g, dim3(512), 0, s, Xs, npad, n, P, ldp, R, tps, part, perm,
-                       box, tcut);
+    if constexpr (sizeof(T) == 4) {
+        // 64-row workgroups: twice the row blocks of the 128-row grid
+        hipLaunchKernelGGL((kmv_mrhs_pipe<KIND, D, NB>), dim3(2 * g.x, g.y), dim3(256), 0, s, Xs, npad, n, P, ldp,
+                           R, tps, part, perm, box, tcut);
+    } else {
+        hipLaunchKernelGGL((kmv_mrhs<KIND, D, T, NB>), g, dim3(512), 0, s, Xs, npad, n, P, ldp, R, tps, part,
+                           perm, box, tcut);
+    }
 }
 
 template <int KIND, typename T, int NB>
@@ -486,8 +653,10 @@ void launch_mrhs_nb(int NBk, int d, dim3 g, const T *Xs, int64_t npad, int64_t n
 
 int mrhs_splits(int64_t npad)
 {
+    // enough (row block, split) workgroups that the last wave of them is a
+    // small part of the launch: pruning makes their work uneven
     const int64_t rt = npad / BM;
-    int64_t s = ceil_div(1024, rt);
+    int64_t s = ceil_div(4096, rt);
     if (s > rt) s = rt;
     if (s > 64) s = 64;
     return (int)(s < 1 ? 1 : s);
