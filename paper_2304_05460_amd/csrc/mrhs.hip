@@ -332,8 +332,33 @@ __global__ __launch_bounds__(256) void mrhs_reduce(const T *__restrict__ part, i
 }
 
 // part[s][i * RP + c] = sum_{t in split s} A(i, t) B(t, c), A(i,t) = A[i*ars + t*acs],
-// B row-major (ldb).  64 rows per workgroup, K in chunks of 64.
-template <typename T, int NB>
+// B row-major (ldb).  64 rows per workgroup, K in chunks of 64, each chunk
+// read with 16-byte loads along the contiguous dimension of A (t when
+// KF, i otherwise) and of B while the MFMAs run on the previous chunk
+// (double-buffered in LDS, one barrier per chunk).  LDS layouts (conflict-
+// free MFMA operand reads by the four lane groups): KF: A as [i][k] with
+// row stride 68; otherwise A as [k][i] and B as [k][c], row stride 80.
+// VEC: every 4-element group is 16-byte aligned (strides and bases checked
+// on the host); groups at the edges are read element by element.
+template <typename T, bool VEC>
+__device__ __forceinline__ void load4(const T *p, bool whole, int nvalid, int64_t step, T (&o)[4])
+{
+    if (VEC && whole) {
+        if constexpr (sizeof(T) == 4) {
+            const float4 x = *reinterpret_cast<const float4 *>(p);
+            o[0] = x.x; o[1] = x.y; o[2] = x.z; o[3] = x.w;
+        } else {
+            const double2 x = *reinterpret_cast<const double2 *>(p);
+            const double2 y = *reinterpret_cast<const double2 *>(p + 2);
+            o[0] = x.x; o[1] = x.y; o[2] = y.x; o[3] = y.y;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) o[u] = u < nvalid ? p[u * step] : T(0);
+    }
+}
+
+template <typename T, int NB, bool KF, bool VEC>
 __global__ __launch_bounds__(256) void gemm_splitk(const T *__restrict__ A, int64_t ars, int64_t acs,
                                                    int64_t m, int64_t K, const T *__restrict__ B,
                                                    int64_t ldb, int R, int64_t k_per_split,
@@ -341,37 +366,81 @@ __global__ __launch_bounds__(256) void gemm_splitk(const T *__restrict__ A, int6
 {
     using M = Mfma<T>;
     constexpr int RP = 16 * NB;
-    __shared__ T AsT[TL][LS];   // AsT[k][i]
-    __shared__ T Bs[TL][LS];    // Bs[k][c]
+    constexpr int LA = KF ? 68 : 80;
+    constexpr int LB = 80;
+    __shared__ T As[2][TL * LA];
+    __shared__ T Bs[2][TL * LB];
     const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
+    const int wave = tid >> 6, lane = tid & 63, lc = lane & 15, g = lane >> 4;
     const int64_t i0 = (int64_t)blockIdx.x * TL;
     const int64_t t0 = (int64_t)blockIdx.y * k_per_split;
     const int64_t t1 = t0 + k_per_split < K ? t0 + k_per_split : K;
     typename M::acc_t acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = typename M::acc_t{};
-    const bool k_fast = acs == 1;
-    for (int64_t tc = t0; tc < t1; tc += TL) {
-        __syncthreads();
-        for (int e = tid; e < TL * TL; e += 256) {
-            int i, k;
-            if (k_fast) { i = e / TL; k = e % TL; } else { k = e / TL; i = e % TL; }
-            const int64_t gi = i0 + i, gt = tc + k;
-            AsT[k][i] = (gi < m && gt < t1) ? A[gi * ars + gt * acs] : T(0);
-        }
-        for (int e = tid; e < TL * RP; e += 256) {
-            const int k = e / RP, c = e % RP;
-            const int64_t gt = tc + k;
-            Bs[k][c] = (gt < t1 && c < R) ? B[gt * ldb + c] : T(0);
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < TL / 4; ++kk) {
-            const int k = 4 * kk + (lane >> 4);
-            const T a = AsT[k][16 * wave + (lane & 15)];
+    T pa[4][4], pb[NB][4];
+    auto load = [&](int64_t tc) {
 #pragma unroll
-            for (int b = 0; b < NB; ++b) acc[b] = M::op(a, Bs[k][16 * b + (lane & 15)], acc[b]);
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + 256 * q;
+            if constexpr (KF) {
+                const int i = e / 16, k = 4 * (e % 16);
+                const int64_t gi = i0 + i, gt = tc + k;
+                const int nv = gi < m ? (int)(t1 - gt < 4 ? (t1 - gt > 0 ? t1 - gt : 0) : 4) : 0;
+                load4<T, VEC>(A + (gi < m ? gi : 0) * ars + (gt < t1 ? gt : t0) * acs, nv == 4, nv, acs, pa[q]);
+            } else {
+                const int k = e / 16, i = 4 * (e % 16);
+                const int64_t gi = i0 + i, gt = tc + k;
+                const int nv = gt < t1 ? (int)(m - gi < 4 ? (m - gi > 0 ? m - gi : 0) : 4) : 0;
+                load4<T, VEC>(A + (gi < m ? gi : 0) * ars + (gt < t1 ? gt : t0) * acs, nv == 4, nv, ars, pa[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int e = tid + 256 * q;
+            const int k = e / (RP / 4), c = 4 * (e % (RP / 4));
+            const int64_t gt = tc + k;
+            const int nv = gt < t1 ? (R - c < 4 ? (R - c > 0 ? R - c : 0) : 4) : 0;
+            load4<T, VEC>(B + (gt < t1 ? gt : t0) * ldb + (c < R ? c : 0), nv == 4, nv, 1, pb[q]);
+        }
+    };
+    auto store = [&](int b) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + 256 * q;
+            T *dst;
+            if constexpr (KF) dst = &As[b][(e / 16) * LA + 4 * (e % 16)];
+            else dst = &As[b][(e / 16) * LA + 4 * (e % 16)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) dst[u] = pa[q][u];
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int e = tid + 256 * q;
+            T *dst = &Bs[b][(e / (RP / 4)) * LB + 4 * (e % (RP / 4))];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) dst[u] = pb[q][u];
+        }
+    };
+    const int64_t nchunk = t1 > t0 ? ceil_div(t1 - t0, TL) : 0;
+    if (nchunk > 0) {
+        load(t0);
+        store(0);
+        __syncthreads();
+        for (int64_t ch = 0; ch < nchunk; ++ch) {
+            const int b = (int)(ch & 1);
+            // the next chunk (past the end: the last one again, staged into
+            // the unused buffer and never read)
+            load(t0 + (ch + 1 < nchunk ? ch + 1 : ch) * TL);
+#pragma unroll
+            for (int kk = 0; kk < TL / 4; ++kk) {
+                const int k = 4 * kk + g, i = 16 * wave + lc;
+                const T a = KF ? As[b][i * LA + k] : As[b][k * LA + i];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) acc[nb] = M::op(a, Bs[b][k * LB + 16 * nb + lc], acc[nb]);
+            }
+            store(b ^ 1);
+            __syncthreads();
         }
     }
     T *out = part + (int64_t)blockIdx.y * mpad * RP;
@@ -380,7 +449,7 @@ __global__ __launch_bounds__(256) void gemm_splitk(const T *__restrict__ A, int6
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int64_t row = i0 + 16 * wave + M::row(lane, q);
-            out[row * RP + 16 * b + (lane & 15)] = acc[b][q];
+            out[row * RP + 16 * b + lc] = acc[b][q];
         }
 }
 
@@ -718,6 +787,22 @@ int64_t gemm_part_elems(int64_t m, int64_t K)
     return (int64_t)gemm_splits(m, K) * round_up(m, TL) * 64;
 }
 
+namespace {
+
+template <typename T, bool KF, bool VEC>
+void launch_gemm(int NBk, dim3 g, const T *A, int64_t ars, int64_t acs, int64_t m, int64_t K, const T *B,
+                 int64_t ldb, int R, int64_t kps, T *part, int64_t mpad, hipStream_t s)
+{
+    switch (NBk) {
+        case 1: hipLaunchKernelGGL((gemm_splitk<T, 1, KF, VEC>), g, dim3(256), 0, s, A, ars, acs, m, K, B, ldb, R, kps, part, mpad); break;
+        case 2: hipLaunchKernelGGL((gemm_splitk<T, 2, KF, VEC>), g, dim3(256), 0, s, A, ars, acs, m, K, B, ldb, R, kps, part, mpad); break;
+        case 3: hipLaunchKernelGGL((gemm_splitk<T, 3, KF, VEC>), g, dim3(256), 0, s, A, ars, acs, m, K, B, ldb, R, kps, part, mpad); break;
+        default: hipLaunchKernelGGL((gemm_splitk<T, 4, KF, VEC>), g, dim3(256), 0, s, A, ars, acs, m, K, B, ldb, R, kps, part, mpad); break;
+    }
+}
+
+}  // namespace
+
 // C = base + sign * A B  (A(i,t) = A[i*ars + t*acs], m x K; B row-major K x R)
 template <typename T>
 afn_status gemm_rows(const T *A, int64_t ars, int64_t acs, int64_t m, int64_t K, const T *B,
@@ -730,12 +815,14 @@ afn_status gemm_rows(const T *A, int64_t ars, int64_t acs, int64_t m, int64_t K,
     const int64_t kps = round_up(ceil_div(K, S), TL);
     const int64_t mpad = round_up(m, TL);
     dim3 g((unsigned)ceil_div(m, TL), (unsigned)S);
-    switch (NBk) {
-        case 1: hipLaunchKernelGGL((gemm_splitk<T, 1>), g, dim3(256), 0, s, A, ars, acs, m, K, B, ldb, R, kps, part, mpad); break;
-        case 2: hipLaunchKernelGGL((gemm_splitk<T, 2>), g, dim3(256), 0, s, A, ars, acs, m, K, B, ldb, R, kps, part, mpad); break;
-        case 3: hipLaunchKernelGGL((gemm_splitk<T, 3>), g, dim3(256), 0, s, A, ars, acs, m, K, B, ldb, R, kps, part, mpad); break;
-        default: hipLaunchKernelGGL((gemm_splitk<T, 4>), g, dim3(256), 0, s, A, ars, acs, m, K, B, ldb, R, kps, part, mpad); break;
-    }
+    // A is read along t when its t stride is 1 (KF), along i otherwise
+    const bool kf = acs == 1;
+    const auto al16 = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
+    const bool vec = al16(A) && al16(B) && ldb % 4 == 0 && (kf ? ars % 4 == 0 : (ars == 1 && acs % 4 == 0));
+    if (kf && vec) launch_gemm<T, true, true>(NBk, g, A, ars, acs, m, K, B, ldb, R, kps, part, mpad, s);
+    else if (kf) launch_gemm<T, true, false>(NBk, g, A, ars, acs, m, K, B, ldb, R, kps, part, mpad, s);
+    else if (vec) launch_gemm<T, false, true>(NBk, g, A, ars, acs, m, K, B, ldb, R, kps, part, mpad, s);
+    else launch_gemm<T, false, false>(NBk, g, A, ars, acs, m, K, B, ldb, R, kps, part, mpad, s);
     AFN_HIP(hipGetLastError());
     hipLaunchKernelGGL((gemm_reduce<T>), dim3((unsigned)ceil_div(m * R, 256)), dim3(256), 0, s, part, mpad,
                        16 * NBk, S, m, R, base, sign, C, ldc);
