@@ -162,14 +162,15 @@ afn_status fsai_rows(const double *Xp, int64_t n, int k, int d, double l, int ki
                      const int32_t *order, hipStream_t s);
 // The same rows with the V columns of each row's pattern recomputed instead of
 // gathered from V: batches of rows whose pattern columns of K12 are filled
-// and solved with L (L^{-1} K12 column by column, identical to V's columns),
-// then read contiguously.  For point sets whose neighbourhoods share few
-// columns (high dimension), where gathers from V would come from HBM.
-// Dinv: diagonal-block inverses of L.  work: fsai_batch_doubles(k, w) doubles.
+// and multiplied by L^{-1} (an MFMA GEMM), then read contiguously.  For point
+// sets whose neighbourhoods share few columns (high dimension), where
+// gathers from V would come from HBM.  The columns equal V's to within the
+// rounding of the two products (V comes from a triangular solve).
+// work: fsai_batch_doubles(k, w) doubles.
 int64_t fsai_batch_rows(int k, int w);
+int64_t fsai_batch_doubles(int k, int w);
 afn_status fsai_rows_batched(const double *Xp, int64_t n, int k, int d, double l, int kind, double mu,
-                             const double *L,
-                             const double *Dinv, const int32_t *cols, int w, double *gval, int *info_dev,
+                             const double *Linv, const int32_t *cols, int w, double *gval, int *info,
                              double *work, hipStream_t s);
 
 // ---------------------------------------------------------------- spatial order
@@ -248,6 +249,8 @@ afn_status kmv_mrhs_run(const T *Xs, int64_t npad, int64_t n, int d, double mu, 
                         const int32_t *perm = nullptr, const T *box = nullptr);
 int gemm_splits(int64_t m, int64_t K);
 int64_t gemm_part_elems(int64_t m, int64_t K);
+// Partial-sum elements enough for gemm_rows with any m <= mmax.
+int64_t gemm_part_bound(int64_t mmax);
 template <typename T>
 afn_status gemm_rows(const T *A, int64_t ars, int64_t acs, int64_t m, int64_t K, const T *B,
                      int64_t ldb, int R, const T *base, T sign, T *C, int64_t ldc, T *part,

@@ -390,8 +390,8 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
         const bool recompute = fr && (fr[0] == '0' || fr[0] == '1') ? fr[0] == '1' : d > 10;
         if (recompute) {
             double *fb = nullptr;
-            AFN_TRY(tmp.alloc_n(&fb, (int64_t)(k > 0 ? k : 1) * fsai_batch_rows(k, h->w) * h->w));
-            AFN_TRY(fsai_rows_batched(h->Xp, n, k, d, l, h->kind, mu, h->L, h->Dinv, h->cols, h->w, h->gval,
+            AFN_TRY(tmp.alloc_n(&fb, fsai_batch_doubles(k, h->w)));
+            AFN_TRY(fsai_rows_batched(h->Xp, n, k, d, l, h->kind, mu, h->Linv, h->cols, h->w, h->gval,
                                       h->flags + 2, fb, s));
         } else {
             int32_t *rorder = nullptr;
@@ -1004,7 +1004,7 @@ afn_status afn_footprint_bytes(int64_t n, int32_t d, const afn_params *prm, size
     if (k > 0 && nr > 0) afn += r(8 * k * nr);
     if (f32) afn += r(4 * k * k) + r(4 * k * nr) + 2 * r(4 * nr * w);
     afn += r((int64_t)fsai_transpose_work_bytes(nr, prm->w)) + r(4 * nr);
-    if (d > 10) afn += r(8 * (k > 0 ? k : 1) * fsai_batch_rows((int)k, (int)w) * w);
+    if (d > 10) afn += r(8 * fsai_batch_doubles((int)k, (int)w));
     // Nystrom: L, Dinv, W, Rginv (+ FP32 W, Rginv); G, its block inverses and GEMM partials
     size_t nys = 0;
     if (k > 0) {

@@ -305,26 +305,41 @@ int64_t fsai_batch_rows(int k, int w)
     return b;
 }
 
+int64_t fsai_batch_doubles(int k, int w)
+{
+    const int64_t cols = fsai_batch_rows(k, w) * w;
+    // the last batch is shorter: its GEMMs may use more splits than a full one
+    return 2 * (int64_t)(k > 0 ? k : 1) * cols + gemm_part_bound(cols);
+}
+
 afn_status fsai_rows_batched(const double *Xp, int64_t n, int k, int d, double l, int kind, double mu,
-                             const double *L,
-                             const double *Dinv, const int32_t *cols, int w, double *gval, int *info,
+                             const double *Linv, const int32_t *cols, int w, double *gval, int *info,
                              double *work, hipStream_t s)
 {
     const int64_t nr = n - k;
     if (nr <= 0) return AFN_OK;
     const int64_t B = fsai_batch_rows(k, w);
+    const int64_t kk = k > 0 ? k : 1;
+    double *kb = work;                       // K12 columns of the batch's patterns (k x B w)
+    double *vb = kb + kk * B * w;            // L^{-1} times them
+    double *gp = vb + kk * B * w;            // GEMM partial sums
     for (int64_t r0 = 0; r0 < nr; r0 += B) {
         const int64_t cnt = nr - r0 < B ? nr - r0 : B;
         if (k > 0) {
-            AFN_TRY(fill_k12_patterns(Xp, n, k, d, l, kind, cols, w, r0, cnt, work, s));
-            AFN_TRY(trsm_lower(L, Dinv, k, work, cnt * w, s));
+            AFN_TRY(fill_k12_patterns(Xp, n, k, d, l, kind, cols, w, r0, cnt, kb, s));
+            // vb = L^{-1} kb, as vb^T = kb^T L^{-T} in 64-column blocks of L^{-T}
+            // (row-major with leading dimension k: L^{-T}(t, c) = Linv[c + t k])
+            for (int c0 = 0; c0 < k; c0 += 64) {
+                const int rc = k - c0 < 64 ? k - c0 : 64;
+                AFN_TRY(gemm_rows<double>(kb, k, 1, cnt * w, k, Linv + c0, k, rc, nullptr, 1.0, vb + c0, k, gp, s));
+            }
         }
         const dim3 grid((unsigned)cnt), block(64);
         switch ((w + 15) / 16) {
-            case 1: hipLaunchKernelGGL(fsai_row_mfma<1>, grid, block, 0, s, Xp, k, d, l * l, kind, mu, work, cols, w, gval, info, nullptr, r0, cnt, r0); break;
-            case 2: hipLaunchKernelGGL(fsai_row_mfma<2>, grid, block, 0, s, Xp, k, d, l * l, kind, mu, work, cols, w, gval, info, nullptr, r0, cnt, r0); break;
-            case 3: hipLaunchKernelGGL(fsai_row_mfma<3>, grid, block, 0, s, Xp, k, d, l * l, kind, mu, work, cols, w, gval, info, nullptr, r0, cnt, r0); break;
-            default: hipLaunchKernelGGL(fsai_row_mfma<4>, grid, block, 0, s, Xp, k, d, l * l, kind, mu, work, cols, w, gval, info, nullptr, r0, cnt, r0); break;
+            case 1: hipLaunchKernelGGL(fsai_row_mfma<1>, grid, block, 0, s, Xp, k, d, l * l, kind, mu, vb, cols, w, gval, info, nullptr, r0, cnt, r0); break;
+            case 2: hipLaunchKernelGGL(fsai_row_mfma<2>, grid, block, 0, s, Xp, k, d, l * l, kind, mu, vb, cols, w, gval, info, nullptr, r0, cnt, r0); break;
+            case 3: hipLaunchKernelGGL(fsai_row_mfma<3>, grid, block, 0, s, Xp, k, d, l * l, kind, mu, vb, cols, w, gval, info, nullptr, r0, cnt, r0); break;
+            default: hipLaunchKernelGGL(fsai_row_mfma<4>, grid, block, 0, s, Xp, k, d, l * l, kind, mu, vb, cols, w, gval, info, nullptr, r0, cnt, r0); break;
         }
         AFN_HIP(hipGetLastError());
     }

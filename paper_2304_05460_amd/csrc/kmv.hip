@@ -28,7 +28,8 @@ namespace {
 constexpr int kRows = 256;
 
 constexpr int kTile = 64;
-constexpr int kMaxST = 8;
+constexpr int kMaxST = 16;      // super-block edge (tiles), plain kernel
+constexpr int kMaxSTmf = 8;     // MFMA variant (per-wave column accumulators in LDS)
 // Largest squared half-diagonal (scaled units) of a row tile whose distances
 // the MFMA variant forms from norms and dot products.
 constexpr double kCentredR2Max = 16.0;
@@ -276,11 +277,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     __shared__ T rx[4 * KC][kTile];         // centred row coordinates, zero beyond D
     __shared__ T rn[kTile], rv[kTile];      // row squared norms and vector values
     constexpr bool STAGE_ALL = sizeof(T) == 4;
-    constexpr int NBUF = STAGE_ALL ? kMaxST : 2;
+    constexpr int NBUF = STAGE_ALL ? kMaxSTmf : 2;
     __shared__ T cb[NBUF][4 * KC][kTile];   // -2 x centred column coordinates
     __shared__ T cn[NBUF][kTile], cv[NBUF][kTile];
-    __shared__ T colacc[4][kMaxST][kTile];  // per-wave column partial sums
-    __shared__ unsigned char keep[kMaxST * kMaxST];
+    __shared__ T colacc[4][kMaxSTmf][kTile];  // per-wave column partial sums
+    __shared__ unsigned char keep[kMaxSTmf * kMaxSTmf];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int lc = lane & 15, lg = lane >> 4;
@@ -288,7 +289,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     decode_pair(blockIdx.x, S, BI, BJ);
     const int64_t SB = (int64_t)ST * kTile;
     const bool diag_super = BI == BJ;
-    for (int e = tid; e < 4 * kMaxST * kTile; e += 256) (&colacc[0][0][0])[e] = T(0);
+    for (int e = tid; e < 4 * kMaxSTmf * kTile; e += 256) (&colacc[0][0][0])[e] = T(0);
     if (tid < ST * ST)
         keep[tid] = box_gap2<D, T>(box, (int64_t)BI * ST + tid / ST, (int64_t)BJ * ST + tid % ST) < tcut;
     T *rowout = part + (int64_t)blockIdx.x * 2 * SB;
@@ -618,18 +619,20 @@ int64_t kmv_splits(int64_t n)
 
 namespace {
 
-// Super-block size: enough workgroups to fill the chip, at most kMaxST tiles.
+// Super-block size: enough workgroups to fill the chip, at most kMaxSTmf
+// tiles where the MFMA variant runs (d <= 4), kMaxST otherwise.
 struct SymShape {
     int ST, S;
     int64_t npad, nwg;
 };
 
-SymShape sym_shape(int64_t n)
+SymShape sym_shape(int64_t n, int d)
 {
     SymShape sh;
     int64_t tiles = ceil_div(n, kTile);
     int64_t st = tiles / 45;
-    sh.ST = (int)(st < 1 ? 1 : (st > kMaxST ? kMaxST : st));
+    const int cap = d <= 4 ? kMaxSTmf : kMaxST;
+    sh.ST = (int)(st < 1 ? 1 : (st > cap ? cap : st));
     sh.ST = sh.ST > 1 ? sh.ST & ~1 : 1;       // even: packed length a multiple of 128
     sh.S = (int)ceil_div(tiles, sh.ST);
     if (sh.ST == 1 && (sh.S & 1)) ++sh.S;
@@ -644,7 +647,7 @@ int64_t kmv_workspace_doubles(int64_t n, int d)
 {
     const int64_t split = kmv_splits(n) * n;     // generic-d and FP32 paths
     if (d >= 1 && d <= 8) {
-        SymShape sh = sym_shape(n);
+        SymShape sh = sym_shape(n, d);
         const int64_t sym = sh.npad * d + sh.nwg * 2 * sh.npad / sh.S;
         return sym > split ? sym : split;
     }
@@ -657,7 +660,7 @@ template <int KIND, int D, typename T, typename VT>
 void launch_mf(dim3 grid, const T *Xs, int64_t npad, int64_t n, const VT *v, const int32_t *perm, const T *box,
                T tcut, T r2, int S, int ST, T *part, hipStream_t s)
 {
-    if constexpr (sizeof(T) == 4 || D <= 4)
+    if constexpr (D <= 4)
         hipLaunchKernelGGL((kmv_sym_mf<KIND, D, T, VT>), grid, dim3(256), 0, s, Xs, npad, n, v, perm, box, tcut, r2,
                            S, ST, part);
 }
@@ -667,9 +670,10 @@ void launch_sym(int d, dim3 grid, const T *Xs, int64_t npad, int64_t n, const VT
                 const T *box, T tcut, int S, int ST, T *part, hipStream_t s)
 {
     const dim3 block(256);
-    // the MFMA variant needs tile boxes; FP64 above d = 4 (two coordinate
-    // chunks) does not fit its register budget and keeps the plain kernel
-    if (box && (sizeof(T) == 4 || d <= 4)) {
+    // the MFMA variant needs tile boxes and pays off up to d = 4 (one MFMA per
+    // 16 x 16 block; in higher dimension tiles are rarely compact enough for
+    // the centred form, and FP64 exceeds its register budget)
+    if (box && d <= 4) {
         const T r2 = T(kCentredR2Max);
         switch (d) {
             case 1: launch_mf<KIND, 1, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, r2, S, ST, part, s); break;
@@ -749,14 +753,14 @@ double kernel_cut_t(int kind, double cut)
 
 int64_t kmv_packed_doubles(int64_t n, int d)
 {
-    const SymShape sh = sym_shape(n);
+    const SymShape sh = sym_shape(n, d);
     return sh.npad * d;
 }
 
 afn_status kmv_pack(const double *X, int64_t n, int d, double l, int kind, void *Xs, bool f32, hipStream_t s,
                     const int32_t *perm)
 {
-    const SymShape sh = sym_shape(n);
+    const SymShape sh = sym_shape(n, d);
     const double scale = kernel_scale(kind, l);
     if (f32)
         hipLaunchKernelGGL(pack_scaled<float>, dim3((unsigned)ceil_div(sh.npad * d, 256)), dim3(256), 0, s,
@@ -768,7 +772,7 @@ afn_status kmv_pack(const double *X, int64_t n, int d, double l, int kind, void 
     return AFN_OK;
 }
 
-int64_t kmv_box_count(int64_t n, int d) { return sym_shape(n).npad / kTile * d * 2; }
+int64_t kmv_box_count(int64_t n, int d) { return sym_shape(n, d).npad / kTile * d * 2; }
 
 namespace {
 
@@ -791,7 +795,7 @@ __global__ __launch_bounds__(256) void count_kept_pairs(const double *__restrict
 afn_status kmv_kept_fraction(const double *box, int64_t n, int d, double tcut, unsigned long long *counts,
                              hipStream_t s)
 {
-    const int64_t ntiles = sym_shape(n).npad / kTile;
+    const int64_t ntiles = sym_shape(n, d).npad / kTile;
     AFN_HIP(hipMemsetAsync(counts, 0, 2 * sizeof(unsigned long long), s));
     for (int64_t a0 = 0; a0 < ntiles; a0 += 32768) {
         const int64_t rows = ntiles - a0 < 32768 ? ntiles - a0 : 32768;
@@ -813,7 +817,7 @@ afn_status kmv_kept_fraction(const double *box, int64_t n, int d, double tcut, u
 
 afn_status kmv_boxes(const void *Xs, int64_t n, int d, bool f32, void *box, hipStream_t s)
 {
-    const SymShape sh = sym_shape(n);
+    const SymShape sh = sym_shape(n, d);
     const unsigned g = (unsigned)ceil_div(sh.npad / kTile * d, 256);
     if (f32)
         hipLaunchKernelGGL(tile_boxes<float>, dim3(g), dim3(256), 0, s, (const float *)Xs, sh.npad, n, d,
@@ -829,7 +833,7 @@ afn_status kmv_packed_f64(const double *Xs, int64_t n, int d, double mu, int kin
                           double *y, int64_t ldy, int nrhs, double *part, hipStream_t s,
                           hipEvent_t ev0, hipEvent_t ev1, const int32_t *perm, const double *box)
 {
-    return kmv_sym_run<double, double>(Xs, sym_shape(n), n, d, mu, kind, v, ldv, y, ldy, nrhs, part, s, ev0,
+    return kmv_sym_run<double, double>(Xs, sym_shape(n, d), n, d, mu, kind, v, ldv, y, ldy, nrhs, part, s, ev0,
                                        ev1, perm, box);
 }
 
@@ -837,7 +841,7 @@ afn_status kmv_packed_f32(const float *Xs, int64_t n, int d, double mu, int kind
                           float *y, int64_t ldy, int nrhs, float *part, hipStream_t s,
                           hipEvent_t ev0, hipEvent_t ev1, const int32_t *perm, const float *box)
 {
-    return kmv_sym_run<float, float>(Xs, sym_shape(n), n, d, mu, kind, v, ldv, y, ldy, nrhs, part, s, ev0,
+    return kmv_sym_run<float, float>(Xs, sym_shape(n, d), n, d, mu, kind, v, ldv, y, ldy, nrhs, part, s, ev0,
                                      ev1, perm, box);
 }
 
@@ -845,7 +849,7 @@ afn_status kmv_packed_f32_dvec(const float *Xs, int64_t n, int d, double mu, int
                                int64_t ldv, double *y, int64_t ldy, int nrhs, float *part, hipStream_t s,
                                const int32_t *perm, const float *box)
 {
-    return kmv_sym_run<float, double>(Xs, sym_shape(n), n, d, mu, kind, v, ldv, y, ldy, nrhs, part, s, nullptr,
+    return kmv_sym_run<float, double>(Xs, sym_shape(n, d), n, d, mu, kind, v, ldv, y, ldy, nrhs, part, s, nullptr,
                                       nullptr, perm, box);
 }
 
@@ -854,7 +858,7 @@ afn_status kmv_f64(const double *X, int64_t n, int d, double l, double mu, int k
                    hipEvent_t ev0, hipEvent_t ev1)
 {
     if (d >= 1 && d <= 8) {
-        const SymShape sh = sym_shape(n);
+        const SymShape sh = sym_shape(n, d);
         double *Xs = work;
         double *part = work + sh.npad * d;
         AFN_TRY(kmv_pack(X, n, d, l, kind, Xs, false, s));
@@ -892,7 +896,7 @@ afn_status kmv_f32(const double *X, int64_t n, int d, double l, double mu, int k
                    int64_t ldv, double *y, int64_t ldy, int nrhs, void *work, hipStream_t s)
 {
     if (d >= 1 && d <= 8) {
-        const SymShape sh = sym_shape(n);
+        const SymShape sh = sym_shape(n, d);
         float *Xs = (float *)work;
         float *part = Xs + round_up(sh.npad * d, 64);
         AFN_TRY(kmv_pack(X, n, d, l, kind, Xs, true, s));

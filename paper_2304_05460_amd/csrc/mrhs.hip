@@ -787,6 +787,14 @@ int64_t gemm_part_elems(int64_t m, int64_t K)
     return (int64_t)gemm_splits(m, K) * round_up(m, TL) * 64;
 }
 
+// gemm_part_elems(m, K) is not monotone in m (fewer row blocks get more
+// splits): for every m <= mmax and any K, splits x row blocks <= row blocks
+// of mmax + 1023, since ceil(1024 / rt) rt < 1024 + rt.
+int64_t gemm_part_bound(int64_t mmax)
+{
+    return (ceil_div(mmax, TL) + 1023) * TL * 64;
+}
+
 namespace {
 
 template <typename T, bool KF, bool VEC>
