@@ -28,7 +28,7 @@ ROOT = pathlib.Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
 PEAK_FP64_TFLOPS = 78.6          # MI355X FP64 vector (FMA = 2 flops)
-PEAK_FP32_TFLOPS = 157.3         # MI355X FP32 vector
+PEAK_FP32_TFLOPS = 157.3         # MI355X FP32 (vector, and dense MFMA)
 # FP64 VALU lane-operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 VALU_F64_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # VALU instructions per unique kernel evaluation in the inner loop of
@@ -275,7 +275,19 @@ def c4_bench(args):
                                  algorithmic_tflops_f64=round(F / (mv["f64_ms"] * 1e-3) / 1e12, 2),
                                  tile_pairs_evaluated_f32=round(si.kmv_kept_f32, 4),
                                  tile_pairs_evaluated_f64=round(si.kmv_kept_f64, 4),
-                                 evaluated_tflops_f32=round(F * si.kmv_kept_f32 / (mv["f32_ms"] * 1e-3) / 1e12, 2))})
+                                 evaluated_tflops_f32=round(F * si.kmv_kept_f32 / (mv["f32_ms"] * 1e-3) / 1e12, 2))},
+          roofline=_c4_roofline(F * si.kmv_kept_f32 / (mv["f32_ms"] * 1e-3) / 1e12))
+
+
+def _c4_roofline(evaluated_tflops: float) -> dict:
+    """The 64-column FP32 tile kernel is bound by the matrix cores: 2 R flops
+    per evaluated pair on MFMA against one kernel value on the VALU.
+    achieved = the algorithmic flops of the tile pairs it evaluates over the
+    time of the whole 64-column kernel_matvec call (its ordering, packing and
+    gathers included, so a lower bound for the kernel itself)."""
+    return {"bound": "mfma", "achieved": round(evaluated_tflops, 3), "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(evaluated_tflops / PEAK_FP32_TFLOPS, 4), "traffic": None,
+            "kernel": "kmv_mrhs_pipe<0, 3, 4>"}
 
 
 def serving_bench(args):
