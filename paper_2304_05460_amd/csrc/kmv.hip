@@ -33,6 +33,11 @@ constexpr int kMaxSTmf = 8;     // MFMA variant (per-wave column accumulators in
 // Largest squared half-diagonal (scaled units) of a row tile whose distances
 // the MFMA variant forms from norms and dot products.
 constexpr double kCentredR2Max = 16.0;
+// FP64 tile pairs whose kernel values are all below 2^-kFarF64 evaluate the
+// exponential in FP32: for t >= 46 the relative error ln 2 * 2^-24 t (t
+// rounded to FP32) + 2^-23 (the hardware exponential) times 2^-t stays below
+// 2^-64, the bound of the skipped pairs (the Matern value likewise).
+constexpr double kFarF64 = 46.0;
 
 // Xs[t * npad + q] = X[perm[q]*d + t] * scale for q < n (perm may be null:
 // identity), 0 beyond (rounded to T).
@@ -270,7 +275,7 @@ __device__ __forceinline__ T lanes16_sum4(T (&v)[4], int lane)
 template <int KIND, int D, typename T, typename VT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void kmv_sym_mf(
     const T *__restrict__ Xs, int64_t npad, int64_t n, const VT *__restrict__ v, const int32_t *__restrict__ perm,
-    const T *__restrict__ box, T tcut, T r2max, int S, int ST, T *__restrict__ part)
+    const T *__restrict__ box, T tcut, T tfar, T r2max, int S, int ST, T *__restrict__ part)
 {
     using M = Mfma<T>;
     constexpr int KC = D <= 4 ? 1 : 2;
@@ -291,7 +296,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const bool diag_super = BI == BJ;
     for (int e = tid; e < 4 * kMaxSTmf * kTile; e += 256) (&colacc[0][0][0])[e] = T(0);
     if (tid < ST * ST)
-        keep[tid] = box_gap2<D, T>(box, (int64_t)BI * ST + tid / ST, (int64_t)BJ * ST + tid % ST) < tcut;
+    {
+        // 0: skipped, 1: evaluated, 2: evaluated with the exponential in FP32
+        const T g2 = box_gap2<D, T>(box, (int64_t)BI * ST + tid / ST, (int64_t)BJ * ST + tid % ST);
+        keep[tid] = g2 < tcut ? (g2 >= tfar ? 2 : 1) : 0;
+    }
     T *rowout = part + (int64_t)blockIdx.x * 2 * SB;
     T *colout = rowout + SB;
     auto next_kept = [&](int ti, int tj) {
@@ -417,20 +426,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                         }
                     }
                 }
+                auto values = [&](auto far_tag) {
+                    constexpr bool FAR = decltype(far_tag)::value;
 #pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const T vcol = cv[b][16 * m + lc];
-                    cacc[m] = T(0);
+                    for (int m = 0; m < 4; ++m) {
+                        const T vcol = cv[b][16 * m + lc];
+                        cacc[m] = T(0);
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        // a slightly negative distance (rounding) is harmless in
-                        // 2^-t, but not under the square root of the Matern kernel
-                        T t2 = c[m][i];
-                        if constexpr (KIND == AFN_KERNEL_MATERN32) t2 = t2 > T(0) ? t2 : T(0);
-                        const T kij = kernel_scaled<KIND, T>(t2);
-                        racc[i] = fmaT(kij, vcol, racc[i]);
-                        cacc[m] = fmaT(kij, vr[i], cacc[m]);
+                        for (int i = 0; i < 4; ++i) {
+                            // a slightly negative distance (rounding) is harmless in
+                            // 2^-t, but not under the square root of the Matern kernel
+                            T t2 = c[m][i];
+                            if constexpr (KIND == AFN_KERNEL_MATERN32) t2 = t2 > T(0) ? t2 : T(0);
+                            T kij;
+                            if constexpr (FAR) kij = (T)kernel_scaled<KIND, float>((float)t2);
+                            else kij = kernel_scaled<KIND, T>(t2);
+                            racc[i] = fmaT(kij, vcol, racc[i]);
+                            cacc[m] = fmaT(kij, vr[i], cacc[m]);
+                        }
                     }
+                };
+                // far tile pairs (FP64 only): every value is below 2^-kFarF64,
+                // and the FP32 exponential is within 2^-64 |v_j| of it
+                if constexpr (sizeof(T) == 8) {
+                    if (keep[ti * ST + tj] == 2) values(std::true_type{});
+                    else values(std::false_type{});
+                } else {
+                    values(std::false_type{});
                 }
                 if (!(diag_super && tj == ti)) colacc[wave][tj][lane] += groups4_sum(cacc, lane);
                 if constexpr (!STAGE_ALL) {
@@ -658,16 +680,16 @@ namespace {
 
 template <int KIND, int D, typename T, typename VT>
 void launch_mf(dim3 grid, const T *Xs, int64_t npad, int64_t n, const VT *v, const int32_t *perm, const T *box,
-               T tcut, T r2, int S, int ST, T *part, hipStream_t s)
+               T tcut, T tfar, T r2, int S, int ST, T *part, hipStream_t s)
 {
     if constexpr (D <= 4)
-        hipLaunchKernelGGL((kmv_sym_mf<KIND, D, T, VT>), grid, dim3(256), 0, s, Xs, npad, n, v, perm, box, tcut, r2,
-                           S, ST, part);
+        hipLaunchKernelGGL((kmv_sym_mf<KIND, D, T, VT>), grid, dim3(256), 0, s, Xs, npad, n, v, perm, box, tcut, tfar,
+                           r2, S, ST, part);
 }
 
 template <int KIND, typename T, typename VT>
 void launch_sym(int d, dim3 grid, const T *Xs, int64_t npad, int64_t n, const VT *v, const int32_t *perm,
-                const T *box, T tcut, int S, int ST, T *part, hipStream_t s)
+                const T *box, T tcut, T tfar, int S, int ST, T *part, hipStream_t s)
 {
     const dim3 block(256);
     // the MFMA variant needs tile boxes and pays off up to d = 4 (one MFMA per
@@ -676,14 +698,14 @@ void launch_sym(int d, dim3 grid, const T *Xs, int64_t npad, int64_t n, const VT
     if (box && d <= 4) {
         const T r2 = T(kCentredR2Max);
         switch (d) {
-            case 1: launch_mf<KIND, 1, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, r2, S, ST, part, s); break;
-            case 2: launch_mf<KIND, 2, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, r2, S, ST, part, s); break;
-            case 3: launch_mf<KIND, 3, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, r2, S, ST, part, s); break;
-            case 4: launch_mf<KIND, 4, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, r2, S, ST, part, s); break;
-            case 5: launch_mf<KIND, 5, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, r2, S, ST, part, s); break;
-            case 6: launch_mf<KIND, 6, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, r2, S, ST, part, s); break;
-            case 7: launch_mf<KIND, 7, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, r2, S, ST, part, s); break;
-            default: launch_mf<KIND, 8, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, r2, S, ST, part, s); break;
+            case 1: launch_mf<KIND, 1, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
+            case 2: launch_mf<KIND, 2, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
+            case 3: launch_mf<KIND, 3, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
+            case 4: launch_mf<KIND, 4, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
+            case 5: launch_mf<KIND, 5, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
+            case 6: launch_mf<KIND, 6, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
+            case 7: launch_mf<KIND, 7, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
+            default: launch_mf<KIND, 8, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
         }
         return;
     }
@@ -705,15 +727,16 @@ afn_status kmv_sym_run(const T *Xs, const SymShape &sh, int64_t n, int d, double
                        hipEvent_t ev0, hipEvent_t ev1, const int32_t *perm, const T *box)
 {
     const T tcut = (T)kernel_cut_t(kind, sizeof(T) == 8 ? kCullF64 : kCullF32);
+    const T tfar = sizeof(T) == 8 ? (T)kernel_cut_t(kind, kFarF64) : (T)__builtin_inf();
     for (int c = 0; c < nrhs; ++c) {
         const VT *vc = v + c * ldv;
         if (ev0) AFN_HIP(hipEventRecord(ev0, s));
         const dim3 grid((unsigned)sh.nwg);
         if (kind == AFN_KERNEL_MATERN32)
-            launch_sym<AFN_KERNEL_MATERN32, T, VT>(d, grid, Xs, sh.npad, n, vc, perm, box, tcut, sh.S, sh.ST,
+            launch_sym<AFN_KERNEL_MATERN32, T, VT>(d, grid, Xs, sh.npad, n, vc, perm, box, tcut, tfar, sh.S, sh.ST,
                                                    part, s);
         else
-            launch_sym<AFN_KERNEL_GAUSSIAN, T, VT>(d, grid, Xs, sh.npad, n, vc, perm, box, tcut, sh.S, sh.ST,
+            launch_sym<AFN_KERNEL_GAUSSIAN, T, VT>(d, grid, Xs, sh.npad, n, vc, perm, box, tcut, tfar, sh.S, sh.ST,
                                                    part, s);
         AFN_HIP(hipGetLastError());
         if (ev1) AFN_HIP(hipEventRecord(ev1, s));
