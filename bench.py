@@ -31,12 +31,15 @@ PEAK_FP64_TFLOPS = 78.6          # MI355X FP64 vector (FMA = 2 flops)
 PEAK_FP32_TFLOPS = 157.3         # MI355X FP32 (vector, and dense MFMA)
 # FP64 VALU lane-operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 VALU_F64_LANE_OPS = 256 * 4 * 16 * 2.4e9
-# VALU instructions per unique kernel evaluation in the inner loop of
-# kmv_sym_mf<0, 3, double, double> (AMD assembly of this build: 335 VALU
-# instructions besides 4 MFMAs per tile pair and lane, i.e. per 16 pairs --
-# the squared norms into the accumulator, 17 for the software 2^-t, 2 FMAs
-# for the row and column products, the column-sum exchanges).
-VALU_F64_OPS_PER_PAIR_D3 = 335 / 16
+# VALU instructions per unique kernel evaluation in the tile-pair loop of
+# kmv_sym_mf<0, 3, double, double> (AMD assembly of this build, per lane and
+# tile pair, i.e. per 16 pairs, besides 4 MFMAs): 326 where the software FP64
+# 2^-t runs (the squared norms into the accumulator, 17 instructions per
+# exponential, 2 FMAs for the row and column products), 96 on tile pairs
+# whose values are all below 2^-46 (FP32 exponential), and 43 for the column
+# sums across lane groups and the loop itself.
+VALU_F64_OPS_PER_PAIR_D3 = (326 + 43) / 16
+VALU_F64_OPS_PER_FAR_PAIR_D3 = (96 + 43) / 16
 
 
 def kmv_flops(n: int, d: int, nrhs: int = 1) -> float:
@@ -476,9 +479,11 @@ def main():
     traffic = ctrs.get("hbm_bytes_per_launch")
     E = p.n * (p.n - 1) / 2
     # the pruned kernel evaluates only the tile pairs whose kernel values can
-    # exceed 2^-64; the instruction floor is for the pairs it evaluates
-    kept = sinfo.kmv_kept_f64
-    valu_floor_ms = kept * E * VALU_F64_OPS_PER_PAIR_D3 / VALU_F64_LANE_OPS * 1e3
+    # exceed 2^-64, those below 2^-46 with the FP32 exponential; the
+    # instruction floor is for the pairs it evaluates
+    kept, far = sinfo.kmv_kept_f64, sinfo.kmv_far_f64
+    valu_floor_ms = E * ((kept - far) * VALU_F64_OPS_PER_PAIR_D3
+                         + far * VALU_F64_OPS_PER_FAR_PAIR_D3) / VALU_F64_LANE_OPS * 1e3
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
                 "traffic": traffic, "kernel": "kmv_sym_mf<0, 3, double, double>",
@@ -486,6 +491,7 @@ def main():
                 "flops_per_launch": F,
                 "kernel_evals_per_s": round(E / (kmv_ms * 1e-3), 1),
                 "tile_pairs_evaluated": round(kept, 4),
+                "tile_pairs_fp32_exp": round(far, 4),
                 "valu_instr_floor_ms": round(valu_floor_ms, 4),
                 "valu_instr_frac": round(valu_floor_ms / kmv_ms, 4)}
     if "valu_issue_frac" in ctrs:

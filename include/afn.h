@@ -135,6 +135,9 @@ typedef struct afn_setup_info {
     double nu;               /* Nystrom stabilizing shift (0 for AFN)              */
     double kmv_kept_f64;     /* fraction of tile pairs the pruned kernel matvec   */
     double kmv_kept_f32;     /* evaluates with FP64 / FP32 tiles (1 if not pruned) */
+    double kmv_far_f64;      /* fraction of tile pairs whose FP64 values are all
+                                below 2^-46 and take the FP32 exponential (d <= 4;
+                                0 otherwise)                                       */
 } afn_setup_info;
 
 /* Result of a PCG solve. */

@@ -60,7 +60,8 @@ class afn_setup_info(ctypes.Structure):
                 ("ms_v", ctypes.c_double), ("ms_fsai", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("method", ctypes.c_int32),
                 ("landmarks", ctypes.c_int32), ("nu", ctypes.c_double),
-                ("kmv_kept_f64", ctypes.c_double), ("kmv_kept_f32", ctypes.c_double)]
+                ("kmv_kept_f64", ctypes.c_double), ("kmv_kept_f32", ctypes.c_double),
+                ("kmv_far_f64", ctypes.c_double)]
 
 
 class afn_solve_info(ctypes.Structure):
@@ -187,6 +188,7 @@ class SetupInfo:
     kmv_kept_f64: float = 1.0
     kmv_kept_f32: float = 1.0
     landmarks: int = 1
+    kmv_far_f64: float = 0.0
 
 
 class Handle:
@@ -220,7 +222,7 @@ class Handle:
                                                    "total")}
         return SetupInfo(inf.n, inf.d, inf.k, inf.w, inf.rank_r, inf.rank_k_est,
                          inf.rank_eig_branch, inf.rank_eig_count, inf.nnz_g, ms, inf.method, inf.nu,
-                         inf.kmv_kept_f64, inf.kmv_kept_f32, inf.landmarks)
+                         inf.kmv_kept_f64, inf.kmv_kept_f32, inf.landmarks, inf.kmv_far_f64)
 
     def landmarks(self):
         import numpy as np

@@ -79,6 +79,12 @@ afn_status kmv_pack(const double *X, int64_t n, int d, double l, int kind, void 
 // i is below 2^-cut sum_j |v_j|.
 constexpr double kCullF64 = 64.0;
 constexpr double kCullF32 = 44.0;
+// FP64 tile pairs whose kernel values are all below 2^-kFarF64 evaluate the
+// exponential in FP32 (the MFMA tile kernel, d <= 4): for t >= 46 the relative
+// error ln 2 * 2^-24 t (t rounded to FP32) + 2^-23 (the hardware exponential)
+// times 2^-t stays below 2^-64, the bound of the skipped pairs (the Matern
+// value likewise).
+constexpr double kFarF64 = 46.0;
 int64_t kmv_box_count(int64_t n, int d);
 // counts[0] = unordered pairs of non-empty tiles kept at cut tcut, counts[1] =
 // all such pairs (FP64 boxes, d <= 8).

@@ -423,16 +423,19 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
         AFN_TRY(kmv_pack(h->Xp, n, d, l, h->kind, h->Xs64, false, s, h->kperm));
         AFN_TRY(h->arena.alloc_n(&h->box64, kmv_box_count(n, d)));
         AFN_TRY(kmv_boxes(h->Xs64, n, d, false, h->box64, s));
-        unsigned long long *cnt = nullptr, hc[4] = {0, 0, 0, 0};
-        AFN_TRY(tmp.alloc_n(&cnt, 4));
+        unsigned long long *cnt = nullptr, hc[6] = {0, 0, 0, 0, 0, 0};
+        AFN_TRY(tmp.alloc_n(&cnt, 6));
         AFN_TRY(kmv_kept_fraction(h->box64, n, d, kernel_cut_t(h->kind, kCullF64), cnt, s));
         AFN_TRY(kmv_kept_fraction(h->box64, n, d, kernel_cut_t(h->kind, kCullF32), cnt + 2, s));
+        AFN_TRY(kmv_kept_fraction(h->box64, n, d, kernel_cut_t(h->kind, kFarF64), cnt + 4, s));
         AFN_HIP(hipMemcpyAsync(hc, cnt, sizeof hc, hipMemcpyDeviceToHost, s));
         AFN_HIP(hipStreamSynchronize(s));
         h->info.kmv_kept_f64 = hc[1] ? (double)hc[0] / (double)hc[1] : 1.0;
         h->info.kmv_kept_f32 = hc[3] ? (double)hc[2] / (double)hc[3] : 1.0;
+        h->info.kmv_far_f64 = (d <= 4 && hc[1]) ? (double)(hc[0] - hc[4]) / (double)hc[1] : 0.0;
     } else {
         h->info.kmv_kept_f64 = h->info.kmv_kept_f32 = 1.0;
+        h->info.kmv_far_f64 = 0.0;
     }
     if (h->precision == AFN_FP32) {
         AFN_TRY(h->arena.alloc_n(&h->Xs32, kmv_packed_doubles(n, d)));

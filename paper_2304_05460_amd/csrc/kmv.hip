@@ -33,11 +33,6 @@ constexpr int kMaxSTmf = 8;     // MFMA variant (per-wave column accumulators in
 // Largest squared half-diagonal (scaled units) of a row tile whose distances
 // the MFMA variant forms from norms and dot products.
 constexpr double kCentredR2Max = 16.0;
-// FP64 tile pairs whose kernel values are all below 2^-kFarF64 evaluate the
-// exponential in FP32: for t >= 46 the relative error ln 2 * 2^-24 t (t
-// rounded to FP32) + 2^-23 (the hardware exponential) times 2^-t stays below
-// 2^-64, the bound of the skipped pairs (the Matern value likewise).
-constexpr double kFarF64 = 46.0;
 
 // Xs[t * npad + q] = X[perm[q]*d + t] * scale for q < n (perm may be null:
 // identity), 0 beyond (rounded to T).
@@ -217,19 +212,61 @@ __device__ __forceinline__ void keep_or_send(bool hi, T &a, T &b, T &keep, T &se
     send = hi ? a : b;
 }
 
-// Four values over the four lane groups (lanes l, l + 16, l + 32, l + 48):
-// on return lane l holds the total of value l >> 4.
-template <typename T>
-__device__ __forceinline__ T groups4_sum(T (&v)[4], int lane)
+// Lanes 32..63 of x trade places with lanes 0..31 of y (v_permlane32_swap),
+// and, within each half, lanes 16..31 of x with lanes 0..15 of y
+// (v_permlane16_swap): a transposition across lane groups with no LDS
+// traffic and no lane-index arithmetic.
+__device__ __forceinline__ void swap_lanes32(float &x, float &y)
 {
-    T h[2], keep, send;
+    auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, x), __builtin_bit_cast(unsigned, y),
+                                              false, false);
+    x = __builtin_bit_cast(float, (unsigned)r[0]);
+    y = __builtin_bit_cast(float, (unsigned)r[1]);
+}
+__device__ __forceinline__ void swap_lanes16(float &x, float &y)
+{
+    auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, x), __builtin_bit_cast(unsigned, y),
+                                              false, false);
+    x = __builtin_bit_cast(float, (unsigned)r[0]);
+    y = __builtin_bit_cast(float, (unsigned)r[1]);
+}
+__device__ __forceinline__ void swap_lanes32(double &x, double &y)
+{
+    const unsigned long long a = __builtin_bit_cast(unsigned long long, x);
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, y);
+    auto lo = __builtin_amdgcn_permlane32_swap((unsigned)a, (unsigned)b, false, false);
+    auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(a >> 32), (unsigned)(b >> 32), false, false);
+    x = __builtin_bit_cast(double, (unsigned long long)(unsigned)lo[0] | ((unsigned long long)(unsigned)hi[0] << 32));
+    y = __builtin_bit_cast(double, (unsigned long long)(unsigned)lo[1] | ((unsigned long long)(unsigned)hi[1] << 32));
+}
+__device__ __forceinline__ void swap_lanes16(double &x, double &y)
+{
+    const unsigned long long a = __builtin_bit_cast(unsigned long long, x);
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, y);
+    auto lo = __builtin_amdgcn_permlane16_swap((unsigned)a, (unsigned)b, false, false);
+    auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(a >> 32), (unsigned)(b >> 32), false, false);
+    x = __builtin_bit_cast(double, (unsigned long long)(unsigned)lo[0] | ((unsigned long long)(unsigned)hi[0] << 32));
+    y = __builtin_bit_cast(double, (unsigned long long)(unsigned)lo[1] | ((unsigned long long)(unsigned)hi[1] << 32));
+}
+
+// Four values over the four lane groups (lanes l, l + 16, l + 32, l + 48):
+// on return lane l holds the total of value l >> 4.  After swap_lanes32 of
+// (v[j], v[2 + j]) a lane of the lower half holds its own v[j] and its
+// partner's, a lane of the upper half both v[2 + j]; swap_lanes16 does the
+// same between the two groups of each half.
+template <typename T>
+__device__ __forceinline__ T groups4_sum(T (&v)[4], int)
+{
+    T h[2];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-        keep_or_send((lane & 32) != 0, v[j], v[2 + j], keep, send);
-        h[j] = keep + __shfl_xor(send, 32);
+        T x = v[j], y = v[2 + j];
+        swap_lanes32(x, y);
+        h[j] = x + y;
     }
-    keep_or_send((lane & 16) != 0, h[0], h[1], keep, send);
-    return keep + __shfl_xor(send, 16);
+    T x = h[0], y = h[1];
+    swap_lanes16(x, y);
+    return x + y;
 }
 
 // Four values over the 16 lanes of a lane group: on return lane l holds the
@@ -271,7 +308,10 @@ __device__ __forceinline__ T lanes16_sum4(T (&v)[4], int lane)
 // from every thread in flight together), so the tile loop has no barrier.
 // FP64 (whose registers allow 4 waves per SIMD only with a small LDS
 // footprint): two buffers, the next kept tile read into registers while the
-// current one is evaluated, one barrier per tile pair.
+// current one is evaluated, one barrier per tile pair.  Each 16-column
+// block's distances become kernel values before the next block's MFMA, and
+// the box centre that column staging needs sits in LDS: that keeps the FP64
+// kernel within 128 registers without spills in its loops.
 template <int KIND, int D, typename T, typename VT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void kmv_sym_mf(
     const T *__restrict__ Xs, int64_t npad, int64_t n, const VT *__restrict__ v, const int32_t *__restrict__ perm,
@@ -287,6 +327,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     __shared__ T cn[NBUF][kTile], cv[NBUF][kTile];
     __shared__ T colacc[4][kMaxSTmf][kTile];  // per-wave column partial sums
     __shared__ unsigned char keep[kMaxSTmf * kMaxSTmf];
+    __shared__ T cenS[D];                   // the row tile's box centre, for store_col
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int lc = lane & 15, lg = lane >> 4;
@@ -320,7 +361,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         T nrm = T(0);
 #pragma unroll
         for (int t = 0; t < 4 * KC; ++t) {
-            const T xc = t < D ? xn[t] - cen[t] : T(0);
+            const T xc = t < D ? xn[t] - cenS[t] : T(0);
             cb[buf][t][tid] = T(-2) * xc;
             nrm = fmaT(xc, xc, nrm);
         }
@@ -344,6 +385,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             continue;
         }
         const bool use_mf = h2 <= r2max;
+        // every read of cenS (store_col) is followed by a barrier
+        if (tid < D) cenS[tid] = cen[tid];
         __syncthreads();      // the previous row tile's readers are done
         const int tfirst = diag_super ? ti : 0;
         int tj = next_kept(ti, tfirst);
@@ -402,41 +445,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 }
                 const int b = STAGE_ALL ? tj : nb;
                 T cacc[4];
-                typename M::acc_t c[4];
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const int col = 16 * m + lc;
-                    if constexpr (MF) {
-                        const T ncol = cn[b][col];
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) c[m][i] = nr[i] + ncol;
-#pragma unroll
-                        for (int kc = 0; kc < KC; ++kc) c[m] = M::op(a[kc], cb[b][4 * kc + lg][col], c[m]);
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const int r = 16 * wave + M::row(lane, i);
-                            T d2 = T(0);
-#pragma unroll
-                            for (int t = 0; t < D; ++t) {
-                                const T del = fmaT(T(0.5), cb[b][t][col], rx[t][r]);
-                                d2 = fmaT(del, del, d2);
-                            }
-                            c[m][i] = d2;
-                        }
-                    }
-                }
+                // per 16-column block: the distances, then the kernel values
                 auto values = [&](auto far_tag) {
                     constexpr bool FAR = decltype(far_tag)::value;
 #pragma unroll
                     for (int m = 0; m < 4; ++m) {
-                        const T vcol = cv[b][16 * m + lc];
+                        const int col = 16 * m + lc;
+                        typename M::acc_t c;
+                        if constexpr (MF) {
+                            const T ncol = cn[b][col];
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) c[i] = nr[i] + ncol;
+#pragma unroll
+                            for (int kc = 0; kc < KC; ++kc) c = M::op(a[kc], cb[b][4 * kc + lg][col], c);
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) {
+                                const int r = 16 * wave + M::row(lane, i);
+                                T d2 = T(0);
+#pragma unroll
+                                for (int t = 0; t < D; ++t) {
+                                    const T del = fmaT(T(0.5), cb[b][t][col], rx[t][r]);
+                                    d2 = fmaT(del, del, d2);
+                                }
+                                c[i] = d2;
+                            }
+                        }
+                        const T vcol = cv[b][col];
                         cacc[m] = T(0);
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
                             // a slightly negative distance (rounding) is harmless in
                             // 2^-t, but not under the square root of the Matern kernel
-                            T t2 = c[m][i];
+                            T t2 = c[i];
                             if constexpr (KIND == AFN_KERNEL_MATERN32) t2 = t2 > T(0) ? t2 : T(0);
                             T kij;
                             if constexpr (FAR) kij = (T)kernel_scaled<KIND, float>((float)t2);

@@ -62,6 +62,9 @@ __global__ __launch_bounds__(256) void sum_stage2(const double *__restrict__ par
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
+// Loads in flight per thread in the GEMV loops (the sums stay in index order).
+constexpr int kGemvUnroll = 8;
+
 // y[i] (+)= sum over column chunk of A[i + j*lda] x[j]; partial per split.
 template <typename T>
 __global__ __launch_bounds__(256) void gemv_n_partial(const T *__restrict__ A, int64_t lda, int64_t m,
@@ -73,7 +76,15 @@ __global__ __launch_bounds__(256) void gemv_n_partial(const T *__restrict__ A, i
     const int64_t j1 = j0 + chunk < ncols ? j0 + chunk : ncols;
     if (i >= m) return;
     T s = T(0);
-    for (int64_t j = j0; j < j1; ++j) s = fmaT(A[i + j * lda], x[j], s);
+    int64_t j = j0;
+    for (; j + kGemvUnroll <= j1; j += kGemvUnroll) {
+        T a[kGemvUnroll];
+#pragma unroll
+        for (int u = 0; u < kGemvUnroll; ++u) a[u] = A[i + (j + u) * lda];
+#pragma unroll
+        for (int u = 0; u < kGemvUnroll; ++u) s = fmaT(a[u], x[j + u], s);
+    }
+    for (; j < j1; ++j) s = fmaT(A[i + j * lda], x[j], s);
     part[(int64_t)blockIdx.y * m + i] = s;
 }
 
@@ -120,41 +131,94 @@ __global__ __launch_bounds__(256) void gemv_t_kernel(const T *__restrict__ A, in
     if (j >= ncols) return;
     const T *col = A + j * lda;
     T s = T(0);
-    for (int64_t i = lane; i < m; i += 64) s = fmaT(col[i], x[i], s);
+    int64_t i = lane;
+    for (; i + 64 * (kGemvUnroll - 1) < m; i += 64 * kGemvUnroll) {
+        T a[kGemvUnroll], b[kGemvUnroll];
+#pragma unroll
+        for (int u = 0; u < kGemvUnroll; ++u) {
+            a[u] = col[i + 64 * u];
+            b[u] = x[i + 64 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < kGemvUnroll; ++u) s = fmaT(a[u], b[u], s);
+    }
+    for (; i < m; i += 64) s = fmaT(col[i], x[i], s);
     s = wave_sumT(s);
     if (lane == 0) y[j] = (base ? base[j] : T(0)) + sign * s;
 }
 
-// u[p] = sum_a gval[p*w + a] t[cols[p*w + a]], a < min(p+1, w); wave per row.
+// Sum over the 16 lanes of each lane group (lanes 16 g .. 16 g + 15), a
+// fixed butterfly: every lane of the group ends with the total.
+template <typename T>
+__device__ __forceinline__ T group16_sum(T s)
+{
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    return s;
+}
+
+// u[p] = sum_a gval[p*w + a] t[cols[p*w + a]], a < min(p+1, w) (w <= 64):
+// 16 lanes per row, lane q taking a = q, q + 16, q + 32, q + 48 (each load
+// instruction reads 16 consecutive entries of a row; 4 rows per wave).
 template <typename T>
 __global__ __launch_bounds__(256) void spmv_padded(const int32_t *__restrict__ cols,
                                                    const T *__restrict__ gval, int64_t nr, int w,
                                                    const T *__restrict__ t, T *__restrict__ u)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int q = threadIdx.x & 15;
+    const int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
     if (p >= nr) return;
     const int m = (int)(p + 1 < w ? p + 1 : w);
+    const int64_t base = p * w;
+    // entries past the row's end load entry m - 1 (in bounds) and count zero,
+    // so that every load is issued before the first wait
+    T g[4], tv[4];
+    int32_t cj[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int a = q + 16 * r < m ? q + 16 * r : m - 1;
+        g[r] = gval[base + a];
+        cj[r] = cols[base + a];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) tv[r] = t[cj[r]];
     T s = T(0);
-    if (lane < m) s = gval[p * w + lane] * t[cols[p * w + lane]];
-    s = wave_sumT(s);
-    if (lane == 0) u[p] = s;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) s = fmaT(q + 16 * r < m ? g[r] : T(0), tv[r], s);
+    s = group16_sum(s);
+    if (q == 0) u[p] = s;
 }
 
-// s[c] = sum_e tval[e] u[trow[e]] over e in [ptr[c], ptr[c+1]); wave per row.
+// s[c] = sum_e tval[e] u[trow[e]] over e in [ptr[c], ptr[c+1]): 16 lanes per
+// row, up to 4 entries per lane in flight per pass (4 rows per wave).
 template <typename T>
 __global__ __launch_bounds__(256) void spmv_csr(const int64_t *__restrict__ ptr,
                                                 const int32_t *__restrict__ idx,
                                                 const T *__restrict__ val, int64_t nrows,
                                                 const T *__restrict__ u, T *__restrict__ out)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int q = threadIdx.x & 15;
+    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
     if (c >= nrows) return;
+    const int64_t e1 = ptr[c + 1];
     T s = T(0);
-    for (int64_t e = ptr[c] + lane; e < ptr[c + 1]; e += 64) s = fmaT(val[e], u[idx[e]], s);
-    s = wave_sumT(s);
-    if (lane == 0) out[c] = s;
+    for (int64_t e = ptr[c] + q; e < e1; e += 64) {
+        // entries past the row's end load entry e1 - 1 and count zero
+        T a[4], b[4];
+        int32_t ri[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t f = e + 16 * r < e1 ? e + 16 * r : e1 - 1;
+            a[r] = val[f];
+            ri[r] = idx[f];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) b[r] = u[ri[r]];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) s = fmaT(e + 16 * r < e1 ? a[r] : T(0), b[r], s);
+    }
+    s = group16_sum(s);
+    if (q == 0) out[c] = s;
 }
 
 __global__ __launch_bounds__(256) void gather_kernel(const double *__restrict__ src, int64_t lds,
@@ -360,7 +424,7 @@ afn_status spmv_gT(const int32_t *cols, const T *gval, int64_t nr, int w, const 
                    hipStream_t s)
 {
     if (nr <= 0) return AFN_OK;
-    hipLaunchKernelGGL((spmv_padded<T>), dim3((unsigned)ceil_div(nr, 4)), dim3(256), 0, s, cols, gval, nr,
+    hipLaunchKernelGGL((spmv_padded<T>), dim3((unsigned)ceil_div(nr, 16)), dim3(256), 0, s, cols, gval, nr,
                        w, t, u);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
@@ -371,7 +435,7 @@ afn_status spmv_gtT(const int64_t *ptr, const int32_t *idx, const T *val, int64_
                     T *out, hipStream_t s)
 {
     if (nr <= 0) return AFN_OK;
-    hipLaunchKernelGGL((spmv_csr<T>), dim3((unsigned)ceil_div(nr, 4)), dim3(256), 0, s, ptr, idx, val, nr,
+    hipLaunchKernelGGL((spmv_csr<T>), dim3((unsigned)ceil_div(nr, 16)), dim3(256), 0, s, ptr, idx, val, nr,
                        u, out);
     AFN_HIP(hipGetLastError());
     return AFN_OK;

@@ -613,12 +613,19 @@ def test_pruned_pair_fraction(afn):
     h = afn.afn_setup(X, 0.01, 1e-3, k=50, w=8)
     inf = h.info()
     h.close()
-    say("kept fractions l=0.01", inf.kmv_kept_f64, inf.kmv_kept_f32)
+    say("kept fractions l=0.01", inf.kmv_kept_f64, inf.kmv_kept_f32, "far", inf.kmv_far_f64)
     assert 0.0 < inf.kmv_kept_f32 <= inf.kmv_kept_f64 < 0.2
+    # pairs between the 2^-46 and 2^-64 cuts: FP32 exponential in the FP64 kernel
+    assert 0.0 < inf.kmv_far_f64 < inf.kmv_kept_f64
     h = afn.afn_setup(X, 10.0, 1e-3, k=50, w=8)
     inf = h.info()
     h.close()
-    assert inf.kmv_kept_f64 == 1.0 and inf.kmv_kept_f32 == 1.0
+    assert inf.kmv_kept_f64 == 1.0 and inf.kmv_kept_f32 == 1.0 and inf.kmv_far_f64 == 0.0
+    # d > 4: the plain tile kernel, no FP32 exponential
+    h = afn.afn_setup(dev(W.points("uniform", 20000, 6, 92)), 0.05, 1e-3, k=50, w=8)
+    inf = h.info()
+    h.close()
+    assert inf.kmv_far_f64 == 0.0
 
 
 @pytest.mark.parametrize("n,d,k,lm", [(3000, 22, 300, 0), (1500, 18, 150, 0), (800, 3, 64, 2)])

@@ -1,0 +1,102 @@
+"""A seeded sweep of kernel-matvec configurations through the C-ABI against
+the oracle on sampled rows: sizes on both sides of the size from which the
+matvec prunes tile pairs (n = 8192), d from 1 to 12, length scales from tiles
+much wider than l to tiles much narrower, both precisions and both kernels,
+one and several columns.
+
+Bound per row i (u the unit roundoff of the precision, ab_i = sum_j |K_ij v_j|
++ mu |v_i|), each term's relative error being at most r u:
+  FP64   (2 (n + 4) + r) u ab_i + 2^-64 sum_j |v_j|
+  FP32   (n + 8 + r) u ab_i + (1e-13 + 2^-44) sum_j |v_j|
+The last terms cover the skipped tile pairs (every value there is below 2^-64,
+resp. 2^-44) and the FP64 pairs whose value is taken in FP32 (below 2^-46).
+r has three parts (c the coordinate scale of the kind, xm = max |x|):
+  - the stored coordinates x c (1 + e), |e| <= u: each coordinate difference
+    is off by at most 2 xm c u, so t by 2 sqrt(t d) 2 xm c u; the Gaussian
+    2^(-t) moves by ln 2 dt relative (t <= 64), the Matern value by at most
+    ln 2 ds with ds <= 2 sqrt(d) xm c u;
+  - t itself, direct or from norms and dot products of centred coordinates
+    (centred radius^2 <= 16): 64 (d + 4) u absolute for the Gaussian, s (d + 4) / 2
+    relative in s for the Matern kernel (s <= 66 in FP64, 50 in FP32);
+  - the exponential and the Matern factor: 8."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2304_05460_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+U32 = 2.0 ** -24
+LN2 = math.log(2.0)
+LOG2E = 1.0 / LN2
+
+
+@pytest.fixture(scope="module")
+def afn():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2304_05460_amd import afn as mod
+    mod.lib()
+    return mod
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def term_rel(kernel, fp64, d, xm, l):
+    if kernel == 0:
+        c = math.sqrt(LOG2E) / l
+        return LN2 * (64 * (d + 4) + 4 * math.sqrt(64 * d) * xm * c) + 8
+    c = math.sqrt(3.0) * LOG2E / l
+    smax = 66 if fp64 else 50
+    return LN2 * (smax * (d + 4) / 2 + 2 * math.sqrt(d) * xm * c) + 8
+
+
+def cases():
+    rng = np.random.default_rng(2024)
+    out = []
+    for i in range(24):
+        n = int(rng.choice([3000, 9000, 24000]))
+        d = int(rng.choice([1, 2, 3, 3, 4, 6, 8, 12]))
+        kinds = ["uniform", "normal", "mixture5"] if d == 3 else ["uniform", "normal"]
+        pts = str(rng.choice(kinds))
+        scale = 3.0 if pts == "normal" else 1.0
+        l = float(scale * 10 ** rng.uniform(-2.3, 0.3))
+        kernel = int(rng.integers(0, 2))
+        nrhs = int(rng.choice([1, 1, 3, 16]))
+        out.append((i, n, d, pts, l, kernel, nrhs))
+    return out
+
+
+@pytest.mark.parametrize("i,n,d,pts,l,kernel,nrhs", cases())
+def test_matvec_sweep(afn, i, n, d, pts, l, kernel, nrhs):
+    print(f"sweep {i}: n={n} d={d} {pts} l={l:.3g} kernel={kernel} nrhs={nrhs}", flush=True)
+    X = W.points(pts, n, d, 3000 + i)
+    V = np.random.default_rng(4000 + i).standard_normal((n, nrhs))
+    rows = np.concatenate([np.arange(3), np.random.default_rng(5000 + i).integers(0, n, 25), [n - 1]])
+    Vd = torch.tensor(V.T.copy(), device="cuda").t()
+    with oracle.use_kernel("matern32" if kernel else "gaussian"):
+        ref = [oracle.kernel_matvec_rows(X, l, 1e-3, V[:, c], rows) for c in range(nrhs)]
+    xm = float(np.abs(X).max())
+    for prec in (afn.AFN_FP64, afn.AFN_FP32):
+        Y = afn.kernel_matvec(dev(X), l, 1e-3, Vd, precision=prec, kernel=kernel).cpu().numpy()
+        fp64 = prec == afn.AFN_FP64
+        r = term_rel(kernel, fp64, d, xm, l)
+        worst = 0.0
+        for c in range(nrhs):
+            yo, ab = ref[c]
+            vs = np.abs(V[:, c]).sum()
+            if fp64:
+                bound = (2 * (n + 4) + r) * U * ab + 2.0 ** -64 * vs
+            else:
+                bound = (n + 8 + r) * U32 * ab + (1e-13 + 2.0 ** -44) * vs
+            err = np.abs(Y[rows, c] - yo)
+            worst = max(worst, float(np.max(err / bound)))
+            assert np.all(err <= bound), (prec, c, float(np.max(err / bound)))
+        print(f"  prec={prec}: worst err/bound {worst:.3f}", flush=True)
