@@ -533,11 +533,27 @@ __global__ __launch_bounds__(256) void kmv_sym_reduce(const T *__restrict__ part
     const int64_t ii = i - (int64_t)s * SB;
     double acc = 0.0;
     const int64_t qs = (int64_t)s * S - (int64_t)s * (s - 1) / 2;   // q(s, s)
-    for (int bj = s; bj < S; ++bj) acc += (double)part[(qs + bj - s) * 2 * SB + ii];
-    for (int bi = 0; bi <= s; ++bi) {
-        const int64_t q = (int64_t)bi * S - (int64_t)bi * (bi - 1) / 2 + (s - bi);
-        acc += (double)part[q * 2 * SB + SB + ii];
+    // 8 loads in flight per thread; the additions stay in index order
+    constexpr int U = 8;
+    int bj = s;
+    for (; bj + U <= S; bj += U) {
+        T a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[u] = part[(qs + bj + u - s) * 2 * SB + ii];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += (double)a[u];
     }
+    for (; bj < S; ++bj) acc += (double)part[(qs + bj - s) * 2 * SB + ii];
+    auto colq = [&](int bi) { return (int64_t)bi * S - (int64_t)bi * (bi - 1) / 2 + (s - bi); };
+    int bi = 0;
+    for (; bi + U <= s + 1; bi += U) {
+        T a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[u] = part[colq(bi + u) * 2 * SB + SB + ii];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += (double)a[u];
+    }
+    for (; bi <= s; ++bi) acc += (double)part[colq(bi) * 2 * SB + SB + ii];
     y[o] = (VT)(acc + mu * (double)v[o]);
 }
 
