@@ -130,6 +130,12 @@ afn_status landmark_permutation(const int32_t *idx, int k, int64_t n, int32_t *p
 // cols[p*w .. p*w+len) (ascending, p last), len = min(p+1, w), the rest -1.
 afn_status knn_pattern(const double *Xr, int64_t nr, int d, int w, int32_t *cols,
                        hipStream_t s);
+// The same pattern with the help of a spatial order of Xr (order[q] = index
+// at position q, d <= 8; otherwise as knn_pattern): 64-point tiles of the
+// order with boxes prune candidate tiles.  work: knn_work_bytes(nr, d).
+size_t knn_work_bytes(int64_t nr, int d);
+afn_status knn_pattern_ordered(const double *Xr, int64_t nr, int d, int w, const int32_t *order, void *work,
+                               int32_t *cols, hipStream_t s);
 
 // ---------------------------------------------------------------- dense factors
 // A = K11 + mu I for the first k points of Xp, column-major lda.
@@ -226,8 +232,15 @@ afn_status gather_points(const double *X, const int32_t *perm, int64_t n, int d,
                          hipStream_t s);
 // PCG scalar slots: sc[0] rho, sc[1] p'q, sc[2] r'r, sc[3] rho_new, sc[4] alpha,
 // sc[5] beta, sc[6] b'b, sc[7] true residual squared.
-afn_status pcg_alpha_launch(double *sc, hipStream_t s);
-afn_status pcg_beta_launch(double *sc, hipStream_t s);
+// The same dot product as dot(), fused with the PCG scalar step that follows
+// it: kPcgAlpha puts a.b in sc[1] and alpha = sc[0] / sc[1] in sc[4];
+// kPcgBeta puts a.b in sc[3], then beta = sc[3] / sc[0] in sc[5] and sc[3]
+// in sc[0].
+enum PcgDotStep { kPcgAlpha = 1, kPcgBeta = 2 };
+afn_status dot_pcg(const double *a, const double *b, int64_t n, double *sc, PcgDotStep step,
+                   double *partials, hipStream_t s);
+afn_status dot_pcg(const float *a, const float *b, int64_t n, double *sc, PcgDotStep step,
+                   double *partials, hipStream_t s);
 afn_status pcg_xr_launch(double *x, double *r, const double *p, const double *q, const double *sc,
                          int64_t n, double *part, double *rr_out, hipStream_t s);
 afn_status pcg_xr_launch(float *x, float *r, const float *p, const float *q, const double *sc,
@@ -350,5 +363,6 @@ struct afn_handle {
     size_t mrhs_bytes = 0;
     double *host_sc = nullptr;  // pinned host copy of PCG scalars
     hipEvent_t kmv_ev[2] = {nullptr, nullptr};  // timing of the matvec tile kernel
+    hipEvent_t chk_ev = nullptr;                // the PCG residual check's host copy
     afn_setup_info info{};
 };

@@ -370,9 +370,20 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
         AFN_TRY(trsm_lower(h->L, h->Dinv, k, h->Linv, k, s));
     }
     tm.mark(3, s);
+    // spatial order of the non-landmark points: tiles for the pattern search
+    // and the row order of the FSAI gathers (d <= 10)
+    int32_t *rorder = nullptr;
+    if (nr > 0 && d <= 10) {
+        void *ows = nullptr;
+        AFN_TRY(tmp.alloc_n(&rorder, nr));
+        AFN_TRY(tmp.alloc(&ows, spatial_order_work_bytes(nr, d)));
+        AFN_TRY(spatial_order(h->Xp + (int64_t)k * d, nr, d, rorder, ows, s));
+    }
     if (nr > 0) {
+        void *kws = nullptr;
         AFN_TRY(h->arena.alloc_n(&h->cols, nr * h->w));
-        AFN_TRY(knn_pattern(h->Xp + (int64_t)k * d, nr, d, h->w, h->cols, s));
+        AFN_TRY(tmp.alloc(&kws, knn_work_bytes(nr, d)));
+        AFN_TRY(knn_pattern_ordered(h->Xp + (int64_t)k * d, nr, d, h->w, rorder, kws, h->cols, s));
     }
     tm.mark(4, s);
     if (k > 0 && nr > 0) {
@@ -394,11 +405,12 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
             AFN_TRY(fsai_rows_batched(h->Xp, n, k, d, l, h->kind, mu, h->Linv, h->cols, h->w, h->gval,
                                       h->flags + 2, fb, s));
         } else {
-            int32_t *rorder = nullptr;
-            void *ows = nullptr;
-            AFN_TRY(tmp.alloc_n(&rorder, nr));
-            AFN_TRY(tmp.alloc(&ows, spatial_order_work_bytes(nr, d)));
-            AFN_TRY(spatial_order(h->Xp + (int64_t)k * d, nr, d, rorder, ows, s));
+            if (!rorder) {
+                void *ows = nullptr;
+                AFN_TRY(tmp.alloc_n(&rorder, nr));
+                AFN_TRY(tmp.alloc(&ows, spatial_order_work_bytes(nr, d)));
+                AFN_TRY(spatial_order(h->Xp + (int64_t)k * d, nr, d, rorder, ows, s));
+            }
             AFN_TRY(fsai_rows(h->Xp, n, k, d, l, h->kind, mu, h->V, h->cols, h->w, h->gval, h->flags + 2, rorder, s));
         }
         AFN_TRY(h->arena.alloc_n(&h->tptr, nr + 1));
@@ -472,6 +484,7 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     AFN_HIP(hipHostMalloc((void **)&h->host_sc, 16 * sizeof(double), hipHostMallocDefault));
     AFN_HIP(hipEventCreate(&h->kmv_ev[0]));
     AFN_HIP(hipEventCreate(&h->kmv_ev[1]));
+    AFN_HIP(hipEventCreateWithFlags(&h->chk_ev, hipEventDisableTiming));
     AFN_TRY(check_flags(h, s));
     h->nnz = 0;
     if (nr > 0 && h->tptr) AFN_HIP(hipMemcpy(&h->nnz, h->tptr + nr, sizeof(int64_t), hipMemcpyDeviceToHost));
@@ -509,11 +522,18 @@ afn_status pcg64_iterate(afn_handle *h, double bnorm, double tol, int maxit, con
     *iters = 0;
     for (int it = 0; it < maxit; ++it) {
         AFN_TRY(op_f64(h, w.p, w.q, w, s, h->kmv_ev[0], h->kmv_ev[1]));
-        AFN_TRY(dot(w.p, n, w.q, n, n, 1, sc + 1, w.dotp, s));
-        AFN_TRY(pcg_alpha_launch(sc, s));
+        AFN_TRY(dot_pcg(w.p, w.q, n, sc, kPcgAlpha, w.dotp, s));
         AFN_TRY(pcg_xr_launch(w.x, w.r, w.p, w.q, sc, n, w.dotp, sc + 2, s));
         AFN_HIP(hipMemcpyAsync(hs + 1, sc + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-        AFN_HIP(hipStreamSynchronize(s));
+        AFN_HIP(hipEventRecord(h->chk_ev, s));
+        // z = M^{-1} r and r'z go on the stream before the host reads the
+        // residual (x, r and p stay as they are, so a check that ends the
+        // loop discards only z): the device never waits for the host
+        if (it + 1 < maxit) {
+            AFN_TRY(apply_block(h, w.r, w.z, w, s));
+            AFN_TRY(dot_pcg(w.r, w.z, n, sc, kPcgBeta, w.dotp, s));
+        }
+        AFN_HIP(hipEventSynchronize(h->chk_ev));
         {
             float t = 0.f;
             if (hipEventElapsedTime(&t, h->kmv_ev[0], h->kmv_ev[1]) == hipSuccess) {
@@ -530,9 +550,6 @@ afn_status pcg64_iterate(afn_handle *h, double bnorm, double tol, int maxit, con
             return AFN_EBREAKDOWN;
         }
         if (rel <= tol) return AFN_OK;
-        AFN_TRY(apply_block(h, w.r, w.z, w, s));
-        AFN_TRY(dot(w.r, n, w.z, n, n, 1, sc + 3, w.dotp, s));
-        AFN_TRY(pcg_beta_launch(sc, s));
         AFN_TRY(pcg_p_launch(w.p, w.z, sc, n, s));
     }
     return AFN_ENOCONV;
@@ -610,11 +627,17 @@ afn_status pcg_inner32(afn_handle *h, double r0norm, double tol_in, int maxit, c
     for (int it = 0; it < maxit; ++it) {
         AFN_TRY(kmv_packed_f32(h->Xs32, n, h->d, h->mu, h->kind, w.p, n, w.q, n, 1, w.kmv, s, h->kmv_ev[0],
                                h->kmv_ev[1], h->kperm, h->box32));
-        AFN_TRY(dot(w.p, n, w.q, n, n, 1, sc + 1, dotp, s));
-        AFN_TRY(pcg_alpha_launch(sc, s));
+        AFN_TRY(dot_pcg(w.p, w.q, n, sc, kPcgAlpha, dotp, s));
         AFN_TRY(pcg_xr_launch(w.e, w.r, w.p, w.q, sc, n, dotp, sc + 2, s));
         AFN_HIP(hipMemcpyAsync(hs + 9, sc + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-        AFN_HIP(hipStreamSynchronize(s));
+        AFN_HIP(hipEventRecord(h->chk_ev, s));
+        // the next z = M^{-1} r and r'z are queued before the check (as in
+        // the FP64 loop)
+        if (it + 1 < maxit) {
+            AFN_TRY(apply_block32(h, w.r, w.z, w, s));
+            AFN_TRY(dot_pcg(w.r, w.z, n, sc, kPcgBeta, dotp, s));
+        }
+        AFN_HIP(hipEventSynchronize(h->chk_ev));
         float t = 0.f;
         if (hipEventElapsedTime(&t, h->kmv_ev[0], h->kmv_ev[1]) == hipSuccess) {
             *ms_kmv += t;
@@ -629,9 +652,6 @@ afn_status pcg_inner32(afn_handle *h, double r0norm, double tol_in, int maxit, c
             return AFN_EBREAKDOWN;
         }
         if (rel <= tol_in) break;
-        AFN_TRY(apply_block32(h, w.r, w.z, w, s));
-        AFN_TRY(dot(w.r, n, w.z, n, n, 1, sc + 3, dotp, s));
-        AFN_TRY(pcg_beta_launch(sc, s));
         AFN_TRY(pcg_p_launch(w.p, w.z, sc, n, s));
     }
     return AFN_OK;
@@ -792,6 +812,7 @@ afn_status afn_setup(const double *X_dev, int64_t n, int32_t d, double l, double
         if (h->host_sc) (void)hipHostFree(h->host_sc);
         for (auto &e : h->kmv_ev)
             if (e) (void)hipEventDestroy(e);
+        if (h->chk_ev) (void)hipEventDestroy(h->chk_ev);
         h->arena.release();
         return st;
     }
@@ -1006,7 +1027,8 @@ afn_status afn_footprint_bytes(int64_t n, int32_t d, const afn_params *prm, size
     if (nr > 0) afn += r(4 * nr * w) + r(8 * nr * w) + r(8 * (nr + 1)) + r(4 * nr * w) + r(8 * nr * w);
     if (k > 0 && nr > 0) afn += r(8 * k * nr);
     if (f32) afn += r(4 * k * k) + r(4 * k * nr) + 2 * r(4 * nr * w);
-    afn += r((int64_t)fsai_transpose_work_bytes(nr, prm->w)) + r(4 * nr);
+    afn += r((int64_t)fsai_transpose_work_bytes(nr, prm->w)) + r(4 * nr) + r((int64_t)knn_work_bytes(nr, d));
+    if (d <= 10) afn += r((int64_t)spatial_order_work_bytes(nr, d));
     if (d > 10) afn += r(8 * fsai_batch_doubles((int)k, (int)w));
     // Nystrom: L, Dinv, W, Rginv (+ FP32 W, Rginv); G, its block inverses and GEMM partials
     size_t nys = 0;
@@ -1029,6 +1051,7 @@ void afn_destroy(afn_handle *h)
     if (h->host_sc) (void)hipHostFree(h->host_sc);
     for (auto &e : h->kmv_ev)
         if (e) (void)hipEventDestroy(e);
+    if (h->chk_ev) (void)hipEventDestroy(h->chk_ev);
     if (h->mrhs_ws) (void)hipFree(h->mrhs_ws);
     h->arena.release();
     delete h;

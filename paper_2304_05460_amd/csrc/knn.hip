@@ -10,6 +10,17 @@
 // wave-wide rank-and-shift.  The final set is unique, so the pattern does not
 // depend on the candidate order.  Queries are dealt round-robin to waves,
 // which balances the O(p) cost per query.
+//
+// With a spatial (Hilbert) order of Xr, d <= 8: queries are taken in that
+// order, the order is cut into 64-point tiles with their bounding boxes and
+// smallest index, and a query with p >= nr/4 first takes the candidates of
+// its own tile and the two on either side, then every other tile whose
+// smallest index is below p and whose box is not farther than the current
+// (w-1)-th key (the box distance, by the same fma chain over per-coordinate
+// gaps, is a lower bound of every candidate's key: rounding is monotone).
+// A query whose list is not full after those five tiles, and every query
+// with p < nr/4, scans all its predecessors as above.  Both give the same
+// unique set.
 #include <climits>
 
 #include "afn_internal.h"
@@ -95,7 +106,193 @@ __global__ __launch_bounds__(256) void knn_pred(const double *__restrict__ Xr, i
     }
 }
 
+// The sorted list of a query: one entry per lane (ld, lq), cnt entries, and
+// the key of the (w-1)-th entry once the list is full.
+struct KnnList {
+    double ld = __builtin_inf();
+    int lq = INT_MAX;
+    int cnt = 0;
+    double thr_d = __builtin_inf();
+    int thr_q = INT_MAX;
+};
+
+// Offer this lane's candidate (dq, qi) if pass; the wave's passing candidates
+// enter one at a time, lowest lane first.
+__device__ __forceinline__ void knn_offer(KnnList &L, int want, bool pass, double dq, int qi)
+{
+    const int lane = threadIdx.x & 63;
+    pass = pass && (L.cnt < want || key_less(dq, qi, L.thr_d, L.thr_q));
+    uint64_t mask = __ballot(pass);
+    while (mask) {
+        const int src = __ffsll((unsigned long long)mask) - 1;
+        const double nd = __shfl(dq, src, 64);
+        const int nq = __shfl(qi, src, 64);
+        const bool lt = lane < L.cnt && key_less(L.ld, L.lq, nd, nq);
+        const int pos = __popcll(__ballot(lt));
+        const double upd = __shfl_up(L.ld, 1, 64);
+        const int upq = __shfl_up(L.lq, 1, 64);
+        if (lane > pos) { L.ld = upd; L.lq = upq; }
+        if (lane == pos) { L.ld = nd; L.lq = nq; }
+        if (lane >= want) { L.ld = __builtin_inf(); L.lq = INT_MAX; }
+        L.cnt = L.cnt + 1 < want ? L.cnt + 1 : want;
+        mask &= mask - 1;
+        if (L.cnt == want) {
+            L.thr_d = __shfl(L.ld, want - 1, 64);
+            L.thr_q = __shfl(L.lq, want - 1, 64);
+            mask &= __ballot(pass && key_less(dq, qi, L.thr_d, L.thr_q));
+        }
+    }
+}
+
+// Tile t of the ordered points: box[(t*d + c)*2 + {0,1}] = min / max of
+// coordinate c, tmin[t] = smallest index.
+__global__ __launch_bounds__(256) void knn_tile_boxes(const double *__restrict__ Xr, int64_t nr, int d,
+                                                      const int32_t *__restrict__ order, int64_t ntiles,
+                                                      double *__restrict__ box, int32_t *__restrict__ tmin)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ntiles * (d + 1)) return;
+    const int64_t t = e / (d + 1);
+    const int c = (int)(e - t * (d + 1));
+    const int64_t j0 = t * 64, j1 = j0 + 64 < nr ? j0 + 64 : nr;
+    if (c == d) {
+        int32_t m = INT_MAX;
+        for (int64_t j = j0; j < j1; ++j) m = order[j] < m ? order[j] : m;
+        tmin[t] = m;
+        return;
+    }
+    double lo = __builtin_inf(), hi = -__builtin_inf();
+    for (int64_t j = j0; j < j1; ++j) {
+        const double x = Xr[(int64_t)order[j] * d + c];
+        lo = x < lo ? x : lo;
+        hi = x > hi ? x : hi;
+    }
+    box[(t * d + c) * 2] = lo;
+    box[(t * d + c) * 2 + 1] = hi;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void knn_pred_tiles(const double *__restrict__ Xr, int64_t nr, int d, int w,
+                                                      const int32_t *__restrict__ order,
+                                                      const double *__restrict__ box,
+                                                      const int32_t *__restrict__ tmin, int64_t ntiles,
+                                                      int32_t *__restrict__ cols)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int want = w - 1;
+    for (int64_t j = wave; j < nr; j += nwaves) {
+        const int64_t p = order[j];
+        double xp[D];
+#pragma unroll
+        for (int t = 0; t < D; ++t) xp[t] = t < d ? Xr[p * d + t] : 0.0;
+        auto key = [&](int64_t q) {
+            double acc = 0.0;
+#pragma unroll
+            for (int t = 0; t < D; ++t) {
+                if (t < d) {
+                    const double del = xp[t] - Xr[q * d + t];
+                    acc = __builtin_fma(del, del, acc);
+                }
+            }
+            return acc;
+        };
+        KnnList L;
+        auto scan_tile = [&](int64_t tt) {
+            const int64_t jj = tt * 64 + lane;
+            const int64_t q = jj < nr ? (int64_t)order[jj] : nr;
+            const bool valid = q < p;
+            knn_offer(L, want, valid, valid ? key(q) : __builtin_inf(), (int)q);
+        };
+        bool brute = want == 0 || 4 * p < nr;
+        const int64_t T = j / 64;
+        if (!brute) {
+            for (int64_t tt = T - 2; tt <= T + 2; ++tt)
+                if (tt >= 0 && tt < ntiles) scan_tile(tt);
+            brute = L.cnt < want;
+        }
+        if (!brute) {
+            for (int64_t t0 = 0; t0 < ntiles; t0 += 64) {
+                const int64_t t = t0 + lane;
+                double g2 = __builtin_inf();
+                if (t < ntiles && (t < T - 2 || t > T + 2) && tmin[t] < p) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int c = 0; c < D; ++c) {
+                        if (c < d) {
+                            const double lo = box[(t * d + c) * 2], hi = box[(t * d + c) * 2 + 1];
+                            const double gap = xp[c] < lo ? lo - xp[c] : (xp[c] > hi ? xp[c] - hi : 0.0);
+                            acc = __builtin_fma(gap, gap, acc);
+                        }
+                    }
+                    g2 = acc;
+                }
+                uint64_t mask = __ballot(g2 <= L.thr_d);
+                while (mask) {
+                    const int src = __ffsll((unsigned long long)mask) - 1;
+                    mask &= mask - 1;
+                    // the threshold may have dropped since the ballot
+                    if (__shfl(g2, src, 64) <= L.thr_d) scan_tile(t0 + src);
+                }
+            }
+        } else if (want > 0) {
+            L = KnnList();
+            for (int64_t q0 = 0; q0 < p; q0 += 64) {
+                const int64_t q = q0 + lane;
+                const bool valid = q < p;
+                knn_offer(L, want, valid, valid ? key(q) : __builtin_inf(), (int)q);
+            }
+        }
+        int rank = 0;
+        for (int i = 0; i < L.cnt; ++i) {
+            const int oq = __shfl(L.lq, i, 64);
+            rank += (oq < L.lq) ? 1 : 0;
+        }
+        int32_t *row = cols + p * w;
+        if (lane < L.cnt) row[rank] = L.lq;
+        if (lane == 0) row[L.cnt] = (int32_t)p;
+        if (lane > L.cnt && lane < w) row[lane] = -1;
+    }
+}
+
 }  // namespace
+
+size_t knn_work_bytes(int64_t nr, int d)
+{
+    const int64_t nt = (nr + 63) / 64;
+    return (size_t)(nt * d * 2 * 8 + 256 + nt * 4 + 256);
+}
+
+afn_status knn_pattern_ordered(const double *Xr, int64_t nr, int d, int w, const int32_t *order, void *work,
+                               int32_t *cols, hipStream_t s)
+{
+    if (nr <= 0) return AFN_OK;
+    if (w < 1 || w > 64) {
+        set_error("knn_pattern: w=%d outside [1, 64]", w);
+        return AFN_EINVAL;
+    }
+    if (d > 8 || !order || !work) return knn_pattern(Xr, nr, d, w, cols, s);
+    const int64_t nt = (nr + 63) / 64;
+    double *box = (double *)work;
+    int32_t *tmin = (int32_t *)((char *)work + ((nt * d * 2 * 8 + 255) / 256) * 256);
+    hipLaunchKernelGGL(knn_tile_boxes, dim3((unsigned)ceil_div(nt * (d + 1), 256)), dim3(256), 0, s, Xr, nr, d,
+                       order, nt, box, tmin);
+    int64_t waves = nr < 16384 ? nr : 16384;
+    dim3 grid((unsigned)ceil_div(waves, 4)), block(256);
+    switch (d) {
+        case 1: hipLaunchKernelGGL(knn_pred_tiles<1>, grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
+        case 2: hipLaunchKernelGGL(knn_pred_tiles<2>, grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
+        case 3: hipLaunchKernelGGL(knn_pred_tiles<3>, grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
+        case 4: hipLaunchKernelGGL(knn_pred_tiles<4>, grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
+        case 5: hipLaunchKernelGGL(knn_pred_tiles<5>, grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
+        case 6: hipLaunchKernelGGL(knn_pred_tiles<6>, grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
+        case 7: hipLaunchKernelGGL(knn_pred_tiles<7>, grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
+        default: hipLaunchKernelGGL(knn_pred_tiles<8>, grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
+    }
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
 
 afn_status knn_pattern(const double *Xr, int64_t nr, int d, int w, int32_t *cols, hipStream_t s)
 {

@@ -116,31 +116,60 @@ __global__ __launch_bounds__(256) void cell_keys(const double *X, int64_t n, int
     atomicAdd(&cnt[kk], 1ULL);
 }
 
-// Exclusive scan of `count` counters into start[0..count] by one workgroup.
-__global__ __launch_bounds__(1024) void scan_cells(const unsigned long long *cnt, int64_t count,
-                                                   int64_t *start)
+// Exclusive scan of `count` counters into start[0..count], in three passes:
+// the sum of each 1024-counter block, the exclusive scan of the block sums
+// (one workgroup), then each block's own scan plus its offset.
+__device__ int64_t block_scan_1024(int64_t v, int64_t *part)
+{
+    // inclusive scan over the 1024 threads of the workgroup (Hillis-Steele)
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    return part[threadIdx.x];
+}
+
+__global__ __launch_bounds__(1024) void scan_block_sums(const unsigned long long *cnt, int64_t count,
+                                                        int64_t *bsum)
+{
+    __shared__ int64_t part[1024];
+    const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    const int64_t v = i < count ? (int64_t)cnt[i] : 0;
+    const int64_t inc = block_scan_1024(v, part);
+    if (threadIdx.x == 1023) bsum[blockIdx.x] = inc;
+}
+
+__global__ __launch_bounds__(1024) void scan_block_offsets(int64_t *bsum, int64_t nblk, int64_t count,
+                                                           int64_t *start)
 {
     __shared__ int64_t part[1024];
     __shared__ int64_t carry;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
-    for (int64_t base = 0; base < count; base += 1024) {
-        const int64_t i = base + threadIdx.x;
-        const int64_t v = i < count ? (int64_t)cnt[i] : 0;
-        part[threadIdx.x] = v;
+    for (int64_t base = 0; base < nblk; base += 1024) {
+        const int64_t b = base + threadIdx.x;
+        const int64_t v = b < nblk ? bsum[b] : 0;
+        const int64_t inc = block_scan_1024(v, part);
+        if (b < nblk) bsum[b] = carry + inc - v;
         __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            const int64_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-            __syncthreads();
-            part[threadIdx.x] += add;
-            __syncthreads();
-        }
-        if (i < count) start[i] = carry + part[threadIdx.x] - v;
-        __syncthreads();
-        if (threadIdx.x == 1023) carry += part[1023];
+        if (threadIdx.x == 1023) carry += inc;
         __syncthreads();
     }
     if (threadIdx.x == 0) start[count] = carry;
+}
+
+__global__ __launch_bounds__(1024) void scan_block_apply(const unsigned long long *cnt, int64_t count,
+                                                         const int64_t *boff, int64_t *start)
+{
+    __shared__ int64_t part[1024];
+    const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    const int64_t v = i < count ? (int64_t)cnt[i] : 0;
+    const int64_t inc = block_scan_1024(v, part);
+    if (i < count) start[i] = boff[blockIdx.x] + inc - v;
 }
 
 __global__ __launch_bounds__(256) void cell_scatter(const int32_t *key, int64_t n, const int64_t *start,
@@ -179,7 +208,8 @@ size_t spatial_order_work_bytes(int64_t n, int d)
     const int64_t cells = (int64_t)1 << (bits * dims);
     const int64_t nn = n > 0 ? n : 1;
     return (size_t)(round_up(8 * 256 * 2 * dims, 256) + round_up(8 * 2 * dims, 256) + round_up(4 * nn, 256) +
-                    round_up(8 * cells, 256) + round_up(8 * (cells + 1), 256) + round_up(4 * nn, 256));
+                    round_up(8 * cells, 256) + round_up(8 * (cells + 1), 256) + round_up(4 * nn, 256) +
+                    round_up(8 * ceil_div(cells, 1024), 256));
 }
 
 afn_status spatial_order(const double *X, int64_t n, int d, int32_t *order, void *work, hipStream_t s)
@@ -200,13 +230,17 @@ afn_status spatial_order(const double *X, int64_t n, int d, int32_t *order, void
     unsigned long long *cnt = (unsigned long long *)take(8 * cells);
     int64_t *start = (int64_t *)take(8 * (cells + 1));
     int32_t *tmp = (int32_t *)take(4 * n);
+    const int64_t nblk = ceil_div(cells, 1024);
+    int64_t *bsum = (int64_t *)take(8 * nblk);
     const int nb = (int)(ceil_div(n, 256) < 256 ? ceil_div(n, 256) : 256);
     const unsigned g = (unsigned)ceil_div(n, 256);
     hipLaunchKernelGGL(bbox_partial, dim3(nb), dim3(256), 0, s, X, n, d, dims, part);
     hipLaunchKernelGGL(bbox_final, dim3(1), dim3(64), 0, s, part, nb, dims, box);
     AFN_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * (size_t)cells, s));
     hipLaunchKernelGGL(cell_keys, dim3(g), dim3(256), 0, s, X, n, d, bits, dims, box, key, cnt);
-    hipLaunchKernelGGL(scan_cells, dim3(1), dim3(1024), 0, s, cnt, cells, start);
+    hipLaunchKernelGGL(scan_block_sums, dim3((unsigned)nblk), dim3(1024), 0, s, cnt, cells, bsum);
+    hipLaunchKernelGGL(scan_block_offsets, dim3(1), dim3(1024), 0, s, bsum, nblk, cells, start);
+    hipLaunchKernelGGL(scan_block_apply, dim3((unsigned)nblk), dim3(1024), 0, s, cnt, cells, bsum, start);
     AFN_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * (size_t)cells, s));
     hipLaunchKernelGGL(cell_scatter, dim3(g), dim3(256), 0, s, key, n, start, cnt, tmp);
     hipLaunchKernelGGL(cell_rank, dim3((unsigned)ceil_div(cells, 4)), dim3(256), 0, s, start, cells, tmp,

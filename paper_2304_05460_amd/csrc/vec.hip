@@ -59,6 +59,26 @@ __global__ __launch_bounds__(256) void sum_stage2(const double *__restrict__ par
     if (threadIdx.x == 0) *out = s;
 }
 
+// sum_stage2 for the PCG dot products, followed by the scalar step
+// (alpha = rho / p'q, or beta = rho_new / rho and rho = rho_new).
+__global__ __launch_bounds__(256) void sum_stage2_pcg(const double *__restrict__ part, int np,
+                                                      double *__restrict__ sc, int step)
+{
+    double s = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
+    s = block_sum(s);
+    if (threadIdx.x == 0) {
+        if (step == kPcgAlpha) {
+            sc[1] = s;
+            sc[4] = sc[0] / s;
+        } else {
+            sc[3] = s;
+            sc[5] = s / sc[0];
+            sc[0] = s;
+        }
+    }
+}
+
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
@@ -253,20 +273,6 @@ __global__ __launch_bounds__(256) void gather_points_kernel(const double *__rest
     Xp[e] = X[(int64_t)perm[i] * d + t];
 }
 
-// PCG scalar slots (device): see PcgScalars.
-__global__ void pcg_alpha(double *sc)
-{
-    // sc[0] rho, sc[1] pq -> sc[4] alpha
-    sc[4] = sc[0] / sc[1];
-}
-
-__global__ void pcg_beta(double *sc)
-{
-    // sc[3] rho_new, sc[0] rho -> sc[5] beta; rho = rho_new
-    sc[5] = sc[3] / sc[0];
-    sc[0] = sc[3];
-}
-
 // x += alpha p; r -= alpha q; partial sums of r.r (FP64 scalars, vectors in T)
 template <typename T>
 __global__ __launch_bounds__(256) void pcg_xr(T *__restrict__ x, T *__restrict__ r,
@@ -385,6 +391,18 @@ afn_status dotT(const T *a, int64_t lda, const T *b, int64_t ldb, int64_t n, int
                            chunk, part);
         hipLaunchKernelGGL(sum_stage2, dim3(1), dim3(256), 0, s, part, (int)nb, out + c);
     }
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+template <typename T>
+afn_status dot_pcgT(const T *a, const T *b, int64_t n, double *sc, PcgDotStep step, double *part,
+                    hipStream_t s)
+{
+    const int64_t nb = dot_partials(n);
+    const int64_t chunk = ceil_div(n, nb);
+    hipLaunchKernelGGL((dot_stage1<T>), dim3((unsigned)nb), dim3(256), 0, s, a, b, n, chunk, part);
+    hipLaunchKernelGGL(sum_stage2_pcg, dim3(1), dim3(256), 0, s, part, (int)nb, sc, (int)step);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }
@@ -581,18 +599,15 @@ afn_status gather_points(const double *X, const int32_t *perm, int64_t n, int d,
     return AFN_OK;
 }
 
-afn_status pcg_alpha_launch(double *sc, hipStream_t s)
+afn_status dot_pcg(const double *a, const double *b, int64_t n, double *sc, PcgDotStep step,
+                   double *partials, hipStream_t s)
 {
-    hipLaunchKernelGGL(pcg_alpha, dim3(1), dim3(1), 0, s, sc);
-    AFN_HIP(hipGetLastError());
-    return AFN_OK;
+    return dot_pcgT(a, b, n, sc, step, partials, s);
 }
-
-afn_status pcg_beta_launch(double *sc, hipStream_t s)
+afn_status dot_pcg(const float *a, const float *b, int64_t n, double *sc, PcgDotStep step,
+                   double *partials, hipStream_t s)
 {
-    hipLaunchKernelGGL(pcg_beta, dim3(1), dim3(1), 0, s, sc);
-    AFN_HIP(hipGetLastError());
-    return AFN_OK;
+    return dot_pcgT(a, b, n, sc, step, partials, s);
 }
 
 afn_status sub_launch(const double *b, const double *y, double *r, int64_t n, hipStream_t s)

@@ -398,6 +398,24 @@ def test_c2_fps_pattern_and_fsai_sampled(afn):
         assert np.linalg.norm(g - fg[s_, :fl[s_]]) <= 1e-6 * np.linalg.norm(g)
 
 
+@pytest.mark.parametrize("n,d,w,pts", [(12000, 3, 64, "mixture5"), (9000, 2, 33, "uniform"),
+                                       (8000, 5, 17, "normal"), (10000, 8, 64, "normal"),
+                                       (5000, 1, 8, "uniform"), (3000, 3, 1, "uniform"),
+                                       (700, 4, 64, "uniform")])
+def test_knn_pattern_full_with_tiles(afn, n, d, w, pts):
+    # every row of the predecessor pattern, bit-exact, across the tile-pruned
+    # search (rows p >= (n-k)/4) and the full scan (the other rows)
+    X = W.points(pts, n, d, 34)
+    k = 30
+    say(f"knn full n={n} d={d} w={w}")
+    h = afn.afn_setup(dev(X), 1.0, 1e-2, k=k, w=w)
+    perm = oracle.permutation(n, h.landmarks())
+    rowptr, cols, _ = h.fsai()
+    orp, ocols = oracle.knn_pattern(X[perm[k:]], w)
+    np.testing.assert_array_equal(rowptr, orp)
+    np.testing.assert_array_equal(cols, ocols)
+
+
 # ------------------------------------------------------------------ rank estimation
 
 @pytest.mark.parametrize("l", [0.02, 0.1, 1.0])
