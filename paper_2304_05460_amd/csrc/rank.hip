@@ -151,7 +151,7 @@ __global__ __launch_bounds__(256) void scan_update(double *K, int m, const int32
 
 // ---------------------------------------------------------------- eigen count
 // Householder tridiagonalization of the symmetric A (m x m, column-major),
-// two launches per step j = 0 .. m-3.  The reflector of step j is
+// one launch per step j = 0 .. m-3 after the first product.  The reflector of step j is
 // H = I - beta v v^T with v supported on rows j+1 .. m-1, kept in one of two
 // buffers (step parity) with beta in sc[0]; the step replaces the trailing
 // block B = A[j+1:, j+1:] by H B H = B - v w^T - w v^T with p = beta B v,
@@ -159,8 +159,11 @@ __global__ __launch_bounds__(256) void scan_update(double *K, int m, const int32
 // wavefront: reads along the column are coalesced, and every sum runs in a
 // fixed order (lane partials in row order, then a butterfly), so the result
 // does not depend on scheduling.  Rows and columns <= j+1 are never read
-// after step j, so the update writes only A[j+2:, j+2:] and the column j+1
-// is consumed on the fly: its wavefront forms the reflector of step j+1.
+// after step j, so the update writes only A[j+2:, j+2:].  The launch of
+// step j also does the product of step j+1: every workgroup forms the
+// updated column j+1 and from it the reflector of step j+1 (the same
+// arithmetic in each), then updates its columns and takes their products
+// with the new reflector while the values are in registers.
 // diag[c] / off[c] collect the tridiagonal T (the sub-diagonal up to sign).
 
 __device__ __forceinline__ double wave_sum(double x)
@@ -254,26 +257,83 @@ __global__ __launch_bounds__(256) void hh_mv(const double *__restrict__ A, int m
     if (threadIdx.x == 0) part[blockIdx.x] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
 }
 
-// Rank-two update of step j on the columns c > j, and the reflector of step
-// j+1 (into vn / scn / off[j+1]) from the updated column j+1.  Every
-// wavefront forms K = beta/2 v^T p from the per-block partials itself (same
-// order everywhere).
-__global__ __launch_bounds__(256) void hh_up(double *__restrict__ A, int m, int j, const double *__restrict__ v,
-                                             const double *__restrict__ sc, const double *__restrict__ p,
-                                             const double *__restrict__ part, int nb, double *__restrict__ vn,
-                                             double *__restrict__ scn, double *__restrict__ diag,
-                                             double *__restrict__ off)
+// Step j's rank-two update fused with step j+1's product.  In: v, sc (beta),
+// p and the nb partials of v^T p of step j.  Out: the reflector of step j+1
+// (vn, scn, off[j+1]; written by workgroup 0), diag[j+1], the updated
+// A[j+2:, j+2:], pn[c] = beta' sum_{i >= j+2} A'[i,c] v'[i] for c >= j+2 and
+// per-workgroup partials partn of v'^T pn (four columns per workgroup, one
+// per wavefront).
+__global__ __launch_bounds__(256) void hh_step(double *__restrict__ A, int m, int j,
+                                               const double *__restrict__ v, const double *__restrict__ sc,
+                                               const double *__restrict__ p, const double *__restrict__ part,
+                                               int nb, double *__restrict__ vn, double *__restrict__ scn,
+                                               double *__restrict__ pn, double *__restrict__ partn,
+                                               double *__restrict__ diag, double *__restrict__ off)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int c = j + 1 + (int)blockIdx.x * 4 + wv;
-    if (c >= m) return;
+    __shared__ double vl[kMaxM];     // the new reflector, by row (rows >= j+2)
+    __shared__ double red[4];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // K = beta/2 v^T p, every wavefront in the same order
     double s = 0.0;
-    for (int b = lane; b < nb; b += 64) s += part[b];
+    for (int b0 = lane; b0 < nb; b0 += 64 * kUnroll) {
+        double q[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) q[u] = b0 + 64 * u < nb ? part[b0 + 64 * u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) s += q[u];
+    }
     const double K = 0.5 * sc[0] * wave_sum(s);
-    const double vc = v[c], wc = p[c] - K * vc;
-    double *col = A + (int64_t)c * m;
-    if (c > j + 1) {
-        for (int base = j + 2 + lane; base < m; base += 64 * kUnroll) {
+    // the updated column j+1 below the diagonal, and its squared norm
+    const int c1 = j + 1, r0 = j + 2;
+    const double v1 = v[c1], w1 = p[c1] - K * v1;
+    const double *col1 = A + (int64_t)c1 * m;
+    double a2 = 0.0;
+    for (int base = r0 + tid; base < m; base += 256 * kUnroll) {
+        double x[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int i = base + 256 * u;
+            if (i < m) {
+                const double vi = v[i], wi = p[i] - K * vi;
+                x[u] = col1[i] - (vi * w1 + wi * v1);
+            } else {
+                x[u] = 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int i = base + 256 * u;
+            if (i < m) vl[i] = x[u];
+            a2 = __builtin_fma(x[u], x[u], a2);
+        }
+    }
+    a2 = wave_sum(a2);
+    if (lane == 0) red[wv] = a2;
+    __syncthreads();
+    const double x0 = vl[r0];
+    const double alpha = sqrt(((red[0] + red[1]) + red[2]) + red[3]);
+    const double snew = x0 >= 0.0 ? -alpha : alpha;
+    const double vn2 = 2.0 * alpha * (alpha + fabs(x0));
+    const double beta1 = alpha == 0.0 || !(vn2 > 0.0) ? 0.0 : 2.0 / vn2;
+    __syncthreads();    // x0 read everywhere before it is replaced
+    if (tid == 0) vl[r0] = x0 - snew;
+    __syncthreads();
+    if (blockIdx.x == 0) {
+        for (int i = r0 + tid; i < m; i += 256) vn[i] = vl[i];
+        if (tid == 0) {
+            scn[0] = beta1;
+            off[c1] = snew;
+            diag[c1] = col1[c1] - (v1 * w1 + w1 * v1);
+        }
+    }
+    // the workgroup's columns: update, then the product with the new reflector
+    const int c = r0 + (int)blockIdx.x * 4 + wv;
+    double dotc = 0.0;
+    if (c < m) {
+        const double vc = v[c], wc = p[c] - K * vc;
+        double *col = A + (int64_t)c * m;
+        double acc = 0.0;
+        for (int base = r0 + lane; base < m; base += 64 * kUnroll) {
             double a[kUnroll], vv[kUnroll], pp[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
@@ -285,20 +345,24 @@ __global__ __launch_bounds__(256) void hh_up(double *__restrict__ A, int m, int 
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const int i = base + 64 * u;
-                const double wi = pp[u] - K * vv[u];
-                const double x = a[u] - (vv[u] * wc + wi * vc);
-                if (i < m) col[i] = x;
-                if (i == c) diag[c] = x;
+                if (i < m) {
+                    const double wi = pp[u] - K * vv[u];
+                    const double x = a[u] - (vv[u] * wc + wi * vc);
+                    col[i] = x;
+                    if (i == c) diag[c] = x;
+                    acc = __builtin_fma(x, vl[i], acc);
+                }
             }
         }
-        return;
+        acc = wave_sum(acc);
+        const double pc = beta1 * acc;
+        if (lane == 0) pn[c] = pc;
+        dotc = vl[c] * pc;
     }
-    if (lane == 0) diag[c] = col[c] - (vc * wc + wc * vc);
-    auto updated = [&](int i) {
-        const double vi = v[i], wi = p[i] - K * vi;
-        return col[i] - (vi * wc + wi * vc);
-    };
-    house_wave(updated, j + 2, m, vn, scn, off + c);
+    __syncthreads();    // red[] reused
+    if (lane == 0) red[wv] = dotc;
+    __syncthreads();
+    if (tid == 0) partn[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 // Number of eigenvalues of T above tau: positive pivots of the LDL^T of
@@ -417,23 +481,28 @@ afn_status rank_estimate(const double *X, int64_t n, int d, double l, int kind, 
     if (kest < 2000) {
         // eigenvalues of K(X_m, X_m) on the unscaled subsample above 0.1 mu
         AFN_TRY(tmp.alloc_n(&v, 2 * (int64_t)m));
-        AFN_TRY(tmp.alloc_n(&pw, m));
+        AFN_TRY(tmp.alloc_n(&pw, 2 * (int64_t)m));
         AFN_TRY(tmp.alloc_n(&sc, 8));
         AFN_TRY(tmp.alloc_n(&cnt, 1));
-        AFN_TRY(tmp.alloc_n(&gp, ceil_div(m, 4) + 1));
+        const int64_t gps = ceil_div(m, 4) + 1;
+        AFN_TRY(tmp.alloc_n(&gp, 2 * gps));
         AFN_TRY(tmp.alloc_n(&tdiag, m));
         AFN_TRY(tmp.alloc_n(&toff, m));
         hipLaunchKernelGGL(gather_scaled, dim3((unsigned)ceil_div((int64_t)m * d, 256)), dim3(256), 0, s,
                            X, sub, m, d, 1.0, Xm);
         hipLaunchKernelGGL(kmat_fill, dim3(gmm), dim3(256), 0, s, Xm, m, d, l2, kind, K);
         hipLaunchKernelGGL(hh_init, dim3(1), dim3(64), 0, s, K, m, v, sc, tdiag, toff);
+        if (m >= 3)
+            hipLaunchKernelGGL(hh_mv, dim3((unsigned)ceil_div(m - 1, 4)), dim3(256), 0, s, K, m, 0, v, sc, pw,
+                               gp);
+        // step j reads buffer set j & 1 (v, beta, p, partials) and writes the other
         for (int j = 0; j + 2 < m; ++j) {
-            const int nb = (int)ceil_div(m - j - 1, 4);
+            const int nb = (int)ceil_div(m - j - 1, 4);         // workgroups of the previous launch
+            const int nbn = (int)ceil_div(m - j - 2, 4);        // of this one (>= 1: j + 2 < m)
             const int cur = j & 1, nxt = cur ^ 1;
-            hipLaunchKernelGGL(hh_mv, dim3((unsigned)nb), dim3(256), 0, s, K, m, j, v + (int64_t)cur * m,
-                               sc + 4 * cur, pw, gp);
-            hipLaunchKernelGGL(hh_up, dim3((unsigned)nb), dim3(256), 0, s, K, m, j, v + (int64_t)cur * m,
-                               sc + 4 * cur, pw, gp, nb, v + (int64_t)nxt * m, sc + 4 * nxt, tdiag, toff);
+            hipLaunchKernelGGL(hh_step, dim3((unsigned)nbn), dim3(256), 0, s, K, m, j, v + (int64_t)cur * m,
+                               sc + 4 * cur, pw + (int64_t)cur * m, gp + cur * gps, nb, v + (int64_t)nxt * m,
+                               sc + 4 * nxt, pw + (int64_t)nxt * m, gp + nxt * gps, tdiag, toff);
         }
         hipLaunchKernelGGL(sturm_count, dim3(1), dim3(1), 0, s, tdiag, toff, m, 0.1 * mu, cnt);
         AFN_HIP(hipGetLastError());
