@@ -58,8 +58,12 @@ __device__ __forceinline__ int64_t xcd_contiguous(int64_t b, int64_t G)
     return start + j;
 }
 
+// Two waves per SIMD: without the bound the compiler keeps the Gram tiles
+// in accumulation registers on top of 221 others (one wave per SIMD, a
+// third slower on the gathers); with it they share the 256 registers, no
+// spill.
 template <int NT>
-__global__ __launch_bounds__(64) void fsai_row_mfma(const double *__restrict__ Xp, int k, int d, double l2,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void fsai_row_mfma(const double *__restrict__ Xp, int k, int d, double l2,
                                                     int kind, double mu, const double *__restrict__ V,
                                                     const int32_t *__restrict__ cols, int w,
                                                     double *__restrict__ gval, int *info,
