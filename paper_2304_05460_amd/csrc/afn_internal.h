@@ -38,6 +38,18 @@ constexpr int kMaxW = 64;
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 
+// Block b of a launch of G blocks, in XCD-aware order: blocks are dealt to
+// the 8 XCDs round-robin, so XCD x gets b = x, x+8, ...; giving it a
+// contiguous range of spatially ordered rows keeps each XCD's gathers within
+// its own L2.
+__device__ __forceinline__ int64_t xcd_contiguous(int64_t b, int64_t G)
+{
+    const int64_t x = b & 7, j = b >> 3;
+    int64_t start = 0;
+    for (int64_t y = 0; y < x; ++y) start += (G - y + 7) >> 3;
+    return start + j;
+}
+
 // Device buffer list owned by a handle.
 struct DevArena {
     std::vector<void *> ptrs;
@@ -215,15 +227,18 @@ afn_status gemv_t(const double *A, int64_t lda, int64_t m, int64_t ncols, const 
                   const double *base, double sign, double *y, hipStream_t s);
 afn_status gemv_t(const float *A, int64_t lda, int64_t m, int64_t ncols, const float *x,
                   const float *base, float sign, float *y, hipStream_t s);
-// u = G t (padded rows) ;  out = G^T u (CSR of G^T)
+// u = G t (padded rows) ;  out = G^T u (CSR of G^T).  order (optional): the
+// rows are visited in this order, each XCD taking a contiguous range of it
+// (a spatial order keeps the gathers of concurrent rows in one L2); results
+// do not depend on it.
 afn_status spmv_g(const int32_t *cols, const double *gval, int64_t nr, int w, const double *t,
-                  double *u, hipStream_t s);
+                  double *u, const int32_t *order, hipStream_t s);
 afn_status spmv_g(const int32_t *cols, const float *gval, int64_t nr, int w, const float *t, float *u,
-                  hipStream_t s);
+                  const int32_t *order, hipStream_t s);
 afn_status spmv_gt(const int64_t *ptr, const int32_t *idx, const double *val, int64_t nr,
-                   const double *u, double *out, hipStream_t s);
+                   const double *u, double *out, const int32_t *order, hipStream_t s);
 afn_status spmv_gt(const int64_t *ptr, const int32_t *idx, const float *val, int64_t nr,
-                   const float *u, float *out, hipStream_t s);
+                   const float *u, float *out, const int32_t *order, hipStream_t s);
 afn_status permute_gather(const double *src, int64_t lds, double *dst, int64_t ldd,
                           const int32_t *perm, int64_t n, int nrhs, hipStream_t s);
 afn_status permute_scatter(const double *src, int64_t lds, double *dst, int64_t ldd,
@@ -274,12 +289,13 @@ template <typename T>
 afn_status gemm_rows(const T *A, int64_t ars, int64_t acs, int64_t m, int64_t K, const T *B,
                      int64_t ldb, int R, const T *base, T sign, T *C, int64_t ldc, T *part,
                      hipStream_t s);
+// G and G^T on R columns (row-major blocks); order as for spmv_g.
 template <typename T>
 afn_status spmm_g(const int32_t *cols, const T *g, int64_t nr, int w, const T *X, int R, T *U,
-                  hipStream_t s);
+                  const int32_t *order, hipStream_t s);
 template <typename T>
 afn_status spmm_gt(const int64_t *ptr, const int32_t *idx, const T *val, int64_t nr, const T *X,
-                   int R, T *U, hipStream_t s);
+                   int R, T *U, const int32_t *order, hipStream_t s);
 int64_t coldot_blocks(int64_t n);
 template <typename T>
 afn_status coldot(const T *A, const T *B, int64_t n, int R, double *out, double *part,
@@ -364,5 +380,6 @@ struct afn_handle {
     double *host_sc = nullptr;  // pinned host copy of PCG scalars
     hipEvent_t kmv_ev[2] = {nullptr, nullptr};  // timing of the matvec tile kernel
     hipEvent_t chk_ev = nullptr;                // the PCG residual check's host copy
+    int32_t *rorder = nullptr;                  // spatial order of the non-landmark rows (d <= 10)
     afn_setup_info info{};
 };

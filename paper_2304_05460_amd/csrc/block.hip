@@ -125,8 +125,8 @@ afn_status apply32_block(afn_handle *h, const float *Rin, float *Zout, int R, co
                                      w.gpart, s));
             t = w.T;
         }
-        AFN_TRY(spmm_g<float>(h->cols, h->gval32, nr, h->w, t, R, w.U, s));
-        AFN_TRY(spmm_gt<float>(h->tptr, h->trow, h->tval32, nr, w.U, R, Zout + (int64_t)k * R, s));
+        AFN_TRY(spmm_g<float>(h->cols, h->gval32, nr, h->w, t, R, w.U, h->rorder, s));
+        AFN_TRY(spmm_gt<float>(h->tptr, h->trow, h->tval32, nr, w.U, R, Zout + (int64_t)k * R, nullptr, s));
     }
     if (k > 0) {
         const float *y = w.Y1;

@@ -137,8 +137,10 @@ afn_status apply_blockT(const afn_handle *h, const Factors<T> &f, const T *rp, T
             AFN_TRY(gemv_t(f.V, k, k, nr, y1, rp + k, T(-1), tt, s));
             t = tt;
         }
-        AFN_TRY(spmv_g(h->cols, f.gval, nr, h->w, t, u, s));
-        AFN_TRY(spmv_gt(h->tptr, h->trow, f.tval, nr, u, sp + k, s));
+        // G in spatial row order (its gathers of t stay close); G^T in its
+        // own order, where the contiguous value stream matters more
+        AFN_TRY(spmv_g(h->cols, f.gval, nr, h->w, t, u, h->rorder, s));
+        AFN_TRY(spmv_gt(h->tptr, h->trow, f.tval, nr, u, sp + k, nullptr, s));
     }
     if (k > 0) {
         const T *y = y1;
@@ -370,12 +372,13 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
         AFN_TRY(trsm_lower(h->L, h->Dinv, k, h->Linv, k, s));
     }
     tm.mark(3, s);
-    // spatial order of the non-landmark points: tiles for the pattern search
-    // and the row order of the FSAI gathers (d <= 10)
+    // spatial order of the non-landmark points: tiles for the pattern search,
+    // the row order of the FSAI gathers and of the G / G^T products (d <= 10)
     int32_t *rorder = nullptr;
     if (nr > 0 && d <= 10) {
         void *ows = nullptr;
-        AFN_TRY(tmp.alloc_n(&rorder, nr));
+        AFN_TRY(h->arena.alloc_n(&h->rorder, nr));
+        rorder = h->rorder;
         AFN_TRY(tmp.alloc(&ows, spatial_order_work_bytes(nr, d)));
         AFN_TRY(spatial_order(h->Xp + (int64_t)k * d, nr, d, rorder, ows, s));
     }

@@ -46,18 +46,6 @@ __device__ __forceinline__ double wave_sum(double x)
 
 constexpr int tile_index(int I, int J) { return I * (I + 1) / 2 + J; }
 
-// Block b of a launch of G blocks, in XCD-aware order: blocks are dealt to
-// the 8 XCDs round-robin, so XCD x gets b = x, x+8, ...; giving it a
-// contiguous range of the (spatially ordered) rows keeps each XCD's gathers of
-// V columns within its own L2.
-__device__ __forceinline__ int64_t xcd_contiguous(int64_t b, int64_t G)
-{
-    const int64_t x = b & 7, j = b >> 3;
-    int64_t start = 0;
-    for (int64_t y = 0; y < x; ++y) start += (G - y + 7) >> 3;
-    return start + j;
-}
-
 // Two waves per SIMD: without the bound the compiler keeps the Gram tiles
 // in accumulation registers on top of 221 others (one wave per SIMD, a
 // third slower on the gathers); with it they share the 256 registers, no

@@ -474,14 +474,28 @@ template <typename T>
 __global__ __launch_bounds__(256) void spmm_padded(const int32_t *__restrict__ cols,
                                                    const T *__restrict__ g, int64_t nr, int w,
                                                    const T *__restrict__ X, int64_t ld, int R,
-                                                   T *__restrict__ U)
+                                                   T *__restrict__ U, const int32_t *__restrict__ order)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (p >= nr || lane >= R) return;
+    const int64_t blk = order ? xcd_contiguous(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    const int64_t slot = blk * 4 + (threadIdx.x >> 6);
+    if (slot >= nr || lane >= R) return;
+    const int64_t p = order ? (int64_t)order[slot] : slot;
     const int m = (int)(p + 1 < w ? p + 1 : w);
     T s = T(0);
-    for (int a = 0; a < m; ++a) s = fmaT(g[p * w + a], X[(int64_t)cols[p * w + a] * ld + lane], s);
+    // 8 gathers in flight; entries past the row's end repeat entry m - 1
+    // with weight zero (the sum stays in entry order)
+    for (int a0 = 0; a0 < m; a0 += 8) {
+        T gv[8], xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int a = a0 + u < m ? a0 + u : m - 1;
+            gv[u] = a0 + u < m ? g[p * w + a] : T(0);
+            xv[u] = X[(int64_t)cols[p * w + a] * ld + lane];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s = fmaT(gv[u], xv[u], s);
+    }
     U[p * ld + lane] = s;
 }
 
@@ -490,13 +504,26 @@ __global__ __launch_bounds__(256) void spmm_csr(const int64_t *__restrict__ ptr,
                                                 const int32_t *__restrict__ idx,
                                                 const T *__restrict__ val, int64_t nrows,
                                                 const T *__restrict__ X, int64_t ld, int R,
-                                                T *__restrict__ U)
+                                                T *__restrict__ U, const int32_t *__restrict__ order)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (q >= nrows || lane >= R) return;
+    const int64_t blk = order ? xcd_contiguous(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    const int64_t slot = blk * 4 + (threadIdx.x >> 6);
+    if (slot >= nrows || lane >= R) return;
+    const int64_t q = order ? (int64_t)order[slot] : slot;
     T s = T(0);
-    for (int64_t e = ptr[q]; e < ptr[q + 1]; ++e) s = fmaT(val[e], X[(int64_t)idx[e] * ld + lane], s);
+    const int64_t e1 = ptr[q + 1];
+    for (int64_t e0 = ptr[q]; e0 < e1; e0 += 8) {
+        T vv[8], xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t e = e0 + u < e1 ? e0 + u : e1 - 1;
+            vv[u] = e0 + u < e1 ? val[e] : T(0);
+            xv[u] = X[(int64_t)idx[e] * ld + lane];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s = fmaT(vv[u], xv[u], s);
+    }
     U[q * ld + lane] = s;
 }
 
@@ -513,7 +540,18 @@ __global__ __launch_bounds__(256) void coldot_stage1(const T *__restrict__ A, co
     const int64_t i1 = i0 + chunk < n ? i0 + chunk : n;
     double s = 0.0;
     if (c < R)
-        for (int64_t i = i0 + g; i < i1; i += 4) s = __builtin_fma((double)A[i * R + c], (double)B[i * R + c], s);
+        for (int64_t i = i0 + g; i < i1; i += 16) {
+            // four rows' loads in flight; the products are added in row order
+            T a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t r = i + 4 * u < i1 ? i + 4 * u : i;
+                a[u] = i + 4 * u < i1 ? A[r * R + c] : T(0);
+                b[u] = B[r * R + c];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s = __builtin_fma((double)a[u], (double)b[u], s);
+        }
     red[g][c] = s;
     __syncthreads();
     if (g == 0 && c < R) part[(int64_t)blockIdx.x * R + c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
@@ -525,7 +563,13 @@ __global__ __launch_bounds__(64) void coldot_stage2(const double *__restrict__ p
     const int c = threadIdx.x;
     if (c >= R) return;
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * R + c];
+    for (int b0 = 0; b0 < nb; b0 += 8) {
+        double q[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) q[u] = b0 + u < nb ? part[(int64_t)(b0 + u) * R + c] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += q[u];
+    }
     out[c] = s;
 }
 
@@ -570,12 +614,27 @@ __global__ __launch_bounds__(256) void col_xr(T *__restrict__ X, T *__restrict__
     double s = 0.0;
     if (c < R) {
         const T a = (T)alpha[c];
-        for (int64_t i = i0 + g; i < i1; i += 4) {
-            const int64_t e = i * R + c;
-            X[e] = fmaT(a, Pv[e], X[e]);
-            const T r = fmaT(-a, Q[e], Rv[e]);
-            Rv[e] = r;
-            s = __builtin_fma((double)r, (double)r, s);
+        for (int64_t i = i0 + g; i < i1; i += 16) {
+            // four rows' loads in flight, updated and summed in row order
+            T xv[4], pv[4], qv[4], rv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t e = (i + 4 * u < i1 ? i + 4 * u : i) * R + c;
+                xv[u] = X[e];
+                pv[u] = Pv[e];
+                qv[u] = Q[e];
+                rv[u] = Rv[e];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (i + 4 * u < i1) {
+                    const int64_t e = (i + 4 * u) * R + c;
+                    X[e] = fmaT(a, pv[u], xv[u]);
+                    const T r = fmaT(-a, qv[u], rv[u]);
+                    Rv[e] = r;
+                    s = __builtin_fma((double)r, (double)r, s);
+                }
+            }
         }
     }
     red[g][c] = s;
@@ -847,39 +906,39 @@ template afn_status gemm_rows<double>(const double *, int64_t, int64_t, int64_t,
 
 template <typename T>
 afn_status spmm_g(const int32_t *cols, const T *g, int64_t nr, int w, const T *X, int R, T *U,
-                  hipStream_t s)
+                  const int32_t *order, hipStream_t s)
 {
     if (nr <= 0) return AFN_OK;
     hipLaunchKernelGGL((spmm_padded<T>), dim3((unsigned)ceil_div(nr, 4)), dim3(256), 0, s, cols, g, nr, w, X,
-                       (int64_t)R, R, U);
+                       (int64_t)R, R, U, order);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }
 
 template <typename T>
 afn_status spmm_gt(const int64_t *ptr, const int32_t *idx, const T *val, int64_t nr, const T *X, int R,
-                   T *U, hipStream_t s)
+                   T *U, const int32_t *order, hipStream_t s)
 {
     if (nr <= 0) return AFN_OK;
     hipLaunchKernelGGL((spmm_csr<T>), dim3((unsigned)ceil_div(nr, 4)), dim3(256), 0, s, ptr, idx, val, nr, X,
-                       (int64_t)R, R, U);
+                       (int64_t)R, R, U, order);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }
 
 template afn_status spmm_g<float>(const int32_t *, const float *, int64_t, int, const float *, int,
-                                  float *, hipStream_t);
+                                  float *, const int32_t *, hipStream_t);
 template afn_status spmm_g<double>(const int32_t *, const double *, int64_t, int, const double *, int,
-                                   double *, hipStream_t);
+                                  double *, const int32_t *, hipStream_t);
 template afn_status spmm_gt<float>(const int64_t *, const int32_t *, const float *, int64_t,
-                                   const float *, int, float *, hipStream_t);
+                                   const float *, int, float *, const int32_t *, hipStream_t);
 template afn_status spmm_gt<double>(const int64_t *, const int32_t *, const double *, int64_t,
-                                    const double *, int, double *, hipStream_t);
+                                    const double *, int, double *, const int32_t *, hipStream_t);
 
 int64_t coldot_blocks(int64_t n)
 {
-    int64_t b = ceil_div(n, 1024);
-    return b < 1 ? 1 : (b > 512 ? 512 : b);
+    int64_t b = ceil_div(n, 256);
+    return b < 1 ? 1 : (b > 2048 ? 2048 : b);
 }
 
 template <typename T>

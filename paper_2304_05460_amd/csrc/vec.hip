@@ -183,11 +183,14 @@ __device__ __forceinline__ T group16_sum(T s)
 template <typename T>
 __global__ __launch_bounds__(256) void spmv_padded(const int32_t *__restrict__ cols,
                                                    const T *__restrict__ gval, int64_t nr, int w,
-                                                   const T *__restrict__ t, T *__restrict__ u)
+                                                   const T *__restrict__ t, T *__restrict__ u,
+                                                   const int32_t *__restrict__ order)
 {
     const int q = threadIdx.x & 15;
-    const int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
-    if (p >= nr) return;
+    const int64_t blk = order ? xcd_contiguous(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    const int64_t slot = blk * 16 + (threadIdx.x >> 4);
+    if (slot >= nr) return;
+    const int64_t p = order ? (int64_t)order[slot] : slot;
     const int m = (int)(p + 1 < w ? p + 1 : w);
     const int64_t base = p * w;
     // entries past the row's end load entry m - 1 (in bounds) and count zero,
@@ -215,11 +218,14 @@ template <typename T>
 __global__ __launch_bounds__(256) void spmv_csr(const int64_t *__restrict__ ptr,
                                                 const int32_t *__restrict__ idx,
                                                 const T *__restrict__ val, int64_t nrows,
-                                                const T *__restrict__ u, T *__restrict__ out)
+                                                const T *__restrict__ u, T *__restrict__ out,
+                                                const int32_t *__restrict__ order)
 {
     const int q = threadIdx.x & 15;
-    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
-    if (c >= nrows) return;
+    const int64_t blk = order ? xcd_contiguous(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    const int64_t slot = blk * 16 + (threadIdx.x >> 4);
+    if (slot >= nrows) return;
+    const int64_t c = order ? (int64_t)order[slot] : slot;
     const int64_t e1 = ptr[c + 1];
     T s = T(0);
     for (int64_t e = ptr[c] + q; e < e1; e += 64) {
@@ -439,22 +445,22 @@ afn_status gemv_tT(const T *A, int64_t lda, int64_t m, int64_t ncols, const T *x
 
 template <typename T>
 afn_status spmv_gT(const int32_t *cols, const T *gval, int64_t nr, int w, const T *t, T *u,
-                   hipStream_t s)
+                   const int32_t *order, hipStream_t s)
 {
     if (nr <= 0) return AFN_OK;
     hipLaunchKernelGGL((spmv_padded<T>), dim3((unsigned)ceil_div(nr, 16)), dim3(256), 0, s, cols, gval, nr,
-                       w, t, u);
+                       w, t, u, order);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }
 
 template <typename T>
 afn_status spmv_gtT(const int64_t *ptr, const int32_t *idx, const T *val, int64_t nr, const T *u,
-                    T *out, hipStream_t s)
+                    T *out, const int32_t *order, hipStream_t s)
 {
     if (nr <= 0) return AFN_OK;
     hipLaunchKernelGGL((spmv_csr<T>), dim3((unsigned)ceil_div(nr, 16)), dim3(256), 0, s, ptr, idx, val, nr,
-                       u, out);
+                       u, out, order);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }
@@ -512,24 +518,24 @@ afn_status gemv_t(const float *A, int64_t lda, int64_t m, int64_t ncols, const f
     return gemv_tT(A, lda, m, ncols, x, base, sign, y, s);
 }
 afn_status spmv_g(const int32_t *cols, const double *gval, int64_t nr, int w, const double *t,
-                  double *u, hipStream_t s)
+                  double *u, const int32_t *order, hipStream_t s)
 {
-    return spmv_gT(cols, gval, nr, w, t, u, s);
+    return spmv_gT(cols, gval, nr, w, t, u, order, s);
 }
 afn_status spmv_g(const int32_t *cols, const float *gval, int64_t nr, int w, const float *t, float *u,
-                  hipStream_t s)
+                  const int32_t *order, hipStream_t s)
 {
-    return spmv_gT(cols, gval, nr, w, t, u, s);
+    return spmv_gT(cols, gval, nr, w, t, u, order, s);
 }
 afn_status spmv_gt(const int64_t *ptr, const int32_t *idx, const double *val, int64_t nr,
-                   const double *u, double *out, hipStream_t s)
+                   const double *u, double *out, const int32_t *order, hipStream_t s)
 {
-    return spmv_gtT(ptr, idx, val, nr, u, out, s);
+    return spmv_gtT(ptr, idx, val, nr, u, out, order, s);
 }
 afn_status spmv_gt(const int64_t *ptr, const int32_t *idx, const float *val, int64_t nr,
-                   const float *u, float *out, hipStream_t s)
+                   const float *u, float *out, const int32_t *order, hipStream_t s)
 {
-    return spmv_gtT(ptr, idx, val, nr, u, out, s);
+    return spmv_gtT(ptr, idx, val, nr, u, out, order, s);
 }
 afn_status pcg_xr_launch(double *x, double *r, const double *p, const double *q, const double *sc,
                          int64_t n, double *part, double *rr_out, hipStream_t s)
