@@ -293,8 +293,11 @@ __device__ __forceinline__ T lanes16_sum4(T (&v)[4], int lane)
 // In a 64 x 64 tile pair, wave w owns rows 16 w .. 16 w + 15 and all 64
 // columns.  Coordinates are centred on the middle of the row tile's box; for
 // each 16-column block one MFMA 16x16x4 per 4 coordinates forms
-// |x_i|^2 + |x_j|^2 - 2 x_i . x_j (the accumulator starts at the two squared
-// norms).  Centring bounds the cancellation: with h2 the squared
+// |x_i|^2 + |x_j|^2 - 2 x_i . x_j: for d < 4 the unused coordinate slot d
+// holds 1 for the rows and |x_j|^2 for the columns, and the row norms are
+// the accumulator input, so no addition per pair is left (d = 4: the
+// accumulator starts at the two norms).  Centring bounds the cancellation:
+// with h2 the squared
 // half-diagonal of the row tile's box, the distance carries an absolute
 // error of about 2 (h2 + (sqrt(t) + sqrt(h2))^2) (d + 2) u, and a row tile
 // with h2 > r2max uses the plain differences instead.
@@ -362,7 +365,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
         for (int t = 0; t < 4 * KC; ++t) {
             const T xc = t < D ? xn[t] - cenS[t] : T(0);
-            cb[buf][t][tid] = T(-2) * xc;
+            cb[buf][t][tid] = t == D ? nrm : T(-2) * xc;
             nrm = fmaT(xc, xc, nrm);
         }
         cn[buf][tid] = nrm;
@@ -396,7 +399,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
             for (int t = 0; t < 4 * KC; ++t) {
                 const T xr = t < D ? Xs[(int64_t)t * npad + q] - cen[t] : T(0);
-                rx[t][tid] = xr;
+                rx[t][tid] = t == D ? T(1) : xr;
                 nrm = fmaT(xr, xr, nrm);
             }
             rn[tid] = nrm;
@@ -411,7 +414,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
                 for (int t = 0; t < 4 * KC; ++t) {
                     const T xc = t < D ? Xs[(int64_t)t * npad + q] - cen[t] : T(0);
-                    cb[tt][t][j] = T(-2) * xc;
+                    cb[tt][t][j] = t == D ? nrm : T(-2) * xc;
                     nrm = fmaT(xc, xc, nrm);
                 }
                 cn[tt][j] = nrm;
@@ -425,12 +428,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         }
         __syncthreads();
         T a[KC], nr[4], vr[4], racc[4];
+        typename M::acc_t nrv;
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc) a[kc] = rx[4 * kc + lg][16 * wave + lc];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int r = 16 * wave + M::row(lane, i);
             nr[i] = rn[r];
+            nrv[i] = nr[i];
             vr[i] = rv[r];
             racc[i] = T(0);
         }
@@ -452,7 +457,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                     for (int m = 0; m < 4; ++m) {
                         const int col = 16 * m + lc;
                         typename M::acc_t c;
-                        if constexpr (MF) {
+                        if constexpr (MF && D < 4 * KC) {
+                            // slot D: 1 x |x_j|^2; the row norms are the accumulator input
+                            c = M::op(a[0], cb[b][lg][col], nrv);
+#pragma unroll
+                            for (int kc = 1; kc < KC; ++kc) c = M::op(a[kc], cb[b][4 * kc + lg][col], c);
+                        } else if constexpr (MF) {
                             const T ncol = cn[b][col];
 #pragma unroll
                             for (int i = 0; i < 4; ++i) c[i] = nr[i] + ncol;
