@@ -167,6 +167,55 @@ __global__ __launch_bounds__(256) void gemv_t_kernel(const T *__restrict__ A, in
     if (lane == 0) y[j] = (base ? base[j] : T(0)) + sign * s;
 }
 
+// The same sums with four columns per wavefront and x staged in LDS (m T
+// values of dynamic LDS): per lane the rows lane, lane + 64, ... of each
+// column in order, then the butterfly, as in gemv_t_kernel; x is read from
+// HBM once per workgroup instead of once per column.
+template <typename T>
+__global__ __launch_bounds__(256) void gemv_t4_kernel(const T *__restrict__ A, int64_t lda, int64_t m,
+                                                      int64_t ncols, const T *__restrict__ x,
+                                                      const T *__restrict__ base, T sign,
+                                                      T *__restrict__ y)
+{
+    extern __shared__ char gemv_smem[];
+    T *xs = reinterpret_cast<T *>(gemv_smem);
+    for (int64_t i = threadIdx.x; i < m; i += 256) xs[i] = x[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t j0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 4;
+    if (j0 >= ncols) return;
+    const int nc = ncols - j0 < 4 ? (int)(ncols - j0) : 4;
+    const T *col[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) col[c] = A + (j0 + (c < nc ? c : nc - 1)) * lda;
+    constexpr int U = 4;
+    T s[4] = {T(0), T(0), T(0), T(0)};
+    int64_t i = lane;
+    for (; i + 64 * (U - 1) < m; i += 64 * U) {
+        T a[4][U];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int u = 0; u < U; ++u) a[c][u] = col[c][i + 64 * u];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const T xv = xs[i + 64 * u];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) s[c] = fmaT(a[c][u], xv, s[c]);
+        }
+    }
+    for (; i < m; i += 64) {
+        const T xv = xs[i];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s[c] = fmaT(col[c][i], xv, s[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const T t = wave_sumT(s[c]);
+        if (c < nc && lane == 0) y[j0 + c] = (base ? base[j0 + c] : T(0)) + sign * t;
+    }
+}
+
 // Sum over the 16 lanes of each lane group (lanes 16 g .. 16 g + 15), a
 // fixed butterfly: every lane of the group ends with the total.
 template <typename T>
@@ -437,8 +486,13 @@ afn_status gemv_tT(const T *A, int64_t lda, int64_t m, int64_t ncols, const T *x
                    T sign, T *y, hipStream_t s)
 {
     if (ncols <= 0) return AFN_OK;
-    hipLaunchKernelGGL((gemv_t_kernel<T>), dim3((unsigned)ceil_div(ncols, 4)), dim3(256), 0, s, A, lda, m,
-                       ncols, x, base, sign, y);
+    const size_t lds = sizeof(T) * (size_t)(m > 0 ? m : 1);
+    if (ncols >= 4096 && lds <= 32768)
+        hipLaunchKernelGGL((gemv_t4_kernel<T>), dim3((unsigned)ceil_div(ncols, 16)), dim3(256), lds, s, A, lda, m,
+                           ncols, x, base, sign, y);
+    else
+        hipLaunchKernelGGL((gemv_t_kernel<T>), dim3((unsigned)ceil_div(ncols, 4)), dim3(256), 0, s, A, lda, m,
+                           ncols, x, base, sign, y);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }
