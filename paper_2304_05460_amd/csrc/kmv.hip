@@ -749,9 +749,8 @@ template <int KIND, int D, typename T, typename VT>
 void launch_mf(dim3 grid, const T *Xs, int64_t npad, int64_t n, const VT *v, const int32_t *perm, const T *box,
                T tcut, T tfar, T r2, int S, int ST, T *part, hipStream_t s)
 {
-    if constexpr (D <= 4)
-        hipLaunchKernelGGL((kmv_sym_mf<KIND, D, T, VT>), grid, dim3(256), 0, s, Xs, npad, n, v, perm, box, tcut, tfar,
-                           r2, S, ST, part);
+    hipLaunchKernelGGL((kmv_sym_mf<KIND, D, T, VT>), grid, dim3(256), 0, s, Xs, npad, n, v, perm, box, tcut, tfar,
+                       r2, S, ST, part);
 }
 
 template <int KIND, typename T, typename VT>
@@ -768,11 +767,7 @@ void launch_sym(int d, dim3 grid, const T *Xs, int64_t npad, int64_t n, const VT
             case 1: launch_mf<KIND, 1, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
             case 2: launch_mf<KIND, 2, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
             case 3: launch_mf<KIND, 3, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
-            case 4: launch_mf<KIND, 4, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
-            case 5: launch_mf<KIND, 5, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
-            case 6: launch_mf<KIND, 6, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
-            case 7: launch_mf<KIND, 7, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
-            default: launch_mf<KIND, 8, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
+            default: launch_mf<KIND, 4, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
         }
         return;
     }

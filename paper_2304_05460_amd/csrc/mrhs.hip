@@ -358,6 +358,9 @@ __device__ __forceinline__ void load4(const T *p, bool whole, int nvalid, int64_
     }
 }
 
+// LDS row strides of gemm_splitk's tiles (A along k, A along i, B).
+constexpr int kGemmLAk = 68, kGemmLAi = 80, kGemmLB = 80;
+
 template <typename T, int NB, bool KF, bool VEC>
 __global__ __launch_bounds__(256) void gemm_splitk(const T *__restrict__ A, int64_t ars, int64_t acs,
                                                    int64_t m, int64_t K, const T *__restrict__ B,
@@ -366,8 +369,8 @@ __global__ __launch_bounds__(256) void gemm_splitk(const T *__restrict__ A, int6
 {
     using M = Mfma<T>;
     constexpr int RP = 16 * NB;
-    constexpr int LA = KF ? 68 : 80;
-    constexpr int LB = 80;
+    constexpr int LA = KF ? kGemmLAk : kGemmLAi;
+    constexpr int LB = kGemmLB;
     __shared__ T As[2][TL * LA];
     __shared__ T Bs[2][TL * LB];
     const int tid = threadIdx.x;
@@ -841,6 +844,49 @@ int gemm_splits(int64_t m, int64_t K)
     return (int)(s < 1 ? 1 : s);
 }
 
+namespace {
+
+// Workgroups of gemm_splitk that fit on one CU by LDS (double-buffered tiles).
+template <typename T>
+int gemm_wgs_per_cu(bool kf)
+{
+    const size_t lds = 2 * (size_t)TL * (kf ? kGemmLAk : kGemmLAi) * sizeof(T) + 2 * (size_t)TL * kGemmLB * sizeof(T);
+    const int per = (int)((160 * 1024) / lds);
+    return per < 1 ? 1 : per;
+}
+
+int device_cus()
+{
+    static const int cus = [] {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            v = 0;
+        return v > 0 ? v : 256;
+    }();
+    return cus;
+}
+
+// Splits of one launch: at most gemm_splits(m, K) (the partial buffers are
+// sized for that), chosen so that the workgroups fill whole rounds of the
+// chip.  The time per row block goes as rounds / splits; take the fewest
+// splits within 2% of the least.
+int gemm_splits_launch(int64_t m, int64_t K, int per_cu)
+{
+    const int smax = gemm_splits(m, K);
+    const int64_t rt = ceil_div(m, TL), cap = (int64_t)device_cus() * per_cu;
+    double best = 1e300;
+    for (int sp = 1; sp <= smax; ++sp) {
+        const double c = (double)ceil_div(rt * sp, cap) / sp;
+        best = c < best ? c : best;
+    }
+    for (int sp = 1; sp <= smax; ++sp)
+        if ((double)ceil_div(rt * sp, cap) / sp <= best * 1.02) return sp;
+    return smax;
+}
+
+}  // namespace
+
 int64_t gemm_part_elems(int64_t m, int64_t K)
 {
     return (int64_t)gemm_splits(m, K) * round_up(m, TL) * 64;
@@ -878,12 +924,12 @@ afn_status gemm_rows(const T *A, int64_t ars, int64_t acs, int64_t m, int64_t K,
 {
     if (m <= 0 || R <= 0) return AFN_OK;
     const int NBk = (R + 15) / 16;
-    const int S = gemm_splits(m, K);
+    // A is read along t when its t stride is 1 (KF), along i otherwise
+    const bool kf = acs == 1;
+    const int S = gemm_splits_launch(m, K, gemm_wgs_per_cu<T>(kf));
     const int64_t kps = round_up(ceil_div(K, S), TL);
     const int64_t mpad = round_up(m, TL);
     dim3 g((unsigned)ceil_div(m, TL), (unsigned)S);
-    // A is read along t when its t stride is 1 (KF), along i otherwise
-    const bool kf = acs == 1;
     const auto al16 = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
     const bool vec = al16(A) && al16(B) && ldb % 4 == 0 && (kf ? ars % 4 == 0 : (ars == 1 && acs % 4 == 0));
     if (kf && vec) launch_gemm<T, true, true>(NBk, g, A, ars, acs, m, K, B, ldb, R, kps, part, mpad, s);
