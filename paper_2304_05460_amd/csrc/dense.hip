@@ -50,25 +50,54 @@ __global__ __launch_bounds__(256) void k12_fill(const double *__restrict__ Xp, i
 // Columns of K12 for the FSAI patterns of rows r0 .. r0+B-1: column
 // c = (q - r0) w + a holds K(x_t, x_{k + cols[q w + a]}) for t < k (the same
 // values k12_fill computes), zero for padding entries (a >= min(q + 1, w)).
-__global__ __launch_bounds__(256) void k12_pattern_fill(const double *__restrict__ Xp, int64_t nr, int k,
-                                                        int d, double l2, int kind,
-                                                        const int32_t *__restrict__ cols,
-                                                        int w, int64_t r0, int64_t B,
-                                                        double *__restrict__ Kb)
+// Tiled: a workgroup takes 256 landmarks and 16 pattern columns, stages the
+// 16 points in LDS and keeps each thread's landmark in registers (d <= D),
+// so a landmark's coordinates are read once per 16 entries and the writes of
+// a column are contiguous.  Same arithmetic as kval, entry for entry.
+template <int D>
+__global__ __launch_bounds__(256) void k12_pattern_fill_tiled(const double *__restrict__ Xp, int64_t nr, int k,
+                                                              int d, double l2, int kind,
+                                                              const int32_t *__restrict__ cols, int w, int64_t r0,
+                                                              int64_t B, double *__restrict__ Kb)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)k * B * w) return;
-    const int64_t c = e / k;
-    const int t = (int)(e - c * k);
-    const int64_t q = r0 + c / w;
-    const int a = (int)(c - (c / w) * w);
-    const int64_t m = q + 1 < w ? q + 1 : w;
-    if (q >= nr || a >= m) {
-        Kb[e] = 0.0;
-        return;
+    constexpr int CB = 16;
+    __shared__ double pts[CB][D];
+    __shared__ int ok[CB];
+    const int64_t ncol = B * w;
+    const int64_t c0 = (int64_t)blockIdx.y * CB;
+    for (int e = threadIdx.x; e < CB * d; e += 256) {
+        const int cc = e / d, t = e - cc * d;
+        const int64_t c = c0 + cc;
+        const int64_t q = r0 + c / w;
+        const int a = (int)(c - (c / w) * w);
+        const int64_t m = q + 1 < w ? q + 1 : w;
+        const bool valid = c < ncol && q < nr && a < m;
+        pts[cc][t] = valid ? Xp[(k + (int64_t)cols[q * w + a]) * d + t] : 0.0;
+        if (t == 0) ok[cc] = valid;
     }
-    const int64_t pt = cols[q * w + a];
-    Kb[e] = kval(Xp + (int64_t)t * d, Xp + (k + pt) * d, d, l2, kind);
+    __syncthreads();
+    const int64_t lt = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (lt >= k) return;
+    double xl[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t) xl[t] = t < d ? Xp[lt * d + t] : 0.0;
+    for (int cc = 0; cc < CB; ++cc) {
+        const int64_t c = c0 + cc;
+        if (c >= ncol) break;
+        double v = 0.0;
+        if (ok[cc]) {
+            double acc = 0.0;
+#pragma unroll
+            for (int t = 0; t < D; ++t) {
+                if (t < d) {
+                    const double del = xl[t] - pts[cc][t];
+                    acc = __builtin_fma(del, del, acc);
+                }
+            }
+            v = kernel_d2(acc, l2, kind);
+        }
+        Kb[c * k + lt] = v;
+    }
 }
 
 // Unblocked Cholesky of the jb x jb diagonal block at (j0, j0), in LDS.
@@ -350,8 +379,15 @@ afn_status fill_k12_patterns(const double *Xp, int64_t n, int k, int d, double l
 {
     const int64_t total = (int64_t)k * B * w;
     if (total <= 0) return AFN_OK;
-    hipLaunchKernelGGL(k12_pattern_fill, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, Xp, n - k, k,
-                       d, l * l, kind, cols, w, r0, B, Kb);
+    const dim3 g((unsigned)ceil_div(k, 256), (unsigned)ceil_div(B * w, 16));
+    const double l2 = l * l;
+    const int64_t nr = n - k;
+    if (d <= 8) hipLaunchKernelGGL(k12_pattern_fill_tiled<8>, g, dim3(256), 0, s, Xp, nr, k, d, l2, kind, cols, w, r0, B, Kb);
+    else if (d <= 16) hipLaunchKernelGGL(k12_pattern_fill_tiled<16>, g, dim3(256), 0, s, Xp, nr, k, d, l2, kind, cols, w, r0, B, Kb);
+    else if (d <= 24) hipLaunchKernelGGL(k12_pattern_fill_tiled<24>, g, dim3(256), 0, s, Xp, nr, k, d, l2, kind, cols, w, r0, B, Kb);
+    else if (d <= 32) hipLaunchKernelGGL(k12_pattern_fill_tiled<32>, g, dim3(256), 0, s, Xp, nr, k, d, l2, kind, cols, w, r0, B, Kb);
+    else if (d <= 48) hipLaunchKernelGGL(k12_pattern_fill_tiled<48>, g, dim3(256), 0, s, Xp, nr, k, d, l2, kind, cols, w, r0, B, Kb);
+    else hipLaunchKernelGGL(k12_pattern_fill_tiled<64>, g, dim3(256), 0, s, Xp, nr, k, d, l2, kind, cols, w, r0, B, Kb);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }
