@@ -371,8 +371,10 @@ __global__ __launch_bounds__(256) void gemm_splitk(const T *__restrict__ A, int6
     constexpr int RP = 16 * NB;
     constexpr int LA = KF ? kGemmLAk : kGemmLAi;
     constexpr int LB = kGemmLB;
-    __shared__ T As[2][TL * LA];
-    __shared__ T Bs[2][TL * LB];
+    // FP64: one LDS buffer (two workgroups per CU), FP32: two
+    constexpr int NBUF = sizeof(T) == 8 ? 1 : 2;
+    __shared__ T As[NBUF][TL * LA];
+    __shared__ T Bs[NBUF][TL * LB];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63, lc = lane & 15, g = lane >> 4;
     const int64_t i0 = (int64_t)blockIdx.x * TL;
@@ -431,9 +433,9 @@ __global__ __launch_bounds__(256) void gemm_splitk(const T *__restrict__ A, int6
         store(0);
         __syncthreads();
         for (int64_t ch = 0; ch < nchunk; ++ch) {
-            const int b = (int)(ch & 1);
-            // the next chunk (past the end: the last one again, staged into
-            // the unused buffer and never read)
+            const int b = NBUF == 1 ? 0 : (int)(ch & 1);
+            // the next chunk (past the end: the last one again, staged and
+            // never read)
             load(t0 + (ch + 1 < nchunk ? ch + 1 : ch) * TL);
 #pragma unroll
             for (int kk = 0; kk < TL / 4; ++kk) {
@@ -442,7 +444,12 @@ __global__ __launch_bounds__(256) void gemm_splitk(const T *__restrict__ A, int6
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) acc[nb] = M::op(a, Bs[b][k * LB + 16 * nb + lc], acc[nb]);
             }
-            store(b ^ 1);
+            if constexpr (NBUF == 1) {
+                __syncthreads();      // every wave is done with the buffer
+                store(0);
+            } else {
+                store(b ^ 1);
+            }
             __syncthreads();
         }
     }
@@ -850,7 +857,8 @@ namespace {
 template <typename T>
 int gemm_wgs_per_cu(bool kf)
 {
-    const size_t lds = 2 * (size_t)TL * (kf ? kGemmLAk : kGemmLAi) * sizeof(T) + 2 * (size_t)TL * kGemmLB * sizeof(T);
+    const size_t nbuf = sizeof(T) == 8 ? 1 : 2;
+    const size_t lds = nbuf * (size_t)TL * (kf ? kGemmLAk : kGemmLAi) * sizeof(T) + nbuf * (size_t)TL * kGemmLB * sizeof(T);
     const int per = (int)((160 * 1024) / lds);
     return per < 1 ? 1 : per;
 }
