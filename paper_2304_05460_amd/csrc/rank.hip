@@ -155,10 +155,12 @@ __global__ __launch_bounds__(256) void scan_update(double *K, int m, const int32
 // H = I - beta v v^T with v supported on rows j+1 .. m-1, kept in one of two
 // buffers (step parity) with beta in sc[0]; the step replaces the trailing
 // block B = A[j+1:, j+1:] by H B H = B - v w^T - w v^T with p = beta B v,
-// K = beta/2 v^T p and w = p - K v.  Each column of B is handled by one
-// wavefront: reads along the column are coalesced, and every sum runs in a
-// fixed order (lane partials in row order, then a butterfly), so the result
-// does not depend on scheduling.  Rows and columns <= j+1 are never read
+// K = beta/2 v^T p and w = p - K v.  Each column of B is handled by two
+// wavefronts (alternate blocks of 64 rows): reads along the column are
+// coalesced, and every sum runs in a fixed order (lane partials in row order,
+// then a butterfly, then the two halves), so the result does not depend on
+// scheduling.  The steps are short and dependent, so a launch issues all its
+// loads that do not wait for the step's reductions at once.  Rows and columns <= j+1 are never read
 // after step j, so the update writes only A[j+2:, j+2:].  The launch of
 // step j also does the product of step j+1: every workgroup forms the
 // updated column j+1 and from it the reflector of step j+1 (the same
@@ -261,106 +263,128 @@ __global__ __launch_bounds__(256) void hh_mv(const double *__restrict__ A, int m
 // p and the nb partials of v^T p of step j.  Out: the reflector of step j+1
 // (vn, scn, off[j+1]; written by workgroup 0), diag[j+1], the updated
 // A[j+2:, j+2:], pn[c] = beta' sum_{i >= j+2} A'[i,c] v'[i] for c >= j+2 and
-// per-workgroup partials partn of v'^T pn (four columns per workgroup, one
-// per wavefront).
-__global__ __launch_bounds__(256) void hh_step(double *__restrict__ A, int m, int j,
+// per-workgroup partials partn of v'^T pn (four columns per workgroup, two
+// wavefronts each).  Dynamic LDS: 3 (m - j - 2) doubles.
+constexpr int kHhPart = 8;     // partials of v^T p per lane loaded up front (nb <= 512)
+constexpr int kHhPre = 4;      // rows of v, p and column j+1 per thread up front (s <= 2048)
+constexpr int kHhCol = 16;     // rows of the wavefront's column per lane up front (s <= 2048)
+
+__global__ __launch_bounds__(512) void hh_step(double *__restrict__ A, int m, int j,
                                                const double *__restrict__ v, const double *__restrict__ sc,
                                                const double *__restrict__ p, const double *__restrict__ part,
                                                int nb, double *__restrict__ vn, double *__restrict__ scn,
                                                double *__restrict__ pn, double *__restrict__ partn,
                                                double *__restrict__ diag, double *__restrict__ off)
 {
-    __shared__ double vl[kMaxM];     // the new reflector, by row (rows >= j+2)
-    __shared__ double red[4];
+    // rows r0 .. m-1 (index i - r0): the new reflector, v, and w = p - K v of step j
+    extern __shared__ double hh_lds[];
+    __shared__ double red[8];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    // K = beta/2 v^T p, every wavefront in the same order
-    double s = 0.0;
-    for (int b0 = lane; b0 < nb; b0 += 64 * kUnroll) {
-        double q[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) q[u] = b0 + 64 * u < nb ? part[b0 + 64 * u] : 0.0;
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) s += q[u];
-    }
-    const double K = 0.5 * sc[0] * wave_sum(s);
-    // the updated column j+1 below the diagonal, and its squared norm
-    const int c1 = j + 1, r0 = j + 2;
-    const double v1 = v[c1], w1 = p[c1] - K * v1;
+    const int c1 = j + 1, r0 = j + 2, s = m - r0;
+    double *vl = hh_lds, *vs = hh_lds + s, *ws = hh_lds + 2 * s;
     const double *col1 = A + (int64_t)c1 * m;
-    double a2 = 0.0;
-    for (int base = r0 + tid; base < m; base += 256 * kUnroll) {
-        double x[kUnroll];
+    // the workgroup's four columns, two wavefronts each (rows r0 + 64 h + 128 u + lane)
+    const int c = r0 + (int)blockIdx.x * 4 + (wv & 3), h = wv >> 2;
+    double *col = c < m ? A + (int64_t)c * m : A;
+    // every load that does not wait for this step's reductions, issued together
+    double q[kHhPart], pv[kHhPre], pp[kHhPre], pc[kHhPre], a[kHhCol];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int i = base + 256 * u;
-            if (i < m) {
-                const double vi = v[i], wi = p[i] - K * vi;
-                x[u] = col1[i] - (vi * w1 + wi * v1);
-            } else {
-                x[u] = 0.0;
-            }
-        }
+    for (int u = 0; u < kHhPart; ++u) q[u] = lane + 64 * u < nb ? part[lane + 64 * u] : 0.0;
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int i = base + 256 * u;
-            if (i < m) vl[i] = x[u];
-            a2 = __builtin_fma(x[u], x[u], a2);
-        }
+    for (int u = 0; u < kHhPre; ++u) {
+        const int i = r0 + tid + 512 * u;
+        pv[u] = i < m ? v[i] : 0.0;
+        pp[u] = i < m ? p[i] : 0.0;
+        pc[u] = i < m ? col1[i] : 0.0;
     }
+#pragma unroll
+    for (int u = 0; u < kHhCol; ++u) {
+        const int i = r0 + 64 * h + lane + 128 * u;
+        a[u] = c < m && i < m ? col[i] : 0.0;
+    }
+    const double v1 = v[c1], p1 = p[c1], d1 = col1[c1];
+    // K = beta/2 v^T p, every wavefront in the same order
+    double sum = 0.0;
+#pragma unroll
+    for (int u = 0; u < kHhPart; ++u) sum += q[u];
+    for (int b0 = lane + 64 * kHhPart; b0 < nb; b0 += 64) sum += part[b0];
+    const double K = 0.5 * sc[0] * wave_sum(sum);
+    // the updated column j+1 below the diagonal, and its squared norm
+    const double w1 = p1 - K * v1;
+    double a2 = 0.0;
+    auto prefix_row = [&](int i, double vi, double pi, double ci) {
+        const double wi = pi - K * vi;
+        const double x = ci - (vi * w1 + wi * v1);
+        vl[i - r0] = x;
+        vs[i - r0] = vi;
+        ws[i - r0] = wi;
+        a2 = __builtin_fma(x, x, a2);
+    };
+#pragma unroll
+    for (int u = 0; u < kHhPre; ++u) {
+        const int i = r0 + tid + 512 * u;
+        if (i < m) prefix_row(i, pv[u], pp[u], pc[u]);
+    }
+    for (int i = r0 + tid + 512 * kHhPre; i < m; i += 512) prefix_row(i, v[i], p[i], col1[i]);
     a2 = wave_sum(a2);
     if (lane == 0) red[wv] = a2;
     __syncthreads();
-    const double x0 = vl[r0];
-    const double alpha = sqrt(((red[0] + red[1]) + red[2]) + red[3]);
+    const double x0 = vl[0];
+    const double alpha = sqrt(((((((red[0] + red[1]) + red[2]) + red[3]) + red[4]) + red[5]) + red[6]) + red[7]);
     const double snew = x0 >= 0.0 ? -alpha : alpha;
     const double vn2 = 2.0 * alpha * (alpha + fabs(x0));
     const double beta1 = alpha == 0.0 || !(vn2 > 0.0) ? 0.0 : 2.0 / vn2;
-    __syncthreads();    // x0 read everywhere before it is replaced
-    if (tid == 0) vl[r0] = x0 - snew;
+    __syncthreads();    // x0 and red[] read everywhere before they are replaced
+    if (tid == 0) vl[0] = x0 - snew;
     __syncthreads();
     if (blockIdx.x == 0) {
-        for (int i = r0 + tid; i < m; i += 256) vn[i] = vl[i];
+        for (int i = tid; i < s; i += 512) vn[r0 + i] = vl[i];
         if (tid == 0) {
             scn[0] = beta1;
             off[c1] = snew;
-            diag[c1] = col1[c1] - (v1 * w1 + w1 * v1);
+            diag[c1] = d1 - (v1 * w1 + w1 * v1);
         }
     }
-    // the workgroup's columns: update, then the product with the new reflector
-    const int c = r0 + (int)blockIdx.x * 4 + wv;
-    double dotc = 0.0;
+    // the columns: update, then the product with the new reflector
+    double acc = 0.0;
     if (c < m) {
-        const double vc = v[c], wc = p[c] - K * vc;
-        double *col = A + (int64_t)c * m;
-        double acc = 0.0;
-        for (int base = r0 + lane; base < m; base += 64 * kUnroll) {
-            double a[kUnroll], vv[kUnroll], pp[kUnroll];
+        const double vc = vs[c - r0], wc = ws[c - r0];
+        auto col_row = [&](int i, double ai) {
+            const double x = ai - (vs[i - r0] * wc + ws[i - r0] * vc);
+            col[i] = x;
+            if (i == c) diag[c] = x;
+            acc = __builtin_fma(x, vl[i - r0], acc);
+        };
+#pragma unroll
+        for (int u = 0; u < kHhCol; ++u) {
+            const int i = r0 + 64 * h + lane + 128 * u;
+            if (i < m) col_row(i, a[u]);
+        }
+        for (int base = r0 + 64 * h + lane + 128 * kHhCol; base < m; base += 128 * kUnroll) {
+            double b[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const int i = base + 64 * u;
-                a[u] = i < m ? col[i] : 0.0;
-                vv[u] = i < m ? v[i] : 0.0;
-                pp[u] = i < m ? p[i] : 0.0;
+                const int i = base + 128 * u;
+                b[u] = i < m ? col[i] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const int i = base + 64 * u;
-                if (i < m) {
-                    const double wi = pp[u] - K * vv[u];
-                    const double x = a[u] - (vv[u] * wc + wi * vc);
-                    col[i] = x;
-                    if (i == c) diag[c] = x;
-                    acc = __builtin_fma(x, vl[i], acc);
-                }
+                const int i = base + 128 * u;
+                if (i < m) col_row(i, b[u]);
             }
         }
-        acc = wave_sum(acc);
-        const double pc = beta1 * acc;
-        if (lane == 0) pn[c] = pc;
-        dotc = vl[c] * pc;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) red[wv] = acc;
+    __syncthreads();
+    double dotc = 0.0;
+    if (h == 0 && c < m) {
+        const double pcn = beta1 * (red[wv] + red[wv + 4]);
+        if (lane == 0) pn[c] = pcn;
+        dotc = vl[c - r0] * pcn;
     }
     __syncthreads();    // red[] reused
-    if (lane == 0) red[wv] = dotc;
+    if (lane == 0 && h == 0) red[wv] = dotc;
     __syncthreads();
     if (tid == 0) partn[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
@@ -495,12 +519,17 @@ afn_status rank_estimate(const double *X, int64_t n, int d, double l, int kind, 
         if (m >= 3)
             hipLaunchKernelGGL(hh_mv, dim3((unsigned)ceil_div(m - 1, 4)), dim3(256), 0, s, K, m, 0, v, sc, pw,
                                gp);
+        const size_t hh_lds_max = 3 * sizeof(double) * (size_t)(m - 2);
+        if (hh_lds_max > 64 * 1024)
+            AFN_HIP(hipFuncSetAttribute((const void *)hh_step, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)hh_lds_max));
         // step j reads buffer set j & 1 (v, beta, p, partials) and writes the other
         for (int j = 0; j + 2 < m; ++j) {
             const int nb = (int)ceil_div(m - j - 1, 4);         // workgroups of the previous launch
             const int nbn = (int)ceil_div(m - j - 2, 4);        // of this one (>= 1: j + 2 < m)
             const int cur = j & 1, nxt = cur ^ 1;
-            hipLaunchKernelGGL(hh_step, dim3((unsigned)nbn), dim3(256), 0, s, K, m, j, v + (int64_t)cur * m,
+            const size_t lds = 3 * sizeof(double) * (size_t)(m - j - 2);
+            hipLaunchKernelGGL(hh_step, dim3((unsigned)nbn), dim3(512), lds, s, K, m, j, v + (int64_t)cur * m,
                                sc + 4 * cur, pw + (int64_t)cur * m, gp + cur * gps, nb, v + (int64_t)nxt * m,
                                sc + 4 * nxt, pw + (int64_t)nxt * m, gp + nxt * gps, tdiag, toff);
         }

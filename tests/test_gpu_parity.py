@@ -434,6 +434,20 @@ def test_rank_estimate_matches_oracle(afn, l):
     np.testing.assert_array_equal(h.landmarks(), idx)
 
 
+def test_rank_estimate_largest_subsample(afn):
+    # m at its maximum: the tridiagonalization's LDS per launch (3 (m - j - 2)
+    # doubles) exceeds 64 KB in the first steps
+    n, m, l = 6000, 4096, 1.0
+    X = W.points("mixture5", n, 3, 33)
+    say(f"rank m={m}")
+    h = afn.afn_setup(dev(X), l, 1e-3, k=-1, w=16, k_max=2000, m=m, seed=99)
+    inf = h.info()
+    ko, info = oracle.rank_estimate(X, l, 1e-3, m, kmax=2000, kswitch=2000, seed=99)
+    say("gpu", inf.k, inf.rank_r, inf.rank_eig_count, "oracle", ko, info)
+    assert inf.rank_r == info[0] and inf.rank_eig_branch == info[2] == 1
+    assert inf.k == ko
+
+
 # ------------------------------------------------------------------ failures
 
 def test_setup_errors(afn):
