@@ -13,9 +13,10 @@
 // kernel value is 2^-cut.
 //
 // 2^(-t) in FP64 (t >= 0): t clamped to 2000 (the result underflows long
-// before), k = rint(t) from c - t with c = 1.5 * 2^52 (ulp 1 there, so the
-// subtraction rounds t to the nearest integer, ties to even, and the low word
-// of c - t is -k as a 32-bit integer), f = k - t in [-1/2, 1/2] exactly, and
+// before; the bounded form leaves that to its caller), k = rint(t) from
+// c - t with c = 1.5 * 2^52 (ulp 1 there, so the subtraction rounds t to
+// the nearest integer, ties to even, and the low word of c - t is -k as a
+// 32-bit integer), f = k - t in [-1/2, 1/2] exactly, and
 // 2^(-t) = p(f) 2^(-k) with p the degree-11 polynomial interpolating 2^f at
 // the Chebyshev nodes of [-1/2, 1/2] (interpolation error 4.4e-18 relative;
 // Horner in FP64 <= 1.7 ulp).  No FP64 round or convert instruction (both
@@ -31,9 +32,11 @@ namespace afn {
 
 constexpr double kLn2 = 0.6931471805599453;
 
-__device__ __forceinline__ double exp2_neg(double t)
+// 2^(-t) for t < 2^31 (also slightly below 0, from rounding): the caller
+// bounds t, so no clamp (whose minimum on an MFMA result also costs a NaN
+// canonicalization) is needed.
+__device__ __forceinline__ double exp2_neg_bounded(double t)
 {
-    t = t < 2000.0 ? t : 2000.0;
     const double kb = 6755399441055744.0 - t;
     const double kd = 6755399441055744.0 - kb;
     const double f = kd - t;
@@ -52,7 +55,10 @@ __device__ __forceinline__ double exp2_neg(double t)
     return __builtin_ldexp(p, __double2loint(kb));
 }
 
+__device__ __forceinline__ double exp2_neg(double t) { return exp2_neg_bounded(t < 2000.0 ? t : 2000.0); }
+
 __device__ __forceinline__ float exp2_neg(float t) { return __builtin_amdgcn_exp2f(-t); }
+__device__ __forceinline__ float exp2_neg_bounded(float t) { return exp2_neg(t); }
 
 __device__ __forceinline__ double sqrtT(double x) { return __builtin_sqrt(x); }
 __device__ __forceinline__ float sqrtT(float x) { return __builtin_sqrtf(x); }
@@ -66,6 +72,19 @@ __device__ __forceinline__ T kernel_scaled(T t)
         return (T(1) + s * T(kLn2)) * exp2_neg(s);
     } else {
         return exp2_neg(t);
+    }
+}
+
+// kernel_scaled without the clamp, for t below 2^31 (Gaussian) or 2^62
+// (Matern, whose exponent is sqrt(t)).
+template <int KIND, typename T>
+__device__ __forceinline__ T kernel_scaled_bounded(T t)
+{
+    if constexpr (KIND == AFN_KERNEL_MATERN32) {
+        const T s = sqrtT(t);
+        return (T(1) + s * T(kLn2)) * exp2_neg_bounded(s);
+    } else {
+        return exp2_neg_bounded(t);
     }
 }
 

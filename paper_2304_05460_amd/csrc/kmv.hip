@@ -33,6 +33,9 @@ constexpr int kMaxSTmf = 8;     // MFMA variant (per-wave column accumulators in
 // Largest squared half-diagonal (scaled units) of a row tile whose distances
 // the MFMA variant forms from norms and dot products.
 constexpr double kCentredR2Max = 16.0;
+// Tile pairs whose largest squared distance (scaled units) is below this take
+// the FP64 exponential without its clamp (valid for t < 2^31).
+constexpr double kBoundedT = 1073741824.0;
 
 // Xs[t * npad + q] = X[perm[q]*d + t] * scale for q < n (perm may be null:
 // identity), 0 beyond (rounded to T).
@@ -89,6 +92,21 @@ __device__ __forceinline__ T box_gap2(const T *__restrict__ box, int64_t a, int6
         g2 = fmaT(gap, gap, g2);
     }
     return g2;
+}
+
+// Largest squared distance between a point of box a and one of box b.
+template <int D, typename T>
+__device__ __forceinline__ T box_span2(const T *__restrict__ box, int64_t a, int64_t b)
+{
+    T s2 = T(0);
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        const T alo = box[(a * D + t) * 2], ahi = box[(a * D + t) * 2 + 1];
+        const T blo = box[(b * D + t) * 2], bhi = box[(b * D + t) * 2 + 1];
+        const T span = (ahi > bhi ? ahi : bhi) - (alo < blo ? alo : blo);
+        s2 = fmaT(span, span, s2);
+    }
+    return s2;
 }
 
 __device__ __forceinline__ void decode_pair(int q, int S, int &BI, int &BJ)
@@ -341,9 +359,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     for (int e = tid; e < 4 * kMaxSTmf * kTile; e += 256) (&colacc[0][0][0])[e] = T(0);
     if (tid < ST * ST)
     {
-        // 0: skipped, 1: evaluated, 2: evaluated with the exponential in FP32
-        const T g2 = box_gap2<D, T>(box, (int64_t)BI * ST + tid / ST, (int64_t)BJ * ST + tid % ST);
-        keep[tid] = g2 < tcut ? (g2 >= tfar ? 2 : 1) : 0;
+        // 0: skipped, 1: evaluated (every t below kBoundedT), 2: evaluated with
+        // the exponential in FP32, 3: evaluated (larger t possible).  The
+        // padding points of a partly filled tile (packed at the origin) lie
+        // outside its box, so its pairs are never 1.
+        const int64_t a = (int64_t)BI * ST + tid / ST, b = (int64_t)BJ * ST + tid % ST;
+        const T g2 = box_gap2<D, T>(box, a, b);
+        const bool full = (a + 1) * kTile <= n && (b + 1) * kTile <= n;
+        const bool bounded = full && box_span2<D, T>(box, a, b) < T(kBoundedT);
+        keep[tid] = g2 < tcut ? (g2 >= tfar ? 2 : (bounded ? 1 : 3)) : 0;
     }
     T *rowout = part + (int64_t)blockIdx.x * 2 * SB;
     T *colout = rowout + SB;
@@ -451,8 +475,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 const int b = STAGE_ALL ? tj : nb;
                 T cacc[4];
                 // per 16-column block: the distances, then the kernel values
-                auto values = [&](auto far_tag) {
+                auto values = [&](auto far_tag, auto bounded_tag) {
                     constexpr bool FAR = decltype(far_tag)::value;
+                    constexpr bool BOUNDED = decltype(bounded_tag)::value;
 #pragma unroll
                     for (int m = 0; m < 4; ++m) {
                         const int col = 16 * m + lc;
@@ -491,6 +516,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                             if constexpr (KIND == AFN_KERNEL_MATERN32) t2 = t2 > T(0) ? t2 : T(0);
                             T kij;
                             if constexpr (FAR) kij = (T)kernel_scaled<KIND, float>((float)t2);
+                            else if constexpr (BOUNDED) kij = kernel_scaled_bounded<KIND, T>(t2);
                             else kij = kernel_scaled<KIND, T>(t2);
                             racc[i] = fmaT(kij, vcol, racc[i]);
                             cacc[m] = fmaT(kij, vr[i], cacc[m]);
@@ -499,11 +525,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 };
                 // far tile pairs (FP64 only): every value is below 2^-kFarF64,
                 // and the FP32 exponential is within 2^-64 |v_j| of it
+                // the clamp-free exponential where the tile boxes bound t
                 if constexpr (sizeof(T) == 8) {
-                    if (keep[ti * ST + tj] == 2) values(std::true_type{});
-                    else values(std::false_type{});
+                    const int kt = keep[ti * ST + tj];
+                    if (kt == 2) values(std::true_type{}, std::false_type{});
+                    else if (kt == 1) values(std::false_type{}, std::true_type{});
+                    else values(std::false_type{}, std::false_type{});
                 } else {
-                    values(std::false_type{});
+                    values(std::false_type{}, std::false_type{});
                 }
                 if (!(diag_super && tj == ti)) colacc[wave][tj][lane] += groups4_sum(cacc, lane);
                 if constexpr (!STAGE_ALL) {

@@ -100,3 +100,34 @@ def test_matvec_sweep(afn, i, n, d, pts, l, kernel, nrhs):
             worst = max(worst, float(np.max(err / bound)))
             assert np.all(err <= bound), (prec, c, float(np.max(err / bound)))
         print(f"  prec={prec}: worst err/bound {worst:.3f}", flush=True)
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("n", [5000, 20000])
+def test_matvec_far_from_origin(afn, kernel, n):
+    """Points far from the origin: the padding points of the last, partly
+    filled tile (packed at the origin) are then far from every point, and the
+    FP64 kernel must take its clamped exponential for those tile pairs."""
+    d, l = 3, 0.05
+    print(f"far from origin: n={n} kernel={kernel}", flush=True)
+    X = W.points("mixture5", n, d, 77) + np.array([1.0e4, -3.0e4, 2.0e4])
+    V = np.random.default_rng(78).standard_normal((n, 1))
+    rows = np.concatenate([np.arange(3), np.random.default_rng(79).integers(0, n, 25), [n - 1]])
+    with oracle.use_kernel("matern32" if kernel else "gaussian"):
+        yo, ab = oracle.kernel_matvec_rows(X, l, 1e-3, V[:, 0], rows)
+    xm = float(np.abs(X - X.mean(0)).max())
+    for prec in (afn.AFN_FP64, afn.AFN_FP32):
+        Y = afn.kernel_matvec(dev(X), l, 1e-3, dev(V), precision=prec, kernel=kernel).cpu().numpy()
+        assert np.all(np.isfinite(Y))
+        err = np.abs(Y[rows, 0] - yo)
+        vs = np.abs(V[:, 0]).sum()
+        fp64 = prec == afn.AFN_FP64
+        # coordinates of magnitude |x| lose |x| u each when stored: the term
+        # bound of the sweep with xm the largest coordinate
+        r = term_rel(kernel, fp64, d, float(np.abs(X).max()), l)
+        if fp64:
+            bound = (2 * (n + 4) + r) * U * ab + 2.0 ** -64 * vs
+        else:
+            bound = (n + 8 + r) * U32 * ab + (1e-13 + 2.0 ** -44) * vs
+        print(f"  prec={prec}: worst err/bound {float(np.max(err / bound)):.3f} (xm {xm:.3g})", flush=True)
+        assert np.all(err <= bound)
