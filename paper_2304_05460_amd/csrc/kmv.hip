@@ -37,19 +37,22 @@ constexpr double kCentredR2Max = 16.0;
 // the FP64 exponential without its clamp (valid for t < 2^31).
 constexpr double kBoundedT = 1073741824.0;
 
-// Xs[t * npad + q] = X[perm[q]*d + t] * scale for q < n (perm may be null:
-// identity), 0 beyond (rounded to T).
+// Xs[t * npad + q] = (X[perm[q]*d + t] - X[perm[0]*d + t]) * scale for q < n
+// (perm may be null: identity), 0 beyond (rounded to T).  The kernel depends
+// on differences only; with the first packed point as the origin, FP32
+// storage keeps its precision for points far from the origin.
 template <typename T>
 __global__ __launch_bounds__(256) void pack_scaled(const double *__restrict__ X,
                                                    const int32_t *__restrict__ perm, int64_t n, int d,
                                                    int64_t npad, double scale, T *__restrict__ Xs)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= npad * d) return;
+    if (e >= npad * d || n < 1) return;
     const int t = (int)(e / npad);
     const int64_t q = e - (int64_t)t * npad;
     const int64_t i = q < n ? (perm ? (int64_t)perm[q] : q) : 0;
-    Xs[e] = (T)(q < n ? X[i * d + t] * scale : 0.0);
+    const int64_t i0 = perm ? (int64_t)perm[0] : 0;
+    Xs[e] = (T)(q < n ? (X[i * d + t] - X[i0 * d + t]) * scale : 0.0);
 }
 
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }

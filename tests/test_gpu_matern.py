@@ -62,7 +62,9 @@ def term_error(X, l, S):
     """Per-term relative error of the tile kernels' Matern value (in units of u)."""
     d = X.shape[1]
     c = math.sqrt(3.0) * LOG2E / l
-    return LN2 * (S * (d + 4) / 2 + math.sqrt(d) * np.abs(X).max() * c) + 8
+    # coordinates packed relative to a data point, with up to 2 u each
+    spread = float((X.max(0) - X.min(0)).max())
+    return LN2 * (S * (d + 4) / 2 + 4 * math.sqrt(d) * spread * c) + 8
 
 
 def bound64(X, l, v, ab):

@@ -10,11 +10,12 @@ Bound per row i (u the unit roundoff of the precision, ab_i = sum_j |K_ij v_j|
   FP32   (n + 8 + r) u ab_i + (1e-13 + 2^-44) sum_j |v_j|
 The last terms cover the skipped tile pairs (every value there is below 2^-64,
 resp. 2^-44) and the FP64 pairs whose value is taken in FP32 (below 2^-46).
-r has three parts (c the coordinate scale of the kind, xm = max |x|):
-  - the stored coordinates x c (1 + e), |e| <= u: each coordinate difference
-    is off by at most 2 xm c u, so t by 2 sqrt(t d) 2 xm c u; the Gaussian
-    2^(-t) moves by ln 2 dt relative (t <= 64), the Matern value by at most
-    ln 2 ds with ds <= 2 sqrt(d) xm c u;
+r has three parts (c the coordinate scale of the kind, xm the largest
+spread max - min of a coordinate):
+  - the stored coordinates (x - x0) c (1 + e), |e| <= 2 u, relative to a
+    data point x0: each coordinate difference is off by at most 4 xm c u, so
+    t by 2 sqrt(t d) 4 xm c u; the Gaussian 2^(-t) moves by ln 2 dt relative
+    (t <= 64), the Matern value by at most ln 2 ds with ds <= 4 sqrt(d) xm c u;
   - t itself, direct or from norms and dot products of centred coordinates
     (centred radius^2 <= 16): 64 (d + 4) u absolute for the Gaussian, s (d + 4) / 2
     relative in s for the Matern kernel (s <= 66 in FP64, 50 in FP32);
@@ -52,10 +53,14 @@ def dev(a):
 def term_rel(kernel, fp64, d, xm, l):
     if kernel == 0:
         c = math.sqrt(LOG2E) / l
-        return LN2 * (64 * (d + 4) + 4 * math.sqrt(64 * d) * xm * c) + 8
+        return LN2 * (64 * (d + 4) + 8 * math.sqrt(64 * d) * xm * c) + 8
     c = math.sqrt(3.0) * LOG2E / l
     smax = 66 if fp64 else 50
-    return LN2 * (smax * (d + 4) / 2 + 2 * math.sqrt(d) * xm * c) + 8
+    return LN2 * (smax * (d + 4) / 2 + 4 * math.sqrt(d) * xm * c) + 8
+
+
+def spread(X):
+    return float((X.max(0) - X.min(0)).max())
 
 
 def cases():
@@ -83,7 +88,7 @@ def test_matvec_sweep(afn, i, n, d, pts, l, kernel, nrhs):
     Vd = torch.tensor(V.T.copy(), device="cuda").t()
     with oracle.use_kernel("matern32" if kernel else "gaussian"):
         ref = [oracle.kernel_matvec_rows(X, l, 1e-3, V[:, c], rows) for c in range(nrhs)]
-    xm = float(np.abs(X).max())
+    xm = spread(X)
     for prec in (afn.AFN_FP64, afn.AFN_FP32):
         Y = afn.kernel_matvec(dev(X), l, 1e-3, Vd, precision=prec, kernel=kernel).cpu().numpy()
         fp64 = prec == afn.AFN_FP64
@@ -105,9 +110,11 @@ def test_matvec_sweep(afn, i, n, d, pts, l, kernel, nrhs):
 @pytest.mark.parametrize("kernel", [0, 1])
 @pytest.mark.parametrize("n", [5000, 20000])
 def test_matvec_far_from_origin(afn, kernel, n):
-    """Points far from the origin: the padding points of the last, partly
-    filled tile (packed at the origin) are then far from every point, and the
-    FP64 kernel must take its clamped exponential for those tile pairs."""
+    """Points far from the origin.  The packed coordinates are relative to a
+    data point, so the FP32 copies keep their precision (absolute coordinates
+    of 3e4 at l = 0.05 would put a few percent of error into every kernel
+    value), and the padding points of the last, partly filled tile must not
+    break the FP64 kernel's choice of exponential."""
     d, l = 3, 0.05
     print(f"far from origin: n={n} kernel={kernel}", flush=True)
     X = W.points("mixture5", n, d, 77) + np.array([1.0e4, -3.0e4, 2.0e4])
@@ -115,19 +122,18 @@ def test_matvec_far_from_origin(afn, kernel, n):
     rows = np.concatenate([np.arange(3), np.random.default_rng(79).integers(0, n, 25), [n - 1]])
     with oracle.use_kernel("matern32" if kernel else "gaussian"):
         yo, ab = oracle.kernel_matvec_rows(X, l, 1e-3, V[:, 0], rows)
-    xm = float(np.abs(X - X.mean(0)).max())
     for prec in (afn.AFN_FP64, afn.AFN_FP32):
         Y = afn.kernel_matvec(dev(X), l, 1e-3, dev(V), precision=prec, kernel=kernel).cpu().numpy()
         assert np.all(np.isfinite(Y))
         err = np.abs(Y[rows, 0] - yo)
         vs = np.abs(V[:, 0]).sum()
         fp64 = prec == afn.AFN_FP64
-        # coordinates of magnitude |x| lose |x| u each when stored: the term
-        # bound of the sweep with xm the largest coordinate
-        r = term_rel(kernel, fp64, d, float(np.abs(X).max()), l)
+        # packed relative to a data point: the spread, not the offset,
+        # sets the storage error, in both precisions
+        r = term_rel(kernel, fp64, d, spread(X), l)
         if fp64:
             bound = (2 * (n + 4) + r) * U * ab + 2.0 ** -64 * vs
         else:
             bound = (n + 8 + r) * U32 * ab + (1e-13 + 2.0 ** -44) * vs
-        print(f"  prec={prec}: worst err/bound {float(np.max(err / bound)):.3f} (xm {xm:.3g})", flush=True)
+        print(f"  prec={prec}: worst err/bound {float(np.max(err / bound)):.3f}", flush=True)
         assert np.all(err <= bound)
