@@ -34,12 +34,12 @@ VALU_F64_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # VALU instructions per unique kernel evaluation in the tile-pair loop of
 # kmv_sym_mf<0, 3, double, double> (AMD assembly of this build, per lane and
 # tile pair, i.e. per 16 pairs, besides 4 MFMAs that also add the squared
-# norms): 277 where the software FP64 2^-t runs (15 instructions per
-# exponential, 2 FMAs for the row and column products; tile pairs whose boxes
-# bound t), 80 on tile pairs whose values are all below 2^-46 (FP32
-# exponential), and 26 for the column sums across lane groups and the loop
-# itself.
-VALU_F64_OPS_PER_PAIR_D3 = (277 + 26) / 16
+# norms): 245 where the software FP64 2^-t runs (13 instructions per
+# table-driven exponential plus one LDS read, 2 FMAs for the row and column
+# products; tile pairs whose boxes bound t), 80 on tile pairs whose values are
+# all below 2^-46 (FP32 exponential), and 26 for the column sums across lane
+# groups and the loop itself.
+VALU_F64_OPS_PER_PAIR_D3 = (245 + 26) / 16
 VALU_F64_OPS_PER_FAR_PAIR_D3 = (80 + 26) / 16
 
 

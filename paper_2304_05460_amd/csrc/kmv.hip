@@ -34,25 +34,48 @@ constexpr int kMaxSTmf = 8;     // MFMA variant (per-wave column accumulators in
 // the MFMA variant forms from norms and dot products.
 constexpr double kCentredR2Max = 16.0;
 // Tile pairs whose largest squared distance (scaled units) is below this take
-// the FP64 exponential without its clamp (valid for t < 2^31).
-constexpr double kBoundedT = 1073741824.0;
+// the table-driven FP64 exponential (valid for t < 2^25) without a clamp.
+constexpr double kBoundedT = 16777216.0;
 
-// Xs[t * npad + q] = (X[perm[q]*d + t] - X[perm[0]*d + t]) * scale for q < n
-// (perm may be null: identity), 0 beyond (rounded to T).  The kernel depends
-// on differences only; with the first packed point as the origin, FP32
-// storage keeps its precision for points far from the origin.
+constexpr int kOriginSample = 255;
+
+// Xs[t * npad + q] = (X[perm[q]*d + t] - o_t) * scale for q < n (perm may be
+// null: identity), 0 beyond (rounded to T); grid (ceil(npad / 256), d).  o_t
+// is the median of coordinate t over kOriginSample points at a fixed stride
+// of the packed order (all points if fewer), found by each workgroup for
+// itself.  The kernel depends on differences only; with the origin inside
+// the bulk of the points, FP32 copies keep their precision for data far from
+// the origin, and outliers do not move it.
 template <typename T>
 __global__ __launch_bounds__(256) void pack_scaled(const double *__restrict__ X,
                                                    const int32_t *__restrict__ perm, int64_t n, int d,
                                                    int64_t npad, double scale, T *__restrict__ Xs)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= npad * d || n < 1) return;
-    const int t = (int)(e / npad);
-    const int64_t q = e - (int64_t)t * npad;
+    __shared__ double smp[kOriginSample];
+    __shared__ double org;
+    const int t = (int)blockIdx.y, tid = (int)threadIdx.x;
+    const int ns = n < kOriginSample ? (int)n : kOriginSample;
+    if (tid == 0) org = 0.0;
+    if (tid < ns) {
+        const int64_t q = (int64_t)tid * n / ns;
+        smp[tid] = X[(perm ? (int64_t)perm[q] : q) * d + t];
+    }
+    __syncthreads();
+    if (tid < ns) {
+        // rank in the order (value, sample index): the middle one is the median
+        const double x = smp[tid];
+        int rank = 0;
+        for (int k = 0; k < ns; ++k) {
+            const double y = smp[k];
+            rank += y < x || (y == x && k < tid) ? 1 : 0;
+        }
+        if (rank == ns / 2) org = x;
+    }
+    __syncthreads();
+    const int64_t q = (int64_t)blockIdx.x * 256 + tid;
+    if (q >= npad) return;
     const int64_t i = q < n ? (perm ? (int64_t)perm[q] : q) : 0;
-    const int64_t i0 = perm ? (int64_t)perm[0] : 0;
-    Xs[e] = (T)(q < n ? (X[i * d + t] - X[i0 * d + t]) * scale : 0.0);
+    Xs[(int64_t)t * npad + q] = (T)(q < n ? (X[i * d + t] - org) * scale : 0.0);
 }
 
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -352,6 +375,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     __shared__ T colacc[4][kMaxSTmf][kTile];  // per-wave column partial sums
     __shared__ unsigned char keep[kMaxSTmf * kMaxSTmf];
     __shared__ T cenS[D];                   // the row tile's box centre, for store_col
+    __shared__ T etab[sizeof(T) == 8 ? 64 : 1];   // 2^(j/64) for the FP64 exponential
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int lc = lane & 15, lg = lane >> 4;
@@ -360,6 +384,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int64_t SB = (int64_t)ST * kTile;
     const bool diag_super = BI == BJ;
     for (int e = tid; e < 4 * kMaxSTmf * kTile; e += 256) (&colacc[0][0][0])[e] = T(0);
+    if constexpr (sizeof(T) == 8) {
+        if (tid < 64) etab[tid] = kExp2Tab64[tid];
+    }
     if (tid < ST * ST)
     {
         // 0: skipped, 1: evaluated (every t below kBoundedT), 2: evaluated with
@@ -415,6 +442,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             continue;
         }
         const bool use_mf = h2 <= r2max;
+        // plain differences (a wide row tile): the stored coordinates, relative
+        // to the packing origin, and not to a box centre that an outlier in
+        // the tile may put far from its other points
+        if (!use_mf) {
+#pragma unroll
+            for (int t = 0; t < D; ++t) cen[t] = T(0);
+        }
         // every read of cenS (store_col) is followed by a barrier
         if (tid < D) cenS[tid] = cen[tid];
         __syncthreads();      // the previous row tile's readers are done
@@ -519,7 +553,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                             if constexpr (KIND == AFN_KERNEL_MATERN32) t2 = t2 > T(0) ? t2 : T(0);
                             T kij;
                             if constexpr (FAR) kij = (T)kernel_scaled<KIND, float>((float)t2);
-                            else if constexpr (BOUNDED) kij = kernel_scaled_bounded<KIND, T>(t2);
+                            else if constexpr (BOUNDED) kij = kernel_scaled_tab<KIND, T>(t2, etab);
                             else kij = kernel_scaled<KIND, T>(t2);
                             racc[i] = fmaT(kij, vcol, racc[i]);
                             cacc[m] = fmaT(kij, vr[i], cacc[m]);
@@ -880,10 +914,10 @@ afn_status kmv_pack(const double *X, int64_t n, int d, double l, int kind, void 
     const SymShape sh = sym_shape(n, d);
     const double scale = kernel_scale(kind, l);
     if (f32)
-        hipLaunchKernelGGL(pack_scaled<float>, dim3((unsigned)ceil_div(sh.npad * d, 256)), dim3(256), 0, s,
+        hipLaunchKernelGGL(pack_scaled<float>, dim3((unsigned)ceil_div(sh.npad, 256), (unsigned)d), dim3(256), 0, s,
                            X, perm, n, d, sh.npad, scale, (float *)Xs);
     else
-        hipLaunchKernelGGL(pack_scaled<double>, dim3((unsigned)ceil_div(sh.npad * d, 256)), dim3(256), 0, s,
+        hipLaunchKernelGGL(pack_scaled<double>, dim3((unsigned)ceil_div(sh.npad, 256), (unsigned)d), dim3(256), 0, s,
                            X, perm, n, d, sh.npad, scale, (double *)Xs);
     AFN_HIP(hipGetLastError());
     return AFN_OK;

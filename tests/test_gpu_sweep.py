@@ -12,8 +12,8 @@ The last terms cover the skipped tile pairs (every value there is below 2^-64,
 resp. 2^-44) and the FP64 pairs whose value is taken in FP32 (below 2^-46).
 r has three parts (c the coordinate scale of the kind, xm the largest
 spread max - min of a coordinate):
-  - the stored coordinates (x - x0) c (1 + e), |e| <= 2 u, relative to a
-    data point x0: each coordinate difference is off by at most 4 xm c u, so
+  - the stored coordinates (x - x0) c (1 + e), |e| <= 2 u, relative to an
+    origin x0 whose every coordinate is one of the data's: each coordinate difference is off by at most 4 xm c u, so
     t by 2 sqrt(t d) 4 xm c u; the Gaussian 2^(-t) moves by ln 2 dt relative
     (t <= 64), the Matern value by at most ln 2 ds with ds <= 4 sqrt(d) xm c u;
   - t itself, direct or from norms and dot products of centred coordinates
@@ -111,7 +111,7 @@ def test_matvec_sweep(afn, i, n, d, pts, l, kernel, nrhs):
 @pytest.mark.parametrize("n", [5000, 20000])
 def test_matvec_far_from_origin(afn, kernel, n):
     """Points far from the origin.  The packed coordinates are relative to a
-    data point, so the FP32 copies keep their precision (absolute coordinates
+    median of the data, so the FP32 copies keep their precision (absolute coordinates
     of 3e4 at l = 0.05 would put a few percent of error into every kernel
     value), and the padding points of the last, partly filled tile must not
     break the FP64 kernel's choice of exponential."""
@@ -135,5 +135,39 @@ def test_matvec_far_from_origin(afn, kernel, n):
             bound = (2 * (n + 4) + r) * U * ab + 2.0 ** -64 * vs
         else:
             bound = (n + 8 + r) * U32 * ab + (1e-13 + 2.0 ** -44) * vs
+        print(f"  prec={prec}: worst err/bound {float(np.max(err / bound)):.3f}", flush=True)
+        assert np.all(err <= bound)
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_matvec_outliers(afn, kernel):
+    """A mixture with 300 points moved 1e2 .. 1e6 away.  Tiles that hold both
+    bulk points and outliers have boxes too wide for the FP64 kernel's
+    table-driven exponential (their pairs take the clamped one), and the
+    origin of the packed coordinates (a median) stays inside the bulk."""
+    n, d, l = 20000, 3, 0.05
+    rng = np.random.default_rng(91)
+    X = W.points("mixture5", n, d, 90)
+    out = rng.choice(n, 300, replace=False)
+    dirs = rng.standard_normal((300, d))
+    X[out] += dirs / np.linalg.norm(dirs, axis=1, keepdims=True) * 10.0 ** rng.uniform(2, 6, (300, 1))
+    bulk = np.setdiff1d(np.arange(n), out)
+    V = rng.standard_normal(n)
+    rows = np.concatenate([rng.choice(bulk, 25, replace=False), out[:10]])
+    print(f"outliers: kernel={kernel}", flush=True)
+    with oracle.use_kernel("matern32" if kernel else "gaussian"):
+        yo, ab = oracle.kernel_matvec_rows(X, l, 1e-3, V, rows)
+    vs = np.abs(V).sum()
+    xm = np.where(np.isin(rows, out), spread(X), spread(X[bulk]))
+    for prec in (afn.AFN_FP64, afn.AFN_FP32):
+        Y = afn.kernel_matvec(dev(X), l, 1e-3, dev(V[:, None]), precision=prec, kernel=kernel).cpu().numpy()
+        assert np.all(np.isfinite(Y))
+        fp64 = prec == afn.AFN_FP64
+        r = np.array([term_rel(kernel, fp64, d, x, l) for x in xm])
+        if fp64:
+            bound = (2 * (n + 4) + r) * U * ab + 2.0 ** -64 * vs
+        else:
+            bound = (n + 8 + r) * U32 * ab + (1e-13 + 2.0 ** -44) * vs
+        err = np.abs(Y[rows, 0] - yo)
         print(f"  prec={prec}: worst err/bound {float(np.max(err / bound)):.3f}", flush=True)
         assert np.all(err <= bound)
