@@ -299,7 +299,7 @@ afn_status block_refine_solve(afn_handle *h, const double *B, int64_t ld, double
             inv[c] = act ? 1.0 / std::sqrt(rr[c]) : 0.0;
             amul[c] = act ? std::sqrt(rr[c]) : 0.0;
             double ti = act ? 0.5 * tol / rel : 0.5;
-            ti = ti > 1e-4 ? ti : 1e-4;
+            ti = ti > 3e-2 ? ti : 3e-2;      // as for single solves: FP32 bounds a step's gain
             tolc[c] = ti < 0.5 ? ti : 0.5;
         }
         *relres_max = worst;
