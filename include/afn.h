@@ -206,7 +206,9 @@ afn_status afn_apply(afn_handle *h, const double *r_dev, double *z_dev, int32_t 
  * rule) or after maxit products with K + mu I.  A handle set up with
  * precision AFN_FP32 solves by iterative refinement instead: the FP64
  * residual ||b - (K + mu I) x|| / ||b|| is the stopping test, each inner FP32
- * PCG runs at most maxit iterations, and the FP64 PCG described under
+ * PCG runs at most maxit iterations and stops at the relative residual its
+ * step needs (half of tol over the current FP64 residual), but at 3e-2 at
+ * the lowest, and the FP64 PCG described under
  * afn_precision takes over when the FP32 corrections stop working (the
  * status is then that of the FP64 PCG).  With nrhs >= 2 and d <= 8 the
  * right-hand sides go through the block solver 64 at a time; a column it
