@@ -326,6 +326,23 @@ def test_splitmix64_published_outputs():
     assert [int(v) for v in out] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
 
 
+def _fisher_yates_prefix(n, m, seed):
+    """First m entries of the Fisher-Yates shuffle of 0..n-1 in which position
+    i swaps with i + (draw_i mod (n - i)), draw_i the i-th splitmix64 output
+    (the generator is pinned to its published outputs above)."""
+    draws = [int(v) for v in oracle.splitmix64_stream(seed, m)]
+    a = list(range(n))
+    for i in range(m):
+        j = i + draws[i] % (n - i)
+        a[i], a[j] = a[j], a[i]
+    return a[:m]
+
+
+@pytest.mark.parametrize("n,m,seed", [(1000, 300, 42), (50, 50, 1), (12345, 2000, 7), (7, 1, 3)])
+def test_subsample_is_the_fisher_yates_prefix(n, m, seed):
+    assert oracle.subsample(n, m, seed).tolist() == _fisher_yates_prefix(n, m, seed)
+
+
 def test_subsample_distinct_and_deterministic():
     a = oracle.subsample(1000, 300, 42)
     assert len(set(a.tolist())) == 300 and a.min() >= 0 and a.max() < 1000
@@ -378,5 +395,68 @@ def test_rank_estimate_branches():
     assert k == int(np.sum(ev > 1e-4))
     # rough kernel: r close to m -> k_est = floor(r n / m) >= switch -> capped
     k2, info2 = oracle.rank_estimate(X, 0.01, 1e-3, 300, kmax=500, kswitch=100, seed=7)
-    assert info2[2] == 0 and info2[0] % 8 == 0 or info2[0] == 300
+    assert info2[2] == 0 and (info2[0] % 8 == 0 or info2[0] == 300)
     assert info2[1] == (info2[0] * 3000) // 300 and k2 == min(500, info2[1])
+
+
+def _fps_by_definition(X, k):
+    """FPS written from its definition (Algorithm 6): the first point is the
+    one nearest to the mean (each coordinate summed exactly by math.fsum), then
+    repeatedly the unselected point farthest from the selected set; ties to the
+    smallest index."""
+    n, d = X.shape
+    cen = np.array([math.fsum(X[:, t]) / n for t in range(d)])
+    first = int(np.argmin(((X - cen) ** 2).sum(1)))
+    D = ((X[:, None, :] - X[None, :, :]) ** 2).sum(-1)
+    sel = [first]
+    dist = D[first].copy()
+    dist[first] = -1.0
+    for _ in range(1, k):
+        j = int(np.argmax(dist))
+        sel.append(j)
+        dist = np.minimum(dist, D[j])
+        dist[sel] = -1.0
+    return sel
+
+
+def _nystrom_rank_by_definition(Xm, l, step=8, tol=0.1):
+    """Smallest r in step, 2 step, ... (or m) whose Nystrom approximation
+    K[:, I] K[I, I]^{-1} K[I, :] on the first r FPS points has relative
+    Frobenius error below tol (Eq. (2.1)), each error formed directly."""
+    m = Xm.shape[0]
+    K = dense_K(Xm, l)
+    order = _fps_by_definition(Xm, m)
+    errs = {}
+    for r in list(range(step, m, step)) + [m]:
+        I = order[:r]
+        Kn = K[:, I] @ np.linalg.solve(K[np.ix_(I, I)], K[I, :])
+        errs[r] = np.linalg.norm(K - Kn) / np.linalg.norm(K)
+        if errs[r] < tol:
+            return r, errs
+    return m, errs
+
+
+def test_rank_estimate_scales_subsample_by_m_over_n():
+    """Algorithm 4 on an interior case (8 < r < m, the eigenvalue branch not
+    taken): the subsample's coordinates are scaled by (m/n)^(1/d) before the
+    Nystrom error scan (Section 3.3), and k_est = floor(r n / m).  Every piece
+    is recomputed here from its definition: the Fisher-Yates subsample, the
+    scaled copy, a dense K, FPS and the Nystrom error of each prefix.  The
+    other two readings of the scale, none and (n/m)^(1/d), give ranks far
+    from it on this case, so either one would fail."""
+    n, m, d, l = 3000, 300, 3, 0.1
+    X = np.random.default_rng(16).random((n, d))
+    k, info = oracle.rank_estimate(X, l, 1e-3, m, kmax=3000, kswitch=1, seed=11)
+    sub = _fisher_yates_prefix(n, m, 11)
+    ranks = {}
+    for name, s in (("m/n", (m / n) ** (1 / d)), ("none", 1.0), ("n/m", (n / m) ** (1 / d))):
+        ranks[name], errs = _nystrom_rank_by_definition(X[sub] * s, l)
+        if name == "m/n":
+            r = ranks[name]
+            # the decision is not a rounding accident
+            assert errs[r] < 0.1 * (1 - 1e-6) and errs[r - 8] > 0.1 * (1 + 1e-6)
+    assert 8 < ranks["m/n"] < m
+    assert abs(ranks["none"] - ranks["m/n"]) >= 64 and abs(ranks["n/m"] - ranks["m/n"]) >= 64
+    assert info[2] == 0
+    assert info[0] == ranks["m/n"]
+    assert info[1] == (ranks["m/n"] * n) // m and k == info[1]
