@@ -222,6 +222,9 @@ afn_status block_refine_solve(afn_handle *h, const double *B, int64_t ld, double
 {
     const int64_t n = h->n;
     const int64_t npad = kmv_packed_doubles(n, h->d) / h->d;
+    // every early return leaves the columns marked unsolved, so the caller
+    // re-solves them one at a time
+    for (int c = 0; c < R; ++c) col_ok[c] = 0;
     const size_t need = block_ws(h, R, nullptr, nullptr);
     if (h->mrhs_bytes < need) {
         if (h->mrhs_ws) {
@@ -280,7 +283,6 @@ afn_status block_refine_solve(afn_handle *h, const double *B, int64_t ld, double
     *iters = 0;
     *outer = 0;
     *conv_all = 0;
-    for (int c = 0; c < R; ++c) col_ok[c] = 0;
     afn_status status = AFN_ENOCONV;
     double prev = INFINITY;
     for (int o = 0;; ++o) {

@@ -610,6 +610,59 @@ def test_block_solve_column_equals_single_solve(afn, block_case):
     assert rel <= 1e-6
 
 
+@pytest.fixture(scope="module")
+def wide_block_case(afn):
+    n = 2000
+    X = W.points("uniform", n, 3, 73)
+    B = np.random.default_rng(74).standard_normal((n, 70))
+    l, mu, k, w = 0.1, 1e-4, 200, 32
+    h = afn.afn_setup(dev(X), l, mu, k=k, w=w, precision=afn.AFN_FP32)
+    idx, _ = oracle.fps(X, k)
+    A = oracle.afn_build(X, l, mu, idx, w)
+    return X, B, l, mu, h, A
+
+
+@pytest.mark.parametrize("R", [64, 70])
+def test_block_solve_wide_matches_oracle(afn, wide_block_case, R):
+    """64 columns (one full block, graph-captured) and 70 (a full block plus
+    a 6-column chunk): sampled columns against the FP64 oracle's solve at
+    matching residual, every column's true residual below tol."""
+    X, B, l, mu, h, A = wide_block_case
+    tol = 1e-10
+    x, info = _block_solve(afn, h, B[:, :R], tol)
+    say(f"block R={R}", info)
+    assert info["converged"] and info["status"] == afn.AFN_OK
+    x = x.cpu().numpy()
+    for c in range(R):
+        r = B[:, c] - oracle.kernel_matvec(X, l, mu, x[:, c])
+        assert np.linalg.norm(r) / np.linalg.norm(B[:, c]) <= 2 * tol, c
+    for c in sorted({0, 31, 63, R - 1}):
+        xo, *_ = oracle.pcg(A, B[:, c], tol, 500)
+        rel = np.linalg.norm(x[:, c] - xo) / np.linalg.norm(xo)
+        say(f"R={R} column {c}: vs FP64 oracle {rel:.2e}")
+        assert rel <= 1e-6
+
+
+def test_block_solve_nan_column_in_second_chunk(afn, wide_block_case):
+    """A non-finite right-hand side in the second 64-column chunk: the call
+    reports EBREAKDOWN, and every other column is still solved to tol."""
+    X, B, l, mu, h, A = wide_block_case
+    tol = 1e-8
+    Bn = B.copy()
+    Bn[5, 66] = np.nan
+    Bt = torch.tensor(Bn.T.copy(), device="cuda").t()
+    out = torch.full((70, Bn.shape[0]), 7.0, dtype=torch.float64, device="cuda").t()
+    with pytest.raises(afn.AFNError) as e:
+        afn.afn_pcg_solve(h, Bt, tol=tol, maxit=500, out=out)
+    assert e.value.status == afn.AFN_EBREAKDOWN
+    x = out.cpu().numpy()
+    for c in range(70):
+        if c == 66:
+            continue
+        r = Bn[:, c] - oracle.kernel_matvec(X, l, mu, x[:, c])
+        assert np.linalg.norm(r) / np.linalg.norm(Bn[:, c]) <= 2 * tol, c
+
+
 # ------------------------------------------------------------------ mixed precision: FP64 fallback
 
 @pytest.mark.parametrize("n,l,mu,k,tol", [(4000, 0.5, 1e-8, 200, 1e-6), (2000, 0.3, 1e-6, 100, 1e-10),
