@@ -179,6 +179,22 @@ afn_status kernel_matvec_ex(const double *X_dev, int64_t n, int32_t d, double l,
                             const double *v_dev, double *y_dev, int32_t nrhs, int64_t ld,
                             int32_t precision, int32_t kernel, void *stream);
 
+/* kernel_matvec_ex for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, bit for bit, with the scratch
+ * (spatial order, packed points, tile boxes, partial sums) in a static
+ * 192 MiB device array that each device holds until the process ends.  No
+ * device memory is allocated or freed by the call.  The scratch needed grows
+ * with n (n = 1e5 at d = 3 fits with one column, n = 6000 with up to 64
+ * columns: the many-column partial sums are larger); a call that would
+ * need more is rejected on the host with EINVAL before any device work.
+ * Every call on a device shares that device's array: calls that overlap in
+ * time on one device (several threads or streams) race on it.  Errors as
+ * kernel_matvec_ex, and EDEVICE if the array's address cannot be taken. */
+afn_status kernel_matvec_noalloc(const double *X_dev, int64_t n, int32_t d, double l, double mu,
+                                 const double *v_dev, double *y_dev, int32_t nrhs, int64_t ld,
+                                 int32_t precision, int32_t kernel, void *stream);
+
 /* Construct the preconditioner.  AFN (Algorithm 2): landmarks by farthest
  * point sampling (Algorithm 6) -- k from params or estimated (Algorithm 4) --,
  * L = chol(K11 + mu I), and the FSAI factor G of the Schur complement

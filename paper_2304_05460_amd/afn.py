@@ -30,7 +30,7 @@ _STATUS_NAMES = ["AFN_OK", "AFN_EINVAL", "AFN_ENOMEM", "AFN_ENOTSPD", "AFN_ENOCO
 def status_name(status: int) -> str:
     return _STATUS_NAMES[status] if 0 <= status < len(_STATUS_NAMES) else f"status {status}"
 
-EXPORTED = ["kernel_matvec", "kernel_matvec_ex", "afn_setup", "afn_apply", "afn_pcg_solve", "afn_get_info",
+EXPORTED = ["kernel_matvec", "kernel_matvec_ex", "kernel_matvec_noalloc", "afn_setup", "afn_apply", "afn_pcg_solve", "afn_get_info",
             "afn_get_landmarks", "afn_get_fsai", "afn_get_cholesky", "afn_footprint_bytes",
             "afn_destroy", "afn_status_string", "afn_last_error"]
 
@@ -91,6 +91,7 @@ _P, _I32, _I64, _D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_d
 def _declare(L):
     L.kernel_matvec.argtypes = [_P, _I64, _I32, _D, _D, _P, _P, _I32, _I64, _I32, _P]
     L.kernel_matvec_ex.argtypes = [_P, _I64, _I32, _D, _D, _P, _P, _I32, _I64, _I32, _I32, _P]
+    L.kernel_matvec_noalloc.argtypes = [_P, _I64, _I32, _D, _D, _P, _P, _I32, _I64, _I32, _I32, _P]
     L.afn_setup.argtypes = [_P, _I64, _I32, _D, _D, ctypes.POINTER(afn_params), _P,
                             ctypes.POINTER(_P)]
     L.afn_apply.argtypes = [_P, _P, _P, _I32, _I64, _P]
@@ -108,7 +109,7 @@ def _declare(L):
     L.afn_status_string.restype = ctypes.c_char_p
     L.afn_last_error.argtypes = []
     L.afn_last_error.restype = ctypes.c_char_p
-    for name in ("kernel_matvec", "kernel_matvec_ex", "afn_setup", "afn_apply", "afn_pcg_solve", "afn_get_info",
+    for name in ("kernel_matvec", "kernel_matvec_ex", "kernel_matvec_noalloc", "afn_setup", "afn_apply", "afn_pcg_solve", "afn_get_info",
                  "afn_get_landmarks", "afn_get_fsai", "afn_get_cholesky", "afn_footprint_bytes"):
         getattr(L, name).restype = ctypes.c_int
 
@@ -168,6 +169,24 @@ def kernel_matvec(X: torch.Tensor, l: float, mu: float, v: torch.Tensor,
         st = lib().kernel_matvec_ex(X.data_ptr(), n, d, l, mu, vp, yp, nrhs, ldv, precision, kernel,
                                     _stream(stream))
     _check(st, "kernel_matvec")
+    return out
+
+
+def kernel_matvec_noalloc(X: torch.Tensor, l: float, mu: float, v: torch.Tensor, out: torch.Tensor,
+                          precision: int = AFN_FP64, stream=None, kernel: int = 0) -> torch.Tensor:
+    """kernel_matvec into a caller-provided out, with the library's static
+    scratch array (no device allocation by the library)."""
+    X = _dev_f64(X, "X")
+    if not X.is_contiguous():
+        raise ValueError("X must be contiguous")
+    n, d = X.shape
+    vp, nrhs, ldv = _colmajor(v, "v")
+    yp, _, ldy = _colmajor(out, "out")
+    if v.shape[0] != n or out.shape != v.shape or ldv != ldy:
+        raise ValueError("v and out must be (n,) or (n, nrhs) with one leading dimension")
+    st = lib().kernel_matvec_noalloc(X.data_ptr(), n, d, l, mu, vp, yp, nrhs, ldv, precision, kernel,
+                                     _stream(stream))
+    _check(st, "kernel_matvec_noalloc")
     return out
 
 
