@@ -1,18 +1,23 @@
 #!/usr/bin/env python3
 """AFN-PCG benchmark on one MI355X.
 
-One step = one complete solve of (K + mu I) a = b through the C-ABI: Nystrom
-rank estimation (Algorithm 4), landmark selection by FPS, chol(K11 + mu I),
-V = L^{-1} K12, the kNN pattern, FSAI of the Schur complement (Algorithm 2)
-and PCG with the AFN apply (Algorithm 3) to relative residual 1e-6.
-Workload: n = 100000 points of a 5-centre Gaussian mixture (sigma 0.05) in
-[0,1]^3, l = 0.1, mu = 1e-3, adaptive k <= 2000, FSAI w = 64, b ~ N(0, 1),
-all FP64.  Inputs are resident in HBM before the timed region.
+Default workload (the mixed-precision head-to-head): n = 200000 points
+~ N(0, I) in R^8, Gaussian kernel l = 2, mu = 1e-2, k = 4000 FPS landmarks, one
+right-hand side b ~ N(0, 1), relative residual 1e-6.  One step = one complete
+solve of (K + mu I) a = b through the C-ABI: landmark selection by FPS
+(Algorithm 6), the preconditioner (Algorithm 5's Nystrom branch at k = 4000:
+chol(K11 + nu I), W = L^{-1} K[S, :], chol(W W^T + mu I)) and PCG, in mixed
+precision (FP32 operator and preconditioner inside FP64 iterative
+refinement); the FP64 path solves the same input beside it, and the AFN
+branch (Algorithm 2's factorization) is reported by --c3-branch afn.
+Inputs are resident in HBM before the timed region.
 
-Prints ONE JSON line: value = solves/s; roofline of the dominant kernel (the
-FP64 kernel-matvec tile kernel, timed live with HIP events around each of its
-launches inside the timed solves); cpu_baseline = the FP64 oracle on a bounded
-sample of the same workload, extrapolated to one solve.
+Prints ONE JSON line: value = mixed-precision solves/s; roofline of the
+dominant kernel (the FP32 kernel-matvec tile kernel of the inner solves, timed
+live with HIP events around each of its launches inside the timed solves);
+cpu_baseline = the FP64 oracle on a bounded sample of the same workload,
+extrapolated to one solve.  --workload c2|c4|highd and --serving select the
+other workloads.
 """
 from __future__ import annotations
 
@@ -127,11 +132,12 @@ def cpu_baseline(X, b, l, mu, k, w, iters, n_rows=2000, n_knn=500, n_fsai=6):
     oracle.kernel_matvec_rows(Xp[: k + nr], l, 0.0, np.ones(n), lm_rows)
     t_apply = (time.perf_counter() - t0) * k / len(lm_rows) * 2
     t_total = sum(t.values()) + iters * (t_mv + t_apply)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    hc = host_cpu()
     return {
+        **hc,
         "value": 1.0 / t_total,
         "unit": "solves/s",
-        "cores": threads,
+        "cores": hc["omp_num_threads"],
         "kind": "oracle",
         "sample": (f"FPS and chol(K11+mu I) in full; {n_rows} kernel-matvec rows, {n_knn} kNN "
                    f"rows, {n_fsai} FSAI rows (with their L^-1 K12 columns) and {len(lm_rows)} "
@@ -149,10 +155,86 @@ def _line(metric, value, unit, steps, warmup, ms, dtype, config, **extra):
     print(json.dumps(out))
 
 
+def host_cpu() -> dict:
+    """The host the oracle ran on: CPU model (lscpu), logical CPUs (nproc) and
+    the OpenMP thread count it used."""
+    import subprocess
+    model = ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:  # noqa: BLE001
+        pass
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"cpu_model": model, "nproc": os.cpu_count(), "omp_num_threads": threads}
+
+
+def cpu_baseline_nystrom(X, l, mu, k, iters, n_rows=1000, n_mv=2000, seed=7):
+    """The oracle's Nystrom-branch solve (FPS, Y = K[:, S], chol(K_SS + nu I),
+    B = Y C^{-T}, thin SVD, then PCG with the Woodbury apply) on a bounded
+    sample, extrapolated to one full solve: FPS in full; the kernel columns,
+    the triangular solve and the SVD on n_rows-row slices scaled by the row
+    count (each is linear in n for n >> k); kernel-matvec rows on n_mv rows;
+    the apply's two products with U on an n_rows-row slice; iters PCG
+    iterations (the GPU's FP64 count)."""
+    import numpy as np
+    import scipy.linalg
+    import oracle
+    from oracle import nystrom as ny
+    rng = np.random.default_rng(seed)
+    n = X.shape[0]
+    t = {}
+    t0 = time.perf_counter()
+    idx, _ = oracle.fps(X, k)
+    t["fps"] = time.perf_counter() - t0
+    rows = rng.choice(n, n_rows, replace=False)
+    Xs = np.vstack([X[rows], X[idx]])
+    t0 = time.perf_counter()
+    Y = ny.kernel_columns(Xs, l, np.arange(n_rows, n_rows + k))     # K[rows and S, S]
+    t["kernel_columns"] = (time.perf_counter() - t0) * n / (n_rows + k)
+    Ys, Kss = Y[:n_rows], Y[n_rows:]
+    t0 = time.perf_counter()
+    C = np.linalg.cholesky(Kss + 1e-12 * np.eye(k))
+    t["chol"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Bs = scipy.linalg.solve_triangular(C, Ys.T, lower=True).T
+    t["trsm"] = (time.perf_counter() - t0) * n / n_rows
+    t0 = time.perf_counter()
+    Bs2 = np.vstack([Bs] * max(1, (2 * k) // n_rows + 1))     # at least 2k rows: the thin-SVD regime
+    np.linalg.svd(Bs2, full_matrices=False)
+    t["svd"] = (time.perf_counter() - t0) * n / Bs2.shape[0]
+    v = rng.standard_normal(n)
+    mv_rows = rng.integers(0, n, n_mv)
+    t0 = time.perf_counter()
+    oracle.kernel_matvec_rows(X, l, mu, v, mv_rows)
+    t_mv = (time.perf_counter() - t0) * n / n_mv
+    U = np.linalg.qr(Bs)[0]
+    r = rng.standard_normal(n_rows)
+    t0 = time.perf_counter()
+    for _ in range(3):
+        tt = U.T @ r
+        _ = U @ tt + r
+    t_apply = (time.perf_counter() - t0) / 3 * n / n_rows
+    setup = sum(t.values())
+    total = setup + iters * (t_mv + t_apply)
+    hc = host_cpu()
+    return dict({"value": 1.0 / total, "unit": "solves/s", "cores": hc["omp_num_threads"], "kind": "oracle",
+                 "sample": (f"FPS (k={k}) in full; kernel columns, triangular solve and SVD on {n_rows}-row "
+                            f"slices, {n_mv} kernel-matvec rows and the apply on a {n_rows}-row slice, "
+                            f"scaled to n={n}; {iters} PCG iterations; extrapolated seconds per solve "
+                            f"{total:.1f} (setup {setup:.1f}: " +
+                            ", ".join(f"{k_} {v_:.1f}" for k_, v_ in t.items()) +
+                            f"; matvec {t_mv:.2f}/it, apply {t_apply:.3f}/it)")}, **hc)
+
+
 def c3_bench(args):
-    """n = 2e5 standard normal points in R^8, l = 2, mu = 1e-2, k = 4000, w = 64:
-    one solve (setup + PCG, maxit 500) in mixed precision and one in FP64 on the
-    same input; reports each path's status, iterations, residual and time."""
+    """n = 2e5 standard normal points in R^8, l = 2, mu = 1e-2, k = 4000 FPS
+    landmarks, tol 1e-6: the mixed-precision solve (value, args.steps timed
+    solves after args.warmup) against the FP64 solve of the same input
+    (min(steps, 2) timed solves), both through the C-ABI."""
     import torch
     from paper_2304_05460_amd import afn, workloads as W
 
@@ -161,27 +243,82 @@ def c3_bench(args):
     X = torch.tensor(X_np, device="cuda")
     b = torch.tensor(b_np, device="cuda")
     afn.lib()
-    res = {}
-    for name, prec in (("mixed", afn.AFN_FP32), ("fp64", afn.AFN_FP64)):
-        print(f"[bench] c3 {name}", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        h = afn.afn_setup(X, p.l, p.mu, k=p.k, w=p.w, precision=prec)
-        x, info = afn.afn_pcg_solve(h, b, tol=p.tol, maxit=p.maxit)
-        torch.cuda.synchronize()
-        t = time.perf_counter() - t0
+    method = afn.AFN_METHOD_AFN if args.c3_branch == "afn" else afn.AFN_METHOD_NYSTROM
+    maxit = args.maxit if args.maxit else (8000 if args.c3_branch == "afn" else p.maxit)
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    def step(prec):
+        h = afn.afn_setup(X, p.l, p.mu, k=p.k, w=p.w, precision=prec, method=method, nrhs_max=0)
+        x, info = afn.afn_pcg_solve(h, b, tol=p.tol, maxit=maxit)
         si = h.info()
         h.close()
-        res[name] = {"seconds": round(t, 3), "status": afn.status_name(info["status"]),
-                     "iterations": info["iterations"], "outer_iterations": info["outer_iterations"],
-                     "relres_true": info["relres_true"], "setup_ms": round(si.ms["total"], 1),
-                     "solve_ms": round(info["ms_solve"], 1),
-                     "kmv_avg_launch_ms": round(info["ms_matvec"] / max(info["matvec_launches"], 1), 3)}
-        print(f"[bench] c3 {name}: {res[name]}", file=sys.stderr, flush=True)
-    _line("AFN-PCG solves/s, mixed precision (FP64 path on the same input beside it)",
-          1.0 / res["mixed"]["seconds"], "solves/s", 1, 0, res["mixed"]["seconds"] * 1e3, "f32+f64",
-          {"workload": p.name, "n": p.n, "d": p.d, "l": p.l, "mu": p.mu, "k": p.k, "w": p.w,
-           "tol": p.tol, "maxit": p.maxit}, c3=res)
+        return x, info, si
+
+    def timed(prec, label, steps, warmup):
+        log(f"c3 {label}: {args.c3_branch} branch; warmup {warmup}, timed {steps}")
+        for _ in range(warmup):
+            step(prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = []
+        for i in range(steps):
+            out.append(step(prec))
+            log(f"c3 {label}: step {i + 1}/{steps}: {afn.status_name(out[-1][1]['status'])}, "
+                f"{out[-1][1]['iterations']} its")
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        return out, el
+
+    res32, el32 = timed(afn.AFN_FP32, "mixed", args.steps, args.warmup)
+    steps64 = min(args.steps, 2)
+    res64, el64 = timed(afn.AFN_FP64, "fp64", steps64, min(args.warmup, 1))
+    x32, i32, s32 = res32[-1]
+    x64, i64, s64 = res64[-1]
+    rel = float(torch.linalg.vector_norm(x32 - x64) / torch.linalg.vector_norm(x64))
+    launches = sum(r[1]["matvec_launches"] for r in res32)
+    kmv_ms = sum(r[1]["ms_matvec"] for r in res32) / max(launches, 1)
+    F = kmv_flops(p.n, p.d)
+    achieved = F * s32.kmv_kept_f32 / (kmv_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "kernel": "FP32 kernel-matvec tile kernel, d = 8 (inner solves)",
+                "avg_launch_ms": round(kmv_ms, 4), "launches": launches,
+                "flops_per_launch": F * s32.kmv_kept_f32, "tile_pairs_evaluated": round(s32.kmv_kept_f32, 4)}
+    ms64 = sum(r[1]["ms_matvec"] for r in res64) / max(sum(r[1]["matvec_launches"] for r in res64), 1)
+    value = args.steps / el32
+    fp64_value = steps64 / el64
+    out = {
+        "metric": "AFN-PCG solves/s at rel-res 1e-6, mixed precision (FP64 path on the same input beside it)",
+        "value": round(value, 4), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(el32 / args.steps * 1e3, 2), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": p.name, "n": p.n, "d": p.d, "points": "normal", "l": p.l, "mu": p.mu,
+                   "k": p.k, "landmarks": "fps", "tol": p.tol, "maxit": maxit, "nrhs": 1,
+                   "preconditioner": args.c3_branch,
+                   "branch_note": ("Algorithm 5's Nystrom branch at k = 4000; Algorithm 2's AFN "
+                                   "factorization (--c3-branch afn) needs thousands of iterations on "
+                                   "this distribution") if args.c3_branch == "nystrom" else
+                                  "Algorithm 2's AFN factorization, w = 64"},
+        "mixed": {"status": afn.status_name(i32["status"]), "iterations_inner": i32["iterations"],
+                  "outer_iterations": i32["outer_iterations"], "fp64_fallback_iterations": i32["fp64_iterations"],
+                  "relres_true_fp64": i32["relres_true"], "rel_diff_vs_fp64_solution": rel,
+                  "setup_ms": round(s32.ms["total"], 1), "solve_ms": round(i32["ms_solve"], 1),
+                  "kmv_f32_avg_launch_ms": round(kmv_ms, 4)},
+        "fp64": {"value": round(fp64_value, 4), "unit": "solves/s", "steps": steps64,
+                 "ms_per_step": round(el64 / steps64 * 1e3, 2), "status": afn.status_name(i64["status"]),
+                 "iterations": i64["iterations"], "relres_true": i64["relres_true"],
+                 "setup_ms": round(s64.ms["total"], 1), "solve_ms": round(i64["ms_solve"], 1),
+                 "kmv_f64_avg_launch_ms": round(ms64, 4),
+                 "kmv_f64_tflops": round(F * s64.kmv_kept_f64 / (ms64 * 1e-3) / 1e12, 3)},
+        "speedup_mixed_vs_fp64": round(value / fp64_value, 3),
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)")
+        out["cpu_baseline"] = cpu_baseline_nystrom(X_np, p.l, p.mu, p.k, i64["iterations"])
+    print(json.dumps(out))
 
 
 def highd_bench(args):
@@ -381,9 +518,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision and Algorithm 5 runs on the same input")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "highd"],
-                    help="c2 (default): the solves/s line; c3: mixed vs FP64 at n=2e5, d=8; "
-                         "c4: 64 right-hand sides at n=1.5e5; highd: n=49990, d=22 (uniform landmarks)")
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "highd"],
+                    help="c3 (default): mixed vs FP64 at n=2e5, d=8; c2: FP64 at n=1e5, d=3 "
+                         "(--l 0.01 / 0.1 / 1); c4: 64 right-hand sides at n=1.5e5; highd: n=49990, "
+                         "d=22 (uniform landmarks)")
+    ap.add_argument("--c3-branch", default="nystrom", choices=["nystrom", "afn"],
+                    help="preconditioner of the c3 solves (Algorithm 5's branches)")
+    ap.add_argument("--maxit", type=int, default=0, help="PCG iteration cap (0: the workload's)")
     ap.add_argument("--serving", action="store_true",
                     help="run the mixed-size request stream instead (p50/p99 latency, solves/s)")
     ap.add_argument("--serving-count", type=int, default=256)
@@ -396,9 +537,7 @@ def main():
               f"(the multi-GPU row sharding is a design note only)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_2304_05460_amd import afn, workloads as W
 
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
@@ -422,6 +561,17 @@ def main():
     if args.workload == "highd":
         highd_bench(args)
         return
+
+    c2_bench(args)
+
+
+def c2_bench(args):
+    """n = 1e5 points of a 5-centre mixture in [0,1]^3, adaptive k <= 2000,
+    w = 64, FP64 (value), with the mixed path and Algorithm 5's choice on the
+    same input beside it."""
+    import numpy as np  # noqa: F401
+    import torch
+    from paper_2304_05460_amd import afn, workloads as W
 
     p = W.c2(args.l, tol=args.tol)
     X_np, b_np = W.make(p)

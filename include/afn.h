@@ -29,6 +29,10 @@
  *    not overlap on the device: they share the handle's workspace (use one
  *    stream per handle, or synchronize between calls on different streams).
  *    Different handles are independent.
+ *  - Device memory: a handle lives in one workspace that the caller passes
+ *    to afn_setup (afn_workspace_size bytes); setup and solves allocate no
+ *    device memory of their own.  kernel_matvec keeps a per-device scratch
+ *    area that it grows on demand; kernel_matvec_noalloc uses a static one.
  */
 #ifndef AFN_H
 #define AFN_H
@@ -115,6 +119,11 @@ typedef struct afn_params {
     uint64_t seed;      /* seed of the rank-estimation subsample (splitmix64)      */
     int32_t landmarks;  /* afn_landmarks                                           */
     int32_t kernel;     /* afn_kernel                                              */
+    int32_t nrhs_max;   /* widest block solve to provision (AFN_FP32, d <= 8):
+                           >= 2 carves a block workspace for min(nrhs_max, 64)
+                           columns; 0 or 1: several columns are solved one at a
+                           time                                                    */
+    int32_t reserved;   /* zero                                                    */
 } afn_params;
 
 /* Facts about a constructed preconditioner. */
@@ -138,6 +147,8 @@ typedef struct afn_setup_info {
     double kmv_far_f64;      /* fraction of tile pairs whose FP64 values are all
                                 below 2^-46 and take the FP32 exponential (d <= 4;
                                 0 otherwise)                                       */
+    int64_t ws_bytes;        /* workspace size (afn_workspace_size)                 */
+    int64_t ws_bytes_used;   /* bytes of it the setup carved                        */
 } afn_setup_info;
 
 /* Result of a PCG solve. */
@@ -195,19 +206,38 @@ afn_status kernel_matvec_noalloc(const double *X_dev, int64_t n, int32_t d, doub
                                  const double *v_dev, double *y_dev, int32_t nrhs, int64_t ld,
                                  int32_t precision, int32_t kernel, void *stream);
 
+/* Device memory, in bytes, that afn_setup carves from its workspace for n
+ * points in d dimensions with these parameters: the handle's persistent
+ * buffers (points, permutation, L, L^{-1}, V = L^{-1} K12, the pattern, G,
+ * G^T, their FP32 copies, packed points, PCG vectors, the block-solve
+ * workspace of params->nrhs_max columns) plus every temporary of the
+ * construction (rank estimation, FPS, orderings, transposes), which are
+ * carved from the same workspace and not reused.  An adaptive landmark count
+ * (k = -1) is priced at min(k_max, n), the most Algorithm 4 can return.
+ * Host-only (no device call); a serving loop admits requests by this number.
+ * Errors: EINVAL (as afn_setup). */
+afn_status afn_workspace_size(int64_t n, int32_t d, const afn_params *params, size_t *bytes);
+
 /* Construct the preconditioner.  AFN (Algorithm 2): landmarks by farthest
  * point sampling (Algorithm 6) -- k from params or estimated (Algorithm 4) --,
  * L = chol(K11 + mu I), and the FSAI factor G of the Schur complement
  * K22 + mu I - K12^T (K11 + mu I)^{-1} K12 (Algorithm 1) on the pattern of
  * the w-1 nearest earlier-numbered points (Section 3.1).  Nystrom and the
  * Algorithm 5 choice: see afn_method (w is then unused).
- * The library copies what it needs from X_dev and owns the device memory of
- * the handle (released by afn_destroy).  Synchronizes 'stream'.
- * Errors: EINVAL (n < 1, d < 1 or d > 64, l <= 0, mu < 0, k < -1 or k > n,
- * w < 1 or w > 64, unknown method, Nystrom with mu = 0), ENOMEM, ENOTSPD,
- * EDEVICE.  *out is NULL on failure. */
+ * ws_dev: caller-owned device workspace of ws_bytes >= afn_workspace_size
+ * bytes, 256-byte aligned; every device buffer of the handle and of its
+ * solves lives in it, the library allocates no device memory, and the
+ * workspace must stay allocated until afn_destroy.  ws_dev = NULL: the
+ * library allocates one block of afn_workspace_size bytes itself and frees it
+ * in afn_destroy.  The library copies what it needs from X_dev.  Synchronizes
+ * 'stream'.  Errors: EINVAL (n < 1, d < 1 or d > 64, l <= 0, mu < 0, k < -1
+ * or k > n, w < 1 or w > 64, unknown method, Nystrom with mu = 0, a
+ * misaligned ws_dev), ENOMEM (ws_bytes below afn_workspace_size, or the
+ * library's own allocation failed), ENOTSPD, EDEVICE.  *out is NULL on
+ * failure. */
 afn_status afn_setup(const double *X_dev, int64_t n, int32_t d, double l, double mu,
-                     const afn_params *params, void *stream, afn_handle **out);
+                     const afn_params *params, void *ws_dev, size_t ws_bytes, void *stream,
+                     afn_handle **out);
 
 /* z = M^{-1} r (Algorithm 3) for nrhs columns:
  *   s2 = G^T G (r2 - K12^T (K11 + mu I)^{-1} r1),
@@ -226,9 +256,12 @@ afn_status afn_apply(afn_handle *h, const double *r_dev, double *z_dev, int32_t 
  * step needs (half of tol over the current FP64 residual), but at 3e-2 at
  * the lowest, and the FP64 PCG described under
  * afn_precision takes over when the FP32 corrections stop working (the
- * status is then that of the FP64 PCG).  With nrhs >= 2 and d <= 8 the
- * right-hand sides go through the block solver 64 at a time; a column it
- * leaves above tol is solved again on its own.  b_dev, x_dev: n x nrhs FP64
+ * status is then that of the FP64 PCG).  On a handle whose setup
+ * provisioned a block workspace (AFN_FP32, d <= 8, params.nrhs_max >= 2) the
+ * right-hand sides go through the block solver nrhs_max (at most 64) at a
+ * time, on a stream the handle owns, ordered after 'stream'; a column it
+ * leaves above tol is solved again on its own.  Otherwise the columns are
+ * solved one at a time.  No device memory is allocated.  b_dev, x_dev: n x nrhs FP64
  * column-major, leading dimension ld.  info_host may be NULL.  Synchronizes.
  * Errors: EINVAL (tol <= 0, maxit < 1, nrhs < 1, ld < n), ENOCONV (x holds
  * the last iterate, info valid), EBREAKDOWN, ESTAGNATION, EDEVICE. */
@@ -255,11 +288,48 @@ afn_status afn_get_fsai(const afn_handle *h, int64_t *rowptr_host, int32_t *cols
  * dimension ld >= k.  Synchronous. */
 afn_status afn_get_cholesky(const afn_handle *h, double *L_host, int64_t ld);
 
-/* Upper bound of the device memory afn_setup allocates (persistent plus its
- * temporaries) for n points in d dimensions with these parameters; an
- * adaptive landmark count is priced at min(k_max, n).  Host-only (no device
- * call); used to admit requests by HBM footprint.  Errors: EINVAL. */
+/* The same number as afn_workspace_size (kept for admission code). */
 afn_status afn_footprint_bytes(int64_t n, int32_t d, const afn_params *params, size_t *bytes);
+
+/* ---- Step-wise PCG (Algorithm 5's solve, advanced from outside) -------------
+ * For a serving loop that advances many solves together: afn_pcg_begin
+ * starts the solve of one right-hand side on a handle, afn_pcg_step_many
+ * advances several started solves (on different handles) by a number of
+ * iterations each, with one host wait per iteration for all of them, and
+ * afn_pcg_query reports progress.  The iterates, stopping tests and results
+ * are those of afn_pcg_solve with nrhs = 1 on the same handle, bit for bit
+ * (FP64 PCG, or the iterative refinement of an AFN_FP32 handle with its FP64
+ * fallback).  A state lives in its handle's workspace: one started solve per
+ * handle at a time. */
+typedef struct afn_pcg_state afn_pcg_state;
+
+/* Start solving (K + mu I) x = b from x0 = 0 (b_dev, x_dev: n FP64 device
+ * vectors in the original point order, not aliasing; both must stay
+ * allocated until the solve is done).  Queues work on 'stream' and returns
+ * without waiting.  Errors: EINVAL (tol <= 0, maxit < 1, a solve already
+ * started on h), EDEVICE. */
+afn_status afn_pcg_begin(afn_handle *h, const double *b_dev, double *x_dev, double tol, int32_t maxit,
+                         void *stream, afn_pcg_state **out);
+
+/* Advance each unfinished state in states[0..count) by up to 'iters'
+ * products with K + mu I, in rounds: every round queues one iteration of
+ * every unfinished state, then waits on each and takes its stopping
+ * decision.  stream NULL: each state's work goes on the stream it was begun
+ * on, so solves on different streams overlap on the device; otherwise all of
+ * it goes on 'stream' (which must then be ordered after the begin streams).
+ * A state that finishes writes x_dev and its info.  Errors: EINVAL (a NULL state, count < 1, iters < 1, two states on
+ * one handle), EDEVICE; the outcome of each solve is read by afn_pcg_query. */
+afn_status afn_pcg_step_many(afn_pcg_state *const *states, int32_t count, int32_t iters, void *stream);
+
+/* *done = 1 once the solve has finished; info_host (may be NULL) then holds
+ * the result, and the return value is the solve's status (OK, ENOCONV,
+ * EBREAKDOWN, ESTAGNATION).  Before that: *done = 0, AFN_OK, info_host
+ * holds the iterations so far. */
+afn_status afn_pcg_query(const afn_pcg_state *st, int32_t *done, afn_solve_info *info_host);
+
+/* Release a state (finished or not); its handle can start another solve.
+ * Work queued for it must be complete (synchronize the stream). */
+void afn_pcg_end(afn_pcg_state *st);
 
 /* Release the handle and its device memory.  NULL is allowed.  Work the
  * caller queued with afn_apply on the handle must be complete. */

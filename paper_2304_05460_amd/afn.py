@@ -30,9 +30,10 @@ _STATUS_NAMES = ["AFN_OK", "AFN_EINVAL", "AFN_ENOMEM", "AFN_ENOTSPD", "AFN_ENOCO
 def status_name(status: int) -> str:
     return _STATUS_NAMES[status] if 0 <= status < len(_STATUS_NAMES) else f"status {status}"
 
-EXPORTED = ["kernel_matvec", "kernel_matvec_ex", "kernel_matvec_noalloc", "afn_setup", "afn_apply", "afn_pcg_solve", "afn_get_info",
-            "afn_get_landmarks", "afn_get_fsai", "afn_get_cholesky", "afn_footprint_bytes",
-            "afn_destroy", "afn_status_string", "afn_last_error"]
+EXPORTED = ["kernel_matvec", "kernel_matvec_ex", "kernel_matvec_noalloc", "afn_workspace_size", "afn_setup",
+            "afn_apply", "afn_pcg_solve", "afn_pcg_begin", "afn_pcg_step_many", "afn_pcg_query",
+            "afn_pcg_end", "afn_get_info", "afn_get_landmarks", "afn_get_fsai", "afn_get_cholesky",
+            "afn_footprint_bytes", "afn_destroy", "afn_status_string", "afn_last_error"]
 
 
 class AFNError(RuntimeError):
@@ -47,7 +48,8 @@ class afn_params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("k_max", ctypes.c_int32), ("w", ctypes.c_int32),
                 ("m", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("method", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("landmarks", ctypes.c_int32), ("kernel", ctypes.c_int32)]
+                ("landmarks", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("nrhs_max", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class afn_setup_info(ctypes.Structure):
@@ -61,7 +63,8 @@ class afn_setup_info(ctypes.Structure):
                 ("ms_total", ctypes.c_double), ("method", ctypes.c_int32),
                 ("landmarks", ctypes.c_int32), ("nu", ctypes.c_double),
                 ("kmv_kept_f64", ctypes.c_double), ("kmv_kept_f32", ctypes.c_double),
-                ("kmv_far_f64", ctypes.c_double)]
+                ("kmv_far_f64", ctypes.c_double), ("ws_bytes", ctypes.c_int64),
+                ("ws_bytes_used", ctypes.c_int64)]
 
 
 class afn_solve_info(ctypes.Structure):
@@ -92,8 +95,15 @@ def _declare(L):
     L.kernel_matvec.argtypes = [_P, _I64, _I32, _D, _D, _P, _P, _I32, _I64, _I32, _P]
     L.kernel_matvec_ex.argtypes = [_P, _I64, _I32, _D, _D, _P, _P, _I32, _I64, _I32, _I32, _P]
     L.kernel_matvec_noalloc.argtypes = [_P, _I64, _I32, _D, _D, _P, _P, _I32, _I64, _I32, _I32, _P]
-    L.afn_setup.argtypes = [_P, _I64, _I32, _D, _D, ctypes.POINTER(afn_params), _P,
-                            ctypes.POINTER(_P)]
+    L.afn_setup.argtypes = [_P, _I64, _I32, _D, _D, ctypes.POINTER(afn_params), _P, ctypes.c_size_t,
+                            _P, ctypes.POINTER(_P)]
+    L.afn_workspace_size.argtypes = [_I64, _I32, ctypes.POINTER(afn_params),
+                                     ctypes.POINTER(ctypes.c_size_t)]
+    L.afn_pcg_begin.argtypes = [_P, _P, _P, _D, _I32, _P, ctypes.POINTER(_P)]
+    L.afn_pcg_step_many.argtypes = [ctypes.POINTER(_P), _I32, _I32, _P]
+    L.afn_pcg_query.argtypes = [_P, ctypes.POINTER(_I32), ctypes.POINTER(afn_solve_info)]
+    L.afn_pcg_end.argtypes = [_P]
+    L.afn_pcg_end.restype = None
     L.afn_apply.argtypes = [_P, _P, _P, _I32, _I64, _P]
     L.afn_pcg_solve.argtypes = [_P, _P, _P, _I32, _I64, _D, _I32,
                                 ctypes.POINTER(afn_solve_info), _P]
@@ -109,8 +119,9 @@ def _declare(L):
     L.afn_status_string.restype = ctypes.c_char_p
     L.afn_last_error.argtypes = []
     L.afn_last_error.restype = ctypes.c_char_p
-    for name in ("kernel_matvec", "kernel_matvec_ex", "kernel_matvec_noalloc", "afn_setup", "afn_apply", "afn_pcg_solve", "afn_get_info",
-                 "afn_get_landmarks", "afn_get_fsai", "afn_get_cholesky", "afn_footprint_bytes"):
+    for name in ("kernel_matvec", "kernel_matvec_ex", "kernel_matvec_noalloc", "afn_workspace_size", "afn_setup",
+                 "afn_apply", "afn_pcg_solve", "afn_pcg_begin", "afn_pcg_step_many", "afn_pcg_query",
+                 "afn_get_info", "afn_get_landmarks", "afn_get_fsai", "afn_get_cholesky", "afn_footprint_bytes"):
         getattr(L, name).restype = ctypes.c_int
 
 
@@ -208,14 +219,17 @@ class SetupInfo:
     kmv_kept_f32: float = 1.0
     landmarks: int = 1
     kmv_far_f64: float = 0.0
+    ws_bytes: int = 0
+    ws_bytes_used: int = 0
 
 
 class Handle:
     """Owns an afn_handle*; afn_destroy runs on close() or garbage collection."""
 
-    def __init__(self, ptr: ctypes.c_void_p, n: int, d: int):
+    def __init__(self, ptr: ctypes.c_void_p, n: int, d: int, ws: torch.Tensor | None = None):
         self._ptr = ptr
         self.n, self.d = n, d
+        self.ws = ws      # the workspace the handle's buffers live in (freed after afn_destroy)
 
     @property
     def ptr(self):
@@ -227,6 +241,7 @@ class Handle:
         if self._ptr:
             lib().afn_destroy(self._ptr)
             self._ptr = ctypes.c_void_p()
+        self.ws = None
 
     def __del__(self):
         try:
@@ -241,7 +256,8 @@ class Handle:
                                                    "total")}
         return SetupInfo(inf.n, inf.d, inf.k, inf.w, inf.rank_r, inf.rank_k_est,
                          inf.rank_eig_branch, inf.rank_eig_count, inf.nnz_g, ms, inf.method, inf.nu,
-                         inf.kmv_kept_f64, inf.kmv_kept_f32, inf.landmarks, inf.kmv_far_f64)
+                         inf.kmv_kept_f64, inf.kmv_kept_f32, inf.landmarks, inf.kmv_far_f64,
+                         inf.ws_bytes, inf.ws_bytes_used)
 
     def landmarks(self):
         import numpy as np
@@ -274,29 +290,49 @@ class Handle:
         return L[:k, :k].copy(order="F")
 
 
+def _params(k=-1, w=64, k_max=2000, m=0, seed=0, precision=AFN_FP64, method=AFN_METHOD_AFN,
+            landmarks=AFN_LANDMARKS_AUTO, kernel=0, nrhs_max=0) -> afn_params:
+    return afn_params(k=k, k_max=k_max, w=w, m=m, precision=precision, method=method, seed=seed,
+                      landmarks=landmarks, kernel=kernel, nrhs_max=nrhs_max, reserved=0)
+
+
+def afn_workspace_size(n: int, d: int, **params) -> int:
+    """Bytes of device workspace afn_setup needs for these sizes (host-only)."""
+    prm = _params(**params)
+    out = ctypes.c_size_t(0)
+    _check(lib().afn_workspace_size(n, d, ctypes.byref(prm), ctypes.byref(out)), "afn_workspace_size")
+    return out.value
+
+
 def afn_setup(X: torch.Tensor, l: float, mu: float, k: int = -1, w: int = 64, k_max: int = 2000,
               m: int = 0, seed: int = 0, precision: int = AFN_FP64, method: int = AFN_METHOD_AFN,
-              landmarks: int = AFN_LANDMARKS_AUTO, kernel: int = 0, stream=None) -> Handle:
+              landmarks: int = AFN_LANDMARKS_AUTO, kernel: int = 0, nrhs_max: int = 64, stream=None,
+              ws: torch.Tensor | None = None) -> Handle:
     """Algorithm 2 (landmarks by FPS, chol(K11 + mu I), FSAI of the Schur complement),
-    or the Nystrom preconditioner, or Algorithm 5's choice between them (method)."""
+    or the Nystrom preconditioner, or Algorithm 5's choice between them (method).
+    The handle's device memory is one torch-owned workspace of afn_workspace_size
+    bytes (allocated here unless ws is given); the library allocates none."""
     X = _dev_f64(X, "X").contiguous()
     n, d = X.shape
-    prm = afn_params(k=k, k_max=k_max, w=w, m=m, precision=precision, method=method, seed=seed,
-                     landmarks=landmarks, kernel=kernel)
+    prm = _params(k=k, k_max=k_max, w=w, m=m, precision=precision, method=method, seed=seed,
+                  landmarks=landmarks, kernel=kernel, nrhs_max=nrhs_max)
+    need = ctypes.c_size_t(0)
+    _check(lib().afn_workspace_size(n, d, ctypes.byref(prm), ctypes.byref(need)), "afn_workspace_size")
+    if ws is None:
+        ws = torch.empty(max(need.value, 1), dtype=torch.uint8, device=X.device)
+    if not (ws.is_cuda and ws.dtype == torch.uint8 and ws.is_contiguous()):
+        raise TypeError("ws must be a contiguous uint8 CUDA (HIP) tensor")
     h = ctypes.c_void_p()
-    _check(lib().afn_setup(X.data_ptr(), n, d, l, mu, ctypes.byref(prm), _stream(stream),
-                           ctypes.byref(h)), "afn_setup")
-    return Handle(h, n, d)
+    _check(lib().afn_setup(X.data_ptr(), n, d, l, mu, ctypes.byref(prm), ws.data_ptr(), ws.numel(),
+                           _stream(stream), ctypes.byref(h)), "afn_setup")
+    return Handle(h, n, d, ws)
 
 
 def afn_footprint_bytes(n: int, d: int, k: int = -1, w: int = 64, k_max: int = 2000, m: int = 0,
-                        precision: int = AFN_FP64, method: int = AFN_METHOD_AFN) -> int:
-    """Upper bound of afn_setup's device memory for these sizes (host-only)."""
-    prm = afn_params(k=k, k_max=k_max, w=w, m=m, precision=precision, method=method, seed=0)
-    out = ctypes.c_size_t(0)
-    _check(lib().afn_footprint_bytes(n, d, ctypes.byref(prm), ctypes.byref(out)),
-           "afn_footprint_bytes")
-    return out.value
+                        precision: int = AFN_FP64, method: int = AFN_METHOD_AFN, nrhs_max: int = 64) -> int:
+    """Device memory of afn_setup for these sizes (= afn_workspace_size; host-only)."""
+    return afn_workspace_size(n, d, k=k, w=w, k_max=k_max, m=m, precision=precision, method=method,
+                              nrhs_max=nrhs_max)
 
 
 def afn_apply(h: Handle, r: torch.Tensor, out: torch.Tensor | None = None,
@@ -330,3 +366,65 @@ def afn_pcg_solve(h: Handle, b: torch.Tensor, tol: float = 1e-6, maxit: int = 50
                      relres=inf.relres, relres_true=inf.relres_true, ms_solve=inf.ms_solve,
                      ms_matvec=inf.ms_matvec, matvec_launches=inf.matvec_launches,
                      outer_iterations=inf.outer_iterations, fp64_iterations=inf.fp64_iterations)
+
+
+class PcgState:
+    """A step-wise solve (afn_pcg_begin); release with end()."""
+
+    def __init__(self, ptr: ctypes.c_void_p, handle: Handle, b: torch.Tensor, x: torch.Tensor):
+        self._ptr = ptr
+        self.handle, self.b, self.x = handle, b, x    # kept alive until the solve ends
+
+    @property
+    def ptr(self):
+        if not self._ptr:
+            raise RuntimeError("state is ended")
+        return self._ptr
+
+    def query(self):
+        """(done, info dict); info["status"] is the solve's status once done."""
+        done = _I32(0)
+        inf = afn_solve_info()
+        st = lib().afn_pcg_query(self.ptr, ctypes.byref(done), ctypes.byref(inf))
+        if st == AFN_EINVAL:
+            raise AFNError(st, "afn_pcg_query")
+        return bool(done.value), dict(status=st, iterations=inf.iterations, converged=bool(inf.converged),
+                                      relres=inf.relres, relres_true=inf.relres_true, ms_solve=inf.ms_solve,
+                                      ms_matvec=inf.ms_matvec, matvec_launches=inf.matvec_launches,
+                                      outer_iterations=inf.outer_iterations,
+                                      fp64_iterations=inf.fp64_iterations)
+
+    def end(self):
+        if self._ptr:
+            lib().afn_pcg_end(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.end()
+        except Exception:
+            pass
+
+
+def afn_pcg_begin(h: Handle, b: torch.Tensor, tol: float = 1e-6, maxit: int = 500,
+                  out: torch.Tensor | None = None, stream=None) -> PcgState:
+    """Start a step-wise solve of one right-hand side (queued, not waited for)."""
+    bp, nrhs, _ = _colmajor(b, "b")
+    if nrhs != 1 or b.shape[0] != h.n:
+        raise ValueError("b must be one vector of length n")
+    if out is None:
+        out = torch.empty_like(b)
+    xp, _, _ = _colmajor(out, "out")
+    ptr = ctypes.c_void_p()
+    _check(lib().afn_pcg_begin(h.ptr, bp, xp, tol, maxit, _stream(stream), ctypes.byref(ptr)),
+           "afn_pcg_begin")
+    return PcgState(ptr, h, b, out)
+
+
+def afn_pcg_step_many(states, iters: int = 1, stream=None) -> None:
+    """Advance every unfinished state by up to iters products with K + mu I,
+    one host wait per round for all of them; stream None: each state on the
+    stream it was begun on."""
+    arr = (ctypes.c_void_p * len(states))(*[s.ptr for s in states])
+    sp = ctypes.c_void_p(None) if stream is None else _stream(stream)
+    _check(lib().afn_pcg_step_many(arr, len(states), iters, sp), "afn_pcg_step_many")

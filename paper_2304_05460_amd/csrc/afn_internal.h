@@ -50,15 +50,19 @@ __device__ __forceinline__ int64_t xcd_contiguous(int64_t b, int64_t G)
     return start + j;
 }
 
-// Device buffer list owned by a handle.
+// Device memory of a handle: a bump allocator over one region (the caller's
+// workspace, or one block the library allocated for the handle).  Buffers
+// start on 256-byte boundaries; temporaries of the setup are carved like
+// everything else and never reclaimed, so the region's size bounds the sum
+// of every allocation (afn_workspace_size).
 struct DevArena {
-    std::vector<void *> ptrs;
+    char *base = nullptr;
+    size_t cap = 0, off = 0, high = 0;
     afn_status alloc(void **p, size_t bytes);
     template <class T>
     afn_status alloc_n(T **p, int64_t count) {
         return alloc(reinterpret_cast<void **>(p), sizeof(T) * (size_t)(count > 0 ? count : 1));
     }
-    void release();
 };
 
 // Per-device scratch for entry points that do not own a handle.  Grows on
@@ -320,7 +324,9 @@ afn_status scatter_rows_f32(const float *Y, int64_t n, int R, double *X, int64_t
                             hipStream_t s);
 afn_status sub_rows_launch(const double *B, const double *Y, double *Rr, int64_t total,
                            hipStream_t s);
-// Block solve (R <= 64, d <= 8, FP32 copies present); see block.hip.
+// Block solve (R <= 64, d <= 8, FP32 copies present); see block.hip.  Its
+// workspace for R columns is carved at setup: block_workspace_bytes bytes.
+size_t block_workspace_bytes(int64_t n, int d, int64_t k, int R);
 afn_status block_refine_solve(afn_handle *h, const double *B, int64_t ld, double *Xout, int R,
                               double tol, int maxit, hipStream_t s, int *iters, int *outer,
                               double *relres_max, int *conv_all, int *col_ok);
@@ -375,8 +381,12 @@ struct afn_handle {
     double *Rginv = nullptr;
     float *W32 = nullptr;
     float *Rginv32 = nullptr;
-    void *mrhs_ws = nullptr;    // workspace of block solves (allocated on first use)
-    size_t mrhs_bytes = 0;
+    void *mrhs_ws = nullptr;    // workspace of block solves (carved at setup)
+    int nrhs_block = 0;         // columns it holds (0: no block solves)
+    hipStream_t block_stream = nullptr;  // stream of the graph-captured block solve
+    hipEvent_t block_ev = nullptr;
+    void *ws_owned = nullptr;   // the workspace, when the library allocated it
+    bool active = false;        // a step-wise solve (afn_pcg_state) is started
     double *host_sc = nullptr;  // pinned host copy of PCG scalars
     hipEvent_t kmv_ev[2] = {nullptr, nullptr};  // timing of the matvec tile kernel
     hipEvent_t chk_ev = nullptr;                // the PCG residual check's host copy

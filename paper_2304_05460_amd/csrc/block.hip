@@ -29,10 +29,10 @@ struct BlockWs {
     int *active, *count, *bad;
 };
 
-size_t block_ws(const afn_handle *h, int R, BlockWs *w, char *base)
+size_t block_ws_layout(int64_t n, int d, int64_t k, int R, BlockWs *w, char *base)
 {
-    const int64_t n = h->n, nr = h->nr, k = h->k;
-    const int64_t npad = kmv_packed_doubles(n, h->d) / h->d;
+    const int64_t nr = n - k;
+    const int64_t npad = kmv_packed_doubles(n, d) / d;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         char *p = base ? base + off : nullptr;
@@ -84,6 +84,11 @@ size_t block_ws(const afn_handle *h, int R, BlockWs *w, char *base)
     t.bad = (int *)take(4 * 4);
     if (w) *w = t;
     return off;
+}
+
+size_t block_ws(const afn_handle *h, int R, BlockWs *w, char *base)
+{
+    return block_ws_layout(h->n, h->d, h->k, R, w, base);
 }
 
 __global__ void init_active(const double *bn2, int *active, int R)
@@ -216,6 +221,11 @@ afn_status inner_block(afn_handle *h, int R, int maxit, const BlockWs &w, hipStr
 
 }  // namespace
 
+size_t block_workspace_bytes(int64_t n, int d, int64_t k, int R)
+{
+    return block_ws_layout(n, d, k, R, nullptr, nullptr);
+}
+
 afn_status block_refine_solve(afn_handle *h, const double *B, int64_t ld, double *Xout, int R,
                               double tol, int maxit, hipStream_t user_s, int *iters, int *outer,
                               double *relres_max, int *conv_all, int *col_ok)
@@ -225,40 +235,20 @@ afn_status block_refine_solve(afn_handle *h, const double *B, int64_t ld, double
     // every early return leaves the columns marked unsolved, so the caller
     // re-solves them one at a time
     for (int c = 0; c < R; ++c) col_ok[c] = 0;
-    const size_t need = block_ws(h, R, nullptr, nullptr);
-    if (h->mrhs_bytes < need) {
-        if (h->mrhs_ws) {
-            AFN_HIP(hipDeviceSynchronize());
-            AFN_HIP(hipFree(h->mrhs_ws));
-            h->mrhs_ws = nullptr;
-            h->mrhs_bytes = 0;
-        }
-        hipError_t e = hipMalloc(&h->mrhs_ws, need);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            h->mrhs_ws = nullptr;
-            set_error("block solve: hipMalloc(%zu) failed", need);
-            return AFN_ENOMEM;
-        }
-        h->mrhs_bytes = need;
+    if (R > h->nrhs_block || !h->mrhs_ws || !h->block_stream) {
+        set_error("block solve: %d columns, but the handle's block workspace holds %d", R, h->nrhs_block);
+        return AFN_EINVAL;
     }
     BlockWs w;
     block_ws(h, R, &w, (char *)h->mrhs_ws);
-    // a library-owned stream (default priority) ordered after the caller's
-    hipStream_t s = nullptr;
-    hipEvent_t ev = nullptr;
-    AFN_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    // the handle's own stream (default priority; created at setup), ordered
+    // after the caller's and the caller's after it
+    hipStream_t s = h->block_stream;
+    hipEvent_t ev = h->block_ev;
     struct StreamGuard {
         hipStream_t s;
-        hipEvent_t *ev;
-        ~StreamGuard()
-        {
-            (void)hipStreamSynchronize(s);
-            (void)hipStreamDestroy(s);
-            if (*ev) (void)hipEventDestroy(*ev);
-        }
-    } sg{s, &ev};
-    AFN_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        ~StreamGuard() { (void)hipStreamSynchronize(s); }
+    } sg{s};
     AFN_HIP(hipEventRecord(ev, user_s));
     AFN_HIP(hipStreamWaitEvent(s, ev, 0));
 

@@ -1,6 +1,7 @@
 // C-ABI of libafn: preconditioner construction (Algorithm 2), application
 // (Algorithm 3) and preconditioned CG (Algorithm 5, AFN branch).
 #include <cfloat>
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -15,7 +16,8 @@ namespace afn {
 // Rank estimation (Algorithm 4); defined in rank.hip.
 afn_status uniform_landmarks(int64_t n, int k, uint64_t seed, int32_t *idx, hipStream_t s);
 afn_status rank_estimate(const double *X, int64_t n, int d, double l, int kind, double mu, int m,
-                         int kmax, uint64_t seed, hipStream_t s, afn_setup_info *info, int *k_out);
+                         int kmax, uint64_t seed, DevArena &tmp, hipStream_t s, afn_setup_info *info,
+                         int *k_out);
 
 namespace {
 
@@ -290,6 +292,89 @@ afn_status nystrom_factors(afn_handle *h, DevArena &tmp, Timer &tm, hipStream_t 
     return AFN_OK;
 }
 
+// Columns of the block-solve workspace a setup provisions (0: none).
+int block_columns(const afn_params *prm, int d)
+{
+    if (prm->precision != AFN_FP32 || d > 8 || prm->nrhs_max < 2) return 0;
+    return prm->nrhs_max < 64 ? prm->nrhs_max : 64;
+}
+
+// Bytes setup_impl carves from the workspace when it ends with k landmarks
+// and the given method: the same allocations in the same order (each starts
+// on a 256-byte boundary), the temporaries included.  rank_m > 0: the rank
+// estimation ran on a subsample of rank_m points (its eigenvalue branch
+// included).
+size_t setup_carve_bytes(int64_t n, int d, int64_t k, int rank_m, int w, const afn_params *prm, int method)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) { off = (size_t)round_up((int64_t)off, 256) + bytes; };
+    auto n8 = [](int64_t c) { return (size_t)8 * (size_t)(c > 0 ? c : 1); };
+    auto n4 = [](int64_t c) { return (size_t)4 * (size_t)(c > 0 ? c : 1); };
+    const int64_t nr = n - k, kk = k * k;
+    const bool f32 = prm->precision == AFN_FP32;
+    take(n4(16));                                            // flags
+    if (rank_m > 0) {
+        const int64_t m = rank_m;
+        take(n4(m)); take(n4(m)); take(n8(m * d)); take(n8(m * m)); take(n8(m)); take(n8(4));
+        take(n8(256)); take(n8(m + 1)); take(n4(1)); take(fps_workspace_bytes(m));
+        take(n8(2 * m)); take(n8(2 * m)); take(n8(8)); take(n4(1)); take(n8(2 * (ceil_div(m, 4) + 1)));
+        take(n8(m)); take(n8(m));
+    }
+    take(n4(n)); take(n4(k)); take(fps_workspace_bytes(n)); take(n4(n)); take(n8(n * d));   // perm, FPS, Xp
+    if (method == AFN_METHOD_NYSTROM) {
+        if (k > 0) {
+            take(n8(kk)); take(n8(dinv_doubles((int)k))); take(n8(k * n));
+            take(n8(dot_partials(kk > k * nr ? kk : k * nr))); take(n8(2));
+            take(n8(kk)); take(n8(dinv_doubles((int)k))); take(n8(gemm_part_elems(k, n))); take(n8(kk));
+        }
+    } else {
+        if (k > 0) { take(n8(kk)); take(n8(kk)); take(n8(dinv_doubles((int)k))); }
+        if (nr > 0 && d <= 10) { take(n4(nr)); take(spatial_order_work_bytes(nr, d)); }
+        if (nr > 0) { take(n4(nr * w)); take(knn_work_bytes(nr, d)); }
+        if (k > 0 && nr > 0) take(n8(k * nr));
+        if (nr > 0) {
+            take(n8(nr * w));
+            if (d > 10) take(n8(fsai_batch_doubles((int)k, w)));
+            take(n8(nr + 1)); take(n4(nr * w)); take(n8(nr * w)); take(fsai_transpose_work_bytes(nr, w));
+        }
+    }
+    if (d <= 8) {
+        take(n4(n)); take(spatial_order_work_bytes(n, d)); take(n8(kmv_packed_doubles(n, d)));
+        take(n8(kmv_box_count(n, d))); take(n8(6));
+    }
+    if (f32) {
+        take(n4(kmv_packed_doubles(n, d))); take(n4(kmv_box_count(n, d)));
+        if (method == AFN_METHOD_NYSTROM && k > 0) { take(n4(k * n)); take(n4(kk)); }
+        if (method != AFN_METHOD_NYSTROM && k > 0) take(n4(kk));
+        if (method != AFN_METHOD_NYSTROM && k > 0 && nr > 0) take(n4(k * nr));
+        if (method != AFN_METHOD_NYSTROM && nr > 0) { take(n4(nr * w)); take(n4(nr * w)); }
+        take(n4(work32_floats(n, d, (int)k, nr, nullptr, nullptr)));
+    }
+    take(n8(work_doubles(n, d, (int)k, nr, nullptr, nullptr)));
+    const int rb = block_columns(prm, d);
+    if (rb >= 2) take(block_workspace_bytes(n, d, k, rb));
+    return (size_t)round_up((int64_t)off, 256);
+}
+
+// afn_workspace_size: the largest carve over every landmark count and method
+// the setup can end with.
+size_t workspace_bytes(int64_t n, int d, const afn_params *prm)
+{
+    const int64_t kmax = prm->k_max > 0 ? prm->k_max : 2000;
+    const int m = prm->k >= 0 ? 0 : (int)(prm->m > 0 ? (prm->m < n ? prm->m : n) : (n < 2000 ? n : 2000));
+    const int64_t klo = prm->k >= 0 ? prm->k : 1;
+    const int64_t khi = prm->k >= 0 ? prm->k : (kmax < n ? kmax : n);
+    size_t best = 0;
+    for (int meth = AFN_METHOD_AFN; meth <= AFN_METHOD_NYSTROM; ++meth) {
+        if (prm->method != AFN_METHOD_AUTO && prm->method != meth) continue;
+        for (int64_t k = klo; k <= khi; ++k) {
+            const size_t b = setup_carve_bytes(n, d, k, m, prm->w, prm, meth);
+            best = b > best ? b : best;
+        }
+    }
+    return best;
+}
+
 afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, const afn_params *prm,
                       hipStream_t s, afn_handle *h)
 {
@@ -314,7 +399,7 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     if (k < 0) {
         const int m = prm->m > 0 ? (int)(prm->m < n ? prm->m : n) : (int)(n < 2000 ? n : 2000);
         const int kmax = prm->k_max > 0 ? prm->k_max : 2000;
-        AFN_TRY(rank_estimate(X, n, d, l, h->kind, mu, m, kmax, prm->seed, s, &h->info, &k));
+        AFN_TRY(rank_estimate(X, n, d, l, h->kind, mu, m, kmax, prm->seed, h->arena, s, &h->info, &k));
     }
     tm.mark(1, s);
     // Algorithm 5: the rank decides between AFN and Nystrom
@@ -332,12 +417,8 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     h->k = k;
     h->nr = n - k;
     const int64_t nr = h->nr;
-    // FPS and the block order
-    DevArena tmp;
-    struct TmpGuard {
-        DevArena &a;
-        ~TmpGuard() { a.release(); }
-    } guard{tmp};
+    // FPS and the block order (temporaries are carved from the same workspace)
+    DevArena &tmp = h->arena;
     AFN_TRY(h->arena.alloc_n(&h->perm, n));
     int32_t *idx = nullptr;
     void *fws = nullptr;
@@ -399,9 +480,7 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
         AFN_TRY(h->arena.alloc_n(&h->gval, nr * h->w));
         // above d = 10 the pattern neighbourhoods share few columns, so each
         // row's columns of V are recomputed in batches rather than gathered
-        // (AFN_FSAI_RECOMPUTE=0/1 overrides the choice)
-        const char *fr = std::getenv("AFN_FSAI_RECOMPUTE");
-        const bool recompute = fr && (fr[0] == '0' || fr[0] == '1') ? fr[0] == '1' : d > 10;
+        const bool recompute = d > 10;
         if (recompute) {
             double *fb = nullptr;
             AFN_TRY(tmp.alloc_n(&fb, fsai_batch_doubles(k, h->w)));
@@ -484,6 +563,15 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     // workspace for apply / PCG
     h->work_doubles = work_doubles(n, d, k, nr, nullptr, nullptr);
     AFN_TRY(h->arena.alloc_n(&h->work, h->work_doubles));
+    // block solves of several right-hand sides (FP32 copies, d <= 8)
+    h->nrhs_block = 0;
+    const int rb = block_columns(prm, d);
+    if (rb >= 2) {
+        AFN_TRY(h->arena.alloc(&h->mrhs_ws, block_workspace_bytes(n, d, k, rb)));
+        AFN_HIP(hipStreamCreateWithFlags(&h->block_stream, hipStreamNonBlocking));
+        AFN_HIP(hipEventCreateWithFlags(&h->block_ev, hipEventDisableTiming));
+        h->nrhs_block = rb;
+    }
     AFN_HIP(hipHostMalloc((void **)&h->host_sc, 16 * sizeof(double), hipHostMallocDefault));
     AFN_HIP(hipEventCreate(&h->kmv_ev[0]));
     AFN_HIP(hipEventCreate(&h->kmv_ev[1]));
@@ -507,55 +595,9 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     inf.ms_fsai = tm.ms(5, 6);
     inf.ms_total = tm.ms(0, 7);
     inf.method = h->method;
+    inf.ws_bytes = (int64_t)h->arena.cap;
+    inf.ws_bytes_used = (int64_t)h->arena.high;
     return AFN_OK;
-}
-
-// FP64 PCG iterations from the state x = w.x, r = w.r = b - (K + mu I) x (block
-// order): stops when ||r|| <= tol * bnorm (recurrence residual), on a
-// breakdown, or after maxit products.
-afn_status pcg64_iterate(afn_handle *h, double bnorm, double tol, int maxit, const WorkLayout &w,
-                         hipStream_t s, int *iters, double *relres, double *ms_kmv, int *n_kmv)
-{
-    const int64_t n = h->n;
-    double *sc = w.sc;
-    double *hs = h->host_sc;
-    AFN_TRY(apply_block(h, w.r, w.z, w, s));
-    AFN_HIP(hipMemcpyAsync(w.p, w.z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    AFN_TRY(dot(w.r, n, w.z, n, n, 1, sc + 0, w.dotp, s));
-    *iters = 0;
-    for (int it = 0; it < maxit; ++it) {
-        AFN_TRY(op_f64(h, w.p, w.q, w, s, h->kmv_ev[0], h->kmv_ev[1]));
-        AFN_TRY(dot_pcg(w.p, w.q, n, sc, kPcgAlpha, w.dotp, s));
-        AFN_TRY(pcg_xr_launch(w.x, w.r, w.p, w.q, sc, n, w.dotp, sc + 2, s));
-        AFN_HIP(hipMemcpyAsync(hs + 1, sc + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-        AFN_HIP(hipEventRecord(h->chk_ev, s));
-        // z = M^{-1} r and r'z go on the stream before the host reads the
-        // residual (x, r and p stay as they are, so a check that ends the
-        // loop discards only z): the device never waits for the host
-        if (it + 1 < maxit) {
-            AFN_TRY(apply_block(h, w.r, w.z, w, s));
-            AFN_TRY(dot_pcg(w.r, w.z, n, sc, kPcgBeta, w.dotp, s));
-        }
-        AFN_HIP(hipEventSynchronize(h->chk_ev));
-        {
-            float t = 0.f;
-            if (hipEventElapsedTime(&t, h->kmv_ev[0], h->kmv_ev[1]) == hipSuccess) {
-                *ms_kmv += t;
-                *n_kmv += 1;
-            }
-        }
-        *iters = it + 1;
-        const double pq = hs[1];
-        const double rel = std::sqrt(hs[2]) / bnorm;
-        *relres = rel;
-        if (!(pq > 0.0) || !(rel == rel)) {
-            set_error("afn_pcg_solve: breakdown at iteration %d (p'Ap = %g)", it + 1, pq);
-            return AFN_EBREAKDOWN;
-        }
-        if (rel <= tol) return AFN_OK;
-        AFN_TRY(pcg_p_launch(w.p, w.z, sc, n, s));
-    }
-    return AFN_ENOCONV;
 }
 
 // ||b - (K + mu I) x|| / bnorm in FP64 (block order; w.tmp clobbered).
@@ -571,217 +613,375 @@ afn_status true_relres(afn_handle *h, double bnorm, const WorkLayout &w, hipStre
     return AFN_OK;
 }
 
-afn_status pcg_one(afn_handle *h, const double *b, double *xout, double tol, int maxit,
-                   const WorkLayout &w, hipStream_t s, int *iters, double *relres,
-                   double *relres_true, int *converged, double *ms_kmv, int *n_kmv)
+}  // namespace
+}  // namespace afn
+
+// One single-right-hand-side solve, advanced a product at a time.  Every
+// solve path goes through it: afn_pcg_solve column by column and the
+// step-wise API, so both take the same launches in the same order.
+//
+// FP64 handle: textbook PCG from x0 = 0 (Algorithm 5's solve), stopping at
+// ||r|| / ||b|| <= tol (recurrence), a breakdown, or maxit products.
+// AFN_FP32 handle: iterative refinement -- x0 = 0; r = b - (K + mu I) x in
+// FP64; a correction e from an inner FP32 PCG on r / ||r|| (FP32 operator,
+// apply and vectors, FP64 scalars) stopped at what the step needs but no
+// lower than 3e-2 of its start; x += ||r|| e; stop when the FP64 ||r|| / ||b||
+// <= tol.  A correction that raised the FP64 residual is taken back, and
+// textbook FP64 PCG finishes from the best iterate when the corrections stop
+// halving the residual, an inner solve breaks down, 40 steps are used, or
+// the inner products pass 4 maxit.
+//
+// Each round queues the next unit of work (begin: the norm of b; an FP64 or
+// FP32 PCG iteration, with the next preconditioner apply queued behind the
+// residual copy; a refinement step's residual norm) ending in an event; the
+// host then waits on the event and takes the stopping decision, queueing
+// what the decision implies.
+struct afn_pcg_state {
+    enum Phase { kStart, kFp64, kOuter, kInner, kDone };
+    afn_handle *h = nullptr;
+    const double *b = nullptr;
+    double *xout = nullptr;
+    double tol = 0.0;
+    int maxit = 0;
+    Phase phase = kStart;
+    bool mixed = false;
+    afn::WorkLayout w{};
+    afn::WorkLayout32 w32{};
+    double bnorm = 0.0;
+    // FP64 PCG (also the fallback of a mixed solve)
+    int it64 = 0;
+    bool p_pending = false;   // p = z + beta p is due before the next product
+    bool fp64_started = false;
+    // refinement
+    int outer = 0;            // refinement steps begun
+    int inner_total = 0;
+    int inner_it = 0;
+    double tol_in = 0.0, rnorm = 0.0, prev = INFINITY;
+    bool fallback = false, fallback_redo = false;
+    // result
+    afn_status status = AFN_OK;
+    double relres = 0.0, relres_true = 0.0;
+    int converged = 0;
+    double ms_kmv = 0.0;
+    int n_kmv = 0;
+    double t_begin = 0.0, t_end = 0.0;
+    hipStream_t stream = nullptr;   // the stream given to afn_pcg_begin
+};
+
+namespace afn {
+namespace {
+
+double host_ms()
 {
-    const int64_t n = h->n;
-    double *sc = w.sc;
-    double *hs = h->host_sc;
-    AFN_TRY(permute_gather(b, n, w.bp, n, h->perm, n, 1, s));
-    AFN_TRY(dot(w.bp, n, w.bp, n, n, 1, sc + 6, w.dotp, s));
-    AFN_HIP(hipMemsetAsync(w.x, 0, sizeof(double) * n, s));
-    AFN_HIP(hipMemcpyAsync(w.r, w.bp, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    AFN_HIP(hipMemcpyAsync(hs + 6, sc + 6, sizeof(double), hipMemcpyDeviceToHost, s));
-    AFN_HIP(hipStreamSynchronize(s));
-    const double bnorm = std::sqrt(hs[6]);
-    *iters = 0;
-    *relres = 0.0;
-    *relres_true = 0.0;
-    *converged = 1;
-    if (!(bnorm > 0.0)) {
-        if (!(bnorm == 0.0)) {
-            set_error("afn_pcg_solve: right-hand side holds a non-finite value");
-            *converged = 0;
-            *relres = NAN;
-            AFN_TRY(permute_scatter(w.x, n, xout, n, h->perm, n, 1, s));
-            return AFN_EBREAKDOWN;
-        }
-        AFN_TRY(permute_scatter(w.x, n, xout, n, h->perm, n, 1, s));
-        return AFN_OK;
-    }
-    *converged = 0;
-    *relres = 1.0;
-    const afn_status status = pcg64_iterate(h, bnorm, tol, maxit, w, s, iters, relres, ms_kmv, n_kmv);
-    *converged = status == AFN_OK ? 1 : 0;
-    AFN_TRY(true_relres(h, bnorm, w, s, relres_true));
-    AFN_TRY(permute_scatter(w.x, n, xout, n, h->perm, n, 1, s));
-    AFN_HIP(hipStreamSynchronize(s));
-    if (status == AFN_ENOCONV)
-        set_error("afn_pcg_solve: no convergence in %d iterations (relres %g)", maxit, *relres);
-    return status;
+    return 1e3 * (double)std::chrono::duration_cast<std::chrono::nanoseconds>(
+                     std::chrono::steady_clock::now().time_since_epoch()).count() * 1e-9;
 }
 
-// Inner PCG in FP32 (operator, preconditioner and vectors), FP64 scalars:
-// solve (K + mu I) e = r0 to relative recurrence residual tol_in.  r0 in w32.r
-// on entry (overwritten), e in w32.e on exit.  sc: 8 device scalar slots.
-afn_status pcg_inner32(afn_handle *h, double r0norm, double tol_in, int maxit, const WorkLayout32 &w,
-                       double *dotp, double *sc, hipStream_t s, int *iters, double *rel_out,
-                       double *ms_kmv, int *n_kmv)
+void take_kmv_time(afn_pcg_state *st)
 {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, st->h->kmv_ev[0], st->h->kmv_ev[1]) == hipSuccess) {
+        st->ms_kmv += t;
+        st->n_kmv += 1;
+    }
+}
+
+// x back to the original order, the true FP64 residual, the end of the solve.
+afn_status finish(afn_pcg_state *st, afn_status status, bool true_res, hipStream_t s)
+{
+    afn_handle *h = st->h;
+    if (true_res) AFN_TRY(true_relres(h, st->bnorm, st->w, s, &st->relres_true));
+    AFN_TRY(permute_scatter(st->w.x, h->n, st->xout, h->n, h->perm, h->n, 1, s));
+    AFN_HIP(hipStreamSynchronize(s));
+    st->status = status;
+    st->converged = status == AFN_OK ? 1 : 0;
+    st->phase = afn_pcg_state::kDone;
+    st->t_end = host_ms();
+    return AFN_OK;
+}
+
+// FP64 PCG: its start (z = M^{-1} r, p = z, r'z) from the current x and r.
+afn_status fp64_start(afn_pcg_state *st, hipStream_t s)
+{
+    afn_handle *h = st->h;
+    const WorkLayout &w = st->w;
+    AFN_TRY(apply_block(h, w.r, w.z, w, s));
+    AFN_HIP(hipMemcpyAsync(w.p, w.z, sizeof(double) * h->n, hipMemcpyDeviceToDevice, s));
+    AFN_TRY(dot(w.r, h->n, w.z, h->n, h->n, 1, w.sc + 0, w.dotp, s));
+    st->fp64_started = true;
+    st->p_pending = false;
+    st->it64 = 0;
+    return AFN_OK;
+}
+
+// One FP64 PCG iteration up to the residual copy, then the next apply.
+afn_status fp64_queue(afn_pcg_state *st, hipStream_t s)
+{
+    afn_handle *h = st->h;
+    const WorkLayout &w = st->w;
     const int64_t n = h->n;
-    double *hs = h->host_sc;
-    AFN_HIP(hipMemsetAsync(w.e, 0, sizeof(float) * n, s));
-    AFN_TRY(apply_block32(h, w.r, w.z, w, s));
-    AFN_HIP(hipMemcpyAsync(w.p, w.z, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
-    AFN_TRY(dot(w.r, n, w.z, n, n, 1, sc + 0, dotp, s));
-    *iters = 0;
-    *rel_out = 1.0;
-    for (int it = 0; it < maxit; ++it) {
-        AFN_TRY(kmv_packed_f32(h->Xs32, n, h->d, h->mu, h->kind, w.p, n, w.q, n, 1, w.kmv, s, h->kmv_ev[0],
-                               h->kmv_ev[1], h->kperm, h->box32));
-        AFN_TRY(dot_pcg(w.p, w.q, n, sc, kPcgAlpha, dotp, s));
-        AFN_TRY(pcg_xr_launch(w.e, w.r, w.p, w.q, sc, n, dotp, sc + 2, s));
-        AFN_HIP(hipMemcpyAsync(hs + 9, sc + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-        AFN_HIP(hipEventRecord(h->chk_ev, s));
-        // the next z = M^{-1} r and r'z are queued before the check (as in
-        // the FP64 loop)
-        if (it + 1 < maxit) {
-            AFN_TRY(apply_block32(h, w.r, w.z, w, s));
-            AFN_TRY(dot_pcg(w.r, w.z, n, sc, kPcgBeta, dotp, s));
-        }
-        AFN_HIP(hipEventSynchronize(h->chk_ev));
-        float t = 0.f;
-        if (hipEventElapsedTime(&t, h->kmv_ev[0], h->kmv_ev[1]) == hipSuccess) {
-            *ms_kmv += t;
-            *n_kmv += 1;
-        }
-        *iters = it + 1;
-        const double pq = hs[9];
-        const double rel = std::sqrt(hs[10]) / r0norm;
-        *rel_out = rel;
-        if (!(pq > 0.0) || !(rel == rel)) {
-            set_error("afn_pcg_solve: inner FP32 breakdown at iteration %d (p'Ap = %g)", it + 1, pq);
-            return AFN_EBREAKDOWN;
-        }
-        if (rel <= tol_in) break;
-        AFN_TRY(pcg_p_launch(w.p, w.z, sc, n, s));
+    if (!st->fp64_started) AFN_TRY(fp64_start(st, s));
+    if (st->p_pending) AFN_TRY(pcg_p_launch(w.p, w.z, w.sc, n, s));
+    st->p_pending = false;
+    AFN_TRY(op_f64(h, w.p, w.q, w, s, h->kmv_ev[0], h->kmv_ev[1]));
+    AFN_TRY(dot_pcg(w.p, w.q, n, w.sc, kPcgAlpha, w.dotp, s));
+    AFN_TRY(pcg_xr_launch(w.x, w.r, w.p, w.q, w.sc, n, w.dotp, w.sc + 2, s));
+    AFN_HIP(hipMemcpyAsync(h->host_sc + 1, w.sc + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    AFN_HIP(hipEventRecord(h->chk_ev, s));
+    // z = M^{-1} r and r'z go on the stream before the host reads the
+    // residual (x, r and p stay as they are, so a check that ends the solve
+    // discards only z): the device never waits for the host
+    if (st->it64 + 1 < st->maxit) {
+        AFN_TRY(apply_block(h, w.r, w.z, w, s));
+        AFN_TRY(dot_pcg(w.r, w.z, n, w.sc, kPcgBeta, w.dotp, s));
     }
     return AFN_OK;
 }
 
-// Iterative refinement: x_0 = 0; r = b - (K + mu I) x in FP64; correction
-// from the FP32 inner PCG on r / ||r||; stop when ||r|| / ||b|| <= tol.
-afn_status pcg_refine(afn_handle *h, const double *b, double *xout, double tol, int maxit,
-                      const WorkLayout &w, const WorkLayout32 &w32, hipStream_t s, int *iters,
-                      int *outer, int *iters64, double *relres, double *relres_true, int *converged,
-                      double *ms_kmv, int *n_kmv)
+afn_status fp64_decide(afn_pcg_state *st, hipStream_t s)
 {
-    *iters64 = 0;
+    afn_handle *h = st->h;
+    take_kmv_time(st);
+    st->it64 += 1;
+    const double pq = h->host_sc[1];
+    const double rel = std::sqrt(h->host_sc[2]) / st->bnorm;
+    st->relres = rel;
+    if (!(pq > 0.0) || !(rel == rel)) {
+        set_error("afn_pcg_solve: breakdown at iteration %d (p'Ap = %g)", st->it64, pq);
+        return finish(st, AFN_EBREAKDOWN, true, s);
+    }
+    if (rel <= st->tol) return finish(st, AFN_OK, true, s);
+    if (st->it64 >= st->maxit) {
+        set_error("afn_pcg_solve: no convergence in %d iterations (relres %g)", st->maxit, rel);
+        return finish(st, AFN_ENOCONV, true, s);
+    }
+    st->p_pending = true;
+    return AFN_OK;
+}
+
+// Refinement: ||r||^2 of the FP64 residual to the host.
+afn_status outer_queue(afn_pcg_state *st, hipStream_t s)
+{
+    afn_handle *h = st->h;
+    const WorkLayout &w = st->w;
+    AFN_TRY(dot(w.r, h->n, w.r, h->n, h->n, 1, w.sc + 7, w.dotp, s));
+    AFN_HIP(hipMemcpyAsync(h->host_sc + 7, w.sc + 7, sizeof(double), hipMemcpyDeviceToHost, s));
+    AFN_HIP(hipEventRecord(h->chk_ev, s));
+    return AFN_OK;
+}
+
+afn_status outer_decide(afn_pcg_state *st, hipStream_t s)
+{
+    afn_handle *h = st->h;
+    const WorkLayout &w = st->w;
     const int64_t n = h->n;
-    double *sc = w.sc;
-    double *hs = h->host_sc;
-    AFN_TRY(permute_gather(b, n, w.bp, n, h->perm, n, 1, s));
-    AFN_HIP(hipMemsetAsync(w.x, 0, sizeof(double) * n, s));
-    AFN_HIP(hipMemcpyAsync(w.r, w.bp, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    AFN_TRY(dot(w.bp, n, w.bp, n, n, 1, sc + 6, w.dotp, s));
-    AFN_HIP(hipMemcpyAsync(hs + 6, sc + 6, sizeof(double), hipMemcpyDeviceToHost, s));
-    AFN_HIP(hipStreamSynchronize(s));
-    const double bnorm = std::sqrt(hs[6]);
-    *iters = 0;
-    *outer = 0;
-    *relres = 0.0;
-    *relres_true = 0.0;
-    *converged = 1;
-    if (!(bnorm > 0.0)) {
-        AFN_TRY(permute_scatter(w.x, n, xout, n, h->perm, n, 1, s));
-        if (!(bnorm == 0.0)) {
-            set_error("afn_pcg_solve: right-hand side holds a non-finite value");
-            *converged = 0;
-            *relres = NAN;
-            return AFN_EBREAKDOWN;
-        }
+    double rnorm = std::sqrt(h->host_sc[7]);
+    double rel = rnorm / st->bnorm;
+    const int o = st->outer;
+    if (o > 0 && !st->fallback_redo && !(rel <= st->prev)) {
+        // the last FP32 correction made things worse: take it back (x and
+        // its residual were kept in rp / sp) and finish in FP64
+        AFN_HIP(hipMemcpyAsync(w.x, w.rp, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        AFN_HIP(hipMemcpyAsync(w.r, w.sp, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        rel = st->prev;
+        rnorm = st->prev * st->bnorm;
+        st->fallback = true;
+    }
+    st->fallback_redo = false;
+    st->relres = rel;
+    st->relres_true = rel;
+    if (!(rel == rel)) {
+        set_error("afn_pcg_solve: refinement produced a non-finite residual");
+        return finish(st, AFN_EBREAKDOWN, false, s);
+    }
+    if (rel <= st->tol) return finish(st, AFN_OK, false, s);
+    if (o >= 40 || (o >= 3 && rel > 0.5 * st->prev) || st->inner_total >= st->maxit * 4) st->fallback = true;
+    if (st->fallback) {
+        // textbook FP64 PCG from the current x and its FP64 residual
+        st->outer = o + 1;
+        st->phase = afn_pcg_state::kFp64;
+        st->fp64_started = false;
         return AFN_OK;
     }
-    *converged = 0;
-    afn_status status = AFN_ENOCONV;
-    double prev = INFINITY;
-    const int max_outer = 40;
-    bool fallback = false;     // the FP32 corrections stopped helping: finish in FP64
-    for (int o = 0;; ++o) {
-        AFN_TRY(dot(w.r, n, w.r, n, n, 1, sc + 7, w.dotp, s));
-        AFN_HIP(hipMemcpyAsync(hs + 7, sc + 7, sizeof(double), hipMemcpyDeviceToHost, s));
-        AFN_HIP(hipStreamSynchronize(s));
-        double rnorm = std::sqrt(hs[7]);
-        double rel = rnorm / bnorm;
-        if (o > 0 && !(rel <= prev)) {
-            // the last FP32 correction made things worse: take it back (x and
-            // its residual were kept in rp / sp) and finish in FP64
-            AFN_HIP(hipMemcpyAsync(w.x, w.rp, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-            AFN_HIP(hipMemcpyAsync(w.r, w.sp, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-            rel = prev;
-            rnorm = prev * bnorm;
-            fallback = true;
-        }
-        *relres = rel;
-        *relres_true = rel;
-        if (!(rel == rel)) {
-            set_error("afn_pcg_solve: refinement produced a non-finite residual");
-            status = AFN_EBREAKDOWN;
-            break;
-        }
-        if (rel <= tol) {
-            status = AFN_OK;
-            *converged = 1;
-            break;
-        }
-        if (o >= max_outer || (o >= 3 && rel > 0.5 * prev) || *iters >= maxit * 4) fallback = true;
-        if (fallback) {
-            // textbook FP64 PCG from the current x and its FP64 residual
-            int it64 = 0;
-            double rel64 = rel;
-            const afn_status st64 =
-                pcg64_iterate(h, bnorm, tol, maxit, w, s, &it64, &rel64, ms_kmv, n_kmv);
-            *iters64 = it64;
-            *outer = o + 1;
-            double rt = 0.0;
-            AFN_TRY(true_relres(h, bnorm, w, s, &rt));
-            *relres = rel64;
-            *relres_true = rt;
-            if (st64 == AFN_OK) {
-                status = AFN_OK;
-                *converged = 1;
-            } else {
-                status = st64;
-                if (st64 == AFN_ENOCONV)
-                    set_error("afn_pcg_solve: no convergence (FP64 after refinement, relres %g)", rel64);
-            }
-            break;
-        }
-        prev = rel;
-        AFN_HIP(hipMemcpyAsync(w.rp, w.x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-        AFN_HIP(hipMemcpyAsync(w.sp, w.r, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-        // inner tolerance: what this step needs, but at least 3e-2 of its
-        // start: the FP32 operator and apply bound what one step gains in
-        // FP64, and a tighter inner solve spends iterations that the next
-        // refinement step does more cheaply
-        double tol_in = 0.5 * tol / rel;
-        tol_in = tol_in > 3e-2 ? tol_in : 3e-2;
-        tol_in = tol_in < 0.5 ? tol_in : 0.5;
-        AFN_TRY(to_f32_scaled_launch(w.r, 1.0 / rnorm, w32.r, n, s));
-        int it = 0;
-        double rel_in = 0;
-        afn_status st = pcg_inner32(h, 1.0, tol_in, maxit, w32, w.dotp, sc + 8, s, &it, &rel_in,
-                                    ms_kmv, n_kmv);
-        *iters += it;
-        *outer = o + 1;
-        if (st == AFN_EBREAKDOWN) {
-            // the FP32 operator or apply lost definiteness: redo this step in FP64
-            fallback = true;
-            --o;
-            continue;
-        }
-        if (st != AFN_OK) {
-            status = st;
-            break;
-        }
-        AFN_TRY(axpy_f32_into_f64_launch(rnorm, w32.e, w.x, n, s));
+    st->prev = rel;
+    st->rnorm = rnorm;
+    AFN_HIP(hipMemcpyAsync(w.rp, w.x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    AFN_HIP(hipMemcpyAsync(w.sp, w.r, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    // inner tolerance: what this step needs, but at least 3e-2 of its
+    // start: the FP32 operator and apply bound what one step gains in FP64,
+    // and a tighter inner solve spends iterations that the next refinement
+    // step does more cheaply
+    double tol_in = 0.5 * st->tol / rel;
+    tol_in = tol_in > 3e-2 ? tol_in : 3e-2;
+    st->tol_in = tol_in < 0.5 ? tol_in : 0.5;
+    const WorkLayout32 &v = st->w32;
+    AFN_TRY(to_f32_scaled_launch(w.r, 1.0 / rnorm, v.r, n, s));
+    // inner FP32 PCG start on r / ||r||: e = 0, z = M^{-1} r, p = z, r'z
+    AFN_HIP(hipMemsetAsync(v.e, 0, sizeof(float) * n, s));
+    AFN_TRY(apply_block32(h, v.r, v.z, v, s));
+    AFN_HIP(hipMemcpyAsync(v.p, v.z, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+    AFN_TRY(dot(v.r, n, v.z, n, n, 1, w.sc + 8, w.dotp, s));
+    st->inner_it = 0;
+    st->p_pending = false;
+    st->outer = o + 1;
+    st->phase = afn_pcg_state::kInner;
+    return AFN_OK;
+}
+
+afn_status inner_queue(afn_pcg_state *st, hipStream_t s)
+{
+    afn_handle *h = st->h;
+    const WorkLayout32 &v = st->w32;
+    double *sc = st->w.sc + 8;
+    const int64_t n = h->n;
+    if (st->p_pending) AFN_TRY(pcg_p_launch(v.p, v.z, sc, n, s));
+    st->p_pending = false;
+    AFN_TRY(kmv_packed_f32(h->Xs32, n, h->d, h->mu, h->kind, v.p, n, v.q, n, 1, v.kmv, s, h->kmv_ev[0],
+                           h->kmv_ev[1], h->kperm, h->box32));
+    AFN_TRY(dot_pcg(v.p, v.q, n, sc, kPcgAlpha, st->w.dotp, s));
+    AFN_TRY(pcg_xr_launch(v.e, v.r, v.p, v.q, sc, n, st->w.dotp, sc + 2, s));
+    AFN_HIP(hipMemcpyAsync(h->host_sc + 9, sc + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    AFN_HIP(hipEventRecord(h->chk_ev, s));
+    // the next z = M^{-1} r and r'z are queued before the check (as in the
+    // FP64 iteration)
+    if (st->inner_it + 1 < st->maxit) {
+        AFN_TRY(apply_block32(h, v.r, v.z, v, s));
+        AFN_TRY(dot_pcg(v.r, v.z, n, sc, kPcgBeta, st->w.dotp, s));
+    }
+    return AFN_OK;
+}
+
+afn_status inner_decide(afn_pcg_state *st, hipStream_t s)
+{
+    afn_handle *h = st->h;
+    take_kmv_time(st);
+    st->inner_it += 1;
+    st->inner_total += 1;
+    const double pq = h->host_sc[9];
+    const double rel = std::sqrt(h->host_sc[10]);     // relative to ||r / ||r|| || = 1
+    if (!(pq > 0.0) || !(rel == rel)) {
+        // the FP32 operator or apply lost definiteness: redo this step in FP64
+        st->fallback = true;
+        st->fallback_redo = true;
+        st->outer -= 1;
+        st->phase = afn_pcg_state::kOuter;
+        return AFN_OK;
+    }
+    if (rel <= st->tol_in || st->inner_it >= st->maxit) {
+        const WorkLayout &w = st->w;
+        const int64_t n = h->n;
+        AFN_TRY(axpy_f32_into_f64_launch(st->rnorm, st->w32.e, w.x, n, s));
         AFN_TRY(op_f64(h, w.x, w.q, w, s));
         AFN_TRY(sub_launch(w.bp, w.q, w.r, n, s));
+        st->phase = afn_pcg_state::kOuter;
+        return AFN_OK;
     }
-    AFN_TRY(permute_scatter(w.x, n, xout, n, h->perm, n, 1, s));
-    AFN_HIP(hipStreamSynchronize(s));
-    return status;
+    st->p_pending = true;
+    return AFN_OK;
+}
+
+// begin: b into block order, ||b||^2 to the host, x = 0, r = b.
+afn_status state_begin(afn_pcg_state *st, hipStream_t s)
+{
+    afn_handle *h = st->h;
+    const WorkLayout &w = st->w;
+    const int64_t n = h->n;
+    st->t_begin = host_ms();
+    AFN_TRY(permute_gather(st->b, n, w.bp, n, h->perm, n, 1, s));
+    AFN_TRY(dot(w.bp, n, w.bp, n, n, 1, w.sc + 6, w.dotp, s));
+    AFN_HIP(hipMemsetAsync(w.x, 0, sizeof(double) * n, s));
+    AFN_HIP(hipMemcpyAsync(w.r, w.bp, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    AFN_HIP(hipMemcpyAsync(h->host_sc + 6, w.sc + 6, sizeof(double), hipMemcpyDeviceToHost, s));
+    AFN_HIP(hipEventRecord(h->chk_ev, s));
+    return AFN_OK;
+}
+
+afn_status start_decide(afn_pcg_state *st, hipStream_t s)
+{
+    st->bnorm = std::sqrt(st->h->host_sc[6]);
+    if (!(st->bnorm > 0.0)) {
+        if (!(st->bnorm == 0.0)) {
+            set_error("afn_pcg_solve: right-hand side holds a non-finite value");
+            st->relres = NAN;
+            return finish(st, AFN_EBREAKDOWN, false, s);
+        }
+        return finish(st, AFN_OK, false, s);
+    }
+    st->relres = 1.0;
+    st->phase = st->mixed ? afn_pcg_state::kOuter : afn_pcg_state::kFp64;
+    return AFN_OK;
+}
+
+// Queue the next unit of work of an unfinished solve (ends with chk_ev).
+afn_status state_queue(afn_pcg_state *st, hipStream_t s)
+{
+    switch (st->phase) {
+        case afn_pcg_state::kStart: return AFN_OK;    // begin queued the norm of b
+        case afn_pcg_state::kFp64: return fp64_queue(st, s);
+        case afn_pcg_state::kOuter: return outer_queue(st, s);
+        case afn_pcg_state::kInner: return inner_queue(st, s);
+        default: return AFN_OK;
+    }
+}
+
+afn_status state_decide(afn_pcg_state *st, hipStream_t s)
+{
+    AFN_HIP(hipEventSynchronize(st->h->chk_ev));
+    switch (st->phase) {
+        case afn_pcg_state::kStart: return start_decide(st, s);
+        case afn_pcg_state::kFp64: return fp64_decide(st, s);
+        case afn_pcg_state::kOuter: return outer_decide(st, s);
+        case afn_pcg_state::kInner: return inner_decide(st, s);
+        default: return AFN_OK;
+    }
+}
+
+// A unit of work counts as a product with K + mu I except the start and
+// the refinement's residual norm (whose FP64 product was queued with the
+// previous inner step).
+bool counts_as_product(const afn_pcg_state *st)
+{
+    return st->phase == afn_pcg_state::kFp64 || st->phase == afn_pcg_state::kInner;
+}
+
+afn_status state_init(afn_handle *h, const double *b, double *x, double tol, int maxit, afn_pcg_state *st)
+{
+    st->h = h;
+    st->b = b;
+    st->xout = x;
+    st->tol = tol;
+    st->maxit = maxit;
+    st->mixed = h->precision == AFN_FP32;
+    work_doubles(h->n, h->d, h->k, h->nr, &st->w, h->work);
+    if (st->mixed) work32_floats(h->n, h->d, h->k, h->nr, &st->w32, h->work32);
+    return AFN_OK;
+}
+
+void state_info(const afn_pcg_state *st, afn_solve_info *info)
+{
+    info->iterations = st->mixed ? st->inner_total : st->it64;
+    info->converged = st->converged;
+    info->relres = st->relres;
+    info->relres_true = st->relres_true;
+    info->ms_solve = (st->phase == afn_pcg_state::kDone ? st->t_end : host_ms()) - st->t_begin;
+    info->ms_matvec = st->ms_kmv;
+    info->matvec_launches = st->n_kmv;
+    info->outer_iterations = st->mixed ? st->outer : 0;
+    info->fp64_iterations = st->mixed ? (st->fallback ? st->it64 : 0) : 0;
+    info->reserved = 0;
+}
+
+// Run one solve to its end on stream s (afn_pcg_solve's column loop).
+afn_status solve_one(afn_handle *h, const double *b, double *x, double tol, int maxit, hipStream_t s,
+                     afn_pcg_state *st)
+{
+    AFN_TRY(state_init(h, b, x, tol, maxit, st));
+    AFN_TRY(state_begin(st, s));
+    while (st->phase != afn_pcg_state::kDone) {
+        AFN_TRY(state_queue(st, s));
+        AFN_TRY(state_decide(st, s));
+    }
+    return AFN_OK;
 }
 
 }  // namespace
@@ -789,10 +989,54 @@ afn_status pcg_refine(afn_handle *h, const double *b, double *xout, double tol, 
 
 using namespace afn;
 
+namespace afn {
+namespace {
+
+bool params_valid(int64_t n, int32_t d, const afn_params *prm)
+{
+    return prm && n >= 1 && n <= INT32_MAX - 1 && d >= 1 && d <= kMaxD && prm->k >= -1 && prm->k <= n &&
+           prm->w >= 1 && prm->w <= kMaxW && prm->method >= AFN_METHOD_AFN && prm->method <= AFN_METHOD_AUTO &&
+           prm->landmarks >= AFN_LANDMARKS_AUTO && prm->landmarks <= AFN_LANDMARKS_UNIFORM &&
+           (prm->kernel == AFN_KERNEL_GAUSSIAN || prm->kernel == AFN_KERNEL_MATERN32) &&
+           (prm->precision == AFN_FP64 || prm->precision == AFN_FP32) && !(prm->precision == AFN_FP32 && d > 8) &&
+           prm->nrhs_max >= 0 && prm->m >= 0;
+}
+
+void release_handle(afn_handle *h)
+{
+    if (h->host_sc) (void)hipHostFree(h->host_sc);
+    for (auto &e : h->kmv_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (h->chk_ev) (void)hipEventDestroy(h->chk_ev);
+    if (h->block_ev) (void)hipEventDestroy(h->block_ev);
+    if (h->block_stream) (void)hipStreamDestroy(h->block_stream);
+    if (h->ws_owned) (void)hipFree(h->ws_owned);
+    delete h;
+}
+
+}  // namespace
+}  // namespace afn
+
 extern "C" {
 
+afn_status afn_workspace_size(int64_t n, int32_t d, const afn_params *prm, size_t *bytes)
+{
+    clear_error();
+    if (!bytes || !params_valid(n, d, prm)) {
+        set_error("afn_workspace_size: invalid argument");
+        return AFN_EINVAL;
+    }
+    *bytes = workspace_bytes(n, d, prm);
+    return AFN_OK;
+}
+
+afn_status afn_footprint_bytes(int64_t n, int32_t d, const afn_params *prm, size_t *bytes)
+{
+    return afn_workspace_size(n, d, prm, bytes);
+}
+
 afn_status afn_setup(const double *X_dev, int64_t n, int32_t d, double l, double mu,
-                     const afn_params *prm, void *stream, afn_handle **out)
+                     const afn_params *prm, void *ws_dev, size_t ws_bytes, void *stream, afn_handle **out)
 {
     clear_error();
     if (!out) {
@@ -800,26 +1044,35 @@ afn_status afn_setup(const double *X_dev, int64_t n, int32_t d, double l, double
         return AFN_EINVAL;
     }
     *out = nullptr;
-    if (!X_dev || !prm || n < 1 || n > INT32_MAX - 1 || d < 1 || d > kMaxD || !(l > 0) ||
-        !std::isfinite(l) || !(mu >= 0) || !std::isfinite(mu) || prm->k < -1 || prm->k > n ||
-        prm->w < 1 || prm->w > kMaxW || prm->method < AFN_METHOD_AFN || prm->method > AFN_METHOD_AUTO ||
-        prm->landmarks < AFN_LANDMARKS_AUTO || prm->landmarks > AFN_LANDMARKS_UNIFORM ||
-        (prm->kernel != AFN_KERNEL_GAUSSIAN && prm->kernel != AFN_KERNEL_MATERN32) ||
-        (prm->precision != AFN_FP64 && prm->precision != AFN_FP32) ||
-        (prm->precision == AFN_FP32 && d > 8)) {
-        set_error("afn_setup: invalid argument (n=%lld d=%d l=%g mu=%g k=%d w=%d)", (long long)n, d,
-                  l, mu, prm ? prm->k : 0, prm ? prm->w : 0);
+    if (!X_dev || !params_valid(n, d, prm) || !(l > 0) || !std::isfinite(l) || !(mu >= 0) ||
+        !std::isfinite(mu) || ((uintptr_t)ws_dev & 255) != 0) {
+        set_error("afn_setup: invalid argument (n=%lld d=%d l=%g mu=%g k=%d w=%d ws=%p)", (long long)n, d, l,
+                  mu, prm ? prm->k : 0, prm ? prm->w : 0, ws_dev);
         return AFN_EINVAL;
     }
-    std::unique_ptr<afn_handle> h(new afn_handle());
+    const size_t need = workspace_bytes(n, d, prm);
+    std::unique_ptr<afn_handle, void (*)(afn_handle *)> h(new afn_handle(), release_handle);
+    if (ws_dev) {
+        if (ws_bytes < need) {
+            set_error("afn_setup: workspace of %zu bytes, afn_workspace_size gives %zu", ws_bytes, need);
+            return AFN_ENOMEM;
+        }
+    } else {
+        const hipError_t e = hipMalloc(&h->ws_owned, need);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            h->ws_owned = nullptr;
+            set_error("afn_setup: allocating the %zu-byte workspace failed: %s", need, hipGetErrorString(e));
+            return AFN_ENOMEM;
+        }
+        ws_dev = h->ws_owned;
+        ws_bytes = need;
+    }
+    h->arena.base = (char *)ws_dev;
+    h->arena.cap = ws_bytes;
     afn_status st = setup_impl(X_dev, n, d, l, mu, prm, (hipStream_t)stream, h.get());
     if (st != AFN_OK) {
         (void)hipStreamSynchronize((hipStream_t)stream);
-        if (h->host_sc) (void)hipHostFree(h->host_sc);
-        for (auto &e : h->kmv_ev)
-            if (e) (void)hipEventDestroy(e);
-        if (h->chk_ev) (void)hipEventDestroy(h->chk_ev);
-        h->arena.release();
         return st;
     }
     *out = h.release();
@@ -832,6 +1085,10 @@ afn_status afn_apply(afn_handle *h, const double *r_dev, double *z_dev, int32_t 
     clear_error();
     if (!h || !r_dev || !z_dev || nrhs < 1 || ld < h->n) {
         set_error("afn_apply: invalid argument");
+        return AFN_EINVAL;
+    }
+    if (h->active) {
+        set_error("afn_apply: a step-wise solve is started on this handle");
         return AFN_EINVAL;
     }
     hipStream_t s = (hipStream_t)stream;
@@ -854,6 +1111,10 @@ afn_status afn_pcg_solve(afn_handle *h, const double *b_dev, double *x_dev, int3
         set_error("afn_pcg_solve: invalid argument");
         return AFN_EINVAL;
     }
+    if (h->active) {
+        set_error("afn_pcg_solve: a step-wise solve is started on this handle");
+        return AFN_EINVAL;
+    }
     hipStream_t s = (hipStream_t)stream;
     WorkLayout w;
     work_doubles(h->n, h->d, h->k, h->nr, &w, h->work);
@@ -868,10 +1129,11 @@ afn_status afn_pcg_solve(afn_handle *h, const double *b_dev, double *x_dev, int3
     double rel_max = 0.0, true_max = 0.0;
     // columns still to solve one at a time (all of them outside the block path)
     std::vector<int> single;
-    if (nrhs >= 2 && h->precision == AFN_FP32 && h->d <= 8) {
-        std::vector<int> col_ok(64);
-        for (int c0 = 0; c0 < nrhs; c0 += 64) {
-            const int Rc = nrhs - c0 < 64 ? nrhs - c0 : 64;
+    if (nrhs >= 2 && h->nrhs_block >= 2) {
+        const int RB = h->nrhs_block;
+        std::vector<int> col_ok(RB);
+        for (int c0 = 0; c0 < nrhs; c0 += RB) {
+            const int Rc = nrhs - c0 < RB ? nrhs - c0 : RB;
             int it = 0, outer = 0, conv = 0;
             double rel = 0.0;
             afn_status st = block_refine_solve(h, b_dev + c0 * ld, ld, x_dev + c0 * ld, Rc, tol, maxit,
@@ -895,24 +1157,20 @@ afn_status afn_pcg_solve(afn_handle *h, const double *b_dev, double *x_dev, int3
         for (int c = 0; c < nrhs; ++c) single.push_back(c);
     }
     for (const int c : single) {
-        int it = 0, conv = 0, outer = 0, it64 = 0;
-        double rel = 0, rt = 0;
-        afn_status st =
-            h->precision == AFN_FP32
-                ? pcg_refine(h, b_dev + c * ld, x_dev + c * ld, tol, maxit, w, w32, s, &it, &outer,
-                             &it64, &rel, &rt, &conv, &ms_kmv, &n_kmv)
-                : pcg_one(h, b_dev + c * ld, x_dev + c * ld, tol, maxit, w, s, &it, &rel, &rt, &conv,
-                          &ms_kmv, &n_kmv);
-        outer_max = outer > outer_max ? outer : outer_max;
-        it64_max = it64 > it64_max ? it64 : it64_max;
-        if (st != AFN_OK && st != AFN_ENOCONV && st != AFN_EBREAKDOWN && st != AFN_ESTAGNATION)
-            return st;
-        if (st != AFN_OK && worst == AFN_OK) worst = st;
-        if (st == AFN_EBREAKDOWN) worst = st;
-        it_max = it > it_max ? it : it_max;
-        conv_all &= conv;
-        rel_max = rel > rel_max || rel != rel ? rel : rel_max;
-        true_max = rt > true_max || rt != rt ? rt : true_max;
+        afn_pcg_state st;
+        AFN_TRY(solve_one(h, b_dev + c * ld, x_dev + c * ld, tol, maxit, s, &st));
+        afn_solve_info ci{};
+        state_info(&st, &ci);
+        ms_kmv += ci.ms_matvec;
+        n_kmv += ci.matvec_launches;
+        outer_max = ci.outer_iterations > outer_max ? ci.outer_iterations : outer_max;
+        it64_max = ci.fp64_iterations > it64_max ? ci.fp64_iterations : it64_max;
+        if (st.status != AFN_OK && worst == AFN_OK) worst = st.status;
+        if (st.status == AFN_EBREAKDOWN) worst = st.status;
+        it_max = ci.iterations > it_max ? ci.iterations : it_max;
+        conv_all &= ci.converged;
+        rel_max = ci.relres > rel_max || ci.relres != ci.relres ? ci.relres : rel_max;
+        true_max = ci.relres_true > true_max || ci.relres_true != ci.relres_true ? ci.relres_true : true_max;
     }
     tm.mark(1, s);
     AFN_HIP(hipStreamSynchronize(s));
@@ -1002,65 +1260,97 @@ afn_status afn_get_cholesky(const afn_handle *h, double *L_host, int64_t ld)
     return AFN_OK;
 }
 
-afn_status afn_footprint_bytes(int64_t n, int32_t d, const afn_params *prm, size_t *bytes)
+afn_status afn_pcg_begin(afn_handle *h, const double *b_dev, double *x_dev, double tol, int32_t maxit,
+                         void *stream, afn_pcg_state **out)
 {
     clear_error();
-    if (!prm || !bytes || n < 1 || d < 1 || d > kMaxD || prm->w < 1 || prm->w > kMaxW ||
-        prm->k < -1 || prm->k > n || prm->method < AFN_METHOD_AFN || prm->method > AFN_METHOD_AUTO) {
-        set_error("afn_footprint_bytes: invalid argument");
+    if (!out) {
+        set_error("afn_pcg_begin: out is NULL");
         return AFN_EINVAL;
     }
-    const int64_t kmax = prm->k_max > 0 ? prm->k_max : 2000;
-    const int64_t k = prm->k >= 0 ? prm->k : (kmax < n ? kmax : n);
-    const int64_t nr = n - k, w = prm->w;
-    const bool f32 = prm->precision == AFN_FP32;
-    auto r = [](int64_t b) { return (size_t)round_up(b > 0 ? b : 1, 256); };
-    // shared by both preconditioners: flags, perm, Xp, packed points, workspaces
-    size_t base = r(64) + r(4 * n) + r(8 * n * d);
-    if (d <= 8) base += r(8 * kmv_packed_doubles(n, d)) + r(4 * n) + r(8 * kmv_box_count(n, d));
-    if (f32) base += r(4 * kmv_packed_doubles(n, d)) + r(4 * kmv_box_count(n, d)) +
-                     r(4 * work32_floats(n, d, (int)k, nr, nullptr, nullptr));
-    base += r(8 * work_doubles(n, d, (int)k, nr, nullptr, nullptr));
-    size_t tmp_base = r(4 * k) + (size_t)fps_workspace_bytes(n) + r(4 * n) +
-                      r((int64_t)spatial_order_work_bytes(n, d));
-    if (prm->k < 0) {
-        const int64_t m = prm->m > 0 ? (prm->m < n ? prm->m : n) : (n < 2000 ? n : 2000);
-        tmp_base += r(8 * m * m) + r(8 * m * (d + 16)) + (size_t)fps_workspace_bytes(m) + r(8 * 8 * m);
+    *out = nullptr;
+    if (!h || !b_dev || !x_dev || !(tol > 0) || maxit < 1) {
+        set_error("afn_pcg_begin: invalid argument");
+        return AFN_EINVAL;
     }
-    // AFN: L, Linv, Dinv, pattern, G, G^T, V (+ FP32 copies); transpose and row-order temporaries
-    size_t afn = 0;
-    if (k > 0) afn += 2 * r(8 * k * k) + r(8 * dinv_doubles((int)k));
-    if (nr > 0) afn += r(4 * nr * w) + r(8 * nr * w) + r(8 * (nr + 1)) + r(4 * nr * w) + r(8 * nr * w);
-    if (k > 0 && nr > 0) afn += r(8 * k * nr);
-    if (f32) afn += r(4 * k * k) + r(4 * k * nr) + 2 * r(4 * nr * w);
-    afn += r((int64_t)fsai_transpose_work_bytes(nr, prm->w)) + r(4 * nr) + r((int64_t)knn_work_bytes(nr, d));
-    if (d <= 10) afn += r((int64_t)spatial_order_work_bytes(nr, d));
-    if (d > 10) afn += r(8 * fsai_batch_doubles((int)k, (int)w));
-    // Nystrom: L, Dinv, W, Rginv (+ FP32 W, Rginv); G, its block inverses and GEMM partials
-    size_t nys = 0;
-    if (k > 0) {
-        nys += 2 * r(8 * k * k) + r(8 * dinv_doubles((int)k)) + r(8 * k * n);
-        if (f32) nys += r(4 * k * n) + r(4 * k * k);
-        nys += r(8 * k * k) + r(8 * dinv_doubles((int)k)) + r(8 * gemm_part_elems(k, n)) +
-               r(8 * dot_partials(k * (nr > k ? nr : k))) + r(16);
+    if (h->active) {
+        set_error("afn_pcg_begin: a solve is already started on this handle");
+        return AFN_EINVAL;
     }
-    size_t extra = prm->method == AFN_METHOD_AFN ? afn
-                   : prm->method == AFN_METHOD_NYSTROM ? nys
-                                                       : (afn > nys ? afn : nys);
-    *bytes = base + tmp_base + extra;
+    std::unique_ptr<afn_pcg_state> st(new afn_pcg_state());
+    AFN_TRY(state_init(h, b_dev, x_dev, tol, maxit, st.get()));
+    st->stream = (hipStream_t)stream;
+    AFN_TRY(state_begin(st.get(), st->stream));
+    h->active = true;
+    *out = st.release();
     return AFN_OK;
+}
+
+afn_status afn_pcg_step_many(afn_pcg_state *const *states, int32_t count, int32_t iters, void *stream)
+{
+    clear_error();
+    if (!states || count < 1 || iters < 1) {
+        set_error("afn_pcg_step_many: invalid argument");
+        return AFN_EINVAL;
+    }
+    for (int32_t i = 0; i < count; ++i) {
+        if (!states[i]) {
+            set_error("afn_pcg_step_many: state %d is NULL", i);
+            return AFN_EINVAL;
+        }
+        for (int32_t j = 0; j < i; ++j)
+            if (states[j]->h == states[i]->h) {
+                set_error("afn_pcg_step_many: states %d and %d share a handle", j, i);
+                return AFN_EINVAL;
+            }
+    }
+    // stream NULL: each solve on the stream it was begun on (solves overlap
+    // on the device); otherwise every solve on 'stream'
+    auto sof = [&](const afn_pcg_state *st) { return stream ? (hipStream_t)stream : st->stream; };
+    std::vector<int> products(count, 0);
+    for (;;) {
+        // one round: the next unit of every unfinished solve, then one wait each
+        bool any = false;
+        for (int32_t i = 0; i < count; ++i) {
+            afn_pcg_state *st = states[i];
+            if (st->phase == afn_pcg_state::kDone || products[i] >= iters) continue;
+            AFN_TRY(state_queue(st, sof(st)));
+            any = true;
+        }
+        if (!any) break;
+        for (int32_t i = 0; i < count; ++i) {
+            afn_pcg_state *st = states[i];
+            if (st->phase == afn_pcg_state::kDone || products[i] >= iters) continue;
+            if (counts_as_product(st)) products[i] += 1;
+            AFN_TRY(state_decide(st, sof(st)));
+        }
+    }
+    return AFN_OK;
+}
+
+afn_status afn_pcg_query(const afn_pcg_state *st, int32_t *done, afn_solve_info *info)
+{
+    clear_error();
+    if (!st || !done) {
+        set_error("afn_pcg_query: invalid argument");
+        return AFN_EINVAL;
+    }
+    *done = st->phase == afn_pcg_state::kDone ? 1 : 0;
+    if (info) state_info(st, info);
+    return *done ? st->status : AFN_OK;
+}
+
+void afn_pcg_end(afn_pcg_state *st)
+{
+    if (!st) return;
+    if (st->h) st->h->active = false;
+    delete st;
 }
 
 void afn_destroy(afn_handle *h)
 {
     if (!h) return;
-    if (h->host_sc) (void)hipHostFree(h->host_sc);
-    for (auto &e : h->kmv_ev)
-        if (e) (void)hipEventDestroy(e);
-    if (h->chk_ev) (void)hipEventDestroy(h->chk_ev);
-    if (h->mrhs_ws) (void)hipFree(h->mrhs_ws);
-    h->arena.release();
-    delete h;
+    release_handle(h);
 }
 
 }  // extern "C"

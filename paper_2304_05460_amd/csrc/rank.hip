@@ -420,17 +420,12 @@ afn_status uniform_landmarks(int64_t n, int k, uint64_t seed, int32_t *idx, hipS
 }
 
 afn_status rank_estimate(const double *X, int64_t n, int d, double l, int kind, double mu, int m, int kmax,
-                         uint64_t seed, hipStream_t s, afn_setup_info *info, int *k_out)
+                         uint64_t seed, DevArena &tmp, hipStream_t s, afn_setup_info *info, int *k_out)
 {
     if (m < 1 || m > n || m > kMaxM) {
         set_error("rank estimation: subsample size m=%d outside [1, min(n, %d)]", m, kMaxM);
         return AFN_EINVAL;
     }
-    DevArena tmp;
-    struct G {
-        DevArena &a;
-        ~G() { a.release(); }
-    } guard{tmp};
     int32_t *sub = nullptr, *ord = nullptr;
     double *Xm = nullptr, *K = nullptr, *c = nullptr, *pv = nullptr, *part = nullptr, *errs = nullptr;
     double *v = nullptr, *pw = nullptr, *gp = nullptr, *sc = nullptr, *tdiag = nullptr, *toff = nullptr;

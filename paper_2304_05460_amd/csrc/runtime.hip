@@ -29,21 +29,15 @@ void clear_error() { g_last_error.clear(); }
 afn_status DevArena::alloc(void **p, size_t bytes)
 {
     *p = nullptr;
-    hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        set_error("hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
-        *p = nullptr;
+    const size_t start = (size_t)round_up((int64_t)off, 256);
+    if (!base || start + bytes > cap) {
+        set_error("workspace exhausted: %zu bytes needed at offset %zu of %zu", bytes, start, cap);
         return AFN_ENOMEM;
     }
-    ptrs.push_back(*p);
+    *p = base + start;
+    off = start + bytes;
+    high = off > high ? off : high;
     return AFN_OK;
-}
-
-void DevArena::release()
-{
-    for (void *p : ptrs) (void)hipFree(p);
-    ptrs.clear();
 }
 
 namespace {

@@ -2,23 +2,25 @@
 
 Requests (points, right-hand side, l, mu) arrive over time.  A request is
 admitted -- first come, first served -- as soon as a slot is free and its
-device footprint (afn_footprint_bytes: an upper bound of what afn_setup
-allocates, plus its inputs and solution) fits in the HBM budget next to the
-requests already running.  Every admitted request runs setup and solve on a
-stream of its own, so the kernels of different requests overlap on the
-device; when it finishes, its handle and buffers are released and the next
-request is admitted.  A request whose footprint exceeds the whole budget is
-rejected.  Every kernel of the library reduces in a fixed order, so a
-request's result does not depend on which other requests share the GPU.
-
-The scheduler and the workers are Python threads; every device call goes
-through the C-ABI (ctypes releases the interpreter lock during the call).
+device footprint (afn_workspace_size, the one workspace its handle lives in,
+plus its inputs and solution) fits in the HBM budget next to the requests
+already admitted; a request whose footprint exceeds the whole budget is
+rejected.  An admitted request is set up (Algorithm 4/5 and the
+preconditioner) on a setup thread, on a stream of its own, while the
+requests already set up keep iterating.  All running solves are advanced
+together: each round of afn_pcg_step_many queues one PCG iteration (or
+refinement step) of every running solve on its own stream -- so their
+kernels overlap on the device -- and then takes every stopping decision
+after one pass of host waits.  A finished solve leaves the batch at once and
+its slot and memory go to the next request, so requests join and leave
+between iterations.  The step API runs the same launches as afn_pcg_solve,
+so a request's result does not depend on which other requests share the GPU.
 """
 from __future__ import annotations
 
 import collections
+import concurrent.futures as cf
 import dataclasses
-import threading
 import time
 
 import numpy as np
@@ -70,94 +72,120 @@ class Result:
         return self.done - self.arrival
 
 
+@dataclasses.dataclass
+class Job:
+    """A request that is set up: its handle, device inputs and PCG state."""
+    req: Request
+    res: Result
+    slot: int
+    stream: object = None
+    handle: object = None
+    X: object = None
+    b: object = None
+    state: object = None
+
+
 class Server:
-    """slots: requests running at once; hbm_budget: bytes for all running
-    requests together (default: 90% of the free device memory at start)."""
+    """slots: requests admitted at once (set up or iterating); hbm_budget:
+    bytes for all of them together (default: 90% of the free device memory
+    at start); iters: products per request between admission checks;
+    setup_workers: setups that may run at once."""
 
     def __init__(self, slots: int = 8, hbm_budget: int | None = None,
-                 precision: int = afn.AFN_FP32, keep_x: bool = False, device: str = "cuda"):
+                 precision: int = afn.AFN_FP32, keep_x: bool | str = False, device: str = "cuda",
+                 iters: int = 1, setup_workers: int = 2):
         self.slots = slots
         self.precision = precision
         self.keep_x = keep_x
         self.device = torch.device(device)
+        self.iters = iters
+        self.setup_workers = setup_workers
         self.peak_active = 0
         if hbm_budget is None:
             free, _ = torch.cuda.mem_get_info(self.device)
             hbm_budget = int(0.9 * free)
         self.hbm_budget = hbm_budget
         self.peak_committed = 0
+        self.peak_batch = 0
 
     def footprint(self, r: Request) -> int:
         n, d = r.X.shape
-        fp = afn.afn_footprint_bytes(n, d, k=r.k, w=r.w, k_max=r.k_max,
-                                     precision=self.precision, method=r.method)
+        fp = afn.afn_workspace_size(n, d, k=r.k, w=r.w, k_max=r.k_max, precision=self.precision,
+                                    method=r.method, kernel=r.kernel, nrhs_max=0)
         return fp + 8 * n * (d + 2) + (1 << 20)     # inputs, solution, allocator slack
 
     def _make_stream(self):
         return torch.cuda.Stream(device=self.device)
 
-    def _work(self, r: Request, res: Result, stream: torch.cuda.Stream):
-        try:
-            with torch.cuda.stream(stream):
-                X = torch.from_numpy(np.ascontiguousarray(r.X)).to(self.device, non_blocking=False)
-                b = torch.from_numpy(np.ascontiguousarray(r.b)).to(self.device, non_blocking=False)
-                h = afn.afn_setup(X, r.l, r.mu, k=r.k, w=r.w, k_max=r.k_max,
-                                  precision=self.precision, method=r.method, kernel=r.kernel,
-                                  stream=stream)
-                try:
-                    x, info = afn.afn_pcg_solve(h, b, tol=r.tol, maxit=r.maxit, stream=stream)
-                    si = h.info()
-                    res.k, res.method = si.k, si.method
-                finally:
-                    h.close()
-                res.status = info["status"]
-                res.iterations = info["iterations"]
-                res.outer_iterations = info["outer_iterations"]
-                res.fp64_iterations = info["fp64_iterations"]
-                res.relres_true = info["relres_true"]
-                if self.keep_x:
-                    res.x = x.cpu() if self.keep_x == "host" else x
-                stream.synchronize()
-        except afn.AFNError as e:
-            res.status = e.status
-            res.error = str(e)
-        except Exception as e:  # noqa: BLE001  (reported per request)
-            res.status = afn.AFN_EDEVICE
-            res.error = repr(e)
+    # -- the three steps of a request; a test may replace them ------------------
+    def _prepare(self, job: Job) -> None:
+        """Setup thread: inputs to the device and afn_setup on the job's stream."""
+        r = job.req
+        with torch.cuda.stream(job.stream):
+            job.X = torch.from_numpy(np.ascontiguousarray(r.X)).to(self.device)
+            job.b = torch.from_numpy(np.ascontiguousarray(r.b)).to(self.device)
+            job.handle = afn.afn_setup(job.X, r.l, r.mu, k=r.k, w=r.w, k_max=r.k_max,
+                                       precision=self.precision, method=r.method, kernel=r.kernel,
+                                       nrhs_max=0, stream=job.stream)
+        si = job.handle.info()
+        job.res.k, job.res.method = si.k, si.method
+
+    def _begin(self, job: Job) -> None:
+        job.state = afn.afn_pcg_begin(job.handle, job.b, tol=job.req.tol, maxit=job.req.maxit,
+                                      stream=job.stream)
+
+    def _step(self, jobs: list[Job]) -> list[Job]:
+        """One batch of rounds over every running solve; returns those that finished."""
+        afn.afn_pcg_step_many([j.state for j in jobs], iters=self.iters, stream=None)
+        done = []
+        for j in jobs:
+            fin, info = j.state.query()
+            if not fin:
+                continue
+            res = j.res
+            res.status = info["status"]
+            res.iterations = info["iterations"]
+            res.outer_iterations = info["outer_iterations"]
+            res.fp64_iterations = info["fp64_iterations"]
+            res.relres_true = info["relres_true"]
+            if self.keep_x:
+                res.x = j.state.x.cpu() if self.keep_x == "host" else j.state.x
+            done.append(j)
+        return done
+
+    def _release(self, job: Job) -> None:
+        if job.state is not None:
+            job.state.end()
+        if job.handle is not None:
+            job.handle.close()
+        job.state = job.handle = job.X = job.b = None
 
     def run(self, requests: list[Request], on_done=None) -> list[Result]:
         """Serve the requests (arrival times relative to the call); on_done(result)
-        runs on the worker thread after each request finishes."""
+        runs after each request finishes."""
         order = sorted(requests, key=lambda q: (q.arrival, q.rid))
         results = {q.rid: Result(q.rid, 0, q.X.shape[0], q.X.shape[1], self.footprint(q),
                                  q.arrival) for q in order}
         arrivals = collections.deque(order)
         ready: collections.deque = collections.deque()
-        cv = threading.Condition()
-        state = {"active": 0, "committed": 0}
         streams = [self._make_stream() for _ in range(self.slots)]
-        free_streams = list(range(self.slots))
+        free_slots = list(range(self.slots))
+        committed = 0
+        pending: dict = {}       # setup future -> job
+        running: list[Job] = []
         t0 = time.perf_counter()
 
-        def finish(q: Request, res: Result, sidx: int):
-            res.done = time.perf_counter() - t0
-            with cv:
-                state["active"] -= 1
-                state["committed"] -= res.footprint
-                free_streams.append(sidx)
-                cv.notify_all()
+        def close(job: Job):
+            nonlocal committed
+            self._release(job)
+            job.res.done = time.perf_counter() - t0
+            committed -= job.res.footprint
+            free_slots.append(job.slot)
+            if on_done is not None:
+                on_done(job.res)
 
-        def runner(q: Request, res: Result, sidx: int):
-            try:
-                self._work(q, res, streams[sidx])
-            finally:
-                finish(q, res, sidx)
-                if on_done is not None:
-                    on_done(res)
-
-        threads = []
-        with cv:
-            while arrivals or ready or state["active"]:
+        with cf.ThreadPoolExecutor(max_workers=max(1, self.setup_workers)) as pool:
+            while arrivals or ready or pending or running:
                 now = time.perf_counter() - t0
                 while arrivals and arrivals[0].arrival <= now:
                     ready.append(arrivals.popleft())
@@ -169,26 +197,43 @@ class Server:
                     res.admitted = res.done = now
                     res.error = "footprint exceeds the HBM budget"
                 # admit in arrival order while a slot and the memory are free
-                while (ready and state["active"] < self.slots and
-                       state["committed"] + results[ready[0].rid].footprint <= self.hbm_budget):
+                while ready and free_slots and committed + results[ready[0].rid].footprint <= self.hbm_budget:
                     q = ready.popleft()
                     res = results[q.rid]
                     res.admitted = time.perf_counter() - t0
-                    state["active"] += 1
-                    state["committed"] += res.footprint
-                    self.peak_committed = max(self.peak_committed, state["committed"])
-                    self.peak_active = max(self.peak_active, state["active"])
-                    sidx = free_streams.pop()
-                    th = threading.Thread(target=runner, args=(q, res, sidx), daemon=True)
-                    threads.append(th)
-                    th.start()
-                timeout = None
+                    committed += res.footprint
+                    slot = free_slots.pop()
+                    job = Job(q, res, slot, streams[slot])
+                    pending[pool.submit(self._prepare, job)] = job
+                    self.peak_committed = max(self.peak_committed, committed)
+                    self.peak_active = max(self.peak_active, self.slots - len(free_slots))
+                # set-up requests join the batch
+                for fut in [f for f in pending if f.done()]:
+                    job = pending.pop(fut)
+                    try:
+                        fut.result()
+                        self._begin(job)
+                        running.append(job)
+                    except afn.AFNError as e:
+                        job.res.status, job.res.error = e.status, str(e)
+                        close(job)
+                    except Exception as e:  # noqa: BLE001  (reported per request)
+                        job.res.status, job.res.error = afn.AFN_EDEVICE, repr(e)
+                        close(job)
+                if running:
+                    self.peak_batch = max(self.peak_batch, len(running))
+                    for job in self._step(running):
+                        running.remove(job)
+                        close(job)
+                    continue
+                # nothing to iterate: wait for a setup or the next arrival
+                timeout = 1.0
                 if arrivals:
                     timeout = max(0.0, arrivals[0].arrival - (time.perf_counter() - t0))
-                if arrivals or ready or state["active"]:
-                    cv.wait(timeout=timeout if timeout is not None else 1.0)
-        for th in threads:
-            th.join()
+                if pending:
+                    cf.wait(list(pending), timeout=timeout, return_when=cf.FIRST_COMPLETED)
+                elif arrivals:
+                    time.sleep(timeout)
         return [results[q.rid] for q in requests]
 
 

@@ -39,8 +39,9 @@ def test_status_strings_without_gpu():
 
 def test_param_struct_layout_matches_header():
     from paper_2304_05460_amd import afn
-    assert ctypes.sizeof(afn.afn_params) == 40
+    assert ctypes.sizeof(afn.afn_params) == 48
     assert afn.afn_params.seed.offset == 24
+    assert afn.afn_params.nrhs_max.offset == 40
 
 
 def test_struct_layouts_match_the_c_compiler(tmp_path):

@@ -8,6 +8,8 @@ from paper_2304_05460_amd import serving
 
 
 class FakeServer(serving.Server):
+    """Setup sleeps; a solve takes 2 + rid % 3 steps."""
+
     def __init__(self, slots, budget, sizes):
         super().__init__(slots=slots, hbm_budget=budget, device="cpu")
         self.sizes = sizes
@@ -22,15 +24,30 @@ class FakeServer(serving.Server):
     def footprint(self, r):
         return self.sizes[r.rid]
 
-    def _work(self, r, res, stream):
+    def _prepare(self, job):
         with self.lock:
             self.running += 1
             self.max_running = max(self.max_running, self.running)
-            self.started.append(r.rid)
-        time.sleep(0.002 + 0.001 * (r.rid % 3))
+            self.started.append(job.req.rid)
+        time.sleep(0.001)
+
+    def _begin(self, job):
+        job.state = 2 + job.req.rid % 3
+
+    def _step(self, jobs):
+        time.sleep(0.0005)
+        done = []
+        for j in jobs:
+            j.state -= 1
+            if j.state == 0:
+                j.res.status = 0
+                done.append(j)
+        return done
+
+    def _release(self, job):
         with self.lock:
             self.running -= 1
-        res.status = 0
+        job.state = None
 
 
 def _reqs(count, rate, seed=3):

@@ -1,0 +1,52 @@
+"""afn_workspace_size on the host (no GPU): the workspace an afn_setup call
+carves bounds every landmark count and method the setup can end with."""
+import pytest
+
+from paper_2304_05460_amd import afn
+
+
+def ws(n, d, **kw):
+    return afn.afn_workspace_size(n, d, **kw)
+
+
+def test_adaptive_count_bounds_every_explicit_count():
+    n, d = 20000, 3
+    adaptive = ws(n, d, k=-1, k_max=600)
+    for k in (1, 10, 200, 599, 600):
+        assert ws(n, d, k=k) <= adaptive
+    assert ws(n, d, k=601) > 0
+
+
+def test_auto_bounds_both_methods():
+    n, d = 30000, 8
+    a = ws(n, d, k=-1, method=afn.AFN_METHOD_AFN)
+    b = ws(n, d, k=-1, method=afn.AFN_METHOD_NYSTROM)
+    assert ws(n, d, k=-1, method=afn.AFN_METHOD_AUTO) == max(a, b)
+
+
+def test_block_workspace_only_for_mixed_low_dimension():
+    n = 10000
+    base = ws(n, 3, k=300, precision=afn.AFN_FP32, nrhs_max=0)
+    blk = ws(n, 3, k=300, precision=afn.AFN_FP32, nrhs_max=64)
+    assert blk > base + 8 * 4 * n * 64          # FP64 blocks of n x 64 at least
+    assert ws(n, 3, k=300, precision=afn.AFN_FP32, nrhs_max=1) == base
+    assert ws(n, 3, k=300, precision=afn.AFN_FP64, nrhs_max=64) == ws(n, 3, k=300, precision=afn.AFN_FP64)
+    assert ws(n, 12, k=300, precision=afn.AFN_FP64, nrhs_max=64) == ws(n, 12, k=300)
+
+
+def test_size_covers_the_persistent_factors():
+    """At least L, L^-1, V = L^-1 K12, the pattern, G and G^T in FP64."""
+    n, d, k, w = 50000, 3, 1000, 64
+    nr = n - k
+    floor = 8 * (2 * k * k + k * nr + 2 * nr * w) + 4 * 2 * nr * w
+    assert ws(n, d, k=k, w=w) >= floor
+    assert afn.afn_footprint_bytes(n, d, k=k, w=w) == ws(n, d, k=k, w=w)
+
+
+@pytest.mark.parametrize("bad", [dict(k=-2), dict(w=0), dict(w=65), dict(method=3), dict(m=-1),
+                                 dict(precision=afn.AFN_FP32, d=9), dict(nrhs_max=-1)])
+def test_invalid_parameters(bad):
+    d = bad.pop("d", 3)
+    with pytest.raises(afn.AFNError) as e:
+        ws(1000, d, **bad)
+    assert e.value.status == afn.AFN_EINVAL
