@@ -360,7 +360,7 @@ __device__ __forceinline__ T lanes16_sum4(T (&v)[4], int lane)
 // the box centre that column staging needs sits in LDS: that keeps the FP64
 // kernel within 128 registers without spills in its loops.
 template <int KIND, int D, typename T, typename VT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void kmv_sym_mf(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D <= 4 || sizeof(T) == 4 ? 4 : 2))) void kmv_sym_mf(
     const T *__restrict__ Xs, int64_t npad, int64_t n, const VT *__restrict__ v, const int32_t *__restrict__ perm,
     const T *__restrict__ box, T tcut, T tfar, T r2max, int S, int ST, T *__restrict__ part)
 {
@@ -786,7 +786,7 @@ SymShape sym_shape(int64_t n, int d)
     SymShape sh;
     int64_t tiles = ceil_div(n, kTile);
     int64_t st = tiles / 45;
-    const int cap = d <= 4 ? kMaxSTmf : kMaxST;
+    const int cap = d <= 8 ? kMaxSTmf : kMaxST;
     sh.ST = (int)(st < 1 ? 1 : (st > cap ? cap : st));
     sh.ST = sh.ST > 1 ? sh.ST & ~1 : 1;       // even: packed length a multiple of 128
     sh.S = (int)ceil_div(tiles, sh.ST);
@@ -827,13 +827,17 @@ void launch_sym(int d, dim3 grid, const T *Xs, int64_t npad, int64_t n, const VT
     // the MFMA variant needs tile boxes and pays off up to d = 4 (one MFMA per
     // 16 x 16 block; in higher dimension tiles are rarely compact enough for
     // the centred form, and FP64 exceeds its register budget)
-    if (box && d <= 4) {
+    if (box && d <= 8) {
         const T r2 = T(kCentredR2Max);
         switch (d) {
             case 1: launch_mf<KIND, 1, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
             case 2: launch_mf<KIND, 2, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
             case 3: launch_mf<KIND, 3, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
-            default: launch_mf<KIND, 4, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
+            case 4: launch_mf<KIND, 4, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
+            case 5: launch_mf<KIND, 5, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
+            case 6: launch_mf<KIND, 6, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
+            case 7: launch_mf<KIND, 7, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
+            default: launch_mf<KIND, 8, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
         }
         return;
     }
