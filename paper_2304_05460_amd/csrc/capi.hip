@@ -272,14 +272,16 @@ afn_status nystrom_factors(afn_handle *h, DevArena &tmp, Timer &tm, hipStream_t 
     if (nr > 0) AFN_TRY(trsm_lower(h->L, h->Dinv, k, h->V, nr, s));
     AFN_TRY(transpose_square(h->L, k, k, h->W, k, s));
     tm.mark(5, s);
-    // W W^T + mu I by 64-column blocks on FP64 MFMA, its factor and inverse
+    // W W^T + mu I by 64-column blocks on FP64 MFMA (block c0 needs the rows
+    // up to c0 + 63 only: the upper triangle is not used), its factor and
+    // inverse
     double *G = nullptr, *Dg = nullptr, *part = nullptr;
     AFN_TRY(tmp.alloc_n(&G, kk));
     AFN_TRY(tmp.alloc_n(&Dg, dinv_doubles(k)));
-    AFN_TRY(tmp.alloc_n(&part, gemm_part_elems(k, n)));
+    AFN_TRY(tmp.alloc_n(&part, gemm_part_bound(k)));      // any m <= k
     for (int c0 = 0; c0 < k; c0 += 64) {
         const int R = k - c0 < 64 ? k - c0 : 64;
-        AFN_TRY(gemm_rows<double>(h->W, 1, k, k, n, h->W + c0, k, R, nullptr, 1.0, G + c0, k, part, s));
+        AFN_TRY(gemm_rows<double>(h->W, 1, k, c0 + R, n, h->W + c0, k, R, nullptr, 1.0, G + c0, k, part, s));
     }
     AFN_TRY(zero_upper(G, k, k, s));
     AFN_TRY(add_diagonal(G, k, k, h->mu, s));
@@ -325,7 +327,7 @@ size_t setup_carve_bytes(int64_t n, int d, int64_t k, int rank_m, int w, const a
         if (k > 0) {
             take(n8(kk)); take(n8(dinv_doubles((int)k))); take(n8(k * n));
             take(n8(dot_partials(kk > k * nr ? kk : k * nr))); take(n8(2));
-            take(n8(kk)); take(n8(dinv_doubles((int)k))); take(n8(gemm_part_elems(k, n))); take(n8(kk));
+            take(n8(kk)); take(n8(dinv_doubles((int)k))); take(n8(gemm_part_bound(k))); take(n8(kk));
         }
     } else {
         if (k > 0) { take(n8(kk)); take(n8(kk)); take(n8(dinv_doubles((int)k))); }

@@ -5,6 +5,7 @@
 // squared distance by the fixed fma chain.
 #include "afn_internal.h"
 #include "kfun.h"
+#include "mfma.h"
 
 namespace afn {
 namespace {
@@ -294,6 +295,105 @@ __global__ __launch_bounds__(256) void trsm_left_lower(const double *__restrict_
     }
 }
 
+// The same solve with the 64 x 64 x 64 products on FP64 MFMA 16x16x4: wave
+// w of the workgroup owns rows 16 w .. 16 w + 15 of the row block and all 64
+// columns of the strip (four 16 x 16 accumulators), for the updates
+// B_I -= L_IT X_T (T < I) and for X_I = Dinv_I B_I alike.  Tiles are staged
+// k-index major in LDS with a row stride of TSM doubles, so each 16-lane
+// group of an operand read touches consecutive doubles.
+constexpr int TSM = NB + 4;
+
+__device__ __forceinline__ void mfma_tile64(const double *__restrict__ As, const double *__restrict__ Bs, int wave,
+                                            int lr, int lk, double sign, doublex4 (&acc)[4])
+{
+#pragma unroll 2
+    for (int kk = 0; kk < NB / 4; ++kk) {
+        const double a = sign * As[(4 * kk + lk) * TSM + 16 * wave + lr];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            const double b = Bs[(4 * kk + lk) * TSM + 16 * cb + lr];
+            acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[cb], 0, 0, 0);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void trsm_left_lower_mf(const double *__restrict__ L,
+                                                          const double *__restrict__ Dinv, int k, double *B,
+                                                          int64_t ncols)
+{
+    __shared__ double As[NB * TSM];    // As[t * TSM + r]: A[r][t]
+    __shared__ double Bs[NB * TSM];    // Bs[t * TSM + c]: B[t][c]
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int64_t c0 = (int64_t)blockIdx.x * NB;
+    const int nblk = (int)ceil_div(k, NB);
+    for (int I = 0; I < nblk; ++I) {
+        const int r0 = I * NB;
+        doublex4 acc[4];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = r0 + 16 * wave + lk + 4 * i;
+                const int64_t c = c0 + 16 * cb + lr;
+                acc[cb][i] = (r < k && c < ncols) ? B[r + c * k] : 0.0;
+            }
+        // the tiles of step T + 1 are read into registers while the MFMAs
+        // of step T run (16 doubles of L and 16 of X per thread)
+        double la[16], xa[16];
+        // thread (r, t0) = (tid & 63, tid >> 6) takes L[r0 + r, T NB + t0 + 4 q] and
+        // B[T NB + r, c0 + t0 + 4 q], q = 0..15: one base address, stride 4 k
+        const int rr = tid & 63, t0 = tid >> 6;
+        const bool rok = r0 + rr < k;
+        const int64_t st4 = 4 * (int64_t)k;
+        auto fetch = [&](int T) {
+            const double *lp = L + (r0 + rr) + (int64_t)(T * NB + t0) * k;
+            const double *xp = B + (T * NB + rr) + (c0 + t0) * k;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                la[q] = rok ? lp[q * st4] : 0.0;
+                xa[q] = c0 + t0 + 4 * q < ncols ? xp[q * st4] : 0.0;
+            }
+        };
+        if (I > 0) fetch(0);
+        for (int T = 0; T < I; ++T) {
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                As[(t0 + 4 * q) * TSM + rr] = la[q];
+                Bs[rr * TSM + t0 + 4 * q] = xa[q];
+            }
+            __syncthreads();
+            if (T + 1 < I) fetch(T + 1);
+            mfma_tile64(As, Bs, wave, lr, lk, -1.0, acc);
+        }
+        // X_I = Dinv_I acc
+        __syncthreads();
+        for (int e = tid; e < NB * NB; e += 256) {
+            const int t = e >> 6, r = e & 63;
+            As[t * TSM + r] = Dinv[(int64_t)I * NB * NB + r + (int64_t)t * NB];
+        }
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) Bs[(16 * wave + lk + 4 * i) * TSM + 16 * cb + lr] = acc[cb][i];
+        __syncthreads();
+        doublex4 out[4];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) out[cb] = doublex4{0.0, 0.0, 0.0, 0.0};
+        mfma_tile64(As, Bs, wave, lr, lk, 1.0, out);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = r0 + 16 * wave + lk + 4 * i;
+                const int64_t c = c0 + 16 * cb + lr;
+                if (r < k && c < ncols) B[r + c * k] = out[cb][i];
+            }
+    }
+}
+
 __global__ __launch_bounds__(256) void set_identity(double *A, int k)
 {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -423,7 +523,7 @@ afn_status trsm_lower(const double *L, const double *Dinv, int k, double *B, int
                       hipStream_t s)
 {
     if (k <= 0 || ncols <= 0) return AFN_OK;
-    hipLaunchKernelGGL(trsm_left_lower, dim3((unsigned)ceil_div(ncols, NB)), dim3(256), 0, s, L,
+    hipLaunchKernelGGL(trsm_left_lower_mf, dim3((unsigned)ceil_div(ncols, NB)), dim3(256), 0, s, L,
                        Dinv, k, B, ncols);
     AFN_HIP(hipGetLastError());
     return AFN_OK;

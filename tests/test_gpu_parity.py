@@ -271,6 +271,62 @@ def test_c1_apply_matches_oracle_and_is_symmetric(afn, c1):
     assert R[:, 0] @ Sg[:, 1] == pytest.approx(R[:, 1] @ Sg[:, 0], rel=1e-9)
 
 
+def _per_row_g_and_apply(afn, h, A, X, l, mu, k, w, seed):
+    """Every row of G against the oracle's, each with the bound of its own
+    block (kappa(S_ss) k 1e3 u, as in the sampled C1 test), and the apply
+    entry by entry, each entry against the largest entry of its own group:
+    the landmark entries, the first w - 1 non-landmark rows (short patterns),
+    the last 64 rows of the block order and the rest.  A wrong short row or
+    tail row cannot hide under the bulk."""
+    n = X.shape[0]
+    rowptr, cols, vals = h.fsai()
+    Xp = X[A.perm]
+    K = dense_K(Xp, l) + mu * np.eye(n)
+    S = K[k:, k:] - (K[:k, k:].T @ np.linalg.solve(K[:k, :k], K[:k, k:]) if k > 0 else 0.0)
+    worst_g = 0.0
+    for q in range(n - k):
+        a, b_ = rowptr[q], rowptr[q + 1]
+        s_, g = cols[a:b_], vals[a:b_]
+        go = A.gval[a:b_]
+        kap = np.linalg.cond(S[np.ix_(s_, s_)])
+        bound = max(1e-9, kap * max(k, 1) * 1e3 * U)
+        rel = np.max(np.abs(g - go)) / np.max(np.abs(go))
+        worst_g = max(worst_g, rel / bound)
+        assert rel <= bound, (q, rel, bound)
+    r = np.random.default_rng(seed).standard_normal(n)
+    z = afn.afn_apply(h, dev(r)).cpu().numpy()
+    zo = oracle.afn_apply(A, r)
+    pos = np.empty(n, dtype=np.int64)
+    pos[A.perm] = np.arange(n)           # block position of each original index
+    groups = {"landmarks": pos < k, "short rows": (pos >= k) & (pos < k + w - 1),
+              "last tile": pos >= n - 64}
+    groups["bulk"] = ~(groups["landmarks"] | groups["short rows"] | groups["last tile"])
+    worst_z = {}
+    for name, m in groups.items():
+        if not m.any():
+            continue
+        scale = np.max(np.abs(zo[m]))
+        err = np.max(np.abs(z[m] - zo[m])) / scale
+        worst_z[name] = err
+        assert err <= 1e-9, (name, err)
+    say("per-row G worst/bound", worst_g, "apply per entry", worst_z)
+
+
+def test_c1_g_rows_and_apply_entries(afn, c1):
+    p, X, b, h, A = c1
+    _per_row_g_and_apply(afn, h, A, X, p.l, p.mu, p.k, p.w, 21)
+
+
+@pytest.mark.parametrize("n,k,w,d", [(70, 3, 64, 3), (333, 17, 5, 8), (1500, 100, 40, 3), (1100, 60, 64, 5)])
+def test_ragged_g_rows_and_apply_entries(afn, n, k, w, d):
+    X = W.points("normal" if d >= 5 else "uniform", n, d, 29 + n)
+    l, mu = 0.7, 1e-2
+    h = afn.afn_setup(dev(X), l, mu, k=k, w=w, landmarks=afn.AFN_LANDMARKS_FPS)
+    A = oracle_setup(X, l, mu, k, w)
+    _per_row_g_and_apply(afn, h, A, X, l, mu, k, w, 22)
+    h.close()
+
+
 def test_c1_pcg_matching_residual(afn, c1):
     p, X, b, h, A = c1
     x, info = afn.afn_pcg_solve(h, dev(b), tol=p.tol, maxit=p.maxit)
@@ -732,7 +788,11 @@ def test_uniform_landmarks_match_oracle(afn, n, d, k, lm):
     r = np.random.default_rng(93).standard_normal(n)
     s_ = afn.afn_apply(h, dev(r)).cpu().numpy()
     so = oracle.afn_apply(A, r)
-    assert np.linalg.norm(s_ - so) <= 1e-8 * np.linalg.norm(so)
+    # entry by entry, landmark and non-landmark entries each at their own scale
+    lm = np.zeros(n, dtype=bool)
+    lm[A.perm[:A.k]] = True
+    for m in (lm, ~lm):
+        assert np.max(np.abs(s_[m] - so[m])) <= 1e-8 * np.max(np.abs(so[m]))
     x, info = afn.afn_pcg_solve(h, dev(r), tol=1e-8, maxit=500)
     h.close()
     res = r - oracle.kernel_matvec(X, l, mu, x.cpu().numpy())
