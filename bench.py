@@ -274,6 +274,7 @@ def c3_bench(args):
     res32, el32 = timed(afn.AFN_FP32, "mixed", args.steps, args.warmup)
     steps64 = min(args.steps, 2)
     res64, el64 = timed(afn.AFN_FP64, "fp64", steps64, min(args.warmup, 1))
+    res16, el16 = timed(afn.AFN_BF16, "mixed-bf16", steps64, min(args.warmup, 1))
     x32, i32, s32 = res32[-1]
     x64, i64, s64 = res64[-1]
     rel = float(torch.linalg.vector_norm(x32 - x64) / torch.linalg.vector_norm(x64))
@@ -312,6 +313,15 @@ def c3_bench(args):
                  "setup_ms": round(s64.ms["total"], 1), "solve_ms": round(i64["ms_solve"], 1),
                  "kmv_f64_avg_launch_ms": round(ms64, 4),
                  "kmv_f64_tflops": round(F * s64.kmv_kept_f64 / (ms64 * 1e-3) / 1e12, 3)},
+        "mixed_bf16": {"value": round(steps64 / el16, 4), "unit": "solves/s", "steps": steps64,
+                       "status": afn.status_name(res16[-1][1]["status"]),
+                       "iterations_inner": res16[-1][1]["iterations"],
+                       "outer_iterations": res16[-1][1]["outer_iterations"],
+                       "relres_true_fp64": res16[-1][1]["relres_true"],
+                       "rel_diff_vs_fp64_solution": float(torch.linalg.vector_norm(res16[-1][0] - x64)
+                                                          / torch.linalg.vector_norm(x64)),
+                       "setup_ms": round(res16[-1][2].ms["total"], 1),
+                       "solve_ms": round(res16[-1][1]["ms_solve"], 1)},
         "speedup_mixed_vs_fp64": round(value / fp64_value, 3),
         "roofline": roofline,
     }

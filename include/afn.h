@@ -65,10 +65,18 @@ typedef enum afn_status {
  * an inner PCG breaks down (p'Ap <= 0 in FP32), or the refinement stops
  * halving the residual, or the inner products exceed 4 maxit, the solve
  * continues with textbook FP64 PCG from the current x (at most maxit more
- * products), so a mixed solve fails only where the FP64 solve would. */
+ * products), so a mixed solve fails only where the FP64 solve would.
+ * afn_setup with AFN_BF16: the same refinement, with the factors of the inner
+ * apply stored in BF16 (V = L^{-1} K12, L^{-1}, G, G^T, or the Nystrom
+ * W = L^{-1} K[S, :]) and widened to FP32 on load, sums in FP32; the Nystrom
+ * W W^T + mu I is formed (in FP64) from the BF16-rounded W and its inverse
+ * factor kept in FP32, so the inner preconditioner stays symmetric positive
+ * definite.  Several right-hand sides are solved one at a time.  AFN_BF16 is
+ * not a kernel_matvec precision (the operator of the inner solves is FP32). */
 typedef enum afn_precision {
     AFN_FP64 = 0,
-    AFN_FP32 = 1
+    AFN_FP32 = 1,
+    AFN_BF16 = 2
 } afn_precision;
 
 /* Preconditioner (Algorithm 5).  AFN_METHOD_AFN: the AFN factorization
@@ -114,7 +122,7 @@ typedef struct afn_params {
     int32_t k_max;      /* cap on the estimated count (Section 3.2: e.g. 2000)     */
     int32_t w;          /* FSAI nonzeros per row incl. the diagonal, 1 <= w <= 64  */
     int32_t m;          /* rank-estimation subsample size; 0 = min(n, 2000)        */
-    int32_t precision;  /* afn_precision of the PCG solve (AFN_FP32 needs d <= 8)   */
+    int32_t precision;  /* afn_precision of the PCG solve (FP32, BF16 need d <= 8) */
     int32_t method;     /* afn_method                                              */
     uint64_t seed;      /* seed of the rank-estimation subsample (splitmix64)      */
     int32_t landmarks;  /* afn_landmarks                                           */

@@ -19,7 +19,7 @@ _lib = None
 
 AFN_OK, AFN_EINVAL, AFN_ENOMEM, AFN_ENOTSPD, AFN_ENOCONV, AFN_EBREAKDOWN, AFN_ESTAGNATION, \
     AFN_EDEVICE = range(8)
-AFN_FP64, AFN_FP32 = 0, 1
+AFN_FP64, AFN_FP32, AFN_BF16 = 0, 1, 2
 AFN_METHOD_AFN, AFN_METHOD_NYSTROM, AFN_METHOD_AUTO = 0, 1, 2
 AFN_LANDMARKS_AUTO, AFN_LANDMARKS_FPS, AFN_LANDMARKS_UNIFORM = 0, 1, 2
 AFN_KERNEL_GAUSSIAN, AFN_KERNEL_MATERN32 = 0, 1

@@ -50,6 +50,18 @@ __device__ __forceinline__ int64_t xcd_contiguous(int64_t b, int64_t G)
     return start + j;
 }
 
+// BF16 storage of preconditioner factors (AFN_BF16): the upper 16 bits of an
+// FP32 value.  Loads widen to FP32 exactly; sums stay in FP32.
+struct bf16_t {
+    uint16_t bits;
+};
+__host__ __device__ inline float bf16_to_f32(bf16_t b) { return __builtin_bit_cast(float, (uint32_t)b.bits << 16); }
+// Value of type M in the arithmetic type T.
+template <typename T, typename M>
+__host__ __device__ inline T widen(M v) { return (T)v; }
+template <>
+__host__ __device__ inline float widen<float, bf16_t>(bf16_t v) { return bf16_to_f32(v); }
+
 // Device memory of a handle: a bump allocator over one region (the caller's
 // workspace, or one block the library allocated for the handle).  Buffers
 // start on 256-byte boundaries; temporaries of the setup are carved like
@@ -243,6 +255,19 @@ afn_status spmv_gt(const int64_t *ptr, const int32_t *idx, const double *val, in
                    const double *u, double *out, const int32_t *order, hipStream_t s);
 afn_status spmv_gt(const int64_t *ptr, const int32_t *idx, const float *val, int64_t nr,
                    const float *u, float *out, const int32_t *order, hipStream_t s);
+// The FP32 products with BF16 factors (AFN_BF16).
+afn_status gemv_n(const bf16_t *A, int64_t lda, int64_t m, int64_t ncols, const float *x, const float *base,
+                  float sign, float *y, float *part, hipStream_t s);
+afn_status gemv_t(const bf16_t *A, int64_t lda, int64_t m, int64_t ncols, const float *x, const float *base,
+                  float sign, float *y, hipStream_t s);
+afn_status spmv_g(const int32_t *cols, const bf16_t *gval, int64_t nr, int w, const float *t, float *u,
+                  const int32_t *order, hipStream_t s);
+afn_status spmv_gt(const int64_t *ptr, const int32_t *idx, const bf16_t *val, int64_t nr, const float *u,
+                   float *out, const int32_t *order, hipStream_t s);
+// b[i] = a[i] rounded to BF16 (nearest, ties to even, through FP32); n values.
+afn_status to_bf16_launch(const double *a, bf16_t *b, int64_t n, hipStream_t s);
+// a[i] = a[i] rounded to BF16 precision (kept in FP64; exact in BF16 after).
+afn_status round_bf16_inplace_launch(double *a, int64_t n, hipStream_t s);
 afn_status permute_gather(const double *src, int64_t lds, double *dst, int64_t ldd,
                           const int32_t *perm, int64_t n, int nrhs, hipStream_t s);
 afn_status permute_scatter(const double *src, int64_t lds, double *dst, int64_t ldd,
@@ -373,6 +398,11 @@ struct afn_handle {
     float *gval32 = nullptr;
     float *tval32 = nullptr;
     float *work32 = nullptr;
+    afn::bf16_t *Linv16 = nullptr;   // AFN_BF16: the inner apply's factors in BF16
+    afn::bf16_t *V16 = nullptr;
+    afn::bf16_t *gval16 = nullptr;
+    afn::bf16_t *tval16 = nullptr;
+    afn::bf16_t *W16 = nullptr;
     // Nystrom preconditioner (method == AFN_METHOD_NYSTROM): W = [L^T | V]
     // (k x n column-major, V = L^{-1} K12 with L = chol(K11 + nu I)) and the
     // inverse Rginv of the lower Cholesky factor of W W^T + mu I

@@ -126,8 +126,8 @@ struct Factors {
 // s = M^{-1} r in block order (landmarks first): Algorithm 3 with
 // V = L^{-1} K12 and Linv = L^{-1}:
 //   y1 = Linv r1 ; t = r2 - V^T y1 ; s2 = G^T (G t) ; s1 = Linv^T (y1 - V s2)
-template <typename T>
-afn_status apply_blockT(const afn_handle *h, const Factors<T> &f, const T *rp, T *sp, T *y1, T *tt,
+template <typename T, typename M>
+afn_status apply_blockT(const afn_handle *h, const Factors<M> &f, const T *rp, T *sp, T *y1, T *tt,
                         T *u, T *y1b, T *gemvp, hipStream_t s)
 {
     const int k = h->k;
@@ -158,8 +158,8 @@ afn_status apply_blockT(const afn_handle *h, const Factors<T> &f, const T *rp, T
 // s = M^{-1} r for the Nystrom preconditioner M = B B^T + mu I, B = W^T
 // (block order): Sherman-Morrison-Woodbury with B^T B + mu I = Rg Rg^T,
 //   y1 = W r ; y2 = Rg^{-T} Rg^{-1} y1 ; s = (r - W^T y2) / mu.
-template <typename T>
-afn_status apply_nysT(const afn_handle *h, const T *W, const T *Rginv, const T *rp, T *sp, T *y1, T *y1b,
+template <typename T, typename M>
+afn_status apply_nysT(const afn_handle *h, const M *W, const T *Rginv, const T *rp, T *sp, T *y1, T *y1b,
                       T *y2, T *gemvp, hipStream_t s)
 {
     const int k = h->k;
@@ -179,18 +179,24 @@ afn_status apply_block(afn_handle *h, const double *rp, double *sp, const WorkLa
                        hipStream_t s)
 {
     if (h->method == AFN_METHOD_NYSTROM)
-        return apply_nysT<double>(h, h->W, h->Rginv, rp, sp, w.y1, w.y1b, w.y2, w.gemvp, s);
+        return apply_nysT<double, double>(h, h->W, h->Rginv, rp, sp, w.y1, w.y1b, w.y2, w.gemvp, s);
     Factors<double> f{h->Linv, h->V, h->gval, h->tval};
-    return apply_blockT<double>(h, f, rp, sp, w.y1, w.t, w.u, w.y1b, w.gemvp, s);
+    return apply_blockT<double, double>(h, f, rp, sp, w.y1, w.t, w.u, w.y1b, w.gemvp, s);
 }
 
 afn_status apply_block32(afn_handle *h, const float *rp, float *sp, const WorkLayout32 &w,
                          hipStream_t s)
 {
+    if (h->precision == AFN_BF16) {
+        if (h->method == AFN_METHOD_NYSTROM)
+            return apply_nysT<float, bf16_t>(h, h->W16, h->Rginv32, rp, sp, w.y1, w.y1b, w.y2, w.gemvp, s);
+        Factors<bf16_t> f{h->Linv16, h->V16, h->gval16, h->tval16};
+        return apply_blockT<float, bf16_t>(h, f, rp, sp, w.y1, w.t, w.u, w.y1b, w.gemvp, s);
+    }
     if (h->method == AFN_METHOD_NYSTROM)
-        return apply_nysT<float>(h, h->W32, h->Rginv32, rp, sp, w.y1, w.y1b, w.y2, w.gemvp, s);
+        return apply_nysT<float, float>(h, h->W32, h->Rginv32, rp, sp, w.y1, w.y1b, w.y2, w.gemvp, s);
     Factors<float> f{h->Linv32, h->V32, h->gval32, h->tval32};
-    return apply_blockT<float>(h, f, rp, sp, w.y1, w.t, w.u, w.y1b, w.gemvp, s);
+    return apply_blockT<float, float>(h, f, rp, sp, w.y1, w.t, w.u, w.y1b, w.gemvp, s);
 }
 
 // (K + mu I) v on the handle's points, FP64
@@ -271,6 +277,10 @@ afn_status nystrom_factors(afn_handle *h, DevArena &tmp, Timer &tm, hipStream_t 
     tm.mark(4, s);
     if (nr > 0) AFN_TRY(trsm_lower(h->L, h->Dinv, k, h->V, nr, s));
     AFN_TRY(transpose_square(h->L, k, k, h->W, k, s));
+    // AFN_BF16: the inner apply uses W rounded to BF16, so W W^T + mu I is
+    // formed from the rounded W (kept in FP64): the Woodbury identity then
+    // holds for the operator applied, which stays symmetric positive definite
+    if (h->precision == AFN_BF16) AFN_TRY(round_bf16_inplace_launch(h->W, (int64_t)k * n, s));
     tm.mark(5, s);
     // W W^T + mu I by 64-column blocks on FP64 MFMA (block c0 needs the rows
     // up to c0 + 63 only: the upper triangle is not used), its factor and
@@ -313,7 +323,7 @@ size_t setup_carve_bytes(int64_t n, int d, int64_t k, int rank_m, int w, const a
     auto n8 = [](int64_t c) { return (size_t)8 * (size_t)(c > 0 ? c : 1); };
     auto n4 = [](int64_t c) { return (size_t)4 * (size_t)(c > 0 ? c : 1); };
     const int64_t nr = n - k, kk = k * k;
-    const bool f32 = prm->precision == AFN_FP32;
+    const bool f32 = prm->precision == AFN_FP32, b16 = prm->precision == AFN_BF16;
     take(n4(16));                                            // flags
     if (rank_m > 0) {
         const int64_t m = rank_m;
@@ -344,12 +354,13 @@ size_t setup_carve_bytes(int64_t n, int d, int64_t k, int rank_m, int w, const a
         take(n4(n)); take(spatial_order_work_bytes(n, d)); take(n8(kmv_packed_doubles(n, d)));
         take(n8(kmv_box_count(n, d))); take(n8(6));
     }
-    if (f32) {
+    if (f32 || b16) {
+        auto nf = [&](int64_t c) { return b16 ? (size_t)2 * (size_t)(c > 0 ? c : 1) : n4(c); };
         take(n4(kmv_packed_doubles(n, d))); take(n4(kmv_box_count(n, d)));
-        if (method == AFN_METHOD_NYSTROM && k > 0) { take(n4(k * n)); take(n4(kk)); }
-        if (method != AFN_METHOD_NYSTROM && k > 0) take(n4(kk));
-        if (method != AFN_METHOD_NYSTROM && k > 0 && nr > 0) take(n4(k * nr));
-        if (method != AFN_METHOD_NYSTROM && nr > 0) { take(n4(nr * w)); take(n4(nr * w)); }
+        if (method == AFN_METHOD_NYSTROM && k > 0) { take(nf(k * n)); take(n4(kk)); }
+        if (method != AFN_METHOD_NYSTROM && k > 0) take(nf(kk));
+        if (method != AFN_METHOD_NYSTROM && k > 0 && nr > 0) take(nf(k * nr));
+        if (method != AFN_METHOD_NYSTROM && nr > 0) { take(nf(nr * w)); take(nf(nr * w)); }
         take(n4(work32_floats(n, d, (int)k, nr, nullptr, nullptr)));
     }
     take(n8(work_doubles(n, d, (int)k, nr, nullptr, nullptr)));
@@ -389,6 +400,7 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     h->mu = mu;
     h->kind = prm->kernel;
     h->w = prm->w;
+    h->precision = prm->precision;
     AFN_TRY(h->arena.alloc_n(&h->flags, 16));
     AFN_HIP(hipMemsetAsync(h->flags, 0, sizeof(int) * 16, s));
     AFN_TRY(finite_launch(X, n * d, h->flags + 0, s));
@@ -507,7 +519,6 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     tm.mark(6, s);
     }
     // points packed for the symmetric tile kernel; FP32 copies for mixed solves
-    h->precision = prm->precision;
     if (d <= 8) {
         // spatial order of all points for the tile kernels: far-apart tile
         // pairs (kernel values below 2^-cut) are skipped
@@ -533,32 +544,37 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
         h->info.kmv_kept_f64 = h->info.kmv_kept_f32 = 1.0;
         h->info.kmv_far_f64 = 0.0;
     }
-    if (h->precision == AFN_FP32) {
+    if (h->precision == AFN_FP32 || h->precision == AFN_BF16) {
+        // the FP32 operator of the inner solves; the factors of the inner
+        // apply in FP32, or in BF16 (AFN_BF16: V, L^{-1}, G, G^T and the
+        // Nystrom W, whose W W^T + mu I was formed from the rounded W; the
+        // k x k inverse factor of that stays FP32)
+        const bool b16 = h->precision == AFN_BF16;
         AFN_TRY(h->arena.alloc_n(&h->Xs32, kmv_packed_doubles(n, d)));
         AFN_TRY(kmv_pack(h->Xp, n, d, l, h->kind, h->Xs32, true, s, h->kperm));
         AFN_TRY(h->arena.alloc_n(&h->box32, kmv_box_count(n, d)));
         AFN_TRY(kmv_boxes(h->Xs32, n, d, true, h->box32, s));
+        auto copy = [&](const double *src, int64_t cnt, float **f32, bf16_t **f16) -> afn_status {
+            if (b16) {
+                AFN_TRY(h->arena.alloc_n(f16, cnt));
+                return to_bf16_launch(src, *f16, cnt, s);
+            }
+            AFN_TRY(h->arena.alloc_n(f32, cnt));
+            return to_f32_launch(src, *f32, cnt, s);
+        };
         if (h->method == AFN_METHOD_NYSTROM) {
             if (k > 0) {
-                AFN_TRY(h->arena.alloc_n(&h->W32, (int64_t)k * n));
-                AFN_TRY(to_f32_launch(h->W, h->W32, (int64_t)k * n, s));
+                AFN_TRY(copy(h->W, (int64_t)k * n, &h->W32, &h->W16));
                 AFN_TRY(h->arena.alloc_n(&h->Rginv32, (int64_t)k * k));
                 AFN_TRY(to_f32_launch(h->Rginv, h->Rginv32, (int64_t)k * k, s));
             }
         }
-        if (h->method != AFN_METHOD_NYSTROM && k > 0) {
-            AFN_TRY(h->arena.alloc_n(&h->Linv32, (int64_t)k * k));
-            AFN_TRY(to_f32_launch(h->Linv, h->Linv32, (int64_t)k * k, s));
-        }
-        if (h->method != AFN_METHOD_NYSTROM && k > 0 && nr > 0) {
-            AFN_TRY(h->arena.alloc_n(&h->V32, (int64_t)k * nr));
-            AFN_TRY(to_f32_launch(h->V, h->V32, (int64_t)k * nr, s));
-        }
+        if (h->method != AFN_METHOD_NYSTROM && k > 0) AFN_TRY(copy(h->Linv, (int64_t)k * k, &h->Linv32, &h->Linv16));
+        if (h->method != AFN_METHOD_NYSTROM && k > 0 && nr > 0)
+            AFN_TRY(copy(h->V, (int64_t)k * nr, &h->V32, &h->V16));
         if (h->method != AFN_METHOD_NYSTROM && nr > 0) {
-            AFN_TRY(h->arena.alloc_n(&h->gval32, nr * h->w));
-            AFN_TRY(h->arena.alloc_n(&h->tval32, nr * h->w));
-            AFN_TRY(to_f32_launch(h->gval, h->gval32, nr * h->w, s));
-            AFN_TRY(to_f32_launch(h->tval, h->tval32, nr * h->w, s));
+            AFN_TRY(copy(h->gval, nr * h->w, &h->gval32, &h->gval16));
+            AFN_TRY(copy(h->tval, nr * h->w, &h->tval32, &h->tval16));
         }
         AFN_TRY(h->arena.alloc_n(&h->work32, work32_floats(n, d, k, nr, nullptr, nullptr)));
     }
@@ -953,7 +969,7 @@ afn_status state_init(afn_handle *h, const double *b, double *x, double tol, int
     st->xout = x;
     st->tol = tol;
     st->maxit = maxit;
-    st->mixed = h->precision == AFN_FP32;
+    st->mixed = h->precision == AFN_FP32 || h->precision == AFN_BF16;
     work_doubles(h->n, h->d, h->k, h->nr, &st->w, h->work);
     if (st->mixed) work32_floats(h->n, h->d, h->k, h->nr, &st->w32, h->work32);
     return AFN_OK;
@@ -1000,7 +1016,8 @@ bool params_valid(int64_t n, int32_t d, const afn_params *prm)
            prm->w >= 1 && prm->w <= kMaxW && prm->method >= AFN_METHOD_AFN && prm->method <= AFN_METHOD_AUTO &&
            prm->landmarks >= AFN_LANDMARKS_AUTO && prm->landmarks <= AFN_LANDMARKS_UNIFORM &&
            (prm->kernel == AFN_KERNEL_GAUSSIAN || prm->kernel == AFN_KERNEL_MATERN32) &&
-           (prm->precision == AFN_FP64 || prm->precision == AFN_FP32) && !(prm->precision == AFN_FP32 && d > 8) &&
+           (prm->precision == AFN_FP64 || prm->precision == AFN_FP32 || prm->precision == AFN_BF16) &&
+           !(prm->precision != AFN_FP64 && d > 8) &&
            prm->nrhs_max >= 0 && prm->m >= 0;
 }
 
@@ -1121,7 +1138,7 @@ afn_status afn_pcg_solve(afn_handle *h, const double *b_dev, double *x_dev, int3
     WorkLayout w;
     work_doubles(h->n, h->d, h->k, h->nr, &w, h->work);
     WorkLayout32 w32{};
-    if (h->precision == AFN_FP32) work32_floats(h->n, h->d, h->k, h->nr, &w32, h->work32);
+    if (h->work32) work32_floats(h->n, h->d, h->k, h->nr, &w32, h->work32);
     Timer tm;
     tm.mark(0, s);
     int outer_max = 0, it64_max = 0;

@@ -86,8 +86,8 @@ __device__ __forceinline__ float fmaT(float a, float b, float c) { return __buil
 constexpr int kGemvUnroll = 8;
 
 // y[i] (+)= sum over column chunk of A[i + j*lda] x[j]; partial per split.
-template <typename T>
-__global__ __launch_bounds__(256) void gemv_n_partial(const T *__restrict__ A, int64_t lda, int64_t m,
+template <typename T, typename M = T>
+__global__ __launch_bounds__(256) void gemv_n_partial(const M *__restrict__ A, int64_t lda, int64_t m,
                                                       int64_t ncols, const T *__restrict__ x,
                                                       int64_t chunk, T *__restrict__ part)
 {
@@ -100,11 +100,11 @@ __global__ __launch_bounds__(256) void gemv_n_partial(const T *__restrict__ A, i
     for (; j + kGemvUnroll <= j1; j += kGemvUnroll) {
         T a[kGemvUnroll];
 #pragma unroll
-        for (int u = 0; u < kGemvUnroll; ++u) a[u] = A[i + (j + u) * lda];
+        for (int u = 0; u < kGemvUnroll; ++u) a[u] = widen<T>(A[i + (j + u) * lda]);
 #pragma unroll
         for (int u = 0; u < kGemvUnroll; ++u) s = fmaT(a[u], x[j + u], s);
     }
-    for (; j < j1; ++j) s = fmaT(A[i + j * lda], x[j], s);
+    for (; j < j1; ++j) s = fmaT(widen<T>(A[i + j * lda]), x[j], s);
     part[(int64_t)blockIdx.y * m + i] = s;
 }
 
@@ -140,8 +140,8 @@ __global__ __launch_bounds__(256) void gemv_n_reduce_wave(const T *__restrict__ 
 }
 
 // y[j] = base[j] + sign * sum_i A[i + j*lda] x[i], one wavefront per column.
-template <typename T>
-__global__ __launch_bounds__(256) void gemv_t_kernel(const T *__restrict__ A, int64_t lda, int64_t m,
+template <typename T, typename M = T>
+__global__ __launch_bounds__(256) void gemv_t_kernel(const M *__restrict__ A, int64_t lda, int64_t m,
                                                      int64_t ncols, const T *__restrict__ x,
                                                      const T *__restrict__ base, T sign,
                                                      T *__restrict__ y)
@@ -149,20 +149,20 @@ __global__ __launch_bounds__(256) void gemv_t_kernel(const T *__restrict__ A, in
     const int lane = threadIdx.x & 63;
     const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (j >= ncols) return;
-    const T *col = A + j * lda;
+    const M *col = A + j * lda;
     T s = T(0);
     int64_t i = lane;
     for (; i + 64 * (kGemvUnroll - 1) < m; i += 64 * kGemvUnroll) {
         T a[kGemvUnroll], b[kGemvUnroll];
 #pragma unroll
         for (int u = 0; u < kGemvUnroll; ++u) {
-            a[u] = col[i + 64 * u];
+            a[u] = widen<T>(col[i + 64 * u]);
             b[u] = x[i + 64 * u];
         }
 #pragma unroll
         for (int u = 0; u < kGemvUnroll; ++u) s = fmaT(a[u], b[u], s);
     }
-    for (; i < m; i += 64) s = fmaT(col[i], x[i], s);
+    for (; i < m; i += 64) s = fmaT(widen<T>(col[i]), x[i], s);
     s = wave_sumT(s);
     if (lane == 0) y[j] = (base ? base[j] : T(0)) + sign * s;
 }
@@ -171,8 +171,8 @@ __global__ __launch_bounds__(256) void gemv_t_kernel(const T *__restrict__ A, in
 // values of dynamic LDS): per lane the rows lane, lane + 64, ... of each
 // column in order, then the butterfly, as in gemv_t_kernel; x is read from
 // HBM once per workgroup instead of once per column.
-template <typename T>
-__global__ __launch_bounds__(256) void gemv_t4_kernel(const T *__restrict__ A, int64_t lda, int64_t m,
+template <typename T, typename M = T>
+__global__ __launch_bounds__(256) void gemv_t4_kernel(const M *__restrict__ A, int64_t lda, int64_t m,
                                                       int64_t ncols, const T *__restrict__ x,
                                                       const T *__restrict__ base, T sign,
                                                       T *__restrict__ y)
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(256) void gemv_t4_kernel(const T *__restrict__ A, i
     const int64_t j0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 4;
     if (j0 >= ncols) return;
     const int nc = ncols - j0 < 4 ? (int)(ncols - j0) : 4;
-    const T *col[4];
+    const M *col[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) col[c] = A + (j0 + (c < nc ? c : nc - 1)) * lda;
     constexpr int U = 4;
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(256) void gemv_t4_kernel(const T *__restrict__ A, i
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
-            for (int u = 0; u < U; ++u) a[c][u] = col[c][i + 64 * u];
+            for (int u = 0; u < U; ++u) a[c][u] = widen<T>(col[c][i + 64 * u]);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const T xv = xs[i + 64 * u];
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void gemv_t4_kernel(const T *__restrict__ A, i
     for (; i < m; i += 64) {
         const T xv = xs[i];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) s[c] = fmaT(col[c][i], xv, s[c]);
+        for (int c = 0; c < 4; ++c) s[c] = fmaT(widen<T>(col[c][i]), xv, s[c]);
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -229,9 +229,9 @@ __device__ __forceinline__ T group16_sum(T s)
 // u[p] = sum_a gval[p*w + a] t[cols[p*w + a]], a < min(p+1, w) (w <= 64):
 // 16 lanes per row, lane q taking a = q, q + 16, q + 32, q + 48 (each load
 // instruction reads 16 consecutive entries of a row; 4 rows per wave).
-template <typename T>
+template <typename T, typename M = T>
 __global__ __launch_bounds__(256) void spmv_padded(const int32_t *__restrict__ cols,
-                                                   const T *__restrict__ gval, int64_t nr, int w,
+                                                   const M *__restrict__ gval, int64_t nr, int w,
                                                    const T *__restrict__ t, T *__restrict__ u,
                                                    const int32_t *__restrict__ order)
 {
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(256) void spmv_padded(const int32_t *__restrict__ c
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int a = q + 16 * r < m ? q + 16 * r : m - 1;
-        g[r] = gval[base + a];
+        g[r] = widen<T>(gval[base + a]);
         cj[r] = cols[base + a];
     }
 #pragma unroll
@@ -263,10 +263,10 @@ __global__ __launch_bounds__(256) void spmv_padded(const int32_t *__restrict__ c
 
 // s[c] = sum_e tval[e] u[trow[e]] over e in [ptr[c], ptr[c+1]): 16 lanes per
 // row, up to 4 entries per lane in flight per pass (4 rows per wave).
-template <typename T>
+template <typename T, typename M = T>
 __global__ __launch_bounds__(256) void spmv_csr(const int64_t *__restrict__ ptr,
                                                 const int32_t *__restrict__ idx,
-                                                const T *__restrict__ val, int64_t nrows,
+                                                const M *__restrict__ val, int64_t nrows,
                                                 const T *__restrict__ u, T *__restrict__ out,
                                                 const int32_t *__restrict__ order)
 {
@@ -284,7 +284,7 @@ __global__ __launch_bounds__(256) void spmv_csr(const int64_t *__restrict__ ptr,
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t f = e + 16 * r < e1 ? e + 16 * r : e1 - 1;
-            a[r] = val[f];
+            a[r] = widen<T>(val[f]);
             ri[r] = idx[f];
         }
 #pragma unroll
@@ -462,14 +462,14 @@ afn_status dot_pcgT(const T *a, const T *b, int64_t n, double *sc, PcgDotStep st
     return AFN_OK;
 }
 
-template <typename T>
-afn_status gemv_nT(const T *A, int64_t lda, int64_t m, int64_t ncols, const T *x, const T *base,
+template <typename T, typename M = T>
+afn_status gemv_nT(const M *A, int64_t lda, int64_t m, int64_t ncols, const T *x, const T *base,
                    T sign, T *y, T *part, hipStream_t s)
 {
     if (m <= 0) return AFN_OK;
     const int64_t S = gemv_splits(m, ncols);
     const int64_t chunk = ceil_div(ncols, S);
-    hipLaunchKernelGGL((gemv_n_partial<T>), dim3((unsigned)ceil_div(m, 256), (unsigned)S), dim3(256), 0, s,
+    hipLaunchKernelGGL((gemv_n_partial<T, M>), dim3((unsigned)ceil_div(m, 256), (unsigned)S), dim3(256), 0, s,
                        A, lda, m, ncols, x, chunk, part);
     if (S > 32)
         hipLaunchKernelGGL((gemv_n_reduce_wave<T>), dim3((unsigned)ceil_div(m, 4)), dim3(256), 0, s, part, m,
@@ -481,39 +481,39 @@ afn_status gemv_nT(const T *A, int64_t lda, int64_t m, int64_t ncols, const T *x
     return AFN_OK;
 }
 
-template <typename T>
-afn_status gemv_tT(const T *A, int64_t lda, int64_t m, int64_t ncols, const T *x, const T *base,
+template <typename T, typename M = T>
+afn_status gemv_tT(const M *A, int64_t lda, int64_t m, int64_t ncols, const T *x, const T *base,
                    T sign, T *y, hipStream_t s)
 {
     if (ncols <= 0) return AFN_OK;
     const size_t lds = sizeof(T) * (size_t)(m > 0 ? m : 1);
     if (ncols >= 4096 && lds <= 32768)
-        hipLaunchKernelGGL((gemv_t4_kernel<T>), dim3((unsigned)ceil_div(ncols, 16)), dim3(256), lds, s, A, lda, m,
+        hipLaunchKernelGGL((gemv_t4_kernel<T, M>), dim3((unsigned)ceil_div(ncols, 16)), dim3(256), lds, s, A, lda, m,
                            ncols, x, base, sign, y);
     else
-        hipLaunchKernelGGL((gemv_t_kernel<T>), dim3((unsigned)ceil_div(ncols, 4)), dim3(256), 0, s, A, lda, m,
+        hipLaunchKernelGGL((gemv_t_kernel<T, M>), dim3((unsigned)ceil_div(ncols, 4)), dim3(256), 0, s, A, lda, m,
                            ncols, x, base, sign, y);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }
 
-template <typename T>
-afn_status spmv_gT(const int32_t *cols, const T *gval, int64_t nr, int w, const T *t, T *u,
+template <typename T, typename M = T>
+afn_status spmv_gT(const int32_t *cols, const M *gval, int64_t nr, int w, const T *t, T *u,
                    const int32_t *order, hipStream_t s)
 {
     if (nr <= 0) return AFN_OK;
-    hipLaunchKernelGGL((spmv_padded<T>), dim3((unsigned)ceil_div(nr, 16)), dim3(256), 0, s, cols, gval, nr,
+    hipLaunchKernelGGL((spmv_padded<T, M>), dim3((unsigned)ceil_div(nr, 16)), dim3(256), 0, s, cols, gval, nr,
                        w, t, u, order);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }
 
-template <typename T>
-afn_status spmv_gtT(const int64_t *ptr, const int32_t *idx, const T *val, int64_t nr, const T *u,
+template <typename T, typename M = T>
+afn_status spmv_gtT(const int64_t *ptr, const int32_t *idx, const M *val, int64_t nr, const T *u,
                     T *out, const int32_t *order, hipStream_t s)
 {
     if (nr <= 0) return AFN_OK;
-    hipLaunchKernelGGL((spmv_csr<T>), dim3((unsigned)ceil_div(nr, 16)), dim3(256), 0, s, ptr, idx, val, nr,
+    hipLaunchKernelGGL((spmv_csr<T, M>), dim3((unsigned)ceil_div(nr, 16)), dim3(256), 0, s, ptr, idx, val, nr,
                        u, out, order);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
@@ -591,6 +591,68 @@ afn_status spmv_gt(const int64_t *ptr, const int32_t *idx, const float *val, int
 {
     return spmv_gtT(ptr, idx, val, nr, u, out, order, s);
 }
+afn_status gemv_n(const bf16_t *A, int64_t lda, int64_t m, int64_t ncols, const float *x, const float *base,
+                  float sign, float *y, float *part, hipStream_t s)
+{
+    return gemv_nT<float, bf16_t>(A, lda, m, ncols, x, base, sign, y, part, s);
+}
+afn_status gemv_t(const bf16_t *A, int64_t lda, int64_t m, int64_t ncols, const float *x, const float *base,
+                  float sign, float *y, hipStream_t s)
+{
+    return gemv_tT<float, bf16_t>(A, lda, m, ncols, x, base, sign, y, s);
+}
+afn_status spmv_g(const int32_t *cols, const bf16_t *gval, int64_t nr, int w, const float *t, float *u,
+                  const int32_t *order, hipStream_t s)
+{
+    return spmv_gT<float, bf16_t>(cols, gval, nr, w, t, u, order, s);
+}
+afn_status spmv_gt(const int64_t *ptr, const int32_t *idx, const bf16_t *val, int64_t nr, const float *u,
+                   float *out, const int32_t *order, hipStream_t s)
+{
+    return spmv_gtT<float, bf16_t>(ptr, idx, val, nr, u, out, order, s);
+}
+
+namespace {
+
+// FP32 bits to BF16 bits, nearest with ties to even (a NaN stays a NaN).
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f)
+{
+    const uint32_t u = __builtin_bit_cast(uint32_t, f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+__global__ __launch_bounds__(256) void to_bf16_kernel(const double *__restrict__ a, bf16_t *__restrict__ b,
+                                                      int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i].bits = f32_to_bf16_bits((float)a[i]);
+}
+
+__global__ __launch_bounds__(256) void round_bf16_kernel(double *__restrict__ a, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = (double)bf16_to_f32(bf16_t{f32_to_bf16_bits((float)a[i])});
+}
+
+}  // namespace
+
+afn_status to_bf16_launch(const double *a, bf16_t *b, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return AFN_OK;
+    hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, a, b, n);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
+afn_status round_bf16_inplace_launch(double *a, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return AFN_OK;
+    hipLaunchKernelGGL(round_bf16_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, a, n);
+    AFN_HIP(hipGetLastError());
+    return AFN_OK;
+}
+
 afn_status pcg_xr_launch(double *x, double *r, const double *p, const double *q, const double *sc,
                          int64_t n, double *part, double *rr_out, hipStream_t s)
 {
