@@ -65,11 +65,11 @@ def source_hash(path: pathlib.Path) -> str:
     return h.hexdigest()[:16]
 
 
-def counters_from_profile(kernel_src: pathlib.Path) -> dict:
+def counters_from_profile(kernel_src: pathlib.Path, name: str = "kmv_f64_sym_c2_counters.txt") -> dict:
     """HBM bytes per launch, clock and VALU issue fraction of the tile kernel
     from the committed rocprofv3 counter summary, if it was taken on the
     current kernel source (else an empty dict)."""
-    f = ROOT / "profiles" / "kmv_f64_sym_c2_counters.txt"
+    f = ROOT / "profiles" / name
     if not f.exists():
         return {}
     vals = {}
@@ -272,6 +272,12 @@ def c3_bench(args):
         return out, el
 
     res32, el32 = timed(afn.AFN_FP32, "mixed", args.steps, args.warmup)
+    if args.mixed_only:      # profiling runs: the timed mixed solves alone
+        i32 = res32[-1][1]
+        print(json.dumps({"workload": p.name, "mixed_only": True, "solves_per_s": args.steps / el32,
+                          "status": afn.status_name(i32["status"]), "iterations_inner": i32["iterations"],
+                          "kmv_f32_avg_launch_ms": i32["ms_matvec"] / max(i32["matvec_launches"], 1)}))
+        return
     steps64 = min(args.steps, 2)
     res64, el64 = timed(afn.AFN_FP64, "fp64", steps64, min(args.warmup, 1))
     res16, el16 = timed(afn.AFN_BF16, "mixed-bf16", steps64, min(args.warmup, 1))
@@ -282,11 +288,15 @@ def c3_bench(args):
     kmv_ms = sum(r[1]["ms_matvec"] for r in res32) / max(launches, 1)
     F = kmv_flops(p.n, p.d)
     achieved = F * s32.kmv_kept_f32 / (kmv_ms * 1e-3) / 1e12
+    ctrs = counters_from_profile(ROOT / "paper_2304_05460_amd" / "csrc" / "kmv.hip", "kmv_d8_c3_counters.txt")
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                "kernel": "FP32 kernel-matvec tile kernel, d = 8 (inner solves)",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": ctrs.get("hbm_bytes_per_launch"),
+                "kernel": "kmv_sym_mf<0, 8, float, float> (inner solves)",
                 "avg_launch_ms": round(kmv_ms, 4), "launches": launches,
                 "flops_per_launch": F * s32.kmv_kept_f32, "tile_pairs_evaluated": round(s32.kmv_kept_f32, 4)}
+    if "valu_issue_frac" in ctrs:
+        roofline["valu_issue_frac_counters"] = ctrs["valu_issue_frac"]
+        roofline["clock_ghz_counters"] = ctrs.get("clock_ghz")
     ms64 = sum(r[1]["ms_matvec"] for r in res64) / max(sum(r[1]["matvec_launches"] for r in res64), 1)
     value = args.steps / el32
     fp64_value = steps64 / el64
@@ -534,6 +544,8 @@ def main():
     ap.add_argument("--c3-branch", default="nystrom", choices=["nystrom", "afn"],
                     help="preconditioner of the c3 solves (Algorithm 5's branches)")
     ap.add_argument("--maxit", type=int, default=0, help="PCG iteration cap (0: the workload's)")
+    ap.add_argument("--mixed-only", action="store_true",
+                    help="c3: time the mixed-precision solves only (for counter runs; no JSON contract line)")
     ap.add_argument("--serving", action="store_true",
                     help="run the mixed-size request stream instead (p50/p99 latency, solves/s)")
     ap.add_argument("--serving-count", type=int, default=256)
@@ -589,7 +601,8 @@ def c2_bench(args):
     afn.lib()
 
     def step(precision=afn.AFN_FP64, method=afn.AFN_METHOD_AFN):
-        h = afn.afn_setup(X, p.l, p.mu, k=p.k, w=p.w, k_max=p.k_max, precision=precision, method=method)
+        h = afn.afn_setup(X, p.l, p.mu, k=p.k, w=p.w, k_max=p.k_max, precision=precision, method=method,
+                          nrhs_max=0)
         x, info = afn.afn_pcg_solve(h, b, tol=p.tol, maxit=p.maxit)
         sinfo = h.info()
         h.close()
@@ -613,8 +626,8 @@ def c2_bench(args):
         log(f"{label}: timed {args.steps} step(s) in {elapsed:.3f} s")
         return x, infos, elapsed
 
-    def mixed_block(x64, value):
-        x32, infos32, elapsed32 = timed(afn.AFN_FP32, "mixed")
+    def mixed_block(x64, value, precision=afn.AFN_FP32, label="mixed"):
+        x32, infos32, elapsed32 = timed(precision, label)
         i32, s32 = infos32[-1]
         rel = float(torch.linalg.vector_norm(x32 - x64) / torch.linalg.vector_norm(x64))
         return {"value": round(args.steps / elapsed32, 4), "unit": "solves/s",
@@ -662,9 +675,10 @@ def c2_bench(args):
 
     # the same input through the mixed-precision path (FP32 inner PCG inside
     # FP64 iterative refinement)
-    mixed = None
+    mixed = mixed_bf16 = None
     if not args.no_mixed:
         mixed = mixed_block(x64, value)
+        mixed_bf16 = mixed_block(x64, value, afn.AFN_BF16, "mixed-bf16")
     # Algorithm 5 on the same input: Nystrom below the rank switch, AFN above
     alg5 = None
     if not args.no_mixed:
@@ -696,6 +710,7 @@ def c2_bench(args):
                   "rank": {"r": sinfo.rank_r, "k_est": sinfo.rank_k_est,
                            "eig_branch": sinfo.rank_eig_branch}},
         "mixed": mixed,
+        "mixed_bf16": mixed_bf16,
         "alg5": alg5,
         "roofline": roofline,
     }

@@ -360,7 +360,7 @@ __device__ __forceinline__ T lanes16_sum4(T (&v)[4], int lane)
 // the box centre that column staging needs sits in LDS: that keeps the FP64
 // kernel within 128 registers without spills in its loops.
 template <int KIND, int D, typename T, typename VT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D <= 4 || sizeof(T) == 4 ? 4 : 2))) void kmv_sym_mf(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : (D <= 4 ? 4 : 2)))) void kmv_sym_mf(
     const T *__restrict__ Xs, int64_t npad, int64_t n, const VT *__restrict__ v, const int32_t *__restrict__ perm,
     const T *__restrict__ box, T tcut, T tfar, T r2max, int S, int ST, T *__restrict__ part)
 {
