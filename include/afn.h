@@ -320,14 +320,18 @@ afn_status afn_pcg_begin(afn_handle *h, const double *b_dev, double *x_dev, doub
                          void *stream, afn_pcg_state **out);
 
 /* Advance each unfinished state in states[0..count) by up to 'iters'
- * products with K + mu I, in rounds: every round queues one iteration of
- * every unfinished state, then waits on each and takes its stopping
- * decision.  stream NULL: each state's work goes on the stream it was begun
- * on, so solves on different streams overlap on the device; otherwise all of
- * it goes on 'stream' (which must then be ordered after the begin streams).
- * A state that finishes writes x_dev and its info.  Errors: EINVAL (a NULL state, count < 1, iters < 1, two states on
- * one handle), EDEVICE; the outcome of each solve is read by afn_pcg_query. */
-afn_status afn_pcg_step_many(afn_pcg_state *const *states, int32_t count, int32_t iters, void *stream);
+ * products with K + mu I.  Every state keeps one unit of work in flight (an
+ * iteration, or a refinement step's residual norm); the host polls their
+ * events and takes each stopping decision as soon as that state's unit is
+ * done, then queues its next one, so solves of different sizes advance at
+ * their own pace.  The call returns when every state has finished or taken
+ * 'iters' products, or, earlier, at the end of the first polling pass in
+ * which a state finished (so the caller can release it and start another);
+ * units still in flight stay with their states for the next call.  stream
+ * NULL: each state's work goes on the stream it was begun on, so solves
+ * overlap on the device; otherwise all of it goes on 'stream' (ordered after
+ * the begin streams; pass the same value on every call for a state).  A state
+ * that finishes writes x_dev and its info.afn_status afn_pcg_step_many(afn_pcg_state *const *states, int32_t count, int32_t iters, void *stream);
 
 /* *done = 1 once the solve has finished; info_host (may be NULL) then holds
  * the result, and the return value is the solve's status (OK, ENOCONV,
@@ -335,8 +339,8 @@ afn_status afn_pcg_step_many(afn_pcg_state *const *states, int32_t count, int32_
  * holds the iterations so far. */
 afn_status afn_pcg_query(const afn_pcg_state *st, int32_t *done, afn_solve_info *info_host);
 
-/* Release a state (finished or not); its handle can start another solve.
- * Work queued for it must be complete (synchronize the stream). */
+/* Release a state (finished or not), waiting for a unit it has in flight;
+ * its handle can start another solve. */
 void afn_pcg_end(afn_pcg_state *st);
 
 /* Release the handle and its device memory.  NULL is allowed.  Work the

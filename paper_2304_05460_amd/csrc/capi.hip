@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <thread>
 #include <vector>
 
 #include "afn_internal.h"
@@ -684,6 +685,7 @@ struct afn_pcg_state {
     int n_kmv = 0;
     double t_begin = 0.0, t_end = 0.0;
     hipStream_t stream = nullptr;   // the stream given to afn_pcg_begin
+    bool queued = false;            // a unit of work is in flight (afn_pcg_step_many)
 };
 
 namespace afn {
@@ -1326,23 +1328,49 @@ afn_status afn_pcg_step_many(afn_pcg_state *const *states, int32_t count, int32_
     // stream NULL: each solve on the stream it was begun on (solves overlap
     // on the device); otherwise every solve on 'stream'
     auto sof = [&](const afn_pcg_state *st) { return stream ? (hipStream_t)stream : st->stream; };
+    // Every solve keeps one unit of work in flight; the host polls their
+    // events and takes each decision as soon as its unit is done, so a small
+    // solve is not held to the pace of a large one.  A solve stops at its
+    // budget of products; the call returns when every solve has finished or
+    // spent its budget, or at the end of the first polling pass in which a
+    // solve finished (its caller can then release it and start another).
+    // Units in flight at the return stay queued for the next call.
     std::vector<int> products(count, 0);
+    bool finished_one = false;
+    for (int32_t i = 0; i < count; ++i) {
+        afn_pcg_state *st = states[i];
+        if (st->phase == afn_pcg_state::kDone || st->queued) continue;
+        AFN_TRY(state_queue(st, sof(st)));
+        st->queued = true;
+    }
     for (;;) {
-        // one round: the next unit of every unfinished solve, then one wait each
-        bool any = false;
+        bool waiting = false, progressed = false;
         for (int32_t i = 0; i < count; ++i) {
             afn_pcg_state *st = states[i];
-            if (st->phase == afn_pcg_state::kDone || products[i] >= iters) continue;
-            AFN_TRY(state_queue(st, sof(st)));
-            any = true;
-        }
-        if (!any) break;
-        for (int32_t i = 0; i < count; ++i) {
-            afn_pcg_state *st = states[i];
-            if (st->phase == afn_pcg_state::kDone || products[i] >= iters) continue;
+            if (!st->queued) continue;
+            const hipError_t q = hipEventQuery(st->h->chk_ev);
+            if (q == hipErrorNotReady) {
+                waiting = true;
+                continue;
+            }
+            if (q != hipSuccess) {
+                set_error("afn_pcg_step_many: hipEventQuery: %s", hipGetErrorString(q));
+                return AFN_EDEVICE;
+            }
+            st->queued = false;
+            progressed = true;
             if (counts_as_product(st)) products[i] += 1;
             AFN_TRY(state_decide(st, sof(st)));
+            if (st->phase == afn_pcg_state::kDone) {
+                finished_one = true;
+            } else if (products[i] < iters) {
+                AFN_TRY(state_queue(st, sof(st)));
+                st->queued = true;
+                waiting = true;
+            }
         }
+        if (!waiting || finished_one) break;
+        if (!progressed) std::this_thread::yield();
     }
     return AFN_OK;
 }
@@ -1362,6 +1390,7 @@ afn_status afn_pcg_query(const afn_pcg_state *st, int32_t *done, afn_solve_info 
 void afn_pcg_end(afn_pcg_state *st)
 {
     if (!st) return;
+    if (st->queued && st->h) (void)hipEventSynchronize(st->h->chk_ev);
     if (st->h) st->h->active = false;
     delete st;
 }

@@ -8,12 +8,12 @@ already admitted; a request whose footprint exceeds the whole budget is
 rejected.  An admitted request is set up (Algorithm 4/5 and the
 preconditioner) on a setup thread, on a stream of its own, while the
 requests already set up keep iterating.  All running solves are advanced
-together: each round of afn_pcg_step_many queues one PCG iteration (or
-refinement step) of every running solve on its own stream -- so their
-kernels overlap on the device -- and then takes every stopping decision
-after one pass of host waits.  A finished solve leaves the batch at once and
-its slot and memory go to the next request, so requests join and leave
-between iterations.  The step API runs the same launches as afn_pcg_solve,
+together by afn_pcg_step_many: each keeps one PCG iteration (or refinement
+step) in flight on its own stream -- so their kernels overlap on the device
+-- and the host takes each stopping decision as soon as that request's
+iteration is done.  A finished solve leaves the batch at once (the call
+returns) and its slot and memory go to the next request, so requests join
+and leave between iterations.  The step API runs the same launches as afn_pcg_solve,
 so a request's result does not depend on which other requests share the GPU.
 """
 from __future__ import annotations
@@ -88,12 +88,13 @@ class Job:
 class Server:
     """slots: requests admitted at once (set up or iterating); hbm_budget:
     bytes for all of them together (default: 90% of the free device memory
-    at start); iters: products per request between admission checks;
+    at start); iters: products per request and afn_pcg_step_many call at most
+    (the call also returns as soon as a request finishes);
     setup_workers: setups that may run at once."""
 
     def __init__(self, slots: int = 8, hbm_budget: int | None = None,
                  precision: int = afn.AFN_FP32, keep_x: bool | str = False, device: str = "cuda",
-                 iters: int = 1, setup_workers: int = 2):
+                 iters: int = 8, setup_workers: int = 2):
         self.slots = slots
         self.precision = precision
         self.keep_x = keep_x
