@@ -331,7 +331,10 @@ afn_status afn_pcg_begin(afn_handle *h, const double *b_dev, double *x_dev, doub
  * NULL: each state's work goes on the stream it was begun on, so solves
  * overlap on the device; otherwise all of it goes on 'stream' (ordered after
  * the begin streams; pass the same value on every call for a state).  A state
- * that finishes writes x_dev and its info.afn_status afn_pcg_step_many(afn_pcg_state *const *states, int32_t count, int32_t iters, void *stream);
+ * that finishes writes x_dev and its info.  Errors: EINVAL (a NULL state,
+ * count < 1, iters < 1, two states on one handle), EDEVICE; the outcome of
+ * each solve is read by afn_pcg_query. */
+afn_status afn_pcg_step_many(afn_pcg_state *const *states, int32_t count, int32_t iters, void *stream);
 
 /* *done = 1 once the solve has finished; info_host (may be NULL) then holds
  * the result, and the return value is the solve's status (OK, ENOCONV,
@@ -346,6 +349,35 @@ void afn_pcg_end(afn_pcg_state *st);
 /* Release the handle and its device memory.  NULL is allowed.  Work the
  * caller queued with afn_apply on the handle must be complete. */
 void afn_destroy(afn_handle *h);
+
+/* ---- Autotuner of launch shapes ---------------------------------------------
+ * Tunables with a few candidates each, all computing the same result up to
+ * the order of the sums: the tile kernel of the kernel matvec for d = 5..8
+ * with tile boxes (MFMA distance contraction or plain differences), the
+ * split count of the split-K GEMMs (the batched apply of block solves, the
+ * Nystrom W W^T, the high-dimension FSAI columns) and the split count of the
+ * GEMVs of the apply.  Modes: AFN_TUNE_OFF (default: the built-in
+ * heuristics), AFN_TUNE_ON (the first call that meets a new shape class, on
+ * a stream that is not recording a graph, times every candidate on its own
+ * buffers -- one warm-up and three timed runs each -- and keeps the fastest
+ * for the process), AFN_TUNE_FORCE (candidate 'index' of every tunable,
+ * clamped to its count: for tests that every candidate agrees).  Decisions are
+ * keyed by tunable, shape class and device (architecture and CU count).
+ * cache_path (may be NULL): decisions are read from it now and the whole
+ * table is written to it after each new decision, one "key choice" line each.
+ * Process-wide; calls that overlap with it are not allowed.  Errors: EINVAL. */
+typedef enum afn_tune_mode {
+    AFN_TUNE_OFF = 0,
+    AFN_TUNE_ON = 1,
+    AFN_TUNE_FORCE = 2
+} afn_tune_mode;
+afn_status afn_tune_config(int32_t mode, int32_t index, const char *cache_path);
+
+/* The decisions so far as text, one line per shape class: key, chosen
+ * candidate and the measured milliseconds of each candidate (none for those
+ * read from a cache file).  Writes at most cap - 1 characters and a NUL;
+ * *len = the full length.  Errors: EINVAL. */
+afn_status afn_tune_report(char *buf_host, int64_t cap, int64_t *len);
 
 /* Static description of a status code. */
 const char *afn_status_string(afn_status s);

@@ -23,6 +23,7 @@ AFN_FP64, AFN_FP32, AFN_BF16 = 0, 1, 2
 AFN_METHOD_AFN, AFN_METHOD_NYSTROM, AFN_METHOD_AUTO = 0, 1, 2
 AFN_LANDMARKS_AUTO, AFN_LANDMARKS_FPS, AFN_LANDMARKS_UNIFORM = 0, 1, 2
 AFN_KERNEL_GAUSSIAN, AFN_KERNEL_MATERN32 = 0, 1
+AFN_TUNE_OFF, AFN_TUNE_ON, AFN_TUNE_FORCE = 0, 1, 2
 _STATUS_NAMES = ["AFN_OK", "AFN_EINVAL", "AFN_ENOMEM", "AFN_ENOTSPD", "AFN_ENOCONV",
                  "AFN_EBREAKDOWN", "AFN_ESTAGNATION", "AFN_EDEVICE"]
 
@@ -33,7 +34,8 @@ def status_name(status: int) -> str:
 EXPORTED = ["kernel_matvec", "kernel_matvec_ex", "kernel_matvec_noalloc", "afn_workspace_size", "afn_setup",
             "afn_apply", "afn_pcg_solve", "afn_pcg_begin", "afn_pcg_step_many", "afn_pcg_query",
             "afn_pcg_end", "afn_get_info", "afn_get_landmarks", "afn_get_fsai", "afn_get_cholesky",
-            "afn_footprint_bytes", "afn_destroy", "afn_status_string", "afn_last_error"]
+            "afn_footprint_bytes", "afn_tune_config", "afn_tune_report", "afn_destroy", "afn_status_string",
+            "afn_last_error"]
 
 
 class AFNError(RuntimeError):
@@ -104,6 +106,8 @@ def _declare(L):
     L.afn_pcg_query.argtypes = [_P, ctypes.POINTER(_I32), ctypes.POINTER(afn_solve_info)]
     L.afn_pcg_end.argtypes = [_P]
     L.afn_pcg_end.restype = None
+    L.afn_tune_config.argtypes = [_I32, _I32, ctypes.c_char_p]
+    L.afn_tune_report.argtypes = [ctypes.c_char_p, _I64, ctypes.POINTER(_I64)]
     L.afn_apply.argtypes = [_P, _P, _P, _I32, _I64, _P]
     L.afn_pcg_solve.argtypes = [_P, _P, _P, _I32, _I64, _D, _I32,
                                 ctypes.POINTER(afn_solve_info), _P]
@@ -121,7 +125,8 @@ def _declare(L):
     L.afn_last_error.restype = ctypes.c_char_p
     for name in ("kernel_matvec", "kernel_matvec_ex", "kernel_matvec_noalloc", "afn_workspace_size", "afn_setup",
                  "afn_apply", "afn_pcg_solve", "afn_pcg_begin", "afn_pcg_step_many", "afn_pcg_query",
-                 "afn_get_info", "afn_get_landmarks", "afn_get_fsai", "afn_get_cholesky", "afn_footprint_bytes"):
+                 "afn_get_info", "afn_get_landmarks", "afn_get_fsai", "afn_get_cholesky", "afn_footprint_bytes",
+                 "afn_tune_config", "afn_tune_report"):
         getattr(L, name).restype = ctypes.c_int
 
 
@@ -428,3 +433,17 @@ def afn_pcg_step_many(states, iters: int = 1, stream=None) -> None:
     arr = (ctypes.c_void_p * len(states))(*[s.ptr for s in states])
     sp = ctypes.c_void_p(None) if stream is None else _stream(stream)
     _check(lib().afn_pcg_step_many(arr, len(states), iters, sp), "afn_pcg_step_many")
+
+
+def tune_config(mode: int = AFN_TUNE_OFF, index: int = 0, cache_path: str | None = None) -> None:
+    """Autotuner mode (afn_tune_config): AFN_TUNE_OFF, AFN_TUNE_ON or AFN_TUNE_FORCE(index)."""
+    _check(lib().afn_tune_config(mode, index, cache_path.encode() if cache_path else None), "afn_tune_config")
+
+
+def tune_report() -> str:
+    """The autotuner's decisions: one line per shape class (key, choice, ms per candidate)."""
+    n = _I64(0)
+    _check(lib().afn_tune_report(None, 0, ctypes.byref(n)), "afn_tune_report")
+    buf = ctypes.create_string_buffer(n.value + 1)
+    _check(lib().afn_tune_report(buf, n.value + 1, ctypes.byref(n)), "afn_tune_report")
+    return buf.value.decode()

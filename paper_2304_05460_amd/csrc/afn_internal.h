@@ -6,6 +6,8 @@
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <functional>
+#include <string>
 #include <vector>
 
 #include "afn.h"
@@ -61,6 +63,11 @@ template <typename T, typename M>
 __host__ __device__ inline T widen(M v) { return (T)v; }
 template <>
 __host__ __device__ inline float widen<float, bf16_t>(bf16_t v) { return bf16_to_f32(v); }
+
+// Autotuner (tune.hip): the candidate to run for shape class 'shape' of
+// tunable 'kernel' (see afn_tune_config); run(i) queues candidate i on s.
+int tune_pick(const char *kernel, const std::string &shape, int ncand, int heuristic,
+              const std::function<afn_status(int)> &run, hipStream_t s);
 
 // Device memory of a handle: a bump allocator over one region (the caller's
 // workspace, or one block the library allocated for the handle).  Buffers

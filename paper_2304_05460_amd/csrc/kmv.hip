@@ -18,6 +18,8 @@
 #include <cmath>
 #include <type_traits>
 
+#include <cstdio>
+
 #include "afn_internal.h"
 #include "kfun.h"
 #include "mfma.h"
@@ -821,13 +823,12 @@ void launch_mf(dim3 grid, const T *Xs, int64_t npad, int64_t n, const VT *v, con
 
 template <int KIND, typename T, typename VT>
 void launch_sym(int d, dim3 grid, const T *Xs, int64_t npad, int64_t n, const VT *v, const int32_t *perm,
-                const T *box, T tcut, T tfar, int S, int ST, T *part, hipStream_t s)
+                const T *box, T tcut, T tfar, int S, int ST, T *part, hipStream_t s, bool mf)
 {
     const dim3 block(256);
-    // the MFMA variant needs tile boxes and pays off up to d = 4 (one MFMA per
-    // 16 x 16 block; in higher dimension tiles are rarely compact enough for
-    // the centred form, and FP64 exceeds its register budget)
-    if (box && d <= 8) {
+    // the MFMA variant needs tile boxes (d <= 8: one MFMA per 4 coordinates
+    // and 16 x 16 block); mf = false takes the plain differences
+    if (box && d <= 8 && mf) {
         const T r2 = T(kCentredR2Max);
         switch (d) {
             case 1: launch_mf<KIND, 1, T, VT>(grid, Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part, s); break;
@@ -860,16 +861,36 @@ afn_status kmv_sym_run(const T *Xs, const SymShape &sh, int64_t n, int d, double
 {
     const T tcut = (T)kernel_cut_t(kind, sizeof(T) == 8 ? kCullF64 : kCullF32);
     const T tfar = sizeof(T) == 8 ? (T)kernel_cut_t(kind, kFarF64) : (T)__builtin_inf();
+    const dim3 grid((unsigned)sh.nwg);
+    auto tile = [&](const VT *vc, bool mf) {
+        if (kind == AFN_KERNEL_MATERN32)
+            launch_sym<AFN_KERNEL_MATERN32, T, VT>(d, grid, Xs, sh.npad, n, vc, perm, box, tcut, tfar, sh.S, sh.ST,
+                                                   part, s, mf);
+        else
+            launch_sym<AFN_KERNEL_GAUSSIAN, T, VT>(d, grid, Xs, sh.npad, n, vc, perm, box, tcut, tfar, sh.S, sh.ST,
+                                                   part, s, mf);
+    };
+    // d = 5..8 with tile boxes: MFMA distance contraction (candidate 0) or
+    // plain differences (1), by the autotuner; one column and its reduction
+    // per timed run (y is written again below)
+    bool mf = true;
+    if (box && d >= 5 && d <= 8 && (const void *)y != (const void *)v) {
+        char shape[96];
+        snprintf(shape, sizeof shape, "d%d_n%lld_%s_k%d", d, (long long)n, sizeof(T) == 8 ? "f64" : "f32", kind);
+        const int pick = tune_pick("kmv_tile", shape, 2, 0, [&](int c) -> afn_status {
+            tile(v, c == 0);
+            AFN_HIP(hipGetLastError());
+            hipLaunchKernelGGL((kmv_sym_reduce<T, VT>), dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, part,
+                               n, sh.S, sh.ST, mu, v, perm, y);
+            AFN_HIP(hipGetLastError());
+            return AFN_OK;
+        }, s);
+        mf = pick == 0;
+    }
     for (int c = 0; c < nrhs; ++c) {
         const VT *vc = v + c * ldv;
         if (ev0) AFN_HIP(hipEventRecord(ev0, s));
-        const dim3 grid((unsigned)sh.nwg);
-        if (kind == AFN_KERNEL_MATERN32)
-            launch_sym<AFN_KERNEL_MATERN32, T, VT>(d, grid, Xs, sh.npad, n, vc, perm, box, tcut, tfar, sh.S, sh.ST,
-                                                   part, s);
-        else
-            launch_sym<AFN_KERNEL_GAUSSIAN, T, VT>(d, grid, Xs, sh.npad, n, vc, perm, box, tcut, tfar, sh.S, sh.ST,
-                                                   part, s);
+        tile(vc, mf);
         AFN_HIP(hipGetLastError());
         if (ev1) AFN_HIP(hipEventRecord(ev1, s));
         hipLaunchKernelGGL((kmv_sym_reduce<T, VT>), dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, part,

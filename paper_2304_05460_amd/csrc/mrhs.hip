@@ -15,6 +15,8 @@
 // MFMA operand layouts: mfma.h.
 #include <cmath>
 
+#include <cstdio>
+
 #include "afn_internal.h"
 #include "kfun.h"
 #include "mfma.h"
@@ -934,21 +936,44 @@ afn_status gemm_rows(const T *A, int64_t ars, int64_t acs, int64_t m, int64_t K,
     const int NBk = (R + 15) / 16;
     // A is read along t when its t stride is 1 (KF), along i otherwise
     const bool kf = acs == 1;
-    const int S = gemm_splits_launch(m, K, gemm_wgs_per_cu<T>(kf));
-    const int64_t kps = round_up(ceil_div(K, S), TL);
+    const int smax = gemm_splits(m, K);      // the partial buffer holds this many
+    const int S0 = gemm_splits_launch(m, K, gemm_wgs_per_cu<T>(kf));
+    // split counts: the heuristic's (whole rounds of the chip), half of it and
+    // twice it, within what the partial buffer holds
+    int cand[3];
+    int nc = 0;
+    for (int q : {S0, S0 / 2, 2 * S0}) {
+        q = q < 1 ? 1 : (q > smax ? smax : q);
+        bool dup = false;
+        for (int c = 0; c < nc; ++c) dup = dup || cand[c] == q;
+        if (!dup) cand[nc++] = q;
+    }
     const int64_t mpad = round_up(m, TL);
-    dim3 g((unsigned)ceil_div(m, TL), (unsigned)S);
     const auto al16 = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
     const bool vec = al16(A) && al16(B) && ldb % 4 == 0 && (kf ? ars % 4 == 0 : (ars == 1 && acs % 4 == 0));
-    if (kf && vec) launch_gemm<T, true, true>(NBk, g, A, ars, acs, m, K, B, ldb, R, kps, part, mpad, s);
-    else if (kf) launch_gemm<T, true, false>(NBk, g, A, ars, acs, m, K, B, ldb, R, kps, part, mpad, s);
-    else if (vec) launch_gemm<T, false, true>(NBk, g, A, ars, acs, m, K, B, ldb, R, kps, part, mpad, s);
-    else launch_gemm<T, false, false>(NBk, g, A, ars, acs, m, K, B, ldb, R, kps, part, mpad, s);
-    AFN_HIP(hipGetLastError());
-    hipLaunchKernelGGL((gemm_reduce<T>), dim3((unsigned)ceil_div(m * R, 256)), dim3(256), 0, s, part, mpad,
-                       16 * NBk, S, m, R, base, sign, C, ldc);
-    AFN_HIP(hipGetLastError());
-    return AFN_OK;
+    auto launch = [&](int c) -> afn_status {
+        const int S = cand[c];
+        const int64_t kps = round_up(ceil_div(K, S), TL);
+        dim3 g((unsigned)ceil_div(m, TL), (unsigned)S);
+        if (kf && vec) launch_gemm<T, true, true>(NBk, g, A, ars, acs, m, K, B, ldb, R, kps, part, mpad, s);
+        else if (kf) launch_gemm<T, true, false>(NBk, g, A, ars, acs, m, K, B, ldb, R, kps, part, mpad, s);
+        else if (vec) launch_gemm<T, false, true>(NBk, g, A, ars, acs, m, K, B, ldb, R, kps, part, mpad, s);
+        else launch_gemm<T, false, false>(NBk, g, A, ars, acs, m, K, B, ldb, R, kps, part, mpad, s);
+        AFN_HIP(hipGetLastError());
+        hipLaunchKernelGGL((gemm_reduce<T>), dim3((unsigned)ceil_div(m * R, 256)), dim3(256), 0, s, part, mpad,
+                           16 * NBk, S, m, R, base, sign, C, ldc);
+        AFN_HIP(hipGetLastError());
+        return AFN_OK;
+    };
+    int pick = 0;
+    if ((const void *)base != (const void *)C && (const void *)A != (const void *)C &&
+        (const void *)B != (const void *)C) {
+        char shape[112];
+        snprintf(shape, sizeof shape, "m%lld_K%lld_R%d_%s%s", (long long)m, (long long)K, R,
+                 sizeof(T) == 8 ? "f64" : "f32", kf ? "_kf" : "");
+        pick = tune_pick("gemm_splits", shape, nc, 0, launch, s);
+    }
+    return launch(pick);
 }
 
 template afn_status gemm_rows<float>(const float *, int64_t, int64_t, int64_t, int64_t, const float *,

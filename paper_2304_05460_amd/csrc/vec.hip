@@ -1,6 +1,8 @@
 // Vector kernels of the AFN apply (Algorithm 3) and of PCG.  Every reduction
 // has a fixed order (per-workgroup partials, then one ordered pass), so results
 // are bitwise reproducible run to run.
+#include <cstdio>
+
 #include "afn_internal.h"
 
 namespace afn {
@@ -467,18 +469,39 @@ afn_status gemv_nT(const M *A, int64_t lda, int64_t m, int64_t ncols, const T *x
                    T sign, T *y, T *part, hipStream_t s)
 {
     if (m <= 0) return AFN_OK;
-    const int64_t S = gemv_splits(m, ncols);
-    const int64_t chunk = ceil_div(ncols, S);
-    hipLaunchKernelGGL((gemv_n_partial<T, M>), dim3((unsigned)ceil_div(m, 256), (unsigned)S), dim3(256), 0, s,
-                       A, lda, m, ncols, x, chunk, part);
-    if (S > 32)
-        hipLaunchKernelGGL((gemv_n_reduce_wave<T>), dim3((unsigned)ceil_div(m, 4)), dim3(256), 0, s, part, m,
-                           (int)S, base, sign, y);
-    else
-        hipLaunchKernelGGL((gemv_n_reduce<T>), dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, part, m,
-                           (int)S, base, sign, y);
-    AFN_HIP(hipGetLastError());
-    return AFN_OK;
+    // split counts: the heuristic's, and a half and a quarter of it (the
+    // partial buffer holds the heuristic's)
+    const int64_t S0 = gemv_splits(m, ncols);
+    int64_t cand[3];
+    int nc = 0;
+    for (int64_t q : {S0, S0 / 2, S0 / 4}) {
+        q = q < 1 ? 1 : q;
+        bool dup = false;
+        for (int c = 0; c < nc; ++c) dup = dup || cand[c] == q;
+        if (!dup) cand[nc++] = q;
+    }
+    auto launch = [&](int c) -> afn_status {
+        const int64_t S = cand[c];
+        const int64_t chunk = ceil_div(ncols, S);
+        hipLaunchKernelGGL((gemv_n_partial<T, M>), dim3((unsigned)ceil_div(m, 256), (unsigned)S), dim3(256), 0,
+                           s, A, lda, m, ncols, x, chunk, part);
+        if (S > 32)
+            hipLaunchKernelGGL((gemv_n_reduce_wave<T>), dim3((unsigned)ceil_div(m, 4)), dim3(256), 0, s, part, m,
+                               (int)S, base, sign, y);
+        else
+            hipLaunchKernelGGL((gemv_n_reduce<T>), dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, part, m,
+                               (int)S, base, sign, y);
+        AFN_HIP(hipGetLastError());
+        return AFN_OK;
+    };
+    int pick = 0;
+    if ((const void *)base != (const void *)y && (const void *)x != (const void *)y) {
+        char shape[96];
+        snprintf(shape, sizeof shape, "m%lld_n%lld_%s", (long long)m, (long long)ncols,
+                 sizeof(M) == 2 ? "bf16" : (sizeof(T) == 8 ? "f64" : "f32"));
+        pick = tune_pick("gemv_n_splits", shape, nc, 0, launch, s);
+    }
+    return launch(pick);
 }
 
 template <typename T, typename M = T>
