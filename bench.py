@@ -155,6 +155,26 @@ def _line(metric, value, unit, steps, warmup, ms, dtype, config, **extra):
     print(json.dumps(out))
 
 
+def tune_decisions(args) -> dict:
+    """The autotuner's decisions of this run (taken in the warm-up): how many
+    shape classes it timed, and those where a candidate other than the
+    built-in heuristic's won, with the ms of each candidate."""
+    from paper_2304_05460_amd import afn
+    out = {"mode": args.tune, "shape_classes": 0, "kmv_tile": {}, "not_heuristic": {}}
+    for line in afn.tune_report().splitlines():
+        f = line.split()
+        if len(f) < 2:
+            continue
+        out["shape_classes"] += 1
+        key = f[0].rsplit("|", 1)[0]
+        val = [int(f[1])] + [round(float(t), 4) for t in f[2:]]
+        if key.startswith("kmv_tile"):
+            out["kmv_tile"][key] = val
+        elif val[0] != 0:
+            out["not_heuristic"][key] = val
+    return out
+
+
 def host_cpu() -> dict:
     """The host the oracle ran on: CPU model (lscpu), logical CPUs (nproc) and
     the OpenMP thread count it used."""
@@ -335,6 +355,7 @@ def c3_bench(args):
         "speedup_mixed_vs_fp64": round(value / fp64_value, 3),
         "roofline": roofline,
     }
+    out["autotune"] = tune_decisions(args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline_nystrom(X_np, p.l, p.mu, p.k, i64["iterations"])
@@ -544,6 +565,8 @@ def main():
     ap.add_argument("--c3-branch", default="nystrom", choices=["nystrom", "afn"],
                     help="preconditioner of the c3 solves (Algorithm 5's branches)")
     ap.add_argument("--maxit", type=int, default=0, help="PCG iteration cap (0: the workload's)")
+    ap.add_argument("--tune", default="on", choices=["on", "off"],
+                    help="autotuner of launch shapes (decisions taken during the warm-up and reported)")
     ap.add_argument("--mixed-only", action="store_true",
                     help="c3: time the mixed-precision solves only (for counter runs; no JSON contract line)")
     ap.add_argument("--serving", action="store_true",
@@ -559,6 +582,10 @@ def main():
         sys.exit(2)
 
     import torch
+    from paper_2304_05460_amd import afn as _afn
+
+    _afn.lib()
+    _afn.tune_config(_afn.AFN_TUNE_ON if args.tune == "on" else _afn.AFN_TUNE_OFF)
 
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
@@ -714,6 +741,7 @@ def c2_bench(args):
         "alg5": alg5,
         "roofline": roofline,
     }
+    out["autotune"] = tune_decisions(args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(X_np, b_np, p.l, p.mu, sinfo.k, p.w,
