@@ -317,6 +317,40 @@ __device__ __forceinline__ void mfma_tile64(const double *__restrict__ As, const
     }
 }
 
+// Trailing update A22 -= L21 L21^T of the blocked Cholesky on lower 64 x 64
+// tiles with FP64 MFMA: tile (I, C) takes the jb-column panel rows of both
+// row blocks as k-index-major operands (zero past k and past jb) and one
+// 64 x 64 x 64 product, as the triangular solve does.
+__global__ __launch_bounds__(256) void syrk_update_mf(double *A, int64_t lda, int j0, int jb, int k)
+{
+    const int I = blockIdx.y, C = blockIdx.x;
+    if (C > I) return;
+    __shared__ double As[NB * TSM];    // As[t * TSM + r] = L21[r0 + r, t]
+    __shared__ double Bs[NB * TSM];    // Bs[t * TSM + c] = L21[c0 + c, t]
+    const int base = j0 + jb;
+    const int r0 = base + I * NB, c0 = base + C * NB;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int e = tid; e < NB * NB; e += 256) {
+        const int t = e >> 6, r = e & 63;
+        As[t * TSM + r] = (t < jb && r0 + r < k) ? A[(r0 + r) + (int64_t)(j0 + t) * lda] : 0.0;
+        Bs[t * TSM + r] = (t < jb && c0 + r < k) ? A[(c0 + r) + (int64_t)(j0 + t) * lda] : 0.0;
+    }
+    __syncthreads();
+    doublex4 acc[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = doublex4{0.0, 0.0, 0.0, 0.0};
+    mfma_tile64(As, Bs, wave, lr, lk, 1.0, acc);
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = r0 + 16 * wave + lk + 4 * i, c = c0 + 16 * cb + lr;
+            if (r < k && c < k && r >= c) A[r + (int64_t)c * lda] -= acc[cb][i];
+        }
+}
+
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void trsm_left_lower_mf(const double *__restrict__ L,
                                                           const double *__restrict__ Dinv, int k, double *B,
                                                           int64_t ncols)
@@ -502,7 +536,7 @@ afn_status cholesky(double *A, int k, int64_t lda, int *info, hipStream_t s)
             hipLaunchKernelGGL(trsm_panel, dim3((unsigned)ceil_div(rest, 64)), dim3(64), 0, s, A, lda,
                                j0, jb, k);
             const unsigned T = (unsigned)ceil_div(rest, NB);
-            hipLaunchKernelGGL(syrk_update, dim3(T, T), dim3(256), 0, s, A, lda, j0, jb, k);
+            hipLaunchKernelGGL(syrk_update_mf, dim3(T, T), dim3(256), 0, s, A, lda, j0, jb, k);
         }
         AFN_HIP(hipGetLastError());
     }
