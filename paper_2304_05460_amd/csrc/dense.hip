@@ -160,42 +160,6 @@ __global__ __launch_bounds__(64) void trsm_panel(double *A, int64_t lda, int j0,
         for (int c = 0; c < jb; ++c) A[row + (int64_t)(j0 + c) * lda] = Xs[c][tid];
 }
 
-// Trailing update A22 -= L21 L21^T on lower 64 x 64 tiles.
-__global__ __launch_bounds__(256) void syrk_update(double *A, int64_t lda, int j0, int jb, int k)
-{
-    const int I = blockIdx.y, C = blockIdx.x;
-    if (C > I) return;
-    __shared__ double Ri[NB][NB + 2];  // Ri[t][row]
-    __shared__ double Rc[NB][NB + 2];  // Rc[t][col]
-    const int base = j0 + jb;
-    const int r0 = base + I * NB, c0 = base + C * NB;
-    const int tid = threadIdx.x;
-    for (int e = tid; e < NB * jb; e += 256) {
-        int t = e / NB, r = e - t * NB;
-        Ri[t][r] = r0 + r < k ? A[(r0 + r) + (int64_t)(j0 + t) * lda] : 0.0;
-        Rc[t][r] = c0 + r < k ? A[(c0 + r) + (int64_t)(j0 + t) * lda] : 0.0;
-    }
-    __syncthreads();
-    const int ty = tid / 16, tx = tid % 16;
-    double acc[4][4] = {};
-    for (int t = 0; t < jb; ++t) {
-        double a[4], b[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) { a[q] = Ri[t][ty * 4 + q]; b[q] = Rc[t][tx * 4 + q]; }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int u = 0; u < 4; ++u) acc[q][u] = __builtin_fma(a[q], b[u], acc[q][u]);
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            int r = r0 + ty * 4 + q, c = c0 + tx * 4 + u;
-            if (r < k && c < k && r >= c) A[r + (int64_t)c * lda] -= acc[q][u];
-        }
-}
-
 // Inverse of each 64 x 64 lower diagonal block of L; identity-padded past k.
 // Dinv[b] column-major 64 x 64.  Thread c forms column c by forward
 // substitution on e_c.
