@@ -392,9 +392,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     if (tid < ST * ST)
     {
         // 0: skipped, 1: evaluated (every t below kBoundedT), 2: evaluated with
-        // the exponential in FP32, 3: evaluated (larger t possible).  The
-        // padding points of a partly filled tile (packed at the origin) lie
-        // outside its box, so its pairs are never 1.
+        // the exponential in FP32, 3: evaluated (larger t possible).  The box
+        // of a partly filled tile covers its real points only, while its
+        // padding points sit at the packing origin, which may lie inside or
+        // outside that box: the `full` test, not the box, keeps such pairs
+        // off the bounded form.
         const int64_t a = (int64_t)BI * ST + tid / ST, b = (int64_t)BJ * ST + tid % ST;
         const T g2 = box_gap2<D, T>(box, a, b);
         const bool full = (a + 1) * kTile <= n && (b + 1) * kTile <= n;
