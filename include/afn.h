@@ -120,7 +120,7 @@ typedef enum afn_landmarks {
 typedef struct afn_params {
     int32_t k;          /* landmark count; -1 = estimate it (Algorithm 4)         */
     int32_t k_max;      /* cap on the estimated count (Section 3.2: e.g. 2000)     */
-    int32_t w;          /* FSAI nonzeros per row incl. the diagonal, 1 <= w <= 64  */
+    int32_t w;          /* FSAI nonzeros per row incl. the diagonal, 1 <= w <= 128 */
     int32_t m;          /* rank-estimation subsample size; 0 = min(n, 2000)        */
     int32_t precision;  /* afn_precision of the PCG solve (FP32, BF16 need d <= 8) */
     int32_t method;     /* afn_method                                              */

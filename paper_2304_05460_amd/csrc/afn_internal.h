@@ -35,7 +35,7 @@ void clear_error();
     } while (0)
 
 constexpr int kMaxD = 64;
-constexpr int kMaxW = 64;
+constexpr int kMaxW = 128;
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }

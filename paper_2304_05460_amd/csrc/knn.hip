@@ -6,8 +6,9 @@
 // One wavefront per query p.  The 64 lanes evaluate 64 candidates at a time
 // (squared distance by the fixed fma chain, -ffp-contract=off, so keys are
 // bit-identical to a sequential evaluation); candidates whose key beats the
-// current (w-1)-th best enter a sorted list held one entry per lane, by a
-// wave-wide rank-and-shift.  The final set is unique, so the pattern does not
+// current (w-1)-th best enter a sorted list held NE entries per lane (entry
+// 64 e + l in lane l; NE = 1 for w <= 64, 2 for w <= 128), by a wave-wide
+// rank-and-shift.  The final set is unique, so the pattern does not
 // depend on the candidate order.  Queries are dealt round-robin to waves,
 // which balances the O(p) cost per query.
 //
@@ -33,10 +34,106 @@ __device__ __forceinline__ bool key_less(double d1, int q1, double d2, int q2)
     return d1 < d2 || (d1 == d2 && q1 < q2);
 }
 
+// The sorted list of a query: NE entries per lane (ld, lq), cnt entries, and
+// the key of the (w-1)-th entry once the list is full.
+template <int NE>
+struct KnnList {
+    double ld[NE];
+    int lq[NE];
+    int cnt = 0;
+    double thr_d = __builtin_inf();
+    int thr_q = INT_MAX;
+    __device__ KnnList()
+    {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            ld[e] = __builtin_inf();
+            lq[e] = INT_MAX;
+        }
+    }
+};
+
+// Offer this lane's candidate (dq, qi) if pass; the wave's passing candidates
+// enter one at a time, lowest lane first.  want <= 64 NE.
+template <int NE>
+__device__ __forceinline__ void knn_offer(KnnList<NE> &L, int want, bool pass, double dq, int qi)
+{
+    const int lane = threadIdx.x & 63;
+    pass = pass && (L.cnt < want || key_less(dq, qi, L.thr_d, L.thr_q));
+    uint64_t mask = __ballot(pass);
+    while (mask) {
+        const int src = __ffsll((unsigned long long)mask) - 1;
+        const double nd = __shfl(dq, src, 64);
+        const int nq = __shfl(qi, src, 64);
+        int pos = 0;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            const bool lt = 64 * e + lane < L.cnt && key_less(L.ld[e], L.lq[e], nd, nq);
+            pos += __popcll(__ballot(lt));
+        }
+        // entries at positions >= pos move up by one; position 64 e takes the
+        // old entry 64 e - 1 (lane 63 of the entry below, read before it moves)
+#pragma unroll
+        for (int e = NE - 1; e >= 0; --e) {
+            double upd = __shfl_up(L.ld[e], 1, 64);
+            int upq = __shfl_up(L.lq[e], 1, 64);
+            if (e > 0) {
+                const double bd = __shfl(L.ld[e > 0 ? e - 1 : 0], 63, 64);
+                const int bq = __shfl(L.lq[e > 0 ? e - 1 : 0], 63, 64);
+                if (lane == 0) { upd = bd; upq = bq; }
+            }
+            const int idx = 64 * e + lane;
+            if (idx > pos) { L.ld[e] = upd; L.lq[e] = upq; }
+            if (idx == pos) { L.ld[e] = nd; L.lq[e] = nq; }
+            if (idx >= want) { L.ld[e] = __builtin_inf(); L.lq[e] = INT_MAX; }
+        }
+        L.cnt = L.cnt + 1 < want ? L.cnt + 1 : want;
+        mask &= mask - 1;
+        if (L.cnt == want) {
+            const int te = (want - 1) >> 6, tl = (want - 1) & 63;
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const double td = __shfl(L.ld[e], tl, 64);
+                const int tq = __shfl(L.lq[e], tl, 64);
+                if (e == te) { L.thr_d = td; L.thr_q = tq; }
+            }
+            mask &= __ballot(pass && key_less(dq, qi, L.thr_d, L.thr_q));
+        }
+    }
+}
+
+// Row p of the pattern from the final list: the cnt neighbours in ascending
+// index (each entry's rank among them), then p, then -1 up to w.
+template <int NE>
+__device__ __forceinline__ void knn_write_row(const KnnList<NE> &L, int64_t p, int w, int32_t *__restrict__ cols)
+{
+    const int lane = threadIdx.x & 63;
+    int rank[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) rank[e] = 0;
+#pragma unroll
+    for (int e2 = 0; e2 < NE; ++e2) {
+        const int lim = L.cnt - 64 * e2;
+        for (int j = 0; j < lim && j < 64; ++j) {
+            const int oq = __shfl(L.lq[e2], j, 64);
+#pragma unroll
+            for (int e = 0; e < NE; ++e) rank[e] += (oq < L.lq[e]) ? 1 : 0;
+        }
+    }
+    int32_t *row = cols + p * w;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+        const int idx = 64 * e + lane;
+        if (idx < L.cnt) row[rank[e]] = L.lq[e];
+        if (idx > L.cnt && idx < w) row[idx] = -1;
+    }
+    if (lane == 0) row[L.cnt] = (int32_t)p;
+}
+
 // D >= d: the query's coordinates sit in registers, zero-padded to D; the
 // candidate's coordinates beyond d are taken as zero too, so the squared
 // distance is the fma chain over t = 0..d-1 followed by additions of +0.
-template <int D>
+template <int D, int NE>
 __global__ __launch_bounds__(256) void knn_pred(const double *__restrict__ Xr, int64_t nr, int d,
                                                 int w, int32_t *__restrict__ cols)
 {
@@ -48,11 +145,7 @@ __global__ __launch_bounds__(256) void knn_pred(const double *__restrict__ Xr, i
         double xp[D];
 #pragma unroll
         for (int t = 0; t < D; ++t) xp[t] = t < d ? Xr[p * d + t] : 0.0;
-        double ld = __builtin_inf();   // this lane's list entry
-        int lq = INT_MAX;
-        int cnt = 0;
-        double thr_d = __builtin_inf();
-        int thr_q = INT_MAX;
+        KnnList<NE> L;
         if (want > 0) {
             for (int64_t q0 = 0; q0 < p; q0 += 64) {
                 const int64_t q = q0 + lane;
@@ -69,78 +162,10 @@ __global__ __launch_bounds__(256) void knn_pred(const double *__restrict__ Xr, i
                     }
                     dq = acc;
                 }
-                const int qi = (int)q;
-                bool pass = valid && (cnt < want || key_less(dq, qi, thr_d, thr_q));
-                uint64_t mask = __ballot(pass);
-                while (mask) {
-                    const int src = __ffsll((unsigned long long)mask) - 1;
-                    const double nd = __shfl(dq, src, 64);
-                    const int nq = __shfl(qi, src, 64);
-                    const bool lt = lane < cnt && key_less(ld, lq, nd, nq);
-                    const int pos = __popcll(__ballot(lt));
-                    const double upd = __shfl_up(ld, 1, 64);
-                    const int upq = __shfl_up(lq, 1, 64);
-                    if (lane > pos) { ld = upd; lq = upq; }
-                    if (lane == pos) { ld = nd; lq = nq; }
-                    if (lane >= want) { ld = __builtin_inf(); lq = INT_MAX; }
-                    cnt = cnt + 1 < want ? cnt + 1 : want;
-                    mask &= mask - 1;
-                    if (cnt == want) {
-                        thr_d = __shfl(ld, want - 1, 64);
-                        thr_q = __shfl(lq, want - 1, 64);
-                        mask &= __ballot(pass && key_less(dq, qi, thr_d, thr_q));
-                    }
-                }
+                knn_offer(L, want, valid, dq, (int)q);
             }
         }
-        // rank of this lane's neighbour among the cnt selected, by index
-        int rank = 0;
-        for (int j = 0; j < cnt; ++j) {
-            int oq = __shfl(lq, j, 64);
-            rank += (oq < lq) ? 1 : 0;
-        }
-        int32_t *row = cols + p * w;
-        if (lane < cnt) row[rank] = lq;
-        if (lane == 0) row[cnt] = (int32_t)p;
-        if (lane > cnt && lane < w) row[lane] = -1;
-    }
-}
-
-// The sorted list of a query: one entry per lane (ld, lq), cnt entries, and
-// the key of the (w-1)-th entry once the list is full.
-struct KnnList {
-    double ld = __builtin_inf();
-    int lq = INT_MAX;
-    int cnt = 0;
-    double thr_d = __builtin_inf();
-    int thr_q = INT_MAX;
-};
-
-// Offer this lane's candidate (dq, qi) if pass; the wave's passing candidates
-// enter one at a time, lowest lane first.
-__device__ __forceinline__ void knn_offer(KnnList &L, int want, bool pass, double dq, int qi)
-{
-    const int lane = threadIdx.x & 63;
-    pass = pass && (L.cnt < want || key_less(dq, qi, L.thr_d, L.thr_q));
-    uint64_t mask = __ballot(pass);
-    while (mask) {
-        const int src = __ffsll((unsigned long long)mask) - 1;
-        const double nd = __shfl(dq, src, 64);
-        const int nq = __shfl(qi, src, 64);
-        const bool lt = lane < L.cnt && key_less(L.ld, L.lq, nd, nq);
-        const int pos = __popcll(__ballot(lt));
-        const double upd = __shfl_up(L.ld, 1, 64);
-        const int upq = __shfl_up(L.lq, 1, 64);
-        if (lane > pos) { L.ld = upd; L.lq = upq; }
-        if (lane == pos) { L.ld = nd; L.lq = nq; }
-        if (lane >= want) { L.ld = __builtin_inf(); L.lq = INT_MAX; }
-        L.cnt = L.cnt + 1 < want ? L.cnt + 1 : want;
-        mask &= mask - 1;
-        if (L.cnt == want) {
-            L.thr_d = __shfl(L.ld, want - 1, 64);
-            L.thr_q = __shfl(L.lq, want - 1, 64);
-            mask &= __ballot(pass && key_less(dq, qi, L.thr_d, L.thr_q));
-        }
+        knn_write_row(L, p, w, cols);
     }
 }
 
@@ -171,7 +196,7 @@ __global__ __launch_bounds__(256) void knn_tile_boxes(const double *__restrict__
     box[(t * d + c) * 2 + 1] = hi;
 }
 
-template <int D>
+template <int D, int NE>
 __global__ __launch_bounds__(256) void knn_pred_tiles(const double *__restrict__ Xr, int64_t nr, int d, int w,
                                                       const int32_t *__restrict__ order,
                                                       const double *__restrict__ box,
@@ -198,7 +223,7 @@ __global__ __launch_bounds__(256) void knn_pred_tiles(const double *__restrict__
             }
             return acc;
         };
-        KnnList L;
+        KnnList<NE> L;
         auto scan_tile = [&](int64_t tt) {
             const int64_t jj = tt * 64 + lane;
             const int64_t q = jj < nr ? (int64_t)order[jj] : nr;
@@ -237,22 +262,53 @@ __global__ __launch_bounds__(256) void knn_pred_tiles(const double *__restrict__
                 }
             }
         } else if (want > 0) {
-            L = KnnList();
+            L = KnnList<NE>();
             for (int64_t q0 = 0; q0 < p; q0 += 64) {
                 const int64_t q = q0 + lane;
                 const bool valid = q < p;
                 knn_offer(L, want, valid, valid ? key(q) : __builtin_inf(), (int)q);
             }
         }
-        int rank = 0;
-        for (int i = 0; i < L.cnt; ++i) {
-            const int oq = __shfl(L.lq, i, 64);
-            rank += (oq < L.lq) ? 1 : 0;
-        }
-        int32_t *row = cols + p * w;
-        if (lane < L.cnt) row[rank] = L.lq;
-        if (lane == 0) row[L.cnt] = (int32_t)p;
-        if (lane > L.cnt && lane < w) row[lane] = -1;
+        knn_write_row(L, p, w, cols);
+    }
+}
+
+template <int NE>
+void launch_tiles(dim3 grid, dim3 block, hipStream_t s, const double *Xr, int64_t nr, int d, int w,
+                  const int32_t *order, const double *box, const int32_t *tmin, int64_t nt, int32_t *cols)
+{
+    switch (d) {
+        case 1: hipLaunchKernelGGL((knn_pred_tiles<1, NE>), grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
+        case 2: hipLaunchKernelGGL((knn_pred_tiles<2, NE>), grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
+        case 3: hipLaunchKernelGGL((knn_pred_tiles<3, NE>), grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
+        case 4: hipLaunchKernelGGL((knn_pred_tiles<4, NE>), grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
+        case 5: hipLaunchKernelGGL((knn_pred_tiles<5, NE>), grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
+        case 6: hipLaunchKernelGGL((knn_pred_tiles<6, NE>), grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
+        case 7: hipLaunchKernelGGL((knn_pred_tiles<7, NE>), grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
+        default: hipLaunchKernelGGL((knn_pred_tiles<8, NE>), grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
+    }
+}
+
+template <int NE>
+void launch_brute(dim3 grid, dim3 block, hipStream_t s, const double *Xr, int64_t nr, int d, int w, int32_t *cols)
+{
+    switch (d) {
+        case 1: hipLaunchKernelGGL((knn_pred<1, NE>), grid, block, 0, s, Xr, nr, d, w, cols); break;
+        case 2: hipLaunchKernelGGL((knn_pred<2, NE>), grid, block, 0, s, Xr, nr, d, w, cols); break;
+        case 3: hipLaunchKernelGGL((knn_pred<3, NE>), grid, block, 0, s, Xr, nr, d, w, cols); break;
+        case 4: hipLaunchKernelGGL((knn_pred<4, NE>), grid, block, 0, s, Xr, nr, d, w, cols); break;
+        case 5: hipLaunchKernelGGL((knn_pred<5, NE>), grid, block, 0, s, Xr, nr, d, w, cols); break;
+        case 6: hipLaunchKernelGGL((knn_pred<6, NE>), grid, block, 0, s, Xr, nr, d, w, cols); break;
+        case 7: hipLaunchKernelGGL((knn_pred<7, NE>), grid, block, 0, s, Xr, nr, d, w, cols); break;
+        case 8: hipLaunchKernelGGL((knn_pred<8, NE>), grid, block, 0, s, Xr, nr, d, w, cols); break;
+        default:
+            if (d <= 12) hipLaunchKernelGGL((knn_pred<12, NE>), grid, block, 0, s, Xr, nr, d, w, cols);
+            else if (d <= 16) hipLaunchKernelGGL((knn_pred<16, NE>), grid, block, 0, s, Xr, nr, d, w, cols);
+            else if (d <= 24) hipLaunchKernelGGL((knn_pred<24, NE>), grid, block, 0, s, Xr, nr, d, w, cols);
+            else if (d <= 32) hipLaunchKernelGGL((knn_pred<32, NE>), grid, block, 0, s, Xr, nr, d, w, cols);
+            else if (d <= 48) hipLaunchKernelGGL((knn_pred<48, NE>), grid, block, 0, s, Xr, nr, d, w, cols);
+            else hipLaunchKernelGGL((knn_pred<64, NE>), grid, block, 0, s, Xr, nr, d, w, cols);
+            break;
     }
 }
 
@@ -268,8 +324,8 @@ afn_status knn_pattern_ordered(const double *Xr, int64_t nr, int d, int w, const
                                int32_t *cols, hipStream_t s)
 {
     if (nr <= 0) return AFN_OK;
-    if (w < 1 || w > 64) {
-        set_error("knn_pattern: w=%d outside [1, 64]", w);
+    if (w < 1 || w > kMaxW) {
+        set_error("knn_pattern: w=%d outside [1, %d]", w, kMaxW);
         return AFN_EINVAL;
     }
     if (d > 8 || !order || !work) return knn_pattern(Xr, nr, d, w, cols, s);
@@ -280,16 +336,8 @@ afn_status knn_pattern_ordered(const double *Xr, int64_t nr, int d, int w, const
                        order, nt, box, tmin);
     int64_t waves = nr < 16384 ? nr : 16384;
     dim3 grid((unsigned)ceil_div(waves, 4)), block(256);
-    switch (d) {
-        case 1: hipLaunchKernelGGL(knn_pred_tiles<1>, grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
-        case 2: hipLaunchKernelGGL(knn_pred_tiles<2>, grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
-        case 3: hipLaunchKernelGGL(knn_pred_tiles<3>, grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
-        case 4: hipLaunchKernelGGL(knn_pred_tiles<4>, grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
-        case 5: hipLaunchKernelGGL(knn_pred_tiles<5>, grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
-        case 6: hipLaunchKernelGGL(knn_pred_tiles<6>, grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
-        case 7: hipLaunchKernelGGL(knn_pred_tiles<7>, grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
-        default: hipLaunchKernelGGL(knn_pred_tiles<8>, grid, block, 0, s, Xr, nr, d, w, order, box, tmin, nt, cols); break;
-    }
+    if (w > 64) launch_tiles<2>(grid, block, s, Xr, nr, d, w, order, box, tmin, nt, cols);
+    else launch_tiles<1>(grid, block, s, Xr, nr, d, w, order, box, tmin, nt, cols);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }
@@ -297,30 +345,14 @@ afn_status knn_pattern_ordered(const double *Xr, int64_t nr, int d, int w, const
 afn_status knn_pattern(const double *Xr, int64_t nr, int d, int w, int32_t *cols, hipStream_t s)
 {
     if (nr <= 0) return AFN_OK;
-    if (w < 1 || w > 64) {
-        set_error("knn_pattern: w=%d outside [1, 64]", w);
+    if (w < 1 || w > kMaxW) {
+        set_error("knn_pattern: w=%d outside [1, %d]", w, kMaxW);
         return AFN_EINVAL;
     }
     int64_t waves = nr < 16384 ? nr : 16384;
     dim3 grid((unsigned)ceil_div(waves, 4)), block(256);
-    switch (d) {
-        case 1: hipLaunchKernelGGL(knn_pred<1>, grid, block, 0, s, Xr, nr, d, w, cols); break;
-        case 2: hipLaunchKernelGGL(knn_pred<2>, grid, block, 0, s, Xr, nr, d, w, cols); break;
-        case 3: hipLaunchKernelGGL(knn_pred<3>, grid, block, 0, s, Xr, nr, d, w, cols); break;
-        case 4: hipLaunchKernelGGL(knn_pred<4>, grid, block, 0, s, Xr, nr, d, w, cols); break;
-        case 5: hipLaunchKernelGGL(knn_pred<5>, grid, block, 0, s, Xr, nr, d, w, cols); break;
-        case 6: hipLaunchKernelGGL(knn_pred<6>, grid, block, 0, s, Xr, nr, d, w, cols); break;
-        case 7: hipLaunchKernelGGL(knn_pred<7>, grid, block, 0, s, Xr, nr, d, w, cols); break;
-        case 8: hipLaunchKernelGGL(knn_pred<8>, grid, block, 0, s, Xr, nr, d, w, cols); break;
-        default:
-            if (d <= 12) hipLaunchKernelGGL(knn_pred<12>, grid, block, 0, s, Xr, nr, d, w, cols);
-            else if (d <= 16) hipLaunchKernelGGL(knn_pred<16>, grid, block, 0, s, Xr, nr, d, w, cols);
-            else if (d <= 24) hipLaunchKernelGGL(knn_pred<24>, grid, block, 0, s, Xr, nr, d, w, cols);
-            else if (d <= 32) hipLaunchKernelGGL(knn_pred<32>, grid, block, 0, s, Xr, nr, d, w, cols);
-            else if (d <= 48) hipLaunchKernelGGL(knn_pred<48>, grid, block, 0, s, Xr, nr, d, w, cols);
-            else hipLaunchKernelGGL(knn_pred<64>, grid, block, 0, s, Xr, nr, d, w, cols);
-            break;
-    }
+    if (w > 64) launch_brute<2>(grid, block, s, Xr, nr, d, w, cols);
+    else launch_brute<1>(grid, block, s, Xr, nr, d, w, cols);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }

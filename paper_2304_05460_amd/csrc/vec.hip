@@ -228,10 +228,11 @@ __device__ __forceinline__ T group16_sum(T s)
     return s;
 }
 
-// u[p] = sum_a gval[p*w + a] t[cols[p*w + a]], a < min(p+1, w) (w <= 64):
-// 16 lanes per row, lane q taking a = q, q + 16, q + 32, q + 48 (each load
-// instruction reads 16 consecutive entries of a row; 4 rows per wave).
-template <typename T, typename M = T>
+// u[p] = sum_a gval[p*w + a] t[cols[p*w + a]], a < min(p+1, w) (w <= 16 RP):
+// 16 lanes per row, lane q taking a = q, q + 16, ..., q + 16 (RP - 1) (each
+// load instruction reads 16 consecutive entries of a row; 4 rows per wave);
+// RP = 4 up to w = 64, 8 up to w = 128.
+template <typename T, typename M = T, int RP = 4>
 __global__ __launch_bounds__(256) void spmv_padded(const int32_t *__restrict__ cols,
                                                    const M *__restrict__ gval, int64_t nr, int w,
                                                    const T *__restrict__ t, T *__restrict__ u,
@@ -246,19 +247,19 @@ __global__ __launch_bounds__(256) void spmv_padded(const int32_t *__restrict__ c
     const int64_t base = p * w;
     // entries past the row's end load entry m - 1 (in bounds) and count zero,
     // so that every load is issued before the first wait
-    T g[4], tv[4];
-    int32_t cj[4];
+    T g[RP], tv[RP];
+    int32_t cj[RP];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < RP; ++r) {
         const int a = q + 16 * r < m ? q + 16 * r : m - 1;
         g[r] = widen<T>(gval[base + a]);
         cj[r] = cols[base + a];
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) tv[r] = t[cj[r]];
+    for (int r = 0; r < RP; ++r) tv[r] = t[cj[r]];
     T s = T(0);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) s = fmaT(q + 16 * r < m ? g[r] : T(0), tv[r], s);
+    for (int r = 0; r < RP; ++r) s = fmaT(q + 16 * r < m ? g[r] : T(0), tv[r], s);
     s = group16_sum(s);
     if (q == 0) u[p] = s;
 }
@@ -525,8 +526,12 @@ afn_status spmv_gT(const int32_t *cols, const M *gval, int64_t nr, int w, const 
                    const int32_t *order, hipStream_t s)
 {
     if (nr <= 0) return AFN_OK;
-    hipLaunchKernelGGL((spmv_padded<T, M>), dim3((unsigned)ceil_div(nr, 16)), dim3(256), 0, s, cols, gval, nr,
-                       w, t, u, order);
+    if (w > 64)
+        hipLaunchKernelGGL((spmv_padded<T, M, 8>), dim3((unsigned)ceil_div(nr, 16)), dim3(256), 0, s, cols, gval,
+                           nr, w, t, u, order);
+    else
+        hipLaunchKernelGGL((spmv_padded<T, M, 4>), dim3((unsigned)ceil_div(nr, 16)), dim3(256), 0, s, cols, gval,
+                           nr, w, t, u, order);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }

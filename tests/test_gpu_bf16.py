@@ -62,12 +62,17 @@ def test_c1_bf16_matches_fp64_oracle(afn, method):
     assert i16 <= 4 * i32 + 20
 
 
-@pytest.mark.parametrize("n,d,pts,l,mu,k,w", [(6000, 3, "mixture5", 0.1, 1e-3, 300, 32),
-                                             (5000, 8, "normal", 2.0, 1e-2, 400, 24)])
-def test_bf16_refines_to_tol_on_larger_inputs(afn, n, d, pts, l, mu, k, w):
+# the last case: a pattern wider than a wavefront (w = 100, as in the paper's
+# AFN runs), on the AFN branch only (Nystrom with 300 landmarks cannot
+# precondition this high-rank, mu = 1e-4 kernel in 500 iterations in any
+# precision)
+@pytest.mark.parametrize("n,d,pts,l,mu,k,w,methods", [(6000, 3, "mixture5", 0.1, 1e-3, 300, 32, (0, 1)),
+                                                     (5000, 8, "normal", 2.0, 1e-2, 400, 24, (0, 1)),
+                                                     (6000, 3, "uniform", 0.1, 1e-4, 300, 100, (0,))])
+def test_bf16_refines_to_tol_on_larger_inputs(afn, n, d, pts, l, mu, k, w, methods):
     X = W.points(pts, n, d, 77)
     b = np.random.default_rng(78).standard_normal(n)
-    for method in (0, 1):
+    for method in methods:
         h = afn.afn_setup(dev(X), l, mu, k=k, w=w, precision=afn.AFN_BF16, method=method, nrhs_max=0)
         x, info = afn.afn_pcg_solve(h, dev(b), tol=1e-8, maxit=500)
         h.close()

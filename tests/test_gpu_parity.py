@@ -317,7 +317,8 @@ def test_c1_g_rows_and_apply_entries(afn, c1):
     _per_row_g_and_apply(afn, h, A, X, p.l, p.mu, p.k, p.w, 21)
 
 
-@pytest.mark.parametrize("n,k,w,d", [(70, 3, 64, 3), (333, 17, 5, 8), (1500, 100, 40, 3), (1100, 60, 64, 5)])
+@pytest.mark.parametrize("n,k,w,d", [(70, 3, 64, 3), (333, 17, 5, 8), (1500, 100, 40, 3), (1100, 60, 64, 5),
+                                     (1500, 100, 100, 3), (900, 40, 128, 8), (300, 10, 70, 5)])
 def test_ragged_g_rows_and_apply_entries(afn, n, k, w, d):
     X = W.points("normal" if d >= 5 else "uniform", n, d, 29 + n)
     l, mu = 0.7, 1e-2
@@ -325,6 +326,31 @@ def test_ragged_g_rows_and_apply_entries(afn, n, k, w, d):
     A = oracle_setup(X, l, mu, k, w)
     _per_row_g_and_apply(afn, h, A, X, l, mu, k, w, 22)
     h.close()
+
+
+@pytest.mark.parametrize("w", [100, 128])
+def test_wide_pattern_pcg_matches_oracle(afn, w):
+    """Patterns wider than one wavefront (w > 64; the paper's AFN runs use
+    w = 100): single and block solves against the oracle's PCG."""
+    n, d, k, l, mu = 3000, 3, 200, 0.1, 1e-4
+    X = W.points("uniform", n, d, 61)
+    b = np.random.default_rng(62).standard_normal(n)
+    h = afn.afn_setup(dev(X), l, mu, k=k, w=w, landmarks=afn.AFN_LANDMARKS_FPS)
+    A = oracle_setup(X, l, mu, k, w)
+    x, info = afn.afn_pcg_solve(h, dev(b), tol=1e-10, maxit=500)
+    xo, ito, *_ = oracle.pcg(A, b, 1e-10, 500)
+    say(f"w={w} gpu", info["iterations"], "oracle", ito)
+    assert info["converged"] and abs(info["iterations"] - ito) <= 2
+    rel = np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo)
+    assert rel <= 1e-6
+    B = np.random.default_rng(63).standard_normal((n, 6))
+    Bt = torch.tensor(B.T.copy(), device="cuda").t()
+    xb, ib = afn.afn_pcg_solve(h, Bt, tol=1e-10, maxit=500)
+    h.close()
+    for c in (0, 5):
+        xoc, *_ = oracle.pcg(A, B[:, c], 1e-10, 500)
+        relc = np.linalg.norm(xb[:, c].cpu().numpy() - xoc) / np.linalg.norm(xoc)
+        assert relc <= 1e-6, (c, relc)
 
 
 def test_c1_pcg_matching_residual(afn, c1):
@@ -402,7 +428,7 @@ def test_k0_w1_is_plain_cg(afn):
 
 
 @pytest.mark.parametrize("n,k,w,d", [(1, 1, 1, 3), (5, 0, 3, 2), (70, 3, 64, 3), (333, 17, 5, 8),
-                                     (129, 64, 64, 3), (200, 65, 7, 12)])
+                                     (129, 64, 64, 3), (200, 65, 7, 12), (150, 20, 100, 3)])
 def test_small_and_ragged_shapes_match_oracle(afn, n, k, w, d):
     say(f"ragged n={n} k={k} w={w} d={d}")
     X = W.points("normal" if d == 8 else "uniform", n, d, 27 + n)
@@ -457,7 +483,9 @@ def test_c2_fps_pattern_and_fsai_sampled(afn):
 @pytest.mark.parametrize("n,d,w,pts", [(12000, 3, 64, "mixture5"), (9000, 2, 33, "uniform"),
                                        (8000, 5, 17, "normal"), (10000, 8, 64, "normal"),
                                        (5000, 1, 8, "uniform"), (3000, 3, 1, "uniform"),
-                                       (700, 4, 64, "uniform")])
+                                       (700, 4, 64, "uniform"), (6000, 3, 100, "uniform"),
+                                       (5000, 8, 128, "normal"), (700, 4, 65, "mixture5"),
+                                       (2500, 12, 100, "normal")])
 def test_knn_pattern_full_with_tiles(afn, n, d, w, pts):
     # every row of the predecessor pattern, bit-exact, across the tile-pruned
     # search (rows p >= (n-k)/4) and the full scan (the other rows)
@@ -512,7 +540,7 @@ def test_setup_errors(afn):
     with pytest.raises(afn.AFNError) as e:
         afn.afn_setup(dev(X), 0.5, 0.0, k=4, w=4)          # duplicate landmarks, mu = 0
     assert e.value.status == afn.AFN_ENOTSPD
-    for kw in [dict(k=21, w=4), dict(k=2, w=0), dict(k=2, w=65), dict(k=-2, w=4)]:
+    for kw in [dict(k=21, w=4), dict(k=2, w=0), dict(k=2, w=129), dict(k=-2, w=4)]:
         with pytest.raises(afn.AFNError) as e:
             afn.afn_setup(dev(W.points("uniform", 20, 3, 1)), 0.5, 1e-2, **kw)
         assert e.value.status == afn.AFN_EINVAL
@@ -807,7 +835,8 @@ def test_uniform_landmarks_limit(afn):
 
 
 
-@pytest.mark.parametrize("n,d,k,w", [(3000, 3, 200, 32), (2500, 12, 150, 64), (4000, 12, 512, 16)])
+@pytest.mark.parametrize("n,d,k,w", [(3000, 3, 200, 32), (2500, 12, 150, 64), (4000, 12, 512, 16),
+                                     (3000, 12, 200, 100)])
 def test_fsai_recompute_equals_gather(afn, monkeypatch, n, d, k, w):
     # the batched mode recomputes each pattern's columns of L^{-1} K12 as a
     # product with L^{-1} (MFMA GEMM), the gather mode reads them from

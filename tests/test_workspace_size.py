@@ -43,7 +43,7 @@ def test_size_covers_the_persistent_factors():
     assert afn.afn_footprint_bytes(n, d, k=k, w=w) == ws(n, d, k=k, w=w)
 
 
-@pytest.mark.parametrize("bad", [dict(k=-2), dict(w=0), dict(w=65), dict(method=3), dict(m=-1),
+@pytest.mark.parametrize("bad", [dict(k=-2), dict(w=0), dict(w=129), dict(method=3), dict(m=-1),
                                  dict(precision=afn.AFN_FP32, d=9), dict(nrhs_max=-1)])
 def test_invalid_parameters(bad):
     d = bad.pop("d", 3)
