@@ -481,7 +481,8 @@ def serving_bench(args):
     from paper_2304_05460_amd import afn, serving, workloads as W
 
     afn.lib()
-    probs = W.serving_requests(args.serving_count)
+    n_lo, n_hi = (float(v) for v in args.serving_n.split(","))
+    probs = W.serving_requests(args.serving_count, n_lo=n_lo, n_hi=n_hi)
     data = [W.make(q) for q in probs]
 
     def log(msg):
@@ -504,18 +505,18 @@ def serving_bench(args):
         return cb
 
     # warm-up: one small request (library load, first allocations)
-    srv = serving.Server(slots=args.slots, precision=afn.AFN_FP32)
+    srv = serving.Server(slots=args.slots, precision=afn.AFN_FP32, setup_workers=args.setup_workers)
     small = int(np.argmin([q.n for q in probs]))
     srv.run([reqs(np.zeros(len(probs)))[small]])
     log(f"{len(probs)} requests; burst run")
-    srv = serving.Server(slots=args.slots, precision=afn.AFN_FP32)
+    srv = serving.Server(slots=args.slots, precision=afn.AFN_FP32, setup_workers=args.setup_workers)
     t0 = time.perf_counter()
     burst = srv.run(reqs(np.zeros(len(probs))), on_done=progress("burst"))
     t_burst = time.perf_counter() - t0
     sb = serving.summarize(burst)
     rate = 0.7 * sb["completed"] / t_burst
     log(f"burst: {sb}; Poisson run at {rate:.3f} requests/s")
-    srv = serving.Server(slots=args.slots, precision=afn.AFN_FP32)
+    srv = serving.Server(slots=args.slots, precision=afn.AFN_FP32, setup_workers=args.setup_workers)
     t0 = time.perf_counter()
     pois = srv.run(reqs(W.poisson_arrivals(len(probs), rate, seed=5)), on_done=progress("poisson"))
     t_pois = time.perf_counter() - t0
@@ -534,8 +535,10 @@ def serving_bench(args):
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"serving_{len(probs)}_requests_n5e3_2e5_d3_8",
-                   "slots": args.slots, "poisson_rate_per_s": round(rate, 4),
+        "config": {"workload": f"serving_{len(probs)}_requests_n{n_lo:.0e}_{n_hi:.0e}_d3_8".replace("+0", ""),
+                   "grouped_launches": os.environ.get("AFN_NO_GROUP") != "1",
+                   "slots": args.slots, "setup_workers": args.setup_workers,
+                   "poisson_rate_per_s": round(rate, 4),
                    "n_median": int(np.median(ns)), "n_max": int(ns.max())},
         "poisson": {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in sp.items()},
         "burst": {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in sb.items()},
@@ -572,6 +575,10 @@ def main():
     ap.add_argument("--serving", action="store_true",
                     help="run the mixed-size request stream instead (p50/p99 latency, solves/s)")
     ap.add_argument("--serving-count", type=int, default=256)
+    ap.add_argument("--setup-workers", type=int, default=2,
+                    help="serving: host threads running afn_setup for admitted requests")
+    ap.add_argument("--serving-n", default="5e3,2e5",
+                    help="request sizes: n log-uniform between these two values")
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (counter calibration)")

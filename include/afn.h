@@ -173,7 +173,9 @@ typedef struct afn_solve_info {
     int32_t outer_iterations;  /* refinement steps of a mixed solve; 0 for FP64      */
     int32_t fp64_iterations;   /* mixed solve: FP64 PCG products after the FP32
                                   corrections broke down or stalled (max over rhs)  */
-    int32_t reserved;
+    int32_t grouped_units;     /* step-wise solve: units of work it advanced inside
+                                  grouped launches shared with other solves
+                                  (afn_pcg_step_many); 0 for afn_pcg_solve         */
 } afn_solve_info;
 
 typedef struct afn_handle afn_handle;

@@ -74,7 +74,7 @@ class afn_solve_info(ctypes.Structure):
                 ("relres", ctypes.c_double), ("relres_true", ctypes.c_double),
                 ("ms_solve", ctypes.c_double), ("ms_matvec", ctypes.c_double),
                 ("matvec_launches", ctypes.c_int32), ("outer_iterations", ctypes.c_int32),
-                ("fp64_iterations", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("fp64_iterations", ctypes.c_int32), ("grouped_units", ctypes.c_int32)]
 
 
 def lib():
@@ -370,7 +370,8 @@ def afn_pcg_solve(h: Handle, b: torch.Tensor, tol: float = 1e-6, maxit: int = 50
     return out, dict(status=st, iterations=inf.iterations, converged=bool(inf.converged),
                      relres=inf.relres, relres_true=inf.relres_true, ms_solve=inf.ms_solve,
                      ms_matvec=inf.ms_matvec, matvec_launches=inf.matvec_launches,
-                     outer_iterations=inf.outer_iterations, fp64_iterations=inf.fp64_iterations)
+                     outer_iterations=inf.outer_iterations, fp64_iterations=inf.fp64_iterations,
+                     grouped_units=inf.grouped_units)
 
 
 class PcgState:
@@ -397,7 +398,7 @@ class PcgState:
                                       relres=inf.relres, relres_true=inf.relres_true, ms_solve=inf.ms_solve,
                                       ms_matvec=inf.ms_matvec, matvec_launches=inf.matvec_launches,
                                       outer_iterations=inf.outer_iterations,
-                                      fp64_iterations=inf.fp64_iterations)
+                                      fp64_iterations=inf.fp64_iterations, grouped_units=inf.grouped_units)
 
     def end(self):
         if self._ptr:

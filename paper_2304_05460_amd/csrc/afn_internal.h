@@ -427,6 +427,7 @@ struct afn_handle {
     double *host_sc = nullptr;  // pinned host copy of PCG scalars
     hipEvent_t kmv_ev[2] = {nullptr, nullptr};  // timing of the matvec tile kernel
     hipEvent_t chk_ev = nullptr;                // the PCG residual check's host copy
+    hipEvent_t end_ev = nullptr;                // a step-wise solve moving to another stream
     int32_t *rorder = nullptr;                  // spatial order of the non-landmark rows (d <= 10)
     afn_setup_info info{};
 };

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "afn_internal.h"
+#include "group.h"
 #include "kfun.h"
 
 namespace afn {
@@ -171,7 +172,7 @@ afn_status apply_nysT(const afn_handle *h, const M *W, const T *Rginv, const T *
         AFN_TRY(gemv_t(Rginv, k, k, k, y1b, (const T *)nullptr, T(1), y2, s));
         AFN_TRY(gemv_t(W, k, k, n, y2, rp, T(-1), sp, s));
     } else {
-        AFN_HIP(hipMemcpyAsync(sp, rp, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
+        AFN_TRY(defer(s, [=](hipStream_t q) { return hipMemcpyAsync(sp, rp, sizeof(T) * n, hipMemcpyDeviceToDevice, q); }));
     }
     return scale_launch(sp, T(1.0 / h->mu), n, s);
 }
@@ -595,6 +596,7 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     AFN_HIP(hipEventCreate(&h->kmv_ev[0]));
     AFN_HIP(hipEventCreate(&h->kmv_ev[1]));
     AFN_HIP(hipEventCreateWithFlags(&h->chk_ev, hipEventDisableTiming));
+    AFN_HIP(hipEventCreateWithFlags(&h->end_ev, hipEventDisableTiming));
     AFN_TRY(check_flags(h, s));
     h->nnz = 0;
     if (nr > 0 && h->tptr) AFN_HIP(hipMemcpy(&h->nnz, h->tptr + nr, sizeof(int64_t), hipMemcpyDeviceToHost));
@@ -685,11 +687,24 @@ struct afn_pcg_state {
     int n_kmv = 0;
     double t_begin = 0.0, t_end = 0.0;
     hipStream_t stream = nullptr;   // the stream given to afn_pcg_begin
+    hipStream_t last = nullptr;     // the stream of the last work queued for it
+    int grouped = 0;                // units advanced inside grouped launches
     bool queued = false;            // a unit of work is in flight (afn_pcg_step_many)
 };
 
 namespace afn {
 namespace {
+
+// Grouped launches in afn_pcg_step_many; AFN_NO_GROUP=1 turns them off
+// (every unit then queued on its own, as a comparison).
+bool grouping_enabled()
+{
+    static const bool on = [] {
+        const char *e = std::getenv("AFN_NO_GROUP");
+        return !(e && e[0] == '1');
+    }();
+    return on;
+}
 
 double host_ms()
 {
@@ -860,8 +875,10 @@ afn_status inner_queue(afn_pcg_state *st, hipStream_t s)
                            h->kmv_ev[1], h->kperm, h->box32));
     AFN_TRY(dot_pcg(v.p, v.q, n, sc, kPcgAlpha, st->w.dotp, s));
     AFN_TRY(pcg_xr_launch(v.e, v.r, v.p, v.q, sc, n, st->w.dotp, sc + 2, s));
-    AFN_HIP(hipMemcpyAsync(h->host_sc + 9, sc + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-    AFN_HIP(hipEventRecord(h->chk_ev, s));
+    double *hs = h->host_sc + 9;
+    hipEvent_t chk = h->chk_ev;
+    AFN_TRY(defer(s, [=](hipStream_t q) { return hipMemcpyAsync(hs, sc + 1, 2 * sizeof(double), hipMemcpyDeviceToHost, q); }));
+    AFN_TRY(defer(s, [=](hipStream_t q) { return hipEventRecord(chk, q); }));
     // the next z = M^{-1} r and r'z are queued before the check (as in the
     // FP64 iteration)
     if (st->inner_it + 1 < st->maxit) {
@@ -988,7 +1005,7 @@ void state_info(const afn_pcg_state *st, afn_solve_info *info)
     info->matvec_launches = st->n_kmv;
     info->outer_iterations = st->mixed ? st->outer : 0;
     info->fp64_iterations = st->mixed ? (st->fallback ? st->it64 : 0) : 0;
-    info->reserved = 0;
+    info->grouped_units = st->grouped;
 }
 
 // Run one solve to its end on stream s (afn_pcg_solve's column loop).
@@ -1029,6 +1046,7 @@ void release_handle(afn_handle *h)
     for (auto &e : h->kmv_ev)
         if (e) (void)hipEventDestroy(e);
     if (h->chk_ev) (void)hipEventDestroy(h->chk_ev);
+    if (h->end_ev) (void)hipEventDestroy(h->end_ev);
     if (h->block_ev) (void)hipEventDestroy(h->block_ev);
     if (h->block_stream) (void)hipStreamDestroy(h->block_stream);
     if (h->ws_owned) (void)hipFree(h->ws_owned);
@@ -1205,7 +1223,7 @@ afn_status afn_pcg_solve(afn_handle *h, const double *b_dev, double *x_dev, int3
         info->matvec_launches = n_kmv;
         info->outer_iterations = outer_max;
         info->fp64_iterations = it64_max;
-        info->reserved = 0;
+        info->grouped_units = 0;
     }
     return worst;
 }
@@ -1301,6 +1319,7 @@ afn_status afn_pcg_begin(afn_handle *h, const double *b_dev, double *x_dev, doub
     std::unique_ptr<afn_pcg_state> st(new afn_pcg_state());
     AFN_TRY(state_init(h, b_dev, x_dev, tol, maxit, st.get()));
     st->stream = (hipStream_t)stream;
+    st->last = st->stream;
     AFN_TRY(state_begin(st.get(), st->stream));
     h->active = true;
     *out = st.release();
@@ -1335,14 +1354,102 @@ afn_status afn_pcg_step_many(afn_pcg_state *const *states, int32_t count, int32_
     // spent its budget, or at the end of the first polling pass in which a
     // solve finished (its caller can then release it and start another).
     // Units in flight at the return stay queued for the next call.
+    //
+    // The units due in one polling pass are queued together at its end:
+    // inner iterations of like mixed-precision solves (same d, kernel,
+    // precision, method, pattern width, n within a factor of 2) are recorded
+    // and replayed as grouped launches on the first one's stream (group.h);
+    // the rest are queued one by one.  An inner iteration that is due while a
+    // like solve's inner iteration is still in flight waits for it (one unit
+    // of a solve at most 4 times as costly), so that the two are queued
+    // together from then on; nothing waits past the end of the call.  A solve whose next unit goes to
+    // another stream than its last one's first waits there for all its work
+    // so far (end_ev), and its decisions are taken on the stream of its last
+    // unit, so each solve's work stays in order.
     std::vector<int> products(count, 0);
     bool finished_one = false;
+    std::vector<afn_pcg_state *> pend;
+    pend.reserve(count);
+    auto move_to = [](afn_pcg_state *st, hipStream_t q) -> afn_status {
+        if (st->last != q) {
+            AFN_HIP(hipEventRecord(st->h->end_ev, st->last));
+            AFN_HIP(hipStreamWaitEvent(q, st->h->end_ev, 0));
+            st->last = q;
+        }
+        return AFN_OK;
+    };
+    auto like = [](const afn_pcg_state *a, const afn_pcg_state *b) {
+        const afn_handle *x = a->h, *y = b->h;
+        auto cls = [](int64_t n) { return 63 - __builtin_clzll((unsigned long long)(n > 0 ? n : 1)); };
+        return x->d == y->d && x->kind == y->kind && x->precision == y->precision && x->method == y->method &&
+               (x->w > 64) == (y->w > 64) && cls(x->n) == cls(y->n);
+    };
+    auto inflight_like = [&](const afn_pcg_state *x) {
+        for (int32_t i = 0; i < count; ++i) {
+            const afn_pcg_state *y = states[i];
+            if (y != x && y->queued && y->phase == afn_pcg_state::kInner && like(x, y)) return true;
+        }
+        return false;
+    };
+    std::vector<afn_pcg_state *> held;
+    auto flush = [&](bool final) -> afn_status {
+        held.clear();
+        if (!final && grouping_enabled()) {
+            size_t m = 0;
+            for (afn_pcg_state *st : pend) {
+                if (st->phase == afn_pcg_state::kInner && inflight_like(st)) held.push_back(st);
+                else pend[m++] = st;
+            }
+            pend.resize(m);
+        }
+        std::vector<char> taken(pend.size(), 0);
+        if (grouping_enabled()) {
+            std::vector<afn_pcg_state *> grp;
+            for (size_t i = 0; i < pend.size(); ++i) {
+                if (taken[i] || pend[i]->phase != afn_pcg_state::kInner) continue;
+                grp.assign(1, pend[i]);
+                for (size_t j = i + 1; j < pend.size(); ++j)
+                    if (!taken[j] && pend[j]->phase == afn_pcg_state::kInner && like(pend[i], pend[j])) {
+                        grp.push_back(pend[j]);
+                        taken[j] = 1;
+                    }
+                if (grp.size() < 2) continue;
+                taken[i] = 1;
+                const hipStream_t q = sof(grp[0]);
+                std::vector<Recorder> recs(grp.size());
+                std::vector<Recorder *> rp(grp.size());
+                for (size_t g = 0; g < grp.size(); ++g) {
+                    AFN_TRY(move_to(grp[g], q));
+                    recorder() = &recs[g];
+                    const afn_status stq = state_queue(grp[g], q);
+                    recorder() = nullptr;
+                    AFN_TRY(stq);
+                    rp[g] = &recs[g];
+                }
+                std::vector<char> merged(grp.size(), 0);
+                AFN_TRY(replay_grouped(rp.data(), (int)rp.size(), q, merged.data()));
+                for (size_t g = 0; g < grp.size(); ++g) {
+                    grp[g]->queued = true;
+                    grp[g]->grouped += merged[g] ? 1 : 0;
+                }
+            }
+        }
+        for (size_t i = 0; i < pend.size(); ++i) {
+            if (taken[i]) continue;
+            afn_pcg_state *st = pend[i];
+            AFN_TRY(move_to(st, sof(st)));
+            AFN_TRY(state_queue(st, sof(st)));
+            st->queued = true;
+        }
+        pend.swap(held);
+        return AFN_OK;
+    };
     for (int32_t i = 0; i < count; ++i) {
         afn_pcg_state *st = states[i];
         if (st->phase == afn_pcg_state::kDone || st->queued) continue;
-        AFN_TRY(state_queue(st, sof(st)));
-        st->queued = true;
+        pend.push_back(st);
     }
+    AFN_TRY(flush(false));
     for (;;) {
         bool waiting = false, progressed = false;
         for (int32_t i = 0; i < count; ++i) {
@@ -1360,16 +1467,17 @@ afn_status afn_pcg_step_many(afn_pcg_state *const *states, int32_t count, int32_
             st->queued = false;
             progressed = true;
             if (counts_as_product(st)) products[i] += 1;
-            AFN_TRY(state_decide(st, sof(st)));
+            AFN_TRY(state_decide(st, st->last));
             if (st->phase == afn_pcg_state::kDone) {
                 finished_one = true;
             } else if (products[i] < iters) {
-                AFN_TRY(state_queue(st, sof(st)));
-                st->queued = true;
+                pend.push_back(st);
                 waiting = true;
             }
         }
-        if (!waiting || finished_one) break;
+        const bool last = !(waiting || !pend.empty()) || finished_one;
+        AFN_TRY(flush(last));
+        if (last) break;
         if (!progressed) std::this_thread::yield();
     }
     return AFN_OK;
@@ -1390,7 +1498,9 @@ afn_status afn_pcg_query(const afn_pcg_state *st, int32_t *done, afn_solve_info 
 void afn_pcg_end(afn_pcg_state *st)
 {
     if (!st) return;
+    // the unit in flight and the work queued behind its check
     if (st->queued && st->h) (void)hipEventSynchronize(st->h->chk_ev);
+    if (st->h) (void)hipStreamSynchronize(st->last);
     if (st->h) st->h->active = false;
     delete st;
 }

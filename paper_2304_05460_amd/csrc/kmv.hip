@@ -21,6 +21,7 @@
 #include <cstdio>
 
 #include "afn_internal.h"
+#include "group.h"
 #include "kfun.h"
 #include "mfma.h"
 
@@ -362,9 +363,27 @@ __device__ __forceinline__ T lanes16_sum4(T (&v)[4], int lane)
 // the box centre that column staging needs sits in LDS: that keeps the FP64
 // kernel within 128 registers without spills in its loops.
 template <int KIND, int D, typename T, typename VT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : (D <= 4 ? 4 : 2)))) void kmv_sym_mf(
-    const T *__restrict__ Xs, int64_t npad, int64_t n, const VT *__restrict__ v, const int32_t *__restrict__ perm,
-    const T *__restrict__ box, T tcut, T tfar, T r2max, int S, int ST, T *__restrict__ part)
+struct KmvMfArgs {
+    const T *Xs;
+    int64_t npad, n;
+    const VT *v;
+    const int32_t *perm;
+    const T *box;
+    T tcut, tfar, r2max;
+    int S, ST;
+    T *part;
+    static void launch1(const KmvMfArgs &p, dim3 grid, size_t lds, hipStream_t s);
+    static void launchG(const GroupTable<KmvMfArgs> &t, unsigned blocks, size_t lds, hipStream_t s);
+};
+
+// The body of the kernel for super-block pair bid (the single launch and the
+// grouped one, group.h; one instantiation per kernel, so that each kernel has
+// LDS arrays of its own).
+template <int KIND, int D, typename T, typename VT, bool GROUPED>
+__device__ __forceinline__ void kmv_sym_mf_body(const T *__restrict__ Xs, int64_t npad, int64_t n,
+                                                const VT *__restrict__ v, const int32_t *__restrict__ perm,
+                                                const T *__restrict__ box, T tcut, T tfar, T r2max, int S, int ST,
+                                                T *__restrict__ part, unsigned bid)
 {
     using M = Mfma<T>;
     constexpr int KC = D <= 4 ? 1 : 2;
@@ -382,7 +401,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     const int wave = tid >> 6, lane = tid & 63;
     const int lc = lane & 15, lg = lane >> 4;
     int BI, BJ;
-    decode_pair(blockIdx.x, S, BI, BJ);
+    decode_pair(bid, S, BI, BJ);
     const int64_t SB = (int64_t)ST * kTile;
     const bool diag_super = BI == BJ;
     for (int e = tid; e < 4 * kMaxSTmf * kTile; e += 256) (&colacc[0][0][0])[e] = T(0);
@@ -403,7 +422,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         const bool bounded = full && box_span2<D, T>(box, a, b) < T(kBoundedT);
         keep[tid] = g2 < tcut ? (g2 >= tfar ? 2 : (bounded ? 1 : 3)) : 0;
     }
-    T *rowout = part + (int64_t)blockIdx.x * 2 * SB;
+    T *rowout = part + (int64_t)bid * 2 * SB;
     T *colout = rowout + SB;
     auto next_kept = [&](int ti, int tj) {
         while (tj < ST && !keep[ti * ST + tj]) ++tj;
@@ -597,15 +616,63 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     }
 }
 
+template <int KIND, int D, typename T, typename VT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : (D <= 4 ? 4 : 2)))) void kmv_sym_mf(
+    const T *__restrict__ Xs, int64_t npad, int64_t n, const VT *__restrict__ v, const int32_t *__restrict__ perm,
+    const T *__restrict__ box, T tcut, T tfar, T r2max, int S, int ST, T *__restrict__ part)
+{
+    kmv_sym_mf_body<KIND, D, T, VT, false>(Xs, npad, n, v, perm, box, tcut, tfar, r2max, S, ST, part, blockIdx.x);
+}
+
+template <int KIND, int D, typename T, typename VT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : (D <= 4 ? 4 : 2)))) void kmv_sym_mf_g(
+    GroupTable<KmvMfArgs<KIND, D, T, VT>> t)
+{
+    const GroupPos q = group_pos(t);
+    const KmvMfArgs<KIND, D, T, VT> &a = t.a[q.g];
+    kmv_sym_mf_body<KIND, D, T, VT, true>(a.Xs, a.npad, a.n, a.v, a.perm, a.box, a.tcut, a.tfar, a.r2max, a.S, a.ST,
+                                          a.part, (unsigned)q.bx);
+}
+
+template <int KIND, int D, typename T, typename VT>
+void KmvMfArgs<KIND, D, T, VT>::launch1(const KmvMfArgs &p, dim3 grid, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL((kmv_sym_mf<KIND, D, T, VT>), grid, dim3(256), lds, s, p.Xs, p.npad, p.n, p.v, p.perm, p.box,
+                       p.tcut, p.tfar, p.r2max, p.S, p.ST, p.part);
+}
+
+template <int KIND, int D, typename T, typename VT>
+void KmvMfArgs<KIND, D, T, VT>::launchG(const GroupTable<KmvMfArgs> &t, unsigned blocks, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL((kmv_sym_mf_g<KIND, D, T, VT>), dim3(blocks), dim3(256), lds, s, t);
+}
+
 // y_i = sum over BJ >= s of row partials + sum over BI <= s of column
 // partials (ascending) + mu v_i, s = super-block of i.
 template <typename T, typename VT>
-__global__ __launch_bounds__(256) void kmv_sym_reduce(const T *__restrict__ part, int64_t n, int S,
-                                                      int ST, double mu, const VT *__restrict__ v,
-                                                      const int32_t *__restrict__ perm,
-                                                      VT *__restrict__ y)
+struct KmvRedArgs {
+    const T *part;
+    int64_t n;
+    int S, ST;
+    double mu;
+    const VT *v;
+    const int32_t *perm;
+    VT *y;
+    static void launch1(const KmvRedArgs &p, dim3 grid, size_t lds, hipStream_t s);
+    static void launchG(const GroupTable<KmvRedArgs> &t, unsigned blocks, size_t lds, hipStream_t s);
+};
+
+template <typename T, typename VT>
+__device__ __forceinline__ void kmv_sym_reduce_body(const KmvRedArgs<T, VT> &args, int64_t bx)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const T *__restrict__ part = args.part;
+    const int64_t n = args.n;
+    const int S = args.S, ST = args.ST;
+    const double mu = args.mu;
+    const VT *__restrict__ v = args.v;
+    const int32_t *__restrict__ perm = args.perm;
+    VT *__restrict__ y = args.y;
+    const int64_t i = bx * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t o = perm ? (int64_t)perm[i] : i;
     const int64_t SB = (int64_t)ST * kTile;
@@ -635,6 +702,28 @@ __global__ __launch_bounds__(256) void kmv_sym_reduce(const T *__restrict__ part
     }
     for (; bi <= s; ++bi) acc += (double)part[colq(bi) * 2 * SB + SB + ii];
     y[o] = (VT)(acc + mu * (double)v[o]);
+}
+
+template <typename T, typename VT>
+__global__ __launch_bounds__(256) void kmv_sym_reduce(KmvRedArgs<T, VT> args) { kmv_sym_reduce_body(args, blockIdx.x); }
+
+template <typename T, typename VT>
+__global__ __launch_bounds__(256) void kmv_sym_reduce_g(GroupTable<KmvRedArgs<T, VT>> t)
+{
+    const GroupPos q = group_pos(t);
+    kmv_sym_reduce_body(t.a[q.g], q.bx);
+}
+
+template <typename T, typename VT>
+void KmvRedArgs<T, VT>::launch1(const KmvRedArgs &p, dim3 grid, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL((kmv_sym_reduce<T, VT>), grid, dim3(256), lds, s, p);
+}
+
+template <typename T, typename VT>
+void KmvRedArgs<T, VT>::launchG(const GroupTable<KmvRedArgs> &t, unsigned blocks, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL((kmv_sym_reduce_g<T, VT>), dim3(blocks), dim3(256), lds, s, t);
 }
 
 // Generic tiles (any d <= D): one thread per row, the row's coordinates in
@@ -819,8 +908,7 @@ template <int KIND, int D, typename T, typename VT>
 void launch_mf(dim3 grid, const T *Xs, int64_t npad, int64_t n, const VT *v, const int32_t *perm, const T *box,
                T tcut, T tfar, T r2, int S, int ST, T *part, hipStream_t s)
 {
-    hipLaunchKernelGGL((kmv_sym_mf<KIND, D, T, VT>), grid, dim3(256), 0, s, Xs, npad, n, v, perm, box, tcut, tfar,
-                       r2, S, ST, part);
+    (void)dlaunch(grid, 0, s, KmvMfArgs<KIND, D, T, VT>{Xs, npad, n, v, perm, box, tcut, tfar, r2, S, ST, part});
 }
 
 template <int KIND, typename T, typename VT>
@@ -844,16 +932,20 @@ void launch_sym(int d, dim3 grid, const T *Xs, int64_t npad, int64_t n, const VT
         }
         return;
     }
-    switch (d) {
-        case 1: hipLaunchKernelGGL((kmv_sym<KIND, 1, T, VT>), grid, block, 0, s, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
-        case 2: hipLaunchKernelGGL((kmv_sym<KIND, 2, T, VT>), grid, block, 0, s, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
-        case 3: hipLaunchKernelGGL((kmv_sym<KIND, 3, T, VT>), grid, block, 0, s, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
-        case 4: hipLaunchKernelGGL((kmv_sym<KIND, 4, T, VT>), grid, block, 0, s, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
-        case 5: hipLaunchKernelGGL((kmv_sym<KIND, 5, T, VT>), grid, block, 0, s, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
-        case 6: hipLaunchKernelGGL((kmv_sym<KIND, 6, T, VT>), grid, block, 0, s, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
-        case 7: hipLaunchKernelGGL((kmv_sym<KIND, 7, T, VT>), grid, block, 0, s, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
-        default: hipLaunchKernelGGL((kmv_sym<KIND, 8, T, VT>), grid, block, 0, s, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
-    }
+    // plain differences: deferred like the rest, no grouped form
+    (void)defer(s, [=](hipStream_t st) {
+        switch (d) {
+            case 1: hipLaunchKernelGGL((kmv_sym<KIND, 1, T, VT>), grid, block, 0, st, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
+            case 2: hipLaunchKernelGGL((kmv_sym<KIND, 2, T, VT>), grid, block, 0, st, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
+            case 3: hipLaunchKernelGGL((kmv_sym<KIND, 3, T, VT>), grid, block, 0, st, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
+            case 4: hipLaunchKernelGGL((kmv_sym<KIND, 4, T, VT>), grid, block, 0, st, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
+            case 5: hipLaunchKernelGGL((kmv_sym<KIND, 5, T, VT>), grid, block, 0, st, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
+            case 6: hipLaunchKernelGGL((kmv_sym<KIND, 6, T, VT>), grid, block, 0, st, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
+            case 7: hipLaunchKernelGGL((kmv_sym<KIND, 7, T, VT>), grid, block, 0, st, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
+            default: hipLaunchKernelGGL((kmv_sym<KIND, 8, T, VT>), grid, block, 0, st, Xs, npad, n, v, perm, box, tcut, S, ST, part); break;
+        }
+        return hipGetLastError();
+    });
 }
 
 template <typename T, typename VT>
@@ -882,22 +974,19 @@ afn_status kmv_sym_run(const T *Xs, const SymShape &sh, int64_t n, int d, double
         const int pick = tune_pick("kmv_tile", shape, 2, 0, [&](int c) -> afn_status {
             tile(v, c == 0);
             AFN_HIP(hipGetLastError());
-            hipLaunchKernelGGL((kmv_sym_reduce<T, VT>), dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, part,
-                               n, sh.S, sh.ST, mu, v, perm, y);
-            AFN_HIP(hipGetLastError());
-            return AFN_OK;
+            return dlaunch(dim3((unsigned)ceil_div(n, 256)), 0, s,
+                           KmvRedArgs<T, VT>{part, n, sh.S, sh.ST, mu, v, perm, y});
         }, s);
         mf = pick == 0;
     }
     for (int c = 0; c < nrhs; ++c) {
         const VT *vc = v + c * ldv;
-        if (ev0) AFN_HIP(hipEventRecord(ev0, s));
+        if (ev0) AFN_TRY(defer(s, [=](hipStream_t st) { return hipEventRecord(ev0, st); }));
         tile(vc, mf);
         AFN_HIP(hipGetLastError());
-        if (ev1) AFN_HIP(hipEventRecord(ev1, s));
-        hipLaunchKernelGGL((kmv_sym_reduce<T, VT>), dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, part,
-                           n, sh.S, sh.ST, mu, vc, perm, y + c * ldy);
-        AFN_HIP(hipGetLastError());
+        if (ev1) AFN_TRY(defer(s, [=](hipStream_t st) { return hipEventRecord(ev1, st); }));
+        AFN_TRY(dlaunch(dim3((unsigned)ceil_div(n, 256)), 0, s,
+                        KmvRedArgs<T, VT>{part, n, sh.S, sh.ST, mu, vc, perm, y + c * ldy}));
     }
     return AFN_OK;
 }

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "afn_internal.h"
+#include "group.h"
 
 namespace afn {
 namespace {
@@ -106,6 +107,10 @@ int tune_pick(const char *kernel, const std::string &shape, int ncand, int heuri
     d.ms.assign(ncand, 0.f);
     bool ok = true;
     constexpr int kReps = 3;
+    // the timed runs go to the stream at once, also while a unit of work is
+    // being recorded for a grouped launch (they write only the launch's own
+    // outputs, which the recorded launch writes again)
+    RecorderPause pause;
     for (int c = 0; c < ncand && ok; ++c) {
         ok = run(c) == AFN_OK;                     // warm-up
         if (!ok) break;

@@ -4,6 +4,7 @@
 #include <cstdio>
 
 #include "afn_internal.h"
+#include "group.h"
 
 namespace afn {
 namespace {
@@ -38,39 +39,64 @@ __device__ double block_sum(double v)
 
 constexpr int kDotBlocks = 512;
 
+// Each kernel below that a PCG iteration launches has its body in a device
+// function taking the block coordinates, an argument struct, the kernel of
+// one launch (its usual name) and a grouped kernel (suffix _g, see group.h)
+// that runs the same body for several solves in one launch.
+#define AFN_GROUPED_ARGS(Args)                                                                  \
+    static void launch1(const Args &p, dim3 grid, size_t lds, hipStream_t s);                  \
+    static void launchG(const GroupTable<Args> &t, unsigned blocks, size_t lds, hipStream_t s);
+
 template <typename T>
-__global__ __launch_bounds__(256) void dot_stage1(const T *__restrict__ a, const T *__restrict__ b,
-                                                  int64_t n, int64_t chunk,
-                                                  double *__restrict__ part)
+struct DotArgs {
+    const T *a, *b;
+    int64_t n, chunk;
+    double *part;
+    AFN_GROUPED_ARGS(DotArgs)
+};
+
+template <typename T>
+__device__ __forceinline__ void dot_stage1_body(const DotArgs<T> &p, int64_t bx)
 {
-    const int64_t i0 = (int64_t)blockIdx.x * chunk;
-    const int64_t i1 = i0 + chunk < n ? i0 + chunk : n;
+    const int64_t i0 = bx * p.chunk;
+    const int64_t i1 = i0 + p.chunk < p.n ? i0 + p.chunk : p.n;
     double s = 0.0;
     for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x)
-        s = __builtin_fma((double)a[i], (double)b[i], s);
+        s = __builtin_fma((double)p.a[i], (double)p.b[i], s);
     s = block_sum(s);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    if (threadIdx.x == 0) p.part[bx] = s;
 }
 
-__global__ __launch_bounds__(256) void sum_stage2(const double *__restrict__ part, int np,
-                                                  double *__restrict__ out)
+template <typename T>
+__global__ __launch_bounds__(256) void dot_stage1(DotArgs<T> p) { dot_stage1_body(p, blockIdx.x); }
+
+template <typename T>
+__global__ __launch_bounds__(256) void dot_stage1_g(GroupTable<DotArgs<T>> t)
 {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
-    s = block_sum(s);
-    if (threadIdx.x == 0) *out = s;
+    const GroupPos q = group_pos(t);
+    dot_stage1_body(t.a[q.g], q.bx);
 }
 
-// sum_stage2 for the PCG dot products, followed by the scalar step
-// (alpha = rho / p'q, or beta = rho_new / rho and rho = rho_new).
-__global__ __launch_bounds__(256) void sum_stage2_pcg(const double *__restrict__ part, int np,
-                                                      double *__restrict__ sc, int step)
+struct SumArgs {
+    const double *part;
+    int np;
+    int step;          // -1: plain sum into *out; else the PCG scalar step
+    double *out;       // the sum (step -1) or the PCG scalars
+    AFN_GROUPED_ARGS(SumArgs)
+};
+
+// The ordered sum of the partials; for the PCG dot products followed by the
+// scalar step (alpha = rho / p'q, or beta = rho_new / rho and rho = rho_new).
+__device__ __forceinline__ void sum_stage2_body(const SumArgs &p)
 {
     double s = 0.0;
-    for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
+    for (int i = threadIdx.x; i < p.np; i += blockDim.x) s += p.part[i];
     s = block_sum(s);
     if (threadIdx.x == 0) {
-        if (step == kPcgAlpha) {
+        double *sc = p.out;
+        if (p.step < 0) {
+            *sc = s;
+        } else if (p.step == kPcgAlpha) {
             sc[1] = s;
             sc[4] = sc[0] / s;
         } else {
@@ -81,6 +107,14 @@ __global__ __launch_bounds__(256) void sum_stage2_pcg(const double *__restrict__
     }
 }
 
+__global__ __launch_bounds__(256) void sum_stage2(SumArgs p) { sum_stage2_body(p); }
+
+__global__ __launch_bounds__(256) void sum_stage2_g(GroupTable<SumArgs> t)
+{
+    const GroupPos q = group_pos(t);
+    sum_stage2_body(t.a[q.g]);
+}
+
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
@@ -88,13 +122,25 @@ __device__ __forceinline__ float fmaT(float a, float b, float c) { return __buil
 constexpr int kGemvUnroll = 8;
 
 // y[i] (+)= sum over column chunk of A[i + j*lda] x[j]; partial per split.
-template <typename T, typename M = T>
-__global__ __launch_bounds__(256) void gemv_n_partial(const M *__restrict__ A, int64_t lda, int64_t m,
-                                                      int64_t ncols, const T *__restrict__ x,
-                                                      int64_t chunk, T *__restrict__ part)
+template <typename T, typename M>
+struct GemvNArgs {
+    const M *A;
+    int64_t lda, m, ncols;
+    const T *x;
+    int64_t chunk;
+    T *part;
+    AFN_GROUPED_ARGS(GemvNArgs)
+};
+
+template <typename T, typename M>
+__device__ __forceinline__ void gemv_n_partial_body(const GemvNArgs<T, M> &p, int64_t bx, int64_t by)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t j0 = (int64_t)blockIdx.y * chunk;
+    const M *__restrict__ A = p.A;
+    const T *__restrict__ x = p.x;
+    const int64_t lda = p.lda, m = p.m, ncols = p.ncols, chunk = p.chunk;
+    T *__restrict__ part = p.part;
+    const int64_t i = bx * blockDim.x + threadIdx.x;
+    const int64_t j0 = by * chunk;
     const int64_t j1 = j0 + chunk < ncols ? j0 + chunk : ncols;
     if (i >= m) return;
     T s = T(0);
@@ -107,49 +153,87 @@ __global__ __launch_bounds__(256) void gemv_n_partial(const M *__restrict__ A, i
         for (int u = 0; u < kGemvUnroll; ++u) s = fmaT(a[u], x[j + u], s);
     }
     for (; j < j1; ++j) s = fmaT(widen<T>(A[i + j * lda]), x[j], s);
-    part[(int64_t)blockIdx.y * m + i] = s;
+    part[by * m + i] = s;
 }
 
-// y[i] = base[i] + sign * sum_s part[s][i]   (base may be null -> 0)
-template <typename T>
-__global__ __launch_bounds__(256) void gemv_n_reduce(const T *__restrict__ part, int64_t m,
-                                                     int splits, const T *__restrict__ base,
-                                                     T sign, T *__restrict__ y)
+template <typename T, typename M>
+__global__ __launch_bounds__(256) void gemv_n_partial(GemvNArgs<T, M> p) { gemv_n_partial_body(p, blockIdx.x, blockIdx.y); }
+
+template <typename T, typename M>
+__global__ __launch_bounds__(256) void gemv_n_partial_g(GroupTable<GemvNArgs<T, M>> t)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    T s = T(0);
-    for (int k = 0; k < splits; ++k) s += part[(int64_t)k * m + i];
-    y[i] = (base ? base[i] : T(0)) + sign * s;
+    const GroupPos q = group_pos(t);
+    gemv_n_partial_body(t.a[q.g], q.bx, q.by);
 }
 
-// The same with one wavefront per row, for many splits: lane q adds splits
-// q, q + 64, ... in order, then the 64 lane sums are added by a fixed
-// butterfly (deterministic).
-template <typename T>
-__global__ __launch_bounds__(256) void gemv_n_reduce_wave(const T *__restrict__ part, int64_t m,
-                                                          int splits, const T *__restrict__ base,
-                                                          T sign, T *__restrict__ y)
+// y[i] = base[i] + sign * sum_s part[s][i]   (base may be null -> 0);
+// WAVE: one wavefront per row, for many splits: lane q adds splits q, q + 64,
+// ... in order, then the 64 lane sums are added by a fixed butterfly
+// (deterministic).
+template <typename T, bool WAVE>
+struct GemvRedArgs {
+    const T *part;
+    int64_t m;
+    int splits;
+    T sign;
+    const T *base;
+    T *y;
+    AFN_GROUPED_ARGS(GemvRedArgs)
+};
+
+template <typename T, bool WAVE>
+__device__ __forceinline__ void gemv_n_reduce_body(const GemvRedArgs<T, WAVE> &p, int64_t bx)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= m) return;
-    T s = T(0);
-    for (int k = lane; k < splits; k += 64) s += part[(int64_t)k * m + i];
+    if constexpr (WAVE) {
+        const int lane = threadIdx.x & 63;
+        const int64_t i = bx * 4 + (threadIdx.x >> 6);
+        if (i >= p.m) return;
+        T s = T(0);
+        for (int k = lane; k < p.splits; k += 64) s += p.part[(int64_t)k * p.m + i];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0) y[i] = (base ? base[i] : T(0)) + sign * s;
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (lane == 0) p.y[i] = (p.base ? p.base[i] : T(0)) + p.sign * s;
+    } else {
+        const int64_t i = bx * blockDim.x + threadIdx.x;
+        if (i >= p.m) return;
+        T s = T(0);
+        for (int k = 0; k < p.splits; ++k) s += p.part[(int64_t)k * p.m + i];
+        p.y[i] = (p.base ? p.base[i] : T(0)) + p.sign * s;
+    }
 }
+
+template <typename T, bool WAVE>
+__global__ __launch_bounds__(256) void gemv_n_reduce(GemvRedArgs<T, WAVE> p) { gemv_n_reduce_body(p, blockIdx.x); }
+
+template <typename T, bool WAVE>
+__global__ __launch_bounds__(256) void gemv_n_reduce_g(GroupTable<GemvRedArgs<T, WAVE>> t)
+{
+    const GroupPos q = group_pos(t);
+    gemv_n_reduce_body(t.a[q.g], q.bx);
+}
+
+template <typename T, typename M, bool FOUR>
+struct GemvTArgs {
+    const M *A;
+    int64_t lda, m, ncols;
+    const T *x, *base;
+    T sign;
+    T *y;
+    AFN_GROUPED_ARGS(GemvTArgs)
+};
 
 // y[j] = base[j] + sign * sum_i A[i + j*lda] x[i], one wavefront per column.
-template <typename T, typename M = T>
-__global__ __launch_bounds__(256) void gemv_t_kernel(const M *__restrict__ A, int64_t lda, int64_t m,
-                                                     int64_t ncols, const T *__restrict__ x,
-                                                     const T *__restrict__ base, T sign,
-                                                     T *__restrict__ y)
+template <typename T, typename M>
+__device__ __forceinline__ void gemv_t_body(const GemvTArgs<T, M, false> &p, int64_t bx)
 {
+    const M *__restrict__ A = p.A;
+    const T *__restrict__ x = p.x;
+    const T *__restrict__ base = p.base;
+    T *__restrict__ y = p.y;
+    const int64_t lda = p.lda, m = p.m, ncols = p.ncols;
+    const T sign = p.sign;
     const int lane = threadIdx.x & 63;
-    const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t j = (bx * blockDim.x + threadIdx.x) >> 6;
     if (j >= ncols) return;
     const M *col = A + j * lda;
     T s = T(0);
@@ -169,22 +253,28 @@ __global__ __launch_bounds__(256) void gemv_t_kernel(const M *__restrict__ A, in
     if (lane == 0) y[j] = (base ? base[j] : T(0)) + sign * s;
 }
 
+template <typename T, typename M>
+__global__ __launch_bounds__(256) void gemv_t_kernel(GemvTArgs<T, M, false> p) { gemv_t_body(p, blockIdx.x); }
+
 // The same sums with four columns per wavefront and x staged in LDS (m T
 // values of dynamic LDS): per lane the rows lane, lane + 64, ... of each
 // column in order, then the butterfly, as in gemv_t_kernel; x is read from
 // HBM once per workgroup instead of once per column.
-template <typename T, typename M = T>
-__global__ __launch_bounds__(256) void gemv_t4_kernel(const M *__restrict__ A, int64_t lda, int64_t m,
-                                                      int64_t ncols, const T *__restrict__ x,
-                                                      const T *__restrict__ base, T sign,
-                                                      T *__restrict__ y)
+template <typename T, typename M>
+__device__ __forceinline__ void gemv_t4_body(const GemvTArgs<T, M, true> &p, int64_t bx)
 {
+    const M *__restrict__ A = p.A;
+    const T *__restrict__ x = p.x;
+    const T *__restrict__ base = p.base;
+    T *__restrict__ y = p.y;
+    const int64_t lda = p.lda, m = p.m, ncols = p.ncols;
+    const T sign = p.sign;
     extern __shared__ char gemv_smem[];
     T *xs = reinterpret_cast<T *>(gemv_smem);
     for (int64_t i = threadIdx.x; i < m; i += 256) xs[i] = x[i];
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int64_t j0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 4;
+    const int64_t j0 = (bx * 4 + (threadIdx.x >> 6)) * 4;
     if (j0 >= ncols) return;
     const int nc = ncols - j0 < 4 ? (int)(ncols - j0) : 4;
     const M *col[4];
@@ -218,6 +308,17 @@ __global__ __launch_bounds__(256) void gemv_t4_kernel(const M *__restrict__ A, i
     }
 }
 
+template <typename T, typename M>
+__global__ __launch_bounds__(256) void gemv_t4_kernel(GemvTArgs<T, M, true> p) { gemv_t4_body(p, blockIdx.x); }
+
+template <typename T, typename M, bool FOUR>
+__global__ __launch_bounds__(256) void gemv_t_g(GroupTable<GemvTArgs<T, M, FOUR>> t)
+{
+    const GroupPos q = group_pos(t);
+    if constexpr (FOUR) gemv_t4_body(t.a[q.g], q.bx);
+    else gemv_t_body(t.a[q.g], q.bx);
+}
+
 // Sum over the 16 lanes of each lane group (lanes 16 g .. 16 g + 15), a
 // fixed butterfly: every lane of the group ends with the total.
 template <typename T>
@@ -232,14 +333,30 @@ __device__ __forceinline__ T group16_sum(T s)
 // 16 lanes per row, lane q taking a = q, q + 16, ..., q + 16 (RP - 1) (each
 // load instruction reads 16 consecutive entries of a row; 4 rows per wave);
 // RP = 4 up to w = 64, 8 up to w = 128.
-template <typename T, typename M = T, int RP = 4>
-__global__ __launch_bounds__(256) void spmv_padded(const int32_t *__restrict__ cols,
-                                                   const M *__restrict__ gval, int64_t nr, int w,
-                                                   const T *__restrict__ t, T *__restrict__ u,
-                                                   const int32_t *__restrict__ order)
+template <typename T, typename M, int RP>
+struct SpmvGArgs {
+    const int32_t *cols;
+    const M *gval;
+    int64_t nr;
+    int w;
+    const T *t;
+    T *u;
+    const int32_t *order;
+    AFN_GROUPED_ARGS(SpmvGArgs)
+};
+
+template <typename T, typename M, int RP>
+__device__ __forceinline__ void spmv_padded_body(const SpmvGArgs<T, M, RP> &pa, int64_t bx, int64_t gx)
 {
+    const int32_t *__restrict__ cols = pa.cols;
+    const M *__restrict__ gval = pa.gval;
+    const T *__restrict__ t = pa.t;
+    T *__restrict__ u = pa.u;
+    const int32_t *__restrict__ order = pa.order;
+    const int64_t nr = pa.nr;
+    const int w = pa.w;
     const int q = threadIdx.x & 15;
-    const int64_t blk = order ? xcd_contiguous(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    const int64_t blk = order ? xcd_contiguous(bx, gx) : bx;
     const int64_t slot = blk * 16 + (threadIdx.x >> 4);
     if (slot >= nr) return;
     const int64_t p = order ? (int64_t)order[slot] : slot;
@@ -264,17 +381,42 @@ __global__ __launch_bounds__(256) void spmv_padded(const int32_t *__restrict__ c
     if (q == 0) u[p] = s;
 }
 
+template <typename T, typename M, int RP>
+__global__ __launch_bounds__(256) void spmv_padded(SpmvGArgs<T, M, RP> p) { spmv_padded_body(p, blockIdx.x, gridDim.x); }
+
+template <typename T, typename M, int RP>
+__global__ __launch_bounds__(256) void spmv_padded_g(GroupTable<SpmvGArgs<T, M, RP>> t)
+{
+    const GroupPos q = group_pos(t);
+    spmv_padded_body(t.a[q.g], q.bx, q.gx);
+}
+
 // s[c] = sum_e tval[e] u[trow[e]] over e in [ptr[c], ptr[c+1]): 16 lanes per
 // row, up to 4 entries per lane in flight per pass (4 rows per wave).
-template <typename T, typename M = T>
-__global__ __launch_bounds__(256) void spmv_csr(const int64_t *__restrict__ ptr,
-                                                const int32_t *__restrict__ idx,
-                                                const M *__restrict__ val, int64_t nrows,
-                                                const T *__restrict__ u, T *__restrict__ out,
-                                                const int32_t *__restrict__ order)
+template <typename T, typename M>
+struct SpmvCsrArgs {
+    const int64_t *ptr;
+    const int32_t *idx;
+    const M *val;
+    int64_t nrows;
+    const T *u;
+    T *out;
+    const int32_t *order;
+    AFN_GROUPED_ARGS(SpmvCsrArgs)
+};
+
+template <typename T, typename M>
+__device__ __forceinline__ void spmv_csr_body(const SpmvCsrArgs<T, M> &pa, int64_t bx, int64_t gx)
 {
+    const int64_t *__restrict__ ptr = pa.ptr;
+    const int32_t *__restrict__ idx = pa.idx;
+    const M *__restrict__ val = pa.val;
+    const T *__restrict__ u = pa.u;
+    T *__restrict__ out = pa.out;
+    const int32_t *__restrict__ order = pa.order;
+    const int64_t nrows = pa.nrows;
     const int q = threadIdx.x & 15;
-    const int64_t blk = order ? xcd_contiguous(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    const int64_t blk = order ? xcd_contiguous(bx, gx) : bx;
     const int64_t slot = blk * 16 + (threadIdx.x >> 4);
     if (slot >= nrows) return;
     const int64_t c = order ? (int64_t)order[slot] : slot;
@@ -297,6 +439,16 @@ __global__ __launch_bounds__(256) void spmv_csr(const int64_t *__restrict__ ptr,
     }
     s = group16_sum(s);
     if (q == 0) out[c] = s;
+}
+
+template <typename T, typename M>
+__global__ __launch_bounds__(256) void spmv_csr(SpmvCsrArgs<T, M> p) { spmv_csr_body(p, blockIdx.x, gridDim.x); }
+
+template <typename T, typename M>
+__global__ __launch_bounds__(256) void spmv_csr_g(GroupTable<SpmvCsrArgs<T, M>> t)
+{
+    const GroupPos q = group_pos(t);
+    spmv_csr_body(t.a[q.g], q.bx, q.gx);
 }
 
 __global__ __launch_bounds__(256) void gather_kernel(const double *__restrict__ src, int64_t lds,
@@ -333,14 +485,25 @@ __global__ __launch_bounds__(256) void gather_points_kernel(const double *__rest
 
 // x += alpha p; r -= alpha q; partial sums of r.r (FP64 scalars, vectors in T)
 template <typename T>
-__global__ __launch_bounds__(256) void pcg_xr(T *__restrict__ x, T *__restrict__ r,
-                                              const T *__restrict__ p, const T *__restrict__ q,
-                                              const double *__restrict__ sc, int64_t n,
-                                              int64_t chunk, double *__restrict__ part)
+struct PcgXrArgs {
+    T *x, *r;
+    const T *p, *q;
+    const double *sc;
+    int64_t n, chunk;
+    double *part;
+    AFN_GROUPED_ARGS(PcgXrArgs)
+};
+
+template <typename T>
+__device__ __forceinline__ void pcg_xr_body(const PcgXrArgs<T> &a, int64_t bx)
 {
-    const T alpha = (T)sc[4];
-    const int64_t i0 = (int64_t)blockIdx.x * chunk;
-    const int64_t i1 = i0 + chunk < n ? i0 + chunk : n;
+    T *__restrict__ x = a.x;
+    T *__restrict__ r = a.r;
+    const T *__restrict__ p = a.p;
+    const T *__restrict__ q = a.q;
+    const T alpha = (T)a.sc[4];
+    const int64_t i0 = bx * a.chunk;
+    const int64_t i1 = i0 + a.chunk < a.n ? i0 + a.chunk : a.n;
     double s = 0.0;
     for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
         x[i] = fmaT(alpha, p[i], x[i]);
@@ -349,17 +512,45 @@ __global__ __launch_bounds__(256) void pcg_xr(T *__restrict__ x, T *__restrict__
         s = __builtin_fma((double)ri, (double)ri, s);
     }
     s = block_sum(s);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    if (threadIdx.x == 0) a.part[bx] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void pcg_xr(PcgXrArgs<T> a) { pcg_xr_body(a, blockIdx.x); }
+
+template <typename T>
+__global__ __launch_bounds__(256) void pcg_xr_g(GroupTable<PcgXrArgs<T>> t)
+{
+    const GroupPos q = group_pos(t);
+    pcg_xr_body(t.a[q.g], q.bx);
 }
 
 // p = z + beta p
 template <typename T>
-__global__ __launch_bounds__(256) void pcg_p(T *__restrict__ p, const T *__restrict__ z,
-                                             const double *__restrict__ sc, int64_t n)
+struct PcgPArgs {
+    T *p;
+    const T *z;
+    const double *sc;
+    int64_t n;
+    AFN_GROUPED_ARGS(PcgPArgs)
+};
+
+template <typename T>
+__device__ __forceinline__ void pcg_p_body(const PcgPArgs<T> &a, int64_t bx)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    p[i] = fmaT((T)sc[5], p[i], z[i]);
+    const int64_t i = bx * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    a.p[i] = fmaT((T)a.sc[5], a.p[i], a.z[i]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void pcg_p(PcgPArgs<T> a) { pcg_p_body(a, blockIdx.x); }
+
+template <typename T>
+__global__ __launch_bounds__(256) void pcg_p_g(GroupTable<PcgPArgs<T>> t)
+{
+    const GroupPos q = group_pos(t);
+    pcg_p_body(t.a[q.g], q.bx);
 }
 
 // r32 = r * scale (rounded to FP32)
@@ -389,13 +580,68 @@ __global__ __launch_bounds__(256) void to_f32(const double *__restrict__ a, floa
     b[i] = (float)a[i];
 }
 
-// r = b - y (true residual)
+// x *= a
 template <typename T>
-__global__ __launch_bounds__(256) void scale_kernel(T *__restrict__ x, T a, int64_t n)
+struct ScaleArgs {
+    T *x;
+    T a;
+    int64_t n;
+    AFN_GROUPED_ARGS(ScaleArgs)
+};
+
+template <typename T>
+__device__ __forceinline__ void scale_body(const ScaleArgs<T> &p, int64_t bx)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) x[i] *= a;
+    const int64_t i = bx * blockDim.x + threadIdx.x;
+    if (i < p.n) p.x[i] *= p.a;
 }
+
+template <typename T>
+__global__ __launch_bounds__(256) void scale_kernel(ScaleArgs<T> p) { scale_body(p, blockIdx.x); }
+
+template <typename T>
+__global__ __launch_bounds__(256) void scale_g(GroupTable<ScaleArgs<T>> t)
+{
+    const GroupPos q = group_pos(t);
+    scale_body(t.a[q.g], q.bx);
+}
+
+// The launchers of the argument structs.
+#define AFN_DEFINE_LAUNCH(TPL, Args, k1, kg)                                                          \
+    TPL void Args::launch1(const Args &p, dim3 grid, size_t lds, hipStream_t s)                     \
+    {                                                                                                \
+        hipLaunchKernelGGL(k1, grid, dim3(256), lds, s, p);                                          \
+    }                                                                                                \
+    TPL void Args::launchG(const GroupTable<Args> &t, unsigned blocks, size_t lds, hipStream_t s)   \
+    {                                                                                                \
+        hipLaunchKernelGGL(kg, dim3(blocks), dim3(256), lds, s, t);                                  \
+    }
+
+AFN_DEFINE_LAUNCH(template <typename T>, DotArgs<T>, dot_stage1<T>, dot_stage1_g<T>)
+AFN_DEFINE_LAUNCH(, SumArgs, sum_stage2, sum_stage2_g)
+#define AFN_COMMA ,
+AFN_DEFINE_LAUNCH(template <typename T AFN_COMMA typename M>, GemvNArgs<T AFN_COMMA M>, (gemv_n_partial<T, M>),
+                  (gemv_n_partial_g<T, M>))
+AFN_DEFINE_LAUNCH(template <typename T AFN_COMMA bool WAVE>, GemvRedArgs<T AFN_COMMA WAVE>, (gemv_n_reduce<T, WAVE>),
+                  (gemv_n_reduce_g<T, WAVE>))
+template <typename T, typename M, bool FOUR>
+void GemvTArgs<T, M, FOUR>::launch1(const GemvTArgs &p, dim3 grid, size_t lds, hipStream_t s)
+{
+    if constexpr (FOUR) hipLaunchKernelGGL((gemv_t4_kernel<T, M>), grid, dim3(256), lds, s, p);
+    else hipLaunchKernelGGL((gemv_t_kernel<T, M>), grid, dim3(256), lds, s, p);
+}
+template <typename T, typename M, bool FOUR>
+void GemvTArgs<T, M, FOUR>::launchG(const GroupTable<GemvTArgs> &t, unsigned blocks, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL((gemv_t_g<T, M, FOUR>), dim3(blocks), dim3(256), lds, s, t);
+}
+AFN_DEFINE_LAUNCH(template <typename T AFN_COMMA typename M AFN_COMMA int RP>, SpmvGArgs<T AFN_COMMA M AFN_COMMA RP>,
+                  (spmv_padded<T, M, RP>), (spmv_padded_g<T, M, RP>))
+AFN_DEFINE_LAUNCH(template <typename T AFN_COMMA typename M>, SpmvCsrArgs<T AFN_COMMA M>, (spmv_csr<T, M>),
+                  (spmv_csr_g<T, M>))
+AFN_DEFINE_LAUNCH(template <typename T>, PcgXrArgs<T>, pcg_xr<T>, pcg_xr_g<T>)
+AFN_DEFINE_LAUNCH(template <typename T>, PcgPArgs<T>, pcg_p<T>, pcg_p_g<T>)
+AFN_DEFINE_LAUNCH(template <typename T>, ScaleArgs<T>, scale_kernel<T>, scale_g<T>)
 
 __global__ __launch_bounds__(256) void sub_kernel(const double *__restrict__ b,
                                                   const double *__restrict__ y,
@@ -445,11 +691,9 @@ afn_status dotT(const T *a, int64_t lda, const T *b, int64_t ldb, int64_t n, int
     const int64_t nb = dot_partials(n);
     const int64_t chunk = ceil_div(n, nb);
     for (int c = 0; c < nrhs; ++c) {
-        hipLaunchKernelGGL((dot_stage1<T>), dim3((unsigned)nb), dim3(256), 0, s, a + c * lda, b + c * ldb, n,
-                           chunk, part);
-        hipLaunchKernelGGL(sum_stage2, dim3(1), dim3(256), 0, s, part, (int)nb, out + c);
+        AFN_TRY(dlaunch(dim3((unsigned)nb), 0, s, DotArgs<T>{a + c * lda, b + c * ldb, n, chunk, part}));
+        AFN_TRY(dlaunch(dim3(1), 0, s, SumArgs{part, (int)nb, -1, out + c}));
     }
-    AFN_HIP(hipGetLastError());
     return AFN_OK;
 }
 
@@ -459,10 +703,8 @@ afn_status dot_pcgT(const T *a, const T *b, int64_t n, double *sc, PcgDotStep st
 {
     const int64_t nb = dot_partials(n);
     const int64_t chunk = ceil_div(n, nb);
-    hipLaunchKernelGGL((dot_stage1<T>), dim3((unsigned)nb), dim3(256), 0, s, a, b, n, chunk, part);
-    hipLaunchKernelGGL(sum_stage2_pcg, dim3(1), dim3(256), 0, s, part, (int)nb, sc, (int)step);
-    AFN_HIP(hipGetLastError());
-    return AFN_OK;
+    AFN_TRY(dlaunch(dim3((unsigned)nb), 0, s, DotArgs<T>{a, b, n, chunk, part}));
+    return dlaunch(dim3(1), 0, s, SumArgs{part, (int)nb, (int)step, sc});
 }
 
 template <typename T, typename M = T>
@@ -484,16 +726,11 @@ afn_status gemv_nT(const M *A, int64_t lda, int64_t m, int64_t ncols, const T *x
     auto launch = [&](int c) -> afn_status {
         const int64_t S = cand[c];
         const int64_t chunk = ceil_div(ncols, S);
-        hipLaunchKernelGGL((gemv_n_partial<T, M>), dim3((unsigned)ceil_div(m, 256), (unsigned)S), dim3(256), 0,
-                           s, A, lda, m, ncols, x, chunk, part);
+        AFN_TRY(dlaunch(dim3((unsigned)ceil_div(m, 256), (unsigned)S), 0, s,
+                        GemvNArgs<T, M>{A, lda, m, ncols, x, chunk, part}));
         if (S > 32)
-            hipLaunchKernelGGL((gemv_n_reduce_wave<T>), dim3((unsigned)ceil_div(m, 4)), dim3(256), 0, s, part, m,
-                               (int)S, base, sign, y);
-        else
-            hipLaunchKernelGGL((gemv_n_reduce<T>), dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, part, m,
-                               (int)S, base, sign, y);
-        AFN_HIP(hipGetLastError());
-        return AFN_OK;
+            return dlaunch(dim3((unsigned)ceil_div(m, 4)), 0, s, GemvRedArgs<T, true>{part, m, (int)S, sign, base, y});
+        return dlaunch(dim3((unsigned)ceil_div(m, 256)), 0, s, GemvRedArgs<T, false>{part, m, (int)S, sign, base, y});
     };
     int pick = 0;
     if ((const void *)base != (const void *)y && (const void *)x != (const void *)y) {
@@ -512,13 +749,8 @@ afn_status gemv_tT(const M *A, int64_t lda, int64_t m, int64_t ncols, const T *x
     if (ncols <= 0) return AFN_OK;
     const size_t lds = sizeof(T) * (size_t)(m > 0 ? m : 1);
     if (ncols >= 4096 && lds <= 32768)
-        hipLaunchKernelGGL((gemv_t4_kernel<T, M>), dim3((unsigned)ceil_div(ncols, 16)), dim3(256), lds, s, A, lda, m,
-                           ncols, x, base, sign, y);
-    else
-        hipLaunchKernelGGL((gemv_t_kernel<T, M>), dim3((unsigned)ceil_div(ncols, 4)), dim3(256), 0, s, A, lda, m,
-                           ncols, x, base, sign, y);
-    AFN_HIP(hipGetLastError());
-    return AFN_OK;
+        return dlaunch(dim3((unsigned)ceil_div(ncols, 16)), lds, s, GemvTArgs<T, M, true>{A, lda, m, ncols, x, base, sign, y});
+    return dlaunch(dim3((unsigned)ceil_div(ncols, 4)), 0, s, GemvTArgs<T, M, false>{A, lda, m, ncols, x, base, sign, y});
 }
 
 template <typename T, typename M = T>
@@ -526,14 +758,9 @@ afn_status spmv_gT(const int32_t *cols, const M *gval, int64_t nr, int w, const 
                    const int32_t *order, hipStream_t s)
 {
     if (nr <= 0) return AFN_OK;
-    if (w > 64)
-        hipLaunchKernelGGL((spmv_padded<T, M, 8>), dim3((unsigned)ceil_div(nr, 16)), dim3(256), 0, s, cols, gval,
-                           nr, w, t, u, order);
-    else
-        hipLaunchKernelGGL((spmv_padded<T, M, 4>), dim3((unsigned)ceil_div(nr, 16)), dim3(256), 0, s, cols, gval,
-                           nr, w, t, u, order);
-    AFN_HIP(hipGetLastError());
-    return AFN_OK;
+    const dim3 grid((unsigned)ceil_div(nr, 16));
+    if (w > 64) return dlaunch(grid, 0, s, SpmvGArgs<T, M, 8>{cols, gval, nr, w, t, u, order});
+    return dlaunch(grid, 0, s, SpmvGArgs<T, M, 4>{cols, gval, nr, w, t, u, order});
 }
 
 template <typename T, typename M = T>
@@ -541,10 +768,7 @@ afn_status spmv_gtT(const int64_t *ptr, const int32_t *idx, const M *val, int64_
                     T *out, const int32_t *order, hipStream_t s)
 {
     if (nr <= 0) return AFN_OK;
-    hipLaunchKernelGGL((spmv_csr<T, M>), dim3((unsigned)ceil_div(nr, 16)), dim3(256), 0, s, ptr, idx, val, nr,
-                       u, out, order);
-    AFN_HIP(hipGetLastError());
-    return AFN_OK;
+    return dlaunch(dim3((unsigned)ceil_div(nr, 16)), 0, s, SpmvCsrArgs<T, M>{ptr, idx, val, nr, u, out, order});
 }
 
 template <typename T>
@@ -553,18 +777,14 @@ afn_status pcg_xrT(T *x, T *r, const T *p, const T *q, const double *sc, int64_t
 {
     const int64_t nb = dot_partials(n);
     const int64_t chunk = ceil_div(n, nb);
-    hipLaunchKernelGGL((pcg_xr<T>), dim3((unsigned)nb), dim3(256), 0, s, x, r, p, q, sc, n, chunk, part);
-    hipLaunchKernelGGL(sum_stage2, dim3(1), dim3(256), 0, s, part, (int)nb, rr_out);
-    AFN_HIP(hipGetLastError());
-    return AFN_OK;
+    AFN_TRY(dlaunch(dim3((unsigned)nb), 0, s, PcgXrArgs<T>{x, r, p, q, sc, n, chunk, part}));
+    return dlaunch(dim3(1), 0, s, SumArgs{part, (int)nb, -1, rr_out});
 }
 
 template <typename T>
 afn_status pcg_pT(T *p, const T *z, const double *sc, int64_t n, hipStream_t s)
 {
-    hipLaunchKernelGGL((pcg_p<T>), dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, p, z, sc, n);
-    AFN_HIP(hipGetLastError());
-    return AFN_OK;
+    return dlaunch(dim3((unsigned)ceil_div(n, 256)), 0, s, PcgPArgs<T>{p, z, sc, n});
 }
 
 }  // namespace
@@ -770,17 +990,13 @@ afn_status sub_launch(const double *b, const double *y, double *r, int64_t n, hi
 afn_status scale_launch(double *x, double a, int64_t n, hipStream_t s)
 {
     if (n <= 0) return AFN_OK;
-    hipLaunchKernelGGL(scale_kernel<double>, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, x, a, n);
-    AFN_HIP(hipGetLastError());
-    return AFN_OK;
+    return dlaunch(dim3((unsigned)ceil_div(n, 256)), 0, s, ScaleArgs<double>{x, a, n});
 }
 
 afn_status scale_launch(float *x, float a, int64_t n, hipStream_t s)
 {
     if (n <= 0) return AFN_OK;
-    hipLaunchKernelGGL(scale_kernel<float>, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, x, a, n);
-    AFN_HIP(hipGetLastError());
-    return AFN_OK;
+    return dlaunch(dim3((unsigned)ceil_div(n, 256)), 0, s, ScaleArgs<float>{x, a, n});
 }
 
 afn_status finite_launch(const double *a, int64_t n, int *flag, hipStream_t s)

@@ -64,6 +64,8 @@ class Result:
     k: int = 0
     method: int = -1
     fp64_iterations: int = 0
+    grouped_units: int = 0       # iterations advanced in launches shared with other requests
+    setup_s: float = float("nan")   # afn_setup on the setup thread, inputs copied in
     x: torch.Tensor | None = None
     error: str = ""
 
@@ -122,6 +124,7 @@ class Server:
     def _prepare(self, job: Job) -> None:
         """Setup thread: inputs to the device and afn_setup on the job's stream."""
         r = job.req
+        t_setup = time.perf_counter()
         with torch.cuda.stream(job.stream):
             job.X = torch.from_numpy(np.ascontiguousarray(r.X)).to(self.device)
             job.b = torch.from_numpy(np.ascontiguousarray(r.b)).to(self.device)
@@ -130,6 +133,7 @@ class Server:
                                        nrhs_max=0, stream=job.stream)
         si = job.handle.info()
         job.res.k, job.res.method = si.k, si.method
+        job.res.setup_s = time.perf_counter() - t_setup
 
     def _begin(self, job: Job) -> None:
         job.state = afn.afn_pcg_begin(job.handle, job.b, tol=job.req.tol, maxit=job.req.maxit,
@@ -148,6 +152,7 @@ class Server:
             res.iterations = info["iterations"]
             res.outer_iterations = info["outer_iterations"]
             res.fp64_iterations = info["fp64_iterations"]
+            res.grouped_units = info["grouped_units"]
             res.relres_true = info["relres_true"]
             if self.keep_x:
                 res.x = j.state.x.cpu() if self.keep_x == "host" else j.state.x
@@ -238,6 +243,11 @@ class Server:
         return [results[q.rid] for q in requests]
 
 
+def _mean(v) -> float:
+    v = [x for x in v if x == x]
+    return float(np.mean(v)) if v else float("nan")
+
+
 def summarize(results: list[Result]) -> dict:
     """Throughput of converged requests; latency percentiles (nearest rank)
     over every request that ran, converged or not."""
@@ -261,4 +271,10 @@ def summarize(results: list[Result]) -> dict:
         "p50_s": pct(50),
         "p99_s": pct(99),
         "max_relres_true": max((r.relres_true for r in ok), default=float("nan")),
+        # share of the iterations advanced in launches shared with other requests
+        "grouped_frac": (sum(r.grouped_units for r in results) /
+                         max(1, sum(r.iterations for r in results))),
+        # mean setup time (setup thread) and mean time from setup to done
+        "mean_setup_s": _mean([r.setup_s for r in ok]),
+        "mean_solve_s": _mean([r.done - r.admitted - r.setup_s for r in ok]),
     }

@@ -111,13 +111,14 @@ def paper_table1a(l2_paper: float, n: int = 160_000) -> Problem:
                    tol=1e-4, maxit=500, seed=6, points="uniform", rhs="uniform_half")
 
 
-def serving_requests(count: int = 256, seed: int = 5):
-    """Mixed-size request stream: n log-uniform in [5e3, 2e5], d in {3, 8},
-    l log-uniform in [0.01, 2], mu in {1e-4, 1e-2}; one right-hand side each."""
+def serving_requests(count: int = 256, seed: int = 5, n_lo: float = 5e3, n_hi: float = 2e5):
+    """Mixed-size request stream: n log-uniform in [n_lo, n_hi] (default
+    [5e3, 2e5]), d in {3, 8}, l log-uniform in [0.01, 2], mu in {1e-4, 1e-2};
+    one right-hand side each."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(count):
-        n = int(round(math.exp(rng.uniform(math.log(5e3), math.log(2e5)))))
+        n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
         d = int(rng.choice([3, 8]))
         l = float(math.exp(rng.uniform(math.log(0.01), math.log(2.0))))
         mu = float(rng.choice([1e-4, 1e-2]))
