@@ -16,7 +16,7 @@ Prints ONE JSON line: value = mixed-precision solves/s; roofline of the
 dominant kernel (the FP32 kernel-matvec tile kernel of the inner solves, timed
 live with HIP events around each of its launches inside the timed solves);
 cpu_baseline = the FP64 oracle on a bounded sample of the same workload,
-extrapolated to one solve.  --workload c2|c4|highd and --serving select the
+extrapolated to one solve.  --workload c2|c4|highd|batch and --serving select the
 other workloads.
 """
 from __future__ import annotations
@@ -471,6 +471,72 @@ def _c4_roofline(evaluated_tflops: float) -> dict:
             "kernel": "kmv_mrhs_pipe<0, 3, 4>"}
 
 
+def batch_bench(args):
+    """Continuous batching of like small solves: 16 mixed-precision AFN solves
+    (n = 3000 .. 3555, d = 3 uniform, l = 0.3, mu = 1e-3, k = 150, w = 32, one
+    right-hand side each), set up first, then advanced together by
+    afn_pcg_step_many to rel-res 1e-6; the iteration phase timed with grouped
+    launches (one ragged launch per kernel over all like solves) and with
+    every solve's kernels launched on their own.  The solutions of the two
+    modes must agree bit for bit."""
+    import numpy as np
+    import torch
+    from paper_2304_05460_amd import afn, workloads as W
+
+    afn.lib()
+    G = 16
+    hs, bs = [], []
+    for i in range(G):
+        n = 3000 + 37 * i
+        X = torch.tensor(W.points("uniform", n, 3, 900 + i), device="cuda")
+        hs.append(afn.afn_setup(X, 0.3, 1e-3, k=150, w=32, precision=afn.AFN_FP32, nrhs_max=0))
+        bs.append(torch.tensor(np.random.default_rng(950 + i).standard_normal(n), device="cuda"))
+
+    def run():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        states = [afn.afn_pcg_begin(h, b, tol=1e-6, maxit=400) for h, b in zip(hs, bs)]
+        while not all(s.query()[0] for s in states):
+            afn.afn_pcg_step_many(states, iters=8)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        infos = [s.query()[1] for s in states]
+        xs = [s.x.clone() for s in states]
+        for s in states:
+            s.end()
+        return t, infos, xs
+
+    res = {}
+    for mode in (False, True):
+        afn.group_config(mode)
+        for _ in range(max(1, args.warmup)):
+            run()
+        best = None
+        for _ in range(max(1, args.steps)):
+            t, infos, xs = run()
+            if best is None or t < best[0]:
+                best = (t, infos, xs)
+        res[mode] = best
+    afn.group_config(True)
+    same = all(torch.equal(a, b) for a, b in zip(res[False][2], res[True][2]))
+    its = sum(i["iterations"] for i in res[True][1])
+    grp = sum(i["grouped_units"] for i in res[True][1])
+    tg, tn = res[True][0], res[False][0]
+    print(json.dumps({
+        "metric": "batched small solves/s (iteration phase, 16 like mixed-precision solves)",
+        "value": round(G / tg, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(tg * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "batch16_uniform3d_n3000_3555", "solves": G, "tol": 1e-6},
+        "ungrouped": {"value": round(G / tn, 3), "ms": round(tn * 1e3, 3)},
+        "speedup": round(tn / tg, 3),
+        "us_per_iteration": {"grouped": round(tg / its * 1e6, 2), "ungrouped": round(tn / its * 1e6, 2)},
+        "iterations": its, "grouped_frac": round(grp / max(1, its), 4), "bitwise_equal": same,
+    }))
+    for h in hs:
+        h.close()
+
+
 def serving_bench(args):
     """Mixed-size request stream: a burst run (every request at t = 0) gives
     the saturated throughput; a Poisson stream at 0.7 x that rate gives the
@@ -561,7 +627,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision and Algorithm 5 runs on the same input")
-    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "highd"],
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "highd", "batch"],
                     help="c3 (default): mixed vs FP64 at n=2e5, d=8; c2: FP64 at n=1e5, d=3 "
                          "(--l 0.01 / 0.1 / 1); c4: 64 right-hand sides at n=1.5e5; highd: n=49990, "
                          "d=22 (uniform landmarks)")
@@ -615,6 +681,9 @@ def main():
         return
     if args.workload == "highd":
         highd_bench(args)
+        return
+    if args.workload == "batch":
+        batch_bench(args)
         return
 
     c2_bench(args)

@@ -333,10 +333,29 @@ afn_status afn_pcg_begin(afn_handle *h, const double *b_dev, double *x_dev, doub
  * NULL: each state's work goes on the stream it was begun on, so solves
  * overlap on the device; otherwise all of it goes on 'stream' (ordered after
  * the begin streams; pass the same value on every call for a state).  A state
- * that finishes writes x_dev and its info.  Errors: EINVAL (a NULL state,
- * count < 1, iters < 1, two states on one handle), EDEVICE; the outcome of
- * each solve is read by afn_pcg_query. */
+ * that finishes writes x_dev and its info.
+ *
+ * Continuous batching (Algorithm 5's solve for many requests at once): the
+ * units due in one polling pass are queued together; the inner FP32/BF16
+ * iterations of like mixed-precision solves -- same d, kernel, precision,
+ * method and pattern width, n within a factor of 2 -- run as ONE ragged
+ * launch per kernel over all of them (a table of per-solve arguments and
+ * block offsets passed as the kernel argument, at most 16 solves per launch;
+ * no device memory of its own), on the stream of the first of them.  An inner
+ * iteration that is due while a like solve's is in flight waits for it, so
+ * like solves stay aligned.  Each solve's arithmetic is that of its own
+ * launches: results are bitwise those of afn_pcg_solve.  info.grouped_units
+ * counts the units a solve advanced in grouped launches.
+ *
+ * Errors: EINVAL (a NULL state, count < 1, iters < 1, two states on one
+ * handle), EDEVICE; the outcome of each solve is read by afn_pcg_query. */
 afn_status afn_pcg_step_many(afn_pcg_state *const *states, int32_t count, int32_t iters, void *stream);
+
+/* Grouped launches in afn_pcg_step_many on (1, the default unless the
+ * environment variable AFN_NO_GROUP=1 is set at load) or off (0: every unit
+ * queued on its own; the results are the same bits).  Process-wide; takes
+ * effect at the next afn_pcg_step_many call. */
+void afn_group_config(int32_t on);
 
 /* *done = 1 once the solve has finished; info_host (may be NULL) then holds
  * the result, and the return value is the solve's status (OK, ENOCONV,

@@ -35,7 +35,7 @@ EXPORTED = ["kernel_matvec", "kernel_matvec_ex", "kernel_matvec_noalloc", "afn_w
             "afn_apply", "afn_pcg_solve", "afn_pcg_begin", "afn_pcg_step_many", "afn_pcg_query",
             "afn_pcg_end", "afn_get_info", "afn_get_landmarks", "afn_get_fsai", "afn_get_cholesky",
             "afn_footprint_bytes", "afn_tune_config", "afn_tune_report", "afn_destroy", "afn_status_string",
-            "afn_last_error"]
+            "afn_last_error", "afn_group_config"]
 
 
 class AFNError(RuntimeError):
@@ -106,6 +106,8 @@ def _declare(L):
     L.afn_pcg_query.argtypes = [_P, ctypes.POINTER(_I32), ctypes.POINTER(afn_solve_info)]
     L.afn_pcg_end.argtypes = [_P]
     L.afn_pcg_end.restype = None
+    L.afn_group_config.argtypes = [_I32]
+    L.afn_group_config.restype = None
     L.afn_tune_config.argtypes = [_I32, _I32, ctypes.c_char_p]
     L.afn_tune_report.argtypes = [ctypes.c_char_p, _I64, ctypes.POINTER(_I64)]
     L.afn_apply.argtypes = [_P, _P, _P, _I32, _I64, _P]
@@ -434,6 +436,11 @@ def afn_pcg_step_many(states, iters: int = 1, stream=None) -> None:
     arr = (ctypes.c_void_p * len(states))(*[s.ptr for s in states])
     sp = ctypes.c_void_p(None) if stream is None else _stream(stream)
     _check(lib().afn_pcg_step_many(arr, len(states), iters, sp), "afn_pcg_step_many")
+
+
+def group_config(on: bool) -> None:
+    """Grouped launches of like solves' iterations in afn_pcg_step_many on or off."""
+    lib().afn_group_config(1 if on else 0)
 
 
 def tune_config(mode: int = AFN_TUNE_OFF, index: int = 0, cache_path: str | None = None) -> None:

@@ -1,6 +1,7 @@
 // C-ABI of libafn: preconditioner construction (Algorithm 2), application
 // (Algorithm 3) and preconditioned CG (Algorithm 5, AFN branch).
 #include <cfloat>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -695,16 +696,18 @@ struct afn_pcg_state {
 namespace afn {
 namespace {
 
-// Grouped launches in afn_pcg_step_many; AFN_NO_GROUP=1 turns them off
-// (every unit then queued on its own, as a comparison).
-bool grouping_enabled()
+// Grouped launches in afn_pcg_step_many (afn_group_config; the environment
+// variable AFN_NO_GROUP=1 sets the initial value to off).
+std::atomic<int> &grouping_flag()
 {
-    static const bool on = [] {
+    static std::atomic<int> on{[] {
         const char *e = std::getenv("AFN_NO_GROUP");
-        return !(e && e[0] == '1');
-    }();
+        return (e && e[0] == '1') ? 0 : 1;
+    }()};
     return on;
 }
+
+bool grouping_enabled() { return grouping_flag().load(std::memory_order_relaxed) != 0; }
 
 double host_ms()
 {
@@ -1482,6 +1485,8 @@ afn_status afn_pcg_step_many(afn_pcg_state *const *states, int32_t count, int32_
     }
     return AFN_OK;
 }
+
+void afn_group_config(int32_t on) { grouping_flag().store(on ? 1 : 0, std::memory_order_relaxed); }
 
 afn_status afn_pcg_query(const afn_pcg_state *st, int32_t *done, afn_solve_info *info)
 {
