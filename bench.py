@@ -59,9 +59,12 @@ def kmv_flops(n: int, d: int, nrhs: int = 1) -> float:
 
 def source_hash(path: pathlib.Path) -> str:
     """sha256[:16] of a tile-kernel source together with the kernel-function
-    header it includes."""
+    header and the tile-kernel body it includes."""
     h = hashlib.sha256(path.read_bytes())
     h.update((path.parent / "kfun.h").read_bytes())
+    body = path.parent / "kmv_sym_mf_body.inc"
+    if body.exists():
+        h.update(body.read_bytes())
     return h.hexdigest()[:16]
 
 

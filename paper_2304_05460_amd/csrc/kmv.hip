@@ -376,262 +376,35 @@ struct KmvMfArgs {
     static void launchG(const GroupTable<KmvMfArgs> &t, unsigned blocks, size_t lds, hipStream_t s);
 };
 
-// The body of the kernel for super-block pair bid (the single launch and the
-// grouped one, group.h; one instantiation per kernel, so that each kernel has
-// LDS arrays of its own).
-template <int KIND, int D, typename T, typename VT, bool GROUPED>
-__device__ __forceinline__ void kmv_sym_mf_body(const T *__restrict__ Xs, int64_t npad, int64_t n,
-                                                const VT *__restrict__ v, const int32_t *__restrict__ perm,
-                                                const T *__restrict__ box, T tcut, T tfar, T r2max, int S, int ST,
-                                                T *__restrict__ part, unsigned bid)
-{
-    using M = Mfma<T>;
-    constexpr int KC = D <= 4 ? 1 : 2;
-    __shared__ T rx[4 * KC][kTile];         // centred row coordinates, zero beyond D
-    __shared__ T rn[kTile], rv[kTile];      // row squared norms and vector values
-    constexpr bool STAGE_ALL = sizeof(T) == 4;
-    constexpr int NBUF = STAGE_ALL ? kMaxSTmf : 2;
-    __shared__ T cb[NBUF][4 * KC][kTile];   // -2 x centred column coordinates
-    __shared__ T cn[NBUF][kTile], cv[NBUF][kTile];
-    __shared__ T colacc[4][kMaxSTmf][kTile];  // per-wave column partial sums
-    __shared__ unsigned char keep[kMaxSTmf * kMaxSTmf];
-    __shared__ T cenS[D];                   // the row tile's box centre, for store_col
-    __shared__ T etab[sizeof(T) == 8 ? 64 : 1];   // 2^(j/64) for the FP64 exponential
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    const int lc = lane & 15, lg = lane >> 4;
-    int BI, BJ;
-    decode_pair(bid, S, BI, BJ);
-    const int64_t SB = (int64_t)ST * kTile;
-    const bool diag_super = BI == BJ;
-    for (int e = tid; e < 4 * kMaxSTmf * kTile; e += 256) (&colacc[0][0][0])[e] = T(0);
-    if constexpr (sizeof(T) == 8) {
-        if (tid < 64) etab[tid] = kExp2Tab64[tid];
-    }
-    if (tid < ST * ST)
-    {
-        // 0: skipped, 1: evaluated (every t below kBoundedT), 2: evaluated with
-        // the exponential in FP32, 3: evaluated (larger t possible).  The box
-        // of a partly filled tile covers its real points only, while its
-        // padding points sit at the packing origin, which may lie inside or
-        // outside that box: the `full` test, not the box, keeps such pairs
-        // off the bounded form.
-        const int64_t a = (int64_t)BI * ST + tid / ST, b = (int64_t)BJ * ST + tid % ST;
-        const T g2 = box_gap2<D, T>(box, a, b);
-        const bool full = (a + 1) * kTile <= n && (b + 1) * kTile <= n;
-        const bool bounded = full && box_span2<D, T>(box, a, b) < T(kBoundedT);
-        keep[tid] = g2 < tcut ? (g2 >= tfar ? 2 : (bounded ? 1 : 3)) : 0;
-    }
-    T *rowout = part + (int64_t)bid * 2 * SB;
-    T *colout = rowout + SB;
-    auto next_kept = [&](int ti, int tj) {
-        while (tj < ST && !keep[ti * ST + tj]) ++tj;
-        return tj;
-    };
-    T cen[D];
-    // one column per thread 0..63 (two-buffer mode)
-    T xn[D], vn = T(0);
-    auto load_col = [&](int tt) {
-        const int64_t q = BJ * SB + (int64_t)tt * kTile + tid;
-#pragma unroll
-        for (int t = 0; t < D; ++t) xn[t] = Xs[(int64_t)t * npad + q];
-        vn = q < n ? (T)v[perm ? (int64_t)perm[q] : q] : T(0);
-    };
-    auto store_col = [&](int buf) {
-        T nrm = T(0);
-#pragma unroll
-        for (int t = 0; t < 4 * KC; ++t) {
-            const T xc = t < D ? xn[t] - cenS[t] : T(0);
-            cb[buf][t][tid] = t == D ? nrm : T(-2) * xc;
-            nrm = fmaT(xc, xc, nrm);
-        }
-        cn[buf][tid] = nrm;
-        cv[buf][tid] = vn;
-    };
-    for (int ti = 0; ti < ST; ++ti) {
-        const int64_t rt = (int64_t)BI * ST + ti;
-        T h2 = T(0);
-        bool empty = false;
-#pragma unroll
-        for (int t = 0; t < D; ++t) {
-            const T lo = box[(rt * D + t) * 2], hi = box[(rt * D + t) * 2 + 1];
-            empty = empty || !(lo <= hi);
-            cen[t] = (lo + hi) * T(0.5);
-            const T half = (hi - lo) * T(0.5);
-            h2 = fmaT(half, half, h2);
-        }
-        if (empty) {          // padding tile: no point, nothing to add
-            if (tid < kTile) rowout[(int64_t)ti * kTile + tid] = T(0);
-            continue;
-        }
-        const bool use_mf = h2 <= r2max;
-        // plain differences (a wide row tile): the stored coordinates, relative
-        // to the packing origin, and not to a box centre that an outlier in
-        // the tile may put far from its other points
-        if (!use_mf) {
-#pragma unroll
-            for (int t = 0; t < D; ++t) cen[t] = T(0);
-        }
-        // every read of cenS (store_col) is followed by a barrier
-        if (tid < D) cenS[tid] = cen[tid];
-        __syncthreads();      // the previous row tile's readers are done
-        const int tfirst = diag_super ? ti : 0;
-        int tj = next_kept(ti, tfirst);
-        if (tid < kTile) {
-            const int64_t q = rt * kTile + tid;
-            T nrm = T(0);
-#pragma unroll
-            for (int t = 0; t < 4 * KC; ++t) {
-                const T xr = t < D ? Xs[(int64_t)t * npad + q] - cen[t] : T(0);
-                rx[t][tid] = t == D ? T(1) : xr;
-                nrm = fmaT(xr, xr, nrm);
-            }
-            rn[tid] = nrm;
-            rv[tid] = q < n ? (T)v[perm ? (int64_t)perm[q] : q] : T(0);
-        }
-        if constexpr (STAGE_ALL) {
-            for (int e = tid; e < ST * kTile; e += 256) {
-                const int tt = e / kTile, j = e % kTile;
-                if (tt < tfirst || !keep[ti * ST + tt]) continue;
-                const int64_t q = BJ * SB + (int64_t)tt * kTile + j;
-                T nrm = T(0);
-#pragma unroll
-                for (int t = 0; t < 4 * KC; ++t) {
-                    const T xc = t < D ? Xs[(int64_t)t * npad + q] - cen[t] : T(0);
-                    cb[tt][t][j] = t == D ? nrm : T(-2) * xc;
-                    nrm = fmaT(xc, xc, nrm);
-                }
-                cn[tt][j] = nrm;
-                cv[tt][j] = q < n ? (T)v[perm ? (int64_t)perm[q] : q] : T(0);
-            }
-        } else {
-            if (tid < kTile && tj < ST) {
-                load_col(tj);
-                store_col(0);
-            }
-        }
-        __syncthreads();
-        T a[KC], nr[4], vr[4], racc[4];
-        typename M::acc_t nrv;
-#pragma unroll
-        for (int kc = 0; kc < KC; ++kc) a[kc] = rx[4 * kc + lg][16 * wave + lc];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = 16 * wave + M::row(lane, i);
-            nr[i] = rn[r];
-            nrv[i] = nr[i];
-            vr[i] = rv[r];
-            racc[i] = T(0);
-        }
-        // the tile loop, instantiated once per way of forming the distances
-        auto tile_loop = [&](auto mf_tag) {
-            constexpr bool MF = decltype(mf_tag)::value;
-            int nb = 0;
-            while (tj < ST) {
-                const int tn = next_kept(ti, tj + 1);
-                if constexpr (!STAGE_ALL) {
-                    if (tn < ST && tid < kTile) load_col(tn);
-                }
-                const int b = STAGE_ALL ? tj : nb;
-                T cacc[4];
-                // per 16-column block: the distances, then the kernel values
-                auto values = [&](auto far_tag, auto bounded_tag) {
-                    constexpr bool FAR = decltype(far_tag)::value;
-                    constexpr bool BOUNDED = decltype(bounded_tag)::value;
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        const int col = 16 * m + lc;
-                        typename M::acc_t c;
-                        if constexpr (MF && D < 4 * KC) {
-                            // slot D: 1 x |x_j|^2; the row norms are the accumulator input
-                            c = M::op(a[0], cb[b][lg][col], nrv);
-#pragma unroll
-                            for (int kc = 1; kc < KC; ++kc) c = M::op(a[kc], cb[b][4 * kc + lg][col], c);
-                        } else if constexpr (MF) {
-                            const T ncol = cn[b][col];
-#pragma unroll
-                            for (int i = 0; i < 4; ++i) c[i] = nr[i] + ncol;
-#pragma unroll
-                            for (int kc = 0; kc < KC; ++kc) c = M::op(a[kc], cb[b][4 * kc + lg][col], c);
-                        } else {
-#pragma unroll
-                            for (int i = 0; i < 4; ++i) {
-                                const int r = 16 * wave + M::row(lane, i);
-                                T d2 = T(0);
-#pragma unroll
-                                for (int t = 0; t < D; ++t) {
-                                    const T del = fmaT(T(0.5), cb[b][t][col], rx[t][r]);
-                                    d2 = fmaT(del, del, d2);
-                                }
-                                c[i] = d2;
-                            }
-                        }
-                        const T vcol = cv[b][col];
-                        cacc[m] = T(0);
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            // a slightly negative distance (rounding) is harmless in
-                            // 2^-t, but not under the square root of the Matern kernel
-                            T t2 = c[i];
-                            if constexpr (KIND == AFN_KERNEL_MATERN32) t2 = t2 > T(0) ? t2 : T(0);
-                            T kij;
-                            if constexpr (FAR) kij = (T)kernel_scaled<KIND, float>((float)t2);
-                            else if constexpr (BOUNDED) kij = kernel_scaled_tab<KIND, T>(t2, etab);
-                            else kij = kernel_scaled<KIND, T>(t2);
-                            racc[i] = fmaT(kij, vcol, racc[i]);
-                            cacc[m] = fmaT(kij, vr[i], cacc[m]);
-                        }
-                    }
-                };
-                // far tile pairs (FP64 only): every value is below 2^-kFarF64,
-                // and the FP32 exponential is within 2^-64 |v_j| of it
-                // the clamp-free exponential where the tile boxes bound t
-                if constexpr (sizeof(T) == 8) {
-                    const int kt = keep[ti * ST + tj];
-                    if (kt == 2) values(std::true_type{}, std::false_type{});
-                    else if (kt == 1) values(std::false_type{}, std::true_type{});
-                    else values(std::false_type{}, std::false_type{});
-                } else {
-                    values(std::false_type{}, std::false_type{});
-                }
-                if (!(diag_super && tj == ti)) colacc[wave][tj][lane] += groups4_sum(cacc, lane);
-                if constexpr (!STAGE_ALL) {
-                    if (tn < ST && tid < kTile) store_col(nb ^ 1);
-                    __syncthreads();
-                    nb ^= 1;
-                }
-                tj = tn;
-            }
-        };
-        if (use_mf) tile_loop(std::true_type{});
-        else tile_loop(std::false_type{});
-        // rows of this wave's stripe: lane l ends with row value i = (l & 15) >> 2
-        const T tot = lanes16_sum4(racc, lane);
-        if ((lc & 3) == 0) rowout[(int64_t)ti * kTile + 16 * wave + M::row(lane, lc >> 2)] = tot;
-    }
-    __syncthreads();
-    for (int e = tid; e < ST * kTile; e += 256) {
-        const int tt = e / kTile, j = e % kTile;
-        colout[e] = ((colacc[0][tt][j] + colacc[1][tt][j]) + colacc[2][tt][j]) + colacc[3][tt][j];
-    }
-}
-
 template <int KIND, int D, typename T, typename VT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : (D <= 4 ? 4 : 2)))) void kmv_sym_mf(
     const T *__restrict__ Xs, int64_t npad, int64_t n, const VT *__restrict__ v, const int32_t *__restrict__ perm,
     const T *__restrict__ box, T tcut, T tfar, T r2max, int S, int ST, T *__restrict__ part)
 {
-    kmv_sym_mf_body<KIND, D, T, VT, false>(Xs, npad, n, v, perm, box, tcut, tfar, r2max, S, ST, part, blockIdx.x);
+#define KMV_SYM_MF_BID blockIdx.x
+#include "kmv_sym_mf_body.inc"
+#undef KMV_SYM_MF_BID
 }
 
+// The same for several solves in one launch (group.h).
 template <int KIND, int D, typename T, typename VT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : (D <= 4 ? 4 : 2)))) void kmv_sym_mf_g(
     GroupTable<KmvMfArgs<KIND, D, T, VT>> t)
 {
     const GroupPos q = group_pos(t);
     const KmvMfArgs<KIND, D, T, VT> &a = t.a[q.g];
-    kmv_sym_mf_body<KIND, D, T, VT, true>(a.Xs, a.npad, a.n, a.v, a.perm, a.box, a.tcut, a.tfar, a.r2max, a.S, a.ST,
-                                          a.part, (unsigned)q.bx);
+    const T *__restrict__ Xs = a.Xs;
+    const int64_t npad = a.npad, n = a.n;
+    const VT *__restrict__ v = a.v;
+    const int32_t *__restrict__ perm = a.perm;
+    const T *__restrict__ box = a.box;
+    const T tcut = a.tcut, tfar = a.tfar, r2max = a.r2max;
+    const int S = a.S, ST = a.ST;
+    T *__restrict__ part = a.part;
+    const unsigned bid = (unsigned)q.bx;
+#define KMV_SYM_MF_BID bid
+#include "kmv_sym_mf_body.inc"
+#undef KMV_SYM_MF_BID
 }
 
 template <int KIND, int D, typename T, typename VT>
