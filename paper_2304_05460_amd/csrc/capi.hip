@@ -227,7 +227,8 @@ afn_status check_flags(afn_handle *h, hipStream_t s)
         return AFN_ENOTSPD;
     }
     if (f[2]) {
-        set_error("afn_setup: an FSAI block of the Schur complement is not positive definite");
+        set_error("afn_setup: the FSAI blocks of the Schur complement of %d rows are not positive definite",
+                  f[2]);
         return AFN_ENOTSPD;
     }
     if (f[3]) {

@@ -169,7 +169,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void fs
 #pragma unroll
         for (int c = j + 1; c < N; ++c) a[c] = __builtin_fma(-lr, readlane_f64(lr, c), a[c]);
     }
-    if (bad && lane == 0) atomicCAS(info, 0, 1);
+    if (bad && lane == 0) atomicAdd(info, 1);     // rows whose block is not positive definite
 
     // R^T g = e_{m-1} column by column: R goes back through LDS so that lane t
     // holds column t (a[i] = R[i][t], i >= t); b is the running right-hand side.
@@ -376,7 +376,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void f
         __syncthreads();
     }
     if (wave != 0) return;
-    if (!ok && lane == 0) atomicCAS(info, 0, 1);
+    if (!ok && lane == 0) atomicAdd(info, 1);
 
     // R22^T g2 = e2, then R11^T g1 = e1 - R21^T g2 (lane t holds column t)
     double rhs = lane == m - 1 - 64 ? 1.0 : 0.0;
