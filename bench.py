@@ -359,6 +359,15 @@ def c3_bench(args):
         "roofline": roofline,
     }
     out["autotune"] = tune_decisions(args)
+    if not args.no_serving:
+        # the latency side of the metric: a short request stream (48 requests,
+        # n log-uniform in [2e3, 2e4], d in {3, 8}, Algorithm 5's method each)
+        log("serving leg: 48 requests, burst then Poisson")
+        sb, sp, rate, pois, ns = run_serving(48, 2e3, 2e4, 8, 2, log)
+        out["serving"] = {"workload": "serving_48_requests_n2e3_2e4_d3_8", "slots": 8,
+                          "poisson_rate_per_s": round(rate, 3), "burst_solves_per_s": round(sb["solves_per_s"], 3),
+                          "poisson": _fmt({k: sp[k] for k in ("completed", "failed", "solves_per_s", "p50_s",
+                                                              "p99_s", "max_relres_true", "grouped_frac")})}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline_nystrom(X_np, p.l, p.mu, p.k, i64["iterations"])
@@ -540,22 +549,19 @@ def batch_bench(args):
         h.close()
 
 
-def serving_bench(args):
-    """Mixed-size request stream: a burst run (every request at t = 0) gives
-    the saturated throughput; a Poisson stream at 0.7 x that rate gives the
-    latency percentiles.  Mixed precision (FP32 inner PCG, FP64 refinement
-    to rel-res 1e-6), one right-hand side per request."""
+def run_serving(count, n_lo, n_hi, slots, setup_workers, log=None):
+    """A mixed-size request stream (workloads.serving_requests): a burst run
+    (every request at t = 0) gives the saturated throughput; a Poisson stream
+    at 0.7 x that rate gives the latency percentiles.  Mixed precision (FP32
+    inner PCG, FP64 refinement to rel-res 1e-6), one right-hand side per
+    request.  Returns (burst summary, Poisson summary, rate, Poisson results,
+    request sizes)."""
     import numpy as np
-    import torch
     from paper_2304_05460_amd import afn, serving, workloads as W
 
     afn.lib()
-    n_lo, n_hi = (float(v) for v in args.serving_n.split(","))
-    probs = W.serving_requests(args.serving_count, n_lo=n_lo, n_hi=n_hi)
+    probs = W.serving_requests(count, n_lo=n_lo, n_hi=n_hi)
     data = [W.make(q) for q in probs]
-
-    def log(msg):
-        print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     def reqs(arrivals):
         return [serving.Request(i, X, b, q.l, q.mu, arrival=float(arrivals[i]), k=q.k, w=q.w,
@@ -563,54 +569,73 @@ def serving_bench(args):
                 for i, (q, (X, b)) in enumerate(zip(probs, data))]
 
     def progress(label):
-        count = [0]
+        done = [0]
         lock = __import__("threading").Lock()
 
         def cb(res):
             with lock:
-                count[0] += 1
-                if count[0] % 16 == 0 or count[0] == len(probs):
-                    log(f"{label}: {count[0]}/{len(probs)} done")
+                done[0] += 1
+                if log and (done[0] % 16 == 0 or done[0] == len(probs)):
+                    log(f"{label}: {done[0]}/{len(probs)} done")
         return cb
 
+    def server():
+        return serving.Server(slots=slots, precision=afn.AFN_FP32, setup_workers=setup_workers)
+
     # warm-up: one small request (library load, first allocations)
-    srv = serving.Server(slots=args.slots, precision=afn.AFN_FP32, setup_workers=args.setup_workers)
     small = int(np.argmin([q.n for q in probs]))
-    srv.run([reqs(np.zeros(len(probs)))[small]])
-    log(f"{len(probs)} requests; burst run")
-    srv = serving.Server(slots=args.slots, precision=afn.AFN_FP32, setup_workers=args.setup_workers)
+    server().run([reqs(np.zeros(len(probs)))[small]])
     t0 = time.perf_counter()
-    burst = srv.run(reqs(np.zeros(len(probs))), on_done=progress("burst"))
+    burst = server().run(reqs(np.zeros(len(probs))), on_done=progress("burst"))
     t_burst = time.perf_counter() - t0
     sb = serving.summarize(burst)
     rate = 0.7 * sb["completed"] / t_burst
-    log(f"burst: {sb}; Poisson run at {rate:.3f} requests/s")
-    srv = serving.Server(slots=args.slots, precision=afn.AFN_FP32, setup_workers=args.setup_workers)
+    if log:
+        log(f"burst: {sb}; Poisson run at {rate:.3f} requests/s")
     t0 = time.perf_counter()
-    pois = srv.run(reqs(W.poisson_arrivals(len(probs), rate, seed=5)), on_done=progress("poisson"))
+    pois = server().run(reqs(W.poisson_arrivals(len(probs), rate, seed=5)), on_done=progress("poisson"))
     t_pois = time.perf_counter() - t0
     sp = serving.summarize(pois)
-    ns = np.array([q.n for q in probs])
+    sp["wall_s"] = t_pois
+    return sb, sp, rate, pois, np.array([q.n for q in probs])
+
+
+def _fmt(d):
+    return {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in d.items()}
+
+
+def serving_bench(args):
+    """The request stream of run_serving at its full size (--serving-count
+    requests, sizes --serving-n)."""
+    import numpy as np
+    from paper_2304_05460_amd import afn
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    n_lo, n_hi = (float(v) for v in args.serving_n.split(","))
+    log(f"{args.serving_count} requests; burst run, then Poisson")
+    sb, sp, rate, pois, ns = run_serving(args.serving_count, n_lo, n_hi, args.slots, args.setup_workers, log)
     out = {
         "metric": "serving solves/s under a Poisson stream (p50/p99 latency beside it)",
-        "value": round(sp["completed"] / t_pois, 4),
+        "value": round(sp["completed"] / sp["wall_s"], 4),
         "unit": "solves/s",
         "n_gpus": 1,
-        "steps": len(probs),
+        "steps": len(ns),
         "warmup": 1,
-        "ms_per_step": round(t_pois / len(probs) * 1e3, 2),
+        "ms_per_step": round(sp["wall_s"] / len(ns) * 1e3, 2),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"serving_{len(probs)}_requests_n{n_lo:.0e}_{n_hi:.0e}_d3_8".replace("+0", ""),
+        "config": {"workload": f"serving_{len(ns)}_requests_n{n_lo:.0e}_{n_hi:.0e}_d3_8".replace("+0", ""),
                    "grouped_launches": os.environ.get("AFN_NO_GROUP") != "1",
                    "slots": args.slots, "setup_workers": args.setup_workers,
                    "poisson_rate_per_s": round(rate, 4),
                    "n_median": int(np.median(ns)), "n_max": int(ns.max())},
-        "poisson": {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in sp.items()},
-        "burst": {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in sb.items()},
+        "poisson": _fmt(sp),
+        "burst": _fmt(sb),
         "statuses": {str(s): int(c) for s, c in
                      zip(*np.unique([r.status for r in pois], return_counts=True))},
         "methods": {["afn", "nystrom"][m]: int(c) for m, c in
@@ -628,6 +653,8 @@ def main():
     ap.add_argument("--l", type=float, default=0.1)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="default (C3) line: skip the short serving leg that reports p50/p99")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision and Algorithm 5 runs on the same input")
     ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "highd", "batch"],
