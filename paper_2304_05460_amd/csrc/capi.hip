@@ -21,6 +21,9 @@ afn_status uniform_landmarks(int64_t n, int k, uint64_t seed, int32_t *idx, hipS
 afn_status rank_estimate(const double *X, int64_t n, int d, double l, int kind, double mu, int m,
                          int kmax, uint64_t seed, DevArena &tmp, hipStream_t s, afn_setup_info *info,
                          int *k_out);
+// Bytes rank_estimate carves for a subsample of m points in d dimensions (its
+// eigenvalue branch included), as whole 256-byte blocks.
+size_t rank_workspace_bytes(int m, int d);
 
 namespace {
 
@@ -330,11 +333,7 @@ size_t setup_carve_bytes(int64_t n, int d, int64_t k, int rank_m, int w, const a
     const bool f32 = prm->precision == AFN_FP32, b16 = prm->precision == AFN_BF16;
     take(n4(16));                                            // flags
     if (rank_m > 0) {
-        const int64_t m = rank_m;
-        take(n4(m)); take(n4(m)); take(n8(m * d)); take(n8(m * m)); take(n8(m)); take(n8(4));
-        take(n8(256)); take(n8(m + 1)); take(n4(1)); take(fps_workspace_bytes(m));
-        take(n8(2 * m)); take(n8(2 * m)); take(n8(8)); take(n4(1)); take(n8(2 * (ceil_div(m, 4) + 1)));
-        take(n8(m)); take(n8(m));
+        take(rank_workspace_bytes(rank_m, d));
     }
     take(n4(n)); take(n4(k)); take(fps_workspace_bytes(n)); take(n4(n)); take(n8(n * d));   // perm, FPS, Xp
     if (method == AFN_METHOD_NYSTROM) {

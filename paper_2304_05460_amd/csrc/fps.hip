@@ -13,9 +13,12 @@
 // Schedule: one launch per selection step.  Every workgroup owns a contiguous
 // range of points; step s first reduces the per-workgroup winners of step s-1
 // (each workgroup redundantly, same order), updates the running distances of
-// its points with the new landmark, and publishes its local winner.
+// its points with the new landmark, and publishes its local winner.  Point
+// sets whose coordinates fit in LDS run a range of steps in one workgroup
+// instead (fps_lds).
 #include <cfloat>
 #include <climits>
+#include <type_traits>
 
 #include "afn_internal.h"
 
@@ -24,6 +27,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kMaxWG = 256;
+constexpr int kPubD = 8;       // d up to which slots also carry their point's coordinates
 
 struct Ws {
     double *dist;      // n running squared distances (-1 = selected)
@@ -33,6 +37,7 @@ struct Ws {
     int *slot_i;       // 2 * kMaxWG
     double *min_d;     // kMaxWG
     int *min_i;        // kMaxWG
+    double *slot_x;    // 2 * kMaxWG * kPubD: coordinates of each slot's point (d <= kPubD)
 };
 
 __device__ __forceinline__ double sqdist_chain(const double *a, const double *b, int d)
@@ -129,7 +134,7 @@ __global__ __launch_bounds__(kThreads) void nearest_centroid(const double *__res
 // First landmark = overall arg-min; seeds the step-0 winner slots.
 __global__ __launch_bounds__(kThreads) void fps_first(const double *min_d, const int *min_i, int nwg,
                                                       int64_t n, double *slot_d, int *slot_i,
-                                                      int *err)
+                                                      const double *X, int d, double *slot_x, int *err)
 {
     double bd = DBL_MAX;
     int bi = INT_MAX;
@@ -141,6 +146,7 @@ __global__ __launch_bounds__(kThreads) void fps_first(const double *min_d, const
         slot_d[g] = g == 0 ? __builtin_inf() : -__builtin_inf();
         slot_i[g] = g == 0 ? bi : INT_MAX;
     }
+    if (d <= kPubD && (int)threadIdx.x < d) slot_x[threadIdx.x] = X[(int64_t)bi * d + threadIdx.x];
 }
 
 // Step s: winner of step s-1 -> idx[s-1]; if !final, update distances with it
@@ -191,6 +197,222 @@ __global__ __launch_bounds__(kThreads) void fps_step(const double *__restrict__ 
     if (threadIdx.x == 0) { next_d[blockIdx.x] = bd; next_i[blockIdx.x] = bi; }
 }
 
+// Step s as fps_step, for d = D <= kPubD and at most PT points per thread:
+// the thread's points (running distances and coordinates) and the previous
+// slots with their points' coordinates are loaded first, none of them
+// waiting for the previous winner; the thread holding the winning slot
+// passes its coordinates on through LDS, and the thread holding this
+// workgroup's winner publishes the winner's coordinates with its slot.
+template <int D, int PT>
+__global__ __launch_bounds__(kThreads) void fps_step_pf(const double *__restrict__ X, int64_t n,
+                                                        double *__restrict__ dist, int64_t chunk, int nwg,
+                                                        const double *prev_d, const int *prev_i,
+                                                        const double *prev_x, double *next_d, int *next_i,
+                                                        double *next_x, int32_t *idx, double *seld, int s,
+                                                        int final_step, int *err)
+{
+    __shared__ double sw[D];
+    const int tid = threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.x * chunk;
+    const int64_t j1 = j0 + chunk < n ? j0 + chunk : n;
+    double cur[PT], xj[PT][D];
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+        const int64_t j = j0 + tid + (int64_t)kThreads * u;
+        const bool in = !final_step && j < j1;
+        cur[u] = in ? dist[j] : -1.0;
+#pragma unroll
+        for (int t = 0; t < D; ++t) xj[u][t] = in ? X[j * D + t] : 0.0;
+    }
+    double wd = -__builtin_inf(), px[D];
+    int wi = INT_MAX;
+    if (tid < nwg) {
+        wd = prev_d[tid];
+        wi = prev_i[tid];
+#pragma unroll
+        for (int t = 0; t < D; ++t) px[t] = prev_x[tid * D + t];
+    }
+    const int pi = wi;
+    block_reduce<true>(wd, wi);
+    const bool bad = wi < 0 || wi >= n;
+    if (bad) {                    // cannot happen for finite inputs; keep accesses in bounds
+        if (tid == 0) *err = 1;
+        wi = 0;
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+        idx[s - 1] = wi;
+        if (seld) seld[s - 1] = wd;
+    }
+    if (final_step) return;
+    if (!bad) {
+        if (tid < nwg && pi == wi) {
+#pragma unroll
+            for (int t = 0; t < D; ++t) sw[t] = px[t];
+        }
+    } else if (tid < D) {
+        sw[tid] = X[tid];
+    }
+    __syncthreads();
+    double sx[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t) sx[t] = sw[t];
+    double bd = -__builtin_inf();
+    int bi = INT_MAX;
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+        const int64_t j = j0 + tid + (int64_t)kThreads * u;
+        if (j >= j1) continue;
+        double c = cur[u];
+        if (j == wi) {
+            c = -1.0;
+            dist[j] = c;
+        } else if (c >= 0.0) {
+            double acc = 0.0;
+#pragma unroll
+            for (int t = 0; t < D; ++t) {
+                const double del = xj[u][t] - sx[t];
+                acc = __builtin_fma(del, del, acc);
+            }
+            if (acc < c) {
+                c = acc;
+                dist[j] = c;
+            }
+        }
+        cur[u] = c;
+        if (amax_better(c, (int)j, bd, bi)) { bd = c; bi = (int)j; }
+    }
+    block_reduce<true>(bd, bi);
+    if (tid == 0) { next_d[blockIdx.x] = bd; next_i[blockIdx.x] = bi; }
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+        const int64_t j = j0 + tid + (int64_t)kThreads * u;
+        if (j < j1 && j == bi) {
+#pragma unroll
+            for (int t = 0; t < D; ++t) next_x[blockIdx.x * D + t] = xj[u][t];
+        }
+    }
+}
+
+// Steps st0+1 .. st1 in one workgroup, for point sets whose coordinates fit
+// in LDS (n d <= kLdsFpsMax, n <= 16 kLdsThreads): the coordinates copied
+// into LDS (read back for the selected point only), each thread's points
+// (j = tid + kLdsThreads u) with their coordinates (D > 0, d = D) and running
+// distances in registers, one block arg-max per step (wave shuffles, then the
+// eight wave winners in a slot pair chosen by step parity, so one barrier per
+// step).  Same distances, masking and tie rule as fps_step; it starts from
+// the slots the previous step published (nwg of them) and, unless its last
+// step is the final one, publishes its winner as slot 0 of the next buffer
+// (the others empty), so launches of either kind can follow each other.
+// D = 0: any d, each point's coordinates read from LDS.
+constexpr int kLdsThreads = 512;
+constexpr int kLdsFpsMax = 20224;   // doubles of coordinates in LDS (158 KiB)
+
+template <int PT, int D>
+__global__ __launch_bounds__(kLdsThreads) void fps_lds(const double *__restrict__ X, int n, int d,
+                                                       double *__restrict__ dist, int nwg,
+                                                       const double *prev_d, const int *prev_i,
+                                                       double *next_d, int *next_i, double *next_x,
+                                                       int32_t *idx, double *seld, int st0, int st1,
+                                                       int k_total, int *err)
+{
+    extern __shared__ double xs[];          // xs[j * d + t], as X
+    __shared__ double wdd[2][kLdsThreads / 64];
+    __shared__ int wii[2][kLdsThreads / 64];
+    constexpr int DR = D > 0 ? D : 1;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int e = tid; e < n * d; e += kLdsThreads) xs[e] = X[e];
+    double cur[PT], own[PT][DR];
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+        const int j = tid + kLdsThreads * u;
+        cur[u] = j < n ? dist[j] : -__builtin_inf();
+        if constexpr (D > 0) {
+#pragma unroll
+            for (int t = 0; t < D; ++t) own[u][t] = j < n ? X[(int64_t)j * D + t] : 0.0;
+        }
+    }
+    // the winner published by step st0
+    double wd = -__builtin_inf();
+    int wi = INT_MAX;
+    for (int g = tid; g < nwg; g += kLdsThreads)
+        if (amax_better(prev_d[g], prev_i[g], wd, wi)) { wd = prev_d[g]; wi = prev_i[g]; }
+    auto reduce = [&](int par) {
+        for (int off = 32; off > 0; off >>= 1) {
+            const double od = __shfl_xor(wd, off, 64);
+            const int oi = __shfl_xor(wi, off, 64);
+            if (amax_better(od, oi, wd, wi)) { wd = od; wi = oi; }
+        }
+        if (lane == 0) { wdd[par][wv] = wd; wii[par][wv] = wi; }
+        __syncthreads();
+        wd = wdd[par][0];
+        wi = wii[par][0];
+        for (int w = 1; w < kLdsThreads / 64; ++w)
+            if (amax_better(wdd[par][w], wii[par][w], wd, wi)) { wd = wdd[par][w]; wi = wii[par][w]; }
+    };
+    reduce(0);     // also orders the coordinate stores before the first reads
+    int par = 1;
+    for (int st = st0 + 1; st <= st1; ++st) {
+        if (wi < 0 || wi >= n) {      // cannot happen for finite inputs; keep accesses in bounds
+            if (tid == 0) *err = 1;
+            wi = 0;
+        }
+        if (tid == 0) {
+            idx[st - 1] = wi;
+            if (seld) seld[st - 1] = wd;
+        }
+        if (st == k_total) break;
+        const int sel = wi;
+        double sx[DR];
+        if constexpr (D > 0) {
+#pragma unroll
+            for (int t = 0; t < D; ++t) sx[t] = xs[sel * D + t];
+        }
+        wd = -__builtin_inf();
+        wi = INT_MAX;
+#pragma unroll
+        for (int u = 0; u < PT; ++u) {
+            const int j = tid + kLdsThreads * u;
+            if (j >= n) continue;
+            double c = cur[u];
+            if (j == sel) {
+                c = -1.0;
+            } else if (c >= 0.0) {
+                double acc = 0.0;
+                if constexpr (D > 0) {
+#pragma unroll
+                    for (int t = 0; t < D; ++t) {
+                        const double del = own[u][t] - sx[t];
+                        acc = __builtin_fma(del, del, acc);
+                    }
+                } else {
+                    for (int t = 0; t < d; ++t) {
+                        const double del = xs[j * d + t] - xs[sel * d + t];
+                        acc = __builtin_fma(del, del, acc);
+                    }
+                }
+                if (acc < c) c = acc;
+            }
+            cur[u] = c;
+            if (amax_better(c, j, wd, wi)) { wd = c; wi = j; }
+        }
+        reduce(par);
+        par ^= 1;
+        if (st == st1) {
+            // published for the next call, which starts at step st1 + 1
+            for (int g = tid; g < nwg; g += kLdsThreads) {
+                next_d[g] = g == 0 ? wd : -__builtin_inf();
+                next_i[g] = g == 0 ? wi : INT_MAX;
+            }
+            if (d <= kPubD && tid < d) next_x[tid] = wi >= 0 && wi < n ? xs[wi * d + tid] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+        const int j = tid + kLdsThreads * u;
+        if (j < n) dist[j] = cur[u];
+    }
+}
+
 Ws carve(void *work, int64_t n, int d)
 {
     Ws w;
@@ -208,6 +430,7 @@ Ws carve(void *work, int64_t n, int d)
     w.slot_i = (int *)take(sizeof(int) * 2 * kMaxWG);
     w.min_d = (double *)take(sizeof(double) * kMaxWG);
     w.min_i = (int *)take(sizeof(int) * kMaxWG);
+    w.slot_x = (double *)take(sizeof(double) * 2 * kMaxWG * kPubD);
     (void)d;
     return w;
 }
@@ -219,7 +442,8 @@ size_t fps_workspace_bytes(int64_t n)
     int64_t nb = ceil_div(n, 256);
     return (size_t)(round_up(8 * n, 256) + round_up(8 * nb * kMaxD, 256) + round_up(8 * kMaxD, 256) +
                     round_up(16 * kMaxWG, 256) + round_up(8 * kMaxWG, 256) +
-                    round_up(8 * kMaxWG, 256) + round_up(4 * kMaxWG, 256) + 256);
+                    round_up(8 * kMaxWG, 256) + round_up(4 * kMaxWG, 256) +
+                    round_up(8 * 2 * kMaxWG * kPubD, 256) + 256);
 }
 
 // First landmark (nearest to the centroid) into the step-0 slots.
@@ -235,7 +459,7 @@ afn_status fps_start(const double *X, int64_t n, int d, void *work, hipStream_t 
     hipLaunchKernelGGL(nearest_centroid, dim3(nwg), dim3(kThreads), 0, s, X, n, d, w.cen, w.dist,
                        chunk, w.min_d, w.min_i);
     hipLaunchKernelGGL(fps_first, dim3(1), dim3(kThreads), 0, s, w.min_d, w.min_i, nwg, n, w.slot_d,
-                       w.slot_i, err);
+                       w.slot_i, X, d, w.slot_x, err);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }
@@ -248,7 +472,79 @@ afn_status fps_advance(const double *X, int64_t n, int d, int st0, int st1, int 
     Ws w = carve(work, n, d);
     const int nwg = (int)(ceil_div(n, kThreads) < kMaxWG ? ceil_div(n, kThreads) : kMaxWG);
     const int64_t chunk = ceil_div(n, nwg);
-    for (int st = st0 + 1; st <= st1; ++st) {
+    if (st1 <= st0) return AFN_OK;
+    if (n * d <= kLdsFpsMax && n <= 16 * kLdsThreads && st1 - st0 > 1) {
+        // one workgroup for the whole range; the slots of step st0 are in
+        // buffer st0 & 1 and the winner of step st1 goes to buffer st1 & 1
+        const size_t lds = sizeof(double) * (size_t)(n * d);
+        const int pb = st0 & 1, nbuf = st1 & 1;
+        auto go = [&](auto kern) -> afn_status {
+            AFN_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)lds));
+            hipLaunchKernelGGL(kern, dim3(1), dim3(kLdsThreads), lds, s, X, (int)n, d, w.dist, nwg,
+                               w.slot_d + pb * kMaxWG, w.slot_i + pb * kMaxWG, w.slot_d + nbuf * kMaxWG,
+                               w.slot_i + nbuf * kMaxWG, w.slot_x + nbuf * kMaxWG * kPubD, idx, seld,
+                               st0, st1, k_total, err);
+            return AFN_OK;
+        };
+        // points per thread: 4, 8 or 16; registers for 64 coordinates at most
+        auto by_n = [&](auto dtag) -> afn_status {
+            constexpr int D = decltype(dtag)::value;
+            if (n <= 4 * kLdsThreads) return go(fps_lds<4, D>);
+            if constexpr (8 * D <= 64) {
+                if (n <= 8 * kLdsThreads) return go(fps_lds<8, D>);
+            }
+            if constexpr (16 * D <= 64) return go(fps_lds<16, D>);
+            return go(fps_lds<16, 0>);
+        };
+        switch (d) {
+        case 1: AFN_TRY(by_n(std::integral_constant<int, 1>{})); break;
+        case 2: AFN_TRY(by_n(std::integral_constant<int, 2>{})); break;
+        case 3: AFN_TRY(by_n(std::integral_constant<int, 3>{})); break;
+        case 4: AFN_TRY(by_n(std::integral_constant<int, 4>{})); break;
+        case 5: AFN_TRY(by_n(std::integral_constant<int, 5>{})); break;
+        case 6: AFN_TRY(by_n(std::integral_constant<int, 6>{})); break;
+        case 7: AFN_TRY(by_n(std::integral_constant<int, 7>{})); break;
+        case 8: AFN_TRY(by_n(std::integral_constant<int, 8>{})); break;
+        default:
+            if (n <= 4 * kLdsThreads) AFN_TRY(go(fps_lds<4, 0>));
+            else AFN_TRY(go(fps_lds<16, 0>));
+        }
+        AFN_HIP(hipGetLastError());
+        return AFN_OK;
+    }
+    // d <= kPubD and at most 4 points per thread: the prefetching step
+    auto pf = [&](auto dtag) -> bool {
+        constexpr int D = decltype(dtag)::value;
+        auto run = [&](auto kern) {
+            for (int st = st0 + 1; st <= st1; ++st) {
+                const int pb = (st - 1) & 1, nbuf = st & 1;
+                const int fin = st == k_total ? 1 : 0;
+                hipLaunchKernelGGL(kern, dim3(fin ? 1 : nwg), dim3(kThreads), 0, s, X, n, w.dist, chunk,
+                                   nwg, w.slot_d + pb * kMaxWG, w.slot_i + pb * kMaxWG,
+                                   w.slot_x + pb * kMaxWG * kPubD, w.slot_d + nbuf * kMaxWG,
+                                   w.slot_i + nbuf * kMaxWG, w.slot_x + nbuf * kMaxWG * kPubD, idx, seld,
+                                   st, fin, err);
+            }
+        };
+        if (chunk <= kThreads) run(fps_step_pf<D, 1>);
+        else if (chunk <= 4 * kThreads) run(fps_step_pf<D, 4>);
+        else return false;
+        return true;
+    };
+    bool done = false;
+    switch (d) {
+    case 1: done = pf(std::integral_constant<int, 1>{}); break;
+    case 2: done = pf(std::integral_constant<int, 2>{}); break;
+    case 3: done = pf(std::integral_constant<int, 3>{}); break;
+    case 4: done = pf(std::integral_constant<int, 4>{}); break;
+    case 5: done = pf(std::integral_constant<int, 5>{}); break;
+    case 6: done = pf(std::integral_constant<int, 6>{}); break;
+    case 7: done = pf(std::integral_constant<int, 7>{}); break;
+    case 8: done = pf(std::integral_constant<int, 8>{}); break;
+    default: break;
+    }
+    for (int st = st0 + 1; !done && st <= st1; ++st) {
         const int pb = (st - 1) & 1, nbuf = st & 1;
         const int fin = st == k_total ? 1 : 0;
         hipLaunchKernelGGL(fps_step, dim3(fin ? 1 : nwg), dim3(kThreads), 0, s, X, n, d, w.dist, chunk,

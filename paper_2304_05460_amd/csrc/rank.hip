@@ -35,12 +35,23 @@ __device__ __forceinline__ uint64_t splitmix64_next(uint64_t &state)
 }
 
 // Partial Fisher-Yates over the virtual array a[j] = j, storing only the
-// positions that were written (open addressing in LDS).
-__global__ __launch_bounds__(64) void subsample_kernel(int64_t n, int m, uint64_t seed, int32_t *sub)
+// positions that were written (open addressing in LDS).  Draw i is the
+// (i+1)-th splitmix64 output, a function of seed + (i+1) gamma alone, so the
+// draws and swap partners are formed by all threads; one thread then applies
+// the swaps in order.
+constexpr int kSubThreads = 256;
+
+__global__ __launch_bounds__(kSubThreads) void subsample_kernel(int64_t n, int m, uint64_t seed, int32_t *sub)
 {
     __shared__ int keys[kHash];
     __shared__ int vals[kHash];
-    for (int i = threadIdx.x; i < kHash; i += 64) keys[i] = -1;
+    __shared__ int partner[kMaxM];
+    for (int i = threadIdx.x; i < kHash; i += kSubThreads) keys[i] = -1;
+    for (int i = threadIdx.x; i < m; i += kSubThreads) {
+        uint64_t st = seed + (uint64_t)i * 0x9E3779B97F4A7C15ULL;
+        const uint64_t draw = splitmix64_next(st);
+        partner[i] = (int)(i + (int64_t)(draw % (uint64_t)(n - i)));
+    }
     __syncthreads();
     if (threadIdx.x != 0) return;
     auto slot = [&](int pos) {
@@ -57,10 +68,8 @@ __global__ __launch_bounds__(64) void subsample_kernel(int64_t n, int m, uint64_
         keys[h] = pos;
         vals[h] = v;
     };
-    uint64_t st = seed;
     for (int i = 0; i < m; ++i) {
-        uint64_t draw = splitmix64_next(st);
-        int j = (int)(i + (int64_t)(draw % (uint64_t)(n - i)));
+        const int j = partner[i];
         int ai = get(i), aj = get(j);
         put(i, aj);
         put(j, ai);
@@ -118,35 +127,198 @@ __global__ __launch_bounds__(256) void sum_parts(const double *part, int np, dou
     if (threadIdx.x == 0) *out = ws[0];
 }
 
-// c = K[:, pj], piv = K[pj, pj]; skip flag if piv <= pivtol.
-__global__ __launch_bounds__(256) void scan_column(const double *K, int m, const int32_t *ord, int r,
-                                                   double pivtol, double *c, double *pv)
+// Blocked form of the elimination scan.  A step r with pivot point pj takes
+// the column c = S[:, pj] of the current residual S and its pivot p = S[pj, pj];
+// it either updates S[x, y] = S[x, y] - c[x] (c[y] / p) everywhere, or, with
+// p <= pivtol, sets row and column pj of S to zero.  32 successive steps are
+// applied by one pass over S (two passes per FPS chunk of 64): scan_panel
+// forms, row by row, the columns c_i and the scaled columns q_i = c_i / p_i
+// of the steps from their pivot columns of S (the same arithmetic, in the
+// same order, as the steps one at a time), and scan_update applies the terms
+// to every entry in step order, so S after the pass is bitwise S after the
+// single steps.  A skipped step's zero row and column are applied lazily: a
+// zeroed row contributes c = 0 to every later step (as the zero row would), a
+// zeroed column (a repeated pivot) gives c = 0 at the step that takes it.
+// The update also sums the squares of S after every eighth step (and after
+// the last), the Nystrom errors, in per-workgroup partials.  This file is
+// compiled without contraction: each term is a product, then a difference.
+constexpr int kScanB = 32;     // steps per pass
+constexpr int kScanE = 4;      // errors per pass, one every 8 steps
+
+// Out: C[i m + x] = c_i(x), Q[i m + x] = c_i(x) / p_i, skip[i] (workgroup 0).
+// Every workgroup first runs the nb x nb block of the pivot rows (wave 0, one
+// lane per row) to obtain the pivots, the skip flags and q_i(piv_j), then its
+// 256 rows; a row's entries are registers, each step updates the later ones.
+__global__ __launch_bounds__(256) void scan_panel(const double *__restrict__ K, int m,
+                                                  const int32_t *__restrict__ ord, int r0, int nb,
+                                                  double pivtol, double *__restrict__ C,
+                                                  double *__restrict__ Q, int *__restrict__ skip)
 {
-    const int pj = ord[r];
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x)
-        c[i] = K[i + (int64_t)pj * m];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        double p = K[pj + (int64_t)pj * m];
-        pv[0] = p;
-        pv[1] = p > pivtol ? 0.0 : 1.0;
+    __shared__ int piv[kScanB];
+    __shared__ double qb[kScanB][kScanB];     // qb[i][j] = q_i(piv_j)
+    __shared__ double pvt[kScanB];
+    __shared__ int skp[kScanB], zc[kScanB];   // zc[j]: column piv_j zeroed before step j
+    const int tid = threadIdx.x;
+    if (tid < kScanB) {
+        piv[tid] = tid < nb ? ord[r0 + tid] : -1;
+        zc[tid] = 0;
     }
+    __syncthreads();
+    // one row: at_step(i, c_i(x)) returns whether step i is skipped
+    auto run_row = [&](int x, double (&P)[kScanB], auto at_step) {
+        bool rowzero = false;
+#pragma unroll
+        for (int i = 0; i < kScanB; ++i) {
+            if (i >= nb) break;
+            const double ci = rowzero || zc[i] ? 0.0 : P[i];
+            if (at_step(i, ci)) {
+                if (x == piv[i]) rowzero = true;
+            } else {
+#pragma unroll
+                for (int j = i + 1; j < kScanB; ++j)
+                    if (j < nb) P[j] = P[j] - ci * qb[i][j];
+            }
+        }
+    };
+    if (tid < 64) {
+        // the pivot rows: lane a holds row piv_a; step i takes its pivot from
+        // lane i, and q_i(piv_j) from lane j through qb (one wave: its LDS
+        // accesses complete in program order)
+        const int a = tid;
+        double P[kScanB];
+#pragma unroll
+        for (int j = 0; j < kScanB; ++j)
+            P[j] = a < nb && j < nb ? K[piv[a] + (int64_t)piv[j] * m] : 0.0;
+        auto at_step = [&](int i, double cai) {
+            const double p = __shfl(cai, i, 64);
+            const bool sk = !(p > pivtol);
+            if (a == 0) {
+                pvt[i] = p;
+                skp[i] = sk ? 1 : 0;
+            }
+            if (a < nb) qb[i][a] = cai / p;
+            if (sk && a > i && a < nb && piv[a] == piv[i]) zc[a] = 1;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            return sk;
+        };
+        run_row(a < nb ? piv[a] : -1, P, at_step);
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && tid < nb) skip[tid] = skp[tid];
+    const int x = blockIdx.x * 256 + tid;
+    if (x >= m) return;
+    double P[kScanB];
+#pragma unroll
+    for (int j = 0; j < kScanB; ++j) P[j] = j < nb ? K[x + (int64_t)piv[j] * m] : 0.0;
+    auto at_step = [&](int i, double ci) {
+        C[(int64_t)i * m + x] = ci;
+        Q[(int64_t)i * m + x] = ci / pvt[i];
+        return skp[i] != 0;
+    };
+    run_row(x, P, at_step);
 }
 
-// K -= c c^T / piv  (entry-wise: K[i,j] -= c[i] * (c[j] / piv)), or zero the
-// row and column of a skipped pivot.
-__global__ __launch_bounds__(256) void scan_update(double *K, int m, const int32_t *ord, int r,
-                                                   const double *c, const double *pv)
+// S[x, y] after the nb steps on a 64 x 64 tile (each thread: rows
+// x0 + lr + 16 a, columns y0 + 4 lc + b, a, b < 4); part[e * nblk + block] =
+// the sum of the squares of the tile after step min(8 e + 7, nb - 1).
+constexpr int kUT = 64;
+
+__global__ __launch_bounds__(256) void scan_update(double *__restrict__ K, int m,
+                                                   const int32_t *__restrict__ ord, int r0, int nb,
+                                                   const double *__restrict__ C,
+                                                   const double *__restrict__ Q,
+                                                   const int *__restrict__ skip, double *__restrict__ part)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)m * m) return;
-    const int j = (int)(e / m), i = (int)(e - (int64_t)j * m);
-    if (pv[1] != 0.0) {
-        const int pj = ord[r];
-        if (i == pj || j == pj) K[e] = 0.0;
-        return;
+    __shared__ double cs[kScanB][kUT], qs[kScanB][kUT];
+    __shared__ int piv[kScanB];
+    __shared__ unsigned long long skm_s;
+    __shared__ double ws[4];
+    const int tid = threadIdx.x, lr = tid & 15, lc = tid >> 4;
+    const int x0 = blockIdx.x * kUT, y0 = blockIdx.y * kUT;
+    double v[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int x = x0 + lr + 16 * a, y = y0 + 4 * lc + b;
+            v[a][b] = x < m && y < m ? K[x + (int64_t)y * m] : 0.0;
+        }
+    for (int e = tid; e < kScanB * kUT; e += 256) {
+        const int i = e / kUT, r = e % kUT;
+        cs[i][r] = i < nb && x0 + r < m ? C[(int64_t)i * m + x0 + r] : 0.0;
+        qs[i][r] = i < nb && y0 + r < m ? Q[(int64_t)i * m + y0 + r] : 0.0;
     }
-    const double cj = c[j] / pv[0];
-    K[e] -= c[i] * cj;
+    if (tid < 64) {
+        piv[tid] = tid < nb ? ord[r0 + tid] : -1;
+        const unsigned long long bm = __ballot(tid < nb && skip[tid] != 0);
+        if (tid == 0) skm_s = bm;
+    }
+    __syncthreads();
+    const unsigned long long skm = skm_s;
+    const int nblk = (int)(gridDim.x * gridDim.y), blk = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    for (int e = 0; 8 * e < nb; ++e) {
+        const int iend = 8 * e + 8 < nb ? 8 * e + 8 : nb;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int i = 8 * e + k;
+            if (i >= iend) break;
+            double c[4], q[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) c[a] = cs[i][lr + 16 * a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) q[b] = qs[i][4 * lc + b];
+            if (!((skm >> i) & 1ull)) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) v[a][b] = v[a][b] - c[a] * q[b];
+            } else {
+                const int p = piv[i];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        if (x0 + lr + 16 * a == p || y0 + 4 * lc + b == p) v[a][b] = 0.0;
+            }
+        }
+        double t = 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) t = __builtin_fma(v[a][b], v[a][b], t);
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+        if ((tid & 63) == 0) ws[tid >> 6] = t;
+        __syncthreads();
+        if (tid == 0) part[(int64_t)e * nblk + blk] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+        __syncthreads();      // ws read before the next group writes it
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int x = x0 + lr + 16 * a, y = y0 + 4 * lc + b;
+            if (x < m && y < m) K[x + (int64_t)y * m] = v[a][b];
+        }
+}
+
+// errs[r0 + min(8 e + 7, nb - 1)] = sum of part[e * np ...] (one workgroup per e)
+__global__ __launch_bounds__(256) void scan_errors(const double *__restrict__ part, int np, int r0, int nb,
+                                                   double *__restrict__ errs)
+{
+    __shared__ double ws[256];
+    const int e = blockIdx.x;
+    if (8 * e >= nb) return;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < np; i += 256) s += part[(int64_t)e * np + i];
+    ws[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) ws[threadIdx.x] += ws[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) errs[r0 + (8 * e + 7 < nb - 1 ? 8 * e + 7 : nb - 1)] = ws[0];
 }
 
 // ---------------------------------------------------------------- eigen count
@@ -414,9 +586,32 @@ afn_status uniform_landmarks(int64_t n, int k, uint64_t seed, int32_t *idx, hipS
         return AFN_EINVAL;
     }
     if (k == 0) return AFN_OK;
-    hipLaunchKernelGGL(subsample_kernel, dim3(1), dim3(64), 0, s, n, k, seed, idx);
+    hipLaunchKernelGGL(subsample_kernel, dim3(1), dim3(kSubThreads), 0, s, n, k, seed, idx);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
+}
+
+namespace {
+
+int64_t scan_parts(int m)
+{
+    const int64_t p = kScanE * ceil_div(m, kUT) * ceil_div(m, kUT);
+    return p > 256 ? p : 256;
+}
+
+}  // namespace
+
+size_t rank_workspace_bytes(int m, int d)
+{
+    // every buffer rank_estimate carves, in its order, each from a 256-byte boundary
+    const int64_t sizes[] = {4 * (int64_t)m, 4 * (int64_t)m, 8 * (int64_t)m * d, 8 * (int64_t)m * m,
+                             8 * (int64_t)kScanB * m, 8 * (int64_t)kScanB * m, 8 * scan_parts(m),
+                             8 * ((int64_t)m + 1), 4, 4 * kScanB, (int64_t)fps_workspace_bytes(m),
+                             16 * (int64_t)m, 16 * (int64_t)m, 64, 4, 16 * (ceil_div(m, 4) + 1),
+                             8 * (int64_t)m, 8 * (int64_t)m};
+    int64_t total = 0;
+    for (int64_t b : sizes) total += round_up(b, 256);
+    return (size_t)total;
 }
 
 afn_status rank_estimate(const double *X, int64_t n, int d, double l, int kind, double mu, int m, int kmax,
@@ -427,26 +622,27 @@ afn_status rank_estimate(const double *X, int64_t n, int d, double l, int kind, 
         return AFN_EINVAL;
     }
     int32_t *sub = nullptr, *ord = nullptr;
-    double *Xm = nullptr, *K = nullptr, *c = nullptr, *pv = nullptr, *part = nullptr, *errs = nullptr;
+    double *Xm = nullptr, *K = nullptr, *C = nullptr, *Q = nullptr, *part = nullptr, *errs = nullptr;
     double *v = nullptr, *pw = nullptr, *gp = nullptr, *sc = nullptr, *tdiag = nullptr, *toff = nullptr;
-    int *cnt = nullptr, *err = nullptr;
+    int *cnt = nullptr, *err = nullptr, *skip = nullptr;
     void *fws = nullptr;
     const int nparts = 256;
     AFN_TRY(tmp.alloc_n(&sub, m));
     AFN_TRY(tmp.alloc_n(&ord, m));
     AFN_TRY(tmp.alloc_n(&Xm, (int64_t)m * d));
     AFN_TRY(tmp.alloc_n(&K, (int64_t)m * m));
-    AFN_TRY(tmp.alloc_n(&c, m));
-    AFN_TRY(tmp.alloc_n(&pv, 4));
-    AFN_TRY(tmp.alloc_n(&part, nparts));
+    AFN_TRY(tmp.alloc_n(&C, (int64_t)kScanB * m));
+    AFN_TRY(tmp.alloc_n(&Q, (int64_t)kScanB * m));
+    AFN_TRY(tmp.alloc_n(&part, scan_parts(m)));
     AFN_TRY(tmp.alloc_n(&errs, m + 1));
     AFN_TRY(tmp.alloc_n(&err, 1));
+    AFN_TRY(tmp.alloc_n(&skip, kScanB));
     AFN_TRY(tmp.alloc(&fws, fps_workspace_bytes(m)));
     AFN_HIP(hipMemsetAsync(err, 0, sizeof(int), s));
     const double l2 = l * l;
     const int64_t mm = (int64_t)m * m;
     const unsigned gmm = (unsigned)ceil_div(mm, 256);
-    hipLaunchKernelGGL(subsample_kernel, dim3(1), dim3(64), 0, s, n, m, seed, sub);
+    hipLaunchKernelGGL(subsample_kernel, dim3(1), dim3(kSubThreads), 0, s, n, m, seed, sub);
     const double scale = std::pow((double)m / (double)n, 1.0 / (double)d);
     hipLaunchKernelGGL(gather_scaled, dim3((unsigned)ceil_div((int64_t)m * d, 256)), dim3(256), 0, s, X,
                        sub, m, d, scale, Xm);
@@ -456,25 +652,25 @@ afn_status rank_estimate(const double *X, int64_t n, int d, double l, int kind, 
     hipLaunchKernelGGL(sumsq_partial, dim3(nparts), dim3(256), 0, s, K, mm, part);
     hipLaunchKernelGGL(sum_parts, dim3(1), dim3(256), 0, s, part, nparts, errs + m);
     AFN_HIP(hipGetLastError());
-    // nested Nystrom scan in batches of 64 eliminations
+    // nested Nystrom scan, one pass over the residual per 32 eliminations (two
+    // per FPS chunk of 64), the errors read back after each chunk
     std::vector<double> herr((size_t)m + 1, -1.0);
     AFN_HIP(hipMemcpyAsync(&herr[m], errs + m, sizeof(double), hipMemcpyDeviceToHost, s));
     AFN_HIP(hipStreamSynchronize(s));
     const double f0 = std::sqrt(herr[m]);
     const double pivtol = 1e-14 * (double)m;
+    const dim3 gpanel((unsigned)ceil_div(m, 256));
+    const dim3 gupd((unsigned)ceil_div(m, kUT), (unsigned)ceil_div(m, kUT));
+    const int nupd = (int)(gupd.x * gupd.y);
     int r_found = m;
     for (int r0 = 0; r0 < m && r_found == m; r0 += 64) {
         const int r1 = r0 + 64 < m ? r0 + 64 : m;
         AFN_TRY(fps_advance(Xm, m, d, r0, r1, m, ord, nullptr, fws, s, err));
-        for (int r = r0; r < r1; ++r) {
-            hipLaunchKernelGGL(scan_column, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, K, m, ord,
-                               r, pivtol, c, pv);
-            hipLaunchKernelGGL(scan_update, dim3(gmm), dim3(256), 0, s, K, m, ord, r, c, pv);
-            const int rr = r + 1;
-            if (rr % 8 == 0 || rr == m) {
-                hipLaunchKernelGGL(sumsq_partial, dim3(nparts), dim3(256), 0, s, K, mm, part);
-                hipLaunchKernelGGL(sum_parts, dim3(1), dim3(256), 0, s, part, nparts, errs + rr - 1);
-            }
+        for (int b0 = r0; b0 < r1; b0 += kScanB) {
+            const int nb = b0 + kScanB < r1 ? kScanB : r1 - b0;
+            hipLaunchKernelGGL(scan_panel, gpanel, dim3(256), 0, s, K, m, ord, b0, nb, pivtol, C, Q, skip);
+            hipLaunchKernelGGL(scan_update, gupd, dim3(256), 0, s, K, m, ord, b0, nb, C, Q, skip, part);
+            hipLaunchKernelGGL(scan_errors, dim3(kScanE), dim3(256), 0, s, part, nupd, b0, nb, errs);
         }
         AFN_HIP(hipGetLastError());
         AFN_HIP(hipMemcpyAsync(&herr[r0], errs + r0, sizeof(double) * (r1 - r0),

@@ -455,6 +455,24 @@ def test_fps_with_ties_and_duplicates(afn):
     np.testing.assert_array_equal(h.landmarks(), idx)
 
 
+@pytest.mark.parametrize("n,d,k", [
+    (2048, 8, 300),     # one workgroup, four points per thread, n d = 16384
+    (2049, 3, 500),     # one workgroup, sixteen points per thread
+    (8192, 2, 400),     # the largest point count of the one-workgroup form
+    (8193, 2, 200),     # one launch per step
+    (6741, 3, 256),     # n d = 20223: coordinates fill the LDS
+    (6742, 3, 130),     # one more point: one launch per step
+    (300, 3, 300),      # every point selected (the final step only reports)
+    (500, 4, 1),        # the first landmark only
+])
+def test_fps_one_workgroup_and_per_step_forms(afn, n, d, k):
+    X = W.points("mixture5", n, d, 40 + d)
+    say(f"fps n={n} d={d} k={k}")
+    h = afn.afn_setup(dev(X), 0.3, 1e-2, k=k, w=8, landmarks=afn.AFN_LANDMARKS_FPS)
+    idx, _ = oracle.fps(X, k)
+    np.testing.assert_array_equal(h.landmarks(), idx)
+
+
 # ------------------------------------------------------------------ full-size setup (C2 shape)
 
 def test_c2_fps_pattern_and_fsai_sampled(afn):
