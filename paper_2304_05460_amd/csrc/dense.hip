@@ -101,63 +101,73 @@ __global__ __launch_bounds__(256) void k12_pattern_fill_tiled(const double *__re
     }
 }
 
-// Unblocked Cholesky of the jb x jb diagonal block at (j0, j0), in LDS.
-__global__ __launch_bounds__(256) void potrf_diag(double *A, int64_t lda, int j0, int jb, int *info)
+__device__ __forceinline__ double readlane_f64(double x, int l)
 {
-    __shared__ double S[NB][NB + 1];   // S[col][row]
-    const int tid = threadIdx.x;
-    for (int e = tid; e < jb * jb; e += 256) {
-        int c = e / jb, r = e - c * jb;
-        S[c][r] = A[(j0 + r) + (int64_t)(j0 + c) * lda];
-    }
-    __syncthreads();
-    for (int j = 0; j < jb; ++j) {
-        if (tid == 0) {
-            double p = S[j][j];
-            if (!(p > 0.0)) {
-                atomicCAS(info, 0, j0 + j + 1);
-                p = 1.0;
-            }
-            S[j][j] = sqrt(p);
-        }
-        __syncthreads();
-        const double piv = S[j][j];
-        for (int r = j + 1 + tid; r < jb; r += 256) S[j][r] /= piv;
-        __syncthreads();
-        const int m = jb - j - 1;
-        for (int e = tid; e < m * m; e += 256) {
-            int c = j + 1 + e / m, r = j + 1 + e % m;
-            if (r >= c) S[c][r] -= S[j][r] * S[j][c];
-        }
-        __syncthreads();
-    }
-    for (int e = tid; e < jb * jb; e += 256) {
-        int c = e / jb, r = e - c * jb;
-        A[(j0 + r) + (int64_t)(j0 + c) * lda] = r >= c ? S[c][r] : 0.0;
-    }
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    return __hiloint2double(hi, lo);
 }
 
-// Rows below the diagonal block: L21 = A21 L11^{-T}, 64 rows per workgroup.
-__global__ __launch_bounds__(64) void trsm_panel(double *A, int64_t lda, int j0, int jb, int k)
+// Step j0 of the blocked Cholesky, one wavefront per workgroup: every
+// workgroup factors the jb x jb diagonal block in registers (lane r holds row
+// r, the identity past jb; right-looking, one fused multiply-add per entry and
+// step), workgroup 0 writes L11 (zero above the diagonal), and workgroup b
+// then solves rows j0 + jb + 64 b + lane of L21 = A21 L11^{-T} by forward
+// substitution (the row in registers, L11 from LDS).  A pivot that is not
+// positive is recorded in *info (first failing column, 1-based) and replaced
+// by 1.
+__global__ __launch_bounds__(64) void potrf_panel(double *A, int64_t lda, int j0, int jb, int k, int *info)
 {
-    __shared__ double Ls[NB][NB + 1];  // Ls[col][row] of L11
-    __shared__ double Xs[NB][NB + 1];  // Xs[col][local row]
-    const int tid = threadIdx.x;
-    for (int e = tid; e < jb * jb; e += 64) {
-        int c = e / jb, r = e - c * jb;
-        Ls[c][r] = A[(j0 + r) + (int64_t)(j0 + c) * lda];
+    __shared__ double Ls[NB][NB + 1];   // Ls[c][r] = L11[r][c]
+    const int lane = threadIdx.x;
+    {
+        double a[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+            a[c] = lane < jb && c < jb ? (c <= lane ? A[(j0 + lane) + (int64_t)(j0 + c) * lda] : 0.0)
+                                       : (lane == c ? 1.0 : 0.0);
+        int badj = -1;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const double djj = readlane_f64(a[j], j);
+            const bool bad = !(djj > 0.0);
+            if (bad && badj < 0) badj = j;
+            const double rjj = sqrt(bad ? 1.0 : djj);
+            const double lr = lane == j ? rjj : a[j] / rjj;
+            a[j] = lr;
+#pragma unroll
+            for (int c = j + 1; c < NB; ++c) a[c] = __builtin_fma(-lr, readlane_f64(lr, c), a[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < NB; ++c) Ls[c][lane] = c <= lane ? a[c] : 0.0;
+        if (blockIdx.x == 0) {
+            if (lane == 0 && badj >= 0) atomicCAS(info, 0, j0 + badj + 1);
+            if (lane < jb) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c)
+                    if (c < jb) A[(j0 + lane) + (int64_t)(j0 + c) * lda] = c <= lane ? a[c] : 0.0;
+            }
+        }
     }
-    const int64_t row = (int64_t)j0 + jb + (int64_t)blockIdx.x * 64 + tid;
-    const bool ok = row < k;
-    for (int c = 0; c < jb; ++c) Xs[c][tid] = ok ? A[row + (int64_t)(j0 + c) * lda] : 0.0;
     __syncthreads();
-    for (int c = 0; c < jb; ++c) {
-        double s = Xs[c][tid];
-        for (int t = 0; t < c; ++t) s -= Ls[t][c] * Xs[t][tid];
-        Xs[c][tid] = s / Ls[c][c];
+    const int64_t row = (int64_t)j0 + jb + (int64_t)blockIdx.x * 64 + lane;
+    if (row >= k) return;
+    double x[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) x[c] = c < jb ? A[row + (int64_t)(j0 + c) * lda] : 0.0;
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+        if (t < jb) {
+            const double xt = x[t] / Ls[t][t];
+            x[t] = xt;
+#pragma unroll
+            for (int c = t + 1; c < NB; ++c)
+                if (c < jb) x[c] = __builtin_fma(-Ls[t][c], xt, x[c]);
+        }
     }
-    if (ok)
-        for (int c = 0; c < jb; ++c) A[row + (int64_t)(j0 + c) * lda] = Xs[c][tid];
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+        if (c < jb) A[row + (int64_t)(j0 + c) * lda] = x[c];
 }
 
 // Inverse of each 64 x 64 lower diagonal block of L; identity-padded past k.
@@ -494,11 +504,10 @@ afn_status cholesky(double *A, int k, int64_t lda, int *info, hipStream_t s)
 {
     for (int j0 = 0; j0 < k; j0 += NB) {
         const int jb = k - j0 < NB ? k - j0 : NB;
-        hipLaunchKernelGGL(potrf_diag, dim3(1), dim3(256), 0, s, A, lda, j0, jb, info);
         const int rest = k - j0 - jb;
+        hipLaunchKernelGGL(potrf_panel, dim3((unsigned)(rest > 0 ? ceil_div(rest, 64) : 1)), dim3(64), 0, s, A,
+                           lda, j0, jb, k, info);
         if (rest > 0) {
-            hipLaunchKernelGGL(trsm_panel, dim3((unsigned)ceil_div(rest, 64)), dim3(64), 0, s, A, lda,
-                               j0, jb, k);
             const unsigned T = (unsigned)ceil_div(rest, NB);
             hipLaunchKernelGGL(syrk_update_mf, dim3(T, T), dim3(256), 0, s, A, lda, j0, jb, k);
         }
