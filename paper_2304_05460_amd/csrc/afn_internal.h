@@ -188,9 +188,10 @@ afn_status cholesky(double *A, int k, int64_t lda, int *info_dev, hipStream_t s)
 // Inverses of the 64 x 64 diagonal blocks of L (dinv_doubles(k) doubles).
 int64_t dinv_doubles(int k);
 afn_status diag_inverses(const double *L, int k, double *Dinv, hipStream_t s);
-// B (k x ncols, ld k) := L^{-1} B.
+// B (k x ncols, ld k) := L^{-1} B.  unit: B is the identity (k = ncols), so
+// the rows above each column's diagonal are not touched.
 afn_status trsm_lower(const double *L, const double *Dinv, int k, double *B, int64_t ncols,
-                      hipStream_t s);
+                      hipStream_t s, bool unit = false);
 afn_status identity(double *A, int k, hipStream_t s);
 // A[i + j lda] = 0 for i < j < k.
 afn_status zero_upper(double *A, int k, int64_t lda, hipStream_t s);

@@ -306,7 +306,7 @@ afn_status nystrom_factors(afn_handle *h, DevArena &tmp, Timer &tm, hipStream_t 
     AFN_TRY(diag_inverses(G, k, Dg, s));
     AFN_TRY(h->arena.alloc_n(&h->Rginv, kk));
     AFN_TRY(identity(h->Rginv, k, s));
-    AFN_TRY(trsm_lower(G, Dg, k, h->Rginv, k, s));
+    AFN_TRY(trsm_lower(G, Dg, k, h->Rginv, k, s, true));
     tm.mark(6, s);
     return AFN_OK;
 }
@@ -317,6 +317,40 @@ int block_columns(const afn_params *prm, int d)
     if (prm->precision != AFN_FP32 || d > 8 || prm->nrhs_max < 2) return 0;
     return prm->nrhs_max < 64 ? prm->nrhs_max : 64;
 }
+
+// Landmark index slots setup_impl carves: k when it is given, else the
+// largest k the rank estimate can return (min(k_max, n)), since the FPS
+// order then runs beside the estimate up to that count.
+int64_t landmark_slots(int64_t n, const afn_params *prm)
+{
+    if (prm->k >= 0) return prm->k;
+    const int64_t kmax = prm->k_max > 0 ? prm->k_max : 2000;
+    return kmax < n ? kmax : n;
+}
+
+// A second stream with two events for work that runs beside the setup
+// stream; the destructor waits for the stream's work (also on error paths,
+// so nothing outlives the caller's workspace) and releases it.
+struct SideStream {
+    hipStream_t st = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    afn_status open()
+    {
+        AFN_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        AFN_HIP(hipEventCreateWithFlags(&ev0, hipEventDisableTiming));
+        AFN_HIP(hipEventCreateWithFlags(&ev1, hipEventDisableTiming));
+        return AFN_OK;
+    }
+    ~SideStream()
+    {
+        if (st) {
+            (void)hipStreamSynchronize(st);
+            (void)hipStreamDestroy(st);
+        }
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+    }
+};
 
 // Bytes setup_impl carves from the workspace when it ends with k landmarks
 // and the given method: the same allocations in the same order (each starts
@@ -332,10 +366,11 @@ size_t setup_carve_bytes(int64_t n, int d, int64_t k, int rank_m, int w, const a
     const int64_t nr = n - k, kk = k * k;
     const bool f32 = prm->precision == AFN_FP32, b16 = prm->precision == AFN_BF16;
     take(n4(16));                                            // flags
+    take(n4(landmark_slots(n, prm))); take(fps_workspace_bytes(n));   // landmark indices, FPS
     if (rank_m > 0) {
         take(rank_workspace_bytes(rank_m, d));
     }
-    take(n4(n)); take(n4(k)); take(fps_workspace_bytes(n)); take(n4(n)); take(n8(n * d));   // perm, FPS, Xp
+    take(n4(n)); take(n4(n)); take(n8(n * d));               // perm, selection marks, Xp
     if (method == AFN_METHOD_NYSTROM) {
         if (k > 0) {
             take(n8(kk)); take(n8(dinv_doubles((int)k))); take(n8(k * n));
@@ -412,6 +447,29 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     h->info.rank_k_est = -1;
     h->info.rank_eig_branch = 0;
     h->info.rank_eig_count = -1;
+    // landmarks (Algorithm 2): FPS in low dimension, uniform sampling above d = 10
+    const int lm = prm->landmarks == AFN_LANDMARKS_AUTO ? (d <= 10 ? AFN_LANDMARKS_FPS : AFN_LANDMARKS_UNIFORM)
+                                                        : prm->landmarks;
+    h->info.landmarks = lm;
+    DevArena &tmp = h->arena;
+    const int64_t kslots = landmark_slots(n, prm);
+    int32_t *idx = nullptr;
+    void *fws = nullptr;
+    AFN_TRY(tmp.alloc_n(&idx, kslots));
+    AFN_TRY(tmp.alloc(&fws, fps_workspace_bytes(n)));
+    // the FPS order does not depend on k (a run of k steps gives the first k
+    // positions of any longer run), so with k still to be estimated the
+    // min(k_max, n) steps run on a second stream beside the rank estimate:
+    // two chains of short dependent launches that overlap
+    SideStream side;
+    const bool overlap = prm->k < 0 && lm == AFN_LANDMARKS_FPS && kslots > 0;
+    if (overlap) {
+        AFN_TRY(side.open());
+        AFN_HIP(hipEventRecord(side.ev0, s));
+        AFN_HIP(hipStreamWaitEvent(side.st, side.ev0, 0));
+        AFN_TRY(fps(X, n, d, (int)kslots, idx, nullptr, fws, side.st, h->flags + 3));
+        AFN_HIP(hipEventRecord(side.ev1, side.st));
+    }
     int k = prm->k;
     if (k < 0) {
         const int m = prm->m > 0 ? (int)(prm->m < n ? prm->m : n) : (int)(n < 2000 ? n : 2000);
@@ -434,20 +492,13 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     h->k = k;
     h->nr = n - k;
     const int64_t nr = h->nr;
-    // FPS and the block order (temporaries are carved from the same workspace)
-    DevArena &tmp = h->arena;
+    // the landmarks and the block order (temporaries are carved from the same workspace)
     AFN_TRY(h->arena.alloc_n(&h->perm, n));
-    int32_t *idx = nullptr;
-    void *fws = nullptr;
     int *sel = nullptr;
-    AFN_TRY(tmp.alloc_n(&idx, k));
-    AFN_TRY(tmp.alloc(&fws, fps_workspace_bytes(n)));
     AFN_TRY(tmp.alloc_n(&sel, n));
-    // landmarks (Algorithm 2): FPS in low dimension, uniform sampling above d = 10
-    const int lm = prm->landmarks == AFN_LANDMARKS_AUTO ? (d <= 10 ? AFN_LANDMARKS_FPS : AFN_LANDMARKS_UNIFORM)
-                                                        : prm->landmarks;
-    h->info.landmarks = lm;
-    if (lm == AFN_LANDMARKS_UNIFORM)
+    if (overlap)
+        AFN_HIP(hipStreamWaitEvent(s, side.ev1, 0));
+    else if (lm == AFN_LANDMARKS_UNIFORM)
         AFN_TRY(uniform_landmarks(n, k, prm->seed + 1, idx, s));
     else
         AFN_TRY(fps(X, n, d, k, idx, nullptr, fws, s, h->flags + 3));
@@ -467,7 +518,7 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
         AFN_TRY(cholesky(h->L, k, k, h->flags + 1, s));
         AFN_TRY(diag_inverses(h->L, k, h->Dinv, s));
         AFN_TRY(identity(h->Linv, k, s));
-        AFN_TRY(trsm_lower(h->L, h->Dinv, k, h->Linv, k, s));
+        AFN_TRY(trsm_lower(h->L, h->Dinv, k, h->Linv, k, s, true));
     }
     tm.mark(3, s);
     // spatial order of the non-landmark points: tiles for the pattern search,

@@ -325,22 +325,48 @@ __global__ __launch_bounds__(256) void syrk_update_mf(double *A, int64_t lda, in
         }
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void trsm_left_lower_mf(const double *__restrict__ L,
-                                                          const double *__restrict__ Dinv, int k, double *B,
-                                                          int64_t ncols)
+// 64 x NC product on FP64 MFMA: wave w takes rows 16 w .. 16 w + 15, both
+// operands k-index major in LDS (A with row stride TSM, B with NC + 4).
+template <int NC>
+__device__ __forceinline__ void mfma_tile_nc(const double *__restrict__ As, const double *__restrict__ Bs, int wave,
+                                             int lr, int lk, double sign, doublex4 (&acc)[NC / 16])
 {
+    constexpr int TSB = NC + 4;
+#pragma unroll 2
+    for (int kk = 0; kk < NB / 4; ++kk) {
+        const double a = sign * As[(4 * kk + lk) * TSM + 16 * wave + lr];
+#pragma unroll
+        for (int cb = 0; cb < NC / 16; ++cb) {
+            const double b = Bs[(4 * kk + lk) * TSB + 16 * cb + lr];
+            acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[cb], 0, 0, 0);
+        }
+    }
+}
+
+// B (k x ncols, ld k) := L^{-1} B, left-looking by 64-row blocks; one
+// workgroup per NC-column strip (so every strip is solved by one workgroup in
+// order and no cross-workgroup synchronization is needed): B_I -= L_IT X_T
+// for T < I, then X_I = Dinv_I B_I, as 64 x 64 x NC products on FP64 MFMA.
+// unit: B is the identity, so the strip's rows above its first column are
+// zero in X and stay as they are (the solve starts at that row block).
+template <int NC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void trsm_left_lower_mf(
+    const double *__restrict__ L, const double *__restrict__ Dinv, int k, double *B, int64_t ncols, int unit)
+{
+    constexpr int CB = NC / 16, TSB = NC + 4, XQ = NC / 4;
     __shared__ double As[NB * TSM];    // As[t * TSM + r]: A[r][t]
-    __shared__ double Bs[NB * TSM];    // Bs[t * TSM + c]: B[t][c]
+    __shared__ double Bs[NB * TSB];    // Bs[t * TSB + c]: B[t][c]
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lk = lane >> 4;
-    const int64_t c0 = (int64_t)blockIdx.x * NB;
+    const int64_t c0 = (int64_t)blockIdx.x * NC;
     const int nblk = (int)ceil_div(k, NB);
-    for (int I = 0; I < nblk; ++I) {
+    const int first = unit ? (int)(c0 / NB) : 0;
+    for (int I = first; I < nblk; ++I) {
         const int r0 = I * NB;
-        doublex4 acc[4];
+        doublex4 acc[CB];
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
+        for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int r = r0 + 16 * wave + lk + 4 * i;
@@ -348,10 +374,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void t
                 acc[cb][i] = (r < k && c < ncols) ? B[r + c * k] : 0.0;
             }
         // the tiles of step T + 1 are read into registers while the MFMAs
-        // of step T run (16 doubles of L and 16 of X per thread)
-        double la[16], xa[16];
-        // thread (r, t0) = (tid & 63, tid >> 6) takes L[r0 + r, T NB + t0 + 4 q] and
-        // B[T NB + r, c0 + t0 + 4 q], q = 0..15: one base address, stride 4 k
+        // of step T run (16 doubles of L and NC / 4 of X per thread)
+        double la[16], xa[XQ];
+        // thread (r, t0) = (tid & 63, tid >> 6) takes L[r0 + r, T NB + t0 + 4 q] (q < 16)
+        // and B[T NB + r, c0 + t0 + 4 q] (q < NC / 4): one base address, stride 4 k
         const int rr = tid & 63, t0 = tid >> 6;
         const bool rok = r0 + rr < k;
         const int64_t st4 = 4 * (int64_t)k;
@@ -359,22 +385,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void t
             const double *lp = L + (r0 + rr) + (int64_t)(T * NB + t0) * k;
             const double *xp = B + (T * NB + rr) + (c0 + t0) * k;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                la[q] = rok ? lp[q * st4] : 0.0;
-                xa[q] = c0 + t0 + 4 * q < ncols ? xp[q * st4] : 0.0;
-            }
+            for (int q = 0; q < 16; ++q) la[q] = rok ? lp[q * st4] : 0.0;
+#pragma unroll
+            for (int q = 0; q < XQ; ++q) xa[q] = c0 + t0 + 4 * q < ncols ? xp[q * st4] : 0.0;
         };
-        if (I > 0) fetch(0);
-        for (int T = 0; T < I; ++T) {
+        if (I > first) fetch(first);
+        for (int T = first; T < I; ++T) {
             __syncthreads();
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                As[(t0 + 4 * q) * TSM + rr] = la[q];
-                Bs[rr * TSM + t0 + 4 * q] = xa[q];
-            }
+            for (int q = 0; q < 16; ++q) As[(t0 + 4 * q) * TSM + rr] = la[q];
+#pragma unroll
+            for (int q = 0; q < XQ; ++q) Bs[rr * TSB + t0 + 4 * q] = xa[q];
             __syncthreads();
             if (T + 1 < I) fetch(T + 1);
-            mfma_tile64(As, Bs, wave, lr, lk, -1.0, acc);
+            mfma_tile_nc<NC>(As, Bs, wave, lr, lk, -1.0, acc);
         }
         // X_I = Dinv_I acc
         __syncthreads();
@@ -383,16 +407,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void t
             As[t * TSM + r] = Dinv[(int64_t)I * NB * NB + r + (int64_t)t * NB];
         }
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
+        for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) Bs[(16 * wave + lk + 4 * i) * TSM + 16 * cb + lr] = acc[cb][i];
+            for (int i = 0; i < 4; ++i) Bs[(16 * wave + lk + 4 * i) * TSB + 16 * cb + lr] = acc[cb][i];
         __syncthreads();
-        doublex4 out[4];
+        doublex4 out[CB];
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) out[cb] = doublex4{0.0, 0.0, 0.0, 0.0};
-        mfma_tile64(As, Bs, wave, lr, lk, 1.0, out);
+        for (int cb = 0; cb < CB; ++cb) out[cb] = doublex4{0.0, 0.0, 0.0, 0.0};
+        mfma_tile_nc<NC>(As, Bs, wave, lr, lk, 1.0, out);
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
+        for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int r = r0 + 16 * wave + lk + 4 * i;
@@ -527,11 +551,18 @@ afn_status diag_inverses(const double *L, int k, double *Dinv, hipStream_t s)
 }
 
 afn_status trsm_lower(const double *L, const double *Dinv, int k, double *B, int64_t ncols,
-                      hipStream_t s)
+                      hipStream_t s, bool unit)
 {
     if (k <= 0 || ncols <= 0) return AFN_OK;
-    hipLaunchKernelGGL(trsm_left_lower_mf, dim3((unsigned)ceil_div(ncols, NB)), dim3(256), 0, s, L,
-                       Dinv, k, B, ncols);
+    // strips of 16 columns while 64-column strips would not fill the CUs
+    // (128-column strips, half the passes over L for very wide B, measured
+    // slower: one workgroup per CU)
+    if (ncols < 64 * 256)
+        hipLaunchKernelGGL(trsm_left_lower_mf<16>, dim3((unsigned)ceil_div(ncols, 16)), dim3(256), 0, s, L,
+                           Dinv, k, B, ncols, unit ? 1 : 0);
+    else
+        hipLaunchKernelGGL(trsm_left_lower_mf<64>, dim3((unsigned)ceil_div(ncols, 64)), dim3(256), 0, s, L,
+                           Dinv, k, B, ncols, unit ? 1 : 0);
     AFN_HIP(hipGetLastError());
     return AFN_OK;
 }

@@ -479,8 +479,10 @@ afn_status fps_advance(const double *X, int64_t n, int d, int st0, int st1, int 
         const size_t lds = sizeof(double) * (size_t)(n * d);
         const int pb = st0 & 1, nbuf = st1 & 1;
         auto go = [&](auto kern) -> afn_status {
+            // one value for every launch: setups on other threads launch the
+            // same function with other sizes at the same time
             AFN_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)lds));
+                                        (int)(sizeof(double) * kLdsFpsMax)));
             hipLaunchKernelGGL(kern, dim3(1), dim3(kLdsThreads), lds, s, X, (int)n, d, w.dist, nwg,
                                w.slot_d + pb * kMaxWG, w.slot_i + pb * kMaxWG, w.slot_d + nbuf * kMaxWG,
                                w.slot_i + nbuf * kMaxWG, w.slot_x + nbuf * kMaxWG * kPubD, idx, seld,

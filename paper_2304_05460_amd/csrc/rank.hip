@@ -710,10 +710,11 @@ afn_status rank_estimate(const double *X, int64_t n, int d, double l, int kind, 
         if (m >= 3)
             hipLaunchKernelGGL(hh_mv, dim3((unsigned)ceil_div(m - 1, 4)), dim3(256), 0, s, K, m, 0, v, sc, pw,
                                gp);
-        const size_t hh_lds_max = 3 * sizeof(double) * (size_t)(m - 2);
-        if (hh_lds_max > 64 * 1024)
+        // one limit for every launch (the largest subsample's): setups on
+        // other threads launch hh_step with other sizes at the same time
+        if (3 * sizeof(double) * (size_t)(m - 2) > 64 * 1024)
             AFN_HIP(hipFuncSetAttribute((const void *)hh_step, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)hh_lds_max));
+                                        (int)(3 * sizeof(double) * (size_t)(kMaxM - 2))));
         // step j reads buffer set j & 1 (v, beta, p, partials) and writes the other
         for (int j = 0; j + 2 < m; ++j) {
             const int nb = (int)ceil_div(m - j - 1, 4);         // workgroups of the previous launch
