@@ -536,6 +536,31 @@ def test_rank_estimate_matches_oracle(afn, l):
     np.testing.assert_array_equal(h.landmarks(), idx)
 
 
+@pytest.mark.parametrize("case", ["skipped_pivots", "ragged_last_pass"])
+def test_rank_scan_edges_match_oracle(afn, case):
+    # skipped_pivots: 40 points, l = 100: K is all but constant, so after the
+    # first elimination every pivot is below 1e-14 m and its row and column are
+    # zeroed (the error is taken after step 8).  ragged_last_pass: 61 points far
+    # apart at l = 1e-3: K = I, the error sqrt((m - r) / m) stays above 0.1 to
+    # the end, so r = m = 61, taken after a last pass of 29 steps whose final
+    # group has 5.
+    if case == "skipped_pivots":
+        X = W.points("uniform", 40, 3, 71)
+        l, m = 100.0, 40
+    else:
+        X = np.arange(61, dtype=float)[:, None] * np.ones((1, 2))
+        l, m = 1e-3, 61
+    n = X.shape[0]
+    say(f"rank scan {case}")
+    h = afn.afn_setup(dev(X), l, 1e-3, k=-1, w=4, k_max=n, m=m, seed=5, method=afn.AFN_METHOD_NYSTROM)
+    inf = h.info()
+    ko, info = oracle.rank_estimate(X, l, 1e-3, m, kmax=n, kswitch=2000, seed=5)
+    say("gpu", inf.k, inf.rank_r, inf.rank_k_est, inf.rank_eig_count, "oracle", ko, info)
+    assert inf.rank_r == info[0]
+    assert inf.rank_r == (8 if case == "skipped_pivots" else 61)
+    assert inf.rank_eig_branch == info[2] and inf.k == ko
+
+
 def test_rank_estimate_largest_subsample(afn):
     # m at its maximum: the tridiagonalization's LDS per launch (3 (m - j - 2)
     # doubles) exceeds 64 KB in the first steps
