@@ -108,47 +108,58 @@ __device__ __forceinline__ double readlane_f64(double x, int l)
     return __hiloint2double(hi, lo);
 }
 
-// Step j0 of the blocked Cholesky, one wavefront per workgroup: every
-// workgroup factors the jb x jb diagonal block in registers (lane r holds row
-// r, the identity past jb; right-looking, one fused multiply-add per entry and
-// step), workgroup 0 writes L11 (zero above the diagonal), and workgroup b
-// then solves rows j0 + jb + 64 b + lane of L21 = A21 L11^{-T} by forward
-// substitution (the row in registers, L11 from LDS).  A pivot that is not
+// Step j0 of the blocked Cholesky, diagonal block: one wavefront factors the
+// jb x jb block in registers (lane r holds row r, the identity past jb;
+// right-looking, one fused multiply-add per entry and step; column j of L
+// goes through LDS so that every lane reads the entries L[c][j] it needs as
+// broadcasts) and writes L11 (zero above the diagonal).  A pivot that is not
 // positive is recorded in *info (first failing column, 1-based) and replaced
-// by 1.
-__global__ __launch_bounds__(64) void potrf_panel(double *A, int64_t lda, int j0, int jb, int k, int *info)
+// by 1.  A separate kernel (potrf_rows) then solves the rows below against the
+// finished L11: a workgroup of one launch that read the diagonal block while
+// another wrote it back would see a partly factored block.
+__global__ __launch_bounds__(64) void potrf_diag(double *A, int64_t lda, int j0, int jb, int *info)
+{
+    __shared__ double Lc[NB][NB + 1];   // Lc[j][r] = L[r][j] as each column is formed
+    const int lane = threadIdx.x;
+    double a[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+        a[c] = lane < jb && c < jb ? (c <= lane ? A[(j0 + lane) + (int64_t)(j0 + c) * lda] : 0.0)
+                                   : (lane == c ? 1.0 : 0.0);
+    int badj = -1;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const double djj = readlane_f64(a[j], j);
+        const bool bad = !(djj > 0.0);
+        if (bad && badj < 0) badj = j;
+        const double rjj = sqrt(bad ? 1.0 : djj);
+        const double lr = lane == j ? rjj : a[j] / rjj;
+        a[j] = lr;
+        Lc[j][lane] = lr;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int c = j + 1; c < NB; ++c) a[c] = __builtin_fma(-lr, Lc[j][c], a[c]);
+    }
+    if (lane == 0 && badj >= 0) atomicCAS(info, 0, j0 + badj + 1);
+    if (lane < jb) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+            if (c < jb) A[(j0 + lane) + (int64_t)(j0 + c) * lda] = c <= lane ? a[c] : 0.0;
+    }
+}
+
+// Step j0, the rows below: workgroup b solves rows j0 + jb + 64 b + lane of
+// L21 = A21 L11^{-T} by forward substitution (the row in registers, L11 from
+// LDS), after potrf_diag has written L11.
+__global__ __launch_bounds__(64) void potrf_rows(double *A, int64_t lda, int j0, int jb, int k)
 {
     __shared__ double Ls[NB][NB + 1];   // Ls[c][r] = L11[r][c]
     const int lane = threadIdx.x;
-    {
-        double a[NB];
 #pragma unroll
-        for (int c = 0; c < NB; ++c)
-            a[c] = lane < jb && c < jb ? (c <= lane ? A[(j0 + lane) + (int64_t)(j0 + c) * lda] : 0.0)
-                                       : (lane == c ? 1.0 : 0.0);
-        int badj = -1;
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const double djj = readlane_f64(a[j], j);
-            const bool bad = !(djj > 0.0);
-            if (bad && badj < 0) badj = j;
-            const double rjj = sqrt(bad ? 1.0 : djj);
-            const double lr = lane == j ? rjj : a[j] / rjj;
-            a[j] = lr;
-#pragma unroll
-            for (int c = j + 1; c < NB; ++c) a[c] = __builtin_fma(-lr, readlane_f64(lr, c), a[c]);
-        }
-#pragma unroll
-        for (int c = 0; c < NB; ++c) Ls[c][lane] = c <= lane ? a[c] : 0.0;
-        if (blockIdx.x == 0) {
-            if (lane == 0 && badj >= 0) atomicCAS(info, 0, j0 + badj + 1);
-            if (lane < jb) {
-#pragma unroll
-                for (int c = 0; c < NB; ++c)
-                    if (c < jb) A[(j0 + lane) + (int64_t)(j0 + c) * lda] = c <= lane ? a[c] : 0.0;
-            }
-        }
-    }
+    for (int c = 0; c < NB; ++c)
+        Ls[c][lane] = lane < jb && c < jb && c <= lane ? A[(j0 + lane) + (int64_t)(j0 + c) * lda] : 0.0;
     __syncthreads();
     const int64_t row = (int64_t)j0 + jb + (int64_t)blockIdx.x * 64 + lane;
     if (row >= k) return;
@@ -192,81 +203,6 @@ __global__ __launch_bounds__(64) void diag_inverse(const double *L, int k, doubl
     }
     double *out = Dinv + (int64_t)b * NB * NB + (int64_t)c * NB;
     for (int i = 0; i < NB; ++i) out[i] = Ys[c][i];
-}
-
-// B (k x ncols, ld k) := L^{-1} B, left-looking by 64-row blocks; one
-// workgroup per 64-column tile (so every column tile is solved by the same
-// workgroup in order and no cross-workgroup synchronization is needed).
-__global__ __launch_bounds__(256) void trsm_left_lower(const double *__restrict__ L,
-                                                       const double *__restrict__ Dinv, int k,
-                                                       double *B, int64_t ncols)
-{
-    __shared__ double Ls[NB][NB + 2];  // Ls[t][row]
-    __shared__ double Xs[NB][NB + 2];  // Xs[t][col]
-    const int tid = threadIdx.x;
-    const int ty = tid / 16, tx = tid % 16;
-    const int64_t c0 = (int64_t)blockIdx.x * NB;
-    const int nblk = (int)ceil_div(k, NB);
-    for (int I = 0; I < nblk; ++I) {
-        const int r0 = I * NB;
-        double acc[4][4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                int r = r0 + ty * 4 + q;
-                int64_t c = c0 + tx * 4 + u;
-                acc[q][u] = (r < k && c < ncols) ? B[r + c * k] : 0.0;
-            }
-        for (int T = 0; T < I; ++T) {
-            __syncthreads();
-            for (int e = tid; e < NB * NB; e += 256) {
-                int t = e / NB, r = e - t * NB;   // Ls[t][r] = L[r0 + r, T*NB + t]
-                Ls[t][r] = r0 + r < k ? L[(r0 + r) + (int64_t)(T * NB + t) * k] : 0.0;
-                int cc = e / NB, tt = e - cc * NB;  // Xs[tt][cc] = B[T*NB + tt, c0 + cc]
-                Xs[tt][cc] = c0 + cc < ncols ? B[(T * NB + tt) + (c0 + cc) * k] : 0.0;
-            }
-            __syncthreads();
-            for (int t = 0; t < NB; ++t) {
-                double a[4], b[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) { a[q] = Ls[t][ty * 4 + q]; b[q] = Xs[t][tx * 4 + q]; }
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) acc[q][u] = __builtin_fma(-a[q], b[u], acc[q][u]);
-            }
-        }
-        __syncthreads();
-        // X_I = Dinv_I * acc
-        for (int e = tid; e < NB * NB; e += 256) {
-            int t = e / NB, r = e - t * NB;     // Ls[t][r] = Dinv_I[r, t]
-            Ls[t][r] = Dinv[(int64_t)I * NB * NB + r + (int64_t)t * NB];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int u = 0; u < 4; ++u) Xs[ty * 4 + q][tx * 4 + u] = acc[q][u];
-        __syncthreads();
-        double out[4][4] = {};
-        for (int t = 0; t < NB; ++t) {
-            double a[4], b[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) { a[q] = Ls[t][ty * 4 + q]; b[q] = Xs[t][tx * 4 + q]; }
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int u = 0; u < 4; ++u) out[q][u] = __builtin_fma(a[q], b[u], out[q][u]);
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                int r = r0 + ty * 4 + q;
-                int64_t c = c0 + tx * 4 + u;
-                if (r < k && c < ncols) B[r + c * k] = out[q][u];
-            }
-    }
 }
 
 // The same solve with the 64 x 64 x 64 products on FP64 MFMA 16x16x4: wave
@@ -423,6 +359,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void t
                 const int64_t c = c0 + 16 * cb + lr;
                 if (r < k && c < ncols) B[r + c * k] = out[cb][i];
             }
+        // each wave stored 16 rows of X_I, and the next row block's first
+        // fetch reads X tiles back across waves (X_I itself when I is the
+        // strip's first block): every store lands before any wave goes on
+        __syncthreads();
     }
 }
 
@@ -529,9 +469,9 @@ afn_status cholesky(double *A, int k, int64_t lda, int *info, hipStream_t s)
     for (int j0 = 0; j0 < k; j0 += NB) {
         const int jb = k - j0 < NB ? k - j0 : NB;
         const int rest = k - j0 - jb;
-        hipLaunchKernelGGL(potrf_panel, dim3((unsigned)(rest > 0 ? ceil_div(rest, 64) : 1)), dim3(64), 0, s, A,
-                           lda, j0, jb, k, info);
+        hipLaunchKernelGGL(potrf_diag, dim3(1), dim3(64), 0, s, A, lda, j0, jb, info);
         if (rest > 0) {
+            hipLaunchKernelGGL(potrf_rows, dim3((unsigned)ceil_div(rest, 64)), dim3(64), 0, s, A, lda, j0, jb, k);
             const unsigned T = (unsigned)ceil_div(rest, NB);
             hipLaunchKernelGGL(syrk_update_mf, dim3(T, T), dim3(256), 0, s, A, lda, j0, jb, k);
         }
