@@ -549,6 +549,54 @@ def batch_bench(args):
         h.close()
 
 
+def setups_bench(args):
+    """Setups of small requests: the first 16 requests of the serving mix
+    with n log-uniform in [2e3, 2e4] (workloads.serving_requests, seed 5:
+    d in {3, 8}, l log-uniform in [0.01, 2], mu in {1e-4, 1e-2}), Algorithm 5
+    choosing the branch, FP32 precision, one after another on one stream;
+    per request the setup time (inputs resident) and afn_setup's phase times,
+    the best of --steps timed runs after --warmup."""
+    import torch
+    from paper_2304_05460_amd import afn, workloads as W
+
+    afn.lib()
+    probs = W.serving_requests(48, n_lo=2e3, n_hi=2e4)[:16]
+    data = [torch.tensor(W.make(q)[0], device="cuda") for q in probs]
+
+    def once():
+        rows = []
+        for q, X in zip(probs, data):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h = afn.afn_setup(X, q.l, q.mu, k=q.k, w=q.w, k_max=q.k_max, precision=afn.AFN_FP32,
+                              method=afn.AFN_METHOD_AUTO, nrhs_max=0)
+            si = h.info()
+            torch.cuda.synchronize()
+            rows.append((time.perf_counter() - t0, q, si))
+            h.close()
+        return rows
+
+    for _ in range(max(0, args.warmup)):
+        once()
+    best = None
+    for _ in range(max(1, args.steps)):
+        rows = once()
+        if best is None or sum(r[0] for r in rows) < sum(r[0] for r in best):
+            best = rows
+    total = sum(r[0] for r in best)
+    print(json.dumps({
+        "metric": "small-request setups/s (16 requests of the serving mix, one after another)",
+        "value": round(len(best) / total, 3), "unit": "setups/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(total * 1e3, 2), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "setups16_serving_mix_n2e3_2e4", "requests": len(best)},
+        "requests": [{"n": q.n, "d": q.d, "k": si.k, "method": "nystrom" if si.method else "afn",
+                      "setup_ms": round(t * 1e3, 2), "phases_ms": {k: round(v, 2) for k, v in si.ms.items()}}
+                     for t, q, si in best],
+        "phases_ms_total": {k: round(sum(si.ms[k] for _, _, si in best), 1) for k in best[0][2].ms},
+    }))
+
+
 def run_serving(count, n_lo, n_hi, slots, setup_workers, log=None):
     """A mixed-size request stream (workloads.serving_requests): a burst run
     (every request at t = 0) gives the saturated throughput; a Poisson stream
@@ -657,10 +705,11 @@ def main():
                     help="default (C3) line: skip the short serving leg that reports p50/p99")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision and Algorithm 5 runs on the same input")
-    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "highd", "batch"],
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "highd", "batch", "setups"],
                     help="c3 (default): mixed vs FP64 at n=2e5, d=8; c2: FP64 at n=1e5, d=3 "
                          "(--l 0.01 / 0.1 / 1); c4: 64 right-hand sides at n=1.5e5; highd: n=49990, "
-                         "d=22 (uniform landmarks)")
+                         "d=22 (uniform landmarks); batch: 16 like small solves, grouped against "
+                         "ungrouped; setups: the setups of 16 small serving requests")
     ap.add_argument("--c3-branch", default="nystrom", choices=["nystrom", "afn"],
                     help="preconditioner of the c3 solves (Algorithm 5's branches)")
     ap.add_argument("--maxit", type=int, default=0, help="PCG iteration cap (0: the workload's)")
@@ -714,6 +763,9 @@ def main():
         return
     if args.workload == "batch":
         batch_bench(args)
+        return
+    if args.workload == "setups":
+        setups_bench(args)
         return
 
     c2_bench(args)

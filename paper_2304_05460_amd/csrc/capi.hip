@@ -352,6 +352,38 @@ struct SideStream {
     }
 };
 
+// A second host thread that enqueues a chain of launches (on a SideStream)
+// while this thread enqueues and waits on its own: a chain of a few thousand
+// short launches costs the host about as long as the GPU takes to run it, so
+// enqueued from the thread that runs the rest it would hold that work back.
+// Joined by the destructor (also on error paths, before the side stream is
+// released); join() hands on the worker's status and message.
+struct HostWorker {
+    std::thread th;
+    afn_status st = AFN_OK;
+    std::string msg;
+    template <class F>
+    void start(int device, F f)
+    {
+        th = std::thread([this, device, f]() {
+            hipError_t e = hipSetDevice(device);
+            st = e == hipSuccess ? f() : AFN_EDEVICE;
+            if (e != hipSuccess) msg = std::string("hipSetDevice: ") + hipGetErrorString(e);
+            else if (st != AFN_OK) msg = afn_last_error();
+        });
+    }
+    afn_status join()
+    {
+        if (th.joinable()) th.join();
+        if (st != AFN_OK) set_error("%s", msg.c_str());
+        return st;
+    }
+    ~HostWorker()
+    {
+        if (th.joinable()) th.join();
+    }
+};
+
 // Bytes setup_impl carves from the workspace when it ends with k landmarks
 // and the given method: the same allocations in the same order (each starts
 // on a 256-byte boundary), the temporaries included.  rank_m > 0: the rank
@@ -462,13 +494,20 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     // min(k_max, n) steps run on a second stream beside the rank estimate:
     // two chains of short dependent launches that overlap
     SideStream side;
+    HostWorker fps_host;   // declared after side: joined before the stream goes
     const bool overlap = prm->k < 0 && lm == AFN_LANDMARKS_FPS && kslots > 0;
     if (overlap) {
         AFN_TRY(side.open());
         AFN_HIP(hipEventRecord(side.ev0, s));
         AFN_HIP(hipStreamWaitEvent(side.st, side.ev0, 0));
-        AFN_TRY(fps(X, n, d, (int)kslots, idx, nullptr, fws, side.st, h->flags + 3));
-        AFN_HIP(hipEventRecord(side.ev1, side.st));
+        int *fflag = h->flags + 3;
+        const hipStream_t fst = side.st;
+        const hipEvent_t fev = side.ev1;
+        fps_host.start(h->device, [=]() -> afn_status {
+            AFN_TRY(fps(X, n, d, (int)kslots, idx, nullptr, fws, fst, fflag));
+            AFN_HIP(hipEventRecord(fev, fst));
+            return AFN_OK;
+        });
     }
     int k = prm->k;
     if (k < 0) {
@@ -496,8 +535,10 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     AFN_TRY(h->arena.alloc_n(&h->perm, n));
     int *sel = nullptr;
     AFN_TRY(tmp.alloc_n(&sel, n));
-    if (overlap)
+    if (overlap) {
+        AFN_TRY(fps_host.join());
         AFN_HIP(hipStreamWaitEvent(s, side.ev1, 0));
+    }
     else if (lm == AFN_LANDMARKS_UNIFORM)
         AFN_TRY(uniform_landmarks(n, k, prm->seed + 1, idx, s));
     else

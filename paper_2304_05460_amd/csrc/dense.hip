@@ -109,76 +109,133 @@ __device__ __forceinline__ double readlane_f64(double x, int l)
 }
 
 // Step j0 of the blocked Cholesky, diagonal block: one wavefront factors the
-// jb x jb block in registers (lane r holds row r, the identity past jb;
-// right-looking, one fused multiply-add per entry and step; column j of L
-// goes through LDS so that every lane reads the entries L[c][j] it needs as
-// broadcasts) and writes L11 (zero above the diagonal).  A pivot that is not
-// positive is recorded in *info (first failing column, 1-based) and replaced
-// by 1.  A separate kernel (potrf_rows) then solves the rows below against the
-// finished L11: a workgroup of one launch that read the diagonal block while
-// another wrote it back would see a partly factored block.
+// jb x jb block (lane r holds row r, the identity past jb) left-looking in
+// chunks of eight columns.  A chunk takes the contributions of the columns
+// already in LDS (the lane's own entry and the chunk rows' entries, read as
+// broadcasts), then factors its eight columns in registers with the pivots
+// and the entries L[c][j] taken from their lanes.  Every entry receives the
+// same fused multiply-adds in the same ascending column order as a
+// right-looking register sweep, while the loops stay rolled: code that runs
+// once per launch and is unrolled over the whole block spends its time on
+// instruction fetch.  Writes L11 (zero above the diagonal).  A pivot that is
+// not positive is recorded in *info (first failing column, 1-based) and
+// replaced by 1.  A separate kernel (potrf_rows) then solves the rows below
+// against the finished L11: a workgroup of one launch that read the diagonal
+// block while another wrote it back would see a partly factored block.
+constexpr int kChol = 8;   // columns per chunk
+
 __global__ __launch_bounds__(64) void potrf_diag(double *A, int64_t lda, int j0, int jb, int *info)
 {
-    __shared__ double Lc[NB][NB + 1];   // Lc[j][r] = L[r][j] as each column is formed
+    __shared__ double Lc[NB][NB];   // Lc[c][r]: A[r][c], then L[r][c] (zero above the diagonal)
     const int lane = threadIdx.x;
-    double a[NB];
+    // the whole block first, sixteen loads in flight at a time (a load per
+    // chunk or per column would wait out the memory latency each time), from
+    // clamped in-range addresses and masked afterwards, so that no branch
+    // separates the loads
+    const int lr = lane < jb ? lane : 0;
+    for (int c0 = 0; c0 < NB; c0 += 16) {
+        double v[16];
 #pragma unroll
-    for (int c = 0; c < NB; ++c)
-        a[c] = lane < jb && c < jb ? (c <= lane ? A[(j0 + lane) + (int64_t)(j0 + c) * lda] : 0.0)
-                                   : (lane == c ? 1.0 : 0.0);
+        for (int u = 0; u < 16; ++u) v[u] = A[(j0 + lr) + (int64_t)(j0 + (c0 + u < jb ? c0 + u : 0)) * lda];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int c = c0 + u;
+            Lc[c][lane] = lane < jb && c < jb ? (c <= lane ? v[u] : 0.0) : (lane == c ? 1.0 : 0.0);
+        }
+    }
     int badj = -1;
+    for (int q = 0; q < NB; q += kChol) {
+        double a[kChol];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        const double djj = readlane_f64(a[j], j);
-        const bool bad = !(djj > 0.0);
-        if (bad && badj < 0) badj = j;
-        const double rjj = sqrt(bad ? 1.0 : djj);
-        const double lr = lane == j ? rjj : a[j] / rjj;
-        a[j] = lr;
-        Lc[j][lane] = lr;
+        for (int t = 0; t < kChol; ++t) a[t] = Lc[q + t][lane];
+        for (int c = 0; c < q; ++c) {
+            const double lr = Lc[c][lane];
+#pragma unroll
+            for (int t = 0; t < kChol; ++t) a[t] = __builtin_fma(-lr, Lc[c][q + t], a[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < kChol; ++t) {
+            const int j = q + t;
+            const double djj = readlane_f64(a[t], j);
+            const bool bad = !(djj > 0.0);
+            if (bad && badj < 0) badj = j;
+            const double rjj = sqrt(bad ? 1.0 : djj);
+            const double lr = lane == j ? rjj : (lane > j ? a[t] / rjj : 0.0);
+            a[t] = lr;
+#pragma unroll
+            for (int u = t + 1; u < kChol; ++u) a[u] = __builtin_fma(-lr, readlane_f64(lr, q + u), a[u]);
+        }
+#pragma unroll
+        for (int t = 0; t < kChol; ++t) {
+            Lc[q + t][lane] = a[t];
+            if (lane < jb && q + t < jb) A[(j0 + lane) + (int64_t)(j0 + q + t) * lda] = a[t];
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-        for (int c = j + 1; c < NB; ++c) a[c] = __builtin_fma(-lr, Lc[j][c], a[c]);
     }
     if (lane == 0 && badj >= 0) atomicCAS(info, 0, j0 + badj + 1);
-    if (lane < jb) {
-#pragma unroll
-        for (int c = 0; c < NB; ++c)
-            if (c < jb) A[(j0 + lane) + (int64_t)(j0 + c) * lda] = c <= lane ? a[c] : 0.0;
-    }
 }
 
 // Step j0, the rows below: workgroup b solves rows j0 + jb + 64 b + lane of
-// L21 = A21 L11^{-T} by forward substitution (the row in registers, L11 from
-// LDS), after potrf_diag has written L11.
+// L21 = A21 L11^{-T} by forward substitution, after potrf_diag has written
+// L11: left-looking in chunks of eight columns against the solved entries of
+// the lane's row kept in LDS, the same operations in the same order as a
+// right-looking sweep (and rolled for the reason given above).
 __global__ __launch_bounds__(64) void potrf_rows(double *A, int64_t lda, int j0, int jb, int k)
 {
-    __shared__ double Ls[NB][NB + 1];   // Ls[c][r] = L11[r][c]
+    __shared__ double Ls[NB][NB];   // Ls[c][r] = L11[r][c]
+    __shared__ double Xs[NB][NB];   // Xs[c][lane]: entry c of the lane's row, then its solution
     const int lane = threadIdx.x;
-#pragma unroll
-    for (int c = 0; c < NB; ++c)
-        Ls[c][lane] = lane < jb && c < jb && c <= lane ? A[(j0 + lane) + (int64_t)(j0 + c) * lda] : 0.0;
-    __syncthreads();
     const int64_t row = (int64_t)j0 + jb + (int64_t)blockIdx.x * 64 + lane;
-    if (row >= k) return;
-    double x[NB];
+    // L11 and the lane's row first, sixteen loads in flight at a time
+    // (clamped in-range addresses, masked afterwards: no branch between loads)
+    const int lr = lane < jb ? lane : 0;
+    const int64_t rr = row < k ? row : (int64_t)j0;
+    for (int c0 = 0; c0 < NB; c0 += 16) {
+        double lv[16], xv[16];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) x[c] = c < jb ? A[row + (int64_t)(j0 + c) * lda] : 0.0;
+        for (int u = 0; u < 16; ++u) {
+            const int64_t col = (int64_t)(j0 + (c0 + u < jb ? c0 + u : 0)) * lda;
+            lv[u] = A[(j0 + lr) + col];
+            xv[u] = A[rr + col];
+        }
 #pragma unroll
-    for (int t = 0; t < NB; ++t) {
-        if (t < jb) {
-            const double xt = x[t] / Ls[t][t];
-            x[t] = xt;
-#pragma unroll
-            for (int c = t + 1; c < NB; ++c)
-                if (c < jb) x[c] = __builtin_fma(-Ls[t][c], xt, x[c]);
+        for (int u = 0; u < 16; ++u) {
+            const int c = c0 + u;
+            Ls[c][lane] = lane < jb && c < jb && c <= lane ? lv[u] : 0.0;
+            Xs[c][lane] = row < k && c < jb ? xv[u] : 0.0;
         }
     }
+    __syncthreads();
+    if (row >= k) return;
+    for (int q = 0; q < jb; q += kChol) {
+        double x[kChol];
 #pragma unroll
-    for (int c = 0; c < NB; ++c)
-        if (c < jb) A[row + (int64_t)(j0 + c) * lda] = x[c];
+        for (int t = 0; t < kChol; ++t) x[t] = Xs[q + t][lane];
+        for (int c = 0; c < q; ++c) {
+            const double xc = Xs[c][lane];
+#pragma unroll
+            for (int t = 0; t < kChol; ++t) x[t] = __builtin_fma(-Ls[c][q + t], xc, x[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < kChol; ++t) {
+            if (q + t < jb) {
+                const double xt = x[t] / Ls[q + t][q + t];
+                x[t] = xt;
+#pragma unroll
+                for (int u = t + 1; u < kChol; ++u) x[u] = __builtin_fma(-Ls[q + t][q + u], xt, x[u]);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < kChol; ++t) {
+            Xs[q + t][lane] = x[t];
+            if (q + t < jb) A[row + (int64_t)(j0 + q + t) * lda] = x[t];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
 }
 
 // Inverse of each 64 x 64 lower diagonal block of L; identity-padded past k.

@@ -83,3 +83,50 @@ def test_serving_admission_by_footprint(mods):
     res2 = srv2.run(reqs)
     rej = [r.rid for r in res2 if r.status == serving.REJECTED]
     assert rej == [int(np.argmax(fps))]
+
+
+def _factors(afn, r, precision, k, stream=None):
+    X = torch.from_numpy(r.X).cuda()
+    h = afn.afn_setup(X, r.l, r.mu, k=k, w=r.w, k_max=r.k_max, precision=precision,
+                      nrhs_max=0, stream=stream)
+    try:
+        (stream.synchronize if stream is not None else torch.cuda.synchronize)()
+        si = h.info()
+        out = {"k": si.k, "method": si.method, "lm": h.landmarks()}
+        if si.k > 0:
+            out["L"] = h.cholesky()
+        if si.method == 0 and si.n > si.k:
+            out["G"] = h.fsai()
+        return out
+    finally:
+        h.close()
+
+
+@pytest.mark.parametrize("kfix", [False, True], ids=["rank_estimate", "k400"])
+def test_setups_on_concurrent_streams_match_solo(mods, kfix):
+    """Setups running at once on four streams give the landmarks, the landmark
+    Cholesky factor and the FSAI factor of the same setup run alone, bit for
+    bit: no kernel of the setup may depend on what else shares the GPU."""
+    import concurrent.futures as cf
+    afn, serving = mods
+    reqs = _requests(serving)
+    ks = [min(400, q.X.shape[0]) if kfix else q.k for q in reqs]
+    solo = [_factors(afn, q, 1, k) for q, k in zip(reqs, ks)]
+    streams = [torch.cuda.Stream() for _ in range(4)]
+
+    def job(i):
+        s = streams[i % 4]
+        with torch.cuda.stream(s):
+            return _factors(afn, reqs[i], 1, ks[i], stream=s)
+
+    for rep in range(3):
+        with cf.ThreadPoolExecutor(4) as ex:
+            got = list(ex.map(job, range(len(reqs))))
+        for i, (a, b) in enumerate(zip(solo, got)):
+            assert (a["k"], a["method"]) == (b["k"], b["method"]), (rep, i)
+            assert np.array_equal(a["lm"], b["lm"]), (rep, i, "landmarks")
+            if "L" in a:
+                assert np.array_equal(a["L"], b["L"]), (rep, i, "cholesky")
+            if "G" in a:
+                for name, p, q in zip(("rowptr", "cols", "vals"), a["G"], b["G"]):
+                    assert np.array_equal(p, q), (rep, i, "fsai " + name)
