@@ -328,29 +328,6 @@ int64_t landmark_slots(int64_t n, const afn_params *prm)
     return kmax < n ? kmax : n;
 }
 
-// A second stream with two events for work that runs beside the setup
-// stream; the destructor waits for the stream's work (also on error paths,
-// so nothing outlives the caller's workspace) and releases it.
-struct SideStream {
-    hipStream_t st = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    afn_status open()
-    {
-        AFN_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-        AFN_HIP(hipEventCreateWithFlags(&ev0, hipEventDisableTiming));
-        AFN_HIP(hipEventCreateWithFlags(&ev1, hipEventDisableTiming));
-        return AFN_OK;
-    }
-    ~SideStream()
-    {
-        if (st) {
-            (void)hipStreamSynchronize(st);
-            (void)hipStreamDestroy(st);
-        }
-        if (ev0) (void)hipEventDestroy(ev0);
-        if (ev1) (void)hipEventDestroy(ev1);
-    }
-};
 
 // A second host thread that enqueues a chain of launches (on a SideStream)
 // while this thread enqueues and waits on its own: a chain of a few thousand

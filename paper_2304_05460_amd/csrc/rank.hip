@@ -647,8 +647,17 @@ afn_status rank_estimate(const double *X, int64_t n, int d, double l, int kind, 
     hipLaunchKernelGGL(gather_scaled, dim3((unsigned)ceil_div((int64_t)m * d, 256)), dim3(256), 0, s, X,
                        sub, m, d, scale, Xm);
     hipLaunchKernelGGL(kmat_fill, dim3(gmm), dim3(256), 0, s, Xm, m, d, l2, kind, K);
-    // FPS order of the subsample, produced 64 positions at a time as the scan needs them
+    // FPS order of the subsample, produced 64 positions at a time as the scan
+    // needs them, on a second stream one chunk ahead of the scan: chunk c + 1
+    // runs while the passes of chunk c do (the scan reads only ord, at
+    // positions an earlier chunk wrote; events ev0 / ev1 mark even / odd chunks)
     AFN_TRY(fps_start(Xm, m, d, fws, s, err));
+    SideStream side;
+    AFN_TRY(side.open());
+    AFN_HIP(hipEventRecord(side.ev0, s));
+    AFN_HIP(hipStreamWaitEvent(side.st, side.ev0, 0));
+    AFN_TRY(fps_advance(Xm, m, d, 0, m < 64 ? m : 64, m, ord, nullptr, fws, side.st, err));
+    AFN_HIP(hipEventRecord(side.ev0, side.st));
     hipLaunchKernelGGL(sumsq_partial, dim3(nparts), dim3(256), 0, s, K, mm, part);
     hipLaunchKernelGGL(sum_parts, dim3(1), dim3(256), 0, s, part, nparts, errs + m);
     AFN_HIP(hipGetLastError());
@@ -665,7 +674,12 @@ afn_status rank_estimate(const double *X, int64_t n, int d, double l, int kind, 
     int r_found = m;
     for (int r0 = 0; r0 < m && r_found == m; r0 += 64) {
         const int r1 = r0 + 64 < m ? r0 + 64 : m;
-        AFN_TRY(fps_advance(Xm, m, d, r0, r1, m, ord, nullptr, fws, s, err));
+        const bool odd = (r0 / 64) & 1;
+        if (r1 < m) {
+            AFN_TRY(fps_advance(Xm, m, d, r1, r1 + 64 < m ? r1 + 64 : m, m, ord, nullptr, fws, side.st, err));
+            AFN_HIP(hipEventRecord(odd ? side.ev0 : side.ev1, side.st));
+        }
+        AFN_HIP(hipStreamWaitEvent(s, odd ? side.ev1 : side.ev0, 0));
         for (int b0 = r0; b0 < r1; b0 += kScanB) {
             const int nb = b0 + kScanB < r1 ? kScanB : r1 - b0;
             hipLaunchKernelGGL(scan_panel, gpanel, dim3(256), 0, s, K, m, ord, b0, nb, pivtol, C, Q, skip);
@@ -687,6 +701,8 @@ afn_status rank_estimate(const double *X, int64_t n, int d, double l, int kind, 
             }
         }
     }
+    // the chunk ahead may still run, and the eigenvalue branch rewrites Xm
+    AFN_HIP(hipStreamSynchronize(side.st));
     const int64_t kest = (int64_t)std::floor((double)r_found * (double)n / (double)m);
     int64_t k = kest;
     info->rank_r = r_found;
