@@ -342,12 +342,18 @@ struct HostWorker {
     template <class F>
     void start(int device, F f)
     {
-        th = std::thread([this, device, f]() {
-            hipError_t e = hipSetDevice(device);
-            st = e == hipSuccess ? f() : AFN_EDEVICE;
-            if (e != hipSuccess) msg = std::string("hipSetDevice: ") + hipGetErrorString(e);
-            else if (st != AFN_OK) msg = afn_last_error();
-        });
+        try {
+            th = std::thread([this, device, f]() {
+                hipError_t e = hipSetDevice(device);
+                st = e == hipSuccess ? f() : AFN_EDEVICE;
+                if (e != hipSuccess) msg = std::string("hipSetDevice: ") + hipGetErrorString(e);
+                else if (st != AFN_OK) msg = afn_last_error();
+            });
+        } catch (...) {
+            // no thread to be had: the same launches from this thread
+            st = f();
+            if (st != AFN_OK) msg = afn_last_error();
+        }
     }
     afn_status join()
     {
