@@ -561,6 +561,42 @@ def test_rank_scan_edges_match_oracle(afn, case):
     assert inf.rank_eig_branch == info[2] and inf.k == ko
 
 
+@pytest.mark.parametrize("case,c,expect_r", [("stop_in_odd_chunk", 100, 104), ("stop_in_even_chunk", 150, 152),
+                                             ("two_full_chunks", 128, 128)])
+def test_rank_scan_fps_chunks_match_oracle(afn, case, c, expect_r):
+    # The subsample's FPS order comes in 64-step chunks, each computed one
+    # chunk ahead of the scan.  Clusters of c groups of nearly coincident
+    # points one unit apart at l = 0.01: K is block diagonal with all-ones
+    # blocks, FPS takes one point per cluster first, and after 8 j steps the
+    # scan error is sqrt(remaining clusters / c), so r = 8 ceil(c / 8): the
+    # scan stops inside chunk 1 or 2 with the next chunk already under way.
+    # two_full_chunks: 128 points far apart at l = 1e-3 (K = I) use both
+    # chunks to the end.  m = n, so no scaling and no sampling choice.
+    rng = np.random.default_rng(123 + c)
+    if case == "two_full_chunks":
+        X = np.stack([np.arange(c, dtype=float), np.zeros(c)], axis=1)
+        l = 1e-3
+    else:
+        per = 4 if c == 100 else 2
+        centres = np.stack([np.arange(c, dtype=float), np.zeros(c)], axis=1)
+        X = np.repeat(centres, per, axis=0) + 1e-6 * rng.standard_normal((c * per, 2))
+        X = X[rng.permutation(X.shape[0])]
+        l = 0.01
+    n = X.shape[0]
+    m = n
+    say(f"rank scan chunks {case} n={n}")
+    h = afn.afn_setup(dev(X), l, 1e-3, k=-1, w=4, k_max=n, m=m, seed=7, method=afn.AFN_METHOD_NYSTROM)
+    inf = h.info()
+    ko, info = oracle.rank_estimate(X, l, 1e-3, m, kmax=n, kswitch=2000, seed=7)
+    say("gpu", inf.k, inf.rank_r, inf.rank_k_est, inf.rank_eig_count, "oracle", ko, info)
+    assert info[0] == expect_r
+    assert inf.rank_r == info[0]
+    assert inf.rank_eig_branch == info[2] == 1 and inf.rank_eig_count == info[3]
+    assert inf.k == ko
+    idx, _ = oracle.fps(X, ko)
+    np.testing.assert_array_equal(h.landmarks(), idx)
+
+
 def test_rank_estimate_largest_subsample(afn):
     # m at its maximum: the tridiagonalization's LDS per launch (3 (m - j - 2)
     # doubles) exceeds 64 KB in the first steps

@@ -460,3 +460,25 @@ def test_rank_estimate_scales_subsample_by_m_over_n():
     assert info[2] == 0
     assert info[0] == ranks["m/n"]
     assert info[1] == (ranks["m/n"] * n) // m and k == info[1]
+
+
+@pytest.mark.parametrize("c,per", [(100, 4), (150, 2), (37, 3)])
+def test_rank_estimate_on_clusters_closed_form(c, per):
+    """Alg. 4 on c clusters of `per` nearly coincident points one unit apart
+    at l = 0.01 (m = n): K is block diagonal with c all-ones blocks of rank
+    one, FPS takes one point per cluster before any second one, and after s
+    eliminations the scan's error is sqrt((c - s) / c) (each block's Frobenius
+    mass per^2), so the first multiple of 8 with error below 0.1 is
+    8 ceil(c / 8); k_est = r < 2000 takes the eigenvalue branch, which counts
+    the c eigenvalues near per above 0.1 mu (the rest are of the order of the
+    squared jitter over l^2)."""
+    rng = np.random.default_rng(500 + c)
+    centres = np.stack([np.arange(c, dtype=float), np.zeros(c)], axis=1)
+    X = np.repeat(centres, per, axis=0) + 1e-6 * rng.standard_normal((c * per, 2))
+    X = X[rng.permutation(X.shape[0])]
+    n = X.shape[0]
+    k, info = oracle.rank_estimate(X, 0.01, 1e-3, n, kmax=n, kswitch=2000, seed=3)
+    r, k_est, eig_branch, eig_count = info
+    assert r == 8 * math.ceil(c / 8)
+    assert k_est == r and eig_branch == 1
+    assert eig_count == c and k == c
