@@ -320,7 +320,23 @@ __global__ __launch_bounds__(kLdsThreads) void fps_lds(const double *__restrict_
     __shared__ int wii[2][kLdsThreads / 64];
     constexpr int DR = D > 0 ? D : 1;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    for (int e = tid; e < n * d; e += kLdsThreads) xs[e] = X[e];
+    // eight loads in flight per thread (clamped in-range addresses, the stores
+    // masked): one load per iteration would wait out the latency each time,
+    // and every launch of a chunked run fills LDS again
+    const int nd = n * d;
+    for (int e0 = 0; e0 < nd; e0 += 8 * kLdsThreads) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + tid + kLdsThreads * u;
+            v[u] = X[e < nd ? e : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + tid + kLdsThreads * u;
+            if (e < nd) xs[e] = v[u];
+        }
+    }
     double cur[PT], own[PT][DR];
 #pragma unroll
     for (int u = 0; u < PT; ++u) {

@@ -148,7 +148,17 @@ constexpr int kScanE = 4;      // errors per pass, one every 8 steps
 // Out: C[i m + x] = c_i(x), Q[i m + x] = c_i(x) / p_i, skip[i] (workgroup 0).
 // Every workgroup first runs the nb x nb block of the pivot rows (wave 0, one
 // lane per row) to obtain the pivots, the skip flags and q_i(piv_j), then its
-// 256 rows; a row's entries are registers, each step updates the later ones.
+// 256 rows.  A row goes left-looking in chunks of eight columns: a chunk's
+// entries (registers) first take the terms c_i q_i(piv_j) of the earlier
+// chunks' steps (c_i from the thread's history in LDS, q_i and the skip
+// flags as broadcasts), then its eight steps run as before, each updating
+// the chunk's later entries.  Every entry thus receives the same products
+// and differences in the same step order as in a right-looking sweep over
+// all 32 columns, while the code stays rolled (unrolled over all 32 steps it
+// waited on instruction fetch: it runs once per launch).  The next chunk's
+// entries are loaded while a chunk is processed.
+constexpr int kScanC = 8;      // columns per chunk
+
 __global__ __launch_bounds__(256) void scan_panel(const double *__restrict__ K, int m,
                                                   const int32_t *__restrict__ ord, int r0, int nb,
                                                   double pivtol, double *__restrict__ C,
@@ -158,25 +168,50 @@ __global__ __launch_bounds__(256) void scan_panel(const double *__restrict__ K, 
     __shared__ double qb[kScanB][kScanB];     // qb[i][j] = q_i(piv_j)
     __shared__ double pvt[kScanB];
     __shared__ int skp[kScanB], zc[kScanB];   // zc[j]: column piv_j zeroed before step j
+    __shared__ double hist[kScanB - kScanC][256];   // hist[i][tid]: the thread's c_i
     const int tid = threadIdx.x;
     if (tid < kScanB) {
         piv[tid] = tid < nb ? ord[r0 + tid] : -1;
         zc[tid] = 0;
     }
     __syncthreads();
-    // one row: at_step(i, c_i(x)) returns whether step i is skipped
-    auto run_row = [&](int x, double (&P)[kScanB], auto at_step) {
+    // row x (the rowzero test; -1 for none) with its entries read from row xl
+    // (in range) when real; at_step(i, c_i(x)) returns whether step i is skipped
+    auto run_row = [&](int x, int xl, bool real, auto at_step) {
+        auto load = [&](int q, double (&R)[kScanC]) {
+#pragma unroll
+            for (int t = 0; t < kScanC; ++t) {
+                const int col = q + t < nb ? piv[q + t] : piv[0];
+                R[t] = K[xl + (int64_t)col * m];
+            }
+        };
+        double Pn[kScanC];
+        load(0, Pn);
         bool rowzero = false;
+        for (int q = 0; q < nb; q += kScanC) {
+            double P[kScanC];
 #pragma unroll
-        for (int i = 0; i < kScanB; ++i) {
-            if (i >= nb) break;
-            const double ci = rowzero || zc[i] ? 0.0 : P[i];
-            if (at_step(i, ci)) {
-                if (x == piv[i]) rowzero = true;
-            } else {
+            for (int t = 0; t < kScanC; ++t) P[t] = real && q + t < nb ? Pn[t] : 0.0;
+            if (q + kScanC < nb) load(q + kScanC, Pn);
+            for (int i = 0; i < q; ++i) {
+                if (skp[i]) continue;
+                const double ci = hist[i][tid];
 #pragma unroll
-                for (int j = i + 1; j < kScanB; ++j)
-                    if (j < nb) P[j] = P[j] - ci * qb[i][j];
+                for (int t = 0; t < kScanC; ++t) P[t] = P[t] - ci * qb[i][q + t];
+            }
+#pragma unroll
+            for (int t = 0; t < kScanC; ++t) {
+                const int i = q + t;
+                if (i < nb) {
+                    const double ci = rowzero || zc[i] ? 0.0 : P[t];
+                    if (at_step(i, ci)) {
+                        if (x == piv[i]) rowzero = true;
+                    } else {
+#pragma unroll
+                        for (int u = t + 1; u < kScanC; ++u) P[u] = P[u] - ci * qb[i][q + u];
+                    }
+                    if (i < kScanB - kScanC) hist[i][tid] = ci;
+                }
             }
         }
     };
@@ -185,10 +220,6 @@ __global__ __launch_bounds__(256) void scan_panel(const double *__restrict__ K, 
         // lane i, and q_i(piv_j) from lane j through qb (one wave: its LDS
         // accesses complete in program order)
         const int a = tid;
-        double P[kScanB];
-#pragma unroll
-        for (int j = 0; j < kScanB; ++j)
-            P[j] = a < nb && j < nb ? K[piv[a] + (int64_t)piv[j] * m] : 0.0;
         auto at_step = [&](int i, double cai) {
             const double p = __shfl(cai, i, 64);
             const bool sk = !(p > pivtol);
@@ -203,21 +234,18 @@ __global__ __launch_bounds__(256) void scan_panel(const double *__restrict__ K, 
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             return sk;
         };
-        run_row(a < nb ? piv[a] : -1, P, at_step);
+        run_row(a < nb ? piv[a] : -1, a < nb ? piv[a] : piv[0], a < nb, at_step);
     }
     __syncthreads();
     if (blockIdx.x == 0 && tid < nb) skip[tid] = skp[tid];
     const int x = blockIdx.x * 256 + tid;
     if (x >= m) return;
-    double P[kScanB];
-#pragma unroll
-    for (int j = 0; j < kScanB; ++j) P[j] = j < nb ? K[x + (int64_t)piv[j] * m] : 0.0;
     auto at_step = [&](int i, double ci) {
         C[(int64_t)i * m + x] = ci;
         Q[(int64_t)i * m + x] = ci / pvt[i];
         return skp[i] != 0;
     };
-    run_row(x, P, at_step);
+    run_row(x, x, true, at_step);
 }
 
 // S[x, y] after the nb steps on a 64 x 64 tile (each thread: rows
@@ -251,7 +279,7 @@ __global__ __launch_bounds__(256) void scan_update(double *__restrict__ K, int m
         qs[i][r] = i < nb && y0 + r < m ? Q[(int64_t)i * m + y0 + r] : 0.0;
     }
     if (tid < 64) {
-        piv[tid] = tid < nb ? ord[r0 + tid] : -1;
+        if (tid < kScanB) piv[tid] = tid < nb ? ord[r0 + tid] : -1;
         const unsigned long long bm = __ballot(tid < nb && skip[tid] != 0);
         if (tid == 0) skm_s = bm;
     }
