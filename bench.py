@@ -37,7 +37,7 @@ PEAK_FP32_TFLOPS = 157.3         # MI355X FP32 (vector, and dense MFMA)
 # FP64 VALU lane-operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 VALU_F64_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # VALU instructions per unique kernel evaluation in the tile-pair loop of
-# kmv_sym_mf<0, 3, double, double> (AMD assembly of this build, per lane and
+# kmv_sym_mf<0, 3, double, double> (AMD assembly of the compiled kernel, per lane and
 # tile pair, i.e. per 16 pairs, besides 4 MFMAs that also add the squared
 # norms): 245 where the software FP64 2^-t runs (13 instructions per
 # table-driven exponential plus one LDS read, 2 FMAs for the row and column
@@ -729,8 +729,8 @@ def main():
                     help="only run a device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
-              f"(the multi-GPU row sharding is a design note only)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              f"(sharding rows over several GPUs is a design note only)", file=sys.stderr)
         sys.exit(2)
 
     import torch
