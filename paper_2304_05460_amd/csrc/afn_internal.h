@@ -152,27 +152,17 @@ size_t fps_workspace_bytes(int64_t n);
 afn_status fps(const double *X, int64_t n, int d, int k, int32_t *idx_dev, double *seld_dev,
                void *work, hipStream_t s, int *err_dev);
 // A second stream with two events for work that runs beside the setup
-// stream; the destructor waits for the stream's work (also on error paths,
-// so nothing outlives the caller's workspace) and releases it.
+// stream.  Streams and events come from a pool of the calling host thread
+// (per device; created on first use and kept for the thread's lifetime, as
+// creating them cost about as much as the work they overlap); the destructor
+// waits for the stream's work (also on error paths, so nothing outlives the
+// caller's workspace) and returns it to the pool.
 struct SideStream {
     hipStream_t st = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    afn_status open()
-    {
-        AFN_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-        AFN_HIP(hipEventCreateWithFlags(&ev0, hipEventDisableTiming));
-        AFN_HIP(hipEventCreateWithFlags(&ev1, hipEventDisableTiming));
-        return AFN_OK;
-    }
-    ~SideStream()
-    {
-        if (st) {
-            (void)hipStreamSynchronize(st);
-            (void)hipStreamDestroy(st);
-        }
-        if (ev0) (void)hipEventDestroy(ev0);
-        if (ev1) (void)hipEventDestroy(ev1);
-    }
+    int slot = -1;
+    afn_status open();
+    ~SideStream();
 };
 
 // The same selection in pieces: fps_start picks the first point, fps_advance

@@ -533,6 +533,16 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     if (h->method == AFN_METHOD_NYSTROM) {
         AFN_TRY(nystrom_factors(h, tmp, tm, s));
     } else {
+    // the kNN pattern of the non-landmark points (and their spatial order)
+    // needs none of the factors: it runs on a second stream beside the
+    // Cholesky, L^{-1} and V, and the FSAI rows wait for it
+    SideStream kside;
+    if (nr > 0) {
+        AFN_TRY(kside.open());
+        AFN_HIP(hipEventRecord(kside.ev0, s));
+        AFN_HIP(hipStreamWaitEvent(kside.st, kside.ev0, 0));
+    }
+    const hipStream_t ks = nr > 0 ? kside.st : s;
     // L = chol(K11 + mu I), Linv, V = L^{-1} K12
     if (k > 0) {
         AFN_TRY(h->arena.alloc_n(&h->L, (int64_t)k * k));
@@ -553,13 +563,14 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
         AFN_TRY(h->arena.alloc_n(&h->rorder, nr));
         rorder = h->rorder;
         AFN_TRY(tmp.alloc(&ows, spatial_order_work_bytes(nr, d)));
-        AFN_TRY(spatial_order(h->Xp + (int64_t)k * d, nr, d, rorder, ows, s));
+        AFN_TRY(spatial_order(h->Xp + (int64_t)k * d, nr, d, rorder, ows, ks));
     }
     if (nr > 0) {
         void *kws = nullptr;
         AFN_TRY(h->arena.alloc_n(&h->cols, nr * h->w));
         AFN_TRY(tmp.alloc(&kws, knn_work_bytes(nr, d)));
-        AFN_TRY(knn_pattern_ordered(h->Xp + (int64_t)k * d, nr, d, h->w, rorder, kws, h->cols, s));
+        AFN_TRY(knn_pattern_ordered(h->Xp + (int64_t)k * d, nr, d, h->w, rorder, kws, h->cols, ks));
+        AFN_HIP(hipEventRecord(kside.ev1, ks));
     }
     tm.mark(4, s);
     if (k > 0 && nr > 0) {
@@ -569,6 +580,7 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     }
     tm.mark(5, s);
     if (nr > 0) {
+        AFN_HIP(hipStreamWaitEvent(s, kside.ev1, 0));
         AFN_TRY(h->arena.alloc_n(&h->gval, nr * h->w));
         // above d = 10 the pattern neighbourhoods share few columns, so each
         // row's columns of V are recomputed in batches rather than gathered

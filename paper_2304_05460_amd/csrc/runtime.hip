@@ -1,6 +1,7 @@
 // Library runtime: error reporting, device memory bookkeeping, the per-device
 // scratch area and the kernel_matvec entry point of the C-ABI.
 #include <mutex>
+#include <vector>
 #include <string>
 
 #include "afn_internal.h"
@@ -25,6 +26,55 @@ void set_error(const char *fmt, ...)
 }
 
 void clear_error() { g_last_error.clear(); }
+
+namespace {
+struct PooledStream {
+    int device;
+    hipStream_t st;
+    hipEvent_t ev0, ev1;
+    bool busy;
+};
+// never destroyed: the thread's streams live until the process ends (their
+// destruction at thread exit could run after the runtime's own teardown)
+std::vector<PooledStream> &side_pool()
+{
+    static thread_local std::vector<PooledStream> *pool = new std::vector<PooledStream>();
+    return *pool;
+}
+}  // namespace
+
+afn_status SideStream::open()
+{
+    int dev = 0;
+    AFN_HIP(hipGetDevice(&dev));
+    auto &pool = side_pool();
+    for (size_t i = 0; i < pool.size(); ++i)
+        if (!pool[i].busy && pool[i].device == dev) {
+            pool[i].busy = true;
+            slot = (int)i;
+            st = pool[i].st;
+            ev0 = pool[i].ev0;
+            ev1 = pool[i].ev1;
+            return AFN_OK;
+        }
+    PooledStream e{dev, nullptr, nullptr, nullptr, true};
+    AFN_HIP(hipStreamCreateWithFlags(&e.st, hipStreamNonBlocking));
+    AFN_HIP(hipEventCreateWithFlags(&e.ev0, hipEventDisableTiming));
+    AFN_HIP(hipEventCreateWithFlags(&e.ev1, hipEventDisableTiming));
+    pool.push_back(e);
+    slot = (int)pool.size() - 1;
+    st = e.st;
+    ev0 = e.ev0;
+    ev1 = e.ev1;
+    return AFN_OK;
+}
+
+SideStream::~SideStream()
+{
+    if (slot < 0) return;
+    (void)hipStreamSynchronize(st);
+    side_pool()[(size_t)slot].busy = false;
+}
 
 afn_status DevArena::alloc(void **p, size_t bytes)
 {
