@@ -161,6 +161,9 @@ struct SideStream {
     hipStream_t st = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int slot = -1;
+    SideStream() = default;
+    SideStream(const SideStream &) = delete;
+    SideStream &operator=(const SideStream &) = delete;
     afn_status open();
     ~SideStream();
 };

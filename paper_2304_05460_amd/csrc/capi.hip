@@ -328,7 +328,6 @@ int64_t landmark_slots(int64_t n, const afn_params *prm)
     return kmax < n ? kmax : n;
 }
 
-
 // A second host thread that enqueues a chain of launches (on a SideStream)
 // while this thread enqueues and waits on its own: a chain of a few thousand
 // short launches costs the host about as long as the GPU takes to run it, so
@@ -521,8 +520,7 @@ afn_status setup_impl(const double *X, int64_t n, int d, double l, double mu, co
     if (overlap) {
         AFN_TRY(fps_host.join());
         AFN_HIP(hipStreamWaitEvent(s, side.ev1, 0));
-    }
-    else if (lm == AFN_LANDMARKS_UNIFORM)
+    } else if (lm == AFN_LANDMARKS_UNIFORM)
         AFN_TRY(uniform_landmarks(n, k, prm->seed + 1, idx, s));
     else
         AFN_TRY(fps(X, n, d, k, idx, nullptr, fws, s, h->flags + 3));
