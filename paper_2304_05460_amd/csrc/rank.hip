@@ -24,7 +24,6 @@ namespace afn {
 namespace {
 
 constexpr int kMaxM = 4096;
-constexpr int kHash = 4 * kMaxM;
 
 __device__ __forceinline__ uint64_t splitmix64_next(uint64_t &state)
 {
@@ -34,46 +33,100 @@ __device__ __forceinline__ uint64_t splitmix64_next(uint64_t &state)
     return z ^ (z >> 31);
 }
 
-// Partial Fisher-Yates over the virtual array a[j] = j, storing only the
-// positions that were written (open addressing in LDS).  Draw i is the
-// (i+1)-th splitmix64 output, a function of seed + (i+1) gamma alone, so the
-// draws and swap partners are formed by all threads; one thread then applies
-// the swaps in order.
-constexpr int kSubThreads = 256;
+// Partial Fisher-Yates over the virtual array a[j] = j: step i swaps
+// positions i and p_i = i + draw_i mod (n - i) and takes sub[i] = the value
+// found at p_i.  Draw i is the (i+1)-th splitmix64 output, a function of
+// seed + (i+1) gamma alone, so every draw is formed in parallel, and so are
+// the swaps: the only writes read later are those of a step's own value a_t
+// (the value at position t just before step t) into position p_t.  Hence
+// sub[i] = a_s for the last step s < i with p_s = p_i (else p_i itself), and
+// a_t = a_w for the last step w < t with p_w = t (else t), a chain that
+// pointer jumping resolves.  The previous step with the same partner, and the
+// last writer of each position, come from the steps sorted by (p_t, t).  The
+// result is the serial sequence of swaps, element for element.
+constexpr int kSubThreads = 1024;
 
 __global__ __launch_bounds__(kSubThreads) void subsample_kernel(int64_t n, int m, uint64_t seed, int32_t *sub)
 {
-    __shared__ int keys[kHash];
-    __shared__ int vals[kHash];
-    __shared__ int partner[kMaxM];
-    for (int i = threadIdx.x; i < kHash; i += kSubThreads) keys[i] = -1;
-    for (int i = threadIdx.x; i < m; i += kSubThreads) {
+    __shared__ unsigned long long srt[kMaxM];   // p_t << 32 | t, sorted; then jump buffer
+    __shared__ int prv[kMaxM];                  // previous step with the same partner, or -1
+    __shared__ int aux[kMaxM];                  // last sorted position of partner t; then chains
+    constexpr int PER = kMaxM / kSubThreads;
+    const int tid = threadIdx.x;
+    int N = 1;
+    while (N < m) N <<= 1;
+    auto partner_of = [&](int i) -> int64_t {
         uint64_t st = seed + (uint64_t)i * 0x9E3779B97F4A7C15ULL;
         const uint64_t draw = splitmix64_next(st);
-        partner[i] = (int)(i + (int64_t)(draw % (uint64_t)(n - i)));
+        return i + (int64_t)(draw % (uint64_t)(n - i));
+    };
+    for (int i = tid; i < N; i += kSubThreads) {
+        srt[i] = i < m ? ((unsigned long long)partner_of(i) << 32) | (unsigned)i : ~0ull;
+        if (i < m) {
+            prv[i] = -1;
+            aux[i] = -1;
+        }
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    auto slot = [&](int pos) {
-        unsigned h = ((unsigned)pos * 2654435761u) & (kHash - 1);
-        while (keys[h] != -1 && keys[h] != pos) h = (h + 1) & (kHash - 1);
-        return h;
-    };
-    auto get = [&](int pos) {
-        unsigned h = slot(pos);
-        return keys[h] == pos ? vals[h] : pos;
-    };
-    auto put = [&](int pos, int v) {
-        unsigned h = slot(pos);
-        keys[h] = pos;
-        vals[h] = v;
-    };
-    for (int i = 0; i < m; ++i) {
-        const int j = partner[i];
-        int ai = get(i), aj = get(j);
-        put(i, aj);
-        put(j, ai);
-        sub[i] = aj;
+    for (int k = 2; k <= N; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < N; i += kSubThreads) {
+                const int ij = i ^ j;
+                if (ij > i) {
+                    const unsigned long long x = srt[i], y = srt[ij];
+                    if ((x > y) == ((i & k) == 0)) {
+                        srt[i] = y;
+                        srt[ij] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    auto key = [&](int q) { return (int)(srt[q] >> 32); };
+    auto step = [&](int q) { return (int)(srt[q] & 0xffffffffu); };
+    for (int q = tid; q < m; q += kSubThreads) {
+        const int kq = key(q);
+        if (q > 0 && key(q - 1) == kq) prv[step(q)] = step(q - 1);
+        if ((q + 1 == m || key(q + 1) != kq) && kq < m) aux[kq] = q;
+    }
+    __syncthreads();
+    // w_t: the last step before t whose partner is t (those steps are <= t)
+    int w[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int t = tid + kSubThreads * u;
+        w[u] = t;
+        if (t < m) {
+            int q = aux[t];
+            if (q >= 0 && step(q) == t) q = q > 0 && key(q - 1) == t ? q - 1 : -1;
+            if (q >= 0) w[u] = step(q);
+        }
+    }
+    __syncthreads();    // aux read everywhere before it holds the chains
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int t = tid + kSubThreads * u;
+        if (t < m) aux[t] = w[u];
+    }
+    __syncthreads();
+    // after r rounds each entry points 2^r links down its chain (or to its
+    // end, a step nothing wrote before, whose value is its own index)
+    int *cur = aux, *nxt = (int *)srt;
+    for (int r = 0; (1 << r) < m; ++r) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int t = tid + kSubThreads * u;
+            if (t < m) nxt[t] = cur[cur[t]];
+        }
+        __syncthreads();
+        int *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int i = tid + kSubThreads * u;
+        if (i < m) sub[i] = prv[i] >= 0 ? cur[prv[i]] : (int32_t)partner_of(i);
     }
 }
 

@@ -906,6 +906,20 @@ def test_uniform_landmarks_match_oracle(afn, n, d, k, lm):
     assert info["status"] == afn.AFN_OK and np.linalg.norm(res) <= 2e-8 * np.linalg.norm(r)
 
 
+@pytest.mark.parametrize("n,k", [(4097, 4096), (1000, 999), (5000, 1), (70000, 4096), (3, 2)])
+def test_uniform_landmark_order_edges(afn, n, k):
+    # The uniform landmarks are a partial Fisher-Yates prefix, formed with all
+    # draws and swaps in parallel (steps sorted by partner, chains of earlier
+    # swaps resolved by pointer jumping).  With k near n nearly every step
+    # meets an earlier swap; k = 4096 is the largest prefix.
+    X = W.points("uniform", n, 3, 95)
+    say(f"uniform landmarks n={n} k={k}")
+    h = afn.afn_setup(dev(X), 0.3, 1e-2, k=k, w=4, seed=11, landmarks=afn.AFN_LANDMARKS_UNIFORM)
+    got = h.landmarks()
+    h.close()
+    np.testing.assert_array_equal(got, oracle.subsample(n, k, 12))
+
+
 def test_uniform_landmarks_limit(afn):
     X = dev(W.points("normal", 5000, 12, 94))
     with pytest.raises(afn.AFNError) as e:
